@@ -1,0 +1,147 @@
+"""ctypes binding of the plain FP64 CPU oracle (``feint_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by the
+benchmark's CPU-baseline leg.  The product library never imports it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from pathlib import Path
+
+import numpy as np
+
+HERE = Path(__file__).resolve().parent
+SRC = HERE / "feint_oracle.c"
+LIB = HERE / "liboracle.so"
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+def build(force: bool = True) -> Path:
+    """Compile the oracle with gcc: -O2, no FMA contraction, no fast-math, OpenMP."""
+    if force or not LIB.exists() or LIB.stat().st_mtime < SRC.stat().st_mtime:
+        tmp = LIB.with_suffix(".so.tmp")
+        cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-fPIC", "-shared", "-Wall", "-o", str(tmp), str(SRC), "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not LIB.exists():
+            build()
+        L = ctypes.CDLL(str(LIB))
+        L.oracle_gauss_legendre.argtypes = [ctypes.c_int, _dp, _dp]
+        L.oracle_gll_nodes.argtypes = [ctypes.c_int, _dp]
+        L.oracle_rule.argtypes = [ctypes.c_int, _dp, _dp]
+        L.oracle_nodes.argtypes = [ctypes.c_int, _dp]
+        L.oracle_basis.argtypes = [ctypes.c_int, _dp, _dp, _dp]
+        L.oracle_geometry.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp]
+        L.oracle_integrate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [_dp] * 8 + [_ip]
+        L.oracle_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [_dp] * 13
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_max_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _c(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def nshp(p):
+    return (p + 1) * (p + 1) * (p + 2) // 2
+
+
+def gauss_legendre(n):
+    x = np.zeros(n); w = np.zeros(n)
+    assert lib().oracle_gauss_legendre(n, _p(x), _p(w)) == 0
+    return x, w
+
+
+def gll_nodes(p):
+    x = np.zeros(p + 1)
+    assert lib().oracle_gll_nodes(p, _p(x)) == 0
+    return x
+
+
+def rule(n1):
+    pts = np.zeros((n1 ** 3, 3)); w = np.zeros(n1 ** 3)
+    assert lib().oracle_rule(n1, _p(pts), _p(w)) == n1 ** 3
+    return pts, w
+
+
+def nodes(p):
+    out = np.zeros((nshp(p), 3))
+    assert lib().oracle_nodes(p, _p(out)) == nshp(p)
+    return out
+
+
+def basis(p, xi):
+    """phi [n], reference gradients [n,3] at one point xi = (xi1, xi2, zeta)."""
+    xi = _c(xi)
+    n = nshp(p)
+    phi = np.zeros(n); dphi = np.zeros((n, 3))
+    assert lib().oracle_basis(p, _p(xi), _p(phi), _p(dphi)) == 0
+    return phi, dphi
+
+
+def geometry(X, xi):
+    """J [3,3], det, K = J^{-1} [3,3], mapped point x [3]."""
+    X = _c(X); xi = _c(xi)
+    J = np.zeros((3, 3)); K = np.zeros((3, 3)); x = np.zeros(3); det = np.zeros(1)
+    lib().oracle_geometry(_p(X), _p(xi), _p(J), _p(det), _p(K), _p(x))
+    return J, float(det[0]), K, x
+
+
+def integrate(p, coords, D, beta, c, f, n1=0, want_xq=False):
+    """A [ne,n,n], b [ne,n], flags [ne] (and xq [ne,nq,3] when asked)."""
+    coords = _c(coords); D = _c(D); beta = _c(beta); c = _c(c); f = _c(f)
+    ne = coords.shape[0]
+    n = nshp(p)
+    nqq = (n1 if n1 > 0 else p + 1) ** 3
+    A = np.zeros((ne, n, n)); b = np.zeros((ne, n))
+    flags = np.zeros(ne, dtype=np.int32)
+    xq = np.zeros((ne, nqq, 3)) if want_xq else None
+    rc = lib().oracle_integrate(p, n1, ne, _p(coords), _p(D), _p(beta), _p(c), _p(f),
+                                _p(A), _p(b), _p(xq), flags.ctypes.data_as(_ip))
+    assert rc == 0, rc
+    if want_xq:
+        return A, b, flags, xq
+    return A, b, flags
+
+
+def adjoint(p, coords, D, beta, c, f, G, g, n1=0):
+    """Gradients of sum_e <G_e,A_e> + <g_e,b_e>: dcoords, dD, dbeta, dc, df, per-element loss."""
+    coords = _c(coords); D = _c(D); beta = _c(beta); c = _c(c); f = _c(f); G = _c(G); g = _c(g)
+    ne = coords.shape[0]
+    dX = np.zeros_like(coords); dD = np.zeros_like(D); db = np.zeros_like(beta)
+    dc = np.zeros(ne); df = np.zeros(ne); Le = np.zeros(ne)
+    rc = lib().oracle_adjoint(p, n1, ne, _p(coords), _p(D), _p(beta), _p(c), _p(f), _p(G), _p(g),
+                              _p(dX), _p(dD), _p(db), _p(dc), _p(df), _p(Le))
+    assert rc == 0, rc
+    return dX, dD, db, dc, df, Le
+
+
+def set_threads(nt: int):
+    lib().oracle_set_threads(int(nt))
+
+
+def max_threads() -> int:
+    return int(lib().oracle_max_threads())

@@ -1,0 +1,79 @@
+"""Sizes, work and traffic of per-element integration on prisms.
+
+Two counting conventions live here:
+
+* the paper's own (Sec. 3 "Computational and memory complexity", Tables 1-3):
+  N_sh shape functions, N_I points of its symmetric triangle rule of degree
+  2p times p+1 line points, 7 operations per matrix entry per point (Laplace
+  term), 220 per point for the Jacobian, and 3(p+1)(p+2)/2 + 6(p+1) + 19 N_sh
+  for the shape functions at one point;
+* this library's: the convection-diffusion-reaction contraction
+  A_e = sum_q B_q^T W_q B_q costs 4 FMAs = 8 flops per entry per point on the
+  (p+1)^3-point collapsed rule, so F_dom = 8 n^2 nq per element.
+"""
+from __future__ import annotations
+
+# Points of the symmetric triangle rule of degree 2p that the paper's point
+# counts imply (Table 3 "xi, w" row / 4 / (p+1)).
+PAPER_TRIANGLE_POINTS = {1: 3, 2: 6, 3: 12, 4: 16, 5: 25, 6: 33, 7: 42}
+
+
+def nshp(p: int) -> int:
+    return (p + 1) * (p + 1) * (p + 2) // 2
+
+
+def ntri(p: int) -> int:
+    return (p + 1) * (p + 2) // 2
+
+
+def nq(p: int) -> int:
+    return (p + 1) ** 3
+
+
+def paper_nI(p: int) -> int:
+    return PAPER_TRIANGLE_POINTS[p] * (p + 1)
+
+
+def paper_shape_ops_per_point(p: int) -> int:
+    return 3 * (p + 1) * (p + 2) // 2 + 6 * (p + 1) + 19 * nshp(p)
+
+
+PAPER_JACOBIAN_OPS = 220
+
+
+def paper_matrix_ops_per_point(p: int) -> int:
+    return 7 * nshp(p) ** 2
+
+
+def paper_total_ops(p: int) -> int:
+    return paper_nI(p) * (paper_shape_ops_per_point(p) + PAPER_JACOBIAN_OPS
+                          + paper_matrix_ops_per_point(p))
+
+
+def f_dom(p: int) -> int:
+    """Algorithmic flops of the contraction per element: 8 n^2 nq."""
+    return 8 * nshp(p) ** 2 * nq(p)
+
+
+def f_full(p: int) -> int:
+    """F_dom + load vector and gradient transform (28 n nq) + geometry (220 nq)."""
+    n, q = nshp(p), nq(p)
+    return f_dom(p) + 28 * n * q + 220 * q
+
+
+INPUT_BYTES = 8 * (18 + 9 + 3 + 1 + 1)   # coords, D, beta, c, f in FP64 = 256
+
+
+def out_bytes(p: int, elem_size: int) -> int:
+    n = nshp(p)
+    return (n * n + n) * elem_size
+
+
+def bytes_per_element(p: int, elem_size: int) -> int:
+    """Algorithmic HBM bytes of the forward pass per element."""
+    return INPUT_BYTES + out_bytes(p, elem_size)
+
+
+def adjoint_bytes_per_element(p: int, elem_size: int) -> int:
+    """Adjoint: read G, g (elem_size each) + the 256 B of inputs, write 32 FP64 gradients."""
+    return out_bytes(p, elem_size) + INPUT_BYTES + 32 * 8

@@ -1,0 +1,164 @@
+"""Seeded synthetic workloads: perturbed prism meshes, per-element coefficients,
+mixed degrees and adjoint seeds.
+
+This module only draws and arranges inputs.  It holds none of the integration
+arithmetic (no quadrature, no basis, no Jacobian): it is shared by the GPU
+path and by the CPU oracle used in the tests, so that both see bit-identical
+inputs.
+
+Mesh (the paper's geometrically bilinear prisms, Sec. 4): an ``nx x ny`` grid of
+squares on [0,1]^2, each split along its (0,0)-(1,1) diagonal into two
+counter-clockwise triangles, extruded over ``nz`` layers on [0,1].  Prism
+vertices ``v0..v2`` are the bottom triangle and ``v3..v5`` the top one, with
+``v(a+3)`` directly above ``v(a)``.  Every strictly interior grid vertex is
+moved by an independent uniform offset in ``[-amp*h_d, +amp*h_d]`` per
+direction ``d`` (``h = (1/nx, 1/ny, 1/nz)``), so the meshed domain stays the
+unit cube.
+
+Coefficients per element: ``D = L L^T + I`` with ``L_ij ~ N(0, 0.3)``,
+``beta ~ N(0,1)^3``, ``c ~ U(0,1)``, ``f ~ U(-1,1)``.
+
+Draw order from ``numpy.random.default_rng(seed)`` (PCG64):
+  1. vertex offsets ``uniform(-1,1,(nvert,3))``
+  2. ``L = normal(0,0.3,(ne,3,3))``
+  3. ``beta = normal(0,1,(ne,3))``
+  4. ``c = uniform(0,1,ne)``
+  5. ``f = uniform(-1,1,ne)``
+  6. (mixed batch only) ``p = integers(1,7,ne)`` then ``perm = permutation(ne)``
+     applied to every per-element array
+  7. (adjoint only, after the above) ``G = normal(0,1,(ne,n,n))``,
+     ``g = normal(0,1,(ne,n))``, ``sample = choice(ne,64,replace=False)``
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+
+def nshp(p: int) -> int:
+    """Number of prism shape functions, (p+1)^2 (p+2) / 2 (Table 1, prism row)."""
+    return (p + 1) * (p + 1) * (p + 2) // 2
+
+
+def nq(p: int) -> int:
+    """Number of collapsed-Gauss quadrature points, (p+1)^3."""
+    return (p + 1) ** 3
+
+
+@dataclass
+class Batch:
+    """Element-major FP64 inputs for ``ne`` prisms (C-contiguous arrays)."""
+
+    coords: np.ndarray          # [ne, 6, 3]
+    D: np.ndarray               # [ne, 3, 3]
+    beta: np.ndarray            # [ne, 3]
+    c: np.ndarray               # [ne]
+    f: np.ndarray               # [ne]
+    p: Optional[np.ndarray] = None   # [ne] int8, mixed batches only
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def ne(self) -> int:
+        return int(self.coords.shape[0])
+
+    def subset(self, idx) -> "Batch":
+        idx = np.asarray(idx)
+        return Batch(
+            np.ascontiguousarray(self.coords[idx]),
+            np.ascontiguousarray(self.D[idx]),
+            np.ascontiguousarray(self.beta[idx]),
+            np.ascontiguousarray(self.c[idx]),
+            np.ascontiguousarray(self.f[idx]),
+            None if self.p is None else np.ascontiguousarray(self.p[idx]),
+            dict(self.meta),
+        )
+
+
+def grid_vertices(nx: int, ny: int, nz: int, amp: float, u: np.ndarray) -> np.ndarray:
+    """Perturbed grid vertex positions, id = (k*(ny+1)+j)*(nx+1)+i."""
+    k, j, i = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
+    i = i.ravel(); j = j.ravel(); k = k.ravel()
+    xyz = np.stack([i / nx, j / ny, k / nz], axis=1).astype(np.float64)
+    interior = (i > 0) & (i < nx) & (j > 0) & (j < ny) & (k > 0) & (k < nz)
+    h = np.array([1.0 / nx, 1.0 / ny, 1.0 / nz])
+    off = u * (amp * h)
+    off[~interior] = 0.0
+    return xyz + off
+
+
+def prism_connectivity(nx: int, ny: int, nz: int) -> np.ndarray:
+    """[ne, 6] vertex ids; element id e = ((k*ny + j)*nx + i)*2 + s."""
+    def vid(i, j, k):
+        return (k * (ny + 1) + j) * (nx + 1) + i
+
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    k = k.ravel(); j = j.ravel(); i = i.ravel()
+    v00 = lambda kk: vid(i, j, kk)
+    v10 = lambda kk: vid(i + 1, j, kk)
+    v11 = lambda kk: vid(i + 1, j + 1, kk)
+    v01 = lambda kk: vid(i, j + 1, kk)
+    t0 = [v00(k), v10(k), v11(k), v00(k + 1), v10(k + 1), v11(k + 1)]
+    t1 = [v00(k), v11(k), v01(k), v00(k + 1), v11(k + 1), v01(k + 1)]
+    conn = np.empty((nx * ny * nz, 2, 6), dtype=np.int64)
+    conn[:, 0, :] = np.stack(t0, axis=1)
+    conn[:, 1, :] = np.stack(t1, axis=1)
+    return conn.reshape(-1, 6)
+
+
+def make_batch(nx: int, ny: int, nz: int, amp: float = 0.2, seed: int = 0,
+               mixed: bool = False, with_conn: bool = False) -> Batch:
+    """Mesh + coefficients (draw steps 1-6)."""
+    rng = np.random.default_rng(seed)
+    nvert = (nx + 1) * (ny + 1) * (nz + 1)
+    u = rng.uniform(-1.0, 1.0, (nvert, 3))
+    verts = grid_vertices(nx, ny, nz, amp, u)
+    conn = prism_connectivity(nx, ny, nz)
+    ne = conn.shape[0]
+    coords = np.ascontiguousarray(verts[conn])               # [ne, 6, 3]
+    L = rng.normal(0.0, 0.3, (ne, 3, 3))
+    D = np.einsum("eik,ejk->eij", L, L) + np.eye(3)[None]
+    beta = rng.normal(0.0, 1.0, (ne, 3))
+    c = rng.uniform(0.0, 1.0, ne)
+    f = rng.uniform(-1.0, 1.0, ne)
+    meta = dict(nx=nx, ny=ny, nz=nz, amp=amp, seed=seed)
+    b = Batch(coords, np.ascontiguousarray(D), beta, c, f, None, meta)
+    if with_conn:
+        b.meta["conn"] = conn
+        b.meta["verts"] = verts
+    if mixed:
+        pdeg = rng.integers(1, 7, ne).astype(np.int8)
+        perm = rng.permutation(ne)
+        b = Batch(np.ascontiguousarray(coords[perm]), np.ascontiguousarray(b.D[perm]),
+                  np.ascontiguousarray(beta[perm]), np.ascontiguousarray(c[perm]),
+                  np.ascontiguousarray(f[perm]), np.ascontiguousarray(pdeg[perm]), meta)
+        b.meta["perm"] = perm
+    b.meta["rng"] = rng
+    return b
+
+
+def adjoint_seeds(batch: Batch, p: int, dtype=np.float64):
+    """Draw step 7: G ~ N(0,1) [ne,n,n], g ~ N(0,1) [ne,n], 64 sampled ids."""
+    rng = batch.meta["rng"]
+    n = nshp(p)
+    ne = batch.ne
+    G = rng.normal(0.0, 1.0, (ne, n, n)).astype(dtype, copy=False)
+    g = rng.normal(0.0, 1.0, (ne, n)).astype(dtype, copy=False)
+    sample = np.sort(rng.choice(ne, min(64, ne), replace=False))
+    return G, g, sample
+
+
+# The workloads of the paper-derived configurations (mesh sizes and amplitudes).
+WORKLOADS = {
+    "p1_4096":      dict(nx=16, ny=16, nz=8,  amp=0.2, seed=0, p=1),
+    "p4_131072":    dict(nx=64, ny=64, nz=16, amp=0.2, seed=1, p=4),
+    "mixed_262144": dict(nx=64, ny=64, nz=32, amp=0.2, seed=2, p=None),
+    "adj_p3_131072": dict(nx=64, ny=64, nz=16, amp=0.2, seed=3, p=3),
+    "p7_16384":     dict(nx=32, ny=32, nz=8,  amp=0.3, seed=4, p=7),
+}
+
+
+def workload(name: str) -> Batch:
+    w = WORKLOADS[name]
+    return make_batch(w["nx"], w["ny"], w["nz"], w["amp"], w["seed"], mixed=w["p"] is None)
