@@ -1,0 +1,185 @@
+/*
+ * feint.h -- C interface of libfeint, element-by-element numerical
+ * integration for geometrically bilinear prismatic finite elements of degree
+ * p = 1..7 on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Krużel & Banaś, "Vectorized OpenCL implementation of numerical
+ * integration for higher order finite elements" (arXiv 1310.1194), Sec. 2
+ * (eqs. (1)-(2), Algorithm 1) and Sec. 4 (bilinear prism).  The Laplace term
+ * of the paper is generalised to convection-diffusion-reaction with a load
+ * vector: for every element e with constant D (3x3), beta (3), c and f,
+ *
+ *   A_ab = sum_q w_q det J_q [ grad phi_a . D grad phi_b
+ *                              + phi_a (beta . grad phi_b) + c phi_a phi_b ]
+ *   b_a  = sum_q w_q det J_q f phi_a
+ *
+ * (row a = test function, grad phi = J^{-T} times the reference gradient,
+ * signed det J).  Quadrature: Duffy-collapsed Gauss-Legendre with p+1 points
+ * per direction, (p+1)^3 points.  Basis: Lagrange on the equispaced triangle
+ * lattice (i/p, j/p), i+j <= p (j outer, i inner) times 1D Lagrange on the
+ * p+1 Gauss-Lobatto nodes (ascending); shape function a = k*ntri + t.
+ * Prism vertices: v0..v2 the bottom triangle (zeta = -1), v3..v5 the top one
+ * (zeta = +1), v(a+3) above v(a).
+ *
+ * Conventions for every entry point below:
+ *   - Array arguments are DEVICE pointers owned by the caller, element-major,
+ *     C-contiguous.  The library never frees or retains them.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Every call is asynchronous on that stream and allocates nothing; the
+ *     reference tables of a degree are built and uploaded by
+ *     feint_prepare() (called implicitly on first use when the stream is
+ *     not capturing).
+ *   - Host-detectable errors (null pointer, bad degree or form, ne < 0, a
+ *     capturing stream with unprepared tables) are returned before any work is
+ *     enqueued.  ne == 0 is a no-op that returns FEINT_OK.
+ *   - Device-detected conditions do not abort: bit 0 of *dev_status is set
+ *     (atomic OR) when some det J <= 0; results still use the signed det J.
+ *   - Calls are safe from several host threads on distinct streams.
+ */
+#ifndef FEINT_H
+#define FEINT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FEINT_OK = 0,
+    FEINT_ERR_INVALID_ARG = -1,
+    FEINT_ERR_UNSUPPORTED_DEGREE = -2,
+    FEINT_ERR_UNSUPPORTED_FORM = -3,
+    FEINT_ERR_NOT_PREPARED = -4,
+    FEINT_ERR_HIP = -5,
+    FEINT_ERR_TOO_LARGE = -6
+} feint_status;
+
+/* Arithmetic of the contraction A_e = sum_q B_q^T W_q B_q.  The Jacobian,
+   its determinant and inverse and the per-point coefficient block W_q are
+   always computed in FP64; the load vector is always accumulated in FP64. */
+typedef enum {
+    FEINT_FP64 = 0,    /* FP64 MFMA, FP64 outputs */
+    FEINT_FP32 = 1,    /* FP32 MFMA, FP32 outputs */
+    FEINT_BF16X3 = 2,  /* split bf16 hi+lo, 3 MFMA products, FP32 accumulate/outputs */
+    FEINT_FP16X3 = 3   /* split fp16 hi+lo with power-of-two scaling, FP32 outputs */
+} feint_form;
+
+/* Per-element inputs, FP64, ne elements. */
+typedef struct {
+    const double *coords;  /* [ne][6][3] prism vertices */
+    const double *D;       /* [ne][3][3] row-major diffusion tensor, used as
+                              grad phi_a^T D grad phi_b (need not be symmetric) */
+    const double *beta;    /* [ne][3] convection vector */
+    const double *c;       /* [ne] reaction coefficient */
+    const double *f;       /* [ne] source */
+    int64_t ne;
+} feint_elements;
+
+/* (p+1)^2 (p+2)/2 shape functions (the paper's Table 1, prism row) and
+   (p+1)^3 quadrature points; -1 when p is outside [1,7]. */
+int feint_nshp(int p);
+int feint_nq(int p);
+
+/* Size in bytes of one output element of a form (8 for FP64, else 4);
+   0 for an unknown form. */
+size_t feint_elem_size(feint_form form);
+
+/* Build and upload the reference tables of degree p (quadrature points and
+   weights; shape-function values and reference gradients at every point, in
+   every precision the forms use).  Idempotent and thread-safe.  Must be
+   called before a stream that will be captured into a graph starts
+   capturing.  Library-owned memory; released by feint_shutdown(). */
+feint_status feint_prepare(int p);
+
+/* Forward integration (Algorithm 1 generalised to CDR + load vector; the
+   paper's eq. (2) as a sum over quadrature points).
+     A          [ne][n][n]  row a = test function; double for FEINT_FP64,
+                            float otherwise
+     b          [ne][n]     same dtype as A
+     xq         nullable, [ne][nq][3] double: mapped quadrature points
+     dev_status nullable, one uint32 on the device, OR-ed with 1 if some
+                det J <= 0 (the caller clears it). */
+feint_status feint_integrate(const feint_elements *el, int p, feint_form form,
+                             void *A, void *b, double *xq, uint32_t *dev_status,
+                             void *stream);
+
+/* Adjoint of feint_integrate: gradients of
+       L = sum_e <G_e, A_e> + <g_e, b_e>
+   with respect to every element's inputs.  G [ne][n][n] and g [ne][n] have
+   the form's output dtype (double for FEINT_FP64, float for FEINT_FP32; the
+   split forms are not differentiated: FEINT_ERR_UNSUPPORTED_FORM).
+   Outputs (overwritten, FP64): dcoords [ne][6][3], dD [ne][3][3] (all nine
+   entries treated as independent), dbeta [ne][3], dc [ne], df [ne].  The
+   per-point Jacobians are recomputed, never stored. */
+feint_status feint_integrate_adjoint(const feint_elements *el, int p, feint_form form,
+                                     const void *G, const void *g,
+                                     double *dcoords, double *dD, double *dbeta,
+                                     double *dc, double *df, void *stream);
+
+/* ---- Mixed-degree batches -------------------------------------------------
+   Elements of degrees 1..6 in any order run as one persistent,
+   degree-bucketed launch (the paper's Sec. 3 advice to group elements by
+   type and degree so that reference data is fetched once per group).
+   Outputs are packed in element order: element e's matrix starts at
+   offA[e] elements of the output dtype, its vector at offb[e], where offA
+   and offb are the exclusive prefix sums of n(p_e)^2 and n(p_e). */
+typedef struct feint_mixed_plan feint_mixed_plan;
+
+/* Create a plan for at most ne_max elements of form FEINT_FP32 or
+   FEINT_FP64.  Allocates the plan's device scratch (bucket counters,
+   permutation, work queue: about 40 bytes per element) and prepares the
+   tables of degrees 1..6. */
+feint_status feint_mixed_plan_create(int64_t ne_max, feint_form form, feint_mixed_plan **plan);
+
+/* Degree bucketing for a batch: histogram of p[ne] (int8, device), stable
+   scatter into degree order (heaviest degree first), and the packed output
+   offsets offA[ne+1], offb[ne+1] (int64, device; entry ne holds the totals).
+   Enqueued on `stream`; elements with p outside [1,6] are an error reported
+   through bit 1 of *dev_status (nullable) and get empty outputs. */
+feint_status feint_mixed_bucket(feint_mixed_plan *plan, const int8_t *p, int64_t ne,
+                                int64_t *offA, int64_t *offb, uint32_t *dev_status,
+                                void *stream);
+
+/* The persistent degree-bucketed launch over the bucketing of the last
+   feint_mixed_bucket call on this plan (same ne, same p). */
+feint_status feint_integrate_mixed(feint_mixed_plan *plan, const feint_elements *el,
+                                   void *A_packed, void *b_packed,
+                                   const int64_t *offA, const int64_t *offb,
+                                   uint32_t *dev_status, void *stream);
+
+/* Capture bucketing + persistent launch for fixed pointers into a HIP graph
+   held by the plan (replaces any previous one), then instantiate it. */
+feint_status feint_mixed_graph_capture(feint_mixed_plan *plan, const feint_elements *el,
+                                       const int8_t *p, void *A_packed, void *b_packed,
+                                       int64_t *offA, int64_t *offb, uint32_t *dev_status,
+                                       void *stream);
+/* Replay the captured graph on `stream`. */
+feint_status feint_mixed_graph_launch(feint_mixed_plan *plan, void *stream);
+void feint_mixed_plan_destroy(feint_mixed_plan *plan);
+
+/* ---- Tile autotuning -------------------------------------------------------
+   Each (degree, form) has several compiled tile shapes (columns of 16x16
+   output tiles per wave).  feint_autotune times each candidate with HIP
+   events on the caller's inputs and outputs (ne elements, `reps`
+   repetitions) and keeps the fastest for later calls; feint_tile_get/set
+   read or force the choice (index into the candidate list). */
+int feint_tile_count(int p, feint_form form);
+int feint_tile_get(int p, feint_form form);
+feint_status feint_tile_set(int p, feint_form form, int tile);
+/* Describe candidate `tile` as "TMxTN" output tiles per wave into buf. */
+feint_status feint_tile_describe(int p, feint_form form, int tile, char *buf, size_t len);
+feint_status feint_autotune(const feint_elements *el, int p, feint_form form,
+                            void *A, void *b, int reps, double *best_ms, void *stream);
+
+const char *feint_status_string(feint_status s);
+/* Last HIP error text seen by the library on this thread ("" if none). */
+const char *feint_last_error(void);
+/* Release every library-owned table (after all work has completed). */
+void feint_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FEINT_H */

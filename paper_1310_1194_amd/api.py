@@ -1,0 +1,153 @@
+"""Python entry points over libfeint (argument marshalling only).
+
+torch supplies device memory and the current stream; every step of the
+integration runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import native
+from .native import FORMS, Elements, check, lib
+
+
+def nshp(p: int) -> int:
+    return (p + 1) * (p + 1) * (p + 2) // 2
+
+
+def nq(p: int) -> int:
+    return (p + 1) ** 3
+
+
+def out_dtype(form: str) -> torch.dtype:
+    return torch.float64 if form == "fp64" else torch.float32
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check_input(name, t, shape_tail, ne):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape) != (ne, *shape_tail):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {(ne, *shape_tail)}")
+
+
+def elements(coords, D, beta, c, f) -> Elements:
+    ne = coords.shape[0]
+    _check_input("coords", coords, (6, 3), ne)
+    _check_input("D", D, (3, 3), ne)
+    _check_input("beta", beta, (3,), ne)
+    _check_input("c", c, (), ne)
+    _check_input("f", f, (), ne)
+    return Elements(coords.data_ptr(), D.data_ptr(), beta.data_ptr(), c.data_ptr(), f.data_ptr(), ne)
+
+
+def prepare(p: int) -> None:
+    check("feint_prepare", lib().feint_prepare(int(p)))
+
+
+def integrate_raw(coords, D, beta, c, f, p: int, form: str = "fp64", *, A=None, b=None,
+                  xq=None, status=None):
+    """Forward integration into (optionally preallocated) outputs; returns (A, b)."""
+    if form not in FORMS:
+        raise ValueError(f"unknown form {form!r}")
+    el = elements(coords, D, beta, c, f)
+    ne, n = coords.shape[0], nshp(p)
+    dt = out_dtype(form)
+    if A is None:
+        A = torch.empty((ne, n, n), dtype=dt, device=coords.device)
+    if b is None:
+        b = torch.empty((ne, n), dtype=dt, device=coords.device)
+    if A.dtype != dt or b.dtype != dt or A.numel() != ne * n * n or b.numel() != ne * n:
+        raise ValueError("output tensors have the wrong dtype or size")
+    if xq is not None and (xq.dtype != torch.float64 or xq.numel() != ne * nq(p) * 3):
+        raise ValueError("xq must be float64 with ne*nq*3 entries")
+    if status is not None and (status.dtype != torch.int32 or status.numel() < 1):
+        raise ValueError("status must be an int32 tensor")
+    check("feint_integrate", lib().feint_integrate(ctypes.byref(el), int(p), FORMS[form], _ptr(A), _ptr(b),
+                                                   _ptr(xq), _ptr(status), _stream()))
+    return A, b
+
+
+def adjoint_raw(coords, D, beta, c, f, G, g, p: int, form: str = "fp64"):
+    """Gradients of sum_e <G_e,A_e> + <g_e,b_e>: (dcoords, dD, dbeta, dc, df), FP64."""
+    el = elements(coords, D, beta, c, f)
+    ne, n = coords.shape[0], nshp(p)
+    dt = out_dtype(form)
+    G = G.contiguous().to(dt)
+    g = g.contiguous().to(dt)
+    if G.numel() != ne * n * n or g.numel() != ne * n:
+        raise ValueError("G, g have the wrong size")
+    outs = [torch.empty_like(t) for t in (coords, D, beta, c, f)]
+    check("feint_integrate_adjoint",
+          lib().feint_integrate_adjoint(ctypes.byref(el), int(p), FORMS[form], _ptr(G), _ptr(g),
+                                        *[_ptr(o) for o in outs], _stream()))
+    return tuple(outs)
+
+
+class IntegrateFn(torch.autograd.Function):
+    """(coords, D, beta, c, f) -> (A, b) with the hand-written adjoint as backward."""
+
+    @staticmethod
+    def forward(ctx, coords, D, beta, c, f, p, form):
+        ctx.p, ctx.form = p, form
+        ctx.save_for_backward(coords, D, beta, c, f)
+        return integrate_raw(coords, D, beta, c, f, p, form)
+
+    @staticmethod
+    def backward(ctx, gA, gb):
+        coords, D, beta, c, f = ctx.saved_tensors
+        n = nshp(ctx.p)
+        dt = out_dtype(ctx.form)
+        if gA is None:
+            gA = torch.zeros((coords.shape[0], n, n), dtype=dt, device=coords.device)
+        if gb is None:
+            gb = torch.zeros((coords.shape[0], n), dtype=dt, device=coords.device)
+        grads = adjoint_raw(coords, D, beta, c, f, gA, gb, ctx.p, ctx.form)
+        return (*grads, None, None)
+
+
+def integrate(coords, D, beta, c, f, p: int, form: str = "fp64"):
+    """Element matrices and load vectors; differentiable for the fp64 and fp32 forms."""
+    if torch.is_grad_enabled() and any(t.requires_grad for t in (coords, D, beta, c, f)):
+        return IntegrateFn.apply(coords, D, beta, c, f, p, form)
+    return integrate_raw(coords, D, beta, c, f, p, form)
+
+
+def tile_count(p: int, form: str) -> int:
+    return lib().feint_tile_count(int(p), FORMS[form])
+
+
+def tile_get(p: int, form: str) -> int:
+    return lib().feint_tile_get(int(p), FORMS[form])
+
+
+def tile_set(p: int, form: str, tile: int) -> None:
+    check("feint_tile_set", lib().feint_tile_set(int(p), FORMS[form], int(tile)))
+
+
+def tile_describe(p: int, form: str, tile: int) -> str:
+    buf = ctypes.create_string_buffer(32)
+    check("feint_tile_describe", lib().feint_tile_describe(int(p), FORMS[form], int(tile), buf, 32))
+    return buf.value.decode()
+
+
+def autotune(coords, D, beta, c, f, p: int, form: str, A, b, reps: int = 3) -> float:
+    """Time every compiled tile shape on these buffers, keep the fastest; returns its ms."""
+    el = elements(coords, D, beta, c, f)
+    best = ctypes.c_double(0)
+    check("feint_autotune", lib().feint_autotune(ctypes.byref(el), int(p), FORMS[form], _ptr(A), _ptr(b),
+                                                 int(reps), ctypes.byref(best), _stream()))
+    return best.value

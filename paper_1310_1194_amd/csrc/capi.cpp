@@ -1,0 +1,300 @@
+// C-ABI of libfeint: argument validation, per-device reference tables,
+// forward dispatch, tile selection and autotuning.
+#include "feint.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "capi_internal.h"
+#include "launch.h"
+#include "tables.h"
+
+namespace feint {
+
+namespace {
+std::mutex g_mu;
+std::map<int, DevTables *> g_tables;        // key: device * 16 + p
+int g_tile[8][4];                           // chosen variant per (p, form)
+thread_local std::string g_err;
+
+bool valid_form(int form) { return form >= FEINT_FP64 && form <= FEINT_FP16X3; }
+}  // namespace
+
+void set_error(const char *what, hipError_t e) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+}
+
+const DevTables *find_tables(int p) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_tables.find(dev * 16 + p);
+    return it == g_tables.end() ? nullptr : it->second;
+}
+
+// Upload the tables of degree p to the current device (once).
+feint_status prepare_tables(int p) {
+    if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) { set_error("hipGetDevice", e); return FEINT_ERR_HIP; }
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_tables.count(dev * 16 + p)) return FEINT_OK;
+    HostTables H = build_tables(p);
+    auto align = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t s_qw = align(H.qw.size() * 8), s_b64 = align(H.B64.size() * 8), s_b32 = align(H.B32.size() * 4);
+    const size_t s_sp = align(H.bf_hi.size() * 2);
+    const size_t total = s_qw + s_b64 + s_b32 + 4 * s_sp;
+    char *base = nullptr;
+    e = hipMalloc((void **)&base, total);
+    if (e != hipSuccess) { set_error("hipMalloc(tables)", e); return FEINT_ERR_HIP; }
+    std::vector<char> host(total, 0);
+    size_t o = 0;
+    auto put = [&](const void *src, size_t bytes, size_t slot) {
+        std::memcpy(host.data() + o, src, bytes);
+        size_t at = o;
+        o += slot;
+        return base + at;
+    };
+    DevTables *T = new DevTables();
+    T->p = p; T->n = H.n; T->npad = H.npad; T->nq = H.nq; T->nqp = H.nqp; T->nkb = H.nkb;
+    T->f16_shift = H.f16_shift;
+    double bmax = 0;
+    for (double v : H.B64) bmax = std::fmax(bmax, std::fabs(v));
+    T->bmax = (float)bmax;
+    T->qw = (const double *)put(H.qw.data(), H.qw.size() * 8, s_qw);
+    T->B64 = (const double *)put(H.B64.data(), H.B64.size() * 8, s_b64);
+    T->B32 = (const float *)put(H.B32.data(), H.B32.size() * 4, s_b32);
+    T->bf_hi = (const uint16_t *)put(H.bf_hi.data(), H.bf_hi.size() * 2, s_sp);
+    T->bf_lo = (const uint16_t *)put(H.bf_lo.data(), H.bf_lo.size() * 2, s_sp);
+    T->hf_hi = (const uint16_t *)put(H.hf_hi.data(), H.hf_hi.size() * 2, s_sp);
+    T->hf_lo = (const uint16_t *)put(H.hf_lo.data(), H.hf_lo.size() * 2, s_sp);
+    T->base = base;
+    e = hipMemcpy(base, host.data(), total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        set_error("hipMemcpy(tables)", e);
+        (void)hipFree(base);
+        delete T;
+        return FEINT_ERR_HIP;
+    }
+    g_tables[dev * 16 + p] = T;
+    return FEINT_OK;
+}
+
+// Tables for a launch on `stream`: prepared on demand unless the stream is
+// being captured.
+feint_status tables_for_launch(int p, hipStream_t stream, const DevTables **out) {
+    const DevTables *T = find_tables(p);
+    if (!T) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        hipError_t e = hipStreamIsCapturing(stream, &cs);
+        if (e != hipSuccess) { set_error("hipStreamIsCapturing", e); return FEINT_ERR_HIP; }
+        if (cs != hipStreamCaptureStatusNone) return FEINT_ERR_NOT_PREPARED;
+        feint_status s = prepare_tables(p);
+        if (s != FEINT_OK) return s;
+        T = find_tables(p);
+    }
+    *out = T;
+    return FEINT_OK;
+}
+
+// Element inputs: ne >= 0; the five arrays must be non-null unless ne == 0.
+feint_status check_elements(const feint_elements *el) {
+    if (!el) return FEINT_ERR_INVALID_ARG;
+    if (el->ne < 0) return FEINT_ERR_INVALID_ARG;
+    if (el->ne == 0) return FEINT_OK;
+    if (!el->coords || !el->D || !el->beta || !el->c || !el->f) return FEINT_ERR_INVALID_ARG;
+    return FEINT_OK;
+}
+
+void fill_fwd_params(FwdParams &prm, const feint_elements *el, int form, const DevTables *T) {
+    std::memset(&prm, 0, sizeof prm);
+    prm.coords = el->coords; prm.D = el->D; prm.beta = el->beta; prm.c = el->c; prm.f = el->f;
+    prm.ne = el->ne;
+    prm.qw = T->qw; prm.B64 = T->B64; prm.B32 = T->B32;
+    prm.Bhi = form == FEINT_FP16X3 ? T->hf_hi : T->bf_hi;
+    prm.Blo = form == FEINT_FP16X3 ? T->hf_lo : T->bf_lo;
+    prm.bmax = T->bmax;
+    prm.f16_shift = T->f16_shift;
+}
+
+const FwdVariant *fwd_variants(int form, int p, int *count) {
+    switch (form) {
+    case FEINT_FP64: return fwd_variants_f64(p, count);
+    case FEINT_FP32: return fwd_variants_f32(p, count);
+    case FEINT_BF16X3: return fwd_variants_bf16(p, count);
+    case FEINT_FP16X3: return fwd_variants_f16(p, count);
+    }
+    *count = 0;
+    return nullptr;
+}
+
+const FwdVariant *chosen_variant(int p, int form) {
+    int cnt = 0;
+    const FwdVariant *v = fwd_variants(form, p, &cnt);
+    if (!v || cnt == 0) return nullptr;
+    int t;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        t = g_tile[p][form];
+    }
+    return &v[(t >= 0 && t < cnt) ? t : 0];
+}
+
+feint_status launch_forward(const FwdParams &prm, const FwdVariant *v, hipStream_t stream) {
+    const int64_t blocks = (prm.ne * v->items_per_elem() + 3) / 4;
+    if (blocks > 0x7fffffffLL) return FEINT_ERR_TOO_LARGE;
+    (void)hipGetLastError();
+    v->launch(prm, stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { set_error("forward launch", e); return FEINT_ERR_HIP; }
+    return FEINT_OK;
+}
+
+}  // namespace feint
+
+using namespace feint;
+
+extern "C" {
+
+int feint_nshp(int p) { return (p < 1 || p > kMaxP) ? -1 : nshp_of(p); }
+int feint_nq(int p) { return (p < 1 || p > kMaxP) ? -1 : nq_of(p); }
+
+size_t feint_elem_size(feint_form form) {
+    if (!valid_form(form)) return 0;
+    return form == FEINT_FP64 ? 8 : 4;
+}
+
+feint_status feint_prepare(int p) { return prepare_tables(p); }
+
+feint_status feint_integrate(const feint_elements *el, int p, feint_form form, void *A, void *b,
+                             double *xq, uint32_t *dev_status, void *stream) {
+    if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
+    if (!valid_form(form)) return FEINT_ERR_UNSUPPORTED_FORM;
+    feint_status s = check_elements(el);
+    if (s != FEINT_OK) return s;
+    if (el->ne == 0) return FEINT_OK;
+    if (!A || !b) return FEINT_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const DevTables *T = nullptr;
+    s = tables_for_launch(p, st, &T);
+    if (s != FEINT_OK) return s;
+    FwdParams prm;
+    fill_fwd_params(prm, el, form, T);
+    prm.A = A; prm.b = b; prm.xq = xq; prm.status = dev_status;
+    const FwdVariant *v = chosen_variant(p, form);
+    if (!v) return FEINT_ERR_UNSUPPORTED_FORM;
+    return launch_forward(prm, v, st);
+}
+
+int feint_tile_count(int p, feint_form form) {
+    int cnt = 0;
+    if (p < 1 || p > kMaxP || !valid_form(form)) return 0;
+    fwd_variants(form, p, &cnt);
+    return cnt;
+}
+
+int feint_tile_get(int p, feint_form form) {
+    if (p < 1 || p > kMaxP || !valid_form(form)) return -1;
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_tile[p][form];
+}
+
+feint_status feint_tile_set(int p, feint_form form, int tile) {
+    if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
+    if (!valid_form(form)) return FEINT_ERR_UNSUPPORTED_FORM;
+    if (tile < 0 || tile >= feint_tile_count(p, form)) return FEINT_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tile[p][form] = tile;
+    return FEINT_OK;
+}
+
+feint_status feint_tile_describe(int p, feint_form form, int tile, char *buf, size_t len) {
+    int cnt = 0;
+    if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
+    if (!valid_form(form)) return FEINT_ERR_UNSUPPORTED_FORM;
+    const FwdVariant *v = fwd_variants(form, p, &cnt);
+    if (!buf || tile < 0 || tile >= cnt) return FEINT_ERR_INVALID_ARG;
+    std::snprintf(buf, len, "%dx%d", v[tile].tm, v[tile].tn);
+    return FEINT_OK;
+}
+
+feint_status feint_autotune(const feint_elements *el, int p, feint_form form, void *A, void *b, int reps,
+                            double *best_ms, void *stream) {
+    if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
+    if (!valid_form(form)) return FEINT_ERR_UNSUPPORTED_FORM;
+    feint_status s = check_elements(el);
+    if (s != FEINT_OK) return s;
+    if (!A || !b || el->ne == 0 || reps < 1) return FEINT_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const DevTables *T = nullptr;
+    s = tables_for_launch(p, st, &T);
+    if (s != FEINT_OK) return s;
+    FwdParams prm;
+    fill_fwd_params(prm, el, form, T);
+    prm.A = A; prm.b = b;
+    int cnt = 0;
+    const FwdVariant *v = fwd_variants(form, p, &cnt);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return FEINT_ERR_HIP;
+    int best = 0;
+    float best_t = 1e30f;
+    for (int t = 0; t < cnt; ++t) {
+        s = launch_forward(prm, &v[t], st);                 // warm-up
+        if (s != FEINT_OK) break;
+        (void)hipEventRecord(e0, st);
+        for (int r = 0; r < reps && s == FEINT_OK; ++r) s = launch_forward(prm, &v[t], st);
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) { s = FEINT_ERR_HIP; break; }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (ms < best_t) { best_t = ms; best = t; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != FEINT_OK) return s;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_tile[p][form] = best;
+    }
+    if (best_ms) *best_ms = best_t;
+    return FEINT_OK;
+}
+
+const char *feint_status_string(feint_status s) {
+    switch (s) {
+    case FEINT_OK: return "ok";
+    case FEINT_ERR_INVALID_ARG: return "invalid argument";
+    case FEINT_ERR_UNSUPPORTED_DEGREE: return "unsupported degree";
+    case FEINT_ERR_UNSUPPORTED_FORM: return "unsupported form";
+    case FEINT_ERR_NOT_PREPARED: return "tables not prepared (stream is capturing)";
+    case FEINT_ERR_HIP: return "HIP runtime error";
+    case FEINT_ERR_TOO_LARGE: return "batch too large for one launch";
+    }
+    return "unknown status";
+}
+
+const char *feint_last_error(void) { return g_err.c_str(); }
+
+void feint_shutdown(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto &kv : g_tables) {
+        (void)hipSetDevice(kv.first / 16);
+        (void)hipFree(kv.second->base);
+        delete kv.second;
+    }
+    (void)hipSetDevice(cur);
+    g_tables.clear();
+}
+
+}  // extern "C"

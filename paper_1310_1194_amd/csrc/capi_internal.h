@@ -1,0 +1,30 @@
+// Internal helpers shared by the C-ABI translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "feint.h"
+#include "launch.h"
+
+namespace feint {
+
+// Device copy of the tables of one degree (one allocation, sub-buffers
+// 256-byte aligned).
+struct DevTables {
+    int p, n, npad, nq, nqp, nkb, f16_shift;
+    float bmax;
+    const double *qw, *B64;
+    const float *B32;
+    const uint16_t *bf_hi, *bf_lo, *hf_hi, *hf_lo;
+    void *base;
+};
+
+void set_error(const char *what, hipError_t e);
+feint_status prepare_tables(int p);
+const DevTables *find_tables(int p);
+feint_status tables_for_launch(int p, hipStream_t stream, const DevTables **out);
+feint_status check_elements(const feint_elements *el);
+void fill_fwd_params(FwdParams &prm, const feint_elements *el, int form, const DevTables *T);
+const FwdVariant *chosen_variant(int p, int form);
+feint_status launch_forward(const FwdParams &prm, const FwdVariant *v, hipStream_t stream);
+
+}  // namespace feint

@@ -1,0 +1,140 @@
+// Device-side building blocks shared by the forward, adjoint and mixed
+// kernels: per-point geometry of the bilinear prism in FP64, the fused
+// coefficient block W_q, MFMA wrappers and wave-level helpers (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace feint {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef short i16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int WAVE = 64;
+
+__host__ __device__ constexpr int c_nshp(int p) { return (p + 1) * (p + 1) * (p + 2) / 2; }
+__host__ __device__ constexpr int c_nq(int p) { return (p + 1) * (p + 1) * (p + 1); }
+__host__ __device__ constexpr int c_pad16(int n) { return (n + 15) / 16 * 16; }
+__host__ __device__ constexpr int c_pad8(int n) { return (n + 7) / 8 * 8; }
+__host__ __device__ constexpr int c_cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// Per-element inputs, FP64 (gathered into registers by each wave).
+struct ElemIn {
+    double X[18];   // vertices v0..v5
+    double D[9];
+    double be[3];
+    double c, f;
+};
+
+__device__ inline void load_elem(const double *__restrict__ coords, const double *__restrict__ D,
+                                 const double *__restrict__ be, const double *__restrict__ c,
+                                 const double *__restrict__ f, int64_t e, ElemIn &E) {
+#pragma unroll
+    for (int i = 0; i < 18; ++i) E.X[i] = coords[18 * e + i];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) E.D[i] = D[9 * e + i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) E.be[i] = be[3 * e + i];
+    E.c = c[e];
+    E.f = f[e];
+}
+
+// Geometry at one reference point (xi1, xi2, zeta) of the bilinear prism
+// (Algorithm 1, step 7).  With t = (1+zeta)/2 the map is
+// x = (1-t) T_bot(xi) + t T_top(xi), so the Jacobian columns are
+//   dx/dxi1 = (1-t)(v1-v0) + t(v4-v3),  dx/dxi2 = (1-t)(v2-v0) + t(v5-v3),
+//   dx/dzeta = ((v3-v0) l0 + (v4-v1) l1 + (v5-v2) l2) / 2,
+// l = barycentrics of (xi1, xi2).  Returns det J; K = J^{-1} via cofactors.
+__device__ inline double prism_jacobian(const double *X, double xi1, double xi2, double ze,
+                                        double K[9]) {
+    const double t = 0.5 * (1.0 + ze), s = 0.5 * (1.0 - ze);
+    const double l0 = 1.0 - xi1 - xi2;
+    double c0[3], c1[3], c2[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        c0[d] = s * (X[3 + d] - X[d]) + t * (X[12 + d] - X[9 + d]);
+        c1[d] = s * (X[6 + d] - X[d]) + t * (X[15 + d] - X[9 + d]);
+        c2[d] = 0.5 * (l0 * (X[9 + d] - X[d]) + xi1 * (X[12 + d] - X[3 + d]) + xi2 * (X[15 + d] - X[6 + d]));
+    }
+    // rows of J^{-1} are the cross products of pairs of columns / det
+    const double r0[3] = {c1[1] * c2[2] - c1[2] * c2[1], c1[2] * c2[0] - c1[0] * c2[2], c1[0] * c2[1] - c1[1] * c2[0]};
+    const double r1[3] = {c2[1] * c0[2] - c2[2] * c0[1], c2[2] * c0[0] - c2[0] * c0[2], c2[0] * c0[1] - c2[1] * c0[0]};
+    const double r2[3] = {c0[1] * c1[2] - c0[2] * c1[1], c0[2] * c1[0] - c0[0] * c1[2], c0[0] * c1[1] - c0[1] * c1[0]};
+    const double det = c0[0] * r0[0] + c0[1] * r0[1] + c0[2] * r0[2];
+    const double inv = 1.0 / det;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        K[d] = r0[d] * inv;
+        K[3 + d] = r1[d] * inv;
+        K[6 + d] = r2[d] * inv;
+    }
+    return det;
+}
+
+__device__ inline void prism_map(const double *X, double xi1, double xi2, double ze, double x[3]) {
+    const double t = 0.5 * (1.0 + ze), s = 0.5 * (1.0 - ze), l0 = 1.0 - xi1 - xi2;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        x[d] = s * (l0 * X[d] + xi1 * X[3 + d] + xi2 * X[6 + d]) + t * (l0 * X[9 + d] + xi1 * X[12 + d] + xi2 * X[15 + d]);
+}
+
+// Fused coefficient block of one point (step a5 of the hot path):
+// grad phi_a . D grad phi_b = ref_a . (K D K^T) ref_b and
+// beta . grad phi_b = (K beta) . ref_b, so with wd = w det J
+//   W = wd [[ c, (K beta)^T ], [ 0, K D K^T ]]     (4x4, row-major into W[16])
+// and sf = wd f is the load-vector weight.  Returns det J.
+__device__ inline double point_block(const ElemIn &E, double xi1, double xi2, double ze, double w,
+                                     double W[16], double &sf) {
+    double K[9];
+    const double det = prism_jacobian(E.X, xi1, xi2, ze, K);
+    const double wd = w * det;
+    double KD[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            KD[3 * i + j] = K[3 * i] * E.D[j] + K[3 * i + 1] * E.D[3 + j] + K[3 * i + 2] * E.D[6 + j];
+    W[0] = wd * E.c;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        W[1 + i] = wd * (K[3 * i] * E.be[0] + K[3 * i + 1] * E.be[1] + K[3 * i + 2] * E.be[2]);
+        W[4 * (i + 1)] = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            W[4 * (i + 1) + 1 + j] = wd * (KD[3 * i] * K[3 * j] + KD[3 * i + 1] * K[3 * j + 1] + KD[3 * i + 2] * K[3 * j + 2]);
+    }
+    sf = wd * E.f;
+    return det;
+}
+
+// Compiler-level fence for data exchanged through LDS between lanes of one
+// wave (a wave's LDS operations complete in issue order).
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ---- MFMA wrappers --------------------------------------------------------
+// 16x16x4 (FP64, FP32): lane l supplies A[l%16][l/16] and B[l/16][l%16].
+// 16x16x32 (bf16, fp16): lane l supplies A[l%16][8(l/16)+v], B[8(l/16)+v][l%16].
+// FP32 accumulators: lane l holds D[4(l/16)+r][l%16], r = 0..3.
+__device__ inline f64x4 mfma4(double a, double b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f32x4 mfma4(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ inline f32x4 mfma32(f16x8 a, f16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+}  // namespace feint

@@ -1,0 +1,29 @@
+// Forward kernels, split bf16x3 form (v_mfma_f32_16x16x32_bf16), tile shapes per degree.
+#include "fwd_registry.h"
+
+namespace feint {
+namespace {
+const FwdVariant v1[] = {FEINT_K32(1, BF16X3, 1, 1)};
+const FwdVariant v2[] = {FEINT_K32(2, BF16X3, 2, 2)};
+const FwdVariant v3[] = {FEINT_K32(3, BF16X3, 3, 3), FEINT_K32(3, BF16X3, 3, 1)};
+const FwdVariant v4[] = {FEINT_K32(4, BF16X3, 5, 5), FEINT_K32(4, BF16X3, 5, 3), FEINT_K32(4, BF16X3, 5, 2)};
+const FwdVariant v5[] = {FEINT_K32(5, BF16X3, 8, 4), FEINT_K32(5, BF16X3, 4, 4), FEINT_K32(5, BF16X3, 8, 2)};
+const FwdVariant v6[] = {FEINT_K32(6, BF16X3, 13, 2), FEINT_K32(6, BF16X3, 7, 4), FEINT_K32(6, BF16X3, 13, 3)};
+const FwdVariant v7[] = {FEINT_K32(7, BF16X3, 6, 6), FEINT_K32(7, BF16X3, 6, 3), FEINT_K32(7, BF16X3, 3, 6)};
+}  // namespace
+
+#define FEINT_N(a) (int)(sizeof(a) / sizeof(a[0]))
+const FwdVariant *fwd_variants_bf16(int p, int *count) {
+    switch (p) {
+    case 1: *count = FEINT_N(v1); return v1;
+    case 2: *count = FEINT_N(v2); return v2;
+    case 3: *count = FEINT_N(v3); return v3;
+    case 4: *count = FEINT_N(v4); return v4;
+    case 5: *count = FEINT_N(v5); return v5;
+    case 6: *count = FEINT_N(v6); return v6;
+    case 7: *count = FEINT_N(v7); return v7;
+    }
+    *count = 0;
+    return nullptr;
+}
+}  // namespace feint

@@ -1,0 +1,29 @@
+// Forward kernels, FP64 form (v_mfma_f64_16x16x4_f64), tile shapes per degree.
+#include "fwd_registry.h"
+
+namespace feint {
+namespace {
+const FwdVariant v1[] = {FEINT_K4(1, double, 1, 1)};
+const FwdVariant v2[] = {FEINT_K4(2, double, 2, 2), FEINT_K4(2, double, 2, 1)};
+const FwdVariant v3[] = {FEINT_K4(3, double, 3, 3), FEINT_K4(3, double, 3, 1)};
+const FwdVariant v4[] = {FEINT_K4(4, double, 5, 5), FEINT_K4(4, double, 5, 3), FEINT_K4(4, double, 5, 1)};
+const FwdVariant v5[] = {FEINT_K4(5, double, 8, 2), FEINT_K4(5, double, 8, 4), FEINT_K4(5, double, 8, 1)};
+const FwdVariant v6[] = {FEINT_K4(6, double, 13, 1), FEINT_K4(6, double, 13, 2)};
+const FwdVariant v7[] = {FEINT_K4(7, double, 9, 2), FEINT_K4(7, double, 6, 2)};
+}  // namespace
+
+#define FEINT_N(a) (int)(sizeof(a) / sizeof(a[0]))
+const FwdVariant *fwd_variants_f64(int p, int *count) {
+    switch (p) {
+    case 1: *count = FEINT_N(v1); return v1;
+    case 2: *count = FEINT_N(v2); return v2;
+    case 3: *count = FEINT_N(v3); return v3;
+    case 4: *count = FEINT_N(v4); return v4;
+    case 5: *count = FEINT_N(v5); return v5;
+    case 6: *count = FEINT_N(v6); return v6;
+    case 7: *count = FEINT_N(v7); return v7;
+    }
+    *count = 0;
+    return nullptr;
+}
+}  // namespace feint

@@ -1,0 +1,362 @@
+// Forward element-integration kernels (hot path of Algorithm 1 generalised
+// to convection-diffusion-reaction + load vector), gfx950.
+//
+// Work decomposition.  The element matrix A_e = sum_q B_q^T W_q B_q is a GEMM
+// with M = N = n (padded to 16) and K = 4 nq: B (4nq x n) is the same for every
+// element of a degree (kept in L2 and reused by every wave), W_q (4x4) is the
+// per-point coefficient block computed in FP64 from the Jacobian.  One wave
+// owns a TM x TN block of 16x16 output tiles of one element; a workgroup holds
+// four such waves.  Per chunk of 64 points each lane computes one point's W_q
+// (FP64 geometry) into the wave's LDS slice; then, point by point (16x16x4
+// forms) or eight points at a time (16x16x32 split forms), the wave forms the
+// B-operand fragments Y = W_q B_q in registers and issues TM x TN MFMAs whose
+// A operands are rows of B read straight from the table.  The load vector
+// b_e = sum_q w_q det J_q f phi(q) is accumulated in FP64 by the waves of the
+// first column block.
+#pragma once
+#include "device_common.h"
+#include "launch.h"
+
+namespace feint {
+
+enum FormId { F64 = 0, F32 = 1, BF16X3 = 2, FP16X3 = 3 };
+
+// Row of the 16x16 output tile held in accumulator register r of lane l.
+template <typename T> __device__ inline int acc_row(int lane, int r);
+template <> __device__ inline int acc_row<double>(int lane, int r) { return 4 * r + (lane >> 4); }
+template <> __device__ inline int acc_row<float>(int lane, int r) { return 4 * (lane >> 4) + r; }
+
+template <typename T> struct AccT;
+template <> struct AccT<double> { typedef f64x4 type; };
+template <> struct AccT<float> { typedef f32x4 type; };
+
+template <int FORM> struct SplitT;
+template <> struct SplitT<BF16X3> { typedef bf16x8 vec; typedef __bf16 scal; };
+template <> struct SplitT<FP16X3> { typedef f16x8 vec; typedef _Float16 scal; };
+
+// Element handled by a work item (identity unless a permutation is given).
+__device__ inline int64_t elem_of(const FwdParams &prm, int64_t slot) {
+    return prm.perm ? (int64_t)prm.perm[slot] : slot;
+}
+__device__ inline int64_t offA_of(const FwdParams &prm, int64_t e, int n) {
+    return prm.offA ? prm.offA[e] : e * (int64_t)n * n;
+}
+__device__ inline int64_t offb_of(const FwdParams &prm, int64_t e, int n) {
+    return prm.offb ? prm.offb[e] : e * (int64_t)n;
+}
+
+// ---------------------------------------------------------------------------
+// 16x16x4 forms (FP64, FP32): one point (4 K-rows) per MFMA.
+// ---------------------------------------------------------------------------
+template <int P, typename T, int TM, int TN>
+struct K4 {
+    static constexpr int N = c_nshp(P), NP = c_pad16(N), NT = NP / 16, NQ = c_nq(P);
+    static constexpr int BM = c_cdiv(NT, TM), BN = c_cdiv(NT, TN), NBLK = BM * BN;
+    static constexpr int NBR = c_cdiv(TM * 16, 64);   // load-vector rows per lane
+    typedef typename AccT<T>::type V4;
+
+    struct Smem {
+        T W[4][64][16];
+        double sf[4][64];
+    };
+
+    // One work item: block `blk` of element slot `slot`.  `wave` indexes the
+    // wave's LDS slice.
+    __device__ static void run(const FwdParams &prm, int64_t slot, int blk, int wave, Smem &sm) {
+        const int lane = threadIdx.x & 63;
+        const int i16 = lane & 15, kg = lane >> 4;
+        const int bi = blk / BN, bj = blk % BN;
+        const int a0 = bi * TM * 16, b0 = bj * TN * 16;
+        const int64_t e = elem_of(prm, slot);
+        ElemIn E;
+        load_elem(prm.coords, prm.D, prm.beta, prm.c, prm.f, e, E);
+        const T *Bt = sizeof(T) == 8 ? (const T *)(const void *)prm.B64 : (const T *)(const void *)prm.B32;
+        V4 acc[TM][TN];
+#pragma unroll
+        for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < TN; ++tj) acc[ti][tj] = V4{0, 0, 0, 0};
+        double bacc[NBR];
+#pragma unroll
+        for (int m = 0; m < NBR; ++m) bacc[m] = 0.0;
+
+        for (int qc = 0; qc < NQ; qc += 64) {
+            const int cnt = NQ - qc < 64 ? NQ - qc : 64;
+            if (lane < cnt) {
+                const int q = qc + lane;
+                const double *qp = prm.qw + 4 * q;
+                double W[16], sf;
+                const double det = point_block(E, qp[0], qp[1], qp[2], qp[3], W, sf);
+                if (!(det > 0.0) && prm.status) atomicOr(prm.status, 1u);
+#pragma unroll
+                for (int k = 0; k < 16; ++k) sm.W[wave][lane][k] = (T)W[k];
+                sm.sf[wave][lane] = sf;
+                if (prm.xq && blk == 0) {
+                    double x[3];
+                    prism_map(E.X, qp[0], qp[1], qp[2], x);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) prm.xq[(e * NQ + q) * 3 + d] = x[d];
+                }
+            }
+            wave_sync();
+            if (bj == 0) {
+#pragma unroll
+                for (int m = 0; m < NBR; ++m) {
+                    const int row = a0 + lane + 64 * m;
+                    if (lane + 64 * m < TM * 16 && row < N) {
+                        double s = 0.0;
+                        for (int qq = 0; qq < cnt; ++qq)
+                            s += sm.sf[wave][qq] * prm.B64[(size_t)(qc + qq) * 4 * NP + row];
+                        bacc[m] += s;
+                    }
+                }
+            }
+            for (int qq = 0; qq < cnt; ++qq) {
+                const int q = qc + qq;
+                const T w0 = sm.W[wave][qq][4 * kg + 0], w1 = sm.W[wave][qq][4 * kg + 1];
+                const T w2 = sm.W[wave][qq][4 * kg + 2], w3 = sm.W[wave][qq][4 * kg + 3];
+                const T *Bq = Bt + (size_t)q * 4 * NP;
+                T yf[TN], af[TM];
+#pragma unroll
+                for (int tj = 0; tj < TN; ++tj) {
+                    yf[tj] = 0;
+                    if (b0 + tj * 16 < NP) {
+                        const T *bp = Bq + b0 + tj * 16 + i16;
+                        yf[tj] = w0 * bp[0] + w1 * bp[NP] + w2 * bp[2 * NP] + w3 * bp[3 * NP];
+                    }
+                }
+#pragma unroll
+                for (int ti = 0; ti < TM; ++ti) {
+                    af[ti] = 0;
+                    if (a0 + ti * 16 < NP) af[ti] = Bq[kg * NP + a0 + ti * 16 + i16];
+                }
+#pragma unroll
+                for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < TN; ++tj)
+                        if (a0 + ti * 16 < NP && b0 + tj * 16 < NP)
+                            acc[ti][tj] = mfma4(af[ti], yf[tj], acc[ti][tj]);
+            }
+            wave_sync();
+        }
+        T *Aout = (T *)prm.A + offA_of(prm, e, N);
+#pragma unroll
+        for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < TN; ++tj) {
+                const int col = b0 + tj * 16 + i16;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = a0 + ti * 16 + acc_row<T>(lane, r);
+                    if (row < N && col < N && a0 + ti * 16 < NP && b0 + tj * 16 < NP)
+                        Aout[(size_t)row * N + col] = acc[ti][tj][r];
+                }
+            }
+        if (bj == 0) {
+            T *bout = (T *)prm.b + offb_of(prm, e, N);
+#pragma unroll
+            for (int m = 0; m < NBR; ++m) {
+                const int row = a0 + lane + 64 * m;
+                if (lane + 64 * m < TM * 16 && row < N) bout[row] = (T)bacc[m];
+            }
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// 16x16x32 split forms (bf16x3, fp16x3): eight points (32 K-rows) per MFMA.
+// x = hi + lo with hi = rn(x), lo = rn(x - hi); products hi*hi + hi*lo + lo*hi
+// accumulate in FP32.  B is split once on the host; Y = W_q B_q is formed in
+// FP32 from the FP32 table and split in registers.  The fp16 form scales B by
+// 2^f16_shift and Y by a per-element power of two so that both use the
+// normal range, and unscales exactly at the store.
+// ---------------------------------------------------------------------------
+template <int P, int FORM, int TM, int TN>
+struct K32 {
+    static constexpr int N = c_nshp(P), NP = c_pad16(N), NT = NP / 16, NQ = c_nq(P);
+    static constexpr int NQP = c_pad8(NQ);
+    static constexpr int BM = c_cdiv(NT, TM), BN = c_cdiv(NT, TN), NBLK = BM * BN;
+    static constexpr int NBR = c_cdiv(TM * 16, 64);
+    typedef typename SplitT<FORM>::vec HV;
+    typedef typename SplitT<FORM>::scal HS;
+
+    struct Smem {
+        float W[4][64][16];
+        double sf[4][64];
+    };
+
+    __device__ static float elem_scale(const FwdParams &prm, const ElemIn &E) {
+        // largest row sum of |W_q| over the element's points, times max |B|:
+        // a bound on |Y|; scale so that the bound lies in [2^13, 2^14)
+        const int lane = threadIdx.x & 63;
+        double m = 0.0;
+        for (int qc = 0; qc < NQ; qc += 64) {
+            const int q = qc + lane;
+            if (q < NQ) {
+                const double *qp = prm.qw + 4 * q;
+                double W[16], sf;
+                point_block(E, qp[0], qp[1], qp[2], qp[3], W, sf);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const double s = fabs(W[4 * r]) + fabs(W[4 * r + 1]) + fabs(W[4 * r + 2]) + fabs(W[4 * r + 3]);
+                    m = s > m ? s : m;
+                }
+            }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double o = __shfl_xor(m, off, 64);
+            m = o > m ? o : m;
+        }
+        m *= (double)prm.bmax;
+        if (!(m > 0.0) || !(m < 1e300)) return 1.0f;
+        const int ex = 13 - (int)floor(log2(m));
+        return ldexpf(1.0f, ex < -60 ? -60 : (ex > 60 ? 60 : ex));
+    }
+
+    __device__ static void split8(const float *y, HV &hi, HV &lo) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const HS h = (HS)y[v];
+            hi[v] = h;
+            lo[v] = (HS)(y[v] - (float)h);
+        }
+    }
+
+    __device__ static void run(const FwdParams &prm, int64_t slot, int blk, int wave, Smem &sm) {
+        const int lane = threadIdx.x & 63;
+        const int i16 = lane & 15, kg = lane >> 4;
+        const int bi = blk / BN, bj = blk % BN;
+        const int a0 = bi * TM * 16, b0 = bj * TN * 16;
+        const int64_t e = elem_of(prm, slot);
+        ElemIn E;
+        load_elem(prm.coords, prm.D, prm.beta, prm.c, prm.f, e, E);
+        const float ys = FORM == FP16X3 ? elem_scale(prm, E) : 1.0f;
+        f32x4 acc[TM][TN];
+#pragma unroll
+        for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < TN; ++tj) acc[ti][tj] = f32x4{0, 0, 0, 0};
+        double bacc[NBR];
+#pragma unroll
+        for (int m = 0; m < NBR; ++m) bacc[m] = 0.0;
+
+        for (int qc = 0; qc < NQP; qc += 64) {
+            const int cnt = NQP - qc < 64 ? NQP - qc : 64;   // multiple of 8
+            if (lane < cnt) {
+                const int q = qc + lane;
+                double W[16], sf = 0.0;
+                if (q < NQ) {
+                    const double *qp = prm.qw + 4 * q;
+                    const double det = point_block(E, qp[0], qp[1], qp[2], qp[3], W, sf);
+                    if (!(det > 0.0) && prm.status) atomicOr(prm.status, 1u);
+                    if (prm.xq && blk == 0) {
+                        double x[3];
+                        prism_map(E.X, qp[0], qp[1], qp[2], x);
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) prm.xq[(e * NQ + q) * 3 + d] = x[d];
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) W[k] = 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < 16; ++k) sm.W[wave][lane][k] = (float)W[k] * ys;
+                sm.sf[wave][lane] = sf;
+            }
+            wave_sync();
+            if (bj == 0) {
+#pragma unroll
+                for (int m = 0; m < NBR; ++m) {
+                    const int row = a0 + lane + 64 * m;
+                    if (lane + 64 * m < TM * 16 && row < N) {
+                        double s = 0.0;
+                        for (int qq = 0; qq < cnt && qc + qq < NQ; ++qq)
+                            s += sm.sf[wave][qq] * prm.B64[(size_t)(qc + qq) * 4 * NP + row];
+                        bacc[m] += s;
+                    }
+                }
+            }
+            for (int kb = 0; kb < cnt / 8; ++kb) {
+                const int qa = kb * 8 + 2 * kg;        // this lane's two points (chunk-local)
+                const float *Wa = sm.W[wave][qa];
+                const float *Wb = sm.W[wave][qa + 1];
+                float wa[16], wb[16];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) { wa[k] = Wa[k]; wb[k] = Wb[k]; }
+                const float *Bqa = prm.B32 + (size_t)(qc + qa) * 4 * NP;
+                HV yh[TN], yl[TN], ah[TM], al[TM];
+#pragma unroll
+                for (int tj = 0; tj < TN; ++tj) {
+                    if (b0 + tj * 16 < NP) {
+                        const float *bp = Bqa + b0 + tj * 16 + i16;
+                        float s0[4], s1[4], y[8];
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) { s0[s] = bp[s * NP]; s1[s] = bp[(4 + s) * NP]; }
+                        y[0] = wa[0] * s0[0] + wa[1] * s0[1] + wa[2] * s0[2] + wa[3] * s0[3];
+                        y[4] = wb[0] * s1[0] + wb[1] * s1[1] + wb[2] * s1[2] + wb[3] * s1[3];
+#pragma unroll
+                        for (int r = 1; r < 4; ++r) {
+                            y[r] = wa[4 * r + 1] * s0[1] + wa[4 * r + 2] * s0[2] + wa[4 * r + 3] * s0[3];
+                            y[4 + r] = wb[4 * r + 1] * s1[1] + wb[4 * r + 2] * s1[2] + wb[4 * r + 3] * s1[3];
+                        }
+                        split8(y, yh[tj], yl[tj]);
+                    }
+                }
+                const size_t kbg = (size_t)(qc / 8 + kb);
+#pragma unroll
+                for (int ti = 0; ti < TM; ++ti) {
+                    if (a0 + ti * 16 < NP) {
+                        const size_t o = (kbg * NP + a0 + ti * 16 + i16) * 32 + 8 * kg;
+                        ah[ti] = *(const HV *)(prm.Bhi + o);
+                        al[ti] = *(const HV *)(prm.Blo + o);
+                    }
+                }
+#pragma unroll
+                for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < TN; ++tj)
+                        if (a0 + ti * 16 < NP && b0 + tj * 16 < NP) {
+                            acc[ti][tj] = mfma32(al[ti], yh[tj], acc[ti][tj]);
+                            acc[ti][tj] = mfma32(ah[ti], yl[tj], acc[ti][tj]);
+                            acc[ti][tj] = mfma32(ah[ti], yh[tj], acc[ti][tj]);
+                        }
+            }
+            wave_sync();
+        }
+        const float unscale = FORM == FP16X3 ? ldexpf(1.0f, -prm.f16_shift) / ys : 1.0f;
+        float *Aout = (float *)prm.A + offA_of(prm, e, N);
+#pragma unroll
+        for (int ti = 0; ti < TM; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < TN; ++tj) {
+                const int col = b0 + tj * 16 + i16;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = a0 + ti * 16 + 4 * kg + r;
+                    if (row < N && col < N && a0 + ti * 16 < NP && b0 + tj * 16 < NP)
+                        Aout[(size_t)row * N + col] = acc[ti][tj][r] * unscale;
+                }
+            }
+        if (bj == 0) {
+            float *bout = (float *)prm.b + offb_of(prm, e, N);
+#pragma unroll
+            for (int m = 0; m < NBR; ++m) {
+                const int row = a0 + lane + 64 * m;
+                if (lane + 64 * m < TM * 16 && row < N) bout[row] = (float)bacc[m];
+            }
+        }
+    }
+};
+
+// Grid-stride-free direct launch: workgroup of 4 waves, one work item each.
+template <class KER>
+__global__ __launch_bounds__(256) void fwd_direct(FwdParams prm) {
+    __shared__ typename KER::Smem sm;
+    const int wave = wave_uniform(threadIdx.x >> 6);
+    const int64_t item = (int64_t)blockIdx.x * 4 + wave;
+    if (item >= prm.ne * KER::NBLK) return;
+    KER::run(prm, item / KER::NBLK, (int)(item % KER::NBLK), wave, sm);
+}
+
+}  // namespace feint

@@ -1,0 +1,41 @@
+// Host-visible kernel parameter blocks and launcher registry.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace feint {
+
+struct FwdParams {
+    const double *coords, *D, *beta, *c, *f;
+    int64_t ne;
+    void *A, *b;
+    double *xq;
+    uint32_t *status;
+    const double *qw;        // [nqp][4]
+    const double *B64;       // [nqp][4][npad]
+    const float *B32;        // [nqp][4][npad]
+    const uint16_t *Bhi;     // [nkb][npad][32] split table of the form (bf16 or fp16)
+    const uint16_t *Blo;
+    float bmax;              // max |B| (fp16 form: used for the per-element scale)
+    int f16_shift;           // fp16 tables hold B * 2^f16_shift
+    // mixed-degree launches: element ids in bucket order and packed offsets
+    const int32_t *perm;     // nullable: element of work slot i is perm[i]
+    const int64_t *offA, *offb;
+};
+
+// One compiled tile shape of a (degree, form): TM x TN 16x16 output tiles
+// per wave; `launch` enqueues the direct (one work item per wave) kernel.
+struct FwdVariant {
+    int tm, tn;
+    void (*launch)(const FwdParams &, hipStream_t);
+    int64_t (*items_per_elem)();
+};
+
+// Registry per form (0 FP64, 1 FP32, 2 BF16X3, 3 FP16X3); p in 1..7.
+const FwdVariant *fwd_variants(int form, int p, int *count);
+const FwdVariant *fwd_variants_f64(int p, int *count);
+const FwdVariant *fwd_variants_f32(int p, int *count);
+const FwdVariant *fwd_variants_bf16(int p, int *count);
+const FwdVariant *fwd_variants_f16(int p, int *count);
+
+}  // namespace feint

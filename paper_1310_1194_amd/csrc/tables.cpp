@@ -1,0 +1,323 @@
+// Host construction of the reference tables (FP64, then rounded or split for
+// the reduced-precision forms).
+//
+// Constructions used here:
+//   * Gauss-Legendre nodes/weights and the interior Gauss-Lobatto nodes are
+//     eigenvalues of the symmetric Jacobi matrices of the Legendre and the
+//     Jacobi(1,1) recurrences (Golub-Welsch), found with cyclic Jacobi
+//     rotations; a weight is 2 * (first eigenvector component)^2.
+//   * Lagrange bases are obtained by inverting the generalised Vandermonde
+//     matrix of a Legendre-product modal basis at the nodes (LU with partial
+//     pivoting in extended precision), then evaluating the modal basis and
+//     its derivatives at each quadrature point.
+#include "tables.h"
+
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+
+namespace feint {
+namespace {
+
+// Eigen-decomposition of a small symmetric matrix a (n x n, row-major,
+// destroyed) by cyclic Jacobi rotations.  vals[j] with eigenvector column
+// vecs[:, j].
+void jacobi_eigen(int n, std::vector<long double> &a, std::vector<long double> &vals,
+                  std::vector<long double> &vecs) {
+    vecs.assign(n * n, 0.0L);
+    for (int i = 0; i < n; ++i) vecs[i * n + i] = 1.0L;
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        long double off = 0, diag = 0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                (i == j ? diag : off) += a[i * n + j] * a[i * n + j];
+        if (off <= 1e-40L * diag) break;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                long double apq = a[p * n + q];
+                if (std::fabs(apq) < 1e-300L) continue;
+                long double theta = (a[q * n + q] - a[p * n + p]) / (2.0L * apq);
+                long double t = (theta >= 0 ? 1.0L : -1.0L) /
+                                (std::fabs(theta) + std::sqrt(theta * theta + 1.0L));
+                long double c = 1.0L / std::sqrt(t * t + 1.0L), s = t * c;
+                // A <- R^T A R with R the rotation in the (p, q) plane
+                for (int k = 0; k < n; ++k) {
+                    long double akp = a[k * n + p], akq = a[k * n + q];
+                    a[k * n + p] = c * akp - s * akq;
+                    a[k * n + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    long double apk = a[p * n + k], aqk = a[q * n + k];
+                    a[p * n + k] = c * apk - s * aqk;
+                    a[q * n + k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    long double vkp = vecs[k * n + p], vkq = vecs[k * n + q];
+                    vecs[k * n + p] = c * vkp - s * vkq;
+                    vecs[k * n + q] = s * vkp + c * vkq;
+                }
+            }
+    }
+    vals.resize(n);
+    for (int i = 0; i < n; ++i) vals[i] = a[i * n + i];
+}
+
+// Symmetric tridiagonal matrix with zero diagonal and off-diagonal
+// entries off[k] at (k, k+1); eigenvalues ascending with first components.
+void tridiag_eigen(int n, const std::vector<long double> &off, std::vector<long double> &x,
+                   std::vector<long double> &v0) {
+    std::vector<long double> a(n * n, 0.0L), vals, vecs;
+    for (int k = 0; k + 1 < n; ++k) a[k * n + k + 1] = a[(k + 1) * n + k] = off[k];
+    jacobi_eigen(n, a, vals, vecs);
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    for (int i = 0; i < n; ++i)       // selection sort, n <= 24
+        for (int j = i + 1; j < n; ++j)
+            if (vals[idx[j]] < vals[idx[i]]) std::swap(idx[i], idx[j]);
+    x.resize(n);
+    v0.resize(n);
+    for (int i = 0; i < n; ++i) {
+        x[i] = vals[idx[i]];
+        long double nrm = 0;
+        for (int k = 0; k < n; ++k) nrm += vecs[k * n + idx[i]] * vecs[k * n + idx[i]];
+        v0[i] = vecs[idx[i]] / std::sqrt(nrm);
+    }
+}
+
+// Legendre P_k(x) and P_k'(x) for k = 0..m (values into P[], derivatives into dP[]).
+void legendre_all(int m, long double x, long double *P, long double *dP) {
+    P[0] = 1.0L;
+    dP[0] = 0.0L;
+    if (m >= 1) { P[1] = x; dP[1] = 1.0L; }
+    for (int k = 1; k < m; ++k) {
+        P[k + 1] = ((2 * k + 1) * x * P[k] - k * P[k - 1]) / (k + 1);
+        dP[k + 1] = dP[k - 1] + (2 * k + 1) * P[k];
+    }
+}
+
+// Inverse of a small dense matrix by LU with partial pivoting.
+std::vector<long double> invert(int n, std::vector<long double> m) {
+    std::vector<int> piv(n);
+    for (int i = 0; i < n; ++i) piv[i] = i;
+    for (int c = 0; c < n; ++c) {
+        int best = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(m[r * n + c]) > std::fabs(m[best * n + c])) best = r;
+        if (m[best * n + c] == 0.0L) throw std::runtime_error("singular Vandermonde matrix");
+        if (best != c) {
+            for (int k = 0; k < n; ++k) std::swap(m[c * n + k], m[best * n + k]);
+            std::swap(piv[c], piv[best]);
+        }
+        for (int r = c + 1; r < n; ++r) {
+            long double l = m[r * n + c] / m[c * n + c];
+            m[r * n + c] = l;
+            for (int k = c + 1; k < n; ++k) m[r * n + k] -= l * m[c * n + k];
+        }
+    }
+    std::vector<long double> inv(n * n, 0.0L);
+    for (int col = 0; col < n; ++col) {
+        std::vector<long double> y(n);
+        for (int i = 0; i < n; ++i) {          // forward: L y = P e_col
+            long double s = (piv[i] == col) ? 1.0L : 0.0L;
+            for (int k = 0; k < i; ++k) s -= m[i * n + k] * y[k];
+            y[i] = s;
+        }
+        for (int i = n - 1; i >= 0; --i) {     // backward: U x = y
+            long double s = y[i];
+            for (int k = i + 1; k < n; ++k) s -= m[i * n + k] * inv[k * n + col];
+            inv[i * n + col] = s / m[i * n + i];
+        }
+    }
+    return inv;
+}
+
+struct ModalBasis {
+    int p = 0, ntri = 0;
+    std::vector<long double> Ctri;   // [mode][t] inverse Vandermonde of the triangle
+    std::vector<long double> Cline;  // [mode][k] inverse Vandermonde of the GLL line
+    std::vector<int> mi, mj;         // triangle mode m = P_mi(2 xi1 - 1) P_mj(2 xi2 - 1)
+};
+
+ModalBasis make_modal(int p) {
+    ModalBasis mb;
+    mb.p = p;
+    mb.ntri = ntri_of(p);
+    for (int j = 0; j <= p; ++j)
+        for (int i = 0; i + j <= p; ++i) { mb.mi.push_back(i); mb.mj.push_back(j); }
+    const int nt = mb.ntri;
+    std::vector<long double> V(nt * nt), Pa(p + 1), dPa(p + 1), Pb(p + 1), dPb(p + 1);
+    int t = 0;
+    for (int j = 0; j <= p; ++j)
+        for (int i = 0; i + j <= p; ++i, ++t) {
+            long double x1 = (long double)i / p, x2 = (long double)j / p;
+            legendre_all(p, 2 * x1 - 1, Pa.data(), dPa.data());
+            legendre_all(p, 2 * x2 - 1, Pb.data(), dPb.data());
+            for (int m = 0; m < nt; ++m) V[t * nt + m] = Pa[mb.mi[m]] * Pb[mb.mj[m]];
+        }
+    mb.Ctri = invert(nt, V);
+    double z[kMaxP + 1];
+    gauss_lobatto_nodes(p, z);
+    std::vector<long double> V1((p + 1) * (p + 1));
+    for (int k = 0; k <= p; ++k) {
+        legendre_all(p, z[k], Pa.data(), dPa.data());
+        for (int m = 0; m <= p; ++m) V1[k * (p + 1) + m] = Pa[m];
+    }
+    mb.Cline = invert(p + 1, V1);
+    return mb;
+}
+
+void eval_modal(const ModalBasis &mb, const double *xi, double *phi, double *dphi) {
+    const int p = mb.p, nt = mb.ntri;
+    long double Pa[kMaxP + 1], dPa[kMaxP + 1], Pb[kMaxP + 1], dPb[kMaxP + 1], Pz[kMaxP + 1], dPz[kMaxP + 1];
+    legendre_all(p, 2.0L * xi[0] - 1, Pa, dPa);
+    legendre_all(p, 2.0L * xi[1] - 1, Pb, dPb);
+    legendre_all(p, (long double)xi[2], Pz, dPz);
+    long double psi[64], d1[64], d2[64], l[kMaxP + 1], dl[kMaxP + 1];
+    for (int t = 0; t < nt; ++t) {
+        long double v = 0, g1 = 0, g2 = 0;
+        for (int m = 0; m < nt; ++m) {
+            long double c = mb.Ctri[m * nt + t];
+            v += c * Pa[mb.mi[m]] * Pb[mb.mj[m]];
+            g1 += c * 2.0L * dPa[mb.mi[m]] * Pb[mb.mj[m]];
+            g2 += c * 2.0L * Pa[mb.mi[m]] * dPb[mb.mj[m]];
+        }
+        psi[t] = v; d1[t] = g1; d2[t] = g2;
+    }
+    for (int k = 0; k <= p; ++k) {
+        long double v = 0, g = 0;
+        for (int m = 0; m <= p; ++m) {
+            v += mb.Cline[m * (p + 1) + k] * Pz[m];
+            g += mb.Cline[m * (p + 1) + k] * dPz[m];
+        }
+        l[k] = v; dl[k] = g;
+    }
+    for (int k = 0; k <= p; ++k)
+        for (int t = 0; t < nt; ++t) {
+            int a = k * nt + t;
+            phi[a] = (double)(psi[t] * l[k]);
+            dphi[3 * a + 0] = (double)(d1[t] * l[k]);
+            dphi[3 * a + 1] = (double)(d2[t] * l[k]);
+            dphi[3 * a + 2] = (double)(psi[t] * dl[k]);
+        }
+}
+
+uint16_t to_bf16(float x) {              // round to nearest even
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+float from_bf16(uint16_t h) {
+    uint32_t u = (uint32_t)h << 16;
+    float x;
+    std::memcpy(&x, &u, 4);
+    return x;
+}
+uint16_t to_f16(double x) {
+    _Float16 h = (_Float16)(float)x;
+    uint16_t u;
+    std::memcpy(&u, &h, 2);
+    return u;
+}
+double from_f16(uint16_t u) {
+    _Float16 h;
+    std::memcpy(&h, &u, 2);
+    return (double)(float)h;
+}
+
+}  // namespace
+
+void gauss_legendre_gw(int n, double *x, double *w) {
+    if (n == 1) { x[0] = 0.0; w[0] = 2.0; return; }
+    std::vector<long double> off(n - 1), xs, v0;
+    for (int k = 1; k < n; ++k) off[k - 1] = k / std::sqrt(4.0L * k * k - 1.0L);
+    tridiag_eigen(n, off, xs, v0);
+    for (int i = 0; i < n; ++i) {
+        x[i] = (double)xs[i];
+        w[i] = (double)(2.0L * v0[i] * v0[i]);
+    }
+}
+
+void gauss_lobatto_nodes(int p, double *x) {
+    x[0] = -1.0;
+    x[p] = 1.0;
+    if (p < 2) return;
+    int m = p - 1;   // roots of P_p' = roots of the Jacobi(1,1) polynomial of degree p-1
+    if (m == 1) { x[1] = 0.0; return; }
+    std::vector<long double> off(m - 1), xs, v0;
+    for (int k = 1; k < m; ++k) off[k - 1] = std::sqrt((long double)k * (k + 2) / ((2.0L * k + 1) * (2.0L * k + 3)));
+    tridiag_eigen(m, off, xs, v0);
+    for (int i = 0; i < m; ++i) x[i + 1] = (double)xs[i];
+}
+
+void lagrange_prism_eval(int p, const double *xi, double *phi, double *dphi) {
+    ModalBasis mb = make_modal(p);
+    eval_modal(mb, xi, phi, dphi);
+}
+
+HostTables build_tables(int p) {
+    if (p < 1 || p > kMaxP) throw std::runtime_error("degree out of range");
+    HostTables T;
+    T.p = p;
+    T.n = nshp_of(p);
+    T.npad = pad16(T.n);
+    T.nq = nq_of(p);
+    T.nqp = pad8(T.nq);
+    T.nkb = T.nqp / 8;
+    const int n1 = p + 1, n = T.n, np = T.npad;
+    double g[kMaxP + 1], gw[kMaxP + 1];
+    gauss_legendre_gw(n1, g, gw);
+    T.qw.assign((size_t)T.nqp * 4, 0.0);
+    for (int q = T.nq; q < T.nqp; ++q) {      // padding points: centroid, zero weight
+        T.qw[4 * q + 0] = 1.0 / 3.0;
+        T.qw[4 * q + 1] = 1.0 / 3.0;
+    }
+    for (int k = 0; k < n1; ++k)
+        for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n1; ++i) {
+                int q = (k * n1 + j) * n1 + i;
+                T.qw[4 * q + 0] = (1.0 + g[i]) * (1.0 - g[j]) / 4.0;
+                T.qw[4 * q + 1] = (1.0 + g[j]) / 2.0;
+                T.qw[4 * q + 2] = g[k];
+                T.qw[4 * q + 3] = gw[i] * gw[j] * gw[k] * (1.0 - g[j]) / 8.0;
+            }
+    ModalBasis mb = make_modal(p);
+    T.B64.assign((size_t)T.nqp * 4 * np, 0.0);
+    std::vector<double> phi(n), dphi(3 * n);
+    for (int q = 0; q < T.nq; ++q) {
+        eval_modal(mb, &T.qw[4 * q], phi.data(), dphi.data());
+        for (int a = 0; a < n; ++a) {
+            T.B64[((size_t)q * 4 + 0) * np + a] = phi[a];
+            for (int r = 0; r < 3; ++r) T.B64[((size_t)q * 4 + 1 + r) * np + a] = dphi[3 * a + r];
+        }
+    }
+    T.B32.resize(T.B64.size());
+    double bmax = 0.0;
+    for (size_t i = 0; i < T.B64.size(); ++i) {
+        T.B32[i] = (float)T.B64[i];
+        bmax = std::fmax(bmax, std::fabs(T.B64[i]));
+    }
+    // fp16 tables are scaled so that max |B| lies in [2^13, 2^14)
+    T.f16_shift = 13 - (int)std::floor(std::log2(bmax));
+    const double fs = std::ldexp(1.0, T.f16_shift);
+    const size_t nsplit = (size_t)T.nkb * np * 32;
+    T.bf_hi.assign(nsplit, 0); T.bf_lo.assign(nsplit, 0);
+    T.hf_hi.assign(nsplit, 0); T.hf_lo.assign(nsplit, 0);
+    for (int kb = 0; kb < T.nkb; ++kb)
+        for (int a = 0; a < np; ++a)
+            for (int k = 0; k < 32; ++k) {
+                int q = kb * 8 + k / 4, r = k % 4;
+                double x = T.B64[((size_t)q * 4 + r) * np + a];
+                size_t o = ((size_t)kb * np + a) * 32 + k;
+                uint16_t h = to_bf16((float)x);
+                T.bf_hi[o] = h;
+                T.bf_lo[o] = to_bf16((float)(x - (double)from_bf16(h)));
+                double xs = x * fs;
+                uint16_t hh = to_f16(xs);
+                T.hf_hi[o] = hh;
+                T.hf_lo[o] = to_f16(xs - from_f16(hh));
+            }
+    return T;
+}
+
+}  // namespace feint

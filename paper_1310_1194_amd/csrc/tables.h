@@ -1,0 +1,39 @@
+// Reference tables of one polynomial degree: quadrature points and weights
+// and the shape-function values and reference gradients at every point,
+// laid out for the kernels.  These are the data the paper's Algorithm 1
+// reads in steps 3 and 6 (and, in Sec. 3, recommends keeping in fast memory
+// because they are identical for every element of a degree).
+#pragma once
+#include <cstdint>
+#include <vector>
+
+namespace feint {
+
+constexpr int kMaxP = 7;
+
+inline int nshp_of(int p) { return (p + 1) * (p + 1) * (p + 2) / 2; }
+inline int ntri_of(int p) { return (p + 1) * (p + 2) / 2; }
+inline int nq_of(int p) { return (p + 1) * (p + 1) * (p + 1); }
+inline int pad16(int n) { return (n + 15) / 16 * 16; }
+inline int pad8(int n) { return (n + 7) / 8 * 8; }
+
+struct HostTables {
+    int p = 0, n = 0, npad = 0, nq = 0, nqp = 0, nkb = 0;
+    int f16_shift = 0;               // fp16 tables hold B * 2^f16_shift
+    std::vector<double> qw;          // [nqp][4]  xi1, xi2, zeta, w  (padded points: w = 0)
+    std::vector<double> B64;         // [nqp][4][npad]  rows: phi, d/dxi1, d/dxi2, d/dzeta
+    std::vector<float> B32;          // same, rounded to FP32
+    std::vector<uint16_t> bf_hi, bf_lo;   // [nkb][npad][32]  k = 4*(point in block) + row
+    std::vector<uint16_t> hf_hi, hf_lo;   // same layout, fp16 of B * 2^f16_shift
+};
+
+// Build every table of degree p (1..7) in FP64 on the host.
+HostTables build_tables(int p);
+
+// Pieces exposed for the CPU tests of the library's host logic.
+void gauss_legendre_gw(int n, double *x, double *w);     // Golub-Welsch
+void gauss_lobatto_nodes(int p, double *x);               // p+1 nodes, ascending
+// phi[n], dphi[n][3] at one reference point, through the Vandermonde construction.
+void lagrange_prism_eval(int p, const double *xi, double *phi, double *dphi);
+
+}  // namespace feint

@@ -1,0 +1,76 @@
+"""CPU tests of the C-ABI library: it loads, exports every declared symbol, and
+rejects bad arguments on the host before any device work."""
+import ctypes
+import re
+from pathlib import Path
+
+import pytest
+
+from paper_1310_1194_amd import native
+
+ROOT = Path(__file__).resolve().parent.parent
+
+
+def declared_symbols():
+    hdr = (ROOT / "include" / "feint.h").read_text()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    return sorted(set(re.findall(r"\b(feint_[a-z0-9_]+)\s*\(", hdr)))
+
+
+def test_header_and_binding_agree():
+    assert declared_symbols() == sorted(native.EXPORTS)
+
+
+def test_library_exports_every_symbol():
+    L = native.lib()
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+
+
+def test_counts():
+    L = native.lib()
+    assert [L.feint_nshp(p) for p in range(0, 9)] == [-1, 6, 18, 40, 75, 126, 196, 288, -1]
+    assert [L.feint_nq(p) for p in range(1, 8)] == [(p + 1) ** 3 for p in range(1, 8)]
+    assert L.feint_elem_size(0) == 8 and L.feint_elem_size(2) == 4 and L.feint_elem_size(9) == 0
+
+
+def _el(ne, null=False):
+    v = 0 if null else 0x1000
+    return native.Elements(v, v, v, v, v, ne)
+
+
+def test_host_validation_before_device_work():
+    L = native.lib()
+    el = _el(4)
+    A = ctypes.c_void_p(0x2000)
+    s = ctypes.c_void_p(0)
+    assert L.feint_integrate(None, 2, 0, A, A, None, None, s) == -1
+    assert L.feint_integrate(ctypes.byref(el), 0, 0, A, A, None, None, s) == -2
+    assert L.feint_integrate(ctypes.byref(el), 8, 0, A, A, None, None, s) == -2
+    assert L.feint_integrate(ctypes.byref(el), 2, 7, A, A, None, None, s) == -3
+    assert L.feint_integrate(ctypes.byref(_el(-1)), 2, 0, A, A, None, None, s) == -1
+    assert L.feint_integrate(ctypes.byref(_el(4, null=True)), 2, 0, A, A, None, None, s) == -1
+    assert L.feint_integrate(ctypes.byref(el), 2, 0, None, A, None, None, s) == -1
+    assert L.feint_integrate(ctypes.byref(_el(0, null=True)), 2, 0, None, None, None, None, s) == 0
+    G = ctypes.c_void_p(0x3000)
+    assert L.feint_integrate_adjoint(ctypes.byref(el), 2, 2, G, G, G, G, G, G, G, s) == -3
+    assert L.feint_integrate_adjoint(ctypes.byref(el), 9, 0, G, G, G, G, G, G, G, s) == -2
+
+
+def test_tiles():
+    L = native.lib()
+    for p in range(1, 8):
+        for form in range(4):
+            n = L.feint_tile_count(p, form)
+            assert n >= 1
+            buf = ctypes.create_string_buffer(16)
+            assert L.feint_tile_describe(p, form, n - 1, buf, 16) == 0
+            assert re.fullmatch(rb"\d+x\d+", buf.value)
+            assert L.feint_tile_set(p, form, n) == -1
+    assert L.feint_tile_count(0, 0) == 0
+
+
+def test_status_strings():
+    L = native.lib()
+    for code in native.STATUS:
+        assert L.feint_status_string(code).decode() == native.STATUS[code]
