@@ -51,7 +51,7 @@ feint_status prepare_tables(int p) {
     auto align = [](size_t x) { return (x + 255) / 256 * 256; };
     const size_t s_qw = align(H.qw.size() * 8), s_b64 = align(H.B64.size() * 8), s_b32 = align(H.B32.size() * 4);
     const size_t s_sp = align(H.bf_hi.size() * 2);
-    const size_t total = s_qw + s_b64 + s_b32 + 4 * s_sp;
+    const size_t total = s_qw + 2 * s_b64 + 2 * s_b32 + 4 * s_sp;
     char *base = nullptr;
     e = hipMalloc((void **)&base, total);
     if (e != hipSuccess) { set_error("hipMalloc(tables)", e); return FEINT_ERR_HIP; }
@@ -72,6 +72,8 @@ feint_status prepare_tables(int p) {
     T->qw = (const double *)put(H.qw.data(), H.qw.size() * 8, s_qw);
     T->B64 = (const double *)put(H.B64.data(), H.B64.size() * 8, s_b64);
     T->B32 = (const float *)put(H.B32.data(), H.B32.size() * 4, s_b32);
+    T->BT64 = (const double *)put(H.BT64.data(), H.BT64.size() * 8, s_b64);
+    T->BT32 = (const float *)put(H.BT32.data(), H.BT32.size() * 4, s_b32);
     T->bf_hi = (const uint16_t *)put(H.bf_hi.data(), H.bf_hi.size() * 2, s_sp);
     T->bf_lo = (const uint16_t *)put(H.bf_lo.data(), H.bf_lo.size() * 2, s_sp);
     T->hf_hi = (const uint16_t *)put(H.hf_hi.data(), H.hf_hi.size() * 2, s_sp);

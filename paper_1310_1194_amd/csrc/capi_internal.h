@@ -12,8 +12,8 @@ namespace feint {
 struct DevTables {
     int p, n, npad, nq, nqp, nkb, f16_shift;
     float bmax;
-    const double *qw, *B64;
-    const float *B32;
+    const double *qw, *B64, *BT64;
+    const float *B32, *BT32;
     const uint16_t *bf_hi, *bf_lo, *hf_hi, *hf_lo;
     void *base;
 };

@@ -291,6 +291,15 @@ HostTables build_tables(int p) {
             for (int r = 0; r < 3; ++r) T.B64[((size_t)q * 4 + 1 + r) * np + a] = dphi[3 * a + r];
         }
     }
+    T.BT64.assign(T.B64.size(), 0.0);
+    T.BT32.assign(T.B64.size(), 0.0f);
+    for (int q = 0; q < T.nqp; ++q)
+        for (int r = 0; r < 4; ++r)
+            for (int a = 0; a < np; ++a) {
+                const double v = T.B64[((size_t)q * 4 + r) * np + a];
+                T.BT64[(size_t)a * T.nqp * 4 + q * 4 + r] = v;
+                T.BT32[(size_t)a * T.nqp * 4 + q * 4 + r] = (float)v;
+            }
     T.B32.resize(T.B64.size());
     double bmax = 0.0;
     for (size_t i = 0; i < T.B64.size(); ++i) {

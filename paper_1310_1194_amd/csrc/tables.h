@@ -23,6 +23,8 @@ struct HostTables {
     std::vector<double> qw;          // [nqp][4]  xi1, xi2, zeta, w  (padded points: w = 0)
     std::vector<double> B64;         // [nqp][4][npad]  rows: phi, d/dxi1, d/dxi2, d/dzeta
     std::vector<float> B32;          // same, rounded to FP32
+    std::vector<double> BT64;        // [npad][nqp*4]  transpose of B64 (shape-function major)
+    std::vector<float> BT32;         // same, FP32
     std::vector<uint16_t> bf_hi, bf_lo;   // [nkb][npad][32]  k = 4*(point in block) + row
     std::vector<uint16_t> hf_hi, hf_lo;   // same layout, fp16 of B * 2^f16_shift
 };
