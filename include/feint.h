@@ -157,6 +157,17 @@ feint_status feint_mixed_graph_capture(feint_mixed_plan *plan, const feint_eleme
                                        void *stream);
 /* Replay the captured graph on `stream`. */
 feint_status feint_mixed_graph_launch(feint_mixed_plan *plan, void *stream);
+/* Time each compiled set of per-degree tile shapes of the persistent launch
+   (`reps` launches each, after bucketing with feint_mixed_bucket) and keep
+   the fastest in the plan; *best_ms receives its mean launch time. */
+feint_status feint_mixed_autotune(feint_mixed_plan *plan, const feint_elements *el,
+                                  void *A_packed, void *b_packed, const int64_t *offA,
+                                  const int64_t *offb, int reps, double *best_ms, void *stream);
+/* Number of compiled tile sets of the plan's form, the one in use, and a
+   forced choice. */
+int feint_mixed_tile_count(const feint_mixed_plan *plan);
+int feint_mixed_tile_get(const feint_mixed_plan *plan);
+feint_status feint_mixed_tile_set(feint_mixed_plan *plan, int tile);
 void feint_mixed_plan_destroy(feint_mixed_plan *plan);
 
 /* ---- Tile autotuning -------------------------------------------------------

@@ -151,3 +151,81 @@ def autotune(coords, D, beta, c, f, p: int, form: str, A, b, reps: int = 3) -> f
     check("feint_autotune", lib().feint_autotune(ctypes.byref(el), int(p), FORMS[form], _ptr(A), _ptr(b),
                                                  int(reps), ctypes.byref(best), _stream()))
     return best.value
+
+
+class MixedPlan:
+    """Mixed-degree batches (degrees 1..6) through one persistent,
+    degree-bucketed launch; optionally captured once into a HIP graph."""
+
+    def __init__(self, ne_max: int, form: str = "fp32"):
+        if form not in ("fp32", "fp64"):
+            raise ValueError("mixed batches support the fp32 and fp64 forms")
+        self.form = form
+        self.ne_max = int(ne_max)
+        h = ctypes.c_void_p()
+        check("feint_mixed_plan_create", lib().feint_mixed_plan_create(self.ne_max, FORMS[form], ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().feint_mixed_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def bucket(self, p, status=None):
+        """Degree bucketing of p (int8 device tensor); returns (offA, offb), int64 [ne+1]."""
+        if p.dtype != torch.int8 or not p.is_cuda or not p.is_contiguous():
+            raise TypeError("p must be a contiguous int8 CUDA tensor")
+        ne = p.numel()
+        offA = torch.empty(ne + 1, dtype=torch.int64, device=p.device)
+        offb = torch.empty(ne + 1, dtype=torch.int64, device=p.device)
+        check("feint_mixed_bucket", lib().feint_mixed_bucket(self._h, _ptr(p), ne, _ptr(offA), _ptr(offb),
+                                                             _ptr(status), _stream()))
+        return offA, offb
+
+    def alloc_outputs(self, offA, offb):
+        """Packed outputs sized from the totals in offA[-1], offb[-1] (synchronises)."""
+        dt = out_dtype(self.form)
+        nA, nb = int(offA[-1].item()), int(offb[-1].item())
+        return (torch.empty(max(nA, 1), dtype=dt, device=offA.device),
+                torch.empty(max(nb, 1), dtype=dt, device=offA.device))
+
+    def integrate(self, coords, D, beta, c, f, A, b, offA, offb, status=None):
+        el = elements(coords, D, beta, c, f)
+        check("feint_integrate_mixed", lib().feint_integrate_mixed(self._h, ctypes.byref(el), _ptr(A), _ptr(b),
+                                                                   _ptr(offA), _ptr(offb), _ptr(status), _stream()))
+
+    def capture(self, coords, D, beta, c, f, p, A, b, offA, offb, status=None):
+        """Capture bucketing + persistent launch for these buffers into a HIP graph."""
+        el = elements(coords, D, beta, c, f)
+        check("feint_mixed_graph_capture",
+              lib().feint_mixed_graph_capture(self._h, ctypes.byref(el), _ptr(p), _ptr(A), _ptr(b), _ptr(offA),
+                                              _ptr(offb), _ptr(status), _stream()))
+
+    def replay(self):
+        check("feint_mixed_graph_launch", lib().feint_mixed_graph_launch(self._h, _stream()))
+
+    def autotune(self, coords, D, beta, c, f, A, b, offA, offb, reps: int = 2) -> float:
+        el = elements(coords, D, beta, c, f)
+        best = ctypes.c_double(0)
+        check("feint_mixed_autotune", lib().feint_mixed_autotune(self._h, ctypes.byref(el), _ptr(A), _ptr(b),
+                                                                 _ptr(offA), _ptr(offb), int(reps),
+                                                                 ctypes.byref(best), _stream()))
+        return best.value
+
+    @property
+    def tile(self) -> int:
+        return lib().feint_mixed_tile_get(self._h)
+
+    @tile.setter
+    def tile(self, t: int):
+        check("feint_mixed_tile_set", lib().feint_mixed_tile_set(self._h, int(t)))
+
+    @property
+    def tile_count(self) -> int:
+        return lib().feint_mixed_tile_count(self._h)

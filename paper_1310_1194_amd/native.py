@@ -20,7 +20,8 @@ EXPORTS = (
     "feint_nshp", "feint_nq", "feint_elem_size", "feint_prepare", "feint_integrate",
     "feint_integrate_adjoint", "feint_mixed_plan_create", "feint_mixed_bucket",
     "feint_integrate_mixed", "feint_mixed_graph_capture", "feint_mixed_graph_launch",
-    "feint_mixed_plan_destroy", "feint_tile_count", "feint_tile_get", "feint_tile_set",
+    "feint_mixed_plan_destroy", "feint_mixed_autotune", "feint_mixed_tile_count", "feint_mixed_tile_get",
+    "feint_mixed_tile_set", "feint_tile_count", "feint_tile_get", "feint_tile_set",
     "feint_tile_describe", "feint_autotune", "feint_status_string", "feint_last_error",
     "feint_shutdown",
 )
@@ -68,6 +69,10 @@ def lib() -> ctypes.CDLL:
             "feint_mixed_graph_capture": (_i, [_vp, P, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
             "feint_mixed_graph_launch": (_i, [_vp, _vp]),
             "feint_mixed_plan_destroy": (None, [_vp]),
+            "feint_mixed_autotune": (_i, [_vp, P, _vp, _vp, _vp, _vp, _i, ctypes.POINTER(ctypes.c_double), _vp]),
+            "feint_mixed_tile_count": (_i, [_vp]),
+            "feint_mixed_tile_get": (_i, [_vp]),
+            "feint_mixed_tile_set": (_i, [_vp, _i]),
             "feint_tile_count": (_i, [_i, _i]),
             "feint_tile_get": (_i, [_i, _i]),
             "feint_tile_set": (_i, [_i, _i, _i]),
