@@ -120,7 +120,7 @@ feint_status feint_integrate_adjoint(const feint_elements *el, int p, feint_form
 
 /* ---- Mixed-degree batches -------------------------------------------------
    Elements of degrees 1..6 in any order run as one persistent,
-   degree-bucketed launch (the paper's Sec. 3 advice to group elements by
+   degree-bucketed launch (the paper's Sec. 2.2 advice to group elements by
    type and degree so that reference data is fetched once per group).
    Outputs are packed in element order: element e's matrix starts at
    offA[e] elements of the output dtype, its vector at offb[e], where offA

@@ -2,7 +2,7 @@
 
 Two counting conventions live here:
 
-* the paper's own (Sec. 3 "Computational and memory complexity", Tables 1-3):
+* the paper's own (Sec. 2.2 "Computational and memory complexity", Tables 1-3):
   N_sh shape functions, N_I points of its symmetric triangle rule of degree
   2p times p+1 line points, 7 operations per matrix entry per point (Laplace
   term), 220 per point for the Jacobian, and 3(p+1)(p+2)/2 + 6(p+1) + 19 N_sh

@@ -1,15 +1,16 @@
-// Forward kernels, FP32 form (v_mfma_f32_16x16x4_f32), tile shapes per degree.
+// Forward kernels, FP32 form (v_mfma_f32_16x16x4_f32): compiled tile shapes per degree (the first is
+// the default until the autotuner picks another).
 #include "fwd_registry.h"
 
 namespace feint {
 namespace {
-const FwdVariant v1[] = {FEINT_K4(1, float, 1, 1)};
-const FwdVariant v2[] = {FEINT_K4(2, float, 2, 2), FEINT_K4(2, float, 2, 1)};
-const FwdVariant v3[] = {FEINT_K4(3, float, 3, 3), FEINT_K4(3, float, 3, 1)};
-const FwdVariant v4[] = {FEINT_K4(4, float, 5, 5), FEINT_K4(4, float, 5, 3), FEINT_K4(4, float, 5, 2)};
-const FwdVariant v5[] = {FEINT_K4(5, float, 8, 2), FEINT_K4(5, float, 8, 4), FEINT_K4(5, float, 8, 1)};
-const FwdVariant v6[] = {FEINT_K4(6, float, 13, 1), FEINT_K4(6, float, 13, 2)};
-const FwdVariant v7[] = {FEINT_K4(7, float, 6, 6), FEINT_K4(7, float, 6, 3), FEINT_K4(7, float, 9, 2)};
+const FwdVariant v1[] = {FEINT_K4S(1, float, 1, 1, 8)};
+const FwdVariant v2[] = {FEINT_K4S(2, float, 2, 2, 8)};
+const FwdVariant v3[] = {FEINT_K4S(3, float, 3, 3, 8), FEINT_K4S(3, float, 3, 1, 8)};
+const FwdVariant v4[] = {FEINT_K4S(4, float, 5, 5, 8), FEINT_K4S(4, float, 5, 3, 8), FEINT_K4S(4, float, 5, 2, 8), FEINT_K4U(4, float, 5, 5)};
+const FwdVariant v5[] = {FEINT_K4S(5, float, 8, 4, 8), FEINT_K4S(5, float, 8, 2, 8), FEINT_K4U(5, float, 8, 2)};
+const FwdVariant v6[] = {FEINT_K4S(6, float, 13, 2, 8), FEINT_K4S(6, float, 13, 1, 8), FEINT_K4U(6, float, 13, 2)};
+const FwdVariant v7[] = {FEINT_K4S(7, float, 6, 6, 8), FEINT_K4S(7, float, 6, 3, 8), FEINT_K4U(7, float, 6, 6)};
 }  // namespace
 
 #define FEINT_N(a) (int)(sizeof(a) / sizeof(a[0]))

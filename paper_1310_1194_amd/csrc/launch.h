@@ -14,6 +14,7 @@ struct FwdParams {
     const double *qw;        // [nqp][4]
     const double *B64;       // [nqp][4][npad]
     const float *B32;        // [nqp][4][npad]
+    const float *Bc32;       // [nqp][npad][4]
     const uint16_t *Bhi;     // [nkb][npad][32] split table of the form (bf16 or fp16)
     const uint16_t *Blo;
     float bmax;              // max |B| (fp16 form: used for the per-element scale)
@@ -27,6 +28,7 @@ struct FwdParams {
 // per wave; `launch` enqueues the direct (one work item per wave) kernel.
 struct FwdVariant {
     int tm, tn;
+    int staged;          // 1: the table is staged through LDS per workgroup
     void (*launch)(const FwdParams &, hipStream_t);
     int64_t (*items_per_elem)();
 };

@@ -1,7 +1,7 @@
 // Mixed-degree batches: integer degree bucketing and one persistent,
 // degree-bucketed launch (optionally captured in a HIP graph).
 //
-// The paper (Sec. 3) recommends grouping elements by type and degree so the
+// The paper (Sec. 2.2) recommends grouping elements by type and degree so the
 // reference data of a group is fetched once.  Here the grouping is done on
 // the device:
 //   k_count    per block of 1024 elements: count per degree, sum of n^2, n;

@@ -300,6 +300,11 @@ HostTables build_tables(int p) {
                 T.BT64[(size_t)a * T.nqp * 4 + q * 4 + r] = v;
                 T.BT32[(size_t)a * T.nqp * 4 + q * 4 + r] = (float)v;
             }
+    T.Bc32.assign(T.B64.size(), 0.0f);
+    for (int q = 0; q < T.nqp; ++q)
+        for (int a = 0; a < np; ++a)
+            for (int r = 0; r < 4; ++r)
+                T.Bc32[((size_t)q * np + a) * 4 + r] = (float)T.B64[((size_t)q * 4 + r) * np + a];
     T.B32.resize(T.B64.size());
     double bmax = 0.0;
     for (size_t i = 0; i < T.B64.size(); ++i) {

@@ -1,7 +1,7 @@
 // Reference tables of one polynomial degree: quadrature points and weights
 // and the shape-function values and reference gradients at every point,
 // laid out for the kernels.  These are the data the paper's Algorithm 1
-// reads in steps 3 and 6 (and, in Sec. 3, recommends keeping in fast memory
+// reads in steps 3 and 6 (and, in Sec. 2.2, recommends keeping in fast memory
 // because they are identical for every element of a degree).
 #pragma once
 #include <cstdint>
@@ -25,6 +25,7 @@ struct HostTables {
     std::vector<float> B32;          // same, rounded to FP32
     std::vector<double> BT64;        // [npad][nqp*4]  transpose of B64 (shape-function major)
     std::vector<float> BT32;         // same, FP32
+    std::vector<float> Bc32;         // [nqp][npad][4]  the four rows of a column side by side, FP32
     std::vector<uint16_t> bf_hi, bf_lo;   // [nkb][npad][32]  k = 4*(point in block) + row
     std::vector<uint16_t> hf_hi, hf_lo;   // same layout, fp16 of B * 2^f16_shift
 };
