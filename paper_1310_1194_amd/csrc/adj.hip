@@ -44,7 +44,7 @@ struct Adj {
     static constexpr bool ATOMIC = NBLK > 1;
     typedef typename AccT<T>::type V4;
 
-    struct Smem { double S[4][64][16]; };
+    struct Smem { double S[4][64][WROW<double>::value]; };
 
     __device__ static void chain_rule(const AdjParams &prm, const ElemIn &E, int q, const double S[16],
                                       bool with_load, int64_t e, double gr[32]) {

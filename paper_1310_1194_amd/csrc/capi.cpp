@@ -51,7 +51,8 @@ feint_status prepare_tables(int p) {
     auto align = [](size_t x) { return (x + 255) / 256 * 256; };
     const size_t s_qw = align(H.qw.size() * 8), s_b64 = align(H.B64.size() * 8), s_b32 = align(H.B32.size() * 4);
     const size_t s_sp = align(H.bf_hi.size() * 2);
-    const size_t total = s_qw + 2 * s_b64 + 3 * s_b32 + 4 * s_sp;
+    const size_t s_ycf = align(H.Ycf.size() * 4);
+    const size_t total = s_qw + 2 * s_b64 + 3 * s_b32 + 4 * s_sp + s_ycf;
     char *base = nullptr;
     e = hipMalloc((void **)&base, total);
     if (e != hipSuccess) { set_error("hipMalloc(tables)", e); return FEINT_ERR_HIP; }
@@ -79,6 +80,7 @@ feint_status prepare_tables(int p) {
     T->bf_lo = (const uint16_t *)put(H.bf_lo.data(), H.bf_lo.size() * 2, s_sp);
     T->hf_hi = (const uint16_t *)put(H.hf_hi.data(), H.hf_hi.size() * 2, s_sp);
     T->hf_lo = (const uint16_t *)put(H.hf_lo.data(), H.hf_lo.size() * 2, s_sp);
+    T->Ycf = (const float *)put(H.Ycf.data(), H.Ycf.size() * 4, s_ycf);
     T->base = base;
     e = hipMemcpy(base, host.data(), total, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -121,7 +123,7 @@ void fill_fwd_params(FwdParams &prm, const feint_elements *el, int form, const D
     std::memset(&prm, 0, sizeof prm);
     prm.coords = el->coords; prm.D = el->D; prm.beta = el->beta; prm.c = el->c; prm.f = el->f;
     prm.ne = el->ne;
-    prm.qw = T->qw; prm.B64 = T->B64; prm.B32 = T->B32; prm.Bc32 = T->Bc32;
+    prm.qw = T->qw; prm.B64 = T->B64; prm.B32 = T->B32; prm.Bc32 = T->Bc32; prm.Ycf = T->Ycf;
     prm.Bhi = form == FEINT_FP16X3 ? T->hf_hi : T->bf_hi;
     prm.Blo = form == FEINT_FP16X3 ? T->hf_lo : T->bf_lo;
     prm.bmax = T->bmax;
@@ -225,8 +227,9 @@ feint_status feint_tile_describe(int p, feint_form form, int tile, char *buf, si
     if (!valid_form(form)) return FEINT_ERR_UNSUPPORTED_FORM;
     const FwdVariant *v = fwd_variants(form, p, &cnt);
     if (!buf || tile < 0 || tile >= cnt) return FEINT_ERR_INVALID_ARG;
-    std::snprintf(buf, len, "%dx%d%s", v[tile].tm, v[tile].tn,
-                  v[tile].staged == 1 ? "s" : (v[tile].staged == 2 ? "sa" : ""));
+    std::snprintf(buf, len, "%dx%d%s%s", v[tile].tm, v[tile].tn,
+                  v[tile].staged == 1 ? "s" : (v[tile].staged == 2 ? "sa" : ""),
+                  v[tile].minw > 1 ? "o2" : "");
     return FEINT_OK;
 }
 

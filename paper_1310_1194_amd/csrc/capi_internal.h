@@ -15,6 +15,7 @@ struct DevTables {
     const double *qw, *B64, *BT64;
     const float *B32, *BT32, *Bc32;
     const uint16_t *bf_hi, *bf_lo, *hf_hi, *hf_lo;
+    const float *Ycf;
     void *base;
 };
 

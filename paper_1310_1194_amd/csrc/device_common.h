@@ -120,6 +120,13 @@ __device__ inline void wave_sync() {
 
 __device__ inline int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Row length of per-lane LDS rows holding 16 values: padded so that the
+// 16-byte accesses of 16 consecutive lanes fall in distinct banks (20 floats
+// = 80 B, 18 doubles = 144 B) while every row stays 16-byte aligned.
+template <typename T> struct WROW;
+template <> struct WROW<float> { static constexpr int value = 20; };
+template <> struct WROW<double> { static constexpr int value = 18; };
+
 // ---- MFMA wrappers --------------------------------------------------------
 // 16x16x4 (FP64, FP32): lane l supplies A[l%16][l/16] and B[l/16][l%16].
 // 16x16x32 (bf16, fp16): lane l supplies A[l%16][8(l/16)+v], B[8(l/16)+v][l%16].

@@ -4,13 +4,32 @@
 
 namespace feint {
 namespace {
-const FwdVariant v1[] = {FEINT_K32S(1, BF16X3, 1, 1, true)};
-const FwdVariant v2[] = {FEINT_K32S(2, BF16X3, 2, 2, true)};
-const FwdVariant v3[] = {FEINT_K32S(3, BF16X3, 3, 3, true), FEINT_K32S(3, BF16X3, 3, 1, true)};
-const FwdVariant v4[] = {FEINT_K32S(4, BF16X3, 5, 3, true), FEINT_K32S(4, BF16X3, 5, 5, true), FEINT_K32S(4, BF16X3, 5, 2, true), FEINT_K32U(4, BF16X3, 5, 3)};
-const FwdVariant v5[] = {FEINT_K32S(5, BF16X3, 8, 4, false), FEINT_K32S(5, BF16X3, 8, 4, true), FEINT_K32S(5, BF16X3, 4, 4, false), FEINT_K32U(5, BF16X3, 8, 4)};
-const FwdVariant v6[] = {FEINT_K32S(6, BF16X3, 13, 2, false), FEINT_K32S(6, BF16X3, 7, 4, false), FEINT_K32U(6, BF16X3, 13, 2)};
-const FwdVariant v7[] = {FEINT_K32S(7, BF16X3, 6, 6, false), FEINT_K32S(7, BF16X3, 6, 3, false), FEINT_K32U(7, BF16X3, 6, 6)};
+const FwdVariant v1[] = {
+    FEINT_K32S(1, BF16X3, 1, 1, true, 1)};
+const FwdVariant v2[] = {
+    FEINT_K32S(2, BF16X3, 2, 2, true, 1)};
+const FwdVariant v3[] = {
+    FEINT_K32S(3, BF16X3, 3, 3, true, 1),
+    FEINT_K32S(3, BF16X3, 3, 1, true, 2)};
+const FwdVariant v4[] = {
+    FEINT_K32U(4, BF16X3, 5, 3, 2),
+    FEINT_K32U(4, BF16X3, 5, 5, 1),
+    FEINT_K32S(4, BF16X3, 5, 5, true, 1),
+    FEINT_K32U(4, BF16X3, 5, 3, 1)};
+const FwdVariant v5[] = {
+    FEINT_K32S(5, BF16X3, 8, 4, false, 1),
+    FEINT_K32S(5, BF16X3, 8, 4, true, 1),
+    FEINT_K32S(5, BF16X3, 4, 4, false, 2),
+    FEINT_K32U(5, BF16X3, 8, 4, 1)};
+const FwdVariant v6[] = {
+    FEINT_K32S(6, BF16X3, 13, 2, false, 2),
+    FEINT_K32S(6, BF16X3, 13, 2, false, 1),
+    FEINT_K32S(6, BF16X3, 7, 4, false, 1),
+    FEINT_K32U(6, BF16X3, 13, 2, 1)};
+const FwdVariant v7[] = {
+    FEINT_K32S(7, BF16X3, 6, 6, false, 1),
+    FEINT_K32S(7, BF16X3, 6, 3, false, 1),
+    FEINT_K32U(7, BF16X3, 6, 6, 1)};
 }  // namespace
 
 #define FEINT_N(a) (int)(sizeof(a) / sizeof(a[0]))

@@ -4,13 +4,29 @@
 
 namespace feint {
 namespace {
-const FwdVariant v1[] = {FEINT_K4S(1, float, 1, 1, 8)};
-const FwdVariant v2[] = {FEINT_K4S(2, float, 2, 2, 8)};
-const FwdVariant v3[] = {FEINT_K4S(3, float, 3, 3, 8), FEINT_K4S(3, float, 3, 1, 8)};
-const FwdVariant v4[] = {FEINT_K4S(4, float, 5, 5, 8), FEINT_K4S(4, float, 5, 3, 8), FEINT_K4S(4, float, 5, 2, 8), FEINT_K4U(4, float, 5, 5)};
-const FwdVariant v5[] = {FEINT_K4S(5, float, 8, 4, 8), FEINT_K4S(5, float, 8, 2, 8), FEINT_K4U(5, float, 8, 2)};
-const FwdVariant v6[] = {FEINT_K4S(6, float, 13, 2, 8), FEINT_K4S(6, float, 13, 1, 8), FEINT_K4U(6, float, 13, 2)};
-const FwdVariant v7[] = {FEINT_K4S(7, float, 6, 6, 8), FEINT_K4S(7, float, 6, 3, 8), FEINT_K4U(7, float, 6, 6)};
+const FwdVariant v1[] = {
+    FEINT_K4S(1, float, 1, 1, 8, 1)};
+const FwdVariant v2[] = {
+    FEINT_K4S(2, float, 2, 2, 8, 1)};
+const FwdVariant v3[] = {
+    FEINT_K4S(3, float, 3, 3, 8, 1),
+    FEINT_K4S(3, float, 3, 1, 8, 2)};
+const FwdVariant v4[] = {
+    FEINT_K4S(4, float, 5, 5, 8, 1),
+    FEINT_K4S(4, float, 5, 3, 8, 2),
+    FEINT_K4U(4, float, 5, 5, 1)};
+const FwdVariant v5[] = {
+    FEINT_K4S(5, float, 8, 4, 8, 1),
+    FEINT_K4S(5, float, 8, 2, 8, 2),
+    FEINT_K4U(5, float, 8, 2, 1)};
+const FwdVariant v6[] = {
+    FEINT_K4S(6, float, 13, 2, 8, 1),
+    FEINT_K4S(6, float, 13, 1, 8, 2),
+    FEINT_K4U(6, float, 13, 2, 1)};
+const FwdVariant v7[] = {
+    FEINT_K4S(7, float, 6, 6, 8, 1),
+    FEINT_K4S(7, float, 6, 3, 8, 1),
+    FEINT_K4U(7, float, 6, 6, 1)};
 }  // namespace
 
 #define FEINT_N(a) (int)(sizeof(a) / sizeof(a[0]))

@@ -56,29 +56,30 @@ struct K4 {
     typedef typename AccT<T>::type V4;
 
     struct Smem {
-        T W[4][64][16];
+        T W[4][64][WROW<T>::value];   // padded rows: conflict-free per-lane writes
         double sf[4][64];
     };
 
     // One work item: block `blk` of element slot `slot`.  `wave` indexes the
     // wave's LDS slice.
-    __device__ static void run(const FwdParams &prm, int64_t slot, int blk, int wave, Smem &sm) {
+    template <int TMV, int TNV>
+    __device__ static void body(const FwdParams &prm, int64_t slot, int blk, int bi, int bj, int wave, Smem &sm) {
+        constexpr int NBRV = c_cdiv(TMV * 16, 64);
         const int lane = threadIdx.x & 63;
         const int i16 = lane & 15, kg = lane >> 4;
-        const int bi = blk / BN, bj = blk % BN;
         const int a0 = bi * TM * 16, b0 = bj * TN * 16;
         const int64_t e = elem_of(prm, slot);
         ElemIn E;
         load_elem(prm.coords, prm.D, prm.beta, prm.c, prm.f, e, E);
         const T *Bt = sizeof(T) == 8 ? (const T *)(const void *)prm.B64 : (const T *)(const void *)prm.B32;
-        V4 acc[TM][TN];
+        V4 acc[TMV][TNV];
 #pragma unroll
-        for (int ti = 0; ti < TM; ++ti)
+        for (int ti = 0; ti < TMV; ++ti)
 #pragma unroll
-            for (int tj = 0; tj < TN; ++tj) acc[ti][tj] = V4{0, 0, 0, 0};
-        double bacc[NBR];
+            for (int tj = 0; tj < TNV; ++tj) acc[ti][tj] = V4{0, 0, 0, 0};
+        double bacc[NBRV];
 #pragma unroll
-        for (int m = 0; m < NBR; ++m) bacc[m] = 0.0;
+        for (int m = 0; m < NBRV; ++m) bacc[m] = 0.0;
 
         for (int qc = 0; qc < NQ; qc += 64) {
             const int cnt = NQ - qc < 64 ? NQ - qc : 64;
@@ -101,9 +102,9 @@ struct K4 {
             wave_sync();
             if (bj == 0) {
 #pragma unroll
-                for (int m = 0; m < NBR; ++m) {
+                for (int m = 0; m < NBRV; ++m) {
                     const int row = a0 + lane + 64 * m;
-                    if (lane + 64 * m < TM * 16 && row < N) {
+                    if (lane + 64 * m < TMV * 16 && row < N) {
                         double s = 0.0;
                         for (int qq = 0; qq < cnt; ++qq)
                             s += sm.sf[wave][qq] * prm.B64[(size_t)(qc + qq) * 4 * NP + row];
@@ -116,49 +117,60 @@ struct K4 {
                 const T w0 = sm.W[wave][qq][4 * kg + 0], w1 = sm.W[wave][qq][4 * kg + 1];
                 const T w2 = sm.W[wave][qq][4 * kg + 2], w3 = sm.W[wave][qq][4 * kg + 3];
                 const T *Bq = Bt + (size_t)q * 4 * NP;
-                T yf[TN], af[TM];
+                T yf[TNV], af[TMV];
 #pragma unroll
-                for (int tj = 0; tj < TN; ++tj) {
-                    yf[tj] = 0;
-                    if (b0 + tj * 16 < NP) {
+                for (int tj = 0; tj < TNV; ++tj) {
+                    {
                         const T *bp = Bq + b0 + tj * 16 + i16;
                         yf[tj] = w0 * bp[0] + w1 * bp[NP] + w2 * bp[2 * NP] + w3 * bp[3 * NP];
                     }
                 }
 #pragma unroll
-                for (int ti = 0; ti < TM; ++ti) {
-                    af[ti] = 0;
-                    if (a0 + ti * 16 < NP) af[ti] = Bq[kg * NP + a0 + ti * 16 + i16];
+                for (int ti = 0; ti < TMV; ++ti) {
+                    af[ti] = Bq[kg * NP + a0 + ti * 16 + i16];
                 }
 #pragma unroll
-                for (int ti = 0; ti < TM; ++ti)
+                for (int ti = 0; ti < TMV; ++ti)
 #pragma unroll
-                    for (int tj = 0; tj < TN; ++tj)
-                        if (a0 + ti * 16 < NP && b0 + tj * 16 < NP)
-                            acc[ti][tj] = mfma4(af[ti], yf[tj], acc[ti][tj]);
+                    for (int tj = 0; tj < TNV; ++tj)
+                        acc[ti][tj] = mfma4(af[ti], yf[tj], acc[ti][tj]);
             }
             wave_sync();
         }
         T *Aout = (T *)prm.A + offA_of(prm, e, N);
 #pragma unroll
-        for (int ti = 0; ti < TM; ++ti)
+        for (int ti = 0; ti < TMV; ++ti)
 #pragma unroll
-            for (int tj = 0; tj < TN; ++tj) {
+            for (int tj = 0; tj < TNV; ++tj) {
                 const int col = b0 + tj * 16 + i16;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = a0 + ti * 16 + acc_row<T>(lane, r);
-                    if (row < N && col < N && a0 + ti * 16 < NP && b0 + tj * 16 < NP)
+                    if (row < N && col < N)
                         Aout[(size_t)row * N + col] = acc[ti][tj][r];
                 }
             }
         if (bj == 0) {
             T *bout = (T *)prm.b + offb_of(prm, e, N);
 #pragma unroll
-            for (int m = 0; m < NBR; ++m) {
+            for (int m = 0; m < NBRV; ++m) {
                 const int row = a0 + lane + 64 * m;
-                if (lane + 64 * m < TM * 16 && row < N) bout[row] = (T)bacc[m];
+                if (lane + 64 * m < TMV * 16 && row < N) bout[row] = (T)bacc[m];
             }
+        }
+    }
+
+    // Tile counts of the last row/column block are compile-time constants,
+    // so the inner loops carry no bounds tests and stay one basic block.
+    __device__ static void run(const FwdParams &prm, int64_t slot, int blk, int wave, Smem &sm) {
+        const int bi = blk / BN, bj = blk % BN;
+        constexpr int TML = NT - (BM - 1) * TM, TNL = NT - (BN - 1) * TN;
+        if (bi == BM - 1) {
+            if (bj == BN - 1) body<TML, TNL>(prm, slot, blk, bi, bj, wave, sm);
+            else body<TML, TN>(prm, slot, blk, bi, bj, wave, sm);
+        } else {
+            if (bj == BN - 1) body<TM, TNL>(prm, slot, blk, bi, bj, wave, sm);
+            else body<TM, TN>(prm, slot, blk, bi, bj, wave, sm);
         }
     }
 };
@@ -181,7 +193,7 @@ struct K32 {
     typedef typename SplitT<FORM>::scal HS;
 
     struct Smem {
-        float W[4][64][16];
+        float W[4][64][WROW<float>::value];   // padded rows: conflict-free per-lane writes
         double sf[4][64];
     };
 
@@ -214,32 +226,40 @@ struct K32 {
         return ldexpf(1.0f, ex < -60 ? -60 : (ex > 60 ? 60 : ex));
     }
 
+    // hi = rn(y), lo = rn(y - hi), two values per conversion instruction.
     __device__ static void split8(const float *y, HV &hi, HV &lo) {
+        typedef float f2 __attribute__((ext_vector_type(2)));
+        typedef HS h2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
-            const HS h = (HS)y[v];
-            hi[v] = h;
-            lo[v] = (HS)(y[v] - (float)h);
+        for (int v = 0; v < 8; v += 2) {
+            const f2 yy = {y[v], y[v + 1]};
+            const h2 h = __builtin_convertvector(yy, h2);
+            const f2 back = __builtin_convertvector(h, f2);
+            const f2 r = {yy.x - back.x, yy.y - back.y};
+            const h2 l = __builtin_convertvector(r, h2);
+            hi[v] = h.x; hi[v + 1] = h.y;
+            lo[v] = l.x; lo[v + 1] = l.y;
         }
     }
 
-    __device__ static void run(const FwdParams &prm, int64_t slot, int blk, int wave, Smem &sm) {
+    template <int TMV, int TNV>
+    __device__ static void body(const FwdParams &prm, int64_t slot, int blk, int bi, int bj, int wave, Smem &sm) {
+        constexpr int NBRV = c_cdiv(TMV * 16, 64);
         const int lane = threadIdx.x & 63;
         const int i16 = lane & 15, kg = lane >> 4;
-        const int bi = blk / BN, bj = blk % BN;
         const int a0 = bi * TM * 16, b0 = bj * TN * 16;
         const int64_t e = elem_of(prm, slot);
         ElemIn E;
         load_elem(prm.coords, prm.D, prm.beta, prm.c, prm.f, e, E);
         const float ys = FORM == FP16X3 ? elem_scale(prm, E) : 1.0f;
-        f32x4 acc[TM][TN];
+        f32x4 acc[TMV][TNV];
 #pragma unroll
-        for (int ti = 0; ti < TM; ++ti)
+        for (int ti = 0; ti < TMV; ++ti)
 #pragma unroll
-            for (int tj = 0; tj < TN; ++tj) acc[ti][tj] = f32x4{0, 0, 0, 0};
-        double bacc[NBR];
+            for (int tj = 0; tj < TNV; ++tj) acc[ti][tj] = f32x4{0, 0, 0, 0};
+        double bacc[NBRV];
 #pragma unroll
-        for (int m = 0; m < NBR; ++m) bacc[m] = 0.0;
+        for (int m = 0; m < NBRV; ++m) bacc[m] = 0.0;
 
         for (int qc = 0; qc < NQP; qc += 64) {
             const int cnt = NQP - qc < 64 ? NQP - qc : 64;   // multiple of 8
@@ -267,9 +287,9 @@ struct K32 {
             wave_sync();
             if (bj == 0) {
 #pragma unroll
-                for (int m = 0; m < NBR; ++m) {
+                for (int m = 0; m < NBRV; ++m) {
                     const int row = a0 + lane + 64 * m;
-                    if (lane + 64 * m < TM * 16 && row < N) {
+                    if (lane + 64 * m < TMV * 16 && row < N) {
                         double s = 0.0;
                         for (int qq = 0; qq < cnt && qc + qq < NQ; ++qq)
                             s += sm.sf[wave][qq] * prm.B64[(size_t)(qc + qq) * 4 * NP + row];
@@ -277,81 +297,110 @@ struct K32 {
                     }
                 }
             }
-            for (int kb = 0; kb < cnt / 8; ++kb) {
+            // The FP32 columns of the next K-block are fetched one iteration
+            // ahead (they feed the first work of an iteration); the A
+            // fragments of the current block are issued first and consumed
+            // only after the fragments Y have been formed.
+            const int nkbc = cnt / 8;
+            const float *Yc0 = prm.Ycf + (size_t)(qc / 8) * NT * 64 * 8 + ((size_t)(b0 / 16) * 64 + lane) * 8;
+            float4 ycn[TNV][2];
+#pragma unroll
+            for (int tj = 0; tj < TNV; ++tj) {
+                ycn[tj][0] = *(const float4 *)(Yc0 + (size_t)tj * 64 * 8);
+                ycn[tj][1] = *(const float4 *)(Yc0 + (size_t)tj * 64 * 8 + 4);
+            }
+            for (int kb = 0; kb < nkbc; ++kb) {
+                const size_t kbg = (size_t)(qc / 8 + kb);
+                float4 yc[TNV][2];
+#pragma unroll
+                for (int tj = 0; tj < TNV; ++tj) { yc[tj][0] = ycn[tj][0]; yc[tj][1] = ycn[tj][1]; }
+                HV yh[TNV], yl[TNV], ah[TMV], al[TMV];
+#pragma unroll
+                for (int ti = 0; ti < TMV; ++ti) {
+                    const size_t o = ((kbg * NT + a0 / 16 + ti) * 64 + lane) * 8;
+                    ah[ti] = *(const HV *)(prm.Bhi + o);
+                    al[ti] = *(const HV *)(prm.Blo + o);
+                }
+                const int kn = kb + 1 < nkbc ? kb + 1 : kb;      // the last block re-reads itself
+#pragma unroll
+                for (int tj = 0; tj < TNV; ++tj) {
+                    const float *yp = Yc0 + (size_t)kn * NT * 64 * 8 + (size_t)tj * 64 * 8;
+                    ycn[tj][0] = *(const float4 *)yp;
+                    ycn[tj][1] = *(const float4 *)(yp + 4);
+                }
                 const int qa = kb * 8 + 2 * kg;        // this lane's two points (chunk-local)
                 const float *Wa = sm.W[wave][qa];
                 const float *Wb = sm.W[wave][qa + 1];
                 float wa[16], wb[16];
 #pragma unroll
                 for (int k = 0; k < 16; ++k) { wa[k] = Wa[k]; wb[k] = Wb[k]; }
-                const float *Bqa = prm.B32 + (size_t)(qc + qa) * 4 * NP;
-                HV yh[TN], yl[TN], ah[TM], al[TM];
 #pragma unroll
-                for (int tj = 0; tj < TN; ++tj) {
-                    if (b0 + tj * 16 < NP) {
-                        const float *bp = Bqa + b0 + tj * 16 + i16;
-                        float s0[4], s1[4], y[8];
+                for (int tj = 0; tj < TNV; ++tj) {
+                    const float s0[4] = {yc[tj][0].x, yc[tj][0].y, yc[tj][0].z, yc[tj][0].w};
+                    const float s1[4] = {yc[tj][1].x, yc[tj][1].y, yc[tj][1].z, yc[tj][1].w};
+                    float y[8];
+                    y[0] = wa[0] * s0[0] + wa[1] * s0[1] + wa[2] * s0[2] + wa[3] * s0[3];
+                    y[4] = wb[0] * s1[0] + wb[1] * s1[1] + wb[2] * s1[2] + wb[3] * s1[3];
 #pragma unroll
-                        for (int s = 0; s < 4; ++s) { s0[s] = bp[s * NP]; s1[s] = bp[(4 + s) * NP]; }
-                        y[0] = wa[0] * s0[0] + wa[1] * s0[1] + wa[2] * s0[2] + wa[3] * s0[3];
-                        y[4] = wb[0] * s1[0] + wb[1] * s1[1] + wb[2] * s1[2] + wb[3] * s1[3];
-#pragma unroll
-                        for (int r = 1; r < 4; ++r) {
-                            y[r] = wa[4 * r + 1] * s0[1] + wa[4 * r + 2] * s0[2] + wa[4 * r + 3] * s0[3];
-                            y[4 + r] = wb[4 * r + 1] * s1[1] + wb[4 * r + 2] * s1[2] + wb[4 * r + 3] * s1[3];
-                        }
-                        split8(y, yh[tj], yl[tj]);
+                    for (int r = 1; r < 4; ++r) {
+                        y[r] = wa[4 * r + 1] * s0[1] + wa[4 * r + 2] * s0[2] + wa[4 * r + 3] * s0[3];
+                        y[4 + r] = wb[4 * r + 1] * s1[1] + wb[4 * r + 2] * s1[2] + wb[4 * r + 3] * s1[3];
                     }
-                }
-                const size_t kbg = (size_t)(qc / 8 + kb);
-#pragma unroll
-                for (int ti = 0; ti < TM; ++ti) {
-                    if (a0 + ti * 16 < NP) {
-                        const size_t o = (kbg * NP + a0 + ti * 16 + i16) * 32 + 8 * kg;
-                        ah[ti] = *(const HV *)(prm.Bhi + o);
-                        al[ti] = *(const HV *)(prm.Blo + o);
-                    }
+                    split8(y, yh[tj], yl[tj]);
                 }
 #pragma unroll
-                for (int ti = 0; ti < TM; ++ti)
+                for (int ti = 0; ti < TMV; ++ti)
 #pragma unroll
-                    for (int tj = 0; tj < TN; ++tj)
-                        if (a0 + ti * 16 < NP && b0 + tj * 16 < NP) {
-                            acc[ti][tj] = mfma32(al[ti], yh[tj], acc[ti][tj]);
-                            acc[ti][tj] = mfma32(ah[ti], yl[tj], acc[ti][tj]);
-                            acc[ti][tj] = mfma32(ah[ti], yh[tj], acc[ti][tj]);
-                        }
+                    for (int tj = 0; tj < TNV; ++tj) {
+                        acc[ti][tj] = mfma32(al[ti], yh[tj], acc[ti][tj]);
+                        acc[ti][tj] = mfma32(ah[ti], yl[tj], acc[ti][tj]);
+                        acc[ti][tj] = mfma32(ah[ti], yh[tj], acc[ti][tj]);
+                    }
             }
             wave_sync();
         }
         const float unscale = FORM == FP16X3 ? ldexpf(1.0f, -prm.f16_shift) / ys : 1.0f;
         float *Aout = (float *)prm.A + offA_of(prm, e, N);
 #pragma unroll
-        for (int ti = 0; ti < TM; ++ti)
+        for (int ti = 0; ti < TMV; ++ti)
 #pragma unroll
-            for (int tj = 0; tj < TN; ++tj) {
+            for (int tj = 0; tj < TNV; ++tj) {
                 const int col = b0 + tj * 16 + i16;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = a0 + ti * 16 + 4 * kg + r;
-                    if (row < N && col < N && a0 + ti * 16 < NP && b0 + tj * 16 < NP)
+                    if (row < N && col < N)
                         Aout[(size_t)row * N + col] = acc[ti][tj][r] * unscale;
                 }
             }
         if (bj == 0) {
             float *bout = (float *)prm.b + offb_of(prm, e, N);
 #pragma unroll
-            for (int m = 0; m < NBR; ++m) {
+            for (int m = 0; m < NBRV; ++m) {
                 const int row = a0 + lane + 64 * m;
-                if (lane + 64 * m < TM * 16 && row < N) bout[row] = (float)bacc[m];
+                if (lane + 64 * m < TMV * 16 && row < N) bout[row] = (float)bacc[m];
             }
+        }
+    }
+
+    // Tile counts of the last row/column block are compile-time constants,
+    // so the inner loops carry no bounds tests and stay one basic block.
+    __device__ static void run(const FwdParams &prm, int64_t slot, int blk, int wave, Smem &sm) {
+        const int bi = blk / BN, bj = blk % BN;
+        constexpr int TML = NT - (BM - 1) * TM, TNL = NT - (BN - 1) * TN;
+        if (bi == BM - 1) {
+            if (bj == BN - 1) body<TML, TNL>(prm, slot, blk, bi, bj, wave, sm);
+            else body<TML, TN>(prm, slot, blk, bi, bj, wave, sm);
+        } else {
+            if (bj == BN - 1) body<TM, TNL>(prm, slot, blk, bi, bj, wave, sm);
+            else body<TM, TN>(prm, slot, blk, bi, bj, wave, sm);
         }
     }
 };
 
 // Grid-stride-free direct launch: workgroup of 4 waves, one work item each.
-template <class KER>
-__global__ __launch_bounds__(256) void fwd_direct(FwdParams prm) {
+template <class KER, int MINW>
+__global__ __launch_bounds__(256, MINW) void fwd_direct(FwdParams prm) {
     __shared__ typename KER::Smem sm;
     const int wave = wave_uniform(threadIdx.x >> 6);
     const int64_t item = (int64_t)blockIdx.x * 4 + wave;

@@ -6,29 +6,32 @@
 
 namespace feint {
 
-template <class KER>
+template <class KER, int MINW>
 void launch_direct(const FwdParams &prm, hipStream_t s) {
     const int64_t items = prm.ne * KER::NBLK;
     const int64_t blocks = (items + 3) / 4;
-    hipLaunchKernelGGL(fwd_direct<KER>, dim3((unsigned)blocks), dim3(256), 0, s, prm);
+    hipLaunchKernelGGL((fwd_direct<KER, MINW>), dim3((unsigned)blocks), dim3(256), 0, s, prm);
 }
 
-template <class KER>
+template <class KER, int MINW>
 void launch_staged(const FwdParams &prm, hipStream_t s) {
     const int64_t items = prm.ne * KER::NBLK;
     const int64_t blocks = (items + 3) / 4;
-    hipLaunchKernelGGL(fwd_staged<KER>, dim3((unsigned)blocks), dim3(256), 0, s, prm);
+    hipLaunchKernelGGL((fwd_staged<KER, MINW>), dim3((unsigned)blocks), dim3(256), 0, s, prm);
 }
 
 template <class KER>
 int64_t items_of() { return KER::NBLK; }
 
 // U: unstaged (each wave reads the table through L2); S: LDS-staged.
-#define FEINT_K4U(P, T, TM, TN) FwdVariant{TM, TN, 0, &launch_direct<K4<P, T, TM, TN>>, &items_of<K4<P, T, TM, TN>>}
-#define FEINT_K4S(P, T, TM, TN, SP) \
-    FwdVariant{TM, TN, 1, &launch_staged<K4S<P, T, TM, TN, SP>>, &items_of<K4S<P, T, TM, TN, SP>>}
-#define FEINT_K32U(P, F, TM, TN) FwdVariant{TM, TN, 0, &launch_direct<K32<P, F, TM, TN>>, &items_of<K32<P, F, TM, TN>>}
-#define FEINT_K32S(P, F, TM, TN, SY) \
-    FwdVariant{TM, TN, 1 + !(SY), &launch_staged<K32S<P, F, TM, TN, SY>>, &items_of<K32S<P, F, TM, TN, SY>>}
+// W: minimum waves per SIMD asked of the register allocator.
+#define FEINT_K4U(P, T, TM, TN, W) \
+    FwdVariant{TM, TN, 0, W, &launch_direct<K4<P, T, TM, TN>, W>, &items_of<K4<P, T, TM, TN>>}
+#define FEINT_K4S(P, T, TM, TN, SP, W) \
+    FwdVariant{TM, TN, 1, W, &launch_staged<K4S<P, T, TM, TN, SP>, W>, &items_of<K4S<P, T, TM, TN, SP>>}
+#define FEINT_K32U(P, F, TM, TN, W) \
+    FwdVariant{TM, TN, 0, W, &launch_direct<K32<P, F, TM, TN>, W>, &items_of<K32<P, F, TM, TN>>}
+#define FEINT_K32S(P, F, TM, TN, SY, W) \
+    FwdVariant{TM, TN, 1 + !(SY), W, &launch_staged<K32S<P, F, TM, TN, SY>, W>, &items_of<K32S<P, F, TM, TN, SY>>}
 
 }  // namespace feint

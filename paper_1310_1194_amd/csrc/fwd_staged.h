@@ -57,27 +57,28 @@ struct K4S {
 
     struct Smem {
         T B[2][STAGE_T];
-        T W[4][64][16];
+        T W[4][64][WROW<T>::value];   // padded rows: conflict-free per-lane writes
         double sf[4][64];
     };
 
-    __device__ static void run(const FwdParams &prm, int64_t slot, int blk, int wave, bool active, Smem &sm) {
+    template <int TMV, int TNV>
+    __device__ static void body(const FwdParams &prm, int64_t slot, int blk, int bi, int bj, int wave, bool active, Smem &sm) {
+        constexpr int NBRV = c_cdiv(TMV * 16, 64);
         const int lane = threadIdx.x & 63;
         const int i16 = lane & 15, kg = lane >> 4;
-        const int bi = blk / BN, bj = blk % BN;
         const int a0 = bi * TM * 16, b0 = bj * TN * 16;
         const int64_t e = active ? elem_of(prm, slot) : 0;
         ElemIn E;
         if (active) load_elem(prm.coords, prm.D, prm.beta, prm.c, prm.f, e, E);
         const T *tab = sizeof(T) == 8 ? (const T *)(const void *)prm.B64 : (const T *)(const void *)prm.B32;
-        V4 acc[TM][TN];
+        V4 acc[TMV][TNV];
 #pragma unroll
-        for (int ti = 0; ti < TM; ++ti)
+        for (int ti = 0; ti < TMV; ++ti)
 #pragma unroll
-            for (int tj = 0; tj < TN; ++tj) acc[ti][tj] = V4{0, 0, 0, 0};
-        double bacc[NBR];
+            for (int tj = 0; tj < TNV; ++tj) acc[ti][tj] = V4{0, 0, 0, 0};
+        double bacc[NBRV];
 #pragma unroll
-        for (int m = 0; m < NBR; ++m) bacc[m] = 0.0;
+        for (int m = 0; m < NBRV; ++m) bacc[m] = 0.0;
 
         StageCopy<STAGE_V> cp;
         cp.fetch((const uint4 *)tab);
@@ -110,9 +111,9 @@ struct K4S {
                     wave_sync();
                     if (bj == 0) {
 #pragma unroll
-                        for (int m = 0; m < NBR; ++m) {
+                        for (int m = 0; m < NBRV; ++m) {
                             const int row = a0 + lane + 64 * m;
-                            if (lane + 64 * m < TM * 16 && row < N) {
+                            if (lane + 64 * m < TMV * 16 && row < N) {
                                 double acc_b = 0.0;
                                 for (int qq = 0; qq < cnt; ++qq)
                                     acc_b += sm.sf[wave][qq] * prm.B64[(size_t)(qc + qq) * 4 * NP + row];
@@ -127,26 +128,23 @@ struct K4S {
                     const T w0 = sm.W[wave][ql][4 * kg + 0], w1 = sm.W[wave][ql][4 * kg + 1];
                     const T w2 = sm.W[wave][ql][4 * kg + 2], w3 = sm.W[wave][ql][4 * kg + 3];
                     const T *Bq = sm.B[buf] + qq * 4 * NP;
-                    T yf[TN], af[TM];
+                    T yf[TNV], af[TMV];
 #pragma unroll
-                    for (int tj = 0; tj < TN; ++tj) {
-                        yf[tj] = 0;
-                        if (b0 + tj * 16 < NP) {
+                    for (int tj = 0; tj < TNV; ++tj) {
+                        {
                             const T *bp = Bq + b0 + tj * 16 + i16;
                             yf[tj] = w0 * bp[0] + w1 * bp[NP] + w2 * bp[2 * NP] + w3 * bp[3 * NP];
                         }
                     }
 #pragma unroll
-                    for (int ti = 0; ti < TM; ++ti) {
-                        af[ti] = 0;
-                        if (a0 + ti * 16 < NP) af[ti] = Bq[kg * NP + a0 + ti * 16 + i16];
+                    for (int ti = 0; ti < TMV; ++ti) {
+                        af[ti] = Bq[kg * NP + a0 + ti * 16 + i16];
                     }
 #pragma unroll
-                    for (int ti = 0; ti < TM; ++ti)
+                    for (int ti = 0; ti < TMV; ++ti)
 #pragma unroll
-                        for (int tj = 0; tj < TN; ++tj)
-                            if (a0 + ti * 16 < NP && b0 + tj * 16 < NP)
-                                acc[ti][tj] = mfma4(af[ti], yf[tj], acc[ti][tj]);
+                        for (int tj = 0; tj < TNV; ++tj)
+                            acc[ti][tj] = mfma4(af[ti], yf[tj], acc[ti][tj]);
                 }
             }
             if (s + 1 < NSTAGE) cp.put((uint4 *)sm.B[buf ^ 1]);
@@ -155,24 +153,38 @@ struct K4S {
         if (!active) return;
         T *Aout = (T *)prm.A + offA_of(prm, e, N);
 #pragma unroll
-        for (int ti = 0; ti < TM; ++ti)
+        for (int ti = 0; ti < TMV; ++ti)
 #pragma unroll
-            for (int tj = 0; tj < TN; ++tj) {
+            for (int tj = 0; tj < TNV; ++tj) {
                 const int col = b0 + tj * 16 + i16;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = a0 + ti * 16 + acc_row<T>(lane, r);
-                    if (row < N && col < N && a0 + ti * 16 < NP && b0 + tj * 16 < NP)
+                    if (row < N && col < N)
                         Aout[(size_t)row * N + col] = acc[ti][tj][r];
                 }
             }
         if (bj == 0) {
             T *bout = (T *)prm.b + offb_of(prm, e, N);
 #pragma unroll
-            for (int m = 0; m < NBR; ++m) {
+            for (int m = 0; m < NBRV; ++m) {
                 const int row = a0 + lane + 64 * m;
-                if (lane + 64 * m < TM * 16 && row < N) bout[row] = (T)bacc[m];
+                if (lane + 64 * m < TMV * 16 && row < N) bout[row] = (T)bacc[m];
             }
+        }
+    }
+
+    // Tile counts of the last row/column block are compile-time constants,
+    // so the inner loops carry no bounds tests and stay one basic block.
+    __device__ static void run(const FwdParams &prm, int64_t slot, int blk, int wave, bool active, Smem &sm) {
+        const int bi = blk / BN, bj = blk % BN;
+        constexpr int TML = NT - (BM - 1) * TM, TNL = NT - (BN - 1) * TN;
+        if (bi == BM - 1) {
+            if (bj == BN - 1) body<TML, TNL>(prm, slot, blk, bi, bj, wave, active, sm);
+            else body<TML, TN>(prm, slot, blk, bi, bj, wave, active, sm);
+        } else {
+            if (bj == BN - 1) body<TM, TNL>(prm, slot, blk, bi, bj, wave, active, sm);
+            else body<TM, TN>(prm, slot, blk, bi, bj, wave, active, sm);
         }
     }
 };
@@ -197,14 +209,14 @@ struct K32S {
 
     struct Smem {
         uint4 S[2][NV];      // [hi A | lo A | FP32 columns]
-        float W[4][64][16];
+        float W[4][64][WROW<float>::value];   // padded rows: conflict-free per-lane writes
         double sf[4][64];
     };
 
     __device__ static void fetch(const FwdParams &prm, int kb, uint4 (&r)[c_cdiv(NV, 256)]) {
         const uint4 *hi = (const uint4 *)(prm.Bhi + (size_t)kb * NP * 32);
         const uint4 *lo = (const uint4 *)(prm.Blo + (size_t)kb * NP * 32);
-        const uint4 *yc = (const uint4 *)(prm.Bc32 + (size_t)kb * 8 * NP * 4);
+        const uint4 *yc = (const uint4 *)(prm.Ycf + (size_t)kb * NP * 32);
 #pragma unroll
         for (int v = 0; v < c_cdiv(NV, 256); ++v) {
             const int i = threadIdx.x + 256 * v;
@@ -221,11 +233,12 @@ struct K32S {
         }
     }
 
-    __device__ static void run(const FwdParams &prm, int64_t slot, int blk, int wave, bool active, Smem &sm) {
-        typedef K32<P, FORM, TM, TN> Plain;
+    template <int TMV, int TNV>
+    __device__ static void body(const FwdParams &prm, int64_t slot, int blk, int bi, int bj, int wave, bool active, Smem &sm) {
+        constexpr int NBRV = c_cdiv(TMV * 16, 64);
+        typedef K32<P, FORM, TMV, TNV> Plain;
         const int lane = threadIdx.x & 63;
         const int i16 = lane & 15, kg = lane >> 4;
-        const int bi = blk / BN, bj = blk % BN;
         const int a0 = bi * TM * 16, b0 = bj * TN * 16;
         const int64_t e = active ? elem_of(prm, slot) : 0;
         ElemIn E;
@@ -234,14 +247,14 @@ struct K32S {
             load_elem(prm.coords, prm.D, prm.beta, prm.c, prm.f, e, E);
             if (FORM == FP16X3) ys = Plain::elem_scale(prm, E);
         }
-        f32x4 acc[TM][TN];
+        f32x4 acc[TMV][TNV];
 #pragma unroll
-        for (int ti = 0; ti < TM; ++ti)
+        for (int ti = 0; ti < TMV; ++ti)
 #pragma unroll
-            for (int tj = 0; tj < TN; ++tj) acc[ti][tj] = f32x4{0, 0, 0, 0};
-        double bacc[NBR];
+            for (int tj = 0; tj < TNV; ++tj) acc[ti][tj] = f32x4{0, 0, 0, 0};
+        double bacc[NBRV];
 #pragma unroll
-        for (int m = 0; m < NBR; ++m) bacc[m] = 0.0;
+        for (int m = 0; m < NBRV; ++m) bacc[m] = 0.0;
 
         uint4 pre[c_cdiv(NV, 256)];
         fetch(prm, 0, pre);
@@ -279,9 +292,9 @@ struct K32S {
                     wave_sync();
                     if (bj == 0) {
 #pragma unroll
-                        for (int m = 0; m < NBR; ++m) {
+                        for (int m = 0; m < NBRV; ++m) {
                             const int row = a0 + lane + 64 * m;
-                            if (lane + 64 * m < TM * 16 && row < N) {
+                            if (lane + 64 * m < TMV * 16 && row < N) {
                                 double acc_b = 0.0;
                                 for (int qq = 0; qq < cnt && qc + qq < NQ; ++qq)
                                     acc_b += sm.sf[wave][qq] * prm.B64[(size_t)(qc + qq) * 4 * NP + row];
@@ -299,14 +312,14 @@ struct K32S {
                 const HS *Ah = (const HS *)(const void *)sm.S[buf];
                 const HS *Al = (const HS *)(const void *)(sm.S[buf] + VA);
                 const float *Yc = SY ? (const float *)(const void *)(sm.S[buf] + 2 * VA)
-                                     : prm.Bc32 + (size_t)q0 * NP * 4;
-                HV yh[TN], yl[TN], ah[TM], al[TM];
+                                     : prm.Ycf + (size_t)kb * NP * 32;
+                HV yh[TNV], yl[TNV], ah[TMV], al[TMV];
 #pragma unroll
-                for (int tj = 0; tj < TN; ++tj) {
-                    if (b0 + tj * 16 < NP) {
-                        const int col = b0 + tj * 16 + i16;
-                        const float4 s0 = *(const float4 *)(Yc + ((size_t)qa * NP + col) * 4);
-                        const float4 s1 = *(const float4 *)(Yc + ((size_t)(qa + 1) * NP + col) * 4);
+                for (int tj = 0; tj < TNV; ++tj) {
+                    {
+                        const float *yp = Yc + ((size_t)(b0 / 16 + tj) * 64 + lane) * 8;
+                        const float4 s0 = *(const float4 *)yp;
+                        const float4 s1 = *(const float4 *)(yp + 4);
                         float y[8];
                         y[0] = wa[0] * s0.x + wa[1] * s0.y + wa[2] * s0.z + wa[3] * s0.w;
                         y[4] = wb[0] * s1.x + wb[1] * s1.y + wb[2] * s1.z + wb[3] * s1.w;
@@ -319,18 +332,18 @@ struct K32S {
                     }
                 }
 #pragma unroll
-                for (int ti = 0; ti < TM; ++ti) {
-                    if (a0 + ti * 16 < NP) {
-                        const int o = (a0 + ti * 16 + i16) * 32 + 8 * kg;
+                for (int ti = 0; ti < TMV; ++ti) {
+                    {
+                        const int o = ((a0 / 16 + ti) * 64 + lane) * 8;
                         ah[ti] = *(const HV *)(Ah + o);
                         al[ti] = *(const HV *)(Al + o);
                     }
                 }
 #pragma unroll
-                for (int ti = 0; ti < TM; ++ti)
+                for (int ti = 0; ti < TMV; ++ti)
 #pragma unroll
-                    for (int tj = 0; tj < TN; ++tj)
-                        if (a0 + ti * 16 < NP && b0 + tj * 16 < NP) {
+                    for (int tj = 0; tj < TNV; ++tj)
+                        {
                             acc[ti][tj] = mfma32(al[ti], yh[tj], acc[ti][tj]);
                             acc[ti][tj] = mfma32(ah[ti], yl[tj], acc[ti][tj]);
                             acc[ti][tj] = mfma32(ah[ti], yh[tj], acc[ti][tj]);
@@ -343,30 +356,45 @@ struct K32S {
         const float unscale = FORM == FP16X3 ? ldexpf(1.0f, -prm.f16_shift) / ys : 1.0f;
         float *Aout = (float *)prm.A + offA_of(prm, e, N);
 #pragma unroll
-        for (int ti = 0; ti < TM; ++ti)
+        for (int ti = 0; ti < TMV; ++ti)
 #pragma unroll
-            for (int tj = 0; tj < TN; ++tj) {
+            for (int tj = 0; tj < TNV; ++tj) {
                 const int col = b0 + tj * 16 + i16;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = a0 + ti * 16 + 4 * kg + r;
-                    if (row < N && col < N && a0 + ti * 16 < NP && b0 + tj * 16 < NP)
+                    if (row < N && col < N)
                         Aout[(size_t)row * N + col] = acc[ti][tj][r] * unscale;
                 }
             }
         if (bj == 0) {
             float *bout = (float *)prm.b + offb_of(prm, e, N);
 #pragma unroll
-            for (int m = 0; m < NBR; ++m) {
+            for (int m = 0; m < NBRV; ++m) {
                 const int row = a0 + lane + 64 * m;
-                if (lane + 64 * m < TM * 16 && row < N) bout[row] = (float)bacc[m];
+                if (lane + 64 * m < TMV * 16 && row < N) bout[row] = (float)bacc[m];
             }
+        }
+    }
+
+    // Tile counts of the last row/column block are compile-time constants,
+    // so the inner loops carry no bounds tests and stay one basic block.
+    __device__ static void run(const FwdParams &prm, int64_t slot, int blk, int wave, bool active, Smem &sm) {
+        const int bi = blk / BN, bj = blk % BN;
+        constexpr int TML = NT - (BM - 1) * TM, TNL = NT - (BN - 1) * TN;
+        if (bi == BM - 1) {
+            if (bj == BN - 1) body<TML, TNL>(prm, slot, blk, bi, bj, wave, active, sm);
+            else body<TML, TN>(prm, slot, blk, bi, bj, wave, active, sm);
+        } else {
+            if (bj == BN - 1) body<TM, TNL>(prm, slot, blk, bi, bj, wave, active, sm);
+            else body<TM, TN>(prm, slot, blk, bi, bj, wave, active, sm);
         }
     }
 };
 
-template <class KER>
-__global__ __launch_bounds__(256) void fwd_staged(FwdParams prm) {
+// MINW: waves per SIMD the register allocation must allow (1 = no limit).
+template <class KER, int MINW>
+__global__ __launch_bounds__(256, MINW) void fwd_staged(FwdParams prm) {
     __shared__ typename KER::Smem sm;
     const int wave = wave_uniform(threadIdx.x >> 6);
     const int64_t item = (int64_t)blockIdx.x * 4 + wave;
@@ -376,3 +404,4 @@ __global__ __launch_bounds__(256) void fwd_staged(FwdParams prm) {
 }
 
 }  // namespace feint
+

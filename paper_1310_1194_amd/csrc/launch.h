@@ -15,8 +15,9 @@ struct FwdParams {
     const double *B64;       // [nqp][4][npad]
     const float *B32;        // [nqp][4][npad]
     const float *Bc32;       // [nqp][npad][4]
-    const uint16_t *Bhi;     // [nkb][npad][32] split table of the form (bf16 or fp16)
-    const uint16_t *Blo;
+    const uint16_t *Bhi;     // [nkb][npad/16][64][8] split table of the form (bf16 or fp16),
+    const uint16_t *Blo;     //   in A-fragment order
+    const float *Ycf;        // [nkb][npad/16][64][8] FP32 columns in B-fragment order
     float bmax;              // max |B| (fp16 form: used for the per-element scale)
     int f16_shift;           // fp16 tables hold B * 2^f16_shift
     // mixed-degree launches: element ids in bucket order and packed offsets
@@ -28,7 +29,8 @@ struct FwdParams {
 // per wave; `launch` enqueues the direct (one work item per wave) kernel.
 struct FwdVariant {
     int tm, tn;
-    int staged;          // 1: the table is staged through LDS per workgroup
+    int staged;          // 1: the table is staged through LDS per workgroup (2: A operands only)
+    int minw;            // waves per SIMD the register allocation allows
     void (*launch)(const FwdParams &, hipStream_t);
     int64_t (*items_per_elem)();
 };

@@ -315,21 +315,26 @@ HostTables build_tables(int p) {
     T.f16_shift = 13 - (int)std::floor(std::log2(bmax));
     const double fs = std::ldexp(1.0, T.f16_shift);
     const size_t nsplit = (size_t)T.nkb * np * 32;
+    const int ntile = np / 16;
     T.bf_hi.assign(nsplit, 0); T.bf_lo.assign(nsplit, 0);
     T.hf_hi.assign(nsplit, 0); T.hf_lo.assign(nsplit, 0);
+    T.Ycf.assign(nsplit, 0.0f);
     for (int kb = 0; kb < T.nkb; ++kb)
         for (int a = 0; a < np; ++a)
             for (int k = 0; k < 32; ++k) {
-                int q = kb * 8 + k / 4, r = k % 4;
-                double x = T.B64[((size_t)q * 4 + r) * np + a];
-                size_t o = ((size_t)kb * np + a) * 32 + k;
-                uint16_t h = to_bf16((float)x);
+                const int q = kb * 8 + k / 4, r = k % 4;
+                const double x = T.B64[((size_t)q * 4 + r) * np + a];
+                const int lane = a % 16 + 16 * (k / 8);
+                const size_t o = (((size_t)kb * ntile + a / 16) * 64 + lane) * 8 + k % 8;
+                const uint16_t h = to_bf16((float)x);
                 T.bf_hi[o] = h;
                 T.bf_lo[o] = to_bf16((float)(x - (double)from_bf16(h)));
-                double xs = x * fs;
-                uint16_t hh = to_f16(xs);
+                const double xs = x * fs;
+                const uint16_t hh = to_f16(xs);
                 T.hf_hi[o] = hh;
                 T.hf_lo[o] = to_f16(xs - from_f16(hh));
+                // the same (point, row, column) as a B-fragment column value
+                T.Ycf[o] = (float)x;
             }
     return T;
 }

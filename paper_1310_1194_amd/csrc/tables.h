@@ -26,8 +26,15 @@ struct HostTables {
     std::vector<double> BT64;        // [npad][nqp*4]  transpose of B64 (shape-function major)
     std::vector<float> BT32;         // same, FP32
     std::vector<float> Bc32;         // [nqp][npad][4]  the four rows of a column side by side, FP32
-    std::vector<uint16_t> bf_hi, bf_lo;   // [nkb][npad][32]  k = 4*(point in block) + row
-    std::vector<uint16_t> hf_hi, hf_lo;   // same layout, fp16 of B * 2^f16_shift
+    // Split tables in 16x16x32 MFMA A-fragment order: [nkb][npad/16][64 lanes][8],
+    // lane l holds rows 16 t + l%16, k = 8 (l/16) .. +7 of K-block kb, where
+    // k = 4*(point in block) + row (phi, d/dxi1, d/dxi2, d/dzeta).
+    std::vector<uint16_t> bf_hi, bf_lo;   // bf16
+    std::vector<uint16_t> hf_hi, hf_lo;   // fp16 of B * 2^f16_shift
+    // FP32 columns in B-fragment order: [nkb][npad/16][64 lanes][2][4], lane
+    // l holds column 16 t + l%16 at points 2 (l/16) and 2 (l/16) + 1 of the
+    // K-block, four rows each.
+    std::vector<float> Ycf;
 };
 
 // Build every table of degree p (1..7) in FP64 on the host.
