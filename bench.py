@@ -34,6 +34,9 @@ HBM_PEAK_GBS = 8000.0
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "fp16x3": 2500.0}
 FORMS = ["bf16x3", "fp16x3", "fp32", "fp64"]
 HEADLINE = "bf16x3"
+DTYPE_DESC = {"bf16x3": "bf16x3 (split bf16 MFMA, fp32 accumulate, fp64 geometry)",
+              "fp16x3": "fp16x3 (split fp16 MFMA, fp32 accumulate, fp64 geometry)",
+              "fp32": "fp32 (fp32 MFMA, fp64 geometry)", "fp64": "fp64"}
 KERNEL_SOURCES = ["paper_1310_1194_amd/csrc/fwd_kernels.h", "paper_1310_1194_amd/csrc/device_common.h"]
 
 
@@ -79,13 +82,40 @@ def rel_err(got, ref):
     return float(np.linalg.norm(got - ref) / np.linalg.norm(ref)), float(per.max())
 
 
+def timed(fn, steps, warmup, stream=None):
+    """Warm up, then time `steps` calls with HIP events on the launch stream
+    (bracketed by device synchronisation); returns (mean, min) ms per call and
+    the wall-clock ms per call."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = stream or torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(steps):
+        fn()
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    per = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+    return float(np.mean(per)), float(np.min(per)), wall
+
+
+def fmt(d):
+    return {k: (float(f"{v:.5g}") if isinstance(v, float) else (fmt(v) if isinstance(v, dict) else v))
+            for k, v in d.items()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="p4_131072")
-    ap.add_argument("--forms", default=",".join(FORMS))
+    ap.add_argument("--mode", default="forward", choices=["forward", "adjoint", "mixed"])
+    ap.add_argument("--workload", default=None)
+    ap.add_argument("--forms", default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (CPU baseline and errors)")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-tune", action="store_true")
@@ -98,7 +128,16 @@ def main():
                                    "is independent per element and is not sharded here",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.mode == "adjoint":
+        return bench_adjoint(args)
+    if args.mode == "mixed":
+        return bench_mixed(args)
+    return bench_forward(args)
 
+
+def bench_forward(args):
+    args.workload = args.workload or "p4_131072"
+    args.forms = args.forms or ",".join(FORMS)
     import torch
     import paper_1310_1194_amd as F
 
@@ -112,7 +151,7 @@ def main():
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     X = (t(batch.coords), t(batch.D), t(batch.beta), t(batch.c), t(batch.f))
     forms = [f for f in args.forms.split(",") if f]
-    assert HEADLINE in forms
+    headline = HEADLINE if HEADLINE in forms else forms[0]
 
     if args.copy_cal:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -178,14 +217,28 @@ def main():
             r["rel_err_b"] = gb
             r["err_sample"] = m
 
-    h = results[HEADLINE]
-    traffic = traffic_record(f"fwd:{HEADLINE}:{args.workload}")
-    roofline = {"bound": "mfma", "achieved": h["gflops"] / 1e3, "peak": PEAK_TFLOPS[HEADLINE],
-                "unit": "TFLOP/s", "frac": h["gflops"] / 1e3 / PEAK_TFLOPS[HEADLINE],
-                "traffic": traffic,
-                "kernel_ms": h["kernel_ms_mean"], "flops_per_launch": fdom * ne,
-                "note": "algorithmic flops 8 n^2 nq per element (one product per entry; "
-                        "the split form issues three bf16 products)"}
+    h = results[headline]
+    traffic = traffic_record(f"fwd:{headline}:{args.workload}")
+    es = 8 if headline == "fp64" else 4
+    alg_bytes = ne * costmodel.bytes_per_element(p, es)
+    # bound = the larger ideal time: MFMA work (three products for a split
+    # form) at the dtype's dense peak, or the algorithmic bytes at HBM peak
+    products = 3 if headline in ("bf16x3", "fp16x3") else 1
+    t_mfma = products * fdom * ne / (PEAK_TFLOPS[headline] * 1e12)
+    t_hbm = alg_bytes / (HBM_PEAK_GBS * 1e9)
+    if t_hbm > t_mfma:
+        roofline = {"bound": "hbm", "achieved": h["hbm_gbs_algorithmic"], "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": h["hbm_gbs_algorithmic"] / HBM_PEAK_GBS}
+    else:
+        roofline = {"bound": "mfma", "achieved": h["gflops"] / 1e3, "peak": PEAK_TFLOPS[headline],
+                    "unit": "TFLOP/s", "frac": h["gflops"] / 1e3 / PEAK_TFLOPS[headline]}
+    npad, nqp = (costmodel.nshp(p) + 15) // 16 * 16, (costmodel.nq(p) + 7) // 8 * 8
+    hw_flops = products * 8.0 * npad * npad * (nqp if products == 3 else costmodel.nq(p)) * ne
+    roofline.update({"traffic": traffic, "kernel_ms": h["kernel_ms_mean"], "flops_per_launch": fdom * ne,
+                     "hw_mfma_frac": hw_flops / (h["kernel_ms_mean"] * 1e-3) / (PEAK_TFLOPS[headline] * 1e12),
+                     "alg_bytes_per_launch": alg_bytes,
+                     "note": "algorithmic flops 8 n^2 nq per element (one product per entry; "
+                             "a split form issues three products); bytes 256 in + (n^2+n) outputs"})
     forms_out = {}
     for form, r in results.items():
         forms_out[form] = {k: (float(f"{v:.5g}") if isinstance(v, float) else v) for k, v in r.items()
@@ -201,11 +254,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16x3 (split bf16 MFMA, fp32 accumulate, fp64 geometry)",
+        "dtype": DTYPE_DESC[headline],
         "data": "synthetic (seeded perturbed prism mesh and coefficients)",
         "config": {"workload": args.workload, "p": p, "ne": ne, "nshp": n, "nq": q,
                    "mesh": f"{w['nx']}x{w['ny']}x{w['nz']}", "perturbation": w["amp"], "seed": w["seed"],
-                   "form": HEADLINE, "parallelism": "single GPU"},
+                   "form": headline, "parallelism": "single GPU"},
         "gflops": h["gflops"],
         "speedup_vs_fp64_gpu": results["fp64"]["kernel_ms_mean"] / h["kernel_ms_mean"] if "fp64" in results else None,
         "roofline": roofline,
@@ -214,6 +267,126 @@ def main():
         "device": torch.cuda.get_device_name(0),
     }
     print(json.dumps(line))
+
+
+def bench_adjoint(args):
+    """Adjoint of the p=3 workload (or another): gradients of
+    sum_e <G_e,A_e> + <g_e,b_e>, FP64 and FP32 forms."""
+    import torch
+    import paper_1310_1194_amd as F
+    args.workload = args.workload or "adj_p3_131072"
+    forms = (args.forms or "fp64,fp32").split(",")
+    w = meshgen.WORKLOADS[args.workload]
+    p = w["p"]
+    batch = meshgen.workload(args.workload)
+    G, g, sample = meshgen.adjoint_seeds(batch, p)
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    X = (t(batch.coords), t(batch.D), t(batch.beta), t(batch.c), t(batch.f))
+    ne = batch.ne
+    res = {}
+    for form in forms:
+        dt = torch.float64 if form == "fp64" else torch.float32
+        Gd, gd = t(G).to(dt), t(g).to(dt)
+        out = None
+
+        def step():
+            nonlocal out
+            out = F.adjoint_raw(*X, Gd, gd, p, form)
+        ms, mn, wall = timed(step, args.steps, args.warmup)
+        es = 8 if form == "fp64" else 4
+        res[form] = dict(kernel_ms_mean=ms, kernel_ms_min=mn, ms_per_step=wall, elements_per_s=ne / (wall * 1e-3),
+                         gflops=costmodel.f_dom(p) * ne / (ms * 1e-3) / 1e9,
+                         hbm_gbs_algorithmic=ne * costmodel.adjoint_bytes_per_element(p, es) / (ms * 1e-3) / 1e9,
+                         grads=[o[torch.from_numpy(sample).to(dev)].cpu().numpy() for o in out])
+        del Gd, gd
+        print(f"[bench] adjoint {form}: {ms:.3f} ms", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        sub = batch.subset(sample)
+        ref = oracle.adjoint(p, sub.coords, sub.D, sub.beta, sub.c, sub.f, G[sample], g[sample])
+        for form, r in res.items():
+            r["rel_err"] = max(float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(r["grads"], ref[:5]))
+        m = min(ne, 4096)
+        t0 = time.perf_counter()
+        part = batch.subset(np.arange(m))
+        oracle.adjoint(p, part.coords, part.D, part.beta, part.c, part.f, G[:m], g[:m])
+        spent = time.perf_counter() - t0
+        cpu = {"value": m / spent, "unit": "elements/s", "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": f"first {m} of {ne} elements ({spent:.1f} s, FP64 reverse mode)"}
+    for r in res.values():
+        r.pop("grads", None)
+    h = res[forms[0]]
+    peak = PEAK_TFLOPS["fp64" if forms[0] == "fp64" else "fp32"]
+    line = {"metric": "adjoint elements/s (gradients w.r.t. D, beta, c, f, coordinates)", "value": h["elements_per_s"],
+            "unit": "elements/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": h["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": forms[0], "data": "synthetic (seeded mesh, coefficients, G, g ~ N(0,1))",
+            "config": {"workload": args.workload, "p": p, "ne": ne, "form": forms[0]},
+            "roofline": {"bound": "mfma", "achieved": h["gflops"] / 1e3, "peak": peak, "unit": "TFLOP/s",
+                         "frac": h["gflops"] / 1e3 / peak, "traffic": None},
+            "cpu_baseline": cpu, "forms": fmt(res)}
+    print(json.dumps(line))
+
+
+def bench_mixed(args):
+    """Mixed-degree batch (p ~ U{1..6}, shuffled): bucketing + persistent
+    launch, eager and as a replayed HIP graph."""
+    import torch
+    import paper_1310_1194_amd as F
+    args.workload = args.workload or "mixed_262144"
+    form = (args.forms or "fp32").split(",")[0]
+    batch = meshgen.workload(args.workload)
+    ne = batch.ne
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    X = (t(batch.coords), t(batch.D), t(batch.beta), t(batch.c), t(batch.f))
+    pd = t(batch.p)
+    plan = F.MixedPlan(ne, form)
+    offA, offb = plan.bucket(pd)
+    A, b = plan.alloc_outputs(offA, offb)
+    tune_ms = None if args.no_tune else plan.autotune(*X, A, b, offA, offb, reps=2)
+    ms_b, _, _ = timed(lambda: plan.bucket(pd), args.steps, args.warmup)
+    ms_p, mn_p, _ = timed(lambda: plan.integrate(*X, A, b, offA, offb), args.steps, args.warmup)
+    gA, gb = torch.empty_like(A), torch.empty_like(b)
+    goA, gob = torch.empty_like(offA), torch.empty_like(offb)
+    plan.capture(*X, pd, gA, gb, goA, gob)
+    ms_g, mn_g, wall_g = timed(plan.replay, args.steps, args.warmup)
+    counts = np.bincount(batch.p, minlength=7)
+    flops = sum(int(counts[d]) * costmodel.f_dom(d) for d in range(1, 7))
+    es = 8 if form == "fp64" else 4
+    bytes_ = sum(int(counts[d]) * costmodel.bytes_per_element(d, es) for d in range(1, 7))
+    peak = PEAK_TFLOPS[form]
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        rates = {}
+        for d in range(1, 7):
+            idx = np.nonzero(batch.p == d)[0][: max(16, 4096 >> (2 * (d - 1)))]
+            sub = batch.subset(idx)
+            t0 = time.perf_counter()
+            oracle.integrate(d, sub.coords, sub.D, sub.beta, sub.c, sub.f)
+            rates[d] = len(idx) / (time.perf_counter() - t0)
+        frac = counts[1:] / ne
+        rate = 1.0 / sum(frac[d - 1] / rates[d] for d in range(1, 7))
+        cpu = {"value": rate, "unit": "elements/s", "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": "per degree the first elements of that degree (4096 >> 2(p-1), at least 16); "
+                         "rate combined with the batch's degree mix"}
+    line = {"metric": "mixed-degree elements/s (one persistent degree-bucketed launch, HIP graph)",
+            "value": ne / (ms_g * 1e-3), "unit": "elements/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": wall_g, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": form, "data": "synthetic (seeded mesh, p ~ U{1..6}, shuffled)",
+            "config": {"workload": args.workload, "ne": ne, "form": form, "degree_counts": counts[1:].tolist(),
+                       "tile_set": plan.tile},
+            "bucket_ms": ms_b, "persistent_ms": ms_p, "persistent_ms_min": mn_p, "graph_ms": ms_g,
+            "graph_ms_min": mn_g, "tune_ms": tune_ms, "gflops": flops / (ms_p * 1e-3) / 1e9,
+            "roofline": {"bound": "mfma", "achieved": flops / (ms_p * 1e-3) / 1e12, "peak": peak,
+                         "unit": "TFLOP/s", "frac": flops / (ms_p * 1e-3) / 1e12 / peak, "traffic": None,
+                         "flops_per_launch": flops, "alg_bytes_per_launch": bytes_},
+            "cpu_baseline": cpu}
+    plan.close()
+    print(json.dumps(fmt(line)))
 
 
 if __name__ == "__main__":

@@ -1,0 +1,64 @@
+"""The paper's printed counts (Tables 1-3) reproduced from their formulas."""
+from pathlib import Path
+
+import pytest
+
+from paper_1310_1194_amd import costmodel as cm
+
+GOLDEN = Path(__file__).resolve().parent / "golden" / "paper_tables.txt"
+
+
+def golden():
+    rows = {}
+    for line in GOLDEN.read_text().splitlines():
+        if line.strip() and not line.startswith("#"):
+            key, *vals = line.split()
+            rows[key] = [float(v) for v in vals]
+    return rows
+
+
+P = range(1, 8)
+
+
+def test_table1_and_table3_sizes():
+    g = golden()
+    assert [4 * cm.nshp(p) for p in P] == g["table3_shape_at_point"]
+    assert [4 * cm.paper_nI(p) for p in P] == g["table3_quadrature"]
+    assert [cm.nshp(p) ** 2 for p in P] == g["table3_element_matrix"]
+    assert [4 * cm.nshp(p) * cm.paper_nI(p) for p in P] == g["table3_shape_all_points"]
+
+
+def test_table2_per_point():
+    g = golden()
+    shape = [cm.paper_shape_ops_per_point(p) for p in P]
+    # p = 7 is printed as 5626; the formula gives 5628 (see the total below)
+    assert shape[:6] == g["table2_shape_per_point"][:6]
+    assert shape[6] == 5628 and g["table2_shape_per_point"][6] == 5626
+    assert [cm.PAPER_JACOBIAN_OPS] * 7 == g["table2_jacobian_per_point"]
+    assert [cm.paper_matrix_ops_per_point(p) for p in P] == g["table2_matrix_per_point"]
+
+
+@pytest.mark.parametrize("p", P)
+def test_table2_totals(p):
+    g = golden()
+    nI = cm.paper_nI(p)
+    assert abs(cm.paper_shape_ops_per_point(p) * nI / 1e3 - g["table2_shape_total"][p - 1]) < 0.05 * max(1, g["table2_shape_total"][p - 1] / 100)
+    assert abs(cm.PAPER_JACOBIAN_OPS * nI / 1e3 - g["table2_jacobian_total"][p - 1]) < 0.006
+    # the printed totals are truncated to whole thousands at p = 5, 6
+    assert 0 <= cm.paper_matrix_ops_per_point(p) * nI / 1e3 - g["table2_matrix_total"][p - 1] < 1.0
+
+
+def test_sandy_bridge_gflops_consistency():
+    """Table 'gigaflops' one-core row = Table 2 totals / Table 'times' row."""
+    g = golden()
+    for p in P:
+        rate = cm.paper_total_ops(p) / (g["times_sandy_bridge"][p - 1] * 1e-6) / 1e9
+        assert abs(rate - g["gflops_sandy_bridge"][p - 1]) < 0.02 * g["gflops_sandy_bridge"][p - 1]
+
+
+def test_this_library_counts():
+    assert [cm.nshp(p) for p in P] == [6, 18, 40, 75, 126, 196, 288]
+    assert [cm.nq(p) for p in P] == [8, 27, 64, 125, 216, 343, 512]
+    assert cm.f_dom(4) == 8 * 75 * 75 * 125
+    assert cm.INPUT_BYTES == 256
+    assert cm.bytes_per_element(4, 8) == 256 + 8 * (75 * 75 + 75)
