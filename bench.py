@@ -281,15 +281,20 @@ def bench_adjoint(args):
     w = meshgen.WORKLOADS[args.workload]
     p = w["p"]
     batch = meshgen.workload(args.workload)
-    G, g, sample = meshgen.adjoint_seeds(batch, p)
     dev = torch.device("cuda:0")
+    if costmodel.nshp(p) ** 2 * batch.ne > 2 ** 28:       # large G: drawn on the device
+        Gdev, gdev, sample = meshgen.adjoint_seeds_device(batch, p, seed=w["seed"])
+        G = g = None
+    else:
+        G, g, sample = meshgen.adjoint_seeds(batch, p)
+        Gdev = gdev = None
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     X = (t(batch.coords), t(batch.D), t(batch.beta), t(batch.c), t(batch.f))
     ne = batch.ne
     res = {}
     for form in forms:
         dt = torch.float64 if form == "fp64" else torch.float32
-        Gd, gd = t(G).to(dt), t(g).to(dt)
+        Gd, gd = (t(G).to(dt), t(g).to(dt)) if G is not None else (Gdev.to(dt), gdev.to(dt))
         out = None
 
         def step():
@@ -307,14 +312,23 @@ def bench_adjoint(args):
     if not args.no_cpu:
         import oracle
         sub = batch.subset(sample)
-        ref = oracle.adjoint(p, sub.coords, sub.D, sub.beta, sub.c, sub.f, G[sample], g[sample])
+        si = torch.from_numpy(sample).to(dev)
+        Gs = G[sample] if G is not None else Gdev[si].cpu().numpy()
+        gs = g[sample] if g is not None else gdev[si].cpu().numpy()
+        ref = oracle.adjoint(p, sub.coords, sub.D, sub.beta, sub.c, sub.f, Gs, gs)
         for form, r in res.items():
             r["rel_err"] = max(float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(r["grads"], ref[:5]))
-        m = min(ne, 4096)
-        t0 = time.perf_counter()
-        part = batch.subset(np.arange(m))
-        oracle.adjoint(p, part.coords, part.D, part.beta, part.c, part.f, G[:m], g[:m])
-        spent = time.perf_counter() - t0
+        chunk = min(ne, max(16, 2048 >> (2 * max(0, p - 3))))
+        m, spent = 0, 0.0
+        while spent < args.cpu_budget and m < ne:     # whole chunks until the time budget is spent
+            lo, hi = m, min(ne, m + chunk)
+            part = batch.subset(np.arange(lo, hi))
+            Gm = G[lo:hi] if G is not None else Gdev[lo:hi].cpu().numpy()
+            gm = g[lo:hi] if g is not None else gdev[lo:hi].cpu().numpy()
+            t0 = time.perf_counter()
+            oracle.adjoint(p, part.coords, part.D, part.beta, part.c, part.f, Gm, gm)
+            spent += time.perf_counter() - t0
+            m = hi
         cpu = {"value": m / spent, "unit": "elements/s", "cores": oracle.max_threads(), "kind": "oracle",
                "sample": f"first {m} of {ne} elements ({spent:.1f} s, FP64 reverse mode)"}
     for r in res.values():
@@ -349,6 +363,14 @@ def bench_mixed(args):
     offA, offb = plan.bucket(pd)
     A, b = plan.alloc_outputs(offA, offb)
     tune_ms = None if args.no_tune else plan.autotune(*X, A, b, offA, offb, reps=2)
+    chosen = plan.tile
+    sets_ms = {}
+    for ts in range(plan.tile_count):       # every compiled tile set, for the record
+        plan.tile = ts
+        sets_ms[plan.tile_describe(ts)] = timed(lambda: plan.integrate(*X, A, b, offA, offb), 3, 1)[0]
+        print(f"[bench] mixed tile set {plan.tile_describe(ts)}: {sets_ms[plan.tile_describe(ts)]:.3f} ms",
+              file=sys.stderr, flush=True)
+    plan.tile = chosen
     ms_b, _, _ = timed(lambda: plan.bucket(pd), args.steps, args.warmup)
     ms_p, mn_p, _ = timed(lambda: plan.integrate(*X, A, b, offA, offb), args.steps, args.warmup)
     gA, gb = torch.empty_like(A), torch.empty_like(b)
@@ -380,7 +402,8 @@ def bench_mixed(args):
             "warmup": args.warmup, "ms_per_step": wall_g, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": form, "data": "synthetic (seeded mesh, p ~ U{1..6}, shuffled)",
             "config": {"workload": args.workload, "ne": ne, "form": form, "degree_counts": counts[1:].tolist(),
-                       "tile_set": plan.tile},
+                       "tile_set": plan.tile, "tile_set_shapes": plan.tile_describe(plan.tile)},
+            "tile_sets_ms": sets_ms,
             "bucket_ms": ms_b, "persistent_ms": ms_p, "persistent_ms_min": mn_p, "graph_ms": ms_g,
             "graph_ms_min": mn_g, "tune_ms": tune_ms, "gflops": flops / (ms_p * 1e-3) / 1e9,
             "roofline": {"bound": "mfma", "achieved": flops / (ms_p * 1e-3) / 1e12, "peak": peak,

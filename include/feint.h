@@ -168,18 +168,30 @@ feint_status feint_mixed_autotune(feint_mixed_plan *plan, const feint_elements *
 int feint_mixed_tile_count(const feint_mixed_plan *plan);
 int feint_mixed_tile_get(const feint_mixed_plan *plan);
 feint_status feint_mixed_tile_set(feint_mixed_plan *plan, int tile);
+/* Describe tile set `tile` into buf: the per-degree shapes for p = 1..6,
+   comma-separated, each "TMxTN" (16x16 MFMA tiles per wave) or "vL"
+   (vector-ALU kernel, L lanes per element).  INVALID_ARG for a null plan or
+   buffer or an index out of range. */
+feint_status feint_mixed_tile_describe(const feint_mixed_plan *plan, int tile, char *buf, size_t len);
 void feint_mixed_plan_destroy(feint_mixed_plan *plan);
 
 /* ---- Tile autotuning -------------------------------------------------------
-   Each (degree, form) has several compiled tile shapes (columns of 16x16
-   output tiles per wave).  feint_autotune times each candidate with HIP
+   Each (degree, form) has several compiled variants: tile shapes of the MFMA
+   kernels (16x16 output tiles per wave) and, for FP64 and FP32 at p <= 3,
+   vector-ALU kernels that give each element a group of lanes (Sec. 2.2's
+   operation counts make the contraction too small at low degree to fill
+   MFMA tiles; which side of the crossover a degree falls on is what the
+   autotuner measures).  feint_autotune times each candidate with HIP
    events on the caller's inputs and outputs (ne elements, `reps`
    repetitions) and keeps the fastest for later calls; feint_tile_get/set
    read or force the choice (index into the candidate list). */
 int feint_tile_count(int p, feint_form form);
 int feint_tile_get(int p, feint_form form);
 feint_status feint_tile_set(int p, feint_form form, int tile);
-/* Describe candidate `tile` as "TMxTN" output tiles per wave into buf. */
+/* Describe candidate `tile` into buf: "TMxTN" output tiles per wave, with
+   "s" (table staged in LDS) or "sa" (A operands staged), or "vL" (vector-ALU
+   kernel, L lanes per element); "o2" marks a two-waves-per-SIMD register
+   budget. */
 feint_status feint_tile_describe(int p, feint_form form, int tile, char *buf, size_t len);
 feint_status feint_autotune(const feint_elements *el, int p, feint_form form,
                             void *A, void *b, int reps, double *best_ms, void *stream);

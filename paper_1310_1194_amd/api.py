@@ -229,3 +229,8 @@ class MixedPlan:
     @property
     def tile_count(self) -> int:
         return lib().feint_mixed_tile_count(self._h)
+
+    def tile_describe(self, t: int) -> str:
+        buf = ctypes.create_string_buffer(64)
+        check("feint_mixed_tile_describe", lib().feint_mixed_tile_describe(self._h, int(t), buf, 64))
+        return buf.value.decode()

@@ -154,7 +154,7 @@ const FwdVariant *chosen_variant(int p, int form) {
 }
 
 feint_status launch_forward(const FwdParams &prm, const FwdVariant *v, hipStream_t stream) {
-    const int64_t blocks = (prm.ne * v->items_per_elem() + 3) / 4;
+    const int64_t blocks = (v->items(prm.ne) + 3) / 4;
     if (blocks > 0x7fffffffLL) return FEINT_ERR_TOO_LARGE;
     (void)hipGetLastError();
     v->launch(prm, stream);
@@ -227,9 +227,12 @@ feint_status feint_tile_describe(int p, feint_form form, int tile, char *buf, si
     if (!valid_form(form)) return FEINT_ERR_UNSUPPORTED_FORM;
     const FwdVariant *v = fwd_variants(form, p, &cnt);
     if (!buf || tile < 0 || tile >= cnt) return FEINT_ERR_INVALID_ARG;
-    std::snprintf(buf, len, "%dx%d%s%s", v[tile].tm, v[tile].tn,
-                  v[tile].staged == 1 ? "s" : (v[tile].staged == 2 ? "sa" : ""),
-                  v[tile].minw > 1 ? "o2" : "");
+    if (v[tile].staged == 3)
+        std::snprintf(buf, len, "v%d%s", v[tile].tn, v[tile].minw > 1 ? "o2" : "");
+    else
+        std::snprintf(buf, len, "%dx%d%s%s", v[tile].tm, v[tile].tn,
+                      v[tile].staged == 1 ? "s" : (v[tile].staged == 2 ? "sa" : ""),
+                      v[tile].minw > 1 ? "o2" : "");
     return FEINT_OK;
 }
 

@@ -120,6 +120,10 @@ __device__ inline void wave_sync() {
 
 __device__ inline int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Fused multiply-add in the operands' own precision.
+__device__ inline float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // Row length of per-lane LDS rows holding 16 values: padded so that the
 // 16-byte accesses of 16 consecutive lanes fall in distinct banks (20 floats
 // = 80 B, 18 doubles = 144 B) while every row stays 16-byte aligned.

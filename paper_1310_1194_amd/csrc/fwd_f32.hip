@@ -1,16 +1,21 @@
-// Forward kernels, FP32 form (v_mfma_f32_16x16x4_f32): compiled tile shapes per degree (the first is
-// the default until the autotuner picks another).
+// Forward kernels, FP32 form: compiled variants per degree (the first is the default until the
+// autotuner picks another): vector-ALU kernels at low degree, v_mfma_f32_16x16x4_f32 tiles.
 #include "fwd_registry.h"
 
 namespace feint {
 namespace {
 const FwdVariant v1[] = {
+    FEINT_KV(1, float, 8, 2),
+    FEINT_KV(1, float, 6, 2),
     FEINT_K4S(1, float, 1, 1, 8, 1)};
 const FwdVariant v2[] = {
+    FEINT_KV(2, float, 18, 2),
+    FEINT_KV(2, float, 32, 2),
     FEINT_K4S(2, float, 2, 2, 8, 1)};
 const FwdVariant v3[] = {
     FEINT_K4S(3, float, 3, 3, 8, 1),
-    FEINT_K4S(3, float, 3, 1, 8, 2)};
+    FEINT_K4S(3, float, 3, 1, 8, 2),
+    FEINT_KV(3, float, 40, 2)};
 const FwdVariant v4[] = {
     FEINT_K4S(4, float, 5, 5, 8, 1),
     FEINT_K4S(4, float, 5, 3, 8, 2),

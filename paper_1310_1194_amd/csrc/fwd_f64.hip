@@ -1,17 +1,22 @@
-// Forward kernels, FP64 form (v_mfma_f64_16x16x4_f64): compiled tile shapes per degree (the first is
-// the default until the autotuner picks another).
+// Forward kernels, FP64 form: compiled variants per degree (the first is the default until the
+// autotuner picks another): vector-ALU kernels at low degree, v_mfma_f64_16x16x4_f64 tiles.
 #include "fwd_registry.h"
 
 namespace feint {
 namespace {
 const FwdVariant v1[] = {
+    FEINT_KV(1, double, 8, 2),
+    FEINT_KV(1, double, 6, 2),
     FEINT_K4S(1, double, 1, 1, 8, 1)};
 const FwdVariant v2[] = {
+    FEINT_KV(2, double, 18, 2),
+    FEINT_KV(2, double, 32, 2),
     FEINT_K4S(2, double, 2, 2, 8, 1),
     FEINT_K4S(2, double, 2, 1, 8, 2)};
 const FwdVariant v3[] = {
     FEINT_K4S(3, double, 3, 3, 8, 1),
-    FEINT_K4S(3, double, 3, 1, 8, 2)};
+    FEINT_K4S(3, double, 3, 1, 8, 2),
+    FEINT_KV(3, double, 40, 2)};
 const FwdVariant v4[] = {
     FEINT_K4S(4, double, 5, 3, 8, 2),
     FEINT_K4U(4, double, 5, 1, 2),

@@ -52,18 +52,20 @@ template <int P, typename T, int TM, int TN>
 struct K4 {
     static constexpr int N = c_nshp(P), NP = c_pad16(N), NT = NP / 16, NQ = c_nq(P);
     static constexpr int BM = c_cdiv(NT, TM), BN = c_cdiv(NT, TN), NBLK = BM * BN;
+    static constexpr int EPI = 1;                      // element slots per work item
     static constexpr int NBR = c_cdiv(TM * 16, 64);   // load-vector rows per lane
     typedef typename AccT<T>::type V4;
 
-    struct Smem {
-        T W[4][64][WROW<T>::value];   // padded rows: conflict-free per-lane writes
-        double sf[4][64];
+    struct Slice {                    // one wave's LDS
+        T W[64][WROW<T>::value];      // padded rows: conflict-free per-lane writes
+        double sf[64];
     };
+    struct Smem { Slice w[4]; };
 
-    // One work item: block `blk` of element slot `slot`.  `wave` indexes the
-    // wave's LDS slice.
+    // One work item: block `blk` of element slot `slot`, with the wave's LDS
+    // slice `sl`.
     template <int TMV, int TNV>
-    __device__ static void body(const FwdParams &prm, int64_t slot, int blk, int bi, int bj, int wave, Smem &sm) {
+    __device__ static void body(const FwdParams &prm, int64_t slot, int blk, int bi, int bj, Slice &sl) {
         constexpr int NBRV = c_cdiv(TMV * 16, 64);
         const int lane = threadIdx.x & 63;
         const int i16 = lane & 15, kg = lane >> 4;
@@ -90,8 +92,8 @@ struct K4 {
                 const double det = point_block(E, qp[0], qp[1], qp[2], qp[3], W, sf);
                 if (!(det > 0.0) && prm.status) atomicOr(prm.status, 1u);
 #pragma unroll
-                for (int k = 0; k < 16; ++k) sm.W[wave][lane][k] = (T)W[k];
-                sm.sf[wave][lane] = sf;
+                for (int k = 0; k < 16; ++k) sl.W[lane][k] = (T)W[k];
+                sl.sf[lane] = sf;
                 if (prm.xq && blk == 0) {
                     double x[3];
                     prism_map(E.X, qp[0], qp[1], qp[2], x);
@@ -107,15 +109,15 @@ struct K4 {
                     if (lane + 64 * m < TMV * 16 && row < N) {
                         double s = 0.0;
                         for (int qq = 0; qq < cnt; ++qq)
-                            s += sm.sf[wave][qq] * prm.B64[(size_t)(qc + qq) * 4 * NP + row];
+                            s += sl.sf[qq] * prm.B64[(size_t)(qc + qq) * 4 * NP + row];
                         bacc[m] += s;
                     }
                 }
             }
             for (int qq = 0; qq < cnt; ++qq) {
                 const int q = qc + qq;
-                const T w0 = sm.W[wave][qq][4 * kg + 0], w1 = sm.W[wave][qq][4 * kg + 1];
-                const T w2 = sm.W[wave][qq][4 * kg + 2], w3 = sm.W[wave][qq][4 * kg + 3];
+                const T w0 = sl.W[qq][4 * kg + 0], w1 = sl.W[qq][4 * kg + 1];
+                const T w2 = sl.W[qq][4 * kg + 2], w3 = sl.W[qq][4 * kg + 3];
                 const T *Bq = Bt + (size_t)q * 4 * NP;
                 T yf[TNV], af[TMV];
 #pragma unroll
@@ -162,16 +164,19 @@ struct K4 {
 
     // Tile counts of the last row/column block are compile-time constants,
     // so the inner loops carry no bounds tests and stay one basic block.
-    __device__ static void run(const FwdParams &prm, int64_t slot, int blk, int wave, Smem &sm) {
+    __device__ static void run_slice(const FwdParams &prm, int64_t slot, int blk, Slice &sl) {
         const int bi = blk / BN, bj = blk % BN;
         constexpr int TML = NT - (BM - 1) * TM, TNL = NT - (BN - 1) * TN;
         if (bi == BM - 1) {
-            if (bj == BN - 1) body<TML, TNL>(prm, slot, blk, bi, bj, wave, sm);
-            else body<TML, TN>(prm, slot, blk, bi, bj, wave, sm);
+            if (bj == BN - 1) body<TML, TNL>(prm, slot, blk, bi, bj, sl);
+            else body<TML, TN>(prm, slot, blk, bi, bj, sl);
         } else {
-            if (bj == BN - 1) body<TM, TNL>(prm, slot, blk, bi, bj, wave, sm);
-            else body<TM, TN>(prm, slot, blk, bi, bj, wave, sm);
+            if (bj == BN - 1) body<TM, TNL>(prm, slot, blk, bi, bj, sl);
+            else body<TM, TN>(prm, slot, blk, bi, bj, sl);
         }
+    }
+    __device__ static void run(const FwdParams &prm, int64_t slot, int blk, int wave, Smem &sm) {
+        run_slice(prm, slot, blk, sm.w[wave]);
     }
 };
 
@@ -188,14 +193,16 @@ struct K32 {
     static constexpr int N = c_nshp(P), NP = c_pad16(N), NT = NP / 16, NQ = c_nq(P);
     static constexpr int NQP = c_pad8(NQ);
     static constexpr int BM = c_cdiv(NT, TM), BN = c_cdiv(NT, TN), NBLK = BM * BN;
+    static constexpr int EPI = 1;
     static constexpr int NBR = c_cdiv(TM * 16, 64);
     typedef typename SplitT<FORM>::vec HV;
     typedef typename SplitT<FORM>::scal HS;
 
-    struct Smem {
-        float W[4][64][WROW<float>::value];   // padded rows: conflict-free per-lane writes
-        double sf[4][64];
+    struct Slice {                            // one wave's LDS
+        float W[64][WROW<float>::value];      // padded rows: conflict-free per-lane writes
+        double sf[64];
     };
+    struct Smem { Slice w[4]; };
 
     __device__ static float elem_scale(const FwdParams &prm, const ElemIn &E) {
         // largest row sum of |W_q| over the element's points, times max |B|:
@@ -243,7 +250,7 @@ struct K32 {
     }
 
     template <int TMV, int TNV>
-    __device__ static void body(const FwdParams &prm, int64_t slot, int blk, int bi, int bj, int wave, Smem &sm) {
+    __device__ static void body(const FwdParams &prm, int64_t slot, int blk, int bi, int bj, Slice &sl) {
         constexpr int NBRV = c_cdiv(TMV * 16, 64);
         const int lane = threadIdx.x & 63;
         const int i16 = lane & 15, kg = lane >> 4;
@@ -281,8 +288,8 @@ struct K32 {
                     for (int k = 0; k < 16; ++k) W[k] = 0.0;
                 }
 #pragma unroll
-                for (int k = 0; k < 16; ++k) sm.W[wave][lane][k] = (float)W[k] * ys;
-                sm.sf[wave][lane] = sf;
+                for (int k = 0; k < 16; ++k) sl.W[lane][k] = (float)W[k] * ys;
+                sl.sf[lane] = sf;
             }
             wave_sync();
             if (bj == 0) {
@@ -292,7 +299,7 @@ struct K32 {
                     if (lane + 64 * m < TMV * 16 && row < N) {
                         double s = 0.0;
                         for (int qq = 0; qq < cnt && qc + qq < NQ; ++qq)
-                            s += sm.sf[wave][qq] * prm.B64[(size_t)(qc + qq) * 4 * NP + row];
+                            s += sl.sf[qq] * prm.B64[(size_t)(qc + qq) * 4 * NP + row];
                         bacc[m] += s;
                     }
                 }
@@ -329,8 +336,8 @@ struct K32 {
                     ycn[tj][1] = *(const float4 *)(yp + 4);
                 }
                 const int qa = kb * 8 + 2 * kg;        // this lane's two points (chunk-local)
-                const float *Wa = sm.W[wave][qa];
-                const float *Wb = sm.W[wave][qa + 1];
+                const float *Wa = sl.W[qa];
+                const float *Wb = sl.W[qa + 1];
                 float wa[16], wb[16];
 #pragma unroll
                 for (int k = 0; k < 16; ++k) { wa[k] = Wa[k]; wb[k] = Wb[k]; }
@@ -385,18 +392,28 @@ struct K32 {
 
     // Tile counts of the last row/column block are compile-time constants,
     // so the inner loops carry no bounds tests and stay one basic block.
-    __device__ static void run(const FwdParams &prm, int64_t slot, int blk, int wave, Smem &sm) {
+    __device__ static void run_slice(const FwdParams &prm, int64_t slot, int blk, Slice &sl) {
         const int bi = blk / BN, bj = blk % BN;
         constexpr int TML = NT - (BM - 1) * TM, TNL = NT - (BN - 1) * TN;
         if (bi == BM - 1) {
-            if (bj == BN - 1) body<TML, TNL>(prm, slot, blk, bi, bj, wave, sm);
-            else body<TML, TN>(prm, slot, blk, bi, bj, wave, sm);
+            if (bj == BN - 1) body<TML, TNL>(prm, slot, blk, bi, bj, sl);
+            else body<TML, TN>(prm, slot, blk, bi, bj, sl);
         } else {
-            if (bj == BN - 1) body<TM, TNL>(prm, slot, blk, bi, bj, wave, sm);
-            else body<TM, TN>(prm, slot, blk, bi, bj, wave, sm);
+            if (bj == BN - 1) body<TM, TNL>(prm, slot, blk, bi, bj, sl);
+            else body<TM, TN>(prm, slot, blk, bi, bj, sl);
         }
     }
+    __device__ static void run(const FwdParams &prm, int64_t slot, int blk, int wave, Smem &sm) {
+        run_slice(prm, slot, blk, sm.w[wave]);
+    }
 };
+
+// Work items of a launch over ne element slots (a work item covers EPI slots
+// and one of NBLK tile blocks).
+template <class KER>
+__host__ __device__ inline int64_t items_for(int64_t ne) {
+    return (ne + KER::EPI - 1) / KER::EPI * KER::NBLK;
+}
 
 // Grid-stride-free direct launch: workgroup of 4 waves, one work item each.
 template <class KER, int MINW>
@@ -404,7 +421,7 @@ __global__ __launch_bounds__(256, MINW) void fwd_direct(FwdParams prm) {
     __shared__ typename KER::Smem sm;
     const int wave = wave_uniform(threadIdx.x >> 6);
     const int64_t item = (int64_t)blockIdx.x * 4 + wave;
-    if (item >= prm.ne * KER::NBLK) return;
+    if (item >= items_for<KER>(prm.ne)) return;
     KER::run(prm, item / KER::NBLK, (int)(item % KER::NBLK), wave, sm);
 }
 

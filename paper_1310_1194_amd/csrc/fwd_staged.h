@@ -48,6 +48,7 @@ template <int P, typename T, int TM, int TN, int SP>
 struct K4S {
     static constexpr int N = c_nshp(P), NP = c_pad16(N), NT = NP / 16, NQ = c_nq(P);
     static constexpr int BM = c_cdiv(NT, TM), BN = c_cdiv(NT, TN), NBLK = BM * BN;
+    static constexpr int EPI = 1;
     static constexpr int NBR = c_cdiv(TM * 16, 64);
     static constexpr int NSTAGE = c_cdiv(NQ, SP);
     static constexpr int STAGE_T = SP * 4 * NP;                  // T values per stage
@@ -200,6 +201,7 @@ struct K32S {
     static constexpr int N = c_nshp(P), NP = c_pad16(N), NT = NP / 16, NQ = c_nq(P);
     static constexpr int NQP = c_pad8(NQ), NKB = NQP / 8;
     static constexpr int BM = c_cdiv(NT, TM), BN = c_cdiv(NT, TN), NBLK = BM * BN;
+    static constexpr int EPI = 1;
     static constexpr int NBR = c_cdiv(TM * 16, 64);
     static constexpr int VA = NP * 32 * 2 / 16;        // 16-byte vectors of one split half
     static constexpr int VY = SY ? 8 * NP * 4 * 4 / 16 : 0;
@@ -398,7 +400,7 @@ __global__ __launch_bounds__(256, MINW) void fwd_staged(FwdParams prm) {
     __shared__ typename KER::Smem sm;
     const int wave = wave_uniform(threadIdx.x >> 6);
     const int64_t item = (int64_t)blockIdx.x * 4 + wave;
-    const bool active = item < prm.ne * KER::NBLK;
+    const bool active = item < items_for<KER>(prm.ne);
     const int64_t it = active ? item : 0;
     KER::run(prm, it / KER::NBLK, (int)(it % KER::NBLK), wave, active, sm);
 }

@@ -1,0 +1,157 @@
+// Forward kernels on the vector ALUs for low degree.  At p = 1, 2, 3 the
+// element matrix (n = 6, 18, 40) fills 16x16 MFMA tiles poorly (padded to 16,
+// 32, 48), while MI355X runs FP64 FMAs on the vector ALUs at the same rate as
+// on the matrix cores, so these kernels group the lanes of a wave per element
+// instead of per output tile.
+//
+// A work item is EPW = 64 / LPE consecutive element slots, LPE lanes each.
+//  * Geometry (steps a3-a5): the EPW * nq (element, point) pairs are spread
+//    over the 64 lanes; each lane computes W_q in FP64 and stores its 13
+//    nonzero entries (W_r0 = 0 for r >= 1) and the load weight w det J f in
+//    the wave's LDS slice.
+//  * Contraction (step a6): lane (el, j), j < n, owns column j of A_e:
+//      y_0 = W_00 B0j + W_01 B1j + W_02 B2j + W_03 B3j,
+//      y_r = W_r1 B1j + W_r2 B2j + W_r3 B3j                  (r = 1..3),
+//      A_ij += B_q[0][i] y_0 + ... + B_q[3][i] y_3           (i = 0..n-1).
+//    B_q[r][i] is the same for every lane of the wave, so it is read with
+//    scalar loads and enters the FMAs as a scalar operand; only the four
+//    B_q[s][j] of the lane's own column are vector loads.
+//  * Load vector (step a7): b_j += sf_q phi_j(q) in FP64.
+// The FP32 form rounds W_q to FP32 and accumulates A in FP32, as the 16x16x4
+// FP32 MFMA kernels do.
+#pragma once
+#include "device_common.h"
+#include "fwd_kernels.h"
+
+namespace feint {
+
+// A copy of a wave-uniform pointer that the compiler can see is uniform
+// (values passed to non-inlined functions are otherwise taken as divergent).
+template <typename T>
+__device__ inline const T *uniform_ptr(const T *p) {
+    const uint64_t v = (uint64_t)(uintptr_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return (const T *)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <int P, typename T, int LPE>
+struct KV {
+    static constexpr int N = c_nshp(P), NP = c_pad16(N), NQ = c_nq(P);
+    static constexpr int EPW = 64 / LPE;        // element slots per work item
+    static constexpr int EPI = EPW, NBLK = 1;
+    static constexpr int NPT = EPW * NQ;        // (element, point) pairs per item
+    static constexpr int WS = sizeof(T) == 8 ? 14 : 16;   // 13 entries, rows 16-byte aligned
+    static_assert(LPE >= N && LPE <= 64, "one lane per column of an element");
+    typedef const __attribute__((address_space(4))) T CT;   // read through the scalar cache
+
+    struct Slice {                    // one wave's LDS
+        T W[NPT][WS];
+        double sf[NPT];
+    };
+    struct Smem { Slice w[4]; };
+
+    __device__ static void run(const FwdParams &prm, int64_t group, int blk, int wave, Smem &sm) {
+        run_slice(prm, group, blk, sm.w[wave]);
+    }
+
+    __device__ static void run_slice(const FwdParams &prm, int64_t group, int blk, Slice &sl) {
+        (void)blk;
+        const int lane = threadIdx.x & 63;
+        const int64_t s0 = group * EPW;
+        const int64_t nslot = prm.ne;
+        const T *Bt = uniform_ptr(sizeof(T) == 8 ? (const T *)(const void *)prm.B64
+                                                 : (const T *)(const void *)prm.B32);
+        const double *B64 = uniform_ptr(prm.B64);
+        const double *qw = uniform_ptr(prm.qw);
+
+        // geometry: lane t handles pair (t / NQ, t % NQ), then t + 64, ...
+#pragma unroll 1
+        for (int t = lane; t < NPT; t += 64) {
+            const int el = t / NQ, q = t - el * NQ;
+            const int64_t slot = s0 + el;
+            if (slot < nslot) {
+                const int64_t e = elem_of(prm, slot);
+                ElemIn E;
+                load_elem(prm.coords, prm.D, prm.beta, prm.c, prm.f, e, E);
+                const double *qp = qw + 4 * q;
+                double W[16], sf;
+                const double det = point_block(E, qp[0], qp[1], qp[2], qp[3], W, sf);
+                if (!(det > 0.0) && prm.status) atomicOr(prm.status, 1u);
+                T *w = sl.W[t];
+                w[0] = (T)W[0]; w[1] = (T)W[1]; w[2] = (T)W[2]; w[3] = (T)W[3];
+#pragma unroll
+                for (int r = 1; r < 4; ++r)
+#pragma unroll
+                    for (int s = 1; s < 4; ++s) w[3 * r + s] = (T)W[4 * r + s];
+                sl.sf[t] = sf;
+                if (prm.xq) {
+                    double x[3];
+                    prism_map(E.X, qp[0], qp[1], qp[2], x);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) prm.xq[(e * NQ + q) * 3 + d] = x[d];
+                }
+            }
+        }
+        wave_sync();
+
+        const int el = lane / LPE, j = lane - el * LPE;
+        const int elc = el < EPW ? el : EPW - 1;
+        const int jc = j < N ? j : N - 1;
+        T acc[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc[i] = (T)0;
+        double bj = 0.0;
+        CT *Bs = (CT *)Bt;
+        const T *wrow = sl.W[elc * NQ];
+        const double *sfrow = &sl.sf[elc * NQ];
+        const T *Bcol = Bt + jc;
+        const double *Bcol64 = B64 + jc;
+        // the lane's own operands of point q + 1 are loaded while point q is
+        // contracted
+        T wv[13], cv[4];
+        double sfv, phiv;
+        auto fetch = [&](int q) {
+#pragma unroll
+            for (int k = 0; k < 13; ++k) wv[k] = wrow[q * WS + k];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) cv[s] = Bcol[(size_t)(4 * q + s) * NP];
+            sfv = sfrow[q];
+            phiv = sizeof(T) == 8 ? 0.0 : Bcol64[(size_t)4 * q * NP];
+        };
+        fetch(0);
+#pragma unroll 1
+        for (int q = 0; q < NQ; ++q) {
+            const T c0 = cv[0], c1 = cv[1], c2 = cv[2], c3 = cv[3];
+            T y0 = wv[0] * c0;
+            y0 = fma_t(wv[1], c1, y0); y0 = fma_t(wv[2], c2, y0); y0 = fma_t(wv[3], c3, y0);
+            T y1 = wv[4] * c1;
+            y1 = fma_t(wv[5], c2, y1); y1 = fma_t(wv[6], c3, y1);
+            T y2 = wv[7] * c1;
+            y2 = fma_t(wv[8], c2, y2); y2 = fma_t(wv[9], c3, y2);
+            T y3 = wv[10] * c1;
+            y3 = fma_t(wv[11], c2, y3); y3 = fma_t(wv[12], c3, y3);
+            bj = __builtin_fma(sfv, sizeof(T) == 8 ? (double)c0 : phiv, bj);
+            if (q + 1 < NQ) fetch(q + 1);
+            CT *Bsq = Bs + (size_t)q * 4 * NP;
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                T a = fma_t(Bsq[i], y0, acc[i]);
+                a = fma_t(Bsq[NP + i], y1, a);
+                a = fma_t(Bsq[2 * NP + i], y2, a);
+                acc[i] = fma_t(Bsq[3 * NP + i], y3, a);
+            }
+        }
+
+        const int64_t slot = s0 + el;
+        if (el < EPW && j < N && slot < nslot) {
+            const int64_t e = elem_of(prm, slot);
+            T *Aout = (T *)prm.A + offA_of(prm, e, N);
+#pragma unroll
+            for (int i = 0; i < N; ++i) Aout[(size_t)i * N + j] = acc[i];
+            ((T *)prm.b)[offb_of(prm, e, N) + j] = (T)bj;
+        }
+    }
+};
+
+}  // namespace feint

@@ -26,13 +26,15 @@ struct FwdParams {
 };
 
 // One compiled tile shape of a (degree, form): TM x TN 16x16 output tiles
-// per wave; `launch` enqueues the direct (one work item per wave) kernel.
+// per wave (MFMA kernels), or tn lanes per element (vector-ALU kernels,
+// tm = 0); `launch` enqueues the direct (one work item per wave) kernel.
 struct FwdVariant {
     int tm, tn;
-    int staged;          // 1: the table is staged through LDS per workgroup (2: A operands only)
+    int staged;          // 1: the table is staged through LDS per workgroup (2: A operands only),
+                         // 3: vector-ALU kernel
     int minw;            // waves per SIMD the register allocation allows
     void (*launch)(const FwdParams &, hipStream_t);
-    int64_t (*items_per_elem)();
+    int64_t (*items)(int64_t ne);   // work items (waves) of a launch over ne elements
 };
 
 // Registry per form (0 FP64, 1 FP32, 2 BF16X3, 3 FP16X3); p in 1..7.

@@ -17,11 +17,13 @@
 // sequence is safe to capture and replay.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 
 #include "capi_internal.h"
 #include "fwd_kernels.h"
+#include "fwd_valu.h"
 #include "tables.h"
 
 namespace feint {
@@ -41,7 +43,8 @@ struct MixedHdr {
 };
 
 struct MixSizes {
-    int32_t items[8];    // work items per element (tile blocks) of degree p
+    int32_t items[8];    // work items per group of element slots (tile blocks) of degree p
+    int32_t epi[8];      // element slots per group (1, or the elements of a vector-ALU wave)
     int32_t grab[8];     // work items taken per queue grab
 };
 
@@ -187,7 +190,7 @@ __global__ void k_prep(MixedHdr *hdr, MixSizes sz) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         int64_t g = 0;
         for (int d = MIX_MAXP; d >= 1; --d) {
-            const int64_t items = (int64_t)hdr->count[d] * sz.items[d];
+            const int64_t items = (hdr->count[d] + sz.epi[d] - 1) / sz.epi[d] * sz.items[d];
             hdr->ngrab[d] = (items + sz.grab[d] - 1) / sz.grab[d];
             hdr->gstart[d] = g;
             g += hdr->ngrab[d];
@@ -197,20 +200,32 @@ __global__ void k_prep(MixedHdr *hdr, MixSizes sz) {
     }
 }
 
+// Each wave owns one LDS slice large enough for any degree's kernel, so waves
+// of a workgroup working on different degrees never share LDS.
 template <class KER>
-__device__ __attribute__((noinline)) void run_item(const MixedParams &mp, int d, int64_t item, int wave, void *smem) {
+__device__ __attribute__((noinline)) void run_item(const MixedParams &mp, int d, int64_t item, void *slice) {
     FwdParams prm = mp.base;
     prm.qw = mp.qw[d];
     prm.B64 = mp.B64[d];
     prm.B32 = mp.B32[d];
     prm.perm = mp.perm + mp.hdr->bstart[d];
-    KER::run(prm, item / KER::NBLK, (int)(item % KER::NBLK), wave, *(typename KER::Smem *)smem);
+    prm.ne = mp.hdr->count[d];          // slots of this bucket
+    KER::run_slice(prm, item / KER::NBLK, (int)(item % KER::NBLK), *(typename KER::Slice *)slice);
 }
+
+template <class... K> struct MaxSlice;
+template <class K> struct MaxSlice<K> { static constexpr size_t value = (sizeof(typename K::Slice) + 15) / 16 * 16; };
+template <class K, class... R> struct MaxSlice<K, R...> {
+    static constexpr size_t value = MaxSlice<K>::value > MaxSlice<R...>::value ? MaxSlice<K>::value
+                                                                               : MaxSlice<R...>::value;
+};
 
 template <class K1, class K2, class K3, class K4_, class K5, class K6>
 __global__ __launch_bounds__(256, 2) void k_persist(MixedParams mp) {
-    __shared__ typename K6::Smem sm;
+    constexpr size_t SL = MaxSlice<K1, K2, K3, K4_, K5, K6>::value;
+    __shared__ __attribute__((aligned(16))) char sm[4 * SL];
     const int wave = wave_uniform(threadIdx.x >> 6);
+    void *slice = sm + wave * SL;
     const int lane = threadIdx.x & 63;
     MixedHdr *h = mp.hdr;
     const int64_t total = h->total_grabs;
@@ -221,17 +236,17 @@ __global__ __launch_bounds__(256, 2) void k_persist(MixedParams mp) {
         if ((int64_t)g >= total) break;
         int d = MIX_MAXP;
         while (d > 1 && (int64_t)g >= h->gstart[d] + h->ngrab[d]) --d;
-        const int64_t nitems = (int64_t)h->count[d] * mp.sz.items[d];
+        const int64_t nitems = (h->count[d] + mp.sz.epi[d] - 1) / mp.sz.epi[d] * mp.sz.items[d];
         const int64_t first = ((int64_t)g - h->gstart[d]) * mp.sz.grab[d];
         const int64_t last = first + mp.sz.grab[d] < nitems ? first + mp.sz.grab[d] : nitems;
         for (int64_t it = first; it < last; ++it) {
             switch (d) {
-            case 1: run_item<K1>(mp, 1, it, wave, &sm); break;
-            case 2: run_item<K2>(mp, 2, it, wave, &sm); break;
-            case 3: run_item<K3>(mp, 3, it, wave, &sm); break;
-            case 4: run_item<K4_>(mp, 4, it, wave, &sm); break;
-            case 5: run_item<K5>(mp, 5, it, wave, &sm); break;
-            default: run_item<K6>(mp, 6, it, wave, &sm); break;
+            case 1: run_item<K1>(mp, 1, it, slice); break;
+            case 2: run_item<K2>(mp, 2, it, slice); break;
+            case 3: run_item<K3>(mp, 3, it, slice); break;
+            case 4: run_item<K4_>(mp, 4, it, slice); break;
+            case 5: run_item<K5>(mp, 5, it, slice); break;
+            default: run_item<K6>(mp, 6, it, slice); break;
             }
         }
     }
@@ -250,32 +265,40 @@ MixVariant make_variant(const char *desc) {
     v.kernel = (const void *)&k_persist<K1, K2, K3, K4_, K5, K6>;
     std::memset(&v.sz, 0, sizeof v.sz);
     const int items[7] = {0, K1::NBLK, K2::NBLK, K3::NBLK, K4_::NBLK, K5::NBLK, K6::NBLK};
-    const int grab[7] = {0, 32, 8, 2, 1, 1, 1};
+    const int epi[7] = {0, K1::EPI, K2::EPI, K3::EPI, K4_::EPI, K5::EPI, K6::EPI};
+    const int grab[7] = {0, 32, 8, 2, 1, 1, 1};   // elements' worth of work per grab
     for (int d = 1; d <= MIX_MAXP; ++d) {
         v.sz.items[d] = items[d];
-        v.sz.grab[d] = grab[d];
+        v.sz.epi[d] = epi[d];
+        v.sz.grab[d] = grab[d] / epi[d] > 1 ? grab[d] / epi[d] : 1;
     }
     v.desc = desc;
     return v;
 }
 
 const MixVariant *mix_variants(int form, int *count) {
+    // p = 1, 2 on the vector ALUs (v8: 8 lanes per element, v18: 18), MFMA tiles above;
+    // the last set of each form keeps MFMA tiles at every degree for comparison
     static const MixVariant f32[] = {
+        make_variant<KV<1, float, 8>, KV<2, float, 18>, K4<3, float, 3, 3>, K4<4, float, 5, 3>,
+                     K4<5, float, 8, 2>, K4<6, float, 13, 1>>("v8,v18,3x3,5x3,8x2,13x1"),
+        make_variant<KV<1, float, 8>, KV<2, float, 18>, K4<3, float, 3, 1>, K4<4, float, 5, 2>,
+                     K4<5, float, 8, 1>, K4<6, float, 13, 1>>("v8,v18,3x1,5x2,8x1,13x1"),
+        make_variant<KV<1, float, 8>, KV<2, float, 18>, K4<3, float, 3, 3>, K4<4, float, 5, 5>,
+                     K4<5, float, 8, 4>, K4<6, float, 13, 2>>("v8,v18,3x3,5x5,8x4,13x2"),
         make_variant<K4<1, float, 1, 1>, K4<2, float, 2, 2>, K4<3, float, 3, 3>, K4<4, float, 5, 3>,
                      K4<5, float, 8, 2>, K4<6, float, 13, 1>>("1x1,2x2,3x3,5x3,8x2,13x1"),
-        make_variant<K4<1, float, 1, 1>, K4<2, float, 2, 1>, K4<3, float, 3, 1>, K4<4, float, 5, 2>,
-                     K4<5, float, 8, 1>, K4<6, float, 13, 1>>("1x1,2x1,3x1,5x2,8x1,13x1"),
-        make_variant<K4<1, float, 1, 1>, K4<2, float, 2, 2>, K4<3, float, 3, 3>, K4<4, float, 5, 5>,
-                     K4<5, float, 8, 4>, K4<6, float, 13, 2>>("1x1,2x2,3x3,5x5,8x4,13x2"),
     };
     static const MixVariant f64[] = {
+        make_variant<KV<1, double, 8>, KV<2, double, 18>, K4<3, double, 3, 3>, K4<4, double, 5, 1>,
+                     K4<5, double, 8, 1>, K4<6, double, 13, 1>>("v8,v18,3x3,5x1,8x1,13x1"),
+        make_variant<KV<1, double, 8>, KV<2, double, 18>, K4<3, double, 3, 1>, K4<4, double, 5, 2>,
+                     K4<5, double, 8, 2>, K4<6, double, 13, 1>>("v8,v18,3x1,5x2,8x2,13x1"),
         make_variant<K4<1, double, 1, 1>, K4<2, double, 2, 2>, K4<3, double, 3, 3>, K4<4, double, 5, 1>,
                      K4<5, double, 8, 1>, K4<6, double, 13, 1>>("1x1,2x2,3x3,5x1,8x1,13x1"),
-        make_variant<K4<1, double, 1, 1>, K4<2, double, 2, 1>, K4<3, double, 3, 1>, K4<4, double, 5, 2>,
-                     K4<5, double, 8, 2>, K4<6, double, 13, 1>>("1x1,2x1,3x1,5x2,8x2,13x1"),
     };
-    if (form == FEINT_FP32) { *count = 3; return f32; }
-    if (form == FEINT_FP64) { *count = 2; return f64; }
+    if (form == FEINT_FP32) { *count = (int)(sizeof f32 / sizeof f32[0]); return f32; }
+    if (form == FEINT_FP64) { *count = (int)(sizeof f64 / sizeof f64[0]); return f64; }
     *count = 0;
     return nullptr;
 }
@@ -504,6 +527,14 @@ int feint_mixed_tile_count(const feint_mixed_plan *pl) {
 }
 
 int feint_mixed_tile_get(const feint_mixed_plan *pl) { return pl ? pl->tile : -1; }
+
+feint_status feint_mixed_tile_describe(const feint_mixed_plan *pl, int tile, char *buf, size_t len) {
+    if (!pl || !buf || len == 0 || tile < 0 || tile >= feint_mixed_tile_count(pl)) return FEINT_ERR_INVALID_ARG;
+    int cnt = 0;
+    const MixVariant *v = mix_variants(pl->form, &cnt);
+    std::snprintf(buf, len, "%s", v[tile].desc);
+    return FEINT_OK;
+}
 
 feint_status feint_mixed_tile_set(feint_mixed_plan *pl, int tile) {
     if (!pl || tile < 0 || tile >= feint_mixed_tile_count(pl)) return FEINT_ERR_INVALID_ARG;

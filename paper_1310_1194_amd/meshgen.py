@@ -149,6 +149,23 @@ def adjoint_seeds(batch: Batch, p: int, dtype=np.float64):
     return G, g, sample
 
 
+def adjoint_seeds_device(batch: Batch, p: int, seed: int, dtype=None, device="cuda"):
+    """Step 7 for batches whose G does not fit comfortably in host memory
+    (16384 elements at p = 7: 10.9 GB in FP64): G ~ N(0,1) [ne,n,n] and
+    g ~ N(0,1) [ne,n] drawn on the device from torch's generator seeded with
+    `seed` (G first, then g), and 64 sampled ids from numpy's generator."""
+    import torch
+    dtype = dtype or torch.float64
+    n = nshp(p)
+    ne = batch.ne
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    G = torch.randn((ne, n, n), generator=gen, dtype=dtype, device=device)
+    g = torch.randn((ne, n), generator=gen, dtype=dtype, device=device)
+    sample = np.sort(np.random.default_rng(seed).choice(ne, min(64, ne), replace=False))
+    return G, g, sample
+
+
 # The workloads of the paper-derived configurations (mesh sizes and amplitudes).
 WORKLOADS = {
     "p1_4096":      dict(nx=16, ny=16, nz=8,  amp=0.2, seed=0, p=1),
@@ -156,6 +173,8 @@ WORKLOADS = {
     "mixed_262144": dict(nx=64, ny=64, nz=32, amp=0.2, seed=2, p=None),
     "adj_p3_131072": dict(nx=64, ny=64, nz=16, amp=0.2, seed=3, p=3),
     "p7_16384":     dict(nx=32, ny=32, nz=8,  amp=0.3, seed=4, p=7),
+    # the p = 1 distributions at a size where HBM rather than launch latency bounds
+    "p1_524288":    dict(nx=64, ny=64, nz=64, amp=0.2, seed=0, p=1),
 }
 
 

@@ -21,7 +21,7 @@ EXPORTS = (
     "feint_integrate_adjoint", "feint_mixed_plan_create", "feint_mixed_bucket",
     "feint_integrate_mixed", "feint_mixed_graph_capture", "feint_mixed_graph_launch",
     "feint_mixed_plan_destroy", "feint_mixed_autotune", "feint_mixed_tile_count", "feint_mixed_tile_get",
-    "feint_mixed_tile_set", "feint_tile_count", "feint_tile_get", "feint_tile_set",
+    "feint_mixed_tile_set", "feint_mixed_tile_describe", "feint_tile_count", "feint_tile_get", "feint_tile_set",
     "feint_tile_describe", "feint_autotune", "feint_status_string", "feint_last_error",
     "feint_shutdown",
 )
@@ -73,6 +73,7 @@ def lib() -> ctypes.CDLL:
             "feint_mixed_tile_count": (_i, [_vp]),
             "feint_mixed_tile_get": (_i, [_vp]),
             "feint_mixed_tile_set": (_i, [_vp, _i]),
+            "feint_mixed_tile_describe": (_i, [_vp, _i, ctypes.c_char_p, ctypes.c_size_t]),
             "feint_tile_count": (_i, [_i, _i]),
             "feint_tile_get": (_i, [_i, _i]),
             "feint_tile_set": (_i, [_i, _i, _i]),

@@ -119,3 +119,30 @@ def test_adjoint_full_size_sampled(torch_cuda, form):
     err = np.linalg.norm(fd - got, axis=1) / np.linalg.norm(got, axis=1)
     flush(f"    central differences: max per-element rel err {err.max():.3e}")
     assert err.max() < 1e-6
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+def test_adjoint_p7_full_size_sampled(torch_cuda, form):
+    """The p=7 workload (32x32x8 mesh at +-0.3h, 16384 elements) with the same
+    loss: G, g drawn on the device; the 64 sampled elements against the oracle."""
+    import oracle
+    import paper_1310_1194_amd as F
+    from paper_1310_1194_amd import meshgen
+    torch = torch_cuda
+    p = 7
+    batch = meshgen.workload("p7_16384")
+    dt = torch.float64 if form == "fp64" else torch.float32
+    G, g, sample = meshgen.adjoint_seeds_device(batch, p, seed=4, dtype=dt)
+    flush(f"[adjoint-p7] form={form} ne={batch.ne}")
+    grads = F.adjoint_raw(*to_dev(batch), G, g, p, form)
+    torch.cuda.synchronize()
+    si = torch.from_numpy(sample).cuda()
+    Gs = G[si].double().cpu().numpy()
+    gs = g[si].double().cpu().numpy()
+    del G, g
+    sub = batch.subset(sample)
+    ref = oracle.adjoint(p, sub.coords, sub.D, sub.beta, sub.c, sub.f, Gs, gs)
+    for name, a, r in zip(NAMES, grads, ref[:5]):
+        e = rel(a[si].cpu().numpy(), r)
+        flush(f"    {name} vs oracle: {e:.3e}")
+        assert e <= TOL[form]

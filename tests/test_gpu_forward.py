@@ -57,29 +57,34 @@ def test_forward_parity_every_tile(torch_cuda, p, form):
         assert gb <= BTOL[form] and mb <= BTOL[form] * 4
 
 
-def test_mapped_points_and_status(torch_cuda):
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_mapped_points_and_status(torch_cuda, p):
+    """Mapped points and the det J <= 0 flag, from every compiled variant."""
     import oracle
     import paper_1310_1194_amd as F
     torch = torch_cuda
-    p = 3
     batch = small_batch(p, seed=11)
     batch.coords[1] = batch.coords[1][[3, 4, 5, 0, 1, 2]]     # element 1 inverted: det J < 0
     Ar, br, flags, xr = oracle.integrate(p, batch.coords, batch.D, batch.beta, batch.c, batch.f, want_xq=True)
     assert flags[1] == 1 and flags.sum() == 1
     args = to_dev(batch)
-    xq = torch.empty((batch.ne, F.nq(p), 3), dtype=torch.float64, device="cuda")
-    st = torch.zeros(1, dtype=torch.int32, device="cuda")
-    A, b = F.integrate_raw(*args, p, "fp64", xq=xq, status=st)
-    torch.cuda.synchronize()
-    assert int(st.item()) & 1 == 1
-    assert np.abs(xq.cpu().numpy() - xr).max() < 1e-15
-    # signed det J: the inverted element still matches the oracle
-    g, m = rel_errors(A.cpu().numpy(), Ar)
-    assert g < 1e-12 and m < 1e-12
-    st.zero_()
-    F.integrate_raw(*to_dev(small_batch(p, seed=12)), p, "fp64", status=st)
-    torch.cuda.synchronize()
-    assert int(st.item()) == 0
+    for tile in range(F.tile_count(p, "fp64")):
+        flush(f"[xq/status] p={p} tile={F.tile_describe(p, 'fp64', tile)}")
+        F.tile_set(p, "fp64", tile)
+        xq = torch.full((batch.ne, F.nq(p), 3), float("nan"), dtype=torch.float64, device="cuda")
+        st = torch.zeros(1, dtype=torch.int32, device="cuda")
+        A, b = F.integrate_raw(*args, p, "fp64", xq=xq, status=st)
+        torch.cuda.synchronize()
+        assert int(st.item()) & 1 == 1
+        assert np.abs(xq.cpu().numpy() - xr).max() < 1e-15
+        # signed det J: the inverted element still matches the oracle
+        g, m = rel_errors(A.cpu().numpy(), Ar)
+        assert g < 1e-12 and m < 1e-12
+        st.zero_()
+        F.integrate_raw(*to_dev(small_batch(p, seed=12)), p, "fp64", status=st)
+        torch.cuda.synchronize()
+        assert int(st.item()) == 0
+    F.tile_set(p, "fp64", 0)
 
 
 def test_deterministic(torch_cuda):

@@ -75,7 +75,7 @@ def test_mixed_every_tile_set(torch_cuda, form):
         plan.tile = t
         A.fill_(float("nan"))
         b.fill_(float("nan"))
-        flush(f"[mixed] form={form} tile set {t} ne={batch.ne}")
+        flush(f"[mixed] form={form} tile set {t} ({plan.tile_describe(t)}) ne={batch.ne}")
         plan.integrate(*X, A, b, offA, offb)
         torch.cuda.synchronize()
         assert bool(torch.isfinite(A).all()) and bool(torch.isfinite(b).all())
