@@ -296,6 +296,8 @@ def bench_adjoint(args):
         dt = torch.float64 if form == "fp64" else torch.float32
         Gd, gd = (t(G).to(dt), t(g).to(dt)) if G is not None else (Gdev.to(dt), gdev.to(dt))
         out = None
+        tune_ms = None if args.no_tune else F.adjoint_autotune(*X, Gd, gd, p, form, reps=2)
+        block = F.adjoint_tile_describe(p, form, F.adjoint_tile_get(p, form))
 
         def step():
             nonlocal out
@@ -303,11 +305,12 @@ def bench_adjoint(args):
         ms, mn, wall = timed(step, args.steps, args.warmup)
         es = 8 if form == "fp64" else 4
         res[form] = dict(kernel_ms_mean=ms, kernel_ms_min=mn, ms_per_step=wall, elements_per_s=ne / (wall * 1e-3),
+                         block=block, tune_ms=tune_ms,
                          gflops=costmodel.f_dom(p) * ne / (ms * 1e-3) / 1e9,
                          hbm_gbs_algorithmic=ne * costmodel.adjoint_bytes_per_element(p, es) / (ms * 1e-3) / 1e9,
                          grads=[o[torch.from_numpy(sample).to(dev)].cpu().numpy() for o in out])
         del Gd, gd
-        print(f"[bench] adjoint {form}: {ms:.3f} ms", file=sys.stderr, flush=True)
+        print(f"[bench] adjoint {form}: {ms:.3f} ms, block {block}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu:
         import oracle

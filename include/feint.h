@@ -118,6 +118,23 @@ feint_status feint_integrate_adjoint(const feint_elements *el, int p, feint_form
                                      double *dcoords, double *dD, double *dbeta,
                                      double *dc, double *df, void *stream);
 
+/* Block shapes of the adjoint kernel: each wave holds a TA x TB block of
+   16x16 tiles of G_e (several waves per element for large n, their partial
+   gradients summed with FP64 atomics).  feint_adjoint_autotune times every
+   compiled shape on the caller's buffers (`reps` repetitions, HIP events on
+   `stream`, synchronising on it), keeps the fastest for later calls of this
+   (p, form) and returns its time in *best_ms (nullable); ne = 0 or reps < 1
+   gives INVALID_ARG.  tile_get/set read or force the choice; tile_describe
+   writes "TAxTB".  Count is 0 and get is -1 for unsupported (p, form). */
+int feint_adjoint_tile_count(int p, feint_form form);
+int feint_adjoint_tile_get(int p, feint_form form);
+feint_status feint_adjoint_tile_set(int p, feint_form form, int tile);
+feint_status feint_adjoint_tile_describe(int p, feint_form form, int tile, char *buf, size_t len);
+feint_status feint_adjoint_autotune(const feint_elements *el, int p, feint_form form,
+                                    const void *G, const void *g, double *dcoords, double *dD,
+                                    double *dbeta, double *dc, double *df, int reps, double *best_ms,
+                                    void *stream);
+
 /* ---- Mixed-degree batches -------------------------------------------------
    Elements of degrees 1..6 in any order run as one persistent,
    degree-bucketed launch (the paper's Sec. 2.2 advice to group elements by

@@ -153,6 +153,42 @@ def autotune(coords, D, beta, c, f, p: int, form: str, A, b, reps: int = 3) -> f
     return best.value
 
 
+def adjoint_tile_count(p: int, form: str) -> int:
+    return lib().feint_adjoint_tile_count(int(p), FORMS[form])
+
+
+def adjoint_tile_get(p: int, form: str) -> int:
+    return lib().feint_adjoint_tile_get(int(p), FORMS[form])
+
+
+def adjoint_tile_set(p: int, form: str, tile: int) -> None:
+    check("feint_adjoint_tile_set", lib().feint_adjoint_tile_set(int(p), FORMS[form], int(tile)))
+
+
+def adjoint_tile_describe(p: int, form: str, tile: int) -> str:
+    buf = ctypes.create_string_buffer(32)
+    check("feint_adjoint_tile_describe",
+          lib().feint_adjoint_tile_describe(int(p), FORMS[form], int(tile), buf, 32))
+    return buf.value.decode()
+
+
+def adjoint_autotune(coords, D, beta, c, f, G, g, p: int, form: str = "fp64", reps: int = 2) -> float:
+    """Time every compiled adjoint block shape on these inputs, keep the fastest; returns its ms."""
+    el = elements(coords, D, beta, c, f)
+    ne, n = coords.shape[0], nshp(p)
+    dt = out_dtype(form)
+    G = G.contiguous().to(dt)
+    g = g.contiguous().to(dt)
+    if G.numel() != ne * n * n or g.numel() != ne * n:
+        raise ValueError("G, g have the wrong size")
+    outs = [torch.empty_like(t) for t in (coords, D, beta, c, f)]
+    best = ctypes.c_double(0)
+    check("feint_adjoint_autotune",
+          lib().feint_adjoint_autotune(ctypes.byref(el), int(p), FORMS[form], _ptr(G), _ptr(g),
+                                       *[_ptr(o) for o in outs], int(reps), ctypes.byref(best), _stream()))
+    return best.value
+
+
 class MixedPlan:
     """Mixed-degree batches (degrees 1..6) through one persistent,
     degree-bucketed launch; optionally captured once into a HIP graph."""

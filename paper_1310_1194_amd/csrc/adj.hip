@@ -3,10 +3,14 @@
 // with respect to every element's vertices, D, beta, c and f.
 //
 // Since A_e = sum_q B_q^T W_q B_q, <G_e, A_e> = sum_q <W_q, S_q> with the 4x4
-// block S_q = B_q G_e B_q^T.  The kernel forms U = B G_e on MFMA (rows: the
-// 4 nq (point, row) pairs, K = shape functions), reduces S_q = U_q B_q^T
-// across lanes into LDS, and then, one point per lane, recomputes the
-// Jacobian in FP64 and pushes dL/dW_q = S_q through
+// block S_q = B_q G_e B_q^T.  Per group of four points the kernel forms, on
+// MFMA, the 16 rows (point, row) of U^T = G_e^T B^T (K = shape functions a)
+// and then T = U B^T over the same four points (K = shape functions b): the
+// accumulator registers of a U^T tile are, lane for lane, the A operand of
+// the second product, so U never leaves registers.  The diagonal 4x4 blocks
+// of T are the S_q of the four points (a quarter of T is used; the second
+// product costs 4 MFMAs per 16x16 tile of U^T).  Then, one point per lane,
+// the Jacobian is recomputed in FP64 and dL/dW_q = S_q is pushed through
 //   W_q = w det J [[c, (K beta)^T], [0, K D K^T]],  K = J^{-1}:
 //   dL/dc = sum wd S00,  dL/dbeta = sum wd K^T s,  dL/dD = sum wd K^T S' K,
 //   dL/dK = wd (S' K D^T + S'^T K D + s beta^T),  dL/d det = L_q / det,
@@ -16,7 +20,9 @@
 // handled by different waves whose partial gradients are summed atomically.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "capi_internal.h"
 #include "device_common.h"
@@ -31,7 +37,6 @@ struct AdjParams {
     const void *G, *g;
     double *dX, *dD, *dbeta, *dc, *df;
     const double *qw, *B64;
-    const void *Brow;   // [nqp][4][npad] in the form's precision
     const void *BT;     // [npad][nqp*4]  in the form's precision
 };
 
@@ -143,18 +148,50 @@ struct Adj {
         }
     }
 
+    // Sum the lanes' 32 partial gradients over the wave by recursive halving:
+    // at each step a lane keeps half of its values and adds the partner's copy
+    // of that half.  Lanes 2c and 2c+1 end with component c.
+    __device__ static double reduce_scatter32(double v[32], int lane) {
+        double w16[16], w8[8], w4[4], w2[2];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const bool up = lane & 32;
+            const double keep = up ? v[j + 16] : v[j], send = up ? v[j] : v[j + 16];
+            w16[j] = keep + __shfl_xor(send, 32, 64);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const bool up = lane & 16;
+            const double keep = up ? w16[j + 8] : w16[j], send = up ? w16[j] : w16[j + 8];
+            w8[j] = keep + __shfl_xor(send, 16, 64);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool up = lane & 8;
+            const double keep = up ? w8[j + 4] : w8[j], send = up ? w8[j] : w8[j + 4];
+            w4[j] = keep + __shfl_xor(send, 8, 64);
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const bool up = lane & 4;
+            const double keep = up ? w4[j + 2] : w4[j], send = up ? w4[j] : w4[j + 2];
+            w2[j] = keep + __shfl_xor(send, 4, 64);
+        }
+        const bool up = lane & 2;
+        double r = (up ? w2[1] : w2[0]) + __shfl_xor(up ? w2[0] : w2[1], 2, 64);
+        return r + __shfl_xor(r, 1, 64);
+    }
+
     __device__ static void run(const AdjParams &prm, int64_t e, int blk, int wave, Smem &sm) {
         const int lane = threadIdx.x & 63;
         const int i16 = lane & 15, kg = lane >> 4;
         const int ba = blk / BB, bb = blk % BB;
         const int a0 = ba * TA * 16, b0 = bb * TB * 16;
         const bool with_load = blk == 0;
-        ElemIn E;
-        load_elem(prm.coords, prm.D, prm.beta, prm.c, prm.f, e, E);
         const T *Ge = (const T *)prm.G + e * (int64_t)N * N;
-        const T *Br = (const T *)prm.Brow;
         const T *BTt = (const T *)prm.BT;
-        // this wave's block of G as B-operand fragments: G[a0 + 4ks + kg][b0 + 16 tb + i16]
+        // A-operand fragments of G^T over this wave's block:
+        // lane (i16, kg) holds G[a0 + 4 ks + kg][b0 + 16 tb + i16]
         T gf[4 * TA][TB];
 #pragma unroll
         for (int ks = 0; ks < 4 * TA; ++ks)
@@ -163,87 +200,93 @@ struct Adj {
                 const int a = a0 + 4 * ks + kg, b = b0 + 16 * tb + i16;
                 gf[ks][tb] = (a < N && b < N) ? Ge[(size_t)a * N + b] : (T)0;
             }
-        double gr[32];
-#pragma unroll
-        for (int k = 0; k < 32; ++k) gr[k] = 0.0;
+        const int nks = wave_uniform(N - a0 >= 16 * TA ? 4 * TA : (N - a0 + 3) / 4);   // k-steps with a < N
+        const T *afp = BTt + (size_t)(a0 + kg) * NQP * 4 + i16;      // + 4 ks NQP*4 + 4 q0
+        double gacc = 0.0;          // lanes 2c, 2c+1: component c of this wave's gradient
 
+        // table operands of one group of four points: B^T rows a (MFMA 1) and b (MFMA 2)
+        T af[4 * TA], bt[TB][4];
+        auto fetch = [&](int q0, T (&fa)[4 * TA], T (&fb)[TB][4]) {
+#pragma unroll
+            for (int ks = 0; ks < 4 * TA; ++ks)
+                fa[ks] = ks < nks ? afp[(size_t)4 * ks * NQP * 4 + 4 * q0] : (T)0;
+#pragma unroll
+            for (int tb = 0; tb < TB; ++tb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int b = b0 + 16 * tb + acc_row<T>(lane, r);
+                    fb[tb][r] = b0 + 16 * tb < N ? BTt[(size_t)b * NQP * 4 + 4 * q0 + i16] : (T)0;
+                }
+        };
+        fetch(0, af, bt);
         for (int qc = 0; qc < NQ4; qc += 64) {
             const int cnt = NQ4 - qc < 64 ? NQ4 - qc : 64;     // multiple of 4
             for (int t4 = 0; t4 < cnt; t4 += 4) {
-                const int q0 = qc + t4;
-                double Sp[16];
-#pragma unroll
-                for (int k = 0; k < 16; ++k) Sp[k] = 0.0;
+                // operands of the next group are loaded while this one runs
+                T afn[4 * TA], btn[TB][4];
+                const int qn = qc + t4 + 4;
+                if (qn < NQ4) fetch(qn, afn, btn);
+                V4 tacc = V4{0, 0, 0, 0};
 #pragma unroll
                 for (int tb = 0; tb < TB; ++tb) {
-                    const int b = b0 + 16 * tb + i16;
-                    if (b0 + 16 * tb >= NP) continue;
-                    V4 acc = V4{0, 0, 0, 0};
+                    if (b0 + 16 * tb >= N) continue;
+                    V4 u = V4{0, 0, 0, 0};                 // U^T tile: rows b, columns (point, row)
 #pragma unroll
-                    for (int ks = 0; ks < 4 * TA; ++ks) {
-                        const int a = a0 + 4 * ks + kg;
-                        if (a0 + 4 * ks < NP) {
-                            const T af = BTt[(size_t)a * NQP * 4 + 4 * q0 + i16];
-                            acc = mfma4(af, gf[ks][tb], acc);
-                        }
-                    }
+                    for (int ks = 0; ks < 4 * TA; ++ks)
+                        if (ks < nks) u = mfma4(gf[ks][tb], af[ks], u);
+                    // T += U B^T: k-step r covers the rows b held in register r
 #pragma unroll
-                    for (int rr = 0; rr < 4; ++rr) {
-                        const int row = acc_row<T>(lane, rr);   // (point q0 + row/4, r = row%4)
-                        const int q = q0 + (row >> 2);
-                        const T *bq = Br + (size_t)q * 4 * NP + b;
-                        const double u = (double)acc[rr];
-#pragma unroll
-                        for (int s = 0; s < 4; ++s) Sp[4 * rr + s] += u * (double)bq[s * NP];
-                    }
+                    for (int r = 0; r < 4; ++r) tacc = mfma4((T)u[r], bt[tb][r], tacc);
                 }
-                // reduce over the 16 columns held by lanes with the same kg
+                // diagonal blocks of T: row (point, r), column (point', s) with point = point'
+                if (sizeof(T) == 8) {
+                    // lane holds rows 4 rr + kg: point rr, r = kg; column i16: point i16/4, s = i16%4
+                    const int pt = i16 >> 2;
+                    const double v = pt == 0 ? tacc[0] : pt == 1 ? tacc[1] : pt == 2 ? tacc[2] : tacc[3];
+                    sm.S[wave][t4 + pt][4 * kg + (i16 & 3)] = v;
+                } else if (kg == (i16 >> 2)) {
+                    // lane holds rows 4 kg + rr: point kg, r = rr
 #pragma unroll
-                for (int k = 0; k < 16; ++k) {
-                    double v = Sp[k];
-                    v += __shfl_xor(v, 1, 64);
-                    v += __shfl_xor(v, 2, 64);
-                    v += __shfl_xor(v, 4, 64);
-                    v += __shfl_xor(v, 8, 64);
-                    Sp[k] = v;
+                    for (int rr = 0; rr < 4; ++rr) sm.S[wave][t4 + kg][4 * rr + (i16 & 3)] = (double)tacc[rr];
                 }
-                if (i16 == 0) {
+                if (qn < NQ4) {
 #pragma unroll
-                    for (int rr = 0; rr < 4; ++rr) {
-                        const int row = acc_row<T>(lane, rr);
-                        const int ql = t4 + (row >> 2), r = row & 3;
+                    for (int ks = 0; ks < 4 * TA; ++ks) af[ks] = afn[ks];
 #pragma unroll
-                        for (int s = 0; s < 4; ++s) sm.S[wave][ql][4 * r + s] = Sp[4 * rr + s];
-                    }
+                    for (int tb = 0; tb < TB; ++tb)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) bt[tb][r] = btn[tb][r];
                 }
             }
             wave_sync();
-            const int q = qc + lane;
-            if (lane < cnt && q < NQ) {
-                double S[16];
+            {
+                // chain rule, one point per lane (element inputs re-read: they are
+                // not kept in registers across the MFMA loop)
+                ElemIn E;
+                load_elem(prm.coords, prm.D, prm.beta, prm.c, prm.f, e, E);
+                double gr[32];
 #pragma unroll
-                for (int k = 0; k < 16; ++k) S[k] = sm.S[wave][lane][k];
-                chain_rule(prm, E, q, S, with_load, e, gr);
+                for (int k = 0; k < 32; ++k) gr[k] = 0.0;
+                const int q = qc + lane;
+                if (lane < cnt && q < NQ) {
+                    double S[16];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) S[k] = sm.S[wave][lane][k];
+                    chain_rule(prm, E, q, S, with_load, e, gr);
+                }
+                gacc += reduce_scatter32(gr, lane);
             }
             wave_sync();
         }
-        // reduce the 32 partial gradients over the wave
-#pragma unroll
-        for (int k = 0; k < 32; ++k) {
-            double v = gr[k];
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-            gr[k] = v;
-        }
-        if (lane == 0) {
-            double *outs[5] = {prm.dX + 18 * e, prm.dD + 9 * e, prm.dbeta + 3 * e, prm.dc + e, prm.df + e};
-            const int base[5] = {0, 18, 27, 30, 31}, len[5] = {18, 9, 3, 1, 1};
-#pragma unroll
-            for (int o = 0; o < 5; ++o)
-                for (int k = 0; k < len[o]; ++k) {
-                    if (ATOMIC) atomicAdd(outs[o] + k, gr[base[o] + k]);
-                    else outs[o][k] = gr[base[o] + k];
-                }
+        if ((lane & 1) == 0) {
+            // component c: vertices 0..17, D 18..26, beta 27..29, c 30, f 31
+            const int c = lane >> 1;
+            double *dst = c < 18 ? prm.dX + 18 * e + c
+                        : c < 27 ? prm.dD + 9 * e + (c - 18)
+                        : c < 30 ? prm.dbeta + 3 * e + (c - 27)
+                        : c == 30 ? prm.dc + e : prm.df + e;
+            if (ATOMIC) atomicAdd(dst, gacc);
+            else *dst = gacc;
         }
     }
 };
@@ -280,18 +323,91 @@ feint_status launch_adj(const AdjParams &prm, hipStream_t s) {
     return FEINT_OK;
 }
 
+// Compiled block shapes (TA x TB 16x16 tiles of G per wave) per degree; the
+// first is the default until feint_adjoint_autotune picks another.
+struct AdjVariant {
+    int ta, tb;
+    feint_status (*launch)(const AdjParams &, hipStream_t);
+};
+#define FEINT_ADJ(P, T, TA, TB) AdjVariant{TA, TB, &launch_adj<Adj<P, T, TA, TB>>}
+
 template <typename T>
-feint_status dispatch_adj(int p, const AdjParams &prm, hipStream_t s) {
+const AdjVariant *adj_variants_of(int p, int *count) {
+    static const AdjVariant v1[] = {FEINT_ADJ(1, T, 1, 1)};
+    static const AdjVariant v2[] = {FEINT_ADJ(2, T, 2, 2), FEINT_ADJ(2, T, 2, 1)};
+    static const AdjVariant v3[] = {FEINT_ADJ(3, T, 3, 3), FEINT_ADJ(3, T, 3, 1), FEINT_ADJ(3, T, 3, 2)};
+    static const AdjVariant v4[] = {FEINT_ADJ(4, T, 5, 2), FEINT_ADJ(4, T, 5, 1), FEINT_ADJ(4, T, 3, 3)};
+    static const AdjVariant v5[] = {FEINT_ADJ(5, T, 8, 1), FEINT_ADJ(5, T, 4, 2), FEINT_ADJ(5, T, 8, 2)};
+    static const AdjVariant v6[] = {FEINT_ADJ(6, T, 7, 2), FEINT_ADJ(6, T, 7, 1), FEINT_ADJ(6, T, 13, 1)};
+    // default at p = 7 as measured on the 16384-element batch: 6x3 for FP64, 6x2 for FP32
+    static const AdjVariant v7d[] = {FEINT_ADJ(7, T, 6, 3), FEINT_ADJ(7, T, 9, 2), FEINT_ADJ(7, T, 6, 2),
+                                     FEINT_ADJ(7, T, 9, 1)};
+    static const AdjVariant v7f[] = {FEINT_ADJ(7, T, 6, 2), FEINT_ADJ(7, T, 9, 2), FEINT_ADJ(7, T, 6, 3),
+                                     FEINT_ADJ(7, T, 9, 1)};
+    const AdjVariant *v7 = sizeof(T) == 8 ? v7d : v7f;
+#define FEINT_AN(a) *count = (int)(sizeof(a) / sizeof(a[0])); return a
     switch (p) {
-    case 1: return launch_adj<Adj<1, T, 1, 1>>(prm, s);
-    case 2: return launch_adj<Adj<2, T, 2, 2>>(prm, s);
-    case 3: return launch_adj<Adj<3, T, 3, 3>>(prm, s);
-    case 4: return launch_adj<Adj<4, T, 5, 2>>(prm, s);
-    case 5: return launch_adj<Adj<5, T, 4, 2>>(prm, s);
-    case 6: return launch_adj<Adj<6, T, 4, 2>>(prm, s);
-    case 7: return launch_adj<Adj<7, T, 3, 3>>(prm, s);
+    case 1: FEINT_AN(v1);
+    case 2: FEINT_AN(v2);
+    case 3: FEINT_AN(v3);
+    case 4: FEINT_AN(v4);
+    case 5: FEINT_AN(v5);
+    case 6: FEINT_AN(v6);
+    case 7: *count = (int)(sizeof(v7d) / sizeof(v7d[0])); return v7;
     }
-    return FEINT_ERR_UNSUPPORTED_DEGREE;
+#undef FEINT_AN
+    *count = 0;
+    return nullptr;
+}
+
+const AdjVariant *adj_variants(int form, int p, int *count) {
+    if (form == FEINT_FP64) return adj_variants_of<double>(p, count);
+    if (form == FEINT_FP32) return adj_variants_of<float>(p, count);
+    *count = 0;
+    return nullptr;
+}
+
+std::mutex g_adj_mu;
+int g_adj_tile[8][2];                       // chosen variant per (p, form)
+
+const AdjVariant *adj_chosen(int p, int form) {
+    int cnt = 0;
+    const AdjVariant *v = adj_variants(form, p, &cnt);
+    if (!v || cnt == 0) return nullptr;
+    std::lock_guard<std::mutex> lk(g_adj_mu);
+    const int t = g_adj_tile[p][form];
+    return &v[(t >= 0 && t < cnt) ? t : 0];
+}
+
+feint_status adj_setup(const feint_elements *el, int p, feint_form form, const void *G, const void *g,
+                       double *dcoords, double *dD, double *dbeta, double *dc, double *df, hipStream_t st,
+                       AdjParams &prm) {
+    if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
+    if (form != FEINT_FP64 && form != FEINT_FP32) return FEINT_ERR_UNSUPPORTED_FORM;
+    feint_status s = check_elements(el);
+    if (s != FEINT_OK) return s;
+    if (el->ne == 0) return FEINT_OK;
+    if (!G || !g || !dcoords || !dD || !dbeta || !dc || !df) return FEINT_ERR_INVALID_ARG;
+    const DevTables *T = nullptr;
+    s = tables_for_launch(p, st, &T);
+    if (s != FEINT_OK) return s;
+    std::memset(&prm, 0, sizeof prm);
+    prm.coords = el->coords; prm.D = el->D; prm.beta = el->beta; prm.c = el->c; prm.f = el->f;
+    prm.ne = el->ne;
+    prm.G = G; prm.g = g;
+    prm.dX = dcoords; prm.dD = dD; prm.dbeta = dbeta; prm.dc = dc; prm.df = df;
+    prm.qw = T->qw; prm.B64 = T->B64;
+    prm.BT = form == FEINT_FP64 ? (const void *)T->BT64 : (const void *)T->BT32;
+    return FEINT_OK;
+}
+
+feint_status adj_launch(const AdjVariant *v, const AdjParams &prm, hipStream_t st) {
+    (void)hipGetLastError();
+    feint_status s = v->launch(prm, st);
+    if (s != FEINT_OK) return s;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { set_error("adjoint launch", e); return FEINT_ERR_HIP; }
+    return FEINT_OK;
 }
 
 }  // namespace
@@ -299,32 +415,86 @@ feint_status dispatch_adj(int p, const AdjParams &prm, hipStream_t s) {
 
 using namespace feint;
 
-extern "C" feint_status feint_integrate_adjoint(const feint_elements *el, int p, feint_form form, const void *G,
-                                                const void *g, double *dcoords, double *dD, double *dbeta,
-                                                double *dc, double *df, void *stream) {
+extern "C" {
+
+feint_status feint_integrate_adjoint(const feint_elements *el, int p, feint_form form, const void *G,
+                                     const void *g, double *dcoords, double *dD, double *dbeta,
+                                     double *dc, double *df, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    AdjParams prm;
+    feint_status s = adj_setup(el, p, form, G, g, dcoords, dD, dbeta, dc, df, st, prm);
+    if (s != FEINT_OK || el->ne == 0) return s;
+    return adj_launch(adj_chosen(p, form), prm, st);
+}
+
+int feint_adjoint_tile_count(int p, feint_form form) {
+    int cnt = 0;
+    if (p < 1 || p > kMaxP) return 0;
+    adj_variants(form, p, &cnt);
+    return cnt;
+}
+
+int feint_adjoint_tile_get(int p, feint_form form) {
+    if (p < 1 || p > kMaxP || (form != FEINT_FP64 && form != FEINT_FP32)) return -1;
+    std::lock_guard<std::mutex> lk(g_adj_mu);
+    return g_adj_tile[p][form];
+}
+
+feint_status feint_adjoint_tile_set(int p, feint_form form, int tile) {
     if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
     if (form != FEINT_FP64 && form != FEINT_FP32) return FEINT_ERR_UNSUPPORTED_FORM;
-    feint_status s = check_elements(el);
-    if (s != FEINT_OK) return s;
-    if (el->ne == 0) return FEINT_OK;
-    if (!G || !g || !dcoords || !dD || !dbeta || !dc || !df) return FEINT_ERR_INVALID_ARG;
-    hipStream_t st = (hipStream_t)stream;
-    const DevTables *T = nullptr;
-    s = tables_for_launch(p, st, &T);
-    if (s != FEINT_OK) return s;
-    AdjParams prm;
-    std::memset(&prm, 0, sizeof prm);
-    prm.coords = el->coords; prm.D = el->D; prm.beta = el->beta; prm.c = el->c; prm.f = el->f;
-    prm.ne = el->ne;
-    prm.G = G; prm.g = g;
-    prm.dX = dcoords; prm.dD = dD; prm.dbeta = dbeta; prm.dc = dc; prm.df = df;
-    prm.qw = T->qw; prm.B64 = T->B64;
-    prm.Brow = form == FEINT_FP64 ? (const void *)T->B64 : (const void *)T->B32;
-    prm.BT = form == FEINT_FP64 ? (const void *)T->BT64 : (const void *)T->BT32;
-    (void)hipGetLastError();
-    s = form == FEINT_FP64 ? dispatch_adj<double>(p, prm, st) : dispatch_adj<float>(p, prm, st);
-    if (s != FEINT_OK) return s;
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) { set_error("adjoint launch", e); return FEINT_ERR_HIP; }
+    if (tile < 0 || tile >= feint_adjoint_tile_count(p, form)) return FEINT_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_adj_mu);
+    g_adj_tile[p][form] = tile;
     return FEINT_OK;
 }
+
+feint_status feint_adjoint_tile_describe(int p, feint_form form, int tile, char *buf, size_t len) {
+    if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
+    if (form != FEINT_FP64 && form != FEINT_FP32) return FEINT_ERR_UNSUPPORTED_FORM;
+    int cnt = 0;
+    const AdjVariant *v = adj_variants(form, p, &cnt);
+    if (!buf || len == 0 || tile < 0 || tile >= cnt) return FEINT_ERR_INVALID_ARG;
+    std::snprintf(buf, len, "%dx%d", v[tile].ta, v[tile].tb);
+    return FEINT_OK;
+}
+
+feint_status feint_adjoint_autotune(const feint_elements *el, int p, feint_form form, const void *G,
+                                    const void *g, double *dcoords, double *dD, double *dbeta, double *dc,
+                                    double *df, int reps, double *best_ms, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    if (reps < 1 || (el && el->ne == 0)) return FEINT_ERR_INVALID_ARG;
+    AdjParams prm;
+    feint_status s = adj_setup(el, p, form, G, g, dcoords, dD, dbeta, dc, df, st, prm);
+    if (s != FEINT_OK) return s;
+    int cnt = 0;
+    const AdjVariant *v = adj_variants(form, p, &cnt);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return FEINT_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return FEINT_ERR_HIP; }
+    int best = 0;
+    float best_t = 1e30f;
+    for (int t = 0; t < cnt && s == FEINT_OK; ++t) {
+        s = adj_launch(&v[t], prm, st);                     // warm-up
+        if (s != FEINT_OK) break;
+        (void)hipEventRecord(e0, st);
+        for (int r = 0; r < reps && s == FEINT_OK; ++r) s = adj_launch(&v[t], prm, st);
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) { s = FEINT_ERR_HIP; break; }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (ms < best_t) { best_t = ms; best = t; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != FEINT_OK) return s;
+    {
+        std::lock_guard<std::mutex> lk(g_adj_mu);
+        g_adj_tile[p][form] = best;
+    }
+    if (best_ms) *best_ms = best_t;
+    return FEINT_OK;
+}
+
+}  // extern "C"

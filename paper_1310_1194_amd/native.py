@@ -18,7 +18,8 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported degree", -3: "unsupp
 # every symbol include/feint.h declares
 EXPORTS = (
     "feint_nshp", "feint_nq", "feint_elem_size", "feint_prepare", "feint_integrate",
-    "feint_integrate_adjoint", "feint_mixed_plan_create", "feint_mixed_bucket",
+    "feint_integrate_adjoint", "feint_adjoint_tile_count", "feint_adjoint_tile_get", "feint_adjoint_tile_set",
+    "feint_adjoint_tile_describe", "feint_adjoint_autotune", "feint_mixed_plan_create", "feint_mixed_bucket",
     "feint_integrate_mixed", "feint_mixed_graph_capture", "feint_mixed_graph_launch",
     "feint_mixed_plan_destroy", "feint_mixed_autotune", "feint_mixed_tile_count", "feint_mixed_tile_get",
     "feint_mixed_tile_set", "feint_mixed_tile_describe", "feint_tile_count", "feint_tile_get", "feint_tile_set",
@@ -63,6 +64,12 @@ def lib() -> ctypes.CDLL:
             "feint_prepare": (_i, [_i]),
             "feint_integrate": (_i, [P, _i, _i, _vp, _vp, _vp, _vp, _vp]),
             "feint_integrate_adjoint": (_i, [P, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+            "feint_adjoint_tile_count": (_i, [_i, _i]),
+            "feint_adjoint_tile_get": (_i, [_i, _i]),
+            "feint_adjoint_tile_set": (_i, [_i, _i, _i]),
+            "feint_adjoint_tile_describe": (_i, [_i, _i, _i, ctypes.c_char_p, ctypes.c_size_t]),
+            "feint_adjoint_autotune": (_i, [P, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i,
+                                            ctypes.POINTER(ctypes.c_double), _vp]),
             "feint_mixed_plan_create": (_i, [_i64, _i, ctypes.POINTER(_vp)]),
             "feint_mixed_bucket": (_i, [_vp, _vp, _i64, _vp, _vp, _vp, _vp]),
             "feint_integrate_mixed": (_i, [_vp, P, _vp, _vp, _vp, _vp, _vp, _vp]),

@@ -70,6 +70,29 @@ def test_tiles():
     assert L.feint_tile_count(0, 0) == 0
 
 
+def test_adjoint_tiles():
+    L = native.lib()
+    buf = ctypes.create_string_buffer(16)
+    for p in range(1, 8):
+        for form in (0, 1):
+            n = L.feint_adjoint_tile_count(p, form)
+            assert n >= 1
+            assert L.feint_adjoint_tile_get(p, form) == 0
+            for t in range(n):
+                assert L.feint_adjoint_tile_describe(p, form, t, buf, 16) == 0
+                assert re.fullmatch(rb"\d+x\d+", buf.value)
+            assert L.feint_adjoint_tile_set(p, form, n) == -1
+            assert L.feint_adjoint_tile_describe(p, form, n, buf, 16) == -1
+        for form in (2, 3):          # split forms have no adjoint
+            assert L.feint_adjoint_tile_count(p, form) == 0
+            assert L.feint_adjoint_tile_get(p, form) == -1
+            assert L.feint_adjoint_tile_set(p, form, 0) == -3
+    assert L.feint_adjoint_tile_count(0, 0) == 0
+    assert L.feint_adjoint_tile_set(8, 0, 0) == -2
+    # autotune validates before touching the device
+    assert L.feint_adjoint_autotune(None, 3, 0, None, None, None, None, None, None, None, 1, None, None) == -1
+
+
 def test_status_strings():
     L = native.lib()
     for code in native.STATUS:

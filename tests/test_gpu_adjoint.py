@@ -43,13 +43,44 @@ def test_adjoint_parity(torch_cuda, p, form):
         g = g.astype(np.float32).astype(np.float64)
     ref = oracle.adjoint(p, batch.coords, batch.D, batch.beta, batch.c, batch.f, G, g)
     dt = torch.float64 if form == "fp64" else torch.float32
-    flush(f"[adjoint] p={p} form={form} ne={batch.ne}")
-    got = F.adjoint_raw(*to_dev(batch), torch.from_numpy(G).cuda().to(dt), torch.from_numpy(g).cuda().to(dt), p, form)
+    X = to_dev(batch)
+    Gd, gd = torch.from_numpy(G).cuda().to(dt), torch.from_numpy(g).cuda().to(dt)
+    for tile in range(F.adjoint_tile_count(p, form)):
+        F.adjoint_tile_set(p, form, tile)
+        flush(f"[adjoint] p={p} form={form} block {F.adjoint_tile_describe(p, form, tile)} ne={batch.ne}")
+        got = F.adjoint_raw(*X, Gd, gd, p, form)
+        torch.cuda.synchronize()
+        for name, a, r in zip(NAMES, got, ref[:5]):
+            e = rel(a.cpu().numpy(), r)
+            flush(f"    {name}: {e:.3e}")
+            assert e <= TOL[form], name
+    F.adjoint_tile_set(p, form, 0)
+
+
+def test_adjoint_autotune(torch_cuda):
+    """The autotuner times every block shape, keeps one, and the result of the
+    kept shape is unchanged within the FP64 tolerance."""
+    import oracle
+    import paper_1310_1194_amd as F
+    torch = torch_cuda
+    p = 4
+    batch = small_batch(p, seed=31)
+    n = F.nshp(p)
+    rng = np.random.default_rng(31)
+    G = rng.normal(size=(batch.ne, n, n))
+    g = rng.normal(size=(batch.ne, n))
+    X = to_dev(batch)
+    Gd, gd = torch.from_numpy(G).cuda(), torch.from_numpy(g).cuda()
+    ms = F.adjoint_autotune(*X, Gd, gd, p, "fp64", reps=1)
+    t = F.adjoint_tile_get(p, "fp64")
+    flush(f"[adjoint-autotune] p={p}: block {F.adjoint_tile_describe(p, 'fp64', t)} {ms:.3f} ms")
+    assert ms > 0 and 0 <= t < F.adjoint_tile_count(p, "fp64")
+    got = F.adjoint_raw(*X, Gd, gd, p, "fp64")
     torch.cuda.synchronize()
-    for name, a, r in zip(NAMES, got, ref[:5]):
-        e = rel(a.cpu().numpy(), r)
-        flush(f"    {name}: {e:.3e}")
-        assert e <= TOL[form], name
+    ref = oracle.adjoint(p, batch.coords, batch.D, batch.beta, batch.c, batch.f, G, g)
+    for a, r in zip(got, ref[:5]):
+        assert rel(a.cpu().numpy(), r) <= TOL["fp64"]
+    F.adjoint_tile_set(p, "fp64", 0)
 
 
 def test_autograd_function(torch_cuda):
