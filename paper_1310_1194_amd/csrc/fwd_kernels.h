@@ -11,8 +11,11 @@
 // forms) or eight points at a time (16x16x32 split forms), the wave forms the
 // B-operand fragments Y = W_q B_q in registers and issues TM x TN MFMAs whose
 // A operands are rows of B read straight from the table.  The load vector
-// b_e = sum_q w_q det J_q f phi(q) is accumulated in FP64 by the waves of the
-// first column block.
+// b_e = sum_q w_q det J_q f phi(q) rides along in the contraction where the
+// padded width leaves a spare column (n < NP: every degree but p = 7): column
+// n of Y carries Z[(q, r)] = (r == 0 ? w_q det J_q f : 0), so column n of the
+// accumulator is b_e, in the form's precision.  At p = 7 it is accumulated
+// in FP64 by the waves of the first column block.
 #pragma once
 #include "device_common.h"
 #include "launch.h"
@@ -45,6 +48,14 @@ __device__ inline int64_t offb_of(const FwdParams &prm, int64_t e, int n) {
     return prm.offb ? prm.offb[e] : e * (int64_t)n;
 }
 
+// The load-vector column of degree P: whether it exists (a spare padded
+// column), the first column of its 16-wide tile and its lane in that tile.
+template <int P> struct LoadCol {
+    static constexpr int N = c_nshp(P);
+    static constexpr bool on = N < c_pad16(N);
+    static constexpr int tile0 = N / 16 * 16, lane = N % 16;
+};
+
 // ---------------------------------------------------------------------------
 // 16x16x4 forms (FP64, FP32): one point (4 K-rows) per MFMA.
 // ---------------------------------------------------------------------------
@@ -55,6 +66,7 @@ struct K4 {
     static constexpr int EPI = 1;                      // element slots per work item
     static constexpr int NBR = c_cdiv(TM * 16, 64);   // load-vector rows per lane
     typedef typename AccT<T>::type V4;
+    typedef LoadCol<P> LC;
 
     struct Slice {                    // one wave's LDS
         T W[64][WROW<T>::value];      // padded rows: conflict-free per-lane writes
@@ -102,7 +114,7 @@ struct K4 {
                 }
             }
             wave_sync();
-            if (bj == 0) {
+            if (!LC::on && bj == 0) {
 #pragma unroll
                 for (int m = 0; m < NBRV; ++m) {
                     const int row = a0 + lane + 64 * m;
@@ -126,6 +138,8 @@ struct K4 {
                         const T *bp = Bq + b0 + tj * 16 + i16;
                         yf[tj] = w0 * bp[0] + w1 * bp[NP] + w2 * bp[2 * NP] + w3 * bp[3 * NP];
                     }
+                    if (LC::on && b0 + tj * 16 == LC::tile0 && i16 == LC::lane)   // load-vector column
+                        yf[tj] = kg == 0 ? (T)sl.sf[qq] : (T)0;
                 }
 #pragma unroll
                 for (int ti = 0; ti < TMV; ++ti) {
@@ -140,6 +154,7 @@ struct K4 {
             wave_sync();
         }
         T *Aout = (T *)prm.A + offA_of(prm, e, N);
+        T *bout = (T *)prm.b + offb_of(prm, e, N);
 #pragma unroll
         for (int ti = 0; ti < TMV; ++ti)
 #pragma unroll
@@ -150,10 +165,11 @@ struct K4 {
                     const int row = a0 + ti * 16 + acc_row<T>(lane, r);
                     if (row < N && col < N)
                         Aout[(size_t)row * N + col] = acc[ti][tj][r];
+                    else if (LC::on && row < N && col == N)
+                        bout[row] = acc[ti][tj][r];
                 }
             }
-        if (bj == 0) {
-            T *bout = (T *)prm.b + offb_of(prm, e, N);
+        if (!LC::on && bj == 0) {
 #pragma unroll
             for (int m = 0; m < NBRV; ++m) {
                 const int row = a0 + lane + 64 * m;
@@ -197,6 +213,7 @@ struct K32 {
     static constexpr int NBR = c_cdiv(TM * 16, 64);
     typedef typename SplitT<FORM>::vec HV;
     typedef typename SplitT<FORM>::scal HS;
+    typedef LoadCol<P> LC;
 
     struct Slice {                            // one wave's LDS
         float W[64][WROW<float>::value];      // padded rows: conflict-free per-lane writes
@@ -205,8 +222,9 @@ struct K32 {
     struct Smem { Slice w[4]; };
 
     __device__ static float elem_scale(const FwdParams &prm, const ElemIn &E) {
-        // largest row sum of |W_q| over the element's points, times max |B|:
-        // a bound on |Y|; scale so that the bound lies in [2^13, 2^14)
+        // largest row sum of |W_q| over the element's points, times max |B|,
+        // and the largest |w det J f| (the load-vector column): a bound on
+        // |Y|; scale so that the bound lies in [2^13, 2^14)
         const int lane = threadIdx.x & 63;
         double m = 0.0;
         for (int qc = 0; qc < NQ; qc += 64) {
@@ -218,6 +236,10 @@ struct K32 {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const double s = fabs(W[4 * r]) + fabs(W[4 * r + 1]) + fabs(W[4 * r + 2]) + fabs(W[4 * r + 3]);
+                    m = s > m ? s : m;
+                }
+                if (LC::on) {
+                    const double s = fabs(sf) / (double)prm.bmax;
                     m = s > m ? s : m;
                 }
             }
@@ -292,7 +314,7 @@ struct K32 {
                 sl.sf[lane] = sf;
             }
             wave_sync();
-            if (bj == 0) {
+            if (!LC::on && bj == 0) {
 #pragma unroll
                 for (int m = 0; m < NBRV; ++m) {
                     const int row = a0 + lane + 64 * m;
@@ -353,6 +375,12 @@ struct K32 {
                         y[r] = wa[4 * r + 1] * s0[1] + wa[4 * r + 2] * s0[2] + wa[4 * r + 3] * s0[3];
                         y[4 + r] = wb[4 * r + 1] * s1[1] + wb[4 * r + 2] * s1[2] + wb[4 * r + 3] * s1[3];
                     }
+                    if (LC::on && b0 + tj * 16 == LC::tile0 && i16 == LC::lane) {   // load-vector column
+#pragma unroll
+                        for (int r = 0; r < 8; ++r) y[r] = 0.0f;
+                        y[0] = (float)sl.sf[qa] * ys;
+                        y[4] = (float)sl.sf[qa + 1] * ys;
+                    }
                     split8(y, yh[tj], yl[tj]);
                 }
 #pragma unroll
@@ -368,6 +396,7 @@ struct K32 {
         }
         const float unscale = FORM == FP16X3 ? ldexpf(1.0f, -prm.f16_shift) / ys : 1.0f;
         float *Aout = (float *)prm.A + offA_of(prm, e, N);
+        float *bout = (float *)prm.b + offb_of(prm, e, N);
 #pragma unroll
         for (int ti = 0; ti < TMV; ++ti)
 #pragma unroll
@@ -378,10 +407,11 @@ struct K32 {
                     const int row = a0 + ti * 16 + 4 * kg + r;
                     if (row < N && col < N)
                         Aout[(size_t)row * N + col] = acc[ti][tj][r] * unscale;
+                    else if (LC::on && row < N && col == N)
+                        bout[row] = acc[ti][tj][r] * unscale;
                 }
             }
-        if (bj == 0) {
-            float *bout = (float *)prm.b + offb_of(prm, e, N);
+        if (!LC::on && bj == 0) {
 #pragma unroll
             for (int m = 0; m < NBRV; ++m) {
                 const int row = a0 + lane + 64 * m;

@@ -55,6 +55,7 @@ struct K4S {
     static constexpr int STAGE_V = STAGE_T * (int)sizeof(T) / 16;
     static_assert(64 % SP == 0, "stages must tile the 64-point chunks");
     typedef typename AccT<T>::type V4;
+    typedef LoadCol<P> LC;
 
     struct Smem {
         T B[2][STAGE_T];
@@ -110,7 +111,7 @@ struct K4S {
                         }
                     }
                     wave_sync();
-                    if (bj == 0) {
+                    if (!LC::on && bj == 0) {
 #pragma unroll
                         for (int m = 0; m < NBRV; ++m) {
                             const int row = a0 + lane + 64 * m;
@@ -136,6 +137,8 @@ struct K4S {
                             const T *bp = Bq + b0 + tj * 16 + i16;
                             yf[tj] = w0 * bp[0] + w1 * bp[NP] + w2 * bp[2 * NP] + w3 * bp[3 * NP];
                         }
+                        if (LC::on && b0 + tj * 16 == LC::tile0 && i16 == LC::lane)   // load-vector column
+                            yf[tj] = kg == 0 ? (T)sm.sf[wave][ql] : (T)0;
                     }
 #pragma unroll
                     for (int ti = 0; ti < TMV; ++ti) {
@@ -153,6 +156,7 @@ struct K4S {
         }
         if (!active) return;
         T *Aout = (T *)prm.A + offA_of(prm, e, N);
+        T *bout = (T *)prm.b + offb_of(prm, e, N);
 #pragma unroll
         for (int ti = 0; ti < TMV; ++ti)
 #pragma unroll
@@ -163,10 +167,11 @@ struct K4S {
                     const int row = a0 + ti * 16 + acc_row<T>(lane, r);
                     if (row < N && col < N)
                         Aout[(size_t)row * N + col] = acc[ti][tj][r];
+                    else if (LC::on && row < N && col == N)
+                        bout[row] = acc[ti][tj][r];
                 }
             }
-        if (bj == 0) {
-            T *bout = (T *)prm.b + offb_of(prm, e, N);
+        if (!LC::on && bj == 0) {
 #pragma unroll
             for (int m = 0; m < NBRV; ++m) {
                 const int row = a0 + lane + 64 * m;
@@ -208,6 +213,7 @@ struct K32S {
     static constexpr int NV = 2 * VA + VY;
     typedef typename SplitT<FORM>::vec HV;
     typedef typename SplitT<FORM>::scal HS;
+    typedef LoadCol<P> LC;
 
     struct Smem {
         uint4 S[2][NV];      // [hi A | lo A | FP32 columns]
@@ -292,7 +298,7 @@ struct K32S {
                         sm.sf[wave][lane] = sf;
                     }
                     wave_sync();
-                    if (bj == 0) {
+                    if (!LC::on && bj == 0) {
 #pragma unroll
                         for (int m = 0; m < NBRV; ++m) {
                             const int row = a0 + lane + 64 * m;
@@ -330,6 +336,12 @@ struct K32S {
                             y[r] = wa[4 * r + 1] * s0.y + wa[4 * r + 2] * s0.z + wa[4 * r + 3] * s0.w;
                             y[4 + r] = wb[4 * r + 1] * s1.y + wb[4 * r + 2] * s1.z + wb[4 * r + 3] * s1.w;
                         }
+                        if (LC::on && b0 + tj * 16 == LC::tile0 && i16 == LC::lane) {   // load-vector column
+#pragma unroll
+                            for (int r = 0; r < 8; ++r) y[r] = 0.0f;
+                            y[0] = (float)sm.sf[wave][q0 + qa - qc] * ys;
+                            y[4] = (float)sm.sf[wave][q0 + qa + 1 - qc] * ys;
+                        }
                         Plain::split8(y, yh[tj], yl[tj]);
                     }
                 }
@@ -357,6 +369,7 @@ struct K32S {
         if (!active) return;
         const float unscale = FORM == FP16X3 ? ldexpf(1.0f, -prm.f16_shift) / ys : 1.0f;
         float *Aout = (float *)prm.A + offA_of(prm, e, N);
+        float *bout = (float *)prm.b + offb_of(prm, e, N);
 #pragma unroll
         for (int ti = 0; ti < TMV; ++ti)
 #pragma unroll
@@ -367,10 +380,11 @@ struct K32S {
                     const int row = a0 + ti * 16 + 4 * kg + r;
                     if (row < N && col < N)
                         Aout[(size_t)row * N + col] = acc[ti][tj][r] * unscale;
+                    else if (LC::on && row < N && col == N)
+                        bout[row] = acc[ti][tj][r] * unscale;
                 }
             }
-        if (bj == 0) {
-            float *bout = (float *)prm.b + offb_of(prm, e, N);
+        if (!LC::on && bj == 0) {
 #pragma unroll
             for (int m = 0; m < NBRV; ++m) {
                 const int row = a0 + lane + 64 * m;

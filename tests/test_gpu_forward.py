@@ -8,8 +8,10 @@ global over the batch and maximum over single elements):
           of K = 4 nq terms: sqrt(K) * 2^-24 * (sum |terms| / |entry|));
   fp16x3  1e-5 global; per element 1e-4 (hi+lo fp16 keeps 22 bits, the FP32
           accumulation dominates as for fp32).
-The load vector is accumulated in FP64 in every form and rounded once, so b
-meets 1e-12 (fp64) or the FP32 rounding bound 2^-23 (other forms).
+The load vector is formed by the same contraction as A (a spare padded
+column of Y carries w det J f), so it carries the form's precision and is held
+to the same tolerances as A; at p = 7 (no spare column) it is accumulated in
+FP64 and is well inside them.
 """
 import numpy as np
 import pytest
@@ -19,7 +21,7 @@ from gpu_util import flush, oracle_of, rel_errors, small_batch, to_dev
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": (1e-12, 1e-12), "fp32": (1e-5, 1e-4), "bf16x3": (1e-5, 2e-4), "fp16x3": (1e-5, 1e-4)}
-BTOL = {"fp64": 1e-12, "fp32": 2.5e-7, "bf16x3": 2.5e-7, "fp16x3": 2.5e-7}
+BTOL = TOL
 
 
 @pytest.fixture(scope="module")
@@ -54,7 +56,7 @@ def test_forward_parity_every_tile(torch_cuda, p, form):
         gb, mb = rel_errors(b, br)
         flush(f"    A: global {gA:.3e} max-elem {mA:.3e}   b: global {gb:.3e} max-elem {mb:.3e}")
         assert gA <= TOL[form][0] and mA <= TOL[form][1]
-        assert gb <= BTOL[form] and mb <= BTOL[form] * 4
+        assert gb <= BTOL[form][0] and mb <= BTOL[form][1]
 
 
 @pytest.mark.parametrize("p", [1, 2, 3])
@@ -129,5 +131,5 @@ def test_full_size_sampled(torch_cuda, name, form):
     gA, mA = rel_errors(A[ti].cpu().numpy(), Ar)
     gb, mb = rel_errors(b[ti].cpu().numpy(), br)
     flush(f"    A: global {gA:.3e} max-elem {mA:.3e}   b: {gb:.3e}")
-    assert gA <= TOL[form][0] and mA <= TOL[form][1] and gb <= BTOL[form]
+    assert gA <= TOL[form][0] and mA <= TOL[form][1] and gb <= BTOL[form][0]
     assert bool(torch.isfinite(A).all())
