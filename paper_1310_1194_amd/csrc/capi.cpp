@@ -231,7 +231,7 @@ feint_status feint_tile_describe(int p, feint_form form, int tile, char *buf, si
         std::snprintf(buf, len, "v%d%s", v[tile].tn, v[tile].minw > 1 ? "o2" : "");
     else
         std::snprintf(buf, len, "%dx%d%s%s", v[tile].tm, v[tile].tn,
-                      v[tile].staged == 1 ? "s" : (v[tile].staged == 2 ? "sa" : ""),
+                      v[tile].staged == 1 ? "s" : v[tile].staged == 2 ? "sa" : v[tile].staged == 4 ? "p" : "",
                       v[tile].minw > 1 ? "o2" : "");
     return FEINT_OK;
 }

@@ -15,7 +15,10 @@ const FwdVariant v4[] = {
     FEINT_K32U(4, BF16X3, 5, 3, 2),
     FEINT_K32U(4, BF16X3, 5, 5, 1),
     FEINT_K32S(4, BF16X3, 5, 5, true, 1),
-    FEINT_K32U(4, BF16X3, 5, 3, 1)};
+    FEINT_K32U(4, BF16X3, 5, 3, 1),
+    FEINT_K32P(4, BF16X3, 5, 5, 1),
+    FEINT_K32P(4, BF16X3, 5, 3, 1),
+    FEINT_K32P(4, BF16X3, 5, 3, 2)};
 const FwdVariant v5[] = {
     FEINT_K32S(5, BF16X3, 8, 4, false, 1),
     FEINT_K32S(5, BF16X3, 8, 4, true, 1),

@@ -256,19 +256,31 @@ struct K32 {
     }
 
     // hi = rn(y), lo = rn(y - hi), two values per conversion instruction.
+    // The residual y - hi is exact in FP32; it is taken with one two-term
+    // dot product of the packed hi with (-1, -0) or (-0, -1) plus y, which
+    // saves converting hi back to FP32.  The zero halves are -0.0 on purpose:
+    // (-1, 0) in bf16 is emitted as the inline constant -1.0, which the
+    // hardware reads as the FP32 pattern, i.e. the pair (0, -1) (measured on
+    // gfx950); with -0.0 the pair can only be encoded as a literal, and
+    // adding -0.0 never changes the residual.
     __device__ static void split8(const float *y, HV &hi, HV &lo) {
         typedef float f2 __attribute__((ext_vector_type(2)));
         typedef HS h2 __attribute__((ext_vector_type(2)));
+        const h2 m0 = {(HS)-1.0f, (HS)-0.0f}, m1 = {(HS)-0.0f, (HS)-1.0f};
 #pragma unroll
         for (int v = 0; v < 8; v += 2) {
             const f2 yy = {y[v], y[v + 1]};
             const h2 h = __builtin_convertvector(yy, h2);
-            const f2 back = __builtin_convertvector(h, f2);
-            const f2 r = {yy.x - back.x, yy.y - back.y};
+            const f2 r = {dot2(h, m0, yy.x), dot2(h, m1, yy.y)};
             const h2 l = __builtin_convertvector(r, h2);
             hi[v] = h.x; hi[v + 1] = h.y;
             lo[v] = l.x; lo[v + 1] = l.y;
         }
+    }
+    template <typename H2>
+    __device__ static float dot2(H2 a, H2 b, float c) {
+        if constexpr (FORM == BF16X3) return __builtin_amdgcn_fdot2_f32_bf16(a, b, c, false);
+        else return __builtin_amdgcn_fdot2(a, b, c, false);
     }
 
     template <int TMV, int TNV>
@@ -383,14 +395,19 @@ struct K32 {
                     }
                     split8(y, yh[tj], yl[tj]);
                 }
+                // product by product over the tiles: consecutive MFMAs are independent
 #pragma unroll
                 for (int ti = 0; ti < TMV; ++ti)
 #pragma unroll
-                    for (int tj = 0; tj < TNV; ++tj) {
-                        acc[ti][tj] = mfma32(al[ti], yh[tj], acc[ti][tj]);
-                        acc[ti][tj] = mfma32(ah[ti], yl[tj], acc[ti][tj]);
-                        acc[ti][tj] = mfma32(ah[ti], yh[tj], acc[ti][tj]);
-                    }
+                    for (int tj = 0; tj < TNV; ++tj) acc[ti][tj] = mfma32(al[ti], yh[tj], acc[ti][tj]);
+#pragma unroll
+                for (int ti = 0; ti < TMV; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < TNV; ++tj) acc[ti][tj] = mfma32(ah[ti], yl[tj], acc[ti][tj]);
+#pragma unroll
+                for (int ti = 0; ti < TMV; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < TNV; ++tj) acc[ti][tj] = mfma32(ah[ti], yh[tj], acc[ti][tj]);
             }
             wave_sync();
         }

@@ -4,6 +4,7 @@
 #include "fwd_kernels.h"
 #include "fwd_staged.h"
 #include "fwd_valu.h"
+#include "fwd_pipe.h"
 
 namespace feint {
 
@@ -35,6 +36,9 @@ int64_t items_of(int64_t ne) { return items_for<KER>(ne); }
 // V: vector-ALU kernel, LPE lanes per element (tm = 0, tn = LPE, staged = 3).
 #define FEINT_KV(P, T, LPE, W) \
     FwdVariant{0, LPE, 3, W, &launch_direct<KV<P, T, LPE>, W>, &items_of<KV<P, T, LPE>>}
+// P: software-pipelined split kernel (staged = 4).
+#define FEINT_K32P(P, F, TM, TN, W) \
+    FwdVariant{TM, TN, 4, W, &launch_direct<K32P<P, F, TM, TN>, W>, &items_of<K32P<P, F, TM, TN>>}
 #define FEINT_K32S(P, F, TM, TN, SY, W) \
     FwdVariant{TM, TN, 1 + !(SY), W, &launch_staged<K32S<P, F, TM, TN, SY>, W>, &items_of<K32S<P, F, TM, TN, SY>>}
 

@@ -353,15 +353,19 @@ struct K32S {
                         al[ti] = *(const HV *)(Al + o);
                     }
                 }
+                // product by product over the tiles: consecutive MFMAs are independent
 #pragma unroll
                 for (int ti = 0; ti < TMV; ++ti)
 #pragma unroll
-                    for (int tj = 0; tj < TNV; ++tj)
-                        {
-                            acc[ti][tj] = mfma32(al[ti], yh[tj], acc[ti][tj]);
-                            acc[ti][tj] = mfma32(ah[ti], yl[tj], acc[ti][tj]);
-                            acc[ti][tj] = mfma32(ah[ti], yh[tj], acc[ti][tj]);
-                        }
+                    for (int tj = 0; tj < TNV; ++tj) acc[ti][tj] = mfma32(al[ti], yh[tj], acc[ti][tj]);
+#pragma unroll
+                for (int ti = 0; ti < TMV; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < TNV; ++tj) acc[ti][tj] = mfma32(ah[ti], yl[tj], acc[ti][tj]);
+#pragma unroll
+                for (int ti = 0; ti < TMV; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < TNV; ++tj) acc[ti][tj] = mfma32(ah[ti], yh[tj], acc[ti][tj]);
             }
             if (kb + 1 < NKB) put(sm.S[buf ^ 1], pre);
             __syncthreads();

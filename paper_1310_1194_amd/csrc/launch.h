@@ -31,7 +31,7 @@ struct FwdParams {
 struct FwdVariant {
     int tm, tn;
     int staged;          // 1: the table is staged through LDS per workgroup (2: A operands only),
-                         // 3: vector-ALU kernel
+                         // 3: vector-ALU kernel, 4: software-pipelined split kernel
     int minw;            // waves per SIMD the register allocation allows
     void (*launch)(const FwdParams &, hipStream_t);
     int64_t (*items)(int64_t ne);   // work items (waves) of a launch over ne elements

@@ -65,7 +65,7 @@ def test_tiles():
             assert n >= 1
             buf = ctypes.create_string_buffer(16)
             assert L.feint_tile_describe(p, form, n - 1, buf, 16) == 0
-            assert re.fullmatch(rb"(\d+x\d+(s|sa)?|v\d+)(o2)?", buf.value)
+            assert re.fullmatch(rb"(\d+x\d+(s|sa|p)?|v\d+)(o2)?", buf.value)
             assert L.feint_tile_set(p, form, n) == -1
     assert L.feint_tile_count(0, 0) == 0
 
