@@ -38,6 +38,7 @@ DTYPE_DESC = {"bf16x3": "bf16x3 (split bf16 MFMA, fp32 accumulate, fp64 geometry
               "fp16x3": "fp16x3 (split fp16 MFMA, fp32 accumulate, fp64 geometry)",
               "fp32": "fp32 (fp32 MFMA, fp64 geometry)", "fp64": "fp64"}
 KERNEL_SOURCES = ["paper_1310_1194_amd/csrc/fwd_kernels.h", "paper_1310_1194_amd/csrc/fwd_staged.h",
+                  "paper_1310_1194_amd/csrc/fwd_pipe.h", "paper_1310_1194_amd/csrc/fwd_valu.h",
                   "paper_1310_1194_amd/csrc/fwd_registry.h", "paper_1310_1194_amd/csrc/fwd_bf16.hip",
                   "paper_1310_1194_amd/csrc/device_common.h", "paper_1310_1194_amd/csrc/tables.cpp"]
 
@@ -49,16 +50,17 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_record(key: str):
-    """HBM bytes per launch measured by rocprofv3 counters (profiles/traffic.json),
-    or None when absent or taken on other kernel sources."""
+def traffic_record(key: str, tile: str):
+    """HBM bytes per launch of the compiled variant `tile` measured by rocprofv3
+    counters (profiles/traffic.json), or None when absent or taken on other
+    kernel sources."""
     path = ROOT / "profiles" / "traffic.json"
     if not path.exists():
         return None
     rec = json.loads(path.read_text()).get(key)
     if not rec or rec.get("source_sha") != kernel_source_sha():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec.get("tiles", {}).get(tile)
 
 
 def cpu_baseline(batch, p, budget_s: float, chunk: int = 4096):
@@ -220,7 +222,7 @@ def bench_forward(args):
             r["err_sample"] = m
 
     h = results[headline]
-    traffic = traffic_record(f"fwd:{headline}:{args.workload}")
+    traffic = traffic_record(f"fwd:{headline}:{args.workload}", results[headline]["tile"])
     es = 8 if headline == "fp64" else 4
     alg_bytes = ne * costmodel.bytes_per_element(p, es)
     # bound = the larger ideal time: MFMA work (three products for a split
