@@ -12,13 +12,12 @@ const FwdVariant v3[] = {
     FEINT_K32S(3, BF16X3, 3, 3, true, 1),
     FEINT_K32S(3, BF16X3, 3, 1, true, 2)};
 const FwdVariant v4[] = {
+    FEINT_K32P(4, BF16X3, 5, 5, 1),
     FEINT_K32U(4, BF16X3, 5, 3, 2),
     FEINT_K32U(4, BF16X3, 5, 5, 1),
     FEINT_K32S(4, BF16X3, 5, 5, true, 1),
     FEINT_K32U(4, BF16X3, 5, 3, 1),
-    FEINT_K32P(4, BF16X3, 5, 5, 1),
-    FEINT_K32P(4, BF16X3, 5, 3, 1),
-    FEINT_K32P(4, BF16X3, 5, 3, 2)};
+    FEINT_K32P(4, BF16X3, 5, 3, 1)};
 const FwdVariant v5[] = {
     FEINT_K32S(5, BF16X3, 8, 4, false, 1),
     FEINT_K32S(5, BF16X3, 8, 4, true, 1),
@@ -30,9 +29,11 @@ const FwdVariant v6[] = {
     FEINT_K32S(6, BF16X3, 7, 4, false, 1),
     FEINT_K32U(6, BF16X3, 13, 2, 1)};
 const FwdVariant v7[] = {
+    FEINT_K32P(7, BF16X3, 6, 6, 1),
     FEINT_K32S(7, BF16X3, 6, 6, false, 1),
-    FEINT_K32S(7, BF16X3, 6, 3, false, 1),
-    FEINT_K32U(7, BF16X3, 6, 6, 1)};
+    FEINT_K32U(7, BF16X3, 6, 6, 1),
+    FEINT_K32P(7, BF16X3, 6, 3, 1),
+    FEINT_K32P(7, BF16X3, 3, 6, 1)};
 }  // namespace
 
 #define FEINT_N(a) (int)(sizeof(a) / sizeof(a[0]))

@@ -15,7 +15,8 @@ const FwdVariant v4[] = {
     FEINT_K32U(4, FP16X3, 5, 3, 2),
     FEINT_K32U(4, FP16X3, 5, 5, 1),
     FEINT_K32S(4, FP16X3, 5, 5, true, 1),
-    FEINT_K32U(4, FP16X3, 5, 3, 1)};
+    FEINT_K32U(4, FP16X3, 5, 3, 1),
+    FEINT_K32P(4, FP16X3, 5, 5, 1)};
 const FwdVariant v5[] = {
     FEINT_K32S(5, FP16X3, 8, 4, false, 1),
     FEINT_K32S(5, FP16X3, 8, 4, true, 1),
@@ -27,9 +28,10 @@ const FwdVariant v6[] = {
     FEINT_K32S(6, FP16X3, 7, 4, false, 1),
     FEINT_K32U(6, FP16X3, 13, 2, 1)};
 const FwdVariant v7[] = {
+    FEINT_K32P(7, FP16X3, 6, 6, 1),
     FEINT_K32S(7, FP16X3, 6, 6, false, 1),
-    FEINT_K32S(7, FP16X3, 6, 3, false, 1),
-    FEINT_K32U(7, FP16X3, 6, 6, 1)};
+    FEINT_K32U(7, FP16X3, 6, 6, 1),
+    FEINT_K32P(7, FP16X3, 3, 6, 1)};
 }  // namespace
 
 #define FEINT_N(a) (int)(sizeof(a) / sizeof(a[0]))

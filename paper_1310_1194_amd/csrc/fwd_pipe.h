@@ -9,8 +9,9 @@
 // block forms and splits Y of block k+1 and loads the A fragments of block
 // k+1 and the FP32 columns of block k+2.  Two register sets alternate between
 // the roles "current" and "next", so nothing is copied between iterations.
-// The load vector rides in the contraction (spare padded column), which
-// restricts these kernels to degrees with n < n_pad.
+// The load vector rides in the contraction where the padded width leaves a
+// spare column (n < n_pad); at p = 7 it is summed in FP64 after the K loop
+// from the load weights kept in LDS.
 #pragma once
 #include "fwd_kernels.h"
 
@@ -22,12 +23,13 @@ struct K32P {
     static constexpr int NQP = c_pad8(NQ), NKB = NQP / 8;
     static constexpr int BM = c_cdiv(NT, TM), BN = c_cdiv(NT, TN), NBLK = BM * BN;
     static constexpr int EPI = 1;
-    static constexpr int RW = 20;                 // padded LDS row: conflict-free per-lane writes
+    // LDS row of W: padded (conflict-free per-lane writes) unless four waves'
+    // slices of the whole element would not fit the 160 KB of a CU
+    static constexpr int RW = NQP * (20 * 4 + 8) * 4 <= 160 * 1024 ? 20 : 16;
     static constexpr int VPM = 3;                 // vector instructions scheduled after each MFMA
     typedef typename SplitT<FORM>::vec HV;
     typedef typename SplitT<FORM>::scal HS;
     typedef LoadCol<P> LC;
-    static_assert(LC::on, "the load vector must ride in a spare padded column");
 
     struct Slice {                                // one wave's LDS: the whole element's points
         float W[NQP][RW];
@@ -241,6 +243,28 @@ struct K32P {
         const float unscale = FORM == FP16X3 ? ldexpf(1.0f, -prm.f16_shift) / ys : 1.0f;
         float *Aout = (float *)prm.A + offA_of(prm, e, N);
         float *bout = (float *)prm.b + offb_of(prm, e, N);
+        if (!LC::on && bj == 0) {
+            // no spare column: b_row = sum_q w_q det J_q f phi_row(q) in FP64, four
+            // independent partial sums per row
+            constexpr int NBRV = c_cdiv(TMV * 16, 64);
+#pragma unroll
+            for (int m = 0; m < NBRV; ++m) {
+                const int row = a0 + lane + 64 * m;
+                if (lane + 64 * m < TMV * 16 && row < N) {
+                    const double *phi = prm.B64 + row;
+                    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+                    int q = 0;
+                    for (; q + 4 <= NQ; q += 4) {
+                        s0 += sl.sf[q] * phi[(size_t)q * 4 * NP];
+                        s1 += sl.sf[q + 1] * phi[(size_t)(q + 1) * 4 * NP];
+                        s2 += sl.sf[q + 2] * phi[(size_t)(q + 2) * 4 * NP];
+                        s3 += sl.sf[q + 3] * phi[(size_t)(q + 3) * 4 * NP];
+                    }
+                    for (; q < NQ; ++q) s0 += sl.sf[q] * phi[(size_t)q * 4 * NP];
+                    bout[row] = (float)((s0 + s1) + (s2 + s3));
+                }
+            }
+        }
 #pragma unroll
         for (int ti = 0; ti < TMV; ++ti)
 #pragma unroll
@@ -251,7 +275,7 @@ struct K32P {
                     const int row = a0 + ti * 16 + 4 * kg + r;
                     if (row < N && col < N)
                         Aout[(size_t)row * N + col] = acc[ti][tj][r] * unscale;
-                    else if (row < N && col == N)
+                    else if (LC::on && row < N && col == N)
                         bout[row] = acc[ti][tj][r] * unscale;
                 }
             }
