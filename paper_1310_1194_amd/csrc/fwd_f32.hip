@@ -29,9 +29,9 @@ const FwdVariant v6[] = {
     FEINT_K4S(6, float, 13, 1, 8, 2),
     FEINT_K4U(6, float, 13, 2, 1)};
 const FwdVariant v7[] = {
-    FEINT_K4S(7, float, 6, 6, 8, 1),
-    FEINT_K4S(7, float, 6, 3, 8, 1),
-    FEINT_K4U(7, float, 6, 6, 1)};
+    FEINT_K4U(7, float, 9, 6, 1),
+    FEINT_K4U(7, float, 9, 3, 1),
+    FEINT_K4U(7, float, 6, 3, 1)};
 }  // namespace
 
 #define FEINT_N(a) (int)(sizeof(a) / sizeof(a[0]))

@@ -29,9 +29,9 @@ const FwdVariant v6[] = {
     FEINT_K4S(6, double, 13, 1, 4, 1),
     FEINT_K4U(6, double, 13, 1, 2)};
 const FwdVariant v7[] = {
-    FEINT_K4S(7, double, 6, 1, 4, 1),
-    FEINT_K4S(7, double, 3, 2, 4, 1),
-    FEINT_K4U(7, double, 6, 1, 1)};
+    FEINT_K4U(7, double, 6, 2, 1),
+    FEINT_K4U(7, double, 9, 2, 1),
+    FEINT_K4U(7, double, 9, 1, 1)};
 }  // namespace
 
 #define FEINT_N(a) (int)(sizeof(a) / sizeof(a[0]))

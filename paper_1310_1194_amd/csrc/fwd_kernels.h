@@ -126,30 +126,43 @@ struct K4 {
                     }
                 }
             }
+            // The table operands of point qq + 1 (the four B rows of the
+            // lane's columns and the A fragments) are loaded while point qq is
+            // contracted.
+            auto fetch = [&](int qq, T (&bpv)[TNV][4], T (&afv)[TMV]) {
+                const T *Bq = Bt + (size_t)(qc + qq) * 4 * NP;
+#pragma unroll
+                for (int tj = 0; tj < TNV; ++tj)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) bpv[tj][r] = Bq[r * NP + b0 + tj * 16 + i16];
+#pragma unroll
+                for (int ti = 0; ti < TMV; ++ti) afv[ti] = Bq[kg * NP + a0 + ti * 16 + i16];
+            };
+            T bpc[TNV][4], afc[TMV];
+            fetch(0, bpc, afc);
             for (int qq = 0; qq < cnt; ++qq) {
-                const int q = qc + qq;
+                T bpn[TNV][4], afn[TMV];
+                fetch(qq + 1 < cnt ? qq + 1 : qq, bpn, afn);
                 const T w0 = sl.W[qq][4 * kg + 0], w1 = sl.W[qq][4 * kg + 1];
                 const T w2 = sl.W[qq][4 * kg + 2], w3 = sl.W[qq][4 * kg + 3];
-                const T *Bq = Bt + (size_t)q * 4 * NP;
-                T yf[TNV], af[TMV];
+                T yf[TNV];
 #pragma unroll
                 for (int tj = 0; tj < TNV; ++tj) {
-                    {
-                        const T *bp = Bq + b0 + tj * 16 + i16;
-                        yf[tj] = w0 * bp[0] + w1 * bp[NP] + w2 * bp[2 * NP] + w3 * bp[3 * NP];
-                    }
+                    yf[tj] = w0 * bpc[tj][0] + w1 * bpc[tj][1] + w2 * bpc[tj][2] + w3 * bpc[tj][3];
                     if (LC::on && b0 + tj * 16 == LC::tile0 && i16 == LC::lane)   // load-vector column
                         yf[tj] = kg == 0 ? (T)sl.sf[qq] : (T)0;
-                }
-#pragma unroll
-                for (int ti = 0; ti < TMV; ++ti) {
-                    af[ti] = Bq[kg * NP + a0 + ti * 16 + i16];
                 }
 #pragma unroll
                 for (int ti = 0; ti < TMV; ++ti)
 #pragma unroll
                     for (int tj = 0; tj < TNV; ++tj)
-                        acc[ti][tj] = mfma4(af[ti], yf[tj], acc[ti][tj]);
+                        acc[ti][tj] = mfma4(afc[ti], yf[tj], acc[ti][tj]);
+#pragma unroll
+                for (int tj = 0; tj < TNV; ++tj)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) bpc[tj][r] = bpn[tj][r];
+#pragma unroll
+                for (int ti = 0; ti < TMV; ++ti) afc[ti] = afn[ti];
             }
             wave_sync();
         }
