@@ -187,8 +187,9 @@ int feint_mixed_tile_get(const feint_mixed_plan *plan);
 feint_status feint_mixed_tile_set(feint_mixed_plan *plan, int tile);
 /* Describe tile set `tile` into buf: the per-degree shapes for p = 1..6,
    comma-separated, each "TMxTN" (16x16 MFMA tiles per wave) or "vL"
-   (vector-ALU kernel, L lanes per element).  INVALID_ARG for a null plan or
-   buffer or an index out of range. */
+   (vector-ALU kernel, L lanes per element), followed by " w1" when the set
+   is compiled for one wave per SIMD.  INVALID_ARG for a null plan or buffer
+   or an index out of range. */
 feint_status feint_mixed_tile_describe(const feint_mixed_plan *plan, int tile, char *buf, size_t len);
 void feint_mixed_plan_destroy(feint_mixed_plan *plan);
 

@@ -23,11 +23,19 @@ const FwdVariant v4[] = {
 const FwdVariant v5[] = {
     FEINT_K4S(5, float, 8, 4, 8, 1),
     FEINT_K4S(5, float, 8, 2, 8, 2),
-    FEINT_K4U(5, float, 8, 2, 1)};
+    FEINT_K4U(5, float, 8, 2, 1),
+    FEINT_K4U(5, float, 8, 4, 1),
+    FEINT_K4U(5, float, 8, 4, 2),
+    FEINT_K4U(5, float, 8, 8, 1),
+    FEINT_K4U(5, float, 4, 4, 2)};
 const FwdVariant v6[] = {
     FEINT_K4S(6, float, 13, 2, 8, 1),
     FEINT_K4S(6, float, 13, 1, 8, 2),
-    FEINT_K4U(6, float, 13, 2, 1)};
+    FEINT_K4U(6, float, 13, 2, 1),
+    FEINT_K4U(6, float, 13, 4, 1),
+    FEINT_K4U(6, float, 13, 3, 2),
+    FEINT_K4U(6, float, 13, 2, 2),
+    FEINT_K4U(6, float, 7, 4, 2)};
 const FwdVariant v7[] = {
     FEINT_K4U(7, float, 9, 6, 1),
     FEINT_K4U(7, float, 9, 3, 1),
