@@ -139,6 +139,44 @@ def adjoint(p, coords, D, beta, c, f, G, g, n1=0):
     return dX, dD, db, dc, df, Le
 
 
+def assemble(dofs, ndof, A, b):
+    """Global assembly (Sec. 2: the element matrices are summed into the global
+    matrix through the element-to-global numbering), plain FP64.
+
+    Every element contributes A_e[a, b] to entry (dofs[e, a], dofs[e, b]) and
+    b_e[a] to rhs[dofs[e, a]].  Entries are grouped by a stable sort of their
+    (row, col) key, so each global entry is the sum of its contributions in
+    element order.  Returns (row_ptr [ndof+1], cols [nnz], vals [nnz], rhs
+    [ndof]) with columns ascending within a row."""
+    dofs = np.asarray(dofs, dtype=np.int64)
+    ne, n = dofs.shape
+    A = np.asarray(A, dtype=np.float64).reshape(ne, n, n)
+    b = np.asarray(b, dtype=np.float64).reshape(ne, n)
+    rows = np.repeat(dofs[:, :, None], n, axis=2).ravel()
+    cols = np.repeat(dofs[:, None, :], n, axis=1).ravel()
+    key = rows * ndof + cols
+    order = np.argsort(key, kind="stable")
+    key_s = key[order]
+    vals_s = A.ravel()[order]
+    start = np.flatnonzero(np.r_[True, key_s[1:] != key_s[:-1]])
+    uniq = key_s[start]
+    vals = np.empty(len(start))
+    for m in range(len(start)):                      # contributions in element order
+        stop = start[m + 1] if m + 1 < len(start) else len(key_s)
+        acc = 0.0
+        for v in vals_s[start[m]:stop]:
+            acc += v
+        vals[m] = acc
+    r = uniq // ndof
+    row_ptr = np.zeros(ndof + 1, dtype=np.int64)
+    np.add.at(row_ptr, r + 1, 1)
+    row_ptr = np.cumsum(row_ptr)
+    rhs = np.zeros(ndof)
+    for e in range(ne):                              # dofs of one element are distinct
+        rhs[dofs[e]] += b[e]
+    return row_ptr, (uniq % ndof).astype(np.int64), vals, rhs
+
+
 def set_threads(nt: int):
     lib().oracle_set_threads(int(nt))
 

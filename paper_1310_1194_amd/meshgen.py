@@ -166,6 +166,44 @@ def adjoint_seeds_device(batch: Batch, p: int, seed: int, dtype=None, device="cu
     return G, g, sample
 
 
+def dof_map(nx: int, ny: int, nz: int, p: int):
+    """Global numbering of the degree-p nodal degrees of freedom of the
+    structured prism mesh (mesh topology only; no integration arithmetic).
+
+    Local node a = k * ntri + t of an element sits at reference position
+    (xi1, xi2) = (i/p, j/p) of the triangle lattice (t runs over j outer, i
+    inner, i + j <= p) and at the k-th of the p+1 ascending Gauss-Lobatto
+    nodes in zeta.  On the unperturbed grid those nodes are points of the
+    lattice (I, J, K), I in [0, p nx], J in [0, p ny], K in [0, p nz]:
+      triangle T0 = (v00, v10, v11):  I = p i + i' + j',  J = p j + j',
+      triangle T1 = (v00, v11, v01):  I = p i + i',       J = p j + i' + j',
+      K = p k + k'.
+    Global id = (K (p ny + 1) + J) (p nx + 1) + I.  Returns (dofs [ne, n]
+    int32, number of global degrees of freedom)."""
+    tri = [(i, j) for j in range(p + 1) for i in range(p + 1 - j)]
+    ntri = len(tri)
+    n = ntri * (p + 1)
+    NI, NJ, NK = p * nx + 1, p * ny + 1, p * nz + 1
+    ndof = NI * NJ * NK
+    assert ndof < 2 ** 31
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    k = k.ravel(); j = j.ravel(); i = i.ravel()
+    ti = np.array([t[0] for t in tri]); tj = np.array([t[1] for t in tri])
+    kk = np.arange(p + 1)
+    dofs = np.empty((nx * ny * nz, 2, n), dtype=np.int64)
+    for s in range(2):
+        if s == 0:
+            I = p * i[:, None] + (ti + tj)[None, :]
+            J = p * j[:, None] + tj[None, :]
+        else:
+            I = p * i[:, None] + ti[None, :]
+            J = p * j[:, None] + (ti + tj)[None, :]
+        K = p * k[:, None, None] + kk[None, :, None]                    # [e, k', 1]
+        g = (K * NJ + J[:, None, :]) * NI + I[:, None, :]              # [e, k', t]
+        dofs[:, s, :] = g.reshape(-1, n)
+    return np.ascontiguousarray(dofs.reshape(-1, n).astype(np.int32)), int(ndof)
+
+
 # The workloads of the paper-derived configurations (mesh sizes and amplitudes).
 WORKLOADS = {
     "p1_4096":      dict(nx=16, ny=16, nz=8,  amp=0.2, seed=0, p=1),
