@@ -187,9 +187,8 @@ int feint_mixed_tile_get(const feint_mixed_plan *plan);
 feint_status feint_mixed_tile_set(feint_mixed_plan *plan, int tile);
 /* Describe tile set `tile` into buf: the per-degree shapes for p = 1..6,
    comma-separated, each "TMxTN" (16x16 MFMA tiles per wave) or "vL"
-   (vector-ALU kernel, L lanes per element), followed by " w1" when the set
-   is compiled for one wave per SIMD.  INVALID_ARG for a null plan or buffer
-   or an index out of range. */
+   (vector-ALU kernel, L lanes per element).  INVALID_ARG for a null plan or
+   buffer or an index out of range. */
 feint_status feint_mixed_tile_describe(const feint_mixed_plan *plan, int tile, char *buf, size_t len);
 void feint_mixed_plan_destroy(feint_mixed_plan *plan);
 
@@ -213,6 +212,44 @@ feint_status feint_tile_set(int p, feint_form form, int tile);
 feint_status feint_tile_describe(int p, feint_form form, int tile, char *buf, size_t len);
 feint_status feint_autotune(const feint_elements *el, int p, feint_form form,
                             void *A, void *b, int reps, double *best_ms, void *stream);
+
+/* ---- Global assembly (Sec. 2) ----------------------------------------------
+   The element matrices and load vectors of one degree are summed into a CSR
+   matrix and a right-hand side through the element-to-global dof map.
+   Elements are coloured so that no two elements of a colour share a global
+   dof; each colour is one launch and adds its entries without atomics.
+
+   feint_asm_plan_create: dofs is a HOST array [ne][n] (int32, n = nshp(p)):
+   the global dof of every local shape function, in the library's local
+   order (a = k*ntri + t: triangle lattice node t = (i/p, j/p), j outer, i
+   inner; Gauss-Lobatto node k in zeta, ascending).  ndof bounds the ids
+   (0 <= dof < ndof < 2^31).  Builds, on the host, the CSR pattern (row i
+   holds every dof sharing an element with i, columns ascending), the
+   offsets of each element entry inside its row and a greedy colouring, and
+   uploads them to the current device (plan-owned memory).  INVALID_ARG for
+   null pointers, ne <= 0, an n that is no prism size, ids out of range or a
+   dof repeated within an element; TOO_LARGE if a row exceeds 65535 columns.
+
+   feint_assemble: A [ne][n][n] and b [ne][n] as produced by feint_integrate
+   with `form` (double for FEINT_FP64, float otherwise), values [nnz] and rhs
+   [ndof] of the same dtype; all device pointers owned by the caller.
+   values and rhs are cleared first unless `accumulate` is nonzero.  Entry
+   (i, j) receives the contributions of the elements in colour order.
+   Asynchronous on `stream`; the plan must outlive the work it enqueues. */
+typedef struct feint_asm_plan feint_asm_plan;
+feint_status feint_asm_plan_create(const int32_t *dofs, int64_t ne, int n, int64_t ndof,
+                                   feint_asm_plan **plan);
+/* nnz of the pattern and number of colours (either output nullable). */
+feint_status feint_asm_plan_info(const feint_asm_plan *plan, int64_t *nnz, int *ncolors);
+/* Copy the pattern into caller device buffers row_ptr [ndof+1] (int64) and
+   col_idx [nnz] (int32), asynchronously on `stream`. */
+feint_status feint_asm_plan_pattern(const feint_asm_plan *plan, int64_t *row_ptr, int32_t *col_idx,
+                                    void *stream);
+/* Colour of every element into a host array [ne]. */
+feint_status feint_asm_plan_colors(const feint_asm_plan *plan, int32_t *color_of);
+feint_status feint_assemble(feint_asm_plan *plan, feint_form form, const void *A, const void *b,
+                            void *values, void *rhs, int accumulate, void *stream);
+void feint_asm_plan_destroy(feint_asm_plan *plan);
 
 const char *feint_status_string(feint_status s);
 /* Last HIP error text seen by the library on this thread ("" if none). */

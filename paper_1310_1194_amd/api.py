@@ -270,3 +270,60 @@ class MixedPlan:
         buf = ctypes.create_string_buffer(64)
         check("feint_mixed_tile_describe", lib().feint_mixed_tile_describe(self._h, int(t), buf, 64))
         return buf.value.decode()
+
+
+class AsmPlan:
+    """Global assembly (CSR) of one degree's element matrices: pattern,
+    colouring and position map built once from a host dof map."""
+
+    def __init__(self, dofs, ndof: int):
+        import numpy as np
+        d = np.ascontiguousarray(dofs, dtype=np.int32)
+        ne, n = d.shape
+        self._h = ctypes.c_void_p()
+        check("feint_asm_plan_create", lib().feint_asm_plan_create(d.ctypes.data_as(ctypes.c_void_p), int(ne),
+                                                                   int(n), int(ndof), ctypes.byref(self._h)))
+        self.ne, self.n, self.ndof = int(ne), int(n), int(ndof)
+        nnz = ctypes.c_int64(0)
+        nc = ctypes.c_int(0)
+        check("feint_asm_plan_info", lib().feint_asm_plan_info(self._h, ctypes.byref(nnz), ctypes.byref(nc)))
+        self.nnz, self.ncolors = int(nnz.value), int(nc.value)
+
+    def pattern(self):
+        """(row_ptr int64 [ndof+1], col_idx int32 [nnz]) as device tensors."""
+        row_ptr = torch.empty(self.ndof + 1, dtype=torch.int64, device="cuda")
+        col_idx = torch.empty(self.nnz, dtype=torch.int32, device="cuda")
+        check("feint_asm_plan_pattern", lib().feint_asm_plan_pattern(self._h, _ptr(row_ptr), _ptr(col_idx),
+                                                                     _stream()))
+        return row_ptr, col_idx
+
+    def colors(self):
+        import numpy as np
+        out = np.empty(self.ne, dtype=np.int32)
+        check("feint_asm_plan_colors", lib().feint_asm_plan_colors(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def assemble(self, A, b, form: str = "fp64", values=None, rhs=None, accumulate: bool = False):
+        """values [nnz], rhs [ndof] in the dtype of A (allocated when not given)."""
+        dt = out_dtype(form)
+        if A.dtype != dt or b.dtype != dt or A.numel() != self.ne * self.n * self.n or b.numel() != self.ne * self.n:
+            raise ValueError("A, b do not match the plan and form")
+        A = A.contiguous(); b = b.contiguous()
+        if values is None:
+            values = torch.empty(self.nnz, dtype=dt, device=A.device)
+        if rhs is None:
+            rhs = torch.empty(self.ndof, dtype=dt, device=A.device)
+        check("feint_assemble", lib().feint_assemble(self._h, FORMS[form], _ptr(A), _ptr(b), _ptr(values), _ptr(rhs),
+                                                     1 if accumulate else 0, _stream()))
+        return values, rhs
+
+    def close(self):
+        if self._h:
+            lib().feint_asm_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -220,10 +220,10 @@ template <class K, class... R> struct MaxSlice<K, R...> {
                                                                                : MaxSlice<R...>::value;
 };
 
-// MINW: waves per SIMD the register allocation must allow (2 for the
-// smaller tile shapes, 1 where a degree's tile needs the whole register file).
-template <int MINW, class K1, class K2, class K3, class K4_, class K5, class K6>
-__global__ __launch_bounds__(256, MINW) void k_persist(MixedParams mp) {
+// One wave per SIMD: the per-degree device functions are called, not inlined,
+// and the largest tiles need the whole register file.
+template <class K1, class K2, class K3, class K4_, class K5, class K6>
+__global__ __launch_bounds__(256, 1) void k_persist(MixedParams mp) {
     constexpr size_t SL = MaxSlice<K1, K2, K3, K4_, K5, K6>::value;
     __shared__ __attribute__((aligned(16))) char sm[4 * SL];
     const int wave = wave_uniform(threadIdx.x >> 6);
@@ -261,10 +261,10 @@ struct MixVariant {
     const char *desc;
 };
 
-template <class K1, class K2, class K3, class K4_, class K5, class K6, int MINW = 2>
+template <class K1, class K2, class K3, class K4_, class K5, class K6>
 MixVariant make_variant(const char *desc) {
     MixVariant v;
-    v.kernel = (const void *)&k_persist<MINW, K1, K2, K3, K4_, K5, K6>;
+    v.kernel = (const void *)&k_persist<K1, K2, K3, K4_, K5, K6>;
     std::memset(&v.sz, 0, sizeof v.sz);
     const int items[7] = {0, K1::NBLK, K2::NBLK, K3::NBLK, K4_::NBLK, K5::NBLK, K6::NBLK};
     const int epi[7] = {0, K1::EPI, K2::EPI, K3::EPI, K4_::EPI, K5::EPI, K6::EPI};
@@ -280,16 +280,14 @@ MixVariant make_variant(const char *desc) {
 
 const MixVariant *mix_variants(int form, int *count) {
     // p = 1, 2 on the vector ALUs (v8: 8 lanes per element, v18: 18), MFMA tiles above;
-    // "w1" sets are compiled for one wave per SIMD (the whole register file for
-    // the largest tiles); the last set of each form keeps MFMA tiles at every
-    // degree for comparison
+    // the last set of each form keeps MFMA tiles at every degree for comparison
     static const MixVariant f32[] = {
         make_variant<KV<1, float, 8>, KV<2, float, 18>, K4<3, float, 3, 3>, K4<4, float, 5, 5>,
-                     K4<5, float, 8, 8>, K4<6, float, 13, 5>, 1>("v8,v18,3x3,5x5,8x8,13x5 w1"),
+                     K4<5, float, 8, 8>, K4<6, float, 13, 5>>("v8,v18,3x3,5x5,8x8,13x5"),
         make_variant<KV<1, float, 8>, KV<2, float, 18>, K4<3, float, 3, 3>, K4<4, float, 5, 5>,
-                     K4<5, float, 8, 8>, K4<6, float, 13, 4>, 1>("v8,v18,3x3,5x5,8x8,13x4 w1"),
+                     K4<5, float, 8, 8>, K4<6, float, 13, 4>>("v8,v18,3x3,5x5,8x8,13x4"),
         make_variant<KV<1, float, 8>, KV<2, float, 18>, K4<3, float, 3, 3>, K4<4, float, 5, 5>,
-                     K4<5, float, 8, 8>, K4<6, float, 13, 3>, 1>("v8,v18,3x3,5x5,8x8,13x3 w1"),
+                     K4<5, float, 8, 8>, K4<6, float, 13, 3>>("v8,v18,3x3,5x5,8x8,13x3"),
         make_variant<KV<1, float, 8>, KV<2, float, 18>, K4<3, float, 3, 3>, K4<4, float, 5, 3>,
                      K4<5, float, 8, 2>, K4<6, float, 13, 1>>("v8,v18,3x3,5x3,8x2,13x1"),
         make_variant<KV<1, float, 8>, KV<2, float, 18>, K4<3, float, 3, 3>, K4<4, float, 5, 5>,
@@ -299,7 +297,7 @@ const MixVariant *mix_variants(int form, int *count) {
     };
     static const MixVariant f64[] = {
         make_variant<KV<1, double, 8>, KV<2, double, 18>, K4<3, double, 3, 3>, K4<4, double, 5, 3>,
-                     K4<5, double, 8, 4>, K4<6, double, 13, 2>, 1>("v8,v18,3x3,5x3,8x4,13x2 w1"),
+                     K4<5, double, 8, 4>, K4<6, double, 13, 2>>("v8,v18,3x3,5x3,8x4,13x2"),
         make_variant<KV<1, double, 8>, KV<2, double, 18>, K4<3, double, 3, 3>, K4<4, double, 5, 1>,
                      K4<5, double, 8, 1>, K4<6, double, 13, 1>>("v8,v18,3x3,5x1,8x1,13x1"),
         make_variant<KV<1, double, 8>, KV<2, double, 18>, K4<3, double, 3, 1>, K4<4, double, 5, 2>,

@@ -24,7 +24,8 @@ EXPORTS = (
     "feint_mixed_plan_destroy", "feint_mixed_autotune", "feint_mixed_tile_count", "feint_mixed_tile_get",
     "feint_mixed_tile_set", "feint_mixed_tile_describe", "feint_tile_count", "feint_tile_get", "feint_tile_set",
     "feint_tile_describe", "feint_autotune", "feint_status_string", "feint_last_error",
-    "feint_shutdown",
+    "feint_shutdown", "feint_asm_plan_create", "feint_asm_plan_info", "feint_asm_plan_pattern",
+    "feint_asm_plan_colors", "feint_assemble", "feint_asm_plan_destroy",
 )
 
 
@@ -89,6 +90,12 @@ def lib() -> ctypes.CDLL:
             "feint_status_string": (ctypes.c_char_p, [_i]),
             "feint_last_error": (ctypes.c_char_p, []),
             "feint_shutdown": (None, []),
+            "feint_asm_plan_create": (_i, [_vp, _i64, _i, _i64, ctypes.POINTER(_vp)]),
+            "feint_asm_plan_info": (_i, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i)]),
+            "feint_asm_plan_pattern": (_i, [_vp, _vp, _vp, _vp]),
+            "feint_asm_plan_colors": (_i, [_vp, _vp]),
+            "feint_assemble": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _i, _vp]),
+            "feint_asm_plan_destroy": (None, [_vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)

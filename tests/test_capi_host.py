@@ -97,3 +97,22 @@ def test_status_strings():
     L = native.lib()
     for code in native.STATUS:
         assert L.feint_status_string(code).decode() == native.STATUS[code]
+
+
+def test_assembly_plan_validation():
+    """Host-detectable errors of the assembly plan come back before any device work."""
+    L = native.lib()
+    import numpy as np
+    h = ctypes.c_void_p()
+    d = np.zeros((2, 6), dtype=np.int32)
+    d[0] = np.arange(6); d[1] = np.arange(3, 9)
+    ptr = d.ctypes.data_as(ctypes.c_void_p)
+    assert L.feint_asm_plan_create(None, 2, 6, 9, ctypes.byref(h)) == -1
+    assert L.feint_asm_plan_create(ptr, 0, 6, 9, ctypes.byref(h)) == -1
+    assert L.feint_asm_plan_create(ptr, 2, 7, 9, ctypes.byref(h)) == -1        # no prism has 7 shape functions
+    assert L.feint_asm_plan_create(ptr, 2, 6, 8, ctypes.byref(h)) == -1        # dof 8 out of range
+    d[1, 0] = d[1, 1]
+    assert L.feint_asm_plan_create(ptr, 2, 6, 9, ctypes.byref(h)) == -1        # dof repeated in an element
+    assert L.feint_asm_plan_create(ptr, 2, 6, 9, None) == -1
+    assert L.feint_asm_plan_info(None, None, None) == -1
+    assert L.feint_assemble(None, 0, None, None, None, None, 0, None) == -1
