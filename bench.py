@@ -117,7 +117,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--mode", default="forward", choices=["forward", "adjoint", "mixed"])
+    ap.add_argument("--mode", default="forward", choices=["forward", "adjoint", "mixed", "assemble"])
     ap.add_argument("--workload", default=None)
     ap.add_argument("--forms", default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (CPU baseline and errors)")
@@ -136,6 +136,8 @@ def main():
         return bench_adjoint(args)
     if args.mode == "mixed":
         return bench_mixed(args)
+    if args.mode == "assemble":
+        return bench_assemble(args)
     return bench_forward(args)
 
 
@@ -415,6 +417,67 @@ def bench_mixed(args):
                          "unit": "TFLOP/s", "frac": flops / (ms_p * 1e-3) / 1e12 / peak, "traffic": None,
                          "flops_per_launch": flops, "alg_bytes_per_launch": bytes_},
             "cpu_baseline": cpu}
+    plan.close()
+    print(json.dumps(fmt(line)))
+
+
+def bench_assemble(args):
+    """Global assembly of the p=4 element matrices (CSR, colour by colour):
+    set-up on the host once, then the timed device assembly per form."""
+    import torch
+    import paper_1310_1194_amd as F
+    args.workload = args.workload or "p4_131072"
+    forms = (args.forms or "fp32,fp64").split(",")
+    w = meshgen.WORKLOADS[args.workload]
+    p = w["p"]
+    batch = meshgen.workload(args.workload)
+    ne, n = batch.ne, costmodel.nshp(p)
+    dofs, ndof = meshgen.dof_map(w["nx"], w["ny"], w["nz"], p)
+    t0 = time.perf_counter()
+    plan = F.AsmPlan(dofs, ndof)
+    setup_s = time.perf_counter() - t0
+    print(f"[bench] assembly set-up {setup_s:.1f} s: ndof {ndof}, nnz {plan.nnz}, {plan.ncolors} colours",
+          file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    X = (t(batch.coords), t(batch.D), t(batch.beta), t(batch.c), t(batch.f))
+    res = {}
+    for form in forms:
+        A, b = F.integrate_raw(*X, p, form)
+        es = 8 if form == "fp64" else 4
+        vals = torch.empty(plan.nnz, dtype=A.dtype, device=dev)
+        rhs = torch.empty(ndof, dtype=A.dtype, device=dev)
+        ms, mn, wall = timed(lambda: plan.assemble(A, b, form, values=vals, rhs=rhs), args.steps, args.warmup)
+        # algorithmic bytes: element matrices, vectors and position map read once, the
+        # global values and rhs cleared and written once, dof map and row starts read
+        alg = ne * n * n * (es + 2) + ne * n * (es + 4) + 2 * (plan.nnz + ndof) * es + (ndof + 1) * 8
+        res[form] = dict(kernel_ms_mean=ms, kernel_ms_min=mn, ms_per_step=wall, elements_per_s=ne / (ms * 1e-3),
+                         alg_bytes=alg, gbs=alg / (ms * 1e-3) / 1e9)
+        print(f"[bench] assembly {form}: {ms:.3f} ms, {alg / (ms * 1e-3) / 1e9:.0f} GB/s algorithmic",
+              file=sys.stderr, flush=True)
+        del A, b, vals, rhs
+        torch.cuda.empty_cache()
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        m = 256                      # the oracle's assembly of the first m elements (their own system)
+        part = batch.subset(np.arange(m))
+        Ar, br, _ = oracle.integrate(p, part.coords, part.D, part.beta, part.c, part.f)
+        t0 = time.perf_counter()
+        oracle.assemble(dofs[:m], ndof, Ar, br)
+        spent = time.perf_counter() - t0
+        cpu = {"value": m / spent, "unit": "elements/s", "cores": 1, "kind": "oracle",
+               "sample": f"assembly of the first {m} elements' matrices ({spent:.1f} s, FP64, one core)"}
+    h = res[forms[0]]
+    line = {"metric": "global assembly elements/s (CSR, colour by colour)", "value": h["elements_per_s"],
+            "unit": "elements/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": h["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": forms[0], "data": "synthetic (seeded mesh; element matrices from the forward pass)",
+            "config": {"workload": args.workload, "p": p, "ne": ne, "ndof": ndof, "nnz": plan.nnz,
+                       "colours": plan.ncolors, "setup_s": setup_s},
+            "roofline": {"bound": "hbm", "achieved": h["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": h["gbs"] / HBM_PEAK_GBS, "traffic": None},
+            "cpu_baseline": cpu, "forms": fmt(res)}
     plan.close()
     print(json.dumps(fmt(line)))
 
