@@ -47,6 +47,7 @@ def lib():
         L.oracle_basis.argtypes = [ctypes.c_int, _dp, _dp, _dp]
         L.oracle_geometry.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp]
         L.oracle_integrate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [_dp] * 8 + [_ip]
+        L.oracle_integrate_fields.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [_dp] * 8 + [_ip]
         L.oracle_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [_dp] * 13
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_max_threads.restype = ctypes.c_int
@@ -121,6 +122,25 @@ def integrate(p, coords, D, beta, c, f, n1=0, want_xq=False):
     xq = np.zeros((ne, nqq, 3)) if want_xq else None
     rc = lib().oracle_integrate(p, n1, ne, _p(coords), _p(D), _p(beta), _p(c), _p(f),
                                 _p(A), _p(b), _p(xq), flags.ctypes.data_as(_ip))
+    assert rc == 0, rc
+    if want_xq:
+        return A, b, flags, xq
+    return A, b, flags
+
+
+def integrate_fields(p, coords, Dv, betav, cv, fv, n1=0, want_xq=False):
+    """Coefficients given at the six vertices (Dv [ne,6,3,3], betav [ne,6,3],
+    cv [ne,6], fv [ne,6]) and evaluated at each point with the geometry shape
+    functions.  Returns A, b, flags (and xq)."""
+    coords = _c(coords); Dv = _c(Dv); betav = _c(betav); cv = _c(cv); fv = _c(fv)
+    ne = coords.shape[0]
+    n = nshp(p)
+    nqq = (n1 if n1 > 0 else p + 1) ** 3
+    A = np.zeros((ne, n, n)); b = np.zeros((ne, n))
+    flags = np.zeros(ne, dtype=np.int32)
+    xq = np.zeros((ne, nqq, 3)) if want_xq else None
+    rc = lib().oracle_integrate_fields(p, n1, ne, _p(coords), _p(Dv), _p(betav), _p(cv), _p(fv),
+                                       _p(A), _p(b), _p(xq), flags.ctypes.data_as(_ip))
     assert rc == 0, rc
     if want_xq:
         return A, b, flags, xq

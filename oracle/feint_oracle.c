@@ -337,9 +337,14 @@ int oracle_max_threads(void)
    c [ne], f [ne]  ->  A [ne][n][n] (row a = test function), b [ne][n],
    optional xq [ne][nq][3], optional flags [ne] (1 = some det J <= 0).
    n1 = points per direction of the collapsed rule (0 -> p+1). */
-int oracle_integrate(int p, int n1, int64_t ne, const double *coords, const double *D,
-                     const double *beta, const double *c, const double *f,
-                     double *A, double *b, double *xq, int32_t *flags)
+/* Element loop of Algorithm 1 with the CDR integrand.  Coefficients are
+   constant per element (Dv etc. hold one value per element, nv = 1) or
+   given at the six vertices (nv = 6) and evaluated at each point with the
+   geometry shape functions, D(x_q) = sum_a N_a(xi_q) D_a (the coefficient
+   fields live in the same bilinear space as the geometry). */
+static int integrate_core(int p, int n1, int64_t ne, int nv, const double *coords, const double *Dv,
+                          const double *betav, const double *cv, const double *fv,
+                          double *A, double *b, double *xq, int32_t *flags)
 {
     rule_tables T;
     if (ne < 0) return -1;
@@ -349,7 +354,6 @@ int oracle_integrate(int p, int n1, int64_t ne, const double *coords, const doub
 #pragma omp parallel for schedule(static)
     for (e = 0; e < ne; ++e) {
         const double *X = coords + 18 * e;          /* step 2: geometry data */
-        const double *De = D + 9 * e, *be = beta + 3 * e;
         double *Ae = A + (size_t)e * n * n, *bv = b + (size_t)e * n;
         double *gphys = (double *)malloc(sizeof(double) * 3 * n);
         double *Dg = (double *)malloc(sizeof(double) * 3 * n);
@@ -362,6 +366,26 @@ int oracle_integrate(int p, int n1, int64_t ne, const double *coords, const doub
             double J[9], K[9], det, x[3];
             bad |= oracle_geometry(X, T.pts + 3 * q, J, &det, K, x);   /* step 7 */
             if (xq) for (int d = 0; d < 3; ++d) xq[((size_t)e * nqp + q) * 3 + d] = x[d];
+            /* coefficients at the point */
+            double De[9], be[3], ce, fe;
+            if (nv == 1) {
+                for (int m = 0; m < 9; ++m) De[m] = Dv[9 * e + m];
+                for (int m = 0; m < 3; ++m) be[m] = betav[3 * e + m];
+                ce = cv[e];
+                fe = fv[e];
+            } else {
+                double N[6], dN[18];
+                geom_shape(T.pts + 3 * q, N, dN);
+                for (int m = 0; m < 9; ++m) De[m] = 0.0;
+                for (int m = 0; m < 3; ++m) be[m] = 0.0;
+                ce = fe = 0.0;
+                for (int a = 0; a < 6; ++a) {
+                    for (int m = 0; m < 9; ++m) De[m] += N[a] * Dv[(6 * e + a) * 9 + m];
+                    for (int m = 0; m < 3; ++m) be[m] += N[a] * betav[(6 * e + a) * 3 + m];
+                    ce += N[a] * cv[6 * e + a];
+                    fe += N[a] * fv[6 * e + a];
+                }
+            }
             double wd = T.w[q] * det;
             for (int a = 0; a < n; ++a) {         /* step 8: grad phi = J^{-T} ref grad */
                 for (int d = 0; d < 3; ++d) {
@@ -382,10 +406,10 @@ int oracle_integrate(int p, int n1, int64_t ne, const double *coords, const doub
                     const double *Dgb = Dg + 3 * bb;
                     double diff = ga[0] * Dgb[0] + ga[1] * Dgb[1] + ga[2] * Dgb[2];
                     double conv = phi[a] * bg[bb];
-                    double mass = c[e] * phi[a] * phi[bb];
+                    double mass = ce * phi[a] * phi[bb];
                     Ae[(size_t)a * n + bb] += wd * (diff + conv + mass);
                 }
-                bv[a] += wd * f[e] * phi[a];
+                bv[a] += wd * fe * phi[a];
             }
         }
         if (flags) flags[e] = bad;
@@ -393,6 +417,22 @@ int oracle_integrate(int p, int n1, int64_t ne, const double *coords, const doub
     }
     free_tables(&T);
     return 0;
+}
+
+int oracle_integrate(int p, int n1, int64_t ne, const double *coords, const double *D,
+                     const double *beta, const double *c, const double *f,
+                     double *A, double *b, double *xq, int32_t *flags)
+{
+    return integrate_core(p, n1, ne, 1, coords, D, beta, c, f, A, b, xq, flags);
+}
+
+/* Coefficients given at the six vertices: Dv [ne][6][9], betav [ne][6][3],
+   cv [ne][6], fv [ne][6]. */
+int oracle_integrate_fields(int p, int n1, int64_t ne, const double *coords, const double *Dv,
+                            const double *betav, const double *cv, const double *fv,
+                            double *A, double *b, double *xq, int32_t *flags)
+{
+    return integrate_core(p, n1, ne, 6, coords, Dv, betav, cv, fv, A, b, xq, flags);
 }
 
 /* ---------------------------------------------------------------------- */

@@ -521,3 +521,62 @@ def test_mesh_is_seeded_and_perturbs_interior_only():
     assert on_boundary.sum() >= 2 * 25   # top and bottom faces at least
     assert np.all(np.abs(b1.D - np.transpose(b1.D, (0, 2, 1))) == 0)
     assert np.all(np.linalg.eigvalsh(b1.D) >= 1 - 1e-12)
+
+
+# ---- spatially varying coefficients (vertex fields) -------------------------
+
+def _vertex_fields(batch):
+    """Per-vertex copies of the element constants (the constant field)."""
+    rep = lambda a: np.repeat(a[:, None], 6, axis=1)
+    return rep(batch.D), rep(batch.beta), rep(batch.c), rep(batch.f)
+
+
+def test_fields_constant_reduce_to_element_constants():
+    from paper_1310_1194_amd import meshgen
+    for p in (1, 3):
+        batch = meshgen.make_batch(2, 2, 1, amp=0.25, seed=50 + p)
+        A0, b0, _ = oracle.integrate(p, batch.coords, batch.D, batch.beta, batch.c, batch.f)
+        A1, b1, _ = oracle.integrate_fields(p, batch.coords, *_vertex_fields(batch))
+        assert np.abs(A1 - A0).max() <= 1e-14 * np.abs(A0).max()
+        assert np.abs(b1 - b0).max() <= 1e-14 * np.abs(b0).max()
+
+
+def test_fields_affine_reaction_and_source_integrate_the_field():
+    """c(x), f(x) affine, given by their vertex values: the mass sum and the
+    load sum equal the rule applied to c and f evaluated at the mapped points
+    (geometry only, no coefficient interpolation), which the rule integrates
+    exactly (degree <= 3 per direction at p >= 2)."""
+    from paper_1310_1194_amd import meshgen
+    p = 2
+    batch = meshgen.make_batch(2, 2, 2, amp=0.25, seed=61)
+    ne = batch.ne
+    g_c, c0 = np.array([0.7, -0.4, 1.3]), 0.9
+    g_f, f0 = np.array([-1.1, 0.5, 0.2]), -0.3
+    cv = c0 + batch.coords @ g_c          # [ne, 6]
+    fv = f0 + batch.coords @ g_f
+    Dv = np.zeros((ne, 6, 3, 3)); bv = np.zeros((ne, 6, 3))
+    A, b, _ = oracle.integrate_fields(p, batch.coords, Dv, bv, cv, fv)
+    pts, w = oracle.rule(p + 1)
+    for e in range(ne):
+        sc = sf = 0.0
+        for q in range(len(w)):
+            J, det, K, x = oracle.geometry(batch.coords[e], pts[q])
+            sc += w[q] * det * (c0 + x @ g_c)
+            sf += w[q] * det * (f0 + x @ g_f)
+        assert abs(A[e].sum() - sc) <= 1e-13 * abs(sc) + 1e-16
+        assert abs(b[e].sum() - sf) <= 1e-13 * abs(sf) + 1e-16
+
+
+def test_fields_are_linear():
+    from paper_1310_1194_amd import meshgen
+    p = 2
+    batch = meshgen.make_batch(2, 1, 1, amp=0.2, seed=62)
+    rng = np.random.default_rng(3)
+    ne = batch.ne
+    F1 = [rng.normal(size=(ne, 6, 3, 3)), rng.normal(size=(ne, 6, 3)), rng.normal(size=(ne, 6)), rng.normal(size=(ne, 6))]
+    F2 = [rng.normal(size=a.shape) for a in F1]
+    A1, b1, _ = oracle.integrate_fields(p, batch.coords, *F1)
+    A2, b2, _ = oracle.integrate_fields(p, batch.coords, *F2)
+    A3, b3, _ = oracle.integrate_fields(p, batch.coords, *[2.0 * x - 3.0 * y for x, y in zip(F1, F2)])
+    assert np.abs(A3 - (2 * A1 - 3 * A2)).max() <= 1e-13 * np.abs(A3).max()
+    assert np.abs(b3 - (2 * b1 - 3 * b2)).max() <= 1e-13 * np.abs(b3).max()
