@@ -105,6 +105,25 @@ feint_status feint_integrate(const feint_elements *el, int p, feint_form form,
                              void *A, void *b, double *xq, uint32_t *dev_status,
                              void *stream);
 
+/* Spatially varying coefficients: the same integration with D, beta, c and f
+   given at each element's six vertices and evaluated at every quadrature
+   point with the geometry shape functions, D(x_q) = sum_a N_a(xi_q) D_a
+   (N_a = lambda_a (1-zeta)/2, N_{a+3} = lambda_a (1+zeta)/2; a field in the
+   bilinear space of the geometry, continuous across elements when the
+   vertex values are shared).  Outputs, forms, variants and errors as
+   feint_integrate; all inputs are device pointers, FP64. */
+typedef struct {
+    const double *coords;  /* [ne][6][3] prism vertices */
+    const double *D;       /* [ne][6][3][3] diffusion tensor at each vertex */
+    const double *beta;    /* [ne][6][3] convection vector at each vertex */
+    const double *c;       /* [ne][6] reaction at each vertex */
+    const double *f;       /* [ne][6] source at each vertex */
+    int64_t ne;
+} feint_fields;
+feint_status feint_integrate_fields(const feint_fields *el, int p, feint_form form,
+                                    void *A, void *b, double *xq, uint32_t *dev_status,
+                                    void *stream);
+
 /* Adjoint of feint_integrate: gradients of
        L = sum_e <G_e, A_e> + <g_e, b_e>
    with respect to every element's inputs.  G [ne][n][n] and g [ne][n] have

@@ -81,6 +81,31 @@ def integrate_raw(coords, D, beta, c, f, p: int, form: str = "fp64", *, A=None, 
     return A, b
 
 
+def integrate_fields_raw(coords, Dv, betav, cv, fv, p: int, form: str = "fp64", *, A=None, b=None,
+                         xq=None, status=None):
+    """Forward integration with coefficients given at the six vertices of every
+    element (Dv [ne,6,3,3], betav [ne,6,3], cv [ne,6], fv [ne,6], FP64)."""
+    if form not in FORMS:
+        raise ValueError(f"unknown form {form!r}")
+    ne, n = coords.shape[0], nshp(p)
+    ts = [coords, Dv, betav, cv, fv]
+    sizes = [18, 54, 18, 6, 6]
+    for t, k in zip(ts, sizes):
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != ne * k:
+            raise ValueError("vertex fields must be contiguous float64 of the documented shapes")
+    fl = native.Fields(*[t.data_ptr() for t in ts], ne)
+    dt = out_dtype(form)
+    if A is None:
+        A = torch.empty((ne, n, n), dtype=dt, device=coords.device)
+    if b is None:
+        b = torch.empty((ne, n), dtype=dt, device=coords.device)
+    if A.dtype != dt or b.dtype != dt or A.numel() != ne * n * n or b.numel() != ne * n:
+        raise ValueError("output tensors have the wrong dtype or size")
+    check("feint_integrate_fields", lib().feint_integrate_fields(ctypes.byref(fl), int(p), FORMS[form], _ptr(A),
+                                                                 _ptr(b), _ptr(xq), _ptr(status), _stream()))
+    return A, b
+
+
 def adjoint_raw(coords, D, beta, c, f, G, g, p: int, form: str = "fp64"):
     """Gradients of sum_e <G_e,A_e> + <g_e,b_e>: (dcoords, dD, dbeta, dc, df), FP64."""
     el = elements(coords, D, beta, c, f)

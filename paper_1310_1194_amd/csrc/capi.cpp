@@ -179,6 +179,27 @@ size_t feint_elem_size(feint_form form) {
 
 feint_status feint_prepare(int p) { return prepare_tables(p); }
 
+feint_status feint_integrate_fields(const feint_fields *fl, int p, feint_form form, void *A, void *b,
+                                    double *xq, uint32_t *dev_status, void *stream) {
+    if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
+    if (!valid_form(form)) return FEINT_ERR_UNSUPPORTED_FORM;
+    if (!fl || fl->ne < 0) return FEINT_ERR_INVALID_ARG;
+    if (fl->ne == 0) return FEINT_OK;
+    if (!fl->coords || !fl->D || !fl->beta || !fl->c || !fl->f || !A || !b) return FEINT_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const DevTables *T = nullptr;
+    feint_status s = tables_for_launch(p, st, &T);
+    if (s != FEINT_OK) return s;
+    feint_elements el = {fl->coords, nullptr, nullptr, nullptr, nullptr, fl->ne};
+    FwdParams prm;
+    fill_fwd_params(prm, &el, form, T);
+    prm.fD = fl->D; prm.fbeta = fl->beta; prm.fc = fl->c; prm.ff = fl->f;
+    prm.A = A; prm.b = b; prm.xq = xq; prm.status = dev_status;
+    const FwdVariant *v = chosen_variant(p, form);
+    if (!v) return FEINT_ERR_UNSUPPORTED_FORM;
+    return launch_forward(prm, v, st);
+}
+
 feint_status feint_integrate(const feint_elements *el, int p, feint_form form, void *A, void *b,
                              double *xq, uint32_t *dev_status, void *stream) {
     if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;

@@ -48,6 +48,43 @@ __device__ inline int64_t offb_of(const FwdParams &prm, int64_t e, int n) {
     return prm.offb ? prm.offb[e] : e * (int64_t)n;
 }
 
+// Element inputs of a forward work item: the vertices, and the constant
+// coefficients unless the launch carries vertex fields.
+__device__ inline void load_elem_fwd(const FwdParams &prm, int64_t e, ElemIn &E) {
+    if (prm.fD) {
+#pragma unroll
+        for (int i = 0; i < 18; ++i) E.X[i] = prm.coords[18 * e + i];
+    } else {
+        load_elem(prm.coords, prm.D, prm.beta, prm.c, prm.f, e, E);
+    }
+}
+
+// Coefficients at reference point (xi1, xi2, zeta) when the launch carries
+// vertex fields: the six vertex values combined with the geometry shape
+// functions N_a = lambda_a (1-zeta)/2, N_{a+3} = lambda_a (1+zeta)/2, i.e. the
+// fields live in the same bilinear space as the geometry.  No-op otherwise.
+__device__ inline void field_at(const FwdParams &prm, int64_t e, double xi1, double xi2, double ze, ElemIn &E) {
+    if (!prm.fD) return;
+    const double t = 0.5 * (1.0 + ze), s = 0.5 * (1.0 - ze), l0 = 1.0 - xi1 - xi2;
+#pragma unroll
+    for (int m = 0; m < 9; ++m) E.D[m] = 0.0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) E.be[m] = 0.0;
+    E.c = 0.0;
+    E.f = 0.0;
+#pragma unroll 1
+    for (int a = 0; a < 6; ++a) {                // one vertex at a time: 14 loads in flight
+        const double *Da = prm.fD + (6 * e + a) * 9, *ba = prm.fbeta + (6 * e + a) * 3;
+        const double Na = (a % 3 == 0 ? l0 : (a % 3 == 1 ? xi1 : xi2)) * (a < 3 ? s : t);
+#pragma unroll
+        for (int m = 0; m < 9; ++m) E.D[m] += Na * Da[m];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) E.be[m] += Na * ba[m];
+        E.c += Na * prm.fc[6 * e + a];
+        E.f += Na * prm.ff[6 * e + a];
+    }
+}
+
 // The load-vector column of degree P: whether it exists (a spare padded
 // column), the first column of its 16-wide tile and its lane in that tile.
 template <int P> struct LoadCol {
@@ -84,7 +121,7 @@ struct K4 {
         const int a0 = bi * TM * 16, b0 = bj * TN * 16;
         const int64_t e = elem_of(prm, slot);
         ElemIn E;
-        load_elem(prm.coords, prm.D, prm.beta, prm.c, prm.f, e, E);
+        load_elem_fwd(prm, e, E);
         const T *Bt = sizeof(T) == 8 ? (const T *)(const void *)prm.B64 : (const T *)(const void *)prm.B32;
         V4 acc[TMV][TNV];
 #pragma unroll
@@ -101,6 +138,7 @@ struct K4 {
                 const int q = qc + lane;
                 const double *qp = prm.qw + 4 * q;
                 double W[16], sf;
+                field_at(prm, e, qp[0], qp[1], qp[2], E);
                 const double det = point_block(E, qp[0], qp[1], qp[2], qp[3], W, sf);
                 if (!(det > 0.0) && prm.status) atomicOr(prm.status, 1u);
 #pragma unroll
@@ -234,7 +272,8 @@ struct K32 {
     };
     struct Smem { Slice w[4]; };
 
-    __device__ static float elem_scale(const FwdParams &prm, const ElemIn &E) {
+    __device__ static float elem_scale(const FwdParams &prm, const ElemIn &E0, int64_t e) {
+        ElemIn E = E0;
         // largest row sum of |W_q| over the element's points, times max |B|,
         // and the largest |w det J f| (the load-vector column): a bound on
         // |Y|; scale so that the bound lies in [2^13, 2^14)
@@ -245,6 +284,7 @@ struct K32 {
             if (q < NQ) {
                 const double *qp = prm.qw + 4 * q;
                 double W[16], sf;
+                field_at(prm, e, qp[0], qp[1], qp[2], E);
                 point_block(E, qp[0], qp[1], qp[2], qp[3], W, sf);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -304,8 +344,8 @@ struct K32 {
         const int a0 = bi * TM * 16, b0 = bj * TN * 16;
         const int64_t e = elem_of(prm, slot);
         ElemIn E;
-        load_elem(prm.coords, prm.D, prm.beta, prm.c, prm.f, e, E);
-        const float ys = FORM == FP16X3 ? elem_scale(prm, E) : 1.0f;
+        load_elem_fwd(prm, e, E);
+        const float ys = FORM == FP16X3 ? elem_scale(prm, E, e) : 1.0f;
         f32x4 acc[TMV][TNV];
 #pragma unroll
         for (int ti = 0; ti < TMV; ++ti)
@@ -322,6 +362,7 @@ struct K32 {
                 double W[16], sf = 0.0;
                 if (q < NQ) {
                     const double *qp = prm.qw + 4 * q;
+                    field_at(prm, e, qp[0], qp[1], qp[2], E);
                     const double det = point_block(E, qp[0], qp[1], qp[2], qp[3], W, sf);
                     if (!(det > 0.0) && prm.status) atomicOr(prm.status, 1u);
                     if (prm.xq && blk == 0) {

@@ -39,7 +39,7 @@ struct K32P {
 
     // W_q (FP32, times the fp16 scale) and w det J f of every point into the
     // slice; returns the element's fp16 scale (1 for bf16).
-    __device__ static float geometry(const FwdParams &prm, const ElemIn &E, int64_t e, int blk, Slice &sl) {
+    __device__ static float geometry(const FwdParams &prm, ElemIn &E, int64_t e, int blk, Slice &sl) {
         const int lane = threadIdx.x & 63;
         double m = 0.0;
         for (int qc = 0; qc < NQP; qc += 64) {
@@ -48,6 +48,7 @@ struct K32P {
                 double W[16], sf = 0.0;
                 if (q < NQ) {
                     const double *qp = prm.qw + 4 * q;
+                    field_at(prm, e, qp[0], qp[1], qp[2], E);
                     const double det = point_block(E, qp[0], qp[1], qp[2], qp[3], W, sf);
                     if (!(det > 0.0) && prm.status) atomicOr(prm.status, 1u);
                     if (prm.xq && blk == 0) {
@@ -183,7 +184,7 @@ struct K32P {
         float ys;
         {
             ElemIn E;
-            load_elem(prm.coords, prm.D, prm.beta, prm.c, prm.f, e, E);
+            load_elem_fwd(prm, e, E);
             ys = geometry(prm, E, e, blk, sl);
         }
         f32x4 acc[TMV][TNV];

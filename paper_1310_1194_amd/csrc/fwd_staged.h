@@ -71,7 +71,7 @@ struct K4S {
         const int a0 = bi * TM * 16, b0 = bj * TN * 16;
         const int64_t e = active ? elem_of(prm, slot) : 0;
         ElemIn E;
-        if (active) load_elem(prm.coords, prm.D, prm.beta, prm.c, prm.f, e, E);
+        if (active) load_elem_fwd(prm, e, E);
         const T *tab = sizeof(T) == 8 ? (const T *)(const void *)prm.B64 : (const T *)(const void *)prm.B32;
         V4 acc[TMV][TNV];
 #pragma unroll
@@ -98,6 +98,7 @@ struct K4S {
                         const int q = qc + lane;
                         const double *qp = prm.qw + 4 * q;
                         double W[16], sf;
+                        field_at(prm, e, qp[0], qp[1], qp[2], E);
                         const double det = point_block(E, qp[0], qp[1], qp[2], qp[3], W, sf);
                         if (!(det > 0.0) && prm.status) atomicOr(prm.status, 1u);
 #pragma unroll
@@ -252,8 +253,8 @@ struct K32S {
         ElemIn E;
         float ys = 1.0f;
         if (active) {
-            load_elem(prm.coords, prm.D, prm.beta, prm.c, prm.f, e, E);
-            if (FORM == FP16X3) ys = Plain::elem_scale(prm, E);
+            load_elem_fwd(prm, e, E);
+            if (FORM == FP16X3) ys = Plain::elem_scale(prm, E, e);
         }
         f32x4 acc[TMV][TNV];
 #pragma unroll
@@ -281,6 +282,7 @@ struct K32S {
                         double W[16], sf = 0.0;
                         if (q < NQ) {
                             const double *qp = prm.qw + 4 * q;
+                            field_at(prm, e, qp[0], qp[1], qp[2], E);
                             const double det = point_block(E, qp[0], qp[1], qp[2], qp[3], W, sf);
                             if (!(det > 0.0) && prm.status) atomicOr(prm.status, 1u);
                             if (prm.xq && blk == 0) {

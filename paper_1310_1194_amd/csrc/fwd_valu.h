@@ -73,9 +73,10 @@ struct KV {
             if (slot < nslot) {
                 const int64_t e = elem_of(prm, slot);
                 ElemIn E;
-                load_elem(prm.coords, prm.D, prm.beta, prm.c, prm.f, e, E);
+                load_elem_fwd(prm, e, E);
                 const double *qp = qw + 4 * q;
                 double W[16], sf;
+                field_at(prm, e, qp[0], qp[1], qp[2], E);
                 const double det = point_block(E, qp[0], qp[1], qp[2], qp[3], W, sf);
                 if (!(det > 0.0) && prm.status) atomicOr(prm.status, 1u);
                 T *w = sl.W[t];

@@ -23,6 +23,9 @@ struct FwdParams {
     // mixed-degree launches: element ids in bucket order and packed offsets
     const int32_t *perm;     // nullable: element of work slot i is perm[i]
     const int64_t *offA, *offb;
+    // nullable: coefficients given at the six vertices ([ne][6][9], [ne][6][3],
+    // [ne][6], [ne][6]) instead of one value per element
+    const double *fD, *fbeta, *fc, *ff;
 };
 
 // One compiled tile shape of a (degree, form): TM x TN 16x16 output tiles

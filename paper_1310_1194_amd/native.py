@@ -17,7 +17,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported degree", -3: "unsupp
 
 # every symbol include/feint.h declares
 EXPORTS = (
-    "feint_nshp", "feint_nq", "feint_elem_size", "feint_prepare", "feint_integrate",
+    "feint_nshp", "feint_nq", "feint_elem_size", "feint_prepare", "feint_integrate", "feint_integrate_fields",
     "feint_integrate_adjoint", "feint_adjoint_tile_count", "feint_adjoint_tile_get", "feint_adjoint_tile_set",
     "feint_adjoint_tile_describe", "feint_adjoint_autotune", "feint_mixed_plan_create", "feint_mixed_bucket",
     "feint_integrate_mixed", "feint_mixed_graph_capture", "feint_mixed_graph_launch",
@@ -43,6 +43,12 @@ class Elements(ctypes.Structure):
                 ("c", ctypes.c_void_p), ("f", ctypes.c_void_p), ("ne", ctypes.c_int64)]
 
 
+class Fields(ctypes.Structure):
+    """feint_fields: the same layout, coefficients per vertex."""
+    _fields_ = [("coords", ctypes.c_void_p), ("D", ctypes.c_void_p), ("beta", ctypes.c_void_p),
+                ("c", ctypes.c_void_p), ("f", ctypes.c_void_p), ("ne", ctypes.c_int64)]
+
+
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
 _i64 = ctypes.c_int64
@@ -64,6 +70,7 @@ def lib() -> ctypes.CDLL:
             "feint_elem_size": (ctypes.c_size_t, [_i]),
             "feint_prepare": (_i, [_i]),
             "feint_integrate": (_i, [P, _i, _i, _vp, _vp, _vp, _vp, _vp]),
+            "feint_integrate_fields": (_i, [ctypes.POINTER(Fields), _i, _i, _vp, _vp, _vp, _vp, _vp]),
             "feint_integrate_adjoint": (_i, [P, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
             "feint_adjoint_tile_count": (_i, [_i, _i]),
             "feint_adjoint_tile_get": (_i, [_i, _i]),

@@ -116,3 +116,14 @@ def test_assembly_plan_validation():
     assert L.feint_asm_plan_create(ptr, 2, 6, 9, None) == -1
     assert L.feint_asm_plan_info(None, None, None) == -1
     assert L.feint_assemble(None, 0, None, None, None, None, 0, None) == -1
+
+
+def test_fields_validation():
+    L = native.lib()
+    fl = native.Fields(0, 0, 0, 0, 0, 4)
+    assert L.feint_integrate_fields(ctypes.byref(fl), 3, 0, None, None, None, None, None) == -1   # null inputs
+    assert L.feint_integrate_fields(ctypes.byref(fl), 9, 0, None, None, None, None, None) == -2   # degree
+    assert L.feint_integrate_fields(ctypes.byref(fl), 3, 7, None, None, None, None, None) == -3   # form
+    assert L.feint_integrate_fields(None, 3, 0, None, None, None, None, None) == -1
+    empty = native.Fields(0, 0, 0, 0, 0, 0)
+    assert L.feint_integrate_fields(ctypes.byref(empty), 3, 0, None, None, None, None, None) == 0
