@@ -11,6 +11,7 @@ every form's relative error against the FP64 oracle on a sample of elements is
 stated in the same line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--copy-cal]
+                    [--mode forward|fields|adjoint|mixed|assemble] [--workload NAME] [--forms LIST]
 """
 from __future__ import annotations
 
@@ -63,15 +64,20 @@ def traffic_record(key: str, tile: str):
     return rec.get("tiles", {}).get(tile)
 
 
-def cpu_baseline(batch, p, budget_s: float, chunk: int = 4096):
+def cpu_baseline(batch, p, budget_s: float, chunk: int = 4096, fields=None):
     """The oracle on the host's cores over the first elements of the workload,
-    chunk by chunk until about `budget_s` seconds have been spent."""
+    chunk by chunk until about `budget_s` seconds have been spent (with vertex
+    coefficient fields when `fields` = (Dv, betav, cv, fv) is given)."""
     import oracle
     done, spent, first = 0, 0.0, None
     while done < batch.ne and (spent < budget_s or done == 0):
-        sub = batch.subset(np.arange(done, min(batch.ne, done + chunk)))
+        sl = np.arange(done, min(batch.ne, done + chunk))
+        sub = batch.subset(sl)
         t0 = time.perf_counter()
-        A, b, _ = oracle.integrate(p, sub.coords, sub.D, sub.beta, sub.c, sub.f)
+        if fields is None:
+            A, b, _ = oracle.integrate(p, sub.coords, sub.D, sub.beta, sub.c, sub.f)
+        else:
+            A, b, _ = oracle.integrate_fields(p, sub.coords, *[np.ascontiguousarray(a[sl]) for a in fields])
         spent += time.perf_counter() - t0
         if first is None:
             first = (A, b)
@@ -117,7 +123,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--mode", default="forward", choices=["forward", "adjoint", "mixed", "assemble"])
+    ap.add_argument("--mode", default="forward", choices=["forward", "fields", "adjoint", "mixed", "assemble"])
     ap.add_argument("--workload", default=None)
     ap.add_argument("--forms", default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (CPU baseline and errors)")
@@ -138,10 +144,28 @@ def main():
         return bench_mixed(args)
     if args.mode == "assemble":
         return bench_assemble(args)
-    return bench_forward(args)
+    return bench_forward(args, fields=args.mode == "fields")
 
 
-def bench_forward(args):
+def tune_tiles(call, p, form, reps=2):
+    """Time every compiled variant of (p, form) through `call`, keep the fastest;
+    returns its mean ms."""
+    import torch
+    import paper_1310_1194_amd as F
+    best = (float("inf"), 0)
+    for t in range(F.tile_count(p, form)):
+        F.tile_set(p, form, t)
+        call()
+        ms, _, _ = timed(call, reps, 0)
+        best = min(best, (ms, t))
+    F.tile_set(p, form, best[1])
+    torch.cuda.synchronize()
+    return best[0]
+
+
+def bench_forward(args, fields=False):
+    """Forward integration; with `fields` the coefficients are vertex fields
+    evaluated at every point (feint_integrate_fields)."""
     args.workload = args.workload or "p4_131072"
     args.forms = args.forms or ",".join(FORMS)
     import torch
@@ -155,7 +179,13 @@ def bench_forward(args):
     batch = meshgen.workload(args.workload)
     ne = batch.ne
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-    X = (t(batch.coords), t(batch.D), t(batch.beta), t(batch.c), t(batch.f))
+    vf = meshgen.vertex_fields(ne, 1000 + w["seed"]) if fields else None
+    if fields:
+        X = (t(batch.coords),) + tuple(t(a) for a in vf)
+        integrate = F.integrate_fields_raw
+    else:
+        X = (t(batch.coords), t(batch.D), t(batch.beta), t(batch.c), t(batch.f))
+        integrate = F.integrate_raw
     forms = [f for f in args.forms.split(",") if f]
     headline = HEADLINE if HEADLINE in forms else forms[0]
 
@@ -176,17 +206,20 @@ def bench_forward(args):
         b = torch.empty((ne, n), dtype=dt, device=dev)
         tile_ms = None
         if not args.no_tune:
-            tile_ms = F.autotune(*X, p, form, A, b, reps=2)
+            if fields:
+                tile_ms = tune_tiles(lambda: integrate(*X, p, form, A=A, b=b), p, form)
+            else:
+                tile_ms = F.autotune(*X, p, form, A, b, reps=2)
         tile = F.tile_describe(p, form, F.tile_get(p, form))
         for _ in range(args.warmup):
-            F.integrate_raw(*X, p, form, A=A, b=b)
+            integrate(*X, p, form, A=A, b=b)
         torch.cuda.synchronize()
         stream = torch.cuda.current_stream()
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
         t0 = time.perf_counter()
         ev[0].record(stream)
         for k in range(args.steps):
-            F.integrate_raw(*X, p, form, A=A, b=b)
+            integrate(*X, p, form, A=A, b=b)
             ev[k + 1].record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -200,16 +233,17 @@ def bench_forward(args):
         print(f"[bench] {form}: {ms:.3f} ms/launch (min {np.min(per):.3f}), tile {tile}", file=sys.stderr, flush=True)
 
     fdom = costmodel.f_dom(p)
+    in_bytes = costmodel.FIELD_INPUT_BYTES if fields else costmodel.INPUT_BYTES
     for form, r in results.items():
         es = costmodel.out_bytes(p, 8 if form == "fp64" else 4)
-        alg_bytes = ne * (costmodel.INPUT_BYTES + es)
+        alg_bytes = ne * (in_bytes + es)
         r["gflops"] = fdom * ne / (r["kernel_ms_mean"] * 1e-3) / 1e9
         r["tflops_frac_of_peak"] = r["gflops"] / 1e3 / PEAK_TFLOPS[form]
         r["hbm_gbs_algorithmic"] = alg_bytes / (r["kernel_ms_mean"] * 1e-3) / 1e9
 
     cpu = None
     if not args.no_cpu:
-        rate, done, spent, cores, (Ar, br) = cpu_baseline(batch, p, args.cpu_budget)
+        rate, done, spent, cores, (Ar, br) = cpu_baseline(batch, p, args.cpu_budget, fields=vf)
         cpu = {"value": rate, "unit": "elements/s", "cores": cores, "kind": "oracle",
                "sample": f"first {done} of the {ne} elements of {args.workload} "
                          f"({spent:.1f} s, FP64, OpenMP over elements)",
@@ -224,9 +258,9 @@ def bench_forward(args):
             r["err_sample"] = m
 
     h = results[headline]
-    traffic = traffic_record(f"fwd:{headline}:{args.workload}", results[headline]["tile"])
+    traffic = traffic_record(f"{'fields' if fields else 'fwd'}:{headline}:{args.workload}", results[headline]["tile"])
     es = 8 if headline == "fp64" else 4
-    alg_bytes = ne * costmodel.bytes_per_element(p, es)
+    alg_bytes = ne * (costmodel.fields_bytes_per_element(p, es) if fields else costmodel.bytes_per_element(p, es))
     # bound = the larger ideal time: MFMA work (three products for a split
     # form) at the dtype's dense peak, or the algorithmic bytes at HBM peak
     products = 3 if headline in ("bf16x3", "fp16x3") else 1
@@ -244,13 +278,14 @@ def bench_forward(args):
                      "hw_mfma_frac": hw_flops / (h["kernel_ms_mean"] * 1e-3) / (PEAK_TFLOPS[headline] * 1e12),
                      "alg_bytes_per_launch": alg_bytes,
                      "note": "algorithmic flops 8 n^2 nq per element (one product per entry; "
-                             "a split form issues three products); bytes 256 in + (n^2+n) outputs"})
+                             "a split form issues three products); bytes %d in + (n^2+n) outputs" % in_bytes})
     forms_out = {}
     for form, r in results.items():
         forms_out[form] = {k: (float(f"{v:.5g}") if isinstance(v, float) else v) for k, v in r.items()
                            if not k.endswith("_sample")}
     line = {
-        "metric": "elements/s + GFLOP/s (roofline %) at p=4, plain FP64 vs MFMA form at stated error",
+        "metric": "elements/s + GFLOP/s (roofline %) at p=4, plain FP64 vs MFMA form at stated error"
+                  + (" (coefficients varying in space, given at the vertices)" if fields else ""),
         "value": h["elements_per_s"],
         "unit": "elements/s",
         "n_gpus": 1,
@@ -262,7 +297,8 @@ def bench_forward(args):
         "vs_baseline": None,
         "dtype": DTYPE_DESC[headline],
         "data": "synthetic (seeded perturbed prism mesh and coefficients)",
-        "config": {"workload": args.workload, "p": p, "ne": ne, "nshp": n, "nq": q,
+        "config": {"workload": args.workload + ("+vertex_fields" if fields else ""), "p": p, "ne": ne,
+                   "nshp": n, "nq": q, "coefficients": "vertex fields" if fields else "element constants",
                    "mesh": f"{w['nx']}x{w['ny']}x{w['nz']}", "perturbation": w["amp"], "seed": w["seed"],
                    "form": headline, "parallelism": "single GPU"},
         "gflops": h["gflops"],

@@ -74,6 +74,15 @@ def bytes_per_element(p: int, elem_size: int) -> int:
     return INPUT_BYTES + out_bytes(p, elem_size)
 
 
+# coords + the coefficients at the six vertices (D, beta, c, f) in FP64 = 816
+FIELD_INPUT_BYTES = 8 * (18 + 6 * (9 + 3 + 1 + 1))
+
+
+def fields_bytes_per_element(p: int, elem_size: int) -> int:
+    """Algorithmic HBM bytes of the forward pass with vertex coefficient fields."""
+    return FIELD_INPUT_BYTES + out_bytes(p, elem_size)
+
+
 def adjoint_bytes_per_element(p: int, elem_size: int) -> int:
     """Adjoint: read G, g (elem_size each) + the 256 B of inputs, write 32 FP64 gradients."""
     return out_bytes(p, elem_size) + INPUT_BYTES + 32 * 8

@@ -138,6 +138,20 @@ def make_batch(nx: int, ny: int, nz: int, amp: float = 0.2, seed: int = 0,
     return b
 
 
+def vertex_fields(ne: int, seed: int):
+    """Coefficients given at the six vertices of every element, drawn with the
+    element-constant recipe per vertex: D = L L^T + I (L ~ N(0, 0.3^2)),
+    beta ~ N(0, 1), c ~ U(0, 1), f ~ U(-1, 1).  Shapes [ne,6,3,3], [ne,6,3],
+    [ne,6], [ne,6], FP64, contiguous."""
+    rng = np.random.default_rng(seed)
+    L = rng.normal(0.0, 0.3, (ne, 6, 3, 3))
+    D = np.einsum("evik,evjk->evij", L, L) + np.eye(3)
+    beta = rng.normal(0.0, 1.0, (ne, 6, 3))
+    c = rng.uniform(0.0, 1.0, (ne, 6))
+    f = rng.uniform(-1.0, 1.0, (ne, 6))
+    return tuple(np.ascontiguousarray(a) for a in (D, beta, c, f))
+
+
 def adjoint_seeds(batch: Batch, p: int, dtype=np.float64):
     """Draw step 7: G ~ N(0,1) [ne,n,n], g ~ N(0,1) [ne,n], 64 sampled ids."""
     rng = batch.meta["rng"]

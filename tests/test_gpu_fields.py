@@ -21,10 +21,8 @@ def torch_cuda():
 
 
 def vertex_fields(ne, seed):
-    rng = np.random.default_rng(seed)
-    L = rng.normal(0.0, 0.3, (ne, 6, 3, 3))
-    D = np.einsum("evik,evjk->evij", L, L) + np.eye(3)
-    return D, rng.normal(0.0, 1.0, (ne, 6, 3)), rng.uniform(0.0, 1.0, (ne, 6)), rng.uniform(-1.0, 1.0, (ne, 6))
+    from paper_1310_1194_amd import meshgen
+    return meshgen.vertex_fields(ne, seed)
 
 
 @pytest.mark.parametrize("form", ["fp64", "fp32", "bf16x3", "fp16x3"])
