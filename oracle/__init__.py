@@ -48,6 +48,8 @@ def lib():
         L.oracle_geometry.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp]
         L.oracle_integrate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [_dp] * 8 + [_ip]
         L.oracle_integrate_fields.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [_dp] * 8 + [_ip]
+        L.oracle_integrate_rule.argtypes = ([ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int64, ctypes.c_int]
+                                            + [_dp] * 8 + [_ip])
         L.oracle_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [_dp] * 13
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_max_threads.restype = ctypes.c_int
@@ -111,8 +113,47 @@ def geometry(X, xi):
     return J, float(det[0]), K, x
 
 
-def integrate(p, coords, D, beta, c, f, n1=0, want_xq=False):
-    """A [ne,n,n], b [ne,n], flags [ne] (and xq [ne,nq,3] when asked)."""
+def prism_rule(p, rule):
+    """(pts [nq,3], w [nq]) of a named rule: "collapsed" ((p+1)^3-point
+    collapsed Gauss) or "symmetric" (symmetric triangle rule of degree 2p x
+    (p+1) Gauss points in zeta, ``oracle/rules.py``)."""
+    if rule == "collapsed":
+        return globals()["rule"](p + 1)
+    if rule == "symmetric":
+        from . import rules
+        return rules.prism_rule(p, gauss_legendre)
+    raise ValueError(f"unknown rule {rule!r}")
+
+
+def _integrate_on(p, pts, w, nv, coords, D, beta, c, f, want_xq):
+    coords = _c(coords); D = _c(D); beta = _c(beta); c = _c(c); f = _c(f)
+    pts = _c(pts); w = _c(w)
+    ne, n, nq = coords.shape[0], nshp(p), w.shape[0]
+    A = np.zeros((ne, n, n)); b = np.zeros((ne, n))
+    flags = np.zeros(ne, dtype=np.int32)
+    xq = np.zeros((ne, nq, 3)) if want_xq else None
+    rc = lib().oracle_integrate_rule(p, nq, _p(pts), _p(w), ne, nv, _p(coords), _p(D), _p(beta), _p(c), _p(f),
+                                     _p(A), _p(b), _p(xq), flags.ctypes.data_as(_ip))
+    assert rc == 0, rc
+    return (A, b, flags, xq) if want_xq else (A, b, flags)
+
+
+def integrate_rule(p, pts, w, coords, D, beta, c, f, want_xq=False):
+    """Element-constant coefficients on the caller's rule (pts [nq,3], w [nq])."""
+    return _integrate_on(p, pts, w, 1, coords, D, beta, c, f, want_xq)
+
+
+def integrate_fields_rule(p, pts, w, coords, Dv, betav, cv, fv, want_xq=False):
+    """Vertex coefficient fields on the caller's rule."""
+    return _integrate_on(p, pts, w, 6, coords, Dv, betav, cv, fv, want_xq)
+
+
+def integrate(p, coords, D, beta, c, f, n1=0, want_xq=False, rule=None):
+    """A [ne,n,n], b [ne,n], flags [ne] (and xq [ne,nq,3] when asked).
+    rule=None: collapsed Gauss with n1 (default p+1) points per direction;
+    rule="symmetric": the symmetric prism rule."""
+    if rule is not None:
+        return integrate_rule(p, *prism_rule(p, rule), coords, D, beta, c, f, want_xq)
     coords = _c(coords); D = _c(D); beta = _c(beta); c = _c(c); f = _c(f)
     ne = coords.shape[0]
     n = nshp(p)
@@ -128,10 +169,12 @@ def integrate(p, coords, D, beta, c, f, n1=0, want_xq=False):
     return A, b, flags
 
 
-def integrate_fields(p, coords, Dv, betav, cv, fv, n1=0, want_xq=False):
+def integrate_fields(p, coords, Dv, betav, cv, fv, n1=0, want_xq=False, rule=None):
     """Coefficients given at the six vertices (Dv [ne,6,3,3], betav [ne,6,3],
     cv [ne,6], fv [ne,6]) and evaluated at each point with the geometry shape
     functions.  Returns A, b, flags (and xq)."""
+    if rule is not None:
+        return integrate_fields_rule(p, *prism_rule(p, rule), coords, Dv, betav, cv, fv, want_xq)
     coords = _c(coords); Dv = _c(Dv); betav = _c(betav); cv = _c(cv); fv = _c(fv)
     ne = coords.shape[0]
     n = nshp(p)

@@ -290,19 +290,28 @@ typedef struct {
     double *pts, *w, *phi, *dphi; /* [nq][3], [nq], [nq][n], [nq][n][3] */
 } rule_tables;
 
-static int make_tables(int p, int n1, rule_tables *T)
+/* Tables of degree p on a rule: the caller's points (qpts [nq][3], qw [nq])
+   when qpts is given, else the collapsed Gauss rule with n1 points per
+   direction (n1 <= 0: p+1). */
+static int make_tables(int p, int n1, int nq, const double *qpts, const double *qw, rule_tables *T)
 {
     if (p < 1 || p > ORACLE_MAXP) return -1;
     if (n1 <= 0) n1 = p + 1;
     if (n1 > ORACLE_MAXN1) return -1;
+    if (qpts && (nq < 1 || !qw)) return -1;
     T->p = p;
     T->n = oracle_nshp(p);
-    T->nq = n1 * n1 * n1;
+    T->nq = qpts ? nq : n1 * n1 * n1;
     T->pts = (double *)malloc(sizeof(double) * 3 * T->nq);
     T->w = (double *)malloc(sizeof(double) * T->nq);
     T->phi = (double *)malloc(sizeof(double) * T->nq * T->n);
     T->dphi = (double *)malloc(sizeof(double) * 3 * T->nq * T->n);
-    oracle_rule(n1, T->pts, T->w);
+    if (qpts) {
+        memcpy(T->pts, qpts, sizeof(double) * 3 * T->nq);
+        memcpy(T->w, qw, sizeof(double) * T->nq);
+    } else {
+        oracle_rule(n1, T->pts, T->w);
+    }
     /* step 6 of Algorithm 1: shape functions at every point (the same for
        every element of degree p, so they are evaluated once) */
     for (int q = 0; q < T->nq; ++q)
@@ -342,13 +351,13 @@ int oracle_max_threads(void)
    given at the six vertices (nv = 6) and evaluated at each point with the
    geometry shape functions, D(x_q) = sum_a N_a(xi_q) D_a (the coefficient
    fields live in the same bilinear space as the geometry). */
-static int integrate_core(int p, int n1, int64_t ne, int nv, const double *coords, const double *Dv,
-                          const double *betav, const double *cv, const double *fv,
-                          double *A, double *b, double *xq, int32_t *flags)
+static int integrate_core(int p, int n1, int nq, const double *qpts, const double *qw, int64_t ne, int nv,
+                          const double *coords, const double *Dv, const double *betav, const double *cv,
+                          const double *fv, double *A, double *b, double *xq, int32_t *flags)
 {
     rule_tables T;
     if (ne < 0) return -1;
-    if (make_tables(p, n1, &T)) return -1;
+    if (make_tables(p, n1, nq, qpts, qw, &T)) return -1;
     const int n = T.n, nqp = T.nq;
     int64_t e;
 #pragma omp parallel for schedule(static)
@@ -423,7 +432,7 @@ int oracle_integrate(int p, int n1, int64_t ne, const double *coords, const doub
                      const double *beta, const double *c, const double *f,
                      double *A, double *b, double *xq, int32_t *flags)
 {
-    return integrate_core(p, n1, ne, 1, coords, D, beta, c, f, A, b, xq, flags);
+    return integrate_core(p, n1, 0, NULL, NULL, ne, 1, coords, D, beta, c, f, A, b, xq, flags);
 }
 
 /* Coefficients given at the six vertices: Dv [ne][6][9], betav [ne][6][3],
@@ -432,7 +441,18 @@ int oracle_integrate_fields(int p, int n1, int64_t ne, const double *coords, con
                             const double *betav, const double *cv, const double *fv,
                             double *A, double *b, double *xq, int32_t *flags)
 {
-    return integrate_core(p, n1, ne, 6, coords, Dv, betav, cv, fv, A, b, xq, flags);
+    return integrate_core(p, n1, 0, NULL, NULL, ne, 6, coords, Dv, betav, cv, fv, A, b, xq, flags);
+}
+
+/* The same element loop on a rule given by the caller: qpts [nq][3] =
+   (xi1, xi2, zeta), qw [nq]; xq (optional) is [ne][nq][3].  nv = 1:
+   coefficients constant per element; nv = 6: given at the six vertices. */
+int oracle_integrate_rule(int p, int nq, const double *qpts, const double *qw, int64_t ne, int nv,
+                          const double *coords, const double *Dv, const double *betav, const double *cv,
+                          const double *fv, double *A, double *b, double *xq, int32_t *flags)
+{
+    if (!qpts || (nv != 1 && nv != 6)) return -1;
+    return integrate_core(p, 0, nq, qpts, qw, ne, nv, coords, Dv, betav, cv, fv, A, b, xq, flags);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -460,7 +480,7 @@ int oracle_adjoint(int p, int n1, int64_t ne, const double *coords, const double
 {
     rule_tables T;
     if (ne < 0) return -1;
-    if (make_tables(p, n1, &T)) return -1;
+    if (make_tables(p, n1, 0, NULL, NULL, &T)) return -1;
     const int n = T.n, nqp = T.nq;
     int64_t e;
 #pragma omp parallel for schedule(static)
