@@ -58,7 +58,9 @@ typedef enum {
 
 /* Arithmetic of the contraction A_e = sum_q B_q^T W_q B_q.  The Jacobian,
    its determinant and inverse and the per-point coefficient block W_q are
-   always computed in FP64; the load vector is always accumulated in FP64. */
+   always computed in FP64.  The load vector is formed by the same
+   contraction (a spare padded column carries w det J f), so it carries the
+   form's precision; at p = 7 (no spare column) it is accumulated in FP64. */
 typedef enum {
     FEINT_FP64 = 0,    /* FP64 MFMA, FP64 outputs */
     FEINT_FP32 = 1,    /* FP32 MFMA, FP32 outputs */
@@ -231,6 +233,47 @@ feint_status feint_tile_set(int p, feint_form form, int tile);
 feint_status feint_tile_describe(int p, feint_form form, int tile, char *buf, size_t len);
 feint_status feint_autotune(const feint_elements *el, int p, feint_form form,
                             void *A, void *b, int reps, double *best_ms, void *stream);
+
+/* ---- Quadrature rules (Sec. 2, Table 3) -------------------------------------
+   The entry points above integrate with the collapsed Gauss rule, (p+1)^3
+   points.  The paper's Table 3 counts N_I = 6, 18, 48, 80, 150, 231, 336
+   points for p = 1..7, which is a fully symmetric triangle rule of degree 2p
+   (3, 6, 12, 16, 25, 33, 42 points, positive weights, interior points)
+   times p+1 Gauss-Legendre points in zeta: products of shape functions are
+   integrated exactly on affine prisms (the paper's accuracy requirement)
+   with 36-52 % fewer points.  Point q = k * ntri + t (Gauss point k in zeta
+   ascending, triangle point t in orbit order: centroid, 3-orbits, 6-orbits). */
+typedef enum {
+    FEINT_RULE_COLLAPSED = 0,  /* (p+1)^3 collapsed Gauss-Legendre */
+    FEINT_RULE_SYMMETRIC = 1   /* symmetric triangle rule of degree 2p x (p+1) Gauss */
+} feint_rule;
+
+/* Number of points of a rule; -1 for p outside [1,7] or an unknown rule. */
+int feint_nq_rule(int p, feint_rule rule);
+/* Host copy of a rule's points: pts [nq][4] = (xi1, xi2, zeta, w), host
+   memory owned by the caller with room for cap points (INVALID_ARG if too
+   small).  No device work. */
+feint_status feint_rule_points(int p, feint_rule rule, double *pts, int64_t cap);
+/* feint_prepare for the tables of degree p on `rule`. */
+feint_status feint_prepare_rule(int p, feint_rule rule);
+/* Forward integration on `rule`: exactly one of el (element-constant
+   coefficients) and fl (vertex fields) is non-null, else INVALID_ARG.
+   Outputs, forms, errors and the det J flag as feint_integrate; xq, when
+   given, is [ne][feint_nq_rule(p, rule)][3]. */
+feint_status feint_integrate_rule(const feint_elements *el, const feint_fields *fl, int p, feint_form form,
+                                  feint_rule rule, void *A, void *b, double *xq, uint32_t *dev_status,
+                                  void *stream);
+/* Compiled variants per (degree, form, rule), chosen and described as for
+   the collapsed rule (feint_tile_*; those calls are these with
+   FEINT_RULE_COLLAPSED).  feint_autotune_rule takes el or fl as
+   feint_integrate_rule does. */
+int feint_rule_tile_count(int p, feint_form form, feint_rule rule);
+int feint_rule_tile_get(int p, feint_form form, feint_rule rule);
+feint_status feint_rule_tile_set(int p, feint_form form, feint_rule rule, int tile);
+feint_status feint_rule_tile_describe(int p, feint_form form, feint_rule rule, int tile, char *buf,
+                                      size_t len);
+feint_status feint_autotune_rule(const feint_elements *el, const feint_fields *fl, int p, feint_form form,
+                                 feint_rule rule, void *A, void *b, int reps, double *best_ms, void *stream);
 
 /* ---- Global assembly (Sec. 2) ----------------------------------------------
    The element matrices and load vectors of one degree are summed into a CSR

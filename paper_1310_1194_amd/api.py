@@ -10,15 +10,33 @@ import ctypes
 import torch
 
 from . import native
-from .native import FORMS, Elements, check, lib
+import numpy as np
+
+from .native import FORMS, RULES, Elements, Fields, check, lib
 
 
 def nshp(p: int) -> int:
     return (p + 1) * (p + 1) * (p + 2) // 2
 
 
-def nq(p: int) -> int:
-    return (p + 1) ** 3
+def nq(p: int, rule: str = "collapsed") -> int:
+    if rule == "collapsed":
+        return (p + 1) ** 3
+    return lib().feint_nq_rule(int(p), _rule(rule))
+
+
+def _rule(rule: str) -> int:
+    if rule not in RULES:
+        raise ValueError(f"unknown rule {rule!r}")
+    return RULES[rule]
+
+
+def rule_points(p: int, rule: str = "collapsed"):
+    """Host copy of a rule's points: numpy [nq, 4] = (xi1, xi2, zeta, w)."""
+    n = nq(p, rule)
+    out = np.zeros((n, 4))
+    check("feint_rule_points", lib().feint_rule_points(int(p), _rule(rule), out.ctypes.data_as(ctypes.c_void_p), n))
+    return out
 
 
 def out_dtype(form: str) -> torch.dtype:
@@ -54,13 +72,18 @@ def elements(coords, D, beta, c, f) -> Elements:
     return Elements(coords.data_ptr(), D.data_ptr(), beta.data_ptr(), c.data_ptr(), f.data_ptr(), ne)
 
 
-def prepare(p: int) -> None:
-    check("feint_prepare", lib().feint_prepare(int(p)))
+def prepare(p: int, rule: str = "collapsed") -> None:
+    if rule == "collapsed":
+        check("feint_prepare", lib().feint_prepare(int(p)))
+    else:
+        check("feint_prepare_rule", lib().feint_prepare_rule(int(p), _rule(rule)))
 
 
 def integrate_raw(coords, D, beta, c, f, p: int, form: str = "fp64", *, A=None, b=None,
-                  xq=None, status=None):
+                  xq=None, status=None, rule: str = "collapsed"):
     """Forward integration into (optionally preallocated) outputs; returns (A, b)."""
+    if rule != "collapsed":
+        return _integrate_rule(elements(coords, D, beta, c, f), None, coords, p, form, rule, A, b, xq, status)
     if form not in FORMS:
         raise ValueError(f"unknown form {form!r}")
     el = elements(coords, D, beta, c, f)
@@ -81,19 +104,46 @@ def integrate_raw(coords, D, beta, c, f, p: int, form: str = "fp64", *, A=None, 
     return A, b
 
 
+def fields(coords, Dv, betav, cv, fv) -> Fields:
+    ne = coords.shape[0]
+    for t, k in zip([coords, Dv, betav, cv, fv], [18, 54, 18, 6, 6]):
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != ne * k:
+            raise ValueError("vertex fields must be contiguous float64 of the documented shapes")
+    return Fields(coords.data_ptr(), Dv.data_ptr(), betav.data_ptr(), cv.data_ptr(), fv.data_ptr(), ne)
+
+
+def _integrate_rule(el, fl, coords, p, form, rule, A, b, xq, status):
+    if form not in FORMS:
+        raise ValueError(f"unknown form {form!r}")
+    ne, n = coords.shape[0], nshp(p)
+    dt = out_dtype(form)
+    if A is None:
+        A = torch.empty((ne, n, n), dtype=dt, device=coords.device)
+    if b is None:
+        b = torch.empty((ne, n), dtype=dt, device=coords.device)
+    if A.dtype != dt or b.dtype != dt or A.numel() != ne * n * n or b.numel() != ne * n:
+        raise ValueError("output tensors have the wrong dtype or size")
+    if xq is not None and (xq.dtype != torch.float64 or xq.numel() != ne * nq(p, rule) * 3):
+        raise ValueError("xq must be float64 with ne*nq*3 entries")
+    if status is not None and (status.dtype != torch.int32 or status.numel() < 1):
+        raise ValueError("status must be an int32 tensor")
+    check("feint_integrate_rule",
+          lib().feint_integrate_rule(ctypes.byref(el) if el is not None else None,
+                                     ctypes.byref(fl) if fl is not None else None, int(p), FORMS[form],
+                                     _rule(rule), _ptr(A), _ptr(b), _ptr(xq), _ptr(status), _stream()))
+    return A, b
+
+
 def integrate_fields_raw(coords, Dv, betav, cv, fv, p: int, form: str = "fp64", *, A=None, b=None,
-                         xq=None, status=None):
+                         xq=None, status=None, rule: str = "collapsed"):
     """Forward integration with coefficients given at the six vertices of every
     element (Dv [ne,6,3,3], betav [ne,6,3], cv [ne,6], fv [ne,6], FP64)."""
     if form not in FORMS:
         raise ValueError(f"unknown form {form!r}")
     ne, n = coords.shape[0], nshp(p)
-    ts = [coords, Dv, betav, cv, fv]
-    sizes = [18, 54, 18, 6, 6]
-    for t, k in zip(ts, sizes):
-        if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != ne * k:
-            raise ValueError("vertex fields must be contiguous float64 of the documented shapes")
-    fl = native.Fields(*[t.data_ptr() for t in ts], ne)
+    fl = fields(coords, Dv, betav, cv, fv)
+    if rule != "collapsed":
+        return _integrate_rule(None, fl, coords, p, form, rule, A, b, xq, status)
     dt = out_dtype(form)
     if A is None:
         A = torch.empty((ne, n, n), dtype=dt, device=coords.device)
@@ -151,30 +201,57 @@ def integrate(coords, D, beta, c, f, p: int, form: str = "fp64"):
     return integrate_raw(coords, D, beta, c, f, p, form)
 
 
-def tile_count(p: int, form: str) -> int:
-    return lib().feint_tile_count(int(p), FORMS[form])
+def tile_count(p: int, form: str, rule: str = "collapsed") -> int:
+    if rule == "collapsed":
+        return lib().feint_tile_count(int(p), FORMS[form])
+    return lib().feint_rule_tile_count(int(p), FORMS[form], _rule(rule))
 
 
-def tile_get(p: int, form: str) -> int:
-    return lib().feint_tile_get(int(p), FORMS[form])
+def tile_get(p: int, form: str, rule: str = "collapsed") -> int:
+    if rule == "collapsed":
+        return lib().feint_tile_get(int(p), FORMS[form])
+    return lib().feint_rule_tile_get(int(p), FORMS[form], _rule(rule))
 
 
-def tile_set(p: int, form: str, tile: int) -> None:
-    check("feint_tile_set", lib().feint_tile_set(int(p), FORMS[form], int(tile)))
+def tile_set(p: int, form: str, tile: int, rule: str = "collapsed") -> None:
+    if rule == "collapsed":
+        check("feint_tile_set", lib().feint_tile_set(int(p), FORMS[form], int(tile)))
+    else:
+        check("feint_rule_tile_set", lib().feint_rule_tile_set(int(p), FORMS[form], _rule(rule), int(tile)))
 
 
-def tile_describe(p: int, form: str, tile: int) -> str:
+def tile_describe(p: int, form: str, tile: int, rule: str = "collapsed") -> str:
     buf = ctypes.create_string_buffer(32)
-    check("feint_tile_describe", lib().feint_tile_describe(int(p), FORMS[form], int(tile), buf, 32))
+    if rule == "collapsed":
+        check("feint_tile_describe", lib().feint_tile_describe(int(p), FORMS[form], int(tile), buf, 32))
+    else:
+        check("feint_rule_tile_describe",
+              lib().feint_rule_tile_describe(int(p), FORMS[form], _rule(rule), int(tile), buf, 32))
     return buf.value.decode()
 
 
-def autotune(coords, D, beta, c, f, p: int, form: str, A, b, reps: int = 3) -> float:
+def autotune(coords, D, beta, c, f, p: int, form: str, A, b, reps: int = 3, rule: str = "collapsed") -> float:
     """Time every compiled tile shape on these buffers, keep the fastest; returns its ms."""
     el = elements(coords, D, beta, c, f)
     best = ctypes.c_double(0)
-    check("feint_autotune", lib().feint_autotune(ctypes.byref(el), int(p), FORMS[form], _ptr(A), _ptr(b),
-                                                 int(reps), ctypes.byref(best), _stream()))
+    if rule == "collapsed":
+        check("feint_autotune", lib().feint_autotune(ctypes.byref(el), int(p), FORMS[form], _ptr(A), _ptr(b),
+                                                     int(reps), ctypes.byref(best), _stream()))
+    else:
+        check("feint_autotune_rule",
+              lib().feint_autotune_rule(ctypes.byref(el), None, int(p), FORMS[form], _rule(rule), _ptr(A), _ptr(b),
+                                        int(reps), ctypes.byref(best), _stream()))
+    return best.value
+
+
+def autotune_fields(coords, Dv, betav, cv, fv, p: int, form: str, A, b, reps: int = 3,
+                    rule: str = "collapsed") -> float:
+    """autotune for the vertex-field entry point."""
+    fl = fields(coords, Dv, betav, cv, fv)
+    best = ctypes.c_double(0)
+    check("feint_autotune_rule",
+          lib().feint_autotune_rule(None, ctypes.byref(fl), int(p), FORMS[form], _rule(rule), _ptr(A), _ptr(b),
+                                    int(reps), ctypes.byref(best), _stream()))
     return best.value
 
 

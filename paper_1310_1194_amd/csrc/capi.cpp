@@ -20,34 +20,36 @@ namespace feint {
 
 namespace {
 std::mutex g_mu;
-std::map<int, DevTables *> g_tables;        // key: device * 16 + p
-int g_tile[8][4];                           // chosen variant per (p, form)
+std::map<int, DevTables *> g_tables;        // key: device * 16 + rule * 8 + p
+int g_tile[2][8][4];                        // chosen variant per (rule, p, form)
 thread_local std::string g_err;
 
 bool valid_form(int form) { return form >= FEINT_FP64 && form <= FEINT_FP16X3; }
+bool valid_rule(int rule) { return rule == FEINT_RULE_COLLAPSED || rule == FEINT_RULE_SYMMETRIC; }
 }  // namespace
 
 void set_error(const char *what, hipError_t e) {
     g_err = std::string(what) + ": " + hipGetErrorString(e);
 }
 
-const DevTables *find_tables(int p) {
+const DevTables *find_tables(int p, int rule) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return nullptr;
     std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_tables.find(dev * 16 + p);
+    auto it = g_tables.find(dev * 16 + rule * 8 + p);
     return it == g_tables.end() ? nullptr : it->second;
 }
 
-// Upload the tables of degree p to the current device (once).
-feint_status prepare_tables(int p) {
+// Upload the tables of degree p on rule `rule` to the current device (once).
+feint_status prepare_tables(int p, int rule) {
     if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
+    if (!valid_rule(rule)) return FEINT_ERR_INVALID_ARG;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) { set_error("hipGetDevice", e); return FEINT_ERR_HIP; }
     std::lock_guard<std::mutex> lk(g_mu);
-    if (g_tables.count(dev * 16 + p)) return FEINT_OK;
-    HostTables H = build_tables(p);
+    if (g_tables.count(dev * 16 + rule * 8 + p)) return FEINT_OK;
+    HostTables H = build_tables(p, rule);
     auto align = [](size_t x) { return (x + 255) / 256 * 256; };
     const size_t s_qw = align(H.qw.size() * 8), s_b64 = align(H.B64.size() * 8), s_b32 = align(H.B32.size() * 4);
     const size_t s_sp = align(H.bf_hi.size() * 2);
@@ -65,7 +67,7 @@ feint_status prepare_tables(int p) {
         return base + at;
     };
     DevTables *T = new DevTables();
-    T->p = p; T->n = H.n; T->npad = H.npad; T->nq = H.nq; T->nqp = H.nqp; T->nkb = H.nkb;
+    T->p = p; T->rule = rule; T->n = H.n; T->npad = H.npad; T->nq = H.nq; T->nqp = H.nqp; T->nkb = H.nkb;
     T->f16_shift = H.f16_shift;
     double bmax = 0;
     for (double v : H.B64) bmax = std::fmax(bmax, std::fabs(v));
@@ -89,22 +91,22 @@ feint_status prepare_tables(int p) {
         delete T;
         return FEINT_ERR_HIP;
     }
-    g_tables[dev * 16 + p] = T;
+    g_tables[dev * 16 + rule * 8 + p] = T;
     return FEINT_OK;
 }
 
 // Tables for a launch on `stream`: prepared on demand unless the stream is
 // being captured.
-feint_status tables_for_launch(int p, hipStream_t stream, const DevTables **out) {
-    const DevTables *T = find_tables(p);
+feint_status tables_for_launch(int p, hipStream_t stream, const DevTables **out, int rule) {
+    const DevTables *T = find_tables(p, rule);
     if (!T) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         hipError_t e = hipStreamIsCapturing(stream, &cs);
         if (e != hipSuccess) { set_error("hipStreamIsCapturing", e); return FEINT_ERR_HIP; }
         if (cs != hipStreamCaptureStatusNone) return FEINT_ERR_NOT_PREPARED;
-        feint_status s = prepare_tables(p);
+        feint_status s = prepare_tables(p, rule);
         if (s != FEINT_OK) return s;
-        T = find_tables(p);
+        T = find_tables(p, rule);
     }
     *out = T;
     return FEINT_OK;
@@ -130,7 +132,8 @@ void fill_fwd_params(FwdParams &prm, const feint_elements *el, int form, const D
     prm.f16_shift = T->f16_shift;
 }
 
-const FwdVariant *fwd_variants(int form, int p, int *count) {
+const FwdVariant *fwd_variants(int form, int p, int *count, int rule) {
+    if (rule == FEINT_RULE_SYMMETRIC) return fwd_variants_sym(form, p, count);
     switch (form) {
     case FEINT_FP64: return fwd_variants_f64(p, count);
     case FEINT_FP32: return fwd_variants_f32(p, count);
@@ -141,14 +144,14 @@ const FwdVariant *fwd_variants(int form, int p, int *count) {
     return nullptr;
 }
 
-const FwdVariant *chosen_variant(int p, int form) {
+const FwdVariant *chosen_variant(int p, int form, int rule) {
     int cnt = 0;
-    const FwdVariant *v = fwd_variants(form, p, &cnt);
+    const FwdVariant *v = fwd_variants(form, p, &cnt, rule);
     if (!v || cnt == 0) return nullptr;
     int t;
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        t = g_tile[p][form];
+        t = g_tile[rule][p][form];
     }
     return &v[(t >= 0 && t < cnt) ? t : 0];
 }
@@ -177,76 +180,94 @@ size_t feint_elem_size(feint_form form) {
     return form == FEINT_FP64 ? 8 : 4;
 }
 
-feint_status feint_prepare(int p) { return prepare_tables(p); }
+feint_status feint_prepare(int p) { return prepare_tables(p, FEINT_RULE_COLLAPSED); }
+
+int feint_nq_rule(int p, feint_rule rule) {
+    return (p < 1 || p > kMaxP || !valid_rule(rule)) ? -1 : nq_rule_of(p, rule);
+}
+
+feint_status feint_prepare_rule(int p, feint_rule rule) { return prepare_tables(p, rule); }
+
+feint_status feint_rule_points(int p, feint_rule rule, double *pts, int64_t cap) {
+    if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
+    if (!valid_rule(rule) || !pts || cap < nq_rule_of(p, rule)) return FEINT_ERR_INVALID_ARG;
+    std::vector<double> qw;
+    rule_points(p, rule, qw);
+    std::memcpy(pts, qw.data(), qw.size() * sizeof(double));
+    return FEINT_OK;
+}
+
+feint_status feint_integrate_rule(const feint_elements *el, const feint_fields *fl, int p, feint_form form,
+                                  feint_rule rule, void *A, void *b, double *xq, uint32_t *dev_status,
+                                  void *stream) {
+    if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
+    if (!valid_form(form)) return FEINT_ERR_UNSUPPORTED_FORM;
+    if (!valid_rule(rule) || (el == nullptr) == (fl == nullptr)) return FEINT_ERR_INVALID_ARG;
+    feint_elements cel;
+    if (el) {
+        feint_status s = check_elements(el);
+        if (s != FEINT_OK) return s;
+        cel = *el;
+    } else {
+        if (fl->ne < 0) return FEINT_ERR_INVALID_ARG;
+        if (fl->ne > 0 && (!fl->coords || !fl->D || !fl->beta || !fl->c || !fl->f)) return FEINT_ERR_INVALID_ARG;
+        cel = {fl->coords, nullptr, nullptr, nullptr, nullptr, fl->ne};
+    }
+    if (cel.ne == 0) return FEINT_OK;
+    if (!A || !b) return FEINT_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const DevTables *T = nullptr;
+    feint_status s = tables_for_launch(p, st, &T, rule);
+    if (s != FEINT_OK) return s;
+    FwdParams prm;
+    fill_fwd_params(prm, &cel, form, T);
+    if (fl) { prm.fD = fl->D; prm.fbeta = fl->beta; prm.fc = fl->c; prm.ff = fl->f; }
+    prm.A = A; prm.b = b; prm.xq = xq; prm.status = dev_status;
+    const FwdVariant *v = chosen_variant(p, form, rule);
+    if (!v) return FEINT_ERR_UNSUPPORTED_FORM;
+    return launch_forward(prm, v, st);
+}
 
 feint_status feint_integrate_fields(const feint_fields *fl, int p, feint_form form, void *A, void *b,
                                     double *xq, uint32_t *dev_status, void *stream) {
-    if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
-    if (!valid_form(form)) return FEINT_ERR_UNSUPPORTED_FORM;
-    if (!fl || fl->ne < 0) return FEINT_ERR_INVALID_ARG;
-    if (fl->ne == 0) return FEINT_OK;
-    if (!fl->coords || !fl->D || !fl->beta || !fl->c || !fl->f || !A || !b) return FEINT_ERR_INVALID_ARG;
-    hipStream_t st = (hipStream_t)stream;
-    const DevTables *T = nullptr;
-    feint_status s = tables_for_launch(p, st, &T);
-    if (s != FEINT_OK) return s;
-    feint_elements el = {fl->coords, nullptr, nullptr, nullptr, nullptr, fl->ne};
-    FwdParams prm;
-    fill_fwd_params(prm, &el, form, T);
-    prm.fD = fl->D; prm.fbeta = fl->beta; prm.fc = fl->c; prm.ff = fl->f;
-    prm.A = A; prm.b = b; prm.xq = xq; prm.status = dev_status;
-    const FwdVariant *v = chosen_variant(p, form);
-    if (!v) return FEINT_ERR_UNSUPPORTED_FORM;
-    return launch_forward(prm, v, st);
+    if (!fl) return FEINT_ERR_INVALID_ARG;
+    return feint_integrate_rule(nullptr, fl, p, form, FEINT_RULE_COLLAPSED, A, b, xq, dev_status, stream);
 }
 
 feint_status feint_integrate(const feint_elements *el, int p, feint_form form, void *A, void *b,
                              double *xq, uint32_t *dev_status, void *stream) {
-    if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
-    if (!valid_form(form)) return FEINT_ERR_UNSUPPORTED_FORM;
-    feint_status s = check_elements(el);
-    if (s != FEINT_OK) return s;
-    if (el->ne == 0) return FEINT_OK;
-    if (!A || !b) return FEINT_ERR_INVALID_ARG;
-    hipStream_t st = (hipStream_t)stream;
-    const DevTables *T = nullptr;
-    s = tables_for_launch(p, st, &T);
-    if (s != FEINT_OK) return s;
-    FwdParams prm;
-    fill_fwd_params(prm, el, form, T);
-    prm.A = A; prm.b = b; prm.xq = xq; prm.status = dev_status;
-    const FwdVariant *v = chosen_variant(p, form);
-    if (!v) return FEINT_ERR_UNSUPPORTED_FORM;
-    return launch_forward(prm, v, st);
+    if (!el) return FEINT_ERR_INVALID_ARG;
+    return feint_integrate_rule(el, nullptr, p, form, FEINT_RULE_COLLAPSED, A, b, xq, dev_status, stream);
 }
 
-int feint_tile_count(int p, feint_form form) {
+int feint_rule_tile_count(int p, feint_form form, feint_rule rule) {
     int cnt = 0;
-    if (p < 1 || p > kMaxP || !valid_form(form)) return 0;
-    fwd_variants(form, p, &cnt);
+    if (p < 1 || p > kMaxP || !valid_form(form) || !valid_rule(rule)) return 0;
+    fwd_variants(form, p, &cnt, rule);
     return cnt;
 }
 
-int feint_tile_get(int p, feint_form form) {
-    if (p < 1 || p > kMaxP || !valid_form(form)) return -1;
+int feint_rule_tile_get(int p, feint_form form, feint_rule rule) {
+    if (p < 1 || p > kMaxP || !valid_form(form) || !valid_rule(rule)) return -1;
     std::lock_guard<std::mutex> lk(g_mu);
-    return g_tile[p][form];
+    return g_tile[rule][p][form];
 }
 
-feint_status feint_tile_set(int p, feint_form form, int tile) {
+feint_status feint_rule_tile_set(int p, feint_form form, feint_rule rule, int tile) {
     if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
     if (!valid_form(form)) return FEINT_ERR_UNSUPPORTED_FORM;
-    if (tile < 0 || tile >= feint_tile_count(p, form)) return FEINT_ERR_INVALID_ARG;
+    if (!valid_rule(rule) || tile < 0 || tile >= feint_rule_tile_count(p, form, rule)) return FEINT_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(g_mu);
-    g_tile[p][form] = tile;
+    g_tile[rule][p][form] = tile;
     return FEINT_OK;
 }
 
-feint_status feint_tile_describe(int p, feint_form form, int tile, char *buf, size_t len) {
+feint_status feint_rule_tile_describe(int p, feint_form form, feint_rule rule, int tile, char *buf, size_t len) {
     int cnt = 0;
     if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
     if (!valid_form(form)) return FEINT_ERR_UNSUPPORTED_FORM;
-    const FwdVariant *v = fwd_variants(form, p, &cnt);
+    if (!valid_rule(rule)) return FEINT_ERR_INVALID_ARG;
+    const FwdVariant *v = fwd_variants(form, p, &cnt, rule);
     if (!buf || tile < 0 || tile >= cnt) return FEINT_ERR_INVALID_ARG;
     if (v[tile].staged == 3)
         std::snprintf(buf, len, "v%d%s", v[tile].tn, v[tile].minw > 1 ? "o2" : "");
@@ -257,22 +278,41 @@ feint_status feint_tile_describe(int p, feint_form form, int tile, char *buf, si
     return FEINT_OK;
 }
 
-feint_status feint_autotune(const feint_elements *el, int p, feint_form form, void *A, void *b, int reps,
-                            double *best_ms, void *stream) {
+int feint_tile_count(int p, feint_form form) { return feint_rule_tile_count(p, form, FEINT_RULE_COLLAPSED); }
+int feint_tile_get(int p, feint_form form) { return feint_rule_tile_get(p, form, FEINT_RULE_COLLAPSED); }
+feint_status feint_tile_set(int p, feint_form form, int tile) {
+    return feint_rule_tile_set(p, form, FEINT_RULE_COLLAPSED, tile);
+}
+feint_status feint_tile_describe(int p, feint_form form, int tile, char *buf, size_t len) {
+    return feint_rule_tile_describe(p, form, FEINT_RULE_COLLAPSED, tile, buf, len);
+}
+
+feint_status feint_autotune_rule(const feint_elements *el, const feint_fields *fl, int p, feint_form form,
+                                 feint_rule rule, void *A, void *b, int reps, double *best_ms, void *stream) {
     if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
     if (!valid_form(form)) return FEINT_ERR_UNSUPPORTED_FORM;
-    feint_status s = check_elements(el);
-    if (s != FEINT_OK) return s;
-    if (!A || !b || el->ne == 0 || reps < 1) return FEINT_ERR_INVALID_ARG;
+    if (!valid_rule(rule) || (el == nullptr) == (fl == nullptr) || reps < 1 || !A || !b) return FEINT_ERR_INVALID_ARG;
+    feint_elements cel;
+    if (el) {
+        feint_status s = check_elements(el);
+        if (s != FEINT_OK) return s;
+        cel = *el;
+    } else {
+        if (fl->ne < 0 || (fl->ne > 0 && (!fl->coords || !fl->D || !fl->beta || !fl->c || !fl->f)))
+            return FEINT_ERR_INVALID_ARG;
+        cel = {fl->coords, nullptr, nullptr, nullptr, nullptr, fl->ne};
+    }
+    if (cel.ne == 0) return FEINT_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
     const DevTables *T = nullptr;
-    s = tables_for_launch(p, st, &T);
+    feint_status s = tables_for_launch(p, st, &T, rule);
     if (s != FEINT_OK) return s;
     FwdParams prm;
-    fill_fwd_params(prm, el, form, T);
+    fill_fwd_params(prm, &cel, form, T);
+    if (fl) { prm.fD = fl->D; prm.fbeta = fl->beta; prm.fc = fl->c; prm.ff = fl->f; }
     prm.A = A; prm.b = b;
     int cnt = 0;
-    const FwdVariant *v = fwd_variants(form, p, &cnt);
+    const FwdVariant *v = fwd_variants(form, p, &cnt, rule);
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return FEINT_ERR_HIP;
     int best = 0;
@@ -294,10 +334,16 @@ feint_status feint_autotune(const feint_elements *el, int p, feint_form form, vo
     if (s != FEINT_OK) return s;
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        g_tile[p][form] = best;
+        g_tile[rule][p][form] = best;
     }
     if (best_ms) *best_ms = best_t;
     return FEINT_OK;
+}
+
+feint_status feint_autotune(const feint_elements *el, int p, feint_form form, void *A, void *b, int reps,
+                            double *best_ms, void *stream) {
+    if (!el) return FEINT_ERR_INVALID_ARG;
+    return feint_autotune_rule(el, nullptr, p, form, FEINT_RULE_COLLAPSED, A, b, reps, best_ms, stream);
 }
 
 const char *feint_status_string(feint_status s) {

@@ -10,7 +10,7 @@ namespace feint {
 // Device copy of the tables of one degree (one allocation, sub-buffers
 // 256-byte aligned).
 struct DevTables {
-    int p, n, npad, nq, nqp, nkb, f16_shift;
+    int p, rule, n, npad, nq, nqp, nkb, f16_shift;
     float bmax;
     const double *qw, *B64, *BT64;
     const float *B32, *BT32, *Bc32;
@@ -20,12 +20,12 @@ struct DevTables {
 };
 
 void set_error(const char *what, hipError_t e);
-feint_status prepare_tables(int p);
-const DevTables *find_tables(int p);
-feint_status tables_for_launch(int p, hipStream_t stream, const DevTables **out);
+feint_status prepare_tables(int p, int rule = 0);
+const DevTables *find_tables(int p, int rule = 0);
+feint_status tables_for_launch(int p, hipStream_t stream, const DevTables **out, int rule = 0);
 feint_status check_elements(const feint_elements *el);
 void fill_fwd_params(FwdParams &prm, const feint_elements *el, int form, const DevTables *T);
-const FwdVariant *chosen_variant(int p, int form);
+const FwdVariant *chosen_variant(int p, int form, int rule = 0);
 feint_status launch_forward(const FwdParams &prm, const FwdVariant *v, hipStream_t stream);
 
 }  // namespace feint

@@ -17,6 +17,14 @@ constexpr int WAVE = 64;
 
 __host__ __device__ constexpr int c_nshp(int p) { return (p + 1) * (p + 1) * (p + 2) / 2; }
 __host__ __device__ constexpr int c_nq(int p) { return (p + 1) * (p + 1) * (p + 1); }
+// Points of the fully symmetric triangle rule of degree 2p (3, 6, 12, 16, 25,
+// 33, 42 for p = 1..7) and of the prism rule R: 0 = collapsed Gauss
+// (p+1)^3, 1 = symmetric triangle rule x (p+1) Gauss points in zeta (the
+// point counts of the paper's Table 3).
+__host__ __device__ constexpr int c_ntri_sym(int p) {
+    return p == 1 ? 3 : p == 2 ? 6 : p == 3 ? 12 : p == 4 ? 16 : p == 5 ? 25 : p == 6 ? 33 : 42;
+}
+__host__ __device__ constexpr int c_nq_rule(int p, int r) { return r == 0 ? c_nq(p) : c_ntri_sym(p) * (p + 1); }
 __host__ __device__ constexpr int c_pad16(int n) { return (n + 15) / 16 * 16; }
 __host__ __device__ constexpr int c_pad8(int n) { return (n + 7) / 8 * 8; }
 __host__ __device__ constexpr int c_cdiv(int a, int b) { return (a + b - 1) / b; }

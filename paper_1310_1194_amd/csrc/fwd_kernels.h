@@ -52,8 +52,16 @@ __device__ inline int64_t offb_of(const FwdParams &prm, int64_t e, int n) {
 // coefficients unless the launch carries vertex fields.
 __device__ inline void load_elem_fwd(const FwdParams &prm, int64_t e, ElemIn &E) {
     if (prm.fD) {
+        // every member defined on both paths: a member left unset on one of
+        // them keeps the whole struct out of registers (private memory)
 #pragma unroll
         for (int i = 0; i < 18; ++i) E.X[i] = prm.coords[18 * e + i];
+#pragma unroll
+        for (int m = 0; m < 9; ++m) E.D[m] = 0.0;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) E.be[m] = 0.0;
+        E.c = 0.0;
+        E.f = 0.0;
     } else {
         load_elem(prm.coords, prm.D, prm.beta, prm.c, prm.f, e, E);
     }
@@ -96,9 +104,9 @@ template <int P> struct LoadCol {
 // ---------------------------------------------------------------------------
 // 16x16x4 forms (FP64, FP32): one point (4 K-rows) per MFMA.
 // ---------------------------------------------------------------------------
-template <int P, typename T, int TM, int TN>
+template <int P, typename T, int TM, int TN, int R = 0>
 struct K4 {
-    static constexpr int N = c_nshp(P), NP = c_pad16(N), NT = NP / 16, NQ = c_nq(P);
+    static constexpr int N = c_nshp(P), NP = c_pad16(N), NT = NP / 16, NQ = c_nq_rule(P, R);
     static constexpr int BM = c_cdiv(NT, TM), BN = c_cdiv(NT, TN), NBLK = BM * BN;
     static constexpr int EPI = 1;                      // element slots per work item
     static constexpr int NBR = c_cdiv(TM * 16, 64);   // load-vector rows per lane
@@ -255,9 +263,9 @@ struct K4 {
 // 2^f16_shift and Y by a per-element power of two so that both use the
 // normal range, and unscales exactly at the store.
 // ---------------------------------------------------------------------------
-template <int P, int FORM, int TM, int TN>
+template <int P, int FORM, int TM, int TN, int R = 0>
 struct K32 {
-    static constexpr int N = c_nshp(P), NP = c_pad16(N), NT = NP / 16, NQ = c_nq(P);
+    static constexpr int N = c_nshp(P), NP = c_pad16(N), NT = NP / 16, NQ = c_nq_rule(P, R);
     static constexpr int NQP = c_pad8(NQ);
     static constexpr int BM = c_cdiv(NT, TM), BN = c_cdiv(NT, TN), NBLK = BM * BN;
     static constexpr int EPI = 1;

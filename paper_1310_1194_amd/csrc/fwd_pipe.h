@@ -17,9 +17,9 @@
 
 namespace feint {
 
-template <int P, int FORM, int TM, int TN>
+template <int P, int FORM, int TM, int TN, int R = 0>
 struct K32P {
-    static constexpr int N = c_nshp(P), NP = c_pad16(N), NT = NP / 16, NQ = c_nq(P);
+    static constexpr int N = c_nshp(P), NP = c_pad16(N), NT = NP / 16, NQ = c_nq_rule(P, R);
     static constexpr int NQP = c_pad8(NQ), NKB = NQP / 8;
     static constexpr int BM = c_cdiv(NT, TM), BN = c_cdiv(NT, TN), NBLK = BM * BN;
     static constexpr int EPI = 1;
@@ -153,7 +153,7 @@ struct K32P {
             y[0] = pw.za;
             y[4] = pw.zb;
         }
-        K32<P, FORM, TM, TN>::split8(y, yh, yl);
+        K32<P, FORM, TM, TN, R>::split8(y, yh, yl);
     }
 
     // The three products of a tile go to the same accumulator; they are issued

@@ -26,20 +26,30 @@ template <class KER>
 int64_t items_of(int64_t ne) { return items_for<KER>(ne); }
 
 // U: unstaged (each wave reads the table through L2); S: LDS-staged.
-// W: minimum waves per SIMD asked of the register allocator.
-#define FEINT_K4U(P, T, TM, TN, W) \
-    FwdVariant{TM, TN, 0, W, &launch_direct<K4<P, T, TM, TN>, W>, &items_of<K4<P, T, TM, TN>>}
-#define FEINT_K4S(P, T, TM, TN, SP, W) \
-    FwdVariant{TM, TN, 1, W, &launch_staged<K4S<P, T, TM, TN, SP>, W>, &items_of<K4S<P, T, TM, TN, SP>>}
-#define FEINT_K32U(P, F, TM, TN, W) \
-    FwdVariant{TM, TN, 0, W, &launch_direct<K32<P, F, TM, TN>, W>, &items_of<K32<P, F, TM, TN>>}
+// W: minimum waves per SIMD asked of the register allocator.  R: quadrature
+// rule (0 = collapsed Gauss, 1 = symmetric triangle rule x Gauss in zeta);
+// the forms without _R compile the collapsed rule.
+#define FEINT_K4U_R(P, T, TM, TN, W, R) \
+    FwdVariant{TM, TN, 0, W, &launch_direct<K4<P, T, TM, TN, R>, W>, &items_of<K4<P, T, TM, TN, R>>}
+#define FEINT_K4S_R(P, T, TM, TN, SP, W, R) \
+    FwdVariant{TM, TN, 1, W, &launch_staged<K4S<P, T, TM, TN, SP, R>, W>, &items_of<K4S<P, T, TM, TN, SP, R>>}
+#define FEINT_K32U_R(P, F, TM, TN, W, R) \
+    FwdVariant{TM, TN, 0, W, &launch_direct<K32<P, F, TM, TN, R>, W>, &items_of<K32<P, F, TM, TN, R>>}
 // V: vector-ALU kernel, LPE lanes per element (tm = 0, tn = LPE, staged = 3).
-#define FEINT_KV(P, T, LPE, W) \
-    FwdVariant{0, LPE, 3, W, &launch_direct<KV<P, T, LPE>, W>, &items_of<KV<P, T, LPE>>}
+#define FEINT_KV_R(P, T, LPE, W, R) \
+    FwdVariant{0, LPE, 3, W, &launch_direct<KV<P, T, LPE, R>, W>, &items_of<KV<P, T, LPE, R>>}
 // P: software-pipelined split kernel (staged = 4).
-#define FEINT_K32P(P, F, TM, TN, W) \
-    FwdVariant{TM, TN, 4, W, &launch_direct<K32P<P, F, TM, TN>, W>, &items_of<K32P<P, F, TM, TN>>}
-#define FEINT_K32S(P, F, TM, TN, SY, W) \
-    FwdVariant{TM, TN, 1 + !(SY), W, &launch_staged<K32S<P, F, TM, TN, SY>, W>, &items_of<K32S<P, F, TM, TN, SY>>}
+#define FEINT_K32P_R(P, F, TM, TN, W, R) \
+    FwdVariant{TM, TN, 4, W, &launch_direct<K32P<P, F, TM, TN, R>, W>, &items_of<K32P<P, F, TM, TN, R>>}
+#define FEINT_K32S_R(P, F, TM, TN, SY, W, R) \
+    FwdVariant{TM, TN, 1 + !(SY), W, &launch_staged<K32S<P, F, TM, TN, SY, R>, W>, \
+               &items_of<K32S<P, F, TM, TN, SY, R>>}
+
+#define FEINT_K4U(P, T, TM, TN, W) FEINT_K4U_R(P, T, TM, TN, W, 0)
+#define FEINT_K4S(P, T, TM, TN, SP, W) FEINT_K4S_R(P, T, TM, TN, SP, W, 0)
+#define FEINT_K32U(P, F, TM, TN, W) FEINT_K32U_R(P, F, TM, TN, W, 0)
+#define FEINT_KV(P, T, LPE, W) FEINT_KV_R(P, T, LPE, W, 0)
+#define FEINT_K32P(P, F, TM, TN, W) FEINT_K32P_R(P, F, TM, TN, W, 0)
+#define FEINT_K32S(P, F, TM, TN, SY, W) FEINT_K32S_R(P, F, TM, TN, SY, W, 0)
 
 }  // namespace feint

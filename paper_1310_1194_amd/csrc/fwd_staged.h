@@ -44,9 +44,9 @@ struct StageCopy {
 // ---------------------------------------------------------------------------
 // 16x16x4 forms (FP64, FP32), stages of SP points (SP divides 64).
 // ---------------------------------------------------------------------------
-template <int P, typename T, int TM, int TN, int SP>
+template <int P, typename T, int TM, int TN, int SP, int R = 0>
 struct K4S {
-    static constexpr int N = c_nshp(P), NP = c_pad16(N), NT = NP / 16, NQ = c_nq(P);
+    static constexpr int N = c_nshp(P), NP = c_pad16(N), NT = NP / 16, NQ = c_nq_rule(P, R);
     static constexpr int BM = c_cdiv(NT, TM), BN = c_cdiv(NT, TN), NBLK = BM * BN;
     static constexpr int EPI = 1;
     static constexpr int NBR = c_cdiv(TM * 16, 64);
@@ -202,9 +202,9 @@ struct K4S {
 // [8][NP][4] the B fragments are formed from (otherwise those are read from
 // global memory, for degrees whose double-buffered stage would not fit).
 // ---------------------------------------------------------------------------
-template <int P, int FORM, int TM, int TN, bool SY>
+template <int P, int FORM, int TM, int TN, bool SY, int R = 0>
 struct K32S {
-    static constexpr int N = c_nshp(P), NP = c_pad16(N), NT = NP / 16, NQ = c_nq(P);
+    static constexpr int N = c_nshp(P), NP = c_pad16(N), NT = NP / 16, NQ = c_nq_rule(P, R);
     static constexpr int NQP = c_pad8(NQ), NKB = NQP / 8;
     static constexpr int BM = c_cdiv(NT, TM), BN = c_cdiv(NT, TN), NBLK = BM * BN;
     static constexpr int EPI = 1;
@@ -245,7 +245,7 @@ struct K32S {
     template <int TMV, int TNV>
     __device__ static void body(const FwdParams &prm, int64_t slot, int blk, int bi, int bj, int wave, bool active, Smem &sm) {
         constexpr int NBRV = c_cdiv(TMV * 16, 64);
-        typedef K32<P, FORM, TMV, TNV> Plain;
+        typedef K32<P, FORM, TMV, TNV, R> Plain;
         const int lane = threadIdx.x & 63;
         const int i16 = lane & 15, kg = lane >> 4;
         const int a0 = bi * TM * 16, b0 = bj * TN * 16;

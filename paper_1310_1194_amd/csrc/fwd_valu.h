@@ -35,9 +35,9 @@ __device__ inline const T *uniform_ptr(const T *p) {
     return (const T *)(uintptr_t)(((uint64_t)hi << 32) | lo);
 }
 
-template <int P, typename T, int LPE>
+template <int P, typename T, int LPE, int R = 0>
 struct KV {
-    static constexpr int N = c_nshp(P), NP = c_pad16(N), NQ = c_nq(P);
+    static constexpr int N = c_nshp(P), NP = c_pad16(N), NQ = c_nq_rule(P, R);
     static constexpr int EPW = 64 / LPE;        // element slots per work item
     static constexpr int EPI = EPW, NBLK = 1;
     static constexpr int NPT = EPW * NQ;        // (element, point) pairs per item

@@ -40,8 +40,10 @@ struct FwdVariant {
     int64_t (*items)(int64_t ne);   // work items (waves) of a launch over ne elements
 };
 
-// Registry per form (0 FP64, 1 FP32, 2 BF16X3, 3 FP16X3); p in 1..7.
-const FwdVariant *fwd_variants(int form, int p, int *count);
+// Registry per form (0 FP64, 1 FP32, 2 BF16X3, 3 FP16X3); p in 1..7; rule 0
+// (collapsed Gauss) or 1 (symmetric triangle rule x Gauss in zeta).
+const FwdVariant *fwd_variants(int form, int p, int *count, int rule = 0);
+const FwdVariant *fwd_variants_sym(int form, int p, int *count);
 const FwdVariant *fwd_variants_f64(int p, int *count);
 const FwdVariant *fwd_variants_f32(int p, int *count);
 const FwdVariant *fwd_variants_bf16(int p, int *count);

@@ -238,6 +238,114 @@ void gauss_legendre_gw(int n, double *x, double *w) {
     }
 }
 
+namespace {
+// Fully symmetric triangle rules of degree 2p (p = 1..7; 3, 6, 12, 16, 25,
+// 33, 42 points): orbit weights (summing to the triangle area 1/2) and
+// barycentric parameters -- centroid weights; (w, a) of each 3-orbit
+// (a, a, 1-2a); (w, a, b) of each 6-orbit (a, b, 1-a-b), a < b < 1-a-b.  They
+// solve the moment equations sum_q w_q xi1^i xi2^j = i! j! / (i+j+2)!
+// (i + j <= 2p), polished in 50-digit arithmetic; every weight is positive and
+// every point interior.  For p <= 4 these are the classical rules; above, the
+// equations have several such solutions and these are the ones taken.
+// p = 1: 0 centroid, 1 3-orbits, 0 6-orbits
+const long double sym1_s3[] = {
+    0.166666666666666666667L, 0.166666666666666666667L};
+// p = 2: 0 centroid, 2 3-orbits, 0 6-orbits
+const long double sym2_s3[] = {
+    0.0549758718276609338192L, 0.0915762135097707434596L,
+    0.111690794839005732848L, 0.445948490915964886318L};
+// p = 3: 0 centroid, 2 3-orbits, 1 6-orbits
+const long double sym3_s3[] = {
+    0.0254224531851034084605L, 0.0630890144915022283403L,
+    0.0583931378631896830126L, 0.249286745170910421292L};
+const long double sym3_s6[] = {
+    0.0414255378091867875968L, 0.0531450498448169473532L, 0.310352451033784405417L};
+// p = 4: 1 centroid, 3 3-orbits, 1 6-orbits
+const long double sym4_c[] = {0.0721578038388935841255L};
+const long double sym4_s3[] = {
+    0.0162292488115990401555L, 0.0505472283170309754584L,
+    0.0516086852673591251409L, 0.170569307751760206622L,
+    0.0475458171336423123969L, 0.459292588292723156029L};
+const long double sym4_s6[] = {
+    0.0136151570872174971324L, 0.00839477740995760533721L, 0.263112829634638113422L};
+// p = 5: 1 centroid, 2 3-orbits, 3 6-orbits
+const long double sym5_c[] = {0.0399472523706198539156L};
+const long double sym5_s3[] = {
+    0.00411190934523209775932L, 0.0233088675100001907145L,
+    0.0355619011161886673196L, 0.42508621060209057297L};
+const long double sym5_s6[] = {
+    0.0186799281171526384131L, 0.0299460319541708865031L, 0.358740141864431464578L,
+    0.0154433284422819943913L, 0.0356325595875034813206L, 0.143295370426867145306L,
+    0.0227152961480850090035L, 0.147925626209534437353L, 0.223766973576973006226L};
+// p = 6: 0 centroid, 5 3-orbits, 3 6-orbits
+const long double sym6_s3[] = {
+    0.00396582125498681922966L, 0.0246463634363355947667L,
+    0.0142430260344387724998L, 0.109257827659354290584L,
+    0.0312706065979513802347L, 0.271462507014926084878L,
+    0.0249591674640304710595L, 0.440111648658593111013L,
+    0.0121334190407260165754L, 0.488203750945541551778L};
+const long double sym6_s6[] = {
+    0.00754183878825571929293L, 0.0213824902561705895942L, 0.127279717233589368788L,
+    0.0108917925193037789663L, 0.0230341563552671394816L, 0.291655679738340960534L,
+    0.0216136818297071052746L, 0.116296019677926586631L, 0.255454228638517346531L};
+// p = 7: 0 centroid, 6 3-orbits, 4 6-orbits
+const long double sym7_s3[] = {
+    0.00246170180120004084091L, 0.0193909612487010481783L,
+    0.00721684983488833380085L, 0.0617998830908726012675L,
+    0.0210812943684965087691L, 0.177205532412543436957L,
+    0.0258870522536457931574L, 0.273477528308838659755L,
+    0.0163941767720626753207L, 0.417644719340453922509L,
+    0.0109417906847144453204L, 0.488963910362178638677L};
+const long double sym7_s6[] = {
+    0.00250511441925033588493L, 0.00126833093287202508725L, 0.118974497696956845398L,
+    0.00721815405676692024804L, 0.0146469500556544096705L, 0.298372882136257752971L,
+    0.0123328766062818369814L, 0.0571247574036479390357L, 0.172266687821355578375L,
+    0.0192857553935303416142L, 0.0929162493569718247582L, 0.336861459796345001744L};
+
+struct SymOrbits {
+    int n0, n1, n2;
+    const long double *c, *s3, *s6;
+};
+
+SymOrbits sym_orbits(int p) {
+    switch (p) {
+    case 1: return {0, 1, 0, nullptr, sym1_s3, nullptr};
+    case 2: return {0, 2, 0, nullptr, sym2_s3, nullptr};
+    case 3: return {0, 2, 1, nullptr, sym3_s3, sym3_s6};
+    case 4: return {1, 3, 1, sym4_c, sym4_s3, sym4_s6};
+    case 5: return {1, 2, 3, sym5_c, sym5_s3, sym5_s6};
+    case 6: return {0, 5, 3, nullptr, sym6_s3, sym6_s6};
+    case 7: return {0, 6, 4, nullptr, sym7_s3, sym7_s6};
+    }
+    throw std::runtime_error("degree out of range");
+}
+}  // namespace
+
+void symmetric_triangle_rule(int p, std::vector<double> &xi1, std::vector<double> &xi2, std::vector<double> &w) {
+    const SymOrbits o = sym_orbits(p);
+    xi1.clear(); xi2.clear(); w.clear();
+    // barycentric (l0, l1, l2) -> (xi1, xi2) = (l1, l2)
+    auto put = [&](long double wt, long double l1, long double l2) {
+        xi1.push_back((double)l1); xi2.push_back((double)l2); w.push_back((double)wt);
+    };
+    for (int i = 0; i < o.n0; ++i) put(o.c[i], 1.0L / 3, 1.0L / 3);
+    for (int i = 0; i < o.n1; ++i) {
+        const long double wt = o.s3[2 * i], a = o.s3[2 * i + 1], c = 1.0L - 2 * a;
+        put(wt, a, c);        // (a, a, c)
+        put(wt, c, a);        // (a, c, a)
+        put(wt, a, a);        // (c, a, a)
+    }
+    for (int i = 0; i < o.n2; ++i) {
+        const long double wt = o.s6[3 * i], a = o.s6[3 * i + 1], b = o.s6[3 * i + 2], c = 1.0L - a - b;
+        put(wt, b, c);        // (a, b, c)
+        put(wt, c, b);        // (a, c, b)
+        put(wt, a, c);        // (b, a, c)
+        put(wt, c, a);        // (b, c, a)
+        put(wt, a, b);        // (c, a, b)
+        put(wt, b, a);        // (c, b, a)
+    }
+}
+
 void gauss_lobatto_nodes(int p, double *x) {
     x[0] = -1.0;
     x[p] = 1.0;
@@ -255,32 +363,56 @@ void lagrange_prism_eval(int p, const double *xi, double *phi, double *dphi) {
     eval_modal(mb, xi, phi, dphi);
 }
 
-HostTables build_tables(int p) {
+void rule_points(int p, int rule, std::vector<double> &qw) {
     if (p < 1 || p > kMaxP) throw std::runtime_error("degree out of range");
-    HostTables T;
-    T.p = p;
-    T.n = nshp_of(p);
-    T.npad = pad16(T.n);
-    T.nq = nq_of(p);
-    T.nqp = pad8(T.nq);
-    T.nkb = T.nqp / 8;
-    const int n1 = p + 1, n = T.n, np = T.npad;
+    if (rule != 0 && rule != 1) throw std::runtime_error("unknown quadrature rule");
+    const int n1 = p + 1;
     double g[kMaxP + 1], gw[kMaxP + 1];
     gauss_legendre_gw(n1, g, gw);
-    T.qw.assign((size_t)T.nqp * 4, 0.0);
+    qw.assign((size_t)nq_rule_of(p, rule) * 4, 0.0);
+    if (rule == 0) {
+        for (int k = 0; k < n1; ++k)
+            for (int j = 0; j < n1; ++j)
+                for (int i = 0; i < n1; ++i) {
+                    int q = (k * n1 + j) * n1 + i;
+                    qw[4 * q + 0] = (1.0 + g[i]) * (1.0 - g[j]) / 4.0;
+                    qw[4 * q + 1] = (1.0 + g[j]) / 2.0;
+                    qw[4 * q + 2] = g[k];
+                    qw[4 * q + 3] = gw[i] * gw[j] * gw[k] * (1.0 - g[j]) / 8.0;
+                }
+    } else {              // symmetric triangle rule x Gauss in zeta, q = k * ntri + t
+        std::vector<double> x1, x2, wt;
+        symmetric_triangle_rule(p, x1, x2, wt);
+        const int nt = (int)wt.size();
+        for (int k = 0; k < n1; ++k)
+            for (int t = 0; t < nt; ++t) {
+                const int q = k * nt + t;
+                qw[4 * q + 0] = x1[t];
+                qw[4 * q + 1] = x2[t];
+                qw[4 * q + 2] = g[k];
+                qw[4 * q + 3] = wt[t] * gw[k];
+            }
+    }
+}
+
+HostTables build_tables(int p, int rule) {
+    if (p < 1 || p > kMaxP) throw std::runtime_error("degree out of range");
+    if (rule != 0 && rule != 1) throw std::runtime_error("unknown quadrature rule");
+    HostTables T;
+    T.p = p;
+    T.rule = rule;
+    T.n = nshp_of(p);
+    T.npad = pad16(T.n);
+    T.nq = nq_rule_of(p, rule);
+    T.nqp = pad8(T.nq);
+    T.nkb = T.nqp / 8;
+    const int n = T.n, np = T.npad;
+    rule_points(p, rule, T.qw);
+    T.qw.resize((size_t)T.nqp * 4, 0.0);
     for (int q = T.nq; q < T.nqp; ++q) {      // padding points: centroid, zero weight
         T.qw[4 * q + 0] = 1.0 / 3.0;
         T.qw[4 * q + 1] = 1.0 / 3.0;
     }
-    for (int k = 0; k < n1; ++k)
-        for (int j = 0; j < n1; ++j)
-            for (int i = 0; i < n1; ++i) {
-                int q = (k * n1 + j) * n1 + i;
-                T.qw[4 * q + 0] = (1.0 + g[i]) * (1.0 - g[j]) / 4.0;
-                T.qw[4 * q + 1] = (1.0 + g[j]) / 2.0;
-                T.qw[4 * q + 2] = g[k];
-                T.qw[4 * q + 3] = gw[i] * gw[j] * gw[k] * (1.0 - g[j]) / 8.0;
-            }
     ModalBasis mb = make_modal(p);
     T.B64.assign((size_t)T.nqp * 4 * np, 0.0);
     std::vector<double> phi(n), dphi(3 * n);

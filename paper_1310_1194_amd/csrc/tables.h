@@ -14,11 +14,19 @@ constexpr int kMaxP = 7;
 inline int nshp_of(int p) { return (p + 1) * (p + 1) * (p + 2) / 2; }
 inline int ntri_of(int p) { return (p + 1) * (p + 2) / 2; }
 inline int nq_of(int p) { return (p + 1) * (p + 1) * (p + 1); }
+// Points of the symmetric triangle rule of degree 2p and of the prism rule
+// `rule` (0: collapsed Gauss (p+1)^3; 1: symmetric triangle rule x (p+1)
+// Gauss points in zeta).
+inline int ntri_sym_of(int p) {
+    static const int k[8] = {0, 3, 6, 12, 16, 25, 33, 42};
+    return (p >= 1 && p <= 7) ? k[p] : 0;
+}
+inline int nq_rule_of(int p, int rule) { return rule == 0 ? nq_of(p) : ntri_sym_of(p) * (p + 1); }
 inline int pad16(int n) { return (n + 15) / 16 * 16; }
 inline int pad8(int n) { return (n + 7) / 8 * 8; }
 
 struct HostTables {
-    int p = 0, n = 0, npad = 0, nq = 0, nqp = 0, nkb = 0;
+    int p = 0, rule = 0, n = 0, npad = 0, nq = 0, nqp = 0, nkb = 0;
     int f16_shift = 0;               // fp16 tables hold B * 2^f16_shift
     std::vector<double> qw;          // [nqp][4]  xi1, xi2, zeta, w  (padded points: w = 0)
     std::vector<double> B64;         // [nqp][4][npad]  rows: phi, d/dxi1, d/dxi2, d/dzeta
@@ -37,13 +45,21 @@ struct HostTables {
     std::vector<float> Ycf;
 };
 
-// Build every table of degree p (1..7) in FP64 on the host.
-HostTables build_tables(int p);
+// Points of the prism rule `rule` for degree p: qw [nq][4] = (xi1, xi2, zeta,
+// w); collapsed Gauss q = (k n1 + j) n1 + i, symmetric q = k ntri + t.
+void rule_points(int p, int rule, std::vector<double> &qw);
+
+// Build every table of degree p (1..7) on quadrature rule `rule` (0, 1) in
+// FP64 on the host.
+HostTables build_tables(int p, int rule = 0);
 
 // Pieces exposed for the CPU tests of the library's host logic.
 void gauss_legendre_gw(int n, double *x, double *w);     // Golub-Welsch
 void gauss_lobatto_nodes(int p, double *x);               // p+1 nodes, ascending
 // phi[n], dphi[n][3] at one reference point, through the Vandermonde construction.
 void lagrange_prism_eval(int p, const double *xi, double *phi, double *dphi);
+// Points (xi1, xi2) and weights of the symmetric triangle rule of degree 2p,
+// in orbit order (centroid, 3-orbits, 6-orbits).
+void symmetric_triangle_rule(int p, std::vector<double> &xi1, std::vector<double> &xi2, std::vector<double> &w);
 
 }  // namespace feint

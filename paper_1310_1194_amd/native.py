@@ -11,6 +11,8 @@ from pathlib import Path
 LIB_PATH = Path(__file__).resolve().parent / "libfeint.so"
 
 FORMS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3}
+# quadrature rules: (p+1)^3 collapsed Gauss; symmetric triangle rule of degree 2p x (p+1) Gauss in zeta
+RULES = {"collapsed": 0, "symmetric": 1}
 STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported degree", -3: "unsupported form",
           -4: "tables not prepared (stream is capturing)", -5: "HIP runtime error",
           -6: "batch too large for one launch"}
@@ -25,7 +27,9 @@ EXPORTS = (
     "feint_mixed_tile_set", "feint_mixed_tile_describe", "feint_tile_count", "feint_tile_get", "feint_tile_set",
     "feint_tile_describe", "feint_autotune", "feint_status_string", "feint_last_error",
     "feint_shutdown", "feint_asm_plan_create", "feint_asm_plan_info", "feint_asm_plan_pattern",
-    "feint_asm_plan_colors", "feint_assemble", "feint_asm_plan_destroy",
+    "feint_asm_plan_colors", "feint_assemble", "feint_asm_plan_destroy", "feint_nq_rule", "feint_rule_points",
+    "feint_prepare_rule", "feint_integrate_rule", "feint_rule_tile_count", "feint_rule_tile_get",
+    "feint_rule_tile_set", "feint_rule_tile_describe", "feint_autotune_rule",
 )
 
 
@@ -103,6 +107,16 @@ def lib() -> ctypes.CDLL:
             "feint_asm_plan_colors": (_i, [_vp, _vp]),
             "feint_assemble": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _i, _vp]),
             "feint_asm_plan_destroy": (None, [_vp]),
+            "feint_nq_rule": (_i, [_i, _i]),
+            "feint_rule_points": (_i, [_i, _i, _vp, _i64]),
+            "feint_prepare_rule": (_i, [_i, _i]),
+            "feint_integrate_rule": (_i, [P, ctypes.POINTER(Fields), _i, _i, _i, _vp, _vp, _vp, _vp, _vp]),
+            "feint_rule_tile_count": (_i, [_i, _i, _i]),
+            "feint_rule_tile_get": (_i, [_i, _i, _i]),
+            "feint_rule_tile_set": (_i, [_i, _i, _i, _i]),
+            "feint_rule_tile_describe": (_i, [_i, _i, _i, _i, ctypes.c_char_p, ctypes.c_size_t]),
+            "feint_autotune_rule": (_i, [P, ctypes.POINTER(Fields), _i, _i, _i, _vp, _vp, _i,
+                                         ctypes.POINTER(ctypes.c_double), _vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)

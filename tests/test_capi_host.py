@@ -127,3 +127,68 @@ def test_fields_validation():
     assert L.feint_integrate_fields(None, 3, 0, None, None, None, None, None) == -1
     empty = native.Fields(0, 0, 0, 0, 0, 0)
     assert L.feint_integrate_fields(ctypes.byref(empty), 3, 0, None, None, None, None, None) == 0
+
+
+def test_rule_counts_and_points():
+    """The library's symmetric rule (host copy, no device work): the paper's
+    point counts (Table 3 / 4 scalars per point), exact monomial integrals up
+    to degree 2p on the triangle and 2p+1 in zeta, and agreement with the
+    oracle's independently solved rule."""
+    from fractions import Fraction
+    from math import factorial
+
+    import numpy as np
+
+    import oracle
+    import paper_1310_1194_amd as F
+    L = native.lib()
+    assert [L.feint_nq_rule(p, 1) for p in range(1, 8)] == [6, 18, 48, 80, 150, 231, 336]
+    assert [L.feint_nq_rule(p, 0) for p in range(1, 8)] == [(p + 1) ** 3 for p in range(1, 8)]
+    assert L.feint_nq_rule(0, 1) == -1 and L.feint_nq_rule(3, 2) == -1
+    for p in range(1, 8):
+        q = F.rule_points(p, "symmetric")
+        assert (q[:, 3] > 0).all() and (q[:, :2] > 0).all() and (q[:, 0] + q[:, 1] < 1).all()
+        for i in range(2 * p + 1):
+            for j in range(2 * p + 1 - i):
+                for g in (0, 2 * p, 2 * p + 1):
+                    ex = Fraction(factorial(i) * factorial(j), factorial(i + j + 2)) * \
+                        (Fraction(0) if g % 2 else Fraction(2, g + 1))
+                    got = np.sum(q[:, 3] * q[:, 0] ** i * q[:, 1] ** j * q[:, 2] ** g)
+                    assert abs(got - float(ex)) < 1e-15, (p, i, j, g)
+        pts, w = oracle.prism_rule(p, "symmetric")
+        assert np.abs(q[:, :3] - pts).max() < 1e-15 and np.abs(q[:, 3] - w).max() < 1e-16
+    buf = np.zeros((5, 4))
+    assert L.feint_rule_points(1, 1, buf.ctypes.data_as(ctypes.c_void_p), 5) == -1    # too small
+    assert L.feint_rule_points(1, 3, buf.ctypes.data_as(ctypes.c_void_p), 5) == -1    # unknown rule
+    assert L.feint_rule_points(8, 1, buf.ctypes.data_as(ctypes.c_void_p), 5) == -2
+
+
+def test_rule_tiles_and_validation():
+    L = native.lib()
+    buf = ctypes.create_string_buffer(32)
+    pat = re.compile(r"(\d+x\d+(s|sa|p)?|v\d+)(o2)?")
+    for form in range(4):
+        for p in range(1, 8):
+            n = L.feint_rule_tile_count(p, form, 1)
+            assert n >= 1
+            assert L.feint_rule_tile_count(p, form, 0) == L.feint_tile_count(p, form)
+            for t in range(n):
+                assert L.feint_rule_tile_describe(p, form, 1, t, buf, 32) == 0
+                assert pat.fullmatch(buf.value.decode()), buf.value
+            assert L.feint_rule_tile_describe(p, form, 1, n, buf, 32) == -1
+            assert L.feint_rule_tile_set(p, form, 1, n) == -1
+    assert L.feint_rule_tile_count(3, 0, 5) == 0 and L.feint_rule_tile_get(3, 0, 5) == -1
+    el = _el(4)
+    fl = native.Fields(0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 4)
+    A = ctypes.c_void_p(0x2000)
+    s = ctypes.c_void_p(0)
+    # exactly one of el and fl
+    assert L.feint_integrate_rule(None, None, 3, 0, 1, A, A, None, None, s) == -1
+    assert L.feint_integrate_rule(ctypes.byref(el), ctypes.byref(fl), 3, 0, 1, A, A, None, None, s) == -1
+    assert L.feint_integrate_rule(ctypes.byref(el), None, 3, 0, 4, A, A, None, None, s) == -1     # rule
+    assert L.feint_integrate_rule(ctypes.byref(el), None, 9, 0, 1, A, A, None, None, s) == -2
+    assert L.feint_integrate_rule(ctypes.byref(el), None, 3, 6, 1, A, A, None, None, s) == -3
+    assert L.feint_integrate_rule(ctypes.byref(_el(4, null=True)), None, 3, 0, 1, A, A, None, None, s) == -1
+    assert L.feint_integrate_rule(ctypes.byref(_el(0, null=True)), None, 3, 0, 1, None, None, None, None, s) == 0
+    assert L.feint_autotune_rule(None, None, 3, 0, 1, A, A, 1, None, s) == -1
+    assert L.feint_autotune_rule(ctypes.byref(_el(0, null=True)), None, 3, 0, 1, A, A, 1, None, s) == -1
