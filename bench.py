@@ -64,7 +64,7 @@ def traffic_record(key: str, tile: str):
     return rec.get("tiles", {}).get(tile)
 
 
-def cpu_baseline(batch, p, budget_s: float, chunk: int = 4096, fields=None):
+def cpu_baseline(batch, p, budget_s: float, chunk: int = 4096, fields=None, rule=None):
     """The oracle on the host's cores over the first elements of the workload,
     chunk by chunk until about `budget_s` seconds have been spent (with vertex
     coefficient fields when `fields` = (Dv, betav, cv, fv) is given)."""
@@ -75,9 +75,10 @@ def cpu_baseline(batch, p, budget_s: float, chunk: int = 4096, fields=None):
         sub = batch.subset(sl)
         t0 = time.perf_counter()
         if fields is None:
-            A, b, _ = oracle.integrate(p, sub.coords, sub.D, sub.beta, sub.c, sub.f)
+            A, b, _ = oracle.integrate(p, sub.coords, sub.D, sub.beta, sub.c, sub.f, rule=rule)
         else:
-            A, b, _ = oracle.integrate_fields(p, sub.coords, *[np.ascontiguousarray(a[sl]) for a in fields])
+            A, b, _ = oracle.integrate_fields(p, sub.coords, *[np.ascontiguousarray(a[sl]) for a in fields],
+                                              rule=rule)
         spent += time.perf_counter() - t0
         if first is None:
             first = (A, b)
@@ -125,6 +126,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", default="forward", choices=["forward", "fields", "adjoint", "mixed", "assemble"])
     ap.add_argument("--workload", default=None)
+    ap.add_argument("--rule", default="collapsed", choices=["collapsed", "symmetric"],
+                    help="quadrature rule of the forward and fields modes")
     ap.add_argument("--forms", default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (CPU baseline and errors)")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
@@ -147,22 +150,6 @@ def main():
     return bench_forward(args, fields=args.mode == "fields")
 
 
-def tune_tiles(call, p, form, reps=2):
-    """Time every compiled variant of (p, form) through `call`, keep the fastest;
-    returns its mean ms."""
-    import torch
-    import paper_1310_1194_amd as F
-    best = (float("inf"), 0)
-    for t in range(F.tile_count(p, form)):
-        F.tile_set(p, form, t)
-        call()
-        ms, _, _ = timed(call, reps, 0)
-        best = min(best, (ms, t))
-    F.tile_set(p, form, best[1])
-    torch.cuda.synchronize()
-    return best[0]
-
-
 def bench_forward(args, fields=False):
     """Forward integration; with `fields` the coefficients are vertex fields
     evaluated at every point (feint_integrate_fields)."""
@@ -175,7 +162,8 @@ def bench_forward(args, fields=False):
     dev = torch.device("cuda:0")
     w = meshgen.WORKLOADS[args.workload]
     p = w["p"]
-    n, q = costmodel.nshp(p), costmodel.nq(p)
+    rule = args.rule
+    n, q = costmodel.nshp(p), costmodel.nq(p, rule)
     batch = meshgen.workload(args.workload)
     ne = batch.ne
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
@@ -207,19 +195,19 @@ def bench_forward(args, fields=False):
         tile_ms = None
         if not args.no_tune:
             if fields:
-                tile_ms = tune_tiles(lambda: integrate(*X, p, form, A=A, b=b), p, form)
+                tile_ms = F.autotune_fields(*X, p, form, A, b, reps=2, rule=rule)
             else:
-                tile_ms = F.autotune(*X, p, form, A, b, reps=2)
-        tile = F.tile_describe(p, form, F.tile_get(p, form))
+                tile_ms = F.autotune(*X, p, form, A, b, reps=2, rule=rule)
+        tile = F.tile_describe(p, form, F.tile_get(p, form, rule=rule), rule=rule)
         for _ in range(args.warmup):
-            integrate(*X, p, form, A=A, b=b)
+            integrate(*X, p, form, A=A, b=b, rule=rule)
         torch.cuda.synchronize()
         stream = torch.cuda.current_stream()
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
         t0 = time.perf_counter()
         ev[0].record(stream)
         for k in range(args.steps):
-            integrate(*X, p, form, A=A, b=b)
+            integrate(*X, p, form, A=A, b=b, rule=rule)
             ev[k + 1].record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -232,7 +220,7 @@ def bench_forward(args, fields=False):
                              A_sample=A[sample_idx].cpu().numpy(), b_sample=b[sample_idx].cpu().numpy())
         print(f"[bench] {form}: {ms:.3f} ms/launch (min {np.min(per):.3f}), tile {tile}", file=sys.stderr, flush=True)
 
-    fdom = costmodel.f_dom(p)
+    fdom = costmodel.f_dom(p, rule)
     in_bytes = costmodel.FIELD_INPUT_BYTES if fields else costmodel.INPUT_BYTES
     for form, r in results.items():
         es = costmodel.out_bytes(p, 8 if form == "fp64" else 4)
@@ -243,7 +231,8 @@ def bench_forward(args, fields=False):
 
     cpu = None
     if not args.no_cpu:
-        rate, done, spent, cores, (Ar, br) = cpu_baseline(batch, p, args.cpu_budget, fields=vf)
+        rate, done, spent, cores, (Ar, br) = cpu_baseline(batch, p, args.cpu_budget, fields=vf,
+                                                          rule=None if rule == "collapsed" else rule)
         cpu = {"value": rate, "unit": "elements/s", "cores": cores, "kind": "oracle",
                "sample": f"first {done} of the {ne} elements of {args.workload} "
                          f"({spent:.1f} s, FP64, OpenMP over elements)",
@@ -258,7 +247,9 @@ def bench_forward(args, fields=False):
             r["err_sample"] = m
 
     h = results[headline]
-    traffic = traffic_record(f"{'fields' if fields else 'fwd'}:{headline}:{args.workload}", results[headline]["tile"])
+    rkey = "" if rule == "collapsed" else ":" + rule
+    traffic = traffic_record(f"{'fields' if fields else 'fwd'}:{headline}:{args.workload}{rkey}",
+                             results[headline]["tile"])
     es = 8 if headline == "fp64" else 4
     alg_bytes = ne * (costmodel.fields_bytes_per_element(p, es) if fields else costmodel.bytes_per_element(p, es))
     # bound = the larger ideal time: MFMA work (three products for a split
@@ -272,8 +263,8 @@ def bench_forward(args, fields=False):
     else:
         roofline = {"bound": "mfma", "achieved": h["gflops"] / 1e3, "peak": PEAK_TFLOPS[headline],
                     "unit": "TFLOP/s", "frac": h["gflops"] / 1e3 / PEAK_TFLOPS[headline]}
-    npad, nqp = (costmodel.nshp(p) + 15) // 16 * 16, (costmodel.nq(p) + 7) // 8 * 8
-    hw_flops = products * 8.0 * npad * npad * (nqp if products == 3 else costmodel.nq(p)) * ne
+    npad, nqp = (costmodel.nshp(p) + 15) // 16 * 16, (q + 7) // 8 * 8
+    hw_flops = products * 8.0 * npad * npad * (nqp if products == 3 else q) * ne
     roofline.update({"traffic": traffic, "kernel_ms": h["kernel_ms_mean"], "flops_per_launch": fdom * ne,
                      "hw_mfma_frac": hw_flops / (h["kernel_ms_mean"] * 1e-3) / (PEAK_TFLOPS[headline] * 1e12),
                      "alg_bytes_per_launch": alg_bytes,
@@ -297,7 +288,8 @@ def bench_forward(args, fields=False):
         "vs_baseline": None,
         "dtype": DTYPE_DESC[headline],
         "data": "synthetic (seeded perturbed prism mesh and coefficients)",
-        "config": {"workload": args.workload + ("+vertex_fields" if fields else ""), "p": p, "ne": ne,
+        "config": {"workload": args.workload + ("+vertex_fields" if fields else "")
+                   + ("+symmetric_rule" if rule != "collapsed" else ""), "p": p, "ne": ne, "rule": rule,
                    "nshp": n, "nq": q, "coefficients": "vertex fields" if fields else "element constants",
                    "mesh": f"{w['nx']}x{w['ny']}x{w['nz']}", "perturbation": w["amp"], "seed": w["seed"],
                    "form": headline, "parallelism": "single GPU"},

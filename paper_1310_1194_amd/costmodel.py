@@ -26,8 +26,10 @@ def ntri(p: int) -> int:
     return (p + 1) * (p + 2) // 2
 
 
-def nq(p: int) -> int:
-    return (p + 1) ** 3
+def nq(p: int, rule: str = "collapsed") -> int:
+    """Points of the collapsed Gauss rule ((p+1)^3) or of the symmetric rule
+    (the paper's N_I)."""
+    return (p + 1) ** 3 if rule == "collapsed" else paper_nI(p)
 
 
 def paper_nI(p: int) -> int:
@@ -50,9 +52,9 @@ def paper_total_ops(p: int) -> int:
                           + paper_matrix_ops_per_point(p))
 
 
-def f_dom(p: int) -> int:
+def f_dom(p: int, rule: str = "collapsed") -> int:
     """Algorithmic flops of the contraction per element: 8 n^2 nq."""
-    return 8 * nshp(p) ** 2 * nq(p)
+    return 8 * nshp(p) ** 2 * nq(p, rule)
 
 
 def f_full(p: int) -> int:
