@@ -227,9 +227,11 @@ int feint_tile_count(int p, feint_form form);
 int feint_tile_get(int p, feint_form form);
 feint_status feint_tile_set(int p, feint_form form, int tile);
 /* Describe candidate `tile` into buf: "TMxTN" output tiles per wave, with
-   "s" (table staged in LDS), "sa" (A operands staged) or "p" (K loop
-   software-pipelined), or "vL" (vector-ALU kernel, L lanes per element);
-   "o2" marks a two-waves-per-SIMD register budget. */
+   "s" (table staged in LDS), "sa" (A operands staged), "p" (K loop
+   software-pipelined) or "c" (shape functions computed at each point from
+   their tensor-product factors, no table read: the paper's SC strategy,
+   Sec. 4), or "vL" (vector-ALU kernel, L lanes per element); "o2" marks a
+   two-waves-per-SIMD register budget. */
 feint_status feint_tile_describe(int p, feint_form form, int tile, char *buf, size_t len);
 feint_status feint_autotune(const feint_elements *el, int p, feint_form form,
                             void *A, void *b, int reps, double *best_ms, void *stream);

@@ -12,7 +12,7 @@ namespace feint {
 struct DevTables {
     int p, rule, n, npad, nq, nqp, nkb, f16_shift;
     float bmax;
-    const double *qw, *B64, *BT64;
+    const double *qw, *gll, *B64, *BT64;
     const float *B32, *BT32, *Bc32;
     const uint16_t *bf_hi, *bf_lo, *hf_hi, *hf_lo;
     const float *Ycf;

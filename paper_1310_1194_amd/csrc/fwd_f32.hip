@@ -7,19 +7,23 @@ namespace {
 const FwdVariant v1[] = {
     FEINT_KV(1, float, 8, 2),
     FEINT_KV(1, float, 6, 2),
-    FEINT_K4S(1, float, 1, 1, 8, 1)};
+    FEINT_K4S(1, float, 1, 1, 8, 1),
+    FEINT_KSC(1, float, 1, 1, 1)};
 const FwdVariant v2[] = {
     FEINT_KV(2, float, 18, 2),
     FEINT_KV(2, float, 32, 2),
-    FEINT_K4S(2, float, 2, 2, 8, 1)};
+    FEINT_K4S(2, float, 2, 2, 8, 1),
+    FEINT_KSC(2, float, 2, 2, 1)};
 const FwdVariant v3[] = {
     FEINT_K4S(3, float, 3, 3, 8, 1),
     FEINT_K4S(3, float, 3, 1, 8, 2),
-    FEINT_KV(3, float, 40, 2)};
+    FEINT_KV(3, float, 40, 2),
+    FEINT_KSC(3, float, 3, 3, 1)};
 const FwdVariant v4[] = {
     FEINT_K4S(4, float, 5, 5, 8, 1),
     FEINT_K4S(4, float, 5, 3, 8, 2),
-    FEINT_K4U(4, float, 5, 5, 1)};
+    FEINT_K4U(4, float, 5, 5, 1),
+    FEINT_KSC(4, float, 5, 5, 1)};
 const FwdVariant v5[] = {
     FEINT_K4S(5, float, 8, 4, 8, 1),
     FEINT_K4S(5, float, 8, 2, 8, 2),
@@ -27,7 +31,8 @@ const FwdVariant v5[] = {
     FEINT_K4U(5, float, 8, 4, 1),
     FEINT_K4U(5, float, 8, 4, 2),
     FEINT_K4U(5, float, 8, 8, 1),
-    FEINT_K4U(5, float, 4, 4, 2)};
+    FEINT_K4U(5, float, 4, 4, 2),
+    FEINT_KSC(5, float, 8, 4, 1)};
 const FwdVariant v6[] = {
     FEINT_K4S(6, float, 13, 2, 8, 1),
     FEINT_K4S(6, float, 13, 1, 8, 2),
@@ -35,11 +40,13 @@ const FwdVariant v6[] = {
     FEINT_K4U(6, float, 13, 4, 1),
     FEINT_K4U(6, float, 13, 3, 2),
     FEINT_K4U(6, float, 13, 2, 2),
-    FEINT_K4U(6, float, 7, 4, 2)};
+    FEINT_K4U(6, float, 7, 4, 2),
+    FEINT_KSC(6, float, 13, 2, 1)};
 const FwdVariant v7[] = {
     FEINT_K4U(7, float, 9, 6, 1),
     FEINT_K4U(7, float, 9, 3, 1),
-    FEINT_K4U(7, float, 6, 3, 1)};
+    FEINT_K4U(7, float, 6, 3, 1),
+    FEINT_KSC(7, float, 9, 3, 1)};
 }  // namespace
 
 #define FEINT_N(a) (int)(sizeof(a) / sizeof(a[0]))

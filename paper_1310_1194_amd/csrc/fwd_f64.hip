@@ -7,31 +7,38 @@ namespace {
 const FwdVariant v1[] = {
     FEINT_KV(1, double, 8, 2),
     FEINT_KV(1, double, 6, 2),
-    FEINT_K4S(1, double, 1, 1, 8, 1)};
+    FEINT_K4S(1, double, 1, 1, 8, 1),
+    FEINT_KSC(1, double, 1, 1, 1)};
 const FwdVariant v2[] = {
     FEINT_KV(2, double, 18, 2),
     FEINT_KV(2, double, 32, 2),
     FEINT_K4S(2, double, 2, 2, 8, 1),
-    FEINT_K4S(2, double, 2, 1, 8, 2)};
+    FEINT_K4S(2, double, 2, 1, 8, 2),
+    FEINT_KSC(2, double, 2, 2, 1)};
 const FwdVariant v3[] = {
     FEINT_K4S(3, double, 3, 3, 8, 1),
     FEINT_K4S(3, double, 3, 1, 8, 2),
-    FEINT_KV(3, double, 40, 2)};
+    FEINT_KV(3, double, 40, 2),
+    FEINT_KSC(3, double, 3, 3, 1)};
 const FwdVariant v4[] = {
     FEINT_K4S(4, double, 5, 3, 8, 2),
     FEINT_K4U(4, double, 5, 1, 2),
-    FEINT_K4S(4, double, 5, 2, 8, 2)};
+    FEINT_K4S(4, double, 5, 2, 8, 2),
+    FEINT_KSC(4, double, 5, 3, 1)};
 const FwdVariant v5[] = {
     FEINT_K4S(5, double, 8, 1, 4, 2),
     FEINT_K4S(5, double, 8, 2, 4, 1),
-    FEINT_K4U(5, double, 8, 1, 2)};
+    FEINT_K4U(5, double, 8, 1, 2),
+    FEINT_KSC(5, double, 8, 2, 1)};
 const FwdVariant v6[] = {
     FEINT_K4S(6, double, 13, 1, 4, 1),
-    FEINT_K4U(6, double, 13, 1, 2)};
+    FEINT_K4U(6, double, 13, 1, 2),
+    FEINT_KSC(6, double, 13, 1, 1)};
 const FwdVariant v7[] = {
     FEINT_K4U(7, double, 6, 2, 1),
     FEINT_K4U(7, double, 9, 2, 1),
-    FEINT_K4U(7, double, 9, 1, 1)};
+    FEINT_K4U(7, double, 9, 1, 1),
+    FEINT_KSC(7, double, 6, 2, 1)};
 }  // namespace
 
 #define FEINT_N(a) (int)(sizeof(a) / sizeof(a[0]))

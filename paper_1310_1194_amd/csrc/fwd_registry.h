@@ -5,6 +5,7 @@
 #include "fwd_staged.h"
 #include "fwd_valu.h"
 #include "fwd_pipe.h"
+#include "fwd_sc.h"
 
 namespace feint {
 
@@ -45,7 +46,12 @@ int64_t items_of(int64_t ne) { return items_for<KER>(ne); }
     FwdVariant{TM, TN, 1 + !(SY), W, &launch_staged<K32S<P, F, TM, TN, SY, R>, W>, \
                &items_of<K32S<P, F, TM, TN, SY, R>>}
 
+// C: shape functions computed at each point, no B table (staged = 5).
+#define FEINT_KSC_R(P, T, TM, TN, W, R) \
+    FwdVariant{TM, TN, 5, W, &launch_direct<KSC<P, T, TM, TN, R>, W>, &items_of<KSC<P, T, TM, TN, R>>}
+
 #define FEINT_K4U(P, T, TM, TN, W) FEINT_K4U_R(P, T, TM, TN, W, 0)
+#define FEINT_KSC(P, T, TM, TN, W) FEINT_KSC_R(P, T, TM, TN, W, 0)
 #define FEINT_K4S(P, T, TM, TN, SP, W) FEINT_K4S_R(P, T, TM, TN, SP, W, 0)
 #define FEINT_K32U(P, F, TM, TN, W) FEINT_K32U_R(P, F, TM, TN, W, 0)
 #define FEINT_KV(P, T, LPE, W) FEINT_KV_R(P, T, LPE, W, 0)

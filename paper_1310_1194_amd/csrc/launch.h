@@ -12,6 +12,7 @@ struct FwdParams {
     double *xq;
     uint32_t *status;
     const double *qw;        // [nqp][4]
+    const double *gll;       // [2][p+1] Gauss-Lobatto nodes and Lagrange denominators
     const double *B64;       // [nqp][4][npad]
     const float *B32;        // [nqp][4][npad]
     const float *Bc32;       // [nqp][npad][4]
@@ -34,7 +35,8 @@ struct FwdParams {
 struct FwdVariant {
     int tm, tn;
     int staged;          // 1: the table is staged through LDS per workgroup (2: A operands only),
-                         // 3: vector-ALU kernel, 4: software-pipelined split kernel
+                         // 3: vector-ALU kernel, 4: software-pipelined split kernel,
+                         // 5: shape functions computed at each point (no B table)
     int minw;            // waves per SIMD the register allocation allows
     void (*launch)(const FwdParams &, hipStream_t);
     int64_t (*items)(int64_t ne);   // work items (waves) of a launch over ne elements

@@ -413,6 +413,15 @@ HostTables build_tables(int p, int rule) {
         T.qw[4 * q + 0] = 1.0 / 3.0;
         T.qw[4 * q + 1] = 1.0 / 3.0;
     }
+    // line factors of the kernels that compute shape functions at each point
+    T.gll.assign(2 * (p + 1), 0.0);
+    gauss_lobatto_nodes(p, T.gll.data());
+    for (int k = 0; k <= p; ++k) {
+        long double d = 1.0L;
+        for (int m = 0; m <= p; ++m)
+            if (m != k) d *= (long double)T.gll[k] - (long double)T.gll[m];
+        T.gll[p + 1 + k] = (double)(1.0L / d);
+    }
     ModalBasis mb = make_modal(p);
     T.B64.assign((size_t)T.nqp * 4 * np, 0.0);
     std::vector<double> phi(n), dphi(3 * n);

@@ -29,6 +29,7 @@ struct HostTables {
     int p = 0, rule = 0, n = 0, npad = 0, nq = 0, nqp = 0, nkb = 0;
     int f16_shift = 0;               // fp16 tables hold B * 2^f16_shift
     std::vector<double> qw;          // [nqp][4]  xi1, xi2, zeta, w  (padded points: w = 0)
+    std::vector<double> gll;         // [2][p+1]  Gauss-Lobatto nodes z_k and 1 / prod_{m != k} (z_k - z_m)
     std::vector<double> B64;         // [nqp][4][npad]  rows: phi, d/dxi1, d/dxi2, d/dzeta
     std::vector<float> B32;          // same, rounded to FP32
     std::vector<double> BT64;        // [npad][nqp*4]  transpose of B64 (shape-function major)
