@@ -20,6 +20,7 @@ import hashlib
 import json
 import os
 import platform
+import re
 import sys
 import time
 from pathlib import Path
@@ -128,6 +129,10 @@ def main():
     ap.add_argument("--workload", default=None)
     ap.add_argument("--rule", default="collapsed", choices=["collapsed", "symmetric"],
                     help="quadrature rule of the forward and fields modes")
+    ap.add_argument("--sc", action="store_true",
+                    help="forward/fields: time the variant that computes shape functions at each point "
+                         "(the paper's SC strategy) instead of autotuning over the table-reading ones; "
+                         "FP64 and FP32 forms")
     ap.add_argument("--forms", default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (CPU baseline and errors)")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
@@ -154,7 +159,7 @@ def bench_forward(args, fields=False):
     """Forward integration; with `fields` the coefficients are vertex fields
     evaluated at every point (feint_integrate_fields)."""
     args.workload = args.workload or "p4_131072"
-    args.forms = args.forms or ",".join(FORMS)
+    args.forms = args.forms or ("fp64,fp32" if args.sc else ",".join(FORMS))
     import torch
     import paper_1310_1194_amd as F
 
@@ -176,6 +181,8 @@ def bench_forward(args, fields=False):
         integrate = F.integrate_raw
     forms = [f for f in args.forms.split(",") if f]
     headline = HEADLINE if HEADLINE in forms else forms[0]
+    if args.sc and not set(forms) <= {"fp64", "fp32"}:
+        raise SystemExit("--sc: the SC variants are compiled for the fp64 and fp32 forms")
 
     if args.copy_cal:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -193,7 +200,13 @@ def bench_forward(args, fields=False):
         A = torch.empty((ne, n, n), dtype=dt, device=dev)
         b = torch.empty((ne, n), dtype=dt, device=dev)
         tile_ms = None
-        if not args.no_tune:
+        if args.sc:
+            sc = [t for t in range(F.tile_count(p, form, rule=rule))
+                  if re.fullmatch(r"\d+x\d+c(o2)?", F.tile_describe(p, form, t, rule=rule))]
+            if not sc:
+                raise SystemExit(f"no SC variant compiled for p={p} form={form}")
+            F.tile_set(p, form, sc[0], rule=rule)
+        elif not args.no_tune:
             if fields:
                 tile_ms = F.autotune_fields(*X, p, form, A, b, reps=2, rule=rule)
             else:
@@ -289,7 +302,8 @@ def bench_forward(args, fields=False):
         "dtype": DTYPE_DESC[headline],
         "data": "synthetic (seeded perturbed prism mesh and coefficients)",
         "config": {"workload": args.workload + ("+vertex_fields" if fields else "")
-                   + ("+symmetric_rule" if rule != "collapsed" else ""), "p": p, "ne": ne, "rule": rule,
+                   + ("+symmetric_rule" if rule != "collapsed" else "") + ("+sc" if args.sc else ""),
+                   "p": p, "ne": ne, "rule": rule, "shape_functions": "computed per point" if args.sc else "tables",
                    "nshp": n, "nq": q, "coefficients": "vertex fields" if fields else "element constants",
                    "mesh": f"{w['nx']}x{w['ny']}x{w['nz']}", "perturbation": w["amp"], "seed": w["seed"],
                    "form": headline, "parallelism": "single GPU"},
