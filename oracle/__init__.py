@@ -50,6 +50,11 @@ def lib():
         L.oracle_integrate_fields.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [_dp] * 8 + [_ip]
         L.oracle_integrate_rule.argtypes = ([ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int64, ctypes.c_int]
                                             + [_dp] * 8 + [_ip])
+        L.oracle_hex_rule.argtypes = [ctypes.c_int, _dp, _dp]
+        L.oracle_hex_nodes.argtypes = [ctypes.c_int, _dp]
+        L.oracle_hex_basis.argtypes = [ctypes.c_int, _dp, _dp, _dp]
+        L.oracle_hex_geometry.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp]
+        L.oracle_integrate_hex.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [_dp] * 8 + [_ip]
         L.oracle_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [_dp] * 13
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_max_threads.restype = ctypes.c_int
@@ -238,6 +243,54 @@ def assemble(dofs, ndof, A, b):
     for e in range(ne):                              # dofs of one element are distinct
         rhs[dofs[e]] += b[e]
     return row_ptr, (uniq % ndof).astype(np.int64), vals, rhs
+
+
+def hex_nshp(p):
+    return (p + 1) ** 3
+
+
+def hex_rule(n1):
+    """n1^3 Gauss points on [-1,1]^3 (pts [nq,3], w [nq]), q = (k n1 + j) n1 + i."""
+    pts = np.zeros((n1 ** 3, 3)); w = np.zeros(n1 ** 3)
+    assert lib().oracle_hex_rule(n1, _p(pts), _p(w)) == n1 ** 3
+    return pts, w
+
+
+def hex_nodes(p):
+    out = np.zeros((hex_nshp(p), 3))
+    assert lib().oracle_hex_nodes(p, _p(out)) == hex_nshp(p)
+    return out
+
+
+def hex_basis(p, xi):
+    """Tensor-product Gauss-Lobatto Lagrange basis: phi [n], gradients [n,3]."""
+    xi = _c(xi)
+    n = hex_nshp(p)
+    phi = np.zeros(n); dphi = np.zeros((n, 3))
+    assert lib().oracle_hex_basis(p, _p(xi), _p(phi), _p(dphi)) == 0
+    return phi, dphi
+
+
+def hex_geometry(X, xi):
+    """Trilinear hexahedron X [8,3]: J [3,3], det, K = J^{-1}, mapped point."""
+    X = _c(X); xi = _c(xi)
+    J = np.zeros((3, 3)); K = np.zeros((3, 3)); x = np.zeros(3); det = np.zeros(1)
+    lib().oracle_hex_geometry(_p(X), _p(xi), _p(J), _p(det), _p(K), _p(x))
+    return J, float(det[0]), K, x
+
+
+def integrate_hex(p, coords, D, beta, c, f, n1=0, want_xq=False):
+    """Hexahedra (coords [ne,8,3]): A [ne,n,n], b [ne,n], flags (and xq)."""
+    coords = _c(coords); D = _c(D); beta = _c(beta); c = _c(c); f = _c(f)
+    ne, n = coords.shape[0], hex_nshp(p)
+    nqq = (n1 if n1 > 0 else p + 1) ** 3
+    A = np.zeros((ne, n, n)); b = np.zeros((ne, n))
+    flags = np.zeros(ne, dtype=np.int32)
+    xq = np.zeros((ne, nqq, 3)) if want_xq else None
+    rc = lib().oracle_integrate_hex(p, n1, ne, _p(coords), _p(D), _p(beta), _p(c), _p(f),
+                                    _p(A), _p(b), _p(xq), flags.ctypes.data_as(_ip))
+    assert rc == 0, rc
+    return (A, b, flags, xq) if want_xq else (A, b, flags)
 
 
 def set_threads(nt: int):

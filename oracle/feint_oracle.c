@@ -243,6 +243,8 @@ static void geom_shape(const double *xi, double *N, double *dN)
     }
 }
 
+static int invert3(const double *J, double *det, double *K);
+
 /* J[d][l] = d x_d / d xi_l, det J (cofactor expansion along row 0),
    K = J^{-1} = adj(J) / det, and the mapped point x. */
 int oracle_geometry(const double *X, const double *xi, double *J, double *det,
@@ -261,6 +263,13 @@ int oracle_geometry(const double *X, const double *xi, double *J, double *det,
             J[3 * d + l] = s;
         }
     }
+    return invert3(J, det, K);
+}
+
+/* det J (cofactor expansion along row 0) and K = J^{-1} = adj(J) / det;
+   returns 1 when det J <= 0. */
+static int invert3(const double *J, double *det, double *K)
+{
     double c00 = J[4] * J[8] - J[5] * J[7];
     double c01 = J[5] * J[6] - J[3] * J[8];
     double c02 = J[3] * J[7] - J[4] * J[6];
@@ -282,25 +291,140 @@ int oracle_geometry(const double *X, const double *xi, double *J, double *det,
 }
 
 /* ---------------------------------------------------------------------- */
+/* Hexahedra (Table 1, tensor-product basis)                               */
+/* ---------------------------------------------------------------------- */
+/* Reference cube [-1,1]^3 (volume 8).  Vertices v = i + 2j + 4k at
+   (2i-1, 2j-1, 2k-1), trilinear geometry N_v = (1 + s_v xi)(1 + t_v eta)
+   (1 + u_v zeta) / 8; shape functions phi_a = L_i(xi) L_j(eta) L_k(zeta),
+   a = (k (p+1) + j) (p+1) + i, with L the Lagrange basis on the p+1
+   Gauss-Lobatto nodes; rule: n1^3 Gauss-Legendre points, q = (k n1 + j) n1 + i. */
+
+int oracle_hex_nshp(int p) { return (p < 1 || p > ORACLE_MAXP) ? -1 : (p + 1) * (p + 1) * (p + 1); }
+
+int oracle_hex_rule(int n1, double *pts, double *w)
+{
+    double g[ORACLE_MAXN1], gw[ORACLE_MAXN1];
+    if (n1 < 1 || n1 > ORACLE_MAXN1) return -1;
+    oracle_gauss_legendre(n1, g, gw);
+    int q = 0;
+    for (int k = 0; k < n1; ++k)
+        for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n1; ++i) {
+                pts[3 * q + 0] = g[i];
+                pts[3 * q + 1] = g[j];
+                pts[3 * q + 2] = g[k];
+                w[q] = gw[i] * gw[j] * gw[k];
+                ++q;
+            }
+    return q;
+}
+
+/* Lagrange basis on the nodes z[0..p] at x: l[k], dl[k] (product formula). */
+static void line_lagrange(int p, const double *z, double x, double *l, double *dl)
+{
+    for (int k = 0; k <= p; ++k) {
+        double v = 1.0, d = 0.0;
+        for (int m = 0; m <= p; ++m) {
+            if (m == k) continue;
+            double fac = (x - z[m]) / (z[k] - z[m]);
+            double dfac = 1.0 / (z[k] - z[m]);
+            d = d * fac + v * dfac;
+            v = v * fac;
+        }
+        l[k] = v;
+        dl[k] = d;
+    }
+}
+
+int oracle_hex_nodes(int p, double *nodes)
+{
+    double z[ORACLE_MAXP + 1];
+    if (p < 1 || p > ORACLE_MAXP) return -1;
+    oracle_gll_nodes(p, z);
+    int a = 0;
+    for (int k = 0; k <= p; ++k)
+        for (int j = 0; j <= p; ++j)
+            for (int i = 0; i <= p; ++i) {
+                nodes[3 * a + 0] = z[i];
+                nodes[3 * a + 1] = z[j];
+                nodes[3 * a + 2] = z[k];
+                ++a;
+            }
+    return a;
+}
+
+int oracle_hex_basis(int p, const double *xi, double *phi, double *dphi)
+{
+    double z[ORACLE_MAXP + 1], l[3][ORACLE_MAXP + 1], dl[3][ORACLE_MAXP + 1];
+    if (p < 1 || p > ORACLE_MAXP) return -1;
+    oracle_gll_nodes(p, z);
+    for (int d = 0; d < 3; ++d) line_lagrange(p, z, xi[d], l[d], dl[d]);
+    int a = 0;
+    for (int k = 0; k <= p; ++k)
+        for (int j = 0; j <= p; ++j)
+            for (int i = 0; i <= p; ++i) {
+                phi[a] = l[0][i] * l[1][j] * l[2][k];
+                dphi[3 * a + 0] = dl[0][i] * l[1][j] * l[2][k];
+                dphi[3 * a + 1] = l[0][i] * dl[1][j] * l[2][k];
+                dphi[3 * a + 2] = l[0][i] * l[1][j] * dl[2][k];
+                ++a;
+            }
+    return 0;
+}
+
+/* Trilinear geometry shape functions N[8] and reference gradients dN[8][3]. */
+static void hex_shape(const double *xi, double *N, double *dN)
+{
+    for (int v = 0; v < 8; ++v) {
+        const double s = (v & 1) ? 1.0 : -1.0, t = (v & 2) ? 1.0 : -1.0, u = (v & 4) ? 1.0 : -1.0;
+        const double a = 1.0 + s * xi[0], b = 1.0 + t * xi[1], c = 1.0 + u * xi[2];
+        N[v] = a * b * c / 8.0;
+        dN[3 * v + 0] = s * b * c / 8.0;
+        dN[3 * v + 1] = a * t * c / 8.0;
+        dN[3 * v + 2] = a * b * u / 8.0;
+    }
+}
+
+/* J = sum_v x_v (grad N_v)^T, det J, K = J^{-1}, mapped point x; X [8][3]. */
+int oracle_hex_geometry(const double *X, const double *xi, double *J, double *det, double *K, double *x)
+{
+    double N[8], dN[24];
+    hex_shape(xi, N, dN);
+    for (int d = 0; d < 3; ++d) {
+        if (x) {
+            x[d] = 0.0;
+            for (int v = 0; v < 8; ++v) x[d] += N[v] * X[3 * v + d];
+        }
+        for (int l = 0; l < 3; ++l) {
+            double s = 0.0;
+            for (int v = 0; v < 8; ++v) s += X[3 * v + d] * dN[3 * v + l];
+            J[3 * d + l] = s;
+        }
+    }
+    return invert3(J, det, K);
+}
+
+/* ---------------------------------------------------------------------- */
 /* Algorithm 1: element loop -> quadrature loop -> i -> j                  */
 /* ---------------------------------------------------------------------- */
 
 typedef struct {
-    int p, n, nq;
+    int type, p, n, nq;                     /* type 0: prism, 1: hexahedron */
     double *pts, *w, *phi, *dphi; /* [nq][3], [nq], [nq][n], [nq][n][3] */
 } rule_tables;
 
 /* Tables of degree p on a rule: the caller's points (qpts [nq][3], qw [nq])
    when qpts is given, else the collapsed Gauss rule with n1 points per
    direction (n1 <= 0: p+1). */
-static int make_tables(int p, int n1, int nq, const double *qpts, const double *qw, rule_tables *T)
+static int make_tables(int type, int p, int n1, int nq, const double *qpts, const double *qw, rule_tables *T)
 {
     if (p < 1 || p > ORACLE_MAXP) return -1;
     if (n1 <= 0) n1 = p + 1;
     if (n1 > ORACLE_MAXN1) return -1;
     if (qpts && (nq < 1 || !qw)) return -1;
+    T->type = type;
     T->p = p;
-    T->n = oracle_nshp(p);
+    T->n = type ? oracle_hex_nshp(p) : oracle_nshp(p);
     T->nq = qpts ? nq : n1 * n1 * n1;
     T->pts = (double *)malloc(sizeof(double) * 3 * T->nq);
     T->w = (double *)malloc(sizeof(double) * T->nq);
@@ -309,13 +433,16 @@ static int make_tables(int p, int n1, int nq, const double *qpts, const double *
     if (qpts) {
         memcpy(T->pts, qpts, sizeof(double) * 3 * T->nq);
         memcpy(T->w, qw, sizeof(double) * T->nq);
+    } else if (type) {
+        oracle_hex_rule(n1, T->pts, T->w);
     } else {
         oracle_rule(n1, T->pts, T->w);
     }
     /* step 6 of Algorithm 1: shape functions at every point (the same for
        every element of degree p, so they are evaluated once) */
     for (int q = 0; q < T->nq; ++q)
-        oracle_basis(p, T->pts + 3 * q, T->phi + (size_t)q * T->n, T->dphi + (size_t)3 * q * T->n);
+        (type ? oracle_hex_basis : oracle_basis)(p, T->pts + 3 * q, T->phi + (size_t)q * T->n,
+                                                 T->dphi + (size_t)3 * q * T->n);
     return 0;
 }
 
@@ -351,18 +478,19 @@ int oracle_max_threads(void)
    given at the six vertices (nv = 6) and evaluated at each point with the
    geometry shape functions, D(x_q) = sum_a N_a(xi_q) D_a (the coefficient
    fields live in the same bilinear space as the geometry). */
-static int integrate_core(int p, int n1, int nq, const double *qpts, const double *qw, int64_t ne, int nv,
-                          const double *coords, const double *Dv, const double *betav, const double *cv,
+static int integrate_core(int type, int p, int n1, int nq, const double *qpts, const double *qw, int64_t ne,
+                          int nv, const double *coords, const double *Dv, const double *betav, const double *cv,
                           const double *fv, double *A, double *b, double *xq, int32_t *flags)
 {
     rule_tables T;
-    if (ne < 0) return -1;
-    if (make_tables(p, n1, nq, qpts, qw, &T)) return -1;
+    if (ne < 0 || (type && nv != 1)) return -1;
+    if (make_tables(type, p, n1, nq, qpts, qw, &T)) return -1;
+    const int nx = type ? 24 : 18;                 /* coordinates per element */
     const int n = T.n, nqp = T.nq;
     int64_t e;
 #pragma omp parallel for schedule(static)
     for (e = 0; e < ne; ++e) {
-        const double *X = coords + 18 * e;          /* step 2: geometry data */
+        const double *X = coords + (size_t)nx * e;  /* step 2: geometry data */
         double *Ae = A + (size_t)e * n * n, *bv = b + (size_t)e * n;
         double *gphys = (double *)malloc(sizeof(double) * 3 * n);
         double *Dg = (double *)malloc(sizeof(double) * 3 * n);
@@ -373,7 +501,7 @@ static int integrate_core(int p, int n1, int nq, const double *qpts, const doubl
         for (int q = 0; q < nqp; ++q) {           /* step 5 */
             const double *phi = T.phi + (size_t)q * n, *dphi = T.dphi + (size_t)3 * q * n;
             double J[9], K[9], det, x[3];
-            bad |= oracle_geometry(X, T.pts + 3 * q, J, &det, K, x);   /* step 7 */
+            bad |= (type ? oracle_hex_geometry : oracle_geometry)(X, T.pts + 3 * q, J, &det, K, x);   /* step 7 */
             if (xq) for (int d = 0; d < 3; ++d) xq[((size_t)e * nqp + q) * 3 + d] = x[d];
             /* coefficients at the point */
             double De[9], be[3], ce, fe;
@@ -432,7 +560,16 @@ int oracle_integrate(int p, int n1, int64_t ne, const double *coords, const doub
                      const double *beta, const double *c, const double *f,
                      double *A, double *b, double *xq, int32_t *flags)
 {
-    return integrate_core(p, n1, 0, NULL, NULL, ne, 1, coords, D, beta, c, f, A, b, xq, flags);
+    return integrate_core(0, p, n1, 0, NULL, NULL, ne, 1, coords, D, beta, c, f, A, b, xq, flags);
+}
+
+/* Hexahedra: coords [ne][8][3], coefficients per element as above; n1
+   Gauss points per direction (0 -> p+1). */
+int oracle_integrate_hex(int p, int n1, int64_t ne, const double *coords, const double *D,
+                         const double *beta, const double *c, const double *f,
+                         double *A, double *b, double *xq, int32_t *flags)
+{
+    return integrate_core(1, p, n1, 0, NULL, NULL, ne, 1, coords, D, beta, c, f, A, b, xq, flags);
 }
 
 /* Coefficients given at the six vertices: Dv [ne][6][9], betav [ne][6][3],
@@ -441,7 +578,7 @@ int oracle_integrate_fields(int p, int n1, int64_t ne, const double *coords, con
                             const double *betav, const double *cv, const double *fv,
                             double *A, double *b, double *xq, int32_t *flags)
 {
-    return integrate_core(p, n1, 0, NULL, NULL, ne, 6, coords, Dv, betav, cv, fv, A, b, xq, flags);
+    return integrate_core(0, p, n1, 0, NULL, NULL, ne, 6, coords, Dv, betav, cv, fv, A, b, xq, flags);
 }
 
 /* The same element loop on a rule given by the caller: qpts [nq][3] =
@@ -452,7 +589,7 @@ int oracle_integrate_rule(int p, int nq, const double *qpts, const double *qw, i
                           const double *fv, double *A, double *b, double *xq, int32_t *flags)
 {
     if (!qpts || (nv != 1 && nv != 6)) return -1;
-    return integrate_core(p, 0, nq, qpts, qw, ne, nv, coords, Dv, betav, cv, fv, A, b, xq, flags);
+    return integrate_core(0, p, 0, nq, qpts, qw, ne, nv, coords, Dv, betav, cv, fv, A, b, xq, flags);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -480,7 +617,7 @@ int oracle_adjoint(int p, int n1, int64_t ne, const double *coords, const double
 {
     rule_tables T;
     if (ne < 0) return -1;
-    if (make_tables(p, n1, 0, NULL, NULL, &T)) return -1;
+    if (make_tables(0, p, n1, 0, NULL, NULL, &T)) return -1;
     const int n = T.n, nqp = T.nq;
     int64_t e;
 #pragma omp parallel for schedule(static)

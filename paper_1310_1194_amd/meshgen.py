@@ -138,6 +138,35 @@ def make_batch(nx: int, ny: int, nz: int, amp: float = 0.2, seed: int = 0,
     return b
 
 
+def hex_connectivity(nx: int, ny: int, nz: int) -> np.ndarray:
+    """One hexahedron per grid cell, vertices v = i + 2j + 4k at the cell's
+    corner (ix + i, iy + j, iz + k)."""
+    ix, iy, iz = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    ix, iy, iz = ix.ravel(), iy.ravel(), iz.ravel()
+    vid = lambda i, j, k: (k * (ny + 1) + j) * (nx + 1) + i
+    corners = [vid(ix + (v & 1), iy + ((v >> 1) & 1), iz + ((v >> 2) & 1)) for v in range(8)]
+    return np.stack(corners, axis=1)
+
+
+def make_hex_batch(nx: int, ny: int, nz: int, amp: float = 0.2, seed: int = 0) -> Batch:
+    """Hexahedral mesh of the perturbed vertex grid (one hexahedron per cell,
+    coords [ne, 8, 3]) with the element-constant coefficient recipe."""
+    rng = np.random.default_rng(seed)
+    nvert = (nx + 1) * (ny + 1) * (nz + 1)
+    u = rng.uniform(-1.0, 1.0, (nvert, 3))
+    verts = grid_vertices(nx, ny, nz, amp, u)
+    conn = hex_connectivity(nx, ny, nz)
+    ne = conn.shape[0]
+    coords = np.ascontiguousarray(verts[conn])               # [ne, 8, 3]
+    L = rng.normal(0.0, 0.3, (ne, 3, 3))
+    D = np.einsum("eik,ejk->eij", L, L) + np.eye(3)[None]
+    beta = rng.normal(0.0, 1.0, (ne, 3))
+    c = rng.uniform(0.0, 1.0, ne)
+    f = rng.uniform(-1.0, 1.0, ne)
+    return Batch(coords, np.ascontiguousarray(D), beta, c, f, None, dict(nx=nx, ny=ny, nz=nz, amp=amp, seed=seed,
+                                                                         element="hexahedron"))
+
+
 def vertex_fields(ne: int, seed: int):
     """Coefficients given at the six vertices of every element, drawn with the
     element-constant recipe per vertex: D = L L^T + I (L ~ N(0, 0.3^2)),
@@ -227,9 +256,13 @@ WORKLOADS = {
     "p7_16384":     dict(nx=32, ny=32, nz=8,  amp=0.3, seed=4, p=7),
     # the p = 1 distributions at a size where HBM rather than launch latency bounds
     "p1_524288":    dict(nx=64, ny=64, nz=64, amp=0.2, seed=0, p=1),
+    # hexahedra (one per cell) on the vertex grid of the p = 4 prism workload
+    "hex_p4_65536": dict(nx=64, ny=64, nz=16, amp=0.2, seed=1, p=4, element="hexahedron"),
 }
 
 
 def workload(name: str) -> Batch:
     w = WORKLOADS[name]
+    if w.get("element") == "hexahedron":
+        return make_hex_batch(w["nx"], w["ny"], w["nz"], w["amp"], w["seed"])
     return make_batch(w["nx"], w["ny"], w["nz"], w["amp"], w["seed"], mixed=w["p"] is None)
