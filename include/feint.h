@@ -277,6 +277,29 @@ feint_status feint_rule_tile_describe(int p, feint_form form, feint_rule rule, i
 feint_status feint_autotune_rule(const feint_elements *el, const feint_fields *fl, int p, feint_form form,
                                  feint_rule rule, void *A, void *b, int reps, double *best_ms, void *stream);
 
+/* ---- Hexahedral elements (Table 1, tensor-product basis) --------------------
+   The same integration (CDR element matrix and load vector, W_q in FP64) on
+   geometrically trilinear hexahedra: reference cube [-1,1]^3, vertex v =
+   i + 2j + 4k at (2i-1, 2j-1, 2k-1); shape functions phi_a = L_i(xi)
+   L_j(eta) L_k(zeta), a = (k (p+1) + j) (p+1) + i, L the Lagrange basis on
+   the p+1 Gauss-Lobatto nodes; (p+1)^3 Gauss-Legendre points, q = (k n1 +
+   j) n1 + i.  Inputs as feint_elements with coords [ne][8][3]; outputs
+   A [ne][n][n] (row = test function), b [ne][n], n = (p+1)^3; xq (nullable)
+   [ne][(p+1)^3][3]; dev_status as feint_integrate.  Forms FEINT_FP64 and
+   FEINT_FP32 (16x16x4 MFMA); the split forms give UNSUPPORTED_FORM.
+   Variants, tile selection and autotuning as for prisms. */
+int feint_hex_nshp(int p);
+int feint_hex_nq(int p);
+feint_status feint_prepare_hex(int p);
+feint_status feint_integrate_hex(const feint_elements *el, int p, feint_form form, void *A, void *b,
+                                 double *xq, uint32_t *dev_status, void *stream);
+int feint_hex_tile_count(int p, feint_form form);
+int feint_hex_tile_get(int p, feint_form form);
+feint_status feint_hex_tile_set(int p, feint_form form, int tile);
+feint_status feint_hex_tile_describe(int p, feint_form form, int tile, char *buf, size_t len);
+feint_status feint_hex_autotune(const feint_elements *el, int p, feint_form form, void *A, void *b, int reps,
+                                double *best_ms, void *stream);
+
 /* ---- Global assembly (Sec. 2) ----------------------------------------------
    The element matrices and load vectors of one degree are summed into a CSR
    matrix and a right-hand side through the element-to-global dof map.

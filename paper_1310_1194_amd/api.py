@@ -156,6 +156,66 @@ def integrate_fields_raw(coords, Dv, betav, cv, fv, p: int, form: str = "fp64", 
     return A, b
 
 
+def hex_nshp(p: int) -> int:
+    return (p + 1) ** 3
+
+
+def hex_elements(coords, D, beta, c, f) -> Elements:
+    ne = coords.shape[0]
+    _check_input("coords", coords, (8, 3), ne)
+    _check_input("D", D, (3, 3), ne)
+    _check_input("beta", beta, (3,), ne)
+    _check_input("c", c, (), ne)
+    _check_input("f", f, (), ne)
+    return Elements(coords.data_ptr(), D.data_ptr(), beta.data_ptr(), c.data_ptr(), f.data_ptr(), ne)
+
+
+def integrate_hex_raw(coords, D, beta, c, f, p: int, form: str = "fp64", *, A=None, b=None, xq=None, status=None):
+    """Hexahedral elements (coords [ne,8,3]): forward integration; returns (A, b)."""
+    if form not in ("fp64", "fp32"):
+        raise ValueError("hexahedra: forms fp64 and fp32")
+    el = hex_elements(coords, D, beta, c, f)
+    ne, n = coords.shape[0], hex_nshp(p)
+    dt = out_dtype(form)
+    if A is None:
+        A = torch.empty((ne, n, n), dtype=dt, device=coords.device)
+    if b is None:
+        b = torch.empty((ne, n), dtype=dt, device=coords.device)
+    if A.dtype != dt or b.dtype != dt or A.numel() != ne * n * n or b.numel() != ne * n:
+        raise ValueError("output tensors have the wrong dtype or size")
+    if xq is not None and (xq.dtype != torch.float64 or xq.numel() != ne * (p + 1) ** 3 * 3):
+        raise ValueError("xq must be float64 with ne*nq*3 entries")
+    check("feint_integrate_hex", lib().feint_integrate_hex(ctypes.byref(el), int(p), FORMS[form], _ptr(A), _ptr(b),
+                                                           _ptr(xq), _ptr(status), _stream()))
+    return A, b
+
+
+def hex_tile_count(p: int, form: str) -> int:
+    return lib().feint_hex_tile_count(int(p), FORMS[form])
+
+
+def hex_tile_get(p: int, form: str) -> int:
+    return lib().feint_hex_tile_get(int(p), FORMS[form])
+
+
+def hex_tile_set(p: int, form: str, tile: int) -> None:
+    check("feint_hex_tile_set", lib().feint_hex_tile_set(int(p), FORMS[form], int(tile)))
+
+
+def hex_tile_describe(p: int, form: str, tile: int) -> str:
+    buf = ctypes.create_string_buffer(32)
+    check("feint_hex_tile_describe", lib().feint_hex_tile_describe(int(p), FORMS[form], int(tile), buf, 32))
+    return buf.value.decode()
+
+
+def hex_autotune(coords, D, beta, c, f, p: int, form: str, A, b, reps: int = 2) -> float:
+    el = hex_elements(coords, D, beta, c, f)
+    best = ctypes.c_double(0)
+    check("feint_hex_autotune", lib().feint_hex_autotune(ctypes.byref(el), int(p), FORMS[form], _ptr(A), _ptr(b),
+                                                         int(reps), ctypes.byref(best), _stream()))
+    return best.value
+
+
 def adjoint_raw(coords, D, beta, c, f, G, g, p: int, form: str = "fp64"):
     """Gradients of sum_e <G_e,A_e> + <g_e,b_e>: (dcoords, dD, dbeta, dc, df), FP64."""
     el = elements(coords, D, beta, c, f)

@@ -20,8 +20,9 @@ namespace feint {
 
 namespace {
 std::mutex g_mu;
-std::map<int, DevTables *> g_tables;        // key: device * 16 + rule * 8 + p
-int g_tile[2][8][4];                        // chosen variant per (rule, p, form)
+std::map<int, DevTables *> g_tables;        // key: device * 64 + type * 16 + rule * 8 + p
+int g_tile[2][8][4];                        // chosen variant per (rule, p, form), prisms
+int g_tile_hex[8][4];                       // chosen variant per (p, form), hexahedra
 thread_local std::string g_err;
 
 bool valid_form(int form) { return form >= FEINT_FP64 && form <= FEINT_FP16X3; }
@@ -32,24 +33,26 @@ void set_error(const char *what, hipError_t e) {
     g_err = std::string(what) + ": " + hipGetErrorString(e);
 }
 
-const DevTables *find_tables(int p, int rule) {
+const DevTables *find_tables(int p, int rule, int type) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return nullptr;
     std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_tables.find(dev * 16 + rule * 8 + p);
+    auto it = g_tables.find(dev * 64 + type * 16 + rule * 8 + p);
     return it == g_tables.end() ? nullptr : it->second;
 }
 
-// Upload the tables of degree p on rule `rule` to the current device (once).
-feint_status prepare_tables(int p, int rule) {
+// Upload the tables of degree p on rule `rule` of element type `type`
+// (0 prism, 1 hexahedron) to the current device (once).
+feint_status prepare_tables(int p, int rule, int type) {
     if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
-    if (!valid_rule(rule)) return FEINT_ERR_INVALID_ARG;
+    if (!valid_rule(rule) || (type != 0 && type != 1) || (type == 1 && rule != 0)) return FEINT_ERR_INVALID_ARG;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) { set_error("hipGetDevice", e); return FEINT_ERR_HIP; }
     std::lock_guard<std::mutex> lk(g_mu);
-    if (g_tables.count(dev * 16 + rule * 8 + p)) return FEINT_OK;
-    HostTables H = build_tables(p, rule);
+    const int key = dev * 64 + type * 16 + rule * 8 + p;
+    if (g_tables.count(key)) return FEINT_OK;
+    HostTables H = type ? build_hex_tables(p) : build_tables(p, rule);
     auto align = [](size_t x) { return (x + 255) / 256 * 256; };
     const size_t s_qw = align(H.qw.size() * 8), s_gll = align(H.gll.size() * 8), s_b64 = align(H.B64.size() * 8), s_b32 = align(H.B32.size() * 4);
     const size_t s_sp = align(H.bf_hi.size() * 2);
@@ -92,22 +95,22 @@ feint_status prepare_tables(int p, int rule) {
         delete T;
         return FEINT_ERR_HIP;
     }
-    g_tables[dev * 16 + rule * 8 + p] = T;
+    g_tables[key] = T;
     return FEINT_OK;
 }
 
 // Tables for a launch on `stream`: prepared on demand unless the stream is
 // being captured.
-feint_status tables_for_launch(int p, hipStream_t stream, const DevTables **out, int rule) {
-    const DevTables *T = find_tables(p, rule);
+feint_status tables_for_launch(int p, hipStream_t stream, const DevTables **out, int rule, int type) {
+    const DevTables *T = find_tables(p, rule, type);
     if (!T) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         hipError_t e = hipStreamIsCapturing(stream, &cs);
         if (e != hipSuccess) { set_error("hipStreamIsCapturing", e); return FEINT_ERR_HIP; }
         if (cs != hipStreamCaptureStatusNone) return FEINT_ERR_NOT_PREPARED;
-        feint_status s = prepare_tables(p, rule);
+        feint_status s = prepare_tables(p, rule, type);
         if (s != FEINT_OK) return s;
-        T = find_tables(p, rule);
+        T = find_tables(p, rule, type);
     }
     *out = T;
     return FEINT_OK;
@@ -348,6 +351,120 @@ feint_status feint_autotune(const feint_elements *el, int p, feint_form form, vo
     return feint_autotune_rule(el, nullptr, p, form, FEINT_RULE_COLLAPSED, A, b, reps, best_ms, stream);
 }
 
+int feint_hex_nshp(int p) { return (p < 1 || p > kMaxP) ? -1 : (p + 1) * (p + 1) * (p + 1); }
+int feint_hex_nq(int p) { return feint_hex_nshp(p); }
+
+feint_status feint_prepare_hex(int p) { return prepare_tables(p, FEINT_RULE_COLLAPSED, 1); }
+
+int feint_hex_tile_count(int p, feint_form form) {
+    int cnt = 0;
+    if (p < 1 || p > kMaxP || !valid_form(form)) return 0;
+    fwd_variants_hex(form, p, &cnt);
+    return cnt;
+}
+
+int feint_hex_tile_get(int p, feint_form form) {
+    if (feint_hex_tile_count(p, form) == 0) return -1;
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_tile_hex[p][form];
+}
+
+feint_status feint_hex_tile_set(int p, feint_form form, int tile) {
+    if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
+    if (!valid_form(form) || feint_hex_tile_count(p, form) == 0) return FEINT_ERR_UNSUPPORTED_FORM;
+    if (tile < 0 || tile >= feint_hex_tile_count(p, form)) return FEINT_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tile_hex[p][form] = tile;
+    return FEINT_OK;
+}
+
+feint_status feint_hex_tile_describe(int p, feint_form form, int tile, char *buf, size_t len) {
+    int cnt = 0;
+    if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
+    if (!valid_form(form)) return FEINT_ERR_UNSUPPORTED_FORM;
+    const FwdVariant *v = fwd_variants_hex(form, p, &cnt);
+    if (!buf || tile < 0 || tile >= cnt) return FEINT_ERR_INVALID_ARG;
+    std::snprintf(buf, len, "%dx%d%s", v[tile].tm, v[tile].tn, v[tile].minw > 1 ? "o2" : "");
+    return FEINT_OK;
+}
+
+// Forward parameters of a hexahedral launch (host checks done by the caller).
+static feint_status hex_params(const feint_elements *el, int p, feint_form form, void *A, void *b, hipStream_t st,
+                               FwdParams &prm, const FwdVariant **vsel, int tile) {
+    const DevTables *T = nullptr;
+    feint_status s = tables_for_launch(p, st, &T, FEINT_RULE_COLLAPSED, 1);
+    if (s != FEINT_OK) return s;
+    fill_fwd_params(prm, el, form, T);
+    prm.A = A; prm.b = b;
+    int cnt = 0;
+    const FwdVariant *v = fwd_variants_hex(form, p, &cnt);
+    if (!v || cnt == 0) return FEINT_ERR_UNSUPPORTED_FORM;
+    if (tile < 0) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        tile = g_tile_hex[p][form];
+    }
+    *vsel = &v[(tile >= 0 && tile < cnt) ? tile : 0];
+    return FEINT_OK;
+}
+
+feint_status feint_integrate_hex(const feint_elements *el, int p, feint_form form, void *A, void *b,
+                                 double *xq, uint32_t *dev_status, void *stream) {
+    if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
+    if (!valid_form(form) || feint_hex_tile_count(p, form) == 0) return FEINT_ERR_UNSUPPORTED_FORM;
+    feint_status s = check_elements(el);
+    if (s != FEINT_OK) return s;
+    if (el->ne == 0) return FEINT_OK;
+    if (!A || !b) return FEINT_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    FwdParams prm;
+    const FwdVariant *v = nullptr;
+    s = hex_params(el, p, form, A, b, st, prm, &v, -1);
+    if (s != FEINT_OK) return s;
+    prm.xq = xq;
+    prm.status = dev_status;
+    return launch_forward(prm, v, st);
+}
+
+feint_status feint_hex_autotune(const feint_elements *el, int p, feint_form form, void *A, void *b, int reps,
+                                double *best_ms, void *stream) {
+    if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
+    if (!valid_form(form) || feint_hex_tile_count(p, form) == 0) return FEINT_ERR_UNSUPPORTED_FORM;
+    feint_status s = check_elements(el);
+    if (s != FEINT_OK) return s;
+    if (!A || !b || el->ne == 0 || reps < 1) return FEINT_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const int cnt = feint_hex_tile_count(p, form);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return FEINT_ERR_HIP;
+    int best = 0;
+    float best_t = 1e30f;
+    for (int t = 0; t < cnt && s == FEINT_OK; ++t) {
+        FwdParams prm;
+        const FwdVariant *v = nullptr;
+        s = hex_params(el, p, form, A, b, st, prm, &v, t);
+        if (s != FEINT_OK) break;
+        s = launch_forward(prm, v, st);                       // warm-up
+        if (s != FEINT_OK) break;
+        (void)hipEventRecord(e0, st);
+        for (int r = 0; r < reps && s == FEINT_OK; ++r) s = launch_forward(prm, v, st);
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) { s = FEINT_ERR_HIP; break; }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (ms < best_t) { best_t = ms; best = t; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != FEINT_OK) return s;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_tile_hex[p][form] = best;
+    }
+    if (best_ms) *best_ms = best_t;
+    return FEINT_OK;
+}
+
 const char *feint_status_string(feint_status s) {
     switch (s) {
     case FEINT_OK: return "ok";
@@ -368,7 +485,7 @@ void feint_shutdown(void) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     for (auto &kv : g_tables) {
-        (void)hipSetDevice(kv.first / 16);
+        (void)hipSetDevice(kv.first / 64);
         (void)hipFree(kv.second->base);
         delete kv.second;
     }

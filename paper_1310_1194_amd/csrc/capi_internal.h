@@ -20,9 +20,9 @@ struct DevTables {
 };
 
 void set_error(const char *what, hipError_t e);
-feint_status prepare_tables(int p, int rule = 0);
-const DevTables *find_tables(int p, int rule = 0);
-feint_status tables_for_launch(int p, hipStream_t stream, const DevTables **out, int rule = 0);
+feint_status prepare_tables(int p, int rule = 0, int type = 0);
+const DevTables *find_tables(int p, int rule = 0, int type = 0);
+feint_status tables_for_launch(int p, hipStream_t stream, const DevTables **out, int rule = 0, int type = 0);
 feint_status check_elements(const feint_elements *el);
 void fill_fwd_params(FwdParams &prm, const feint_elements *el, int form, const DevTables *T);
 const FwdVariant *chosen_variant(int p, int form, int rule = 0);

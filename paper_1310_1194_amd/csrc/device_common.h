@@ -93,12 +93,9 @@ __device__ inline void prism_map(const double *X, double xi1, double xi2, double
 // grad phi_a . D grad phi_b = ref_a . (K D K^T) ref_b and
 // beta . grad phi_b = (K beta) . ref_b, so with wd = w det J
 //   W = wd [[ c, (K beta)^T ], [ 0, K D K^T ]]     (4x4, row-major into W[16])
-// and sf = wd f is the load-vector weight.  Returns det J.
-__device__ inline double point_block(const ElemIn &E, double xi1, double xi2, double ze, double w,
-                                     double W[16], double &sf) {
-    double K[9];
-    const double det = prism_jacobian(E.X, xi1, xi2, ze, K);
-    const double wd = w * det;
+// and sf = wd f is the load-vector weight.  El holds D, be, c, f.
+template <class El>
+__device__ inline void fused_block(const El &E, const double K[9], double wd, double W[16], double &sf) {
     double KD[9];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -115,6 +112,75 @@ __device__ inline double point_block(const ElemIn &E, double xi1, double xi2, do
             W[4 * (i + 1) + 1 + j] = wd * (KD[3 * i] * K[3 * j] + KD[3 * i + 1] * K[3 * j + 1] + KD[3 * i + 2] * K[3 * j + 2]);
     }
     sf = wd * E.f;
+}
+
+// Prism: W_q and sf at reference point (xi1, xi2, zeta) with weight w; returns det J.
+__device__ inline double point_block(const ElemIn &E, double xi1, double xi2, double ze, double w,
+                                     double W[16], double &sf) {
+    double K[9];
+    const double det = prism_jacobian(E.X, xi1, xi2, ze, K);
+    fused_block(E, K, w * det, W, sf);
+    return det;
+}
+
+// ---------------------------------------------------------------------------
+// Hexahedra (trilinear geometry on the reference cube [-1,1]^3; vertex
+// v = i + 2j + 4k sits at (2i-1, 2j-1, 2k-1)).
+struct ElemHex {
+    double X[24];   // vertices v0..v7
+    double D[9];
+    double be[3];
+    double c, f;
+};
+
+// Jacobian columns of the trilinear map as averages of the four parallel
+// edge vectors, weighted by the bilinear factors of the other two
+// coordinates: dx/dxi = sum over the edges along xi of
+// (v_hi - v_lo) (1 +- eta)(1 +- zeta) / 8, and likewise for eta and zeta.
+// Returns det J; K = J^{-1} via cofactors.
+__device__ inline double hex_jacobian(const double *X, double xi, double eta, double ze, double K[9]) {
+    const double a0 = 1.0 - xi, a1 = 1.0 + xi, b0 = 1.0 - eta, b1 = 1.0 + eta, g0 = 1.0 - ze, g1 = 1.0 + ze;
+    double c0[3], c1[3], c2[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double x0 = X[d], x1 = X[3 + d], x2 = X[6 + d], x3 = X[9 + d];
+        const double x4 = X[12 + d], x5 = X[15 + d], x6 = X[18 + d], x7 = X[21 + d];
+        c0[d] = 0.125 * (b0 * g0 * (x1 - x0) + b1 * g0 * (x3 - x2) + b0 * g1 * (x5 - x4) + b1 * g1 * (x7 - x6));
+        c1[d] = 0.125 * (a0 * g0 * (x2 - x0) + a1 * g0 * (x3 - x1) + a0 * g1 * (x6 - x4) + a1 * g1 * (x7 - x5));
+        c2[d] = 0.125 * (a0 * b0 * (x4 - x0) + a1 * b0 * (x5 - x1) + a0 * b1 * (x6 - x2) + a1 * b1 * (x7 - x3));
+    }
+    const double r0[3] = {c1[1] * c2[2] - c1[2] * c2[1], c1[2] * c2[0] - c1[0] * c2[2], c1[0] * c2[1] - c1[1] * c2[0]};
+    const double r1[3] = {c2[1] * c0[2] - c2[2] * c0[1], c2[2] * c0[0] - c2[0] * c0[2], c2[0] * c0[1] - c2[1] * c0[0]};
+    const double r2[3] = {c0[1] * c1[2] - c0[2] * c1[1], c0[2] * c1[0] - c0[0] * c1[2], c0[0] * c1[1] - c0[1] * c1[0]};
+    const double det = c0[0] * r0[0] + c0[1] * r0[1] + c0[2] * r0[2];
+    const double inv = 1.0 / det;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        K[d] = r0[d] * inv;
+        K[3 + d] = r1[d] * inv;
+        K[6 + d] = r2[d] * inv;
+    }
+    return det;
+}
+
+__device__ inline void hex_map(const double *X, double xi, double eta, double ze, double x[3]) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        // trilinear interpolation, one coordinate direction at a time
+        const double e00 = X[d] + 0.5 * (1.0 + xi) * (X[3 + d] - X[d]);
+        const double e10 = X[6 + d] + 0.5 * (1.0 + xi) * (X[9 + d] - X[6 + d]);
+        const double e01 = X[12 + d] + 0.5 * (1.0 + xi) * (X[15 + d] - X[12 + d]);
+        const double e11 = X[18 + d] + 0.5 * (1.0 + xi) * (X[21 + d] - X[18 + d]);
+        const double f0 = e00 + 0.5 * (1.0 + eta) * (e10 - e00), f1 = e01 + 0.5 * (1.0 + eta) * (e11 - e01);
+        x[d] = f0 + 0.5 * (1.0 + ze) * (f1 - f0);
+    }
+}
+
+__device__ inline double point_block_hex(const ElemHex &E, double xi, double eta, double ze, double w,
+                                         double W[16], double &sf) {
+    double K[9];
+    const double det = hex_jacobian(E.X, xi, eta, ze, K);
+    fused_block(E, K, w * det, W, sf);
     return det;
 }
 

@@ -93,25 +93,67 @@ __device__ inline void field_at(const FwdParams &prm, int64_t e, double xi1, dou
     }
 }
 
-// The load-vector column of degree P: whether it exists (a spare padded
-// column), the first column of its 16-wide tile and its lane in that tile.
-template <int P> struct LoadCol {
-    static constexpr int N = c_nshp(P);
+// The load-vector column of an element with NS shape functions: whether it
+// exists (a spare padded column), the first column of its 16-wide tile and
+// its lane in that tile.
+template <int NS> struct LoadColN {
+    static constexpr int N = NS;
     static constexpr bool on = N < c_pad16(N);
     static constexpr int tile0 = N / 16 * 16, lane = N % 16;
+};
+template <int P> using LoadCol = LoadColN<c_nshp(P)>;
+
+// Element geometry of a forward kernel: the element record, the shape-function
+// and point counts, the element load, the coefficients at a point, W_q and the
+// mapped point.  qp = (reference coordinates, weight) of the point.
+struct PrismGeo {
+    typedef ElemIn Elem;
+    __host__ __device__ static constexpr int nshp(int p) { return c_nshp(p); }
+    __host__ __device__ static constexpr int nq(int p, int r) { return c_nq_rule(p, r); }
+    __device__ static void load(const FwdParams &prm, int64_t e, Elem &E) { load_elem_fwd(prm, e, E); }
+    __device__ static void coeffs(const FwdParams &prm, int64_t e, const double *qp, Elem &E) {
+        field_at(prm, e, qp[0], qp[1], qp[2], E);
+    }
+    __device__ static double block(const Elem &E, const double *qp, double W[16], double &sf) {
+        return point_block(E, qp[0], qp[1], qp[2], qp[3], W, sf);
+    }
+    __device__ static void map(const Elem &E, const double *qp, double x[3]) { prism_map(E.X, qp[0], qp[1], qp[2], x); }
+};
+
+// Hexahedra (Table 1's tensor-product element): (p+1)^3 shape functions and
+// (p+1)^3 Gauss points; coordinates [ne][8][3], coefficients per element.
+struct HexGeo {
+    typedef ElemHex Elem;
+    __host__ __device__ static constexpr int nshp(int p) { return (p + 1) * (p + 1) * (p + 1); }
+    __host__ __device__ static constexpr int nq(int p, int) { return (p + 1) * (p + 1) * (p + 1); }
+    __device__ static void load(const FwdParams &prm, int64_t e, Elem &E) {
+#pragma unroll
+        for (int i = 0; i < 24; ++i) E.X[i] = prm.coords[24 * e + i];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) E.D[i] = prm.D[9 * e + i];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) E.be[i] = prm.beta[3 * e + i];
+        E.c = prm.c[e];
+        E.f = prm.f[e];
+    }
+    __device__ static void coeffs(const FwdParams &, int64_t, const double *, Elem &) {}
+    __device__ static double block(const Elem &E, const double *qp, double W[16], double &sf) {
+        return point_block_hex(E, qp[0], qp[1], qp[2], qp[3], W, sf);
+    }
+    __device__ static void map(const Elem &E, const double *qp, double x[3]) { hex_map(E.X, qp[0], qp[1], qp[2], x); }
 };
 
 // ---------------------------------------------------------------------------
 // 16x16x4 forms (FP64, FP32): one point (4 K-rows) per MFMA.
 // ---------------------------------------------------------------------------
-template <int P, typename T, int TM, int TN, int R = 0>
+template <int P, typename T, int TM, int TN, int R = 0, class G = PrismGeo>
 struct K4 {
-    static constexpr int N = c_nshp(P), NP = c_pad16(N), NT = NP / 16, NQ = c_nq_rule(P, R);
+    static constexpr int N = G::nshp(P), NP = c_pad16(N), NT = NP / 16, NQ = G::nq(P, R);
     static constexpr int BM = c_cdiv(NT, TM), BN = c_cdiv(NT, TN), NBLK = BM * BN;
     static constexpr int EPI = 1;                      // element slots per work item
     static constexpr int NBR = c_cdiv(TM * 16, 64);   // load-vector rows per lane
     typedef typename AccT<T>::type V4;
-    typedef LoadCol<P> LC;
+    typedef LoadColN<N> LC;
 
     struct Slice {                    // one wave's LDS
         T W[64][WROW<T>::value];      // padded rows: conflict-free per-lane writes
@@ -128,8 +170,8 @@ struct K4 {
         const int i16 = lane & 15, kg = lane >> 4;
         const int a0 = bi * TM * 16, b0 = bj * TN * 16;
         const int64_t e = elem_of(prm, slot);
-        ElemIn E;
-        load_elem_fwd(prm, e, E);
+        typename G::Elem E;
+        G::load(prm, e, E);
         const T *Bt = sizeof(T) == 8 ? (const T *)(const void *)prm.B64 : (const T *)(const void *)prm.B32;
         V4 acc[TMV][TNV];
 #pragma unroll
@@ -146,15 +188,15 @@ struct K4 {
                 const int q = qc + lane;
                 const double *qp = prm.qw + 4 * q;
                 double W[16], sf;
-                field_at(prm, e, qp[0], qp[1], qp[2], E);
-                const double det = point_block(E, qp[0], qp[1], qp[2], qp[3], W, sf);
+                G::coeffs(prm, e, qp, E);
+                const double det = G::block(E, qp, W, sf);
                 if (!(det > 0.0) && prm.status) atomicOr(prm.status, 1u);
 #pragma unroll
                 for (int k = 0; k < 16; ++k) sl.W[lane][k] = (T)W[k];
                 sl.sf[lane] = sf;
                 if (prm.xq && blk == 0) {
                     double x[3];
-                    prism_map(E.X, qp[0], qp[1], qp[2], x);
+                    G::map(E, qp, x);
 #pragma unroll
                     for (int d = 0; d < 3; ++d) prm.xq[(e * NQ + q) * 3 + d] = x[d];
                 }

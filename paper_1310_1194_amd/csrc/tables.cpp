@@ -363,6 +363,56 @@ void lagrange_prism_eval(int p, const double *xi, double *phi, double *dphi) {
     eval_modal(mb, xi, phi, dphi);
 }
 
+// Every layout the kernels read, derived from B64 (and nq, nqp, npad).
+static void derive_layouts(HostTables &T) {
+    const int np = T.npad;
+    T.BT64.assign(T.B64.size(), 0.0);
+    T.BT32.assign(T.B64.size(), 0.0f);
+    for (int q = 0; q < T.nqp; ++q)
+        for (int r = 0; r < 4; ++r)
+            for (int a = 0; a < np; ++a) {
+                const double v = T.B64[((size_t)q * 4 + r) * np + a];
+                T.BT64[(size_t)a * T.nqp * 4 + q * 4 + r] = v;
+                T.BT32[(size_t)a * T.nqp * 4 + q * 4 + r] = (float)v;
+            }
+    T.Bc32.assign(T.B64.size(), 0.0f);
+    for (int q = 0; q < T.nqp; ++q)
+        for (int a = 0; a < np; ++a)
+            for (int r = 0; r < 4; ++r)
+                T.Bc32[((size_t)q * np + a) * 4 + r] = (float)T.B64[((size_t)q * 4 + r) * np + a];
+    T.B32.resize(T.B64.size());
+    double bmax = 0.0;
+    for (size_t i = 0; i < T.B64.size(); ++i) {
+        T.B32[i] = (float)T.B64[i];
+        bmax = std::fmax(bmax, std::fabs(T.B64[i]));
+    }
+    // fp16 tables are scaled so that max |B| lies in [2^13, 2^14)
+    T.f16_shift = 13 - (int)std::floor(std::log2(bmax));
+    const double fs = std::ldexp(1.0, T.f16_shift);
+    const size_t nsplit = (size_t)T.nkb * np * 32;
+    const int ntile = np / 16;
+    T.bf_hi.assign(nsplit, 0); T.bf_lo.assign(nsplit, 0);
+    T.hf_hi.assign(nsplit, 0); T.hf_lo.assign(nsplit, 0);
+    T.Ycf.assign(nsplit, 0.0f);
+    for (int kb = 0; kb < T.nkb; ++kb)
+        for (int a = 0; a < np; ++a)
+            for (int k = 0; k < 32; ++k) {
+                const int q = kb * 8 + k / 4, r = k % 4;
+                const double x = T.B64[((size_t)q * 4 + r) * np + a];
+                const int lane = a % 16 + 16 * (k / 8);
+                const size_t o = (((size_t)kb * ntile + a / 16) * 64 + lane) * 8 + k % 8;
+                const uint16_t h = to_bf16((float)x);
+                T.bf_hi[o] = h;
+                T.bf_lo[o] = to_bf16((float)(x - (double)from_bf16(h)));
+                const double xs = x * fs;
+                const uint16_t hh = to_f16(xs);
+                T.hf_hi[o] = hh;
+                T.hf_lo[o] = to_f16(xs - from_f16(hh));
+                // the same (point, row, column) as a B-fragment column value
+                T.Ycf[o] = (float)x;
+            }
+}
+
 void rule_points(int p, int rule, std::vector<double> &qw) {
     if (p < 1 || p > kMaxP) throw std::runtime_error("degree out of range");
     if (rule != 0 && rule != 1) throw std::runtime_error("unknown quadrature rule");
@@ -432,51 +482,75 @@ HostTables build_tables(int p, int rule) {
             for (int r = 0; r < 3; ++r) T.B64[((size_t)q * 4 + 1 + r) * np + a] = dphi[3 * a + r];
         }
     }
-    T.BT64.assign(T.B64.size(), 0.0);
-    T.BT32.assign(T.B64.size(), 0.0f);
-    for (int q = 0; q < T.nqp; ++q)
-        for (int r = 0; r < 4; ++r)
-            for (int a = 0; a < np; ++a) {
-                const double v = T.B64[((size_t)q * 4 + r) * np + a];
-                T.BT64[(size_t)a * T.nqp * 4 + q * 4 + r] = v;
-                T.BT32[(size_t)a * T.nqp * 4 + q * 4 + r] = (float)v;
+    derive_layouts(T);
+    return T;
+}
+
+HostTables build_hex_tables(int p) {
+    if (p < 1 || p > kMaxP) throw std::runtime_error("degree out of range");
+    HostTables T;
+    T.p = p;
+    T.rule = 0;
+    const int n1 = p + 1;
+    T.n = n1 * n1 * n1;
+    T.npad = pad16(T.n);
+    T.nq = n1 * n1 * n1;
+    T.nqp = pad8(T.nq);
+    T.nkb = T.nqp / 8;
+    double g[kMaxP + 1], gw[kMaxP + 1];
+    gauss_legendre_gw(n1, g, gw);
+    T.qw.assign((size_t)T.nqp * 4, 0.0);
+    for (int k = 0; k < n1; ++k)
+        for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n1; ++i) {
+                const int q = (k * n1 + j) * n1 + i;
+                T.qw[4 * q + 0] = g[i];
+                T.qw[4 * q + 1] = g[j];
+                T.qw[4 * q + 2] = g[k];
+                T.qw[4 * q + 3] = gw[i] * gw[j] * gw[k];
             }
-    T.Bc32.assign(T.B64.size(), 0.0f);
-    for (int q = 0; q < T.nqp; ++q)
-        for (int a = 0; a < np; ++a)
-            for (int r = 0; r < 4; ++r)
-                T.Bc32[((size_t)q * np + a) * 4 + r] = (float)T.B64[((size_t)q * 4 + r) * np + a];
-    T.B32.resize(T.B64.size());
-    double bmax = 0.0;
-    for (size_t i = 0; i < T.B64.size(); ++i) {
-        T.B32[i] = (float)T.B64[i];
-        bmax = std::fmax(bmax, std::fabs(T.B64[i]));
+    // (padding points: reference centre, zero weight -- already zero)
+    T.gll.assign(2 * n1, 0.0);
+    gauss_lobatto_nodes(p, T.gll.data());
+    // 1D Lagrange basis on the Gauss-Lobatto nodes as Legendre combinations:
+    // C = V^{-1}, V[i][m] = P_m(z_i); L_k = sum_m C[m][k] P_m
+    std::vector<long double> V((size_t)n1 * n1);
+    long double P[kMaxP + 1], dP[kMaxP + 1];
+    for (int i = 0; i < n1; ++i) {
+        legendre_all(p, (long double)T.gll[i], P, dP);
+        for (int m = 0; m < n1; ++m) V[i * n1 + m] = P[m];
     }
-    // fp16 tables are scaled so that max |B| lies in [2^13, 2^14)
-    T.f16_shift = 13 - (int)std::floor(std::log2(bmax));
-    const double fs = std::ldexp(1.0, T.f16_shift);
-    const size_t nsplit = (size_t)T.nkb * np * 32;
-    const int ntile = np / 16;
-    T.bf_hi.assign(nsplit, 0); T.bf_lo.assign(nsplit, 0);
-    T.hf_hi.assign(nsplit, 0); T.hf_lo.assign(nsplit, 0);
-    T.Ycf.assign(nsplit, 0.0f);
-    for (int kb = 0; kb < T.nkb; ++kb)
-        for (int a = 0; a < np; ++a)
-            for (int k = 0; k < 32; ++k) {
-                const int q = kb * 8 + k / 4, r = k % 4;
-                const double x = T.B64[((size_t)q * 4 + r) * np + a];
-                const int lane = a % 16 + 16 * (k / 8);
-                const size_t o = (((size_t)kb * ntile + a / 16) * 64 + lane) * 8 + k % 8;
-                const uint16_t h = to_bf16((float)x);
-                T.bf_hi[o] = h;
-                T.bf_lo[o] = to_bf16((float)(x - (double)from_bf16(h)));
-                const double xs = x * fs;
-                const uint16_t hh = to_f16(xs);
-                T.hf_hi[o] = hh;
-                T.hf_lo[o] = to_f16(xs - from_f16(hh));
-                // the same (point, row, column) as a B-fragment column value
-                T.Ycf[o] = (float)x;
+    const std::vector<long double> C = invert(n1, V);
+    auto line = [&](double x, double *l, double *dl) {
+        legendre_all(p, (long double)x, P, dP);
+        for (int k = 0; k < n1; ++k) {
+            long double v = 0, d = 0;
+            for (int m = 0; m < n1; ++m) {
+                v += C[m * n1 + k] * P[m];
+                d += C[m * n1 + k] * dP[m];
             }
+            l[k] = (double)v;
+            dl[k] = (double)d;
+        }
+    };
+    const int np = T.npad;
+    T.B64.assign((size_t)T.nqp * 4 * np, 0.0);
+    double lx[kMaxP + 1], dlx[kMaxP + 1], ly[kMaxP + 1], dly[kMaxP + 1], lz[kMaxP + 1], dlz[kMaxP + 1];
+    for (int q = 0; q < T.nq; ++q) {
+        line(T.qw[4 * q + 0], lx, dlx);
+        line(T.qw[4 * q + 1], ly, dly);
+        line(T.qw[4 * q + 2], lz, dlz);
+        for (int k = 0; k < n1; ++k)
+            for (int j = 0; j < n1; ++j)
+                for (int i = 0; i < n1; ++i) {
+                    const int a = (k * n1 + j) * n1 + i;
+                    T.B64[((size_t)q * 4 + 0) * np + a] = lx[i] * ly[j] * lz[k];
+                    T.B64[((size_t)q * 4 + 1) * np + a] = dlx[i] * ly[j] * lz[k];
+                    T.B64[((size_t)q * 4 + 2) * np + a] = lx[i] * dly[j] * lz[k];
+                    T.B64[((size_t)q * 4 + 3) * np + a] = lx[i] * ly[j] * dlz[k];
+                }
+    }
+    derive_layouts(T);
     return T;
 }
 

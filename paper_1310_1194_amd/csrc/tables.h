@@ -53,6 +53,10 @@ void rule_points(int p, int rule, std::vector<double> &qw);
 // Build every table of degree p (1..7) on quadrature rule `rule` (0, 1) in
 // FP64 on the host.
 HostTables build_tables(int p, int rule = 0);
+// Tables of the hexahedral element of degree p: tensor Gauss rule (q = (k n1 +
+// j) n1 + i, points on [-1,1]^3) and the tensor-product Gauss-Lobatto
+// Lagrange basis (a = (k (p+1) + j) (p+1) + i).
+HostTables build_hex_tables(int p);
 
 // Pieces exposed for the CPU tests of the library's host logic.
 void gauss_legendre_gw(int n, double *x, double *w);     // Golub-Welsch

@@ -29,7 +29,9 @@ EXPORTS = (
     "feint_shutdown", "feint_asm_plan_create", "feint_asm_plan_info", "feint_asm_plan_pattern",
     "feint_asm_plan_colors", "feint_assemble", "feint_asm_plan_destroy", "feint_nq_rule", "feint_rule_points",
     "feint_prepare_rule", "feint_integrate_rule", "feint_rule_tile_count", "feint_rule_tile_get",
-    "feint_rule_tile_set", "feint_rule_tile_describe", "feint_autotune_rule",
+    "feint_rule_tile_set", "feint_rule_tile_describe", "feint_autotune_rule", "feint_hex_nshp", "feint_hex_nq",
+    "feint_prepare_hex", "feint_integrate_hex", "feint_hex_tile_count", "feint_hex_tile_get", "feint_hex_tile_set",
+    "feint_hex_tile_describe", "feint_hex_autotune",
 )
 
 
@@ -117,6 +119,15 @@ def lib() -> ctypes.CDLL:
             "feint_rule_tile_describe": (_i, [_i, _i, _i, _i, ctypes.c_char_p, ctypes.c_size_t]),
             "feint_autotune_rule": (_i, [P, ctypes.POINTER(Fields), _i, _i, _i, _vp, _vp, _i,
                                          ctypes.POINTER(ctypes.c_double), _vp]),
+            "feint_hex_nshp": (_i, [_i]),
+            "feint_hex_nq": (_i, [_i]),
+            "feint_prepare_hex": (_i, [_i]),
+            "feint_integrate_hex": (_i, [P, _i, _i, _vp, _vp, _vp, _vp, _vp]),
+            "feint_hex_tile_count": (_i, [_i, _i]),
+            "feint_hex_tile_get": (_i, [_i, _i]),
+            "feint_hex_tile_set": (_i, [_i, _i, _i]),
+            "feint_hex_tile_describe": (_i, [_i, _i, _i, ctypes.c_char_p, ctypes.c_size_t]),
+            "feint_hex_autotune": (_i, [P, _i, _i, _vp, _vp, _i, ctypes.POINTER(ctypes.c_double), _vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
