@@ -65,7 +65,7 @@ def traffic_record(key: str, tile: str):
     return rec.get("tiles", {}).get(tile)
 
 
-def cpu_baseline(batch, p, budget_s: float, chunk: int = 4096, fields=None, rule=None):
+def cpu_baseline(batch, p, budget_s: float, chunk: int = 4096, fields=None, rule=None, hexa=False):
     """The oracle on the host's cores over the first elements of the workload,
     chunk by chunk until about `budget_s` seconds have been spent (with vertex
     coefficient fields when `fields` = (Dv, betav, cv, fv) is given)."""
@@ -75,7 +75,9 @@ def cpu_baseline(batch, p, budget_s: float, chunk: int = 4096, fields=None, rule
         sl = np.arange(done, min(batch.ne, done + chunk))
         sub = batch.subset(sl)
         t0 = time.perf_counter()
-        if fields is None:
+        if hexa:
+            A, b, _ = oracle.integrate_hex(p, sub.coords, sub.D, sub.beta, sub.c, sub.f)
+        elif fields is None:
             A, b, _ = oracle.integrate(p, sub.coords, sub.D, sub.beta, sub.c, sub.f, rule=rule)
         else:
             A, b, _ = oracle.integrate_fields(p, sub.coords, *[np.ascontiguousarray(a[sl]) for a in fields],
@@ -125,7 +127,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--mode", default="forward", choices=["forward", "fields", "adjoint", "mixed", "assemble"])
+    ap.add_argument("--mode", default="forward", choices=["forward", "fields", "hex", "adjoint", "mixed", "assemble"])
     ap.add_argument("--workload", default=None)
     ap.add_argument("--rule", default="collapsed", choices=["collapsed", "symmetric"],
                     help="quadrature rule of the forward and fields modes")
@@ -152,14 +154,15 @@ def main():
         return bench_mixed(args)
     if args.mode == "assemble":
         return bench_assemble(args)
-    return bench_forward(args, fields=args.mode == "fields")
+    return bench_forward(args, fields=args.mode == "fields", hexa=args.mode == "hex")
 
 
-def bench_forward(args, fields=False):
+def bench_forward(args, fields=False, hexa=False):
     """Forward integration; with `fields` the coefficients are vertex fields
-    evaluated at every point (feint_integrate_fields)."""
-    args.workload = args.workload or "p4_131072"
-    args.forms = args.forms or ("fp64,fp32" if args.sc else ",".join(FORMS))
+    evaluated at every point (feint_integrate_fields); with `hexa` the
+    elements are hexahedra (feint_integrate_hex)."""
+    args.workload = args.workload or ("hex_p4_65536" if hexa else "p4_131072")
+    args.forms = args.forms or ("fp64,fp32" if args.sc or hexa else ",".join(FORMS))
     import torch
     import paper_1310_1194_amd as F
 
@@ -169,11 +172,20 @@ def bench_forward(args, fields=False):
     p = w["p"]
     rule = args.rule
     n, q = costmodel.nshp(p), costmodel.nq(p, rule)
+    if hexa:
+        if rule != "collapsed" or args.sc or fields:
+            raise SystemExit("hexahedra: tensor Gauss rule, table-reading kernels, element constants")
+        n = q = (p + 1) ** 3
     batch = meshgen.workload(args.workload)
     ne = batch.ne
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     vf = meshgen.vertex_fields(ne, 1000 + w["seed"]) if fields else None
-    if fields:
+    if hexa:
+        X = (t(batch.coords), t(batch.D), t(batch.beta), t(batch.c), t(batch.f))
+
+        def integrate(*a, A=None, b=None, rule=None):
+            return F.integrate_hex_raw(*a, A=A, b=b)
+    elif fields:
         X = (t(batch.coords),) + tuple(t(a) for a in vf)
         integrate = F.integrate_fields_raw
     else:
@@ -207,11 +219,16 @@ def bench_forward(args, fields=False):
                 raise SystemExit(f"no SC variant compiled for p={p} form={form}")
             F.tile_set(p, form, sc[0], rule=rule)
         elif not args.no_tune:
-            if fields:
+            if hexa:
+                tile_ms = F.hex_autotune(*X, p, form, A, b, reps=2)
+            elif fields:
                 tile_ms = F.autotune_fields(*X, p, form, A, b, reps=2, rule=rule)
             else:
                 tile_ms = F.autotune(*X, p, form, A, b, reps=2, rule=rule)
-        tile = F.tile_describe(p, form, F.tile_get(p, form, rule=rule), rule=rule)
+        if hexa:
+            tile = F.hex_tile_describe(p, form, F.hex_tile_get(p, form))
+        else:
+            tile = F.tile_describe(p, form, F.tile_get(p, form, rule=rule), rule=rule)
         for _ in range(args.warmup):
             integrate(*X, p, form, A=A, b=b, rule=rule)
         torch.cuda.synchronize()
@@ -233,10 +250,11 @@ def bench_forward(args, fields=False):
                              A_sample=A[sample_idx].cpu().numpy(), b_sample=b[sample_idx].cpu().numpy())
         print(f"[bench] {form}: {ms:.3f} ms/launch (min {np.min(per):.3f}), tile {tile}", file=sys.stderr, flush=True)
 
-    fdom = costmodel.f_dom(p, rule)
-    in_bytes = costmodel.FIELD_INPUT_BYTES if fields else costmodel.INPUT_BYTES
+    fdom = 8 * n * n * q if hexa else costmodel.f_dom(p, rule)
+    in_bytes = (8 * (24 + 9 + 3 + 1 + 1) if hexa else
+                costmodel.FIELD_INPUT_BYTES if fields else costmodel.INPUT_BYTES)
     for form, r in results.items():
-        es = costmodel.out_bytes(p, 8 if form == "fp64" else 4)
+        es = (n * n + n) * (8 if form == "fp64" else 4)
         alg_bytes = ne * (in_bytes + es)
         r["gflops"] = fdom * ne / (r["kernel_ms_mean"] * 1e-3) / 1e9
         r["tflops_frac_of_peak"] = r["gflops"] / 1e3 / PEAK_TFLOPS[form]
@@ -245,7 +263,7 @@ def bench_forward(args, fields=False):
     cpu = None
     if not args.no_cpu:
         rate, done, spent, cores, (Ar, br) = cpu_baseline(batch, p, args.cpu_budget, fields=vf,
-                                                          rule=None if rule == "collapsed" else rule)
+                                                          rule=None if rule == "collapsed" else rule, hexa=hexa)
         cpu = {"value": rate, "unit": "elements/s", "cores": cores, "kind": "oracle",
                "sample": f"first {done} of the {ne} elements of {args.workload} "
                          f"({spent:.1f} s, FP64, OpenMP over elements)",
@@ -261,10 +279,10 @@ def bench_forward(args, fields=False):
 
     h = results[headline]
     rkey = "" if rule == "collapsed" else ":" + rule
-    traffic = traffic_record(f"{'fields' if fields else 'fwd'}:{headline}:{args.workload}{rkey}",
+    traffic = traffic_record(f"{'hex' if hexa else 'fields' if fields else 'fwd'}:{headline}:{args.workload}{rkey}",
                              results[headline]["tile"])
     es = 8 if headline == "fp64" else 4
-    alg_bytes = ne * (costmodel.fields_bytes_per_element(p, es) if fields else costmodel.bytes_per_element(p, es))
+    alg_bytes = ne * (in_bytes + (n * n + n) * es)
     # bound = the larger ideal time: MFMA work (three products for a split
     # form) at the dtype's dense peak, or the algorithmic bytes at HBM peak
     products = 3 if headline in ("bf16x3", "fp16x3") else 1
@@ -276,7 +294,7 @@ def bench_forward(args, fields=False):
     else:
         roofline = {"bound": "mfma", "achieved": h["gflops"] / 1e3, "peak": PEAK_TFLOPS[headline],
                     "unit": "TFLOP/s", "frac": h["gflops"] / 1e3 / PEAK_TFLOPS[headline]}
-    npad, nqp = (costmodel.nshp(p) + 15) // 16 * 16, (q + 7) // 8 * 8
+    npad, nqp = (n + 15) // 16 * 16, (q + 7) // 8 * 8
     hw_flops = products * 8.0 * npad * npad * (nqp if products == 3 else q) * ne
     roofline.update({"traffic": traffic, "kernel_ms": h["kernel_ms_mean"], "flops_per_launch": fdom * ne,
                      "hw_mfma_frac": hw_flops / (h["kernel_ms_mean"] * 1e-3) / (PEAK_TFLOPS[headline] * 1e12),
@@ -289,7 +307,8 @@ def bench_forward(args, fields=False):
                            if not k.endswith("_sample")}
     line = {
         "metric": "elements/s + GFLOP/s (roofline %) at p=4, plain FP64 vs MFMA form at stated error"
-                  + (" (coefficients varying in space, given at the vertices)" if fields else ""),
+                  + (" (coefficients varying in space, given at the vertices)" if fields else "")
+                  + (" (hexahedral elements)" if hexa else ""),
         "value": h["elements_per_s"],
         "unit": "elements/s",
         "n_gpus": 1,
@@ -304,6 +323,7 @@ def bench_forward(args, fields=False):
         "config": {"workload": args.workload + ("+vertex_fields" if fields else "")
                    + ("+symmetric_rule" if rule != "collapsed" else "") + ("+sc" if args.sc else ""),
                    "p": p, "ne": ne, "rule": rule, "shape_functions": "computed per point" if args.sc else "tables",
+                   "element": "hexahedron" if hexa else "prism",
                    "nshp": n, "nq": q, "coefficients": "vertex fields" if fields else "element constants",
                    "mesh": f"{w['nx']}x{w['ny']}x{w['nz']}", "perturbation": w["amp"], "seed": w["seed"],
                    "form": headline, "parallelism": "single GPU"},
