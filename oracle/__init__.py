@@ -50,6 +50,11 @@ def lib():
         L.oracle_integrate_fields.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [_dp] * 8 + [_ip]
         L.oracle_integrate_rule.argtypes = ([ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int64, ctypes.c_int]
                                             + [_dp] * 8 + [_ip])
+        L.oracle_tet_rule.argtypes = [ctypes.c_int, _dp, _dp]
+        L.oracle_tet_nodes.argtypes = [ctypes.c_int, _dp]
+        L.oracle_tet_basis.argtypes = [ctypes.c_int, _dp, _dp, _dp]
+        L.oracle_tet_geometry.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp]
+        L.oracle_integrate_tet.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [_dp] * 8 + [_ip]
         L.oracle_hex_rule.argtypes = [ctypes.c_int, _dp, _dp]
         L.oracle_hex_nodes.argtypes = [ctypes.c_int, _dp]
         L.oracle_hex_basis.argtypes = [ctypes.c_int, _dp, _dp, _dp]
@@ -288,6 +293,52 @@ def integrate_hex(p, coords, D, beta, c, f, n1=0, want_xq=False):
     flags = np.zeros(ne, dtype=np.int32)
     xq = np.zeros((ne, nqq, 3)) if want_xq else None
     rc = lib().oracle_integrate_hex(p, n1, ne, _p(coords), _p(D), _p(beta), _p(c), _p(f),
+                                    _p(A), _p(b), _p(xq), flags.ctypes.data_as(_ip))
+    assert rc == 0, rc
+    return (A, b, flags, xq) if want_xq else (A, b, flags)
+
+
+def tet_nshp(p):
+    return (p + 1) * (p + 2) * (p + 3) // 6
+
+
+def tet_rule(n1):
+    """n1^3 collapsed Gauss points on the reference tetrahedron (pts, w)."""
+    pts = np.zeros((n1 ** 3, 3)); w = np.zeros(n1 ** 3)
+    assert lib().oracle_tet_rule(n1, _p(pts), _p(w)) == n1 ** 3
+    return pts, w
+
+
+def tet_nodes(p):
+    out = np.zeros((tet_nshp(p), 3))
+    assert lib().oracle_tet_nodes(p, _p(out)) == tet_nshp(p)
+    return out
+
+
+def tet_basis(p, xi):
+    xi = _c(xi)
+    n = tet_nshp(p)
+    phi = np.zeros(n); dphi = np.zeros((n, 3))
+    assert lib().oracle_tet_basis(p, _p(xi), _p(phi), _p(dphi)) == 0
+    return phi, dphi
+
+
+def tet_geometry(X, xi):
+    X = _c(X); xi = _c(xi)
+    J = np.zeros((3, 3)); K = np.zeros((3, 3)); x = np.zeros(3); det = np.zeros(1)
+    lib().oracle_tet_geometry(_p(X), _p(xi), _p(J), _p(det), _p(K), _p(x))
+    return J, float(det[0]), K, x
+
+
+def integrate_tet(p, coords, D, beta, c, f, n1=0, want_xq=False):
+    """Tetrahedra (coords [ne,4,3]): A [ne,n,n], b [ne,n], flags (and xq)."""
+    coords = _c(coords); D = _c(D); beta = _c(beta); c = _c(c); f = _c(f)
+    ne, n = coords.shape[0], tet_nshp(p)
+    nqq = (n1 if n1 > 0 else p + 2) ** 3
+    A = np.zeros((ne, n, n)); b = np.zeros((ne, n))
+    flags = np.zeros(ne, dtype=np.int32)
+    xq = np.zeros((ne, nqq, 3)) if want_xq else None
+    rc = lib().oracle_integrate_tet(p, n1, ne, _p(coords), _p(D), _p(beta), _p(c), _p(f),
                                     _p(A), _p(b), _p(xq), flags.ctypes.data_as(_ip))
     assert rc == 0, rc
     return (A, b, flags, xq) if want_xq else (A, b, flags)

@@ -405,11 +405,93 @@ int oracle_hex_geometry(const double *X, const double *xi, double *J, double *de
 }
 
 /* ---------------------------------------------------------------------- */
+/* Tetrahedra (Table 1, complete basis)                                    */
+/* ---------------------------------------------------------------------- */
+/* Reference tetrahedron {xi >= 0, xi1 + xi2 + xi3 <= 1} (volume 1/6),
+   vertices v0 = 0, v1 = e1, v2 = e2, v3 = e3, affine geometry x = v0 +
+   sum_i xi_i (v_i - v0).  Shape functions: Lagrange on the lattice
+   (i/p, j/p, k/p), i + j + k <= p, k outer, j middle, i inner, by
+   Silvester's product in the four barycentric coordinates.  Rule: n1^3
+   collapsed Gauss-Legendre points (n1 = p+2 by default, exact for products of
+   shape functions), z = (1+c)/2, y = (1+b)(1-z)/2, x = (1+a)(1-y-z)/2,
+   w = w_a w_b w_c (1-b)(1-c)^2 / 64, q = (k n1 + j) n1 + i (a_i, b_j, c_k). */
+
+int oracle_tet_nshp(int p) { return (p < 1 || p > ORACLE_MAXP) ? -1 : (p + 1) * (p + 2) * (p + 3) / 6; }
+
+int oracle_tet_rule(int n1, double *pts, double *w)
+{
+    double g[ORACLE_MAXN1], gw[ORACLE_MAXN1];
+    if (n1 < 1 || n1 > ORACLE_MAXN1) return -1;
+    oracle_gauss_legendre(n1, g, gw);
+    int q = 0;
+    for (int k = 0; k < n1; ++k)
+        for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n1; ++i) {
+                double a = g[i], b = g[j], c = g[k];
+                double z = (1.0 + c) / 2.0;
+                double y = (1.0 + b) * (1.0 - z) / 2.0;
+                double x = (1.0 + a) * (1.0 - y - z) / 2.0;
+                pts[3 * q + 0] = x;
+                pts[3 * q + 1] = y;
+                pts[3 * q + 2] = z;
+                w[q] = gw[i] * gw[j] * gw[k] * (1.0 - b) * (1.0 - c) * (1.0 - c) / 64.0;
+                ++q;
+            }
+    return q;
+}
+
+int oracle_tet_nodes(int p, double *nodes)
+{
+    if (p < 1 || p > ORACLE_MAXP) return -1;
+    int a = 0;
+    for (int k = 0; k <= p; ++k)
+        for (int j = 0; j <= p - k; ++j)
+            for (int i = 0; i <= p - j - k; ++i) {
+                nodes[3 * a + 0] = (double)i / p;
+                nodes[3 * a + 1] = (double)j / p;
+                nodes[3 * a + 2] = (double)k / p;
+                ++a;
+            }
+    return a;
+}
+
+int oracle_tet_basis(int p, const double *xi, double *phi, double *dphi)
+{
+    if (p < 1 || p > ORACLE_MAXP) return -1;
+    const double lam[4] = {1.0 - xi[0] - xi[1] - xi[2], xi[0], xi[1], xi[2]};
+    int a = 0;
+    for (int k = 0; k <= p; ++k)
+        for (int j = 0; j <= p - k; ++j)
+            for (int i = 0; i <= p - j - k; ++i) {
+                int al[4] = {p - i - j - k, i, j, k};
+                double R[4], dR[4];
+                for (int m = 0; m < 4; ++m) silvester(p, al[m], lam[m], &R[m], &dR[m]);
+                double d0 = dR[0] * R[1] * R[2] * R[3];     /* d phi / d lambda_0 */
+                phi[a] = R[0] * R[1] * R[2] * R[3];
+                dphi[3 * a + 0] = R[0] * dR[1] * R[2] * R[3] - d0;
+                dphi[3 * a + 1] = R[0] * R[1] * dR[2] * R[3] - d0;
+                dphi[3 * a + 2] = R[0] * R[1] * R[2] * dR[3] - d0;
+                ++a;
+            }
+    return 0;
+}
+
+/* Affine tetrahedron X [4][3]: J[d][l] = (v_{l+1} - v_0)_d, det, K, x. */
+int oracle_tet_geometry(const double *X, const double *xi, double *J, double *det, double *K, double *x)
+{
+    for (int d = 0; d < 3; ++d) {
+        for (int l = 0; l < 3; ++l) J[3 * d + l] = X[3 * (l + 1) + d] - X[d];
+        if (x) x[d] = X[d] + J[3 * d] * xi[0] + J[3 * d + 1] * xi[1] + J[3 * d + 2] * xi[2];
+    }
+    return invert3(J, det, K);
+}
+
+/* ---------------------------------------------------------------------- */
 /* Algorithm 1: element loop -> quadrature loop -> i -> j                  */
 /* ---------------------------------------------------------------------- */
 
 typedef struct {
-    int type, p, n, nq;                     /* type 0: prism, 1: hexahedron */
+    int type, p, n, nq;                     /* type 0: prism, 1: hexahedron, 2: tetrahedron */
     double *pts, *w, *phi, *dphi; /* [nq][3], [nq], [nq][n], [nq][n][3] */
 } rule_tables;
 
@@ -419,12 +501,12 @@ typedef struct {
 static int make_tables(int type, int p, int n1, int nq, const double *qpts, const double *qw, rule_tables *T)
 {
     if (p < 1 || p > ORACLE_MAXP) return -1;
-    if (n1 <= 0) n1 = p + 1;
+    if (n1 <= 0) n1 = type == 2 ? p + 2 : p + 1;
     if (n1 > ORACLE_MAXN1) return -1;
     if (qpts && (nq < 1 || !qw)) return -1;
     T->type = type;
     T->p = p;
-    T->n = type ? oracle_hex_nshp(p) : oracle_nshp(p);
+    T->n = type == 2 ? oracle_tet_nshp(p) : type ? oracle_hex_nshp(p) : oracle_nshp(p);
     T->nq = qpts ? nq : n1 * n1 * n1;
     T->pts = (double *)malloc(sizeof(double) * 3 * T->nq);
     T->w = (double *)malloc(sizeof(double) * T->nq);
@@ -433,6 +515,8 @@ static int make_tables(int type, int p, int n1, int nq, const double *qpts, cons
     if (qpts) {
         memcpy(T->pts, qpts, sizeof(double) * 3 * T->nq);
         memcpy(T->w, qw, sizeof(double) * T->nq);
+    } else if (type == 2) {
+        oracle_tet_rule(n1, T->pts, T->w);
     } else if (type) {
         oracle_hex_rule(n1, T->pts, T->w);
     } else {
@@ -441,8 +525,8 @@ static int make_tables(int type, int p, int n1, int nq, const double *qpts, cons
     /* step 6 of Algorithm 1: shape functions at every point (the same for
        every element of degree p, so they are evaluated once) */
     for (int q = 0; q < T->nq; ++q)
-        (type ? oracle_hex_basis : oracle_basis)(p, T->pts + 3 * q, T->phi + (size_t)q * T->n,
-                                                 T->dphi + (size_t)3 * q * T->n);
+        (type == 2 ? oracle_tet_basis : type ? oracle_hex_basis : oracle_basis)(
+            p, T->pts + 3 * q, T->phi + (size_t)q * T->n, T->dphi + (size_t)3 * q * T->n);
     return 0;
 }
 
@@ -485,7 +569,7 @@ static int integrate_core(int type, int p, int n1, int nq, const double *qpts, c
     rule_tables T;
     if (ne < 0 || (type && nv != 1)) return -1;
     if (make_tables(type, p, n1, nq, qpts, qw, &T)) return -1;
-    const int nx = type ? 24 : 18;                 /* coordinates per element */
+    const int nx = type == 2 ? 12 : type ? 24 : 18;   /* coordinates per element */
     const int n = T.n, nqp = T.nq;
     int64_t e;
 #pragma omp parallel for schedule(static)
@@ -501,7 +585,8 @@ static int integrate_core(int type, int p, int n1, int nq, const double *qpts, c
         for (int q = 0; q < nqp; ++q) {           /* step 5 */
             const double *phi = T.phi + (size_t)q * n, *dphi = T.dphi + (size_t)3 * q * n;
             double J[9], K[9], det, x[3];
-            bad |= (type ? oracle_hex_geometry : oracle_geometry)(X, T.pts + 3 * q, J, &det, K, x);   /* step 7 */
+            bad |= (type == 2 ? oracle_tet_geometry : type ? oracle_hex_geometry : oracle_geometry)(
+                X, T.pts + 3 * q, J, &det, K, x);                                      /* step 7 */
             if (xq) for (int d = 0; d < 3; ++d) xq[((size_t)e * nqp + q) * 3 + d] = x[d];
             /* coefficients at the point */
             double De[9], be[3], ce, fe;
@@ -561,6 +646,15 @@ int oracle_integrate(int p, int n1, int64_t ne, const double *coords, const doub
                      double *A, double *b, double *xq, int32_t *flags)
 {
     return integrate_core(0, p, n1, 0, NULL, NULL, ne, 1, coords, D, beta, c, f, A, b, xq, flags);
+}
+
+/* Tetrahedra: coords [ne][4][3], coefficients per element; n1 collapsed
+   Gauss points per direction (0 -> p+2). */
+int oracle_integrate_tet(int p, int n1, int64_t ne, const double *coords, const double *D,
+                         const double *beta, const double *c, const double *f,
+                         double *A, double *b, double *xq, int32_t *flags)
+{
+    return integrate_core(2, p, n1, 0, NULL, NULL, ne, 1, coords, D, beta, c, f, A, b, xq, flags);
 }
 
 /* Hexahedra: coords [ne][8][3], coefficients per element as above; n1

@@ -167,6 +167,32 @@ def make_hex_batch(nx: int, ny: int, nz: int, amp: float = 0.2, seed: int = 0) -
                                                                          element="hexahedron"))
 
 
+# The six tetrahedra of a cube cell around its main diagonal (corner 0 to
+# corner 7, corners v = i + 2j + 4k), each listed with positive orientation.
+_TETS_OF_CUBE = [(0, 1, 3, 7), (0, 3, 2, 7), (0, 2, 6, 7), (0, 6, 4, 7), (0, 4, 5, 7), (0, 5, 1, 7)]
+
+
+def make_tet_batch(nx: int, ny: int, nz: int, amp: float = 0.2, seed: int = 0) -> Batch:
+    """Tetrahedral mesh of the perturbed vertex grid (six tetrahedra per cell
+    around the cell's main diagonal, coords [ne, 4, 3]) with the
+    element-constant coefficient recipe."""
+    rng = np.random.default_rng(seed)
+    nvert = (nx + 1) * (ny + 1) * (nz + 1)
+    u = rng.uniform(-1.0, 1.0, (nvert, 3))
+    verts = grid_vertices(nx, ny, nz, amp, u)
+    cells = hex_connectivity(nx, ny, nz)
+    conn = np.concatenate([cells[:, list(t)] for t in _TETS_OF_CUBE], axis=0)
+    ne = conn.shape[0]
+    coords = np.ascontiguousarray(verts[conn])               # [ne, 4, 3]
+    L = rng.normal(0.0, 0.3, (ne, 3, 3))
+    D = np.einsum("eik,ejk->eij", L, L) + np.eye(3)[None]
+    beta = rng.normal(0.0, 1.0, (ne, 3))
+    c = rng.uniform(0.0, 1.0, ne)
+    f = rng.uniform(-1.0, 1.0, ne)
+    return Batch(coords, np.ascontiguousarray(D), beta, c, f, None, dict(nx=nx, ny=ny, nz=nz, amp=amp, seed=seed,
+                                                                         element="tetrahedron"))
+
+
 def vertex_fields(ne: int, seed: int):
     """Coefficients given at the six vertices of every element, drawn with the
     element-constant recipe per vertex: D = L L^T + I (L ~ N(0, 0.3^2)),
@@ -258,6 +284,8 @@ WORKLOADS = {
     "p1_524288":    dict(nx=64, ny=64, nz=64, amp=0.2, seed=0, p=1),
     # hexahedra (one per cell) on the vertex grid of the p = 4 prism workload
     "hex_p4_65536": dict(nx=64, ny=64, nz=16, amp=0.2, seed=1, p=4, element="hexahedron"),
+    # tetrahedra (six per cell) on the vertex grid of the p = 4 prism workload
+    "tet_p4_393216": dict(nx=64, ny=64, nz=16, amp=0.2, seed=1, p=4, element="tetrahedron"),
 }
 
 
@@ -265,4 +293,6 @@ def workload(name: str) -> Batch:
     w = WORKLOADS[name]
     if w.get("element") == "hexahedron":
         return make_hex_batch(w["nx"], w["ny"], w["nz"], w["amp"], w["seed"])
+    if w.get("element") == "tetrahedron":
+        return make_tet_batch(w["nx"], w["ny"], w["nz"], w["amp"], w["seed"])
     return make_batch(w["nx"], w["ny"], w["nz"], w["amp"], w["seed"], mixed=w["p"] is None)
