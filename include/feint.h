@@ -300,6 +300,27 @@ feint_status feint_hex_tile_describe(int p, feint_form form, int tile, char *buf
 feint_status feint_hex_autotune(const feint_elements *el, int p, feint_form form, void *A, void *b, int reps,
                                 double *best_ms, void *stream);
 
+/* ---- Tetrahedral elements (Table 1, complete basis) -------------------------
+   The same integration on affine tetrahedra: reference tetrahedron {xi >= 0,
+   xi1 + xi2 + xi3 <= 1}, vertices v0..v3 at 0, e1, e2, e3, x = v0 + J xi with
+   the edge vectors v_i - v0 as the columns of J; Lagrange basis on the
+   lattice (i/p, j/p, k/p), i + j + k <= p, k outer, j, i inner (n = (p+1)
+   (p+2)(p+3)/6); (p+2)^3 collapsed Gauss points, q = (k n1 + j) n1 + i with
+   zeta = (1+c)/2, eta = (1+b)(1-zeta)/2, xi = (1+a)(1-eta-zeta)/2 (products
+   of shape functions integrated exactly).  Inputs as feint_elements with
+   coords [ne][4][3]; outputs, forms, errors and variants as for hexahedra. */
+int feint_tet_nshp(int p);
+int feint_tet_nq(int p);
+feint_status feint_prepare_tet(int p);
+feint_status feint_integrate_tet(const feint_elements *el, int p, feint_form form, void *A, void *b,
+                                 double *xq, uint32_t *dev_status, void *stream);
+int feint_tet_tile_count(int p, feint_form form);
+int feint_tet_tile_get(int p, feint_form form);
+feint_status feint_tet_tile_set(int p, feint_form form, int tile);
+feint_status feint_tet_tile_describe(int p, feint_form form, int tile, char *buf, size_t len);
+feint_status feint_tet_autotune(const feint_elements *el, int p, feint_form form, void *A, void *b, int reps,
+                                double *best_ms, void *stream);
+
 /* ---- Global assembly (Sec. 2) ----------------------------------------------
    The element matrices and load vectors of one degree are summed into a CSR
    matrix and a right-hand side through the element-to-global dof map.

@@ -156,13 +156,24 @@ def integrate_fields_raw(coords, Dv, betav, cv, fv, p: int, form: str = "fp64", 
     return A, b
 
 
+# Other element types of Table 1: kind -> (vertices, shape functions, points, C-ABI prefix)
+ELEMENTS = {
+    "hex": (8, lambda p: (p + 1) ** 3, lambda p: (p + 1) ** 3, "hex"),
+    "tet": (4, lambda p: (p + 1) * (p + 2) * (p + 3) // 6, lambda p: (p + 2) ** 3, "tet"),
+}
+
+
 def hex_nshp(p: int) -> int:
-    return (p + 1) ** 3
+    return ELEMENTS["hex"][1](p)
 
 
-def hex_elements(coords, D, beta, c, f) -> Elements:
+def tet_nshp(p: int) -> int:
+    return ELEMENTS["tet"][1](p)
+
+
+def _elem_inputs(kind, coords, D, beta, c, f) -> Elements:
     ne = coords.shape[0]
-    _check_input("coords", coords, (8, 3), ne)
+    _check_input("coords", coords, (ELEMENTS[kind][0], 3), ne)
     _check_input("D", D, (3, 3), ne)
     _check_input("beta", beta, (3,), ne)
     _check_input("c", c, (), ne)
@@ -170,12 +181,18 @@ def hex_elements(coords, D, beta, c, f) -> Elements:
     return Elements(coords.data_ptr(), D.data_ptr(), beta.data_ptr(), c.data_ptr(), f.data_ptr(), ne)
 
 
-def integrate_hex_raw(coords, D, beta, c, f, p: int, form: str = "fp64", *, A=None, b=None, xq=None, status=None):
-    """Hexahedral elements (coords [ne,8,3]): forward integration; returns (A, b)."""
+def _fn(kind, name):
+    return getattr(lib(), name.format(ELEMENTS[kind][3]))
+
+
+def integrate_elem_raw(kind: str, coords, D, beta, c, f, p: int, form: str = "fp64", *, A=None, b=None, xq=None,
+                       status=None):
+    """Hexahedra ("hex", coords [ne,8,3]) or tetrahedra ("tet", coords [ne,4,3]):
+    forward integration; returns (A, b)."""
     if form not in ("fp64", "fp32"):
-        raise ValueError("hexahedra: forms fp64 and fp32")
-    el = hex_elements(coords, D, beta, c, f)
-    ne, n = coords.shape[0], hex_nshp(p)
+        raise ValueError(f"{kind}: forms fp64 and fp32")
+    el = _elem_inputs(kind, coords, D, beta, c, f)
+    ne, n, nqe = coords.shape[0], ELEMENTS[kind][1](p), ELEMENTS[kind][2](p)
     dt = out_dtype(form)
     if A is None:
         A = torch.empty((ne, n, n), dtype=dt, device=coords.device)
@@ -183,37 +200,53 @@ def integrate_hex_raw(coords, D, beta, c, f, p: int, form: str = "fp64", *, A=No
         b = torch.empty((ne, n), dtype=dt, device=coords.device)
     if A.dtype != dt or b.dtype != dt or A.numel() != ne * n * n or b.numel() != ne * n:
         raise ValueError("output tensors have the wrong dtype or size")
-    if xq is not None and (xq.dtype != torch.float64 or xq.numel() != ne * (p + 1) ** 3 * 3):
+    if xq is not None and (xq.dtype != torch.float64 or xq.numel() != ne * nqe * 3):
         raise ValueError("xq must be float64 with ne*nq*3 entries")
-    check("feint_integrate_hex", lib().feint_integrate_hex(ctypes.byref(el), int(p), FORMS[form], _ptr(A), _ptr(b),
-                                                           _ptr(xq), _ptr(status), _stream()))
+    name = f"feint_integrate_{ELEMENTS[kind][3]}"
+    check(name, getattr(lib(), name)(ctypes.byref(el), int(p), FORMS[form], _ptr(A), _ptr(b), _ptr(xq),
+                                     _ptr(status), _stream()))
     return A, b
 
 
-def hex_tile_count(p: int, form: str) -> int:
-    return lib().feint_hex_tile_count(int(p), FORMS[form])
+def elem_tile_count(kind: str, p: int, form: str) -> int:
+    return _fn(kind, "feint_{}_tile_count")(int(p), FORMS[form])
 
 
-def hex_tile_get(p: int, form: str) -> int:
-    return lib().feint_hex_tile_get(int(p), FORMS[form])
+def elem_tile_get(kind: str, p: int, form: str) -> int:
+    return _fn(kind, "feint_{}_tile_get")(int(p), FORMS[form])
 
 
-def hex_tile_set(p: int, form: str, tile: int) -> None:
-    check("feint_hex_tile_set", lib().feint_hex_tile_set(int(p), FORMS[form], int(tile)))
+def elem_tile_set(kind: str, p: int, form: str, tile: int) -> None:
+    check(f"feint_{kind}_tile_set", _fn(kind, "feint_{}_tile_set")(int(p), FORMS[form], int(tile)))
 
 
-def hex_tile_describe(p: int, form: str, tile: int) -> str:
+def elem_tile_describe(kind: str, p: int, form: str, tile: int) -> str:
     buf = ctypes.create_string_buffer(32)
-    check("feint_hex_tile_describe", lib().feint_hex_tile_describe(int(p), FORMS[form], int(tile), buf, 32))
+    check(f"feint_{kind}_tile_describe", _fn(kind, "feint_{}_tile_describe")(int(p), FORMS[form], int(tile), buf, 32))
     return buf.value.decode()
 
 
-def hex_autotune(coords, D, beta, c, f, p: int, form: str, A, b, reps: int = 2) -> float:
-    el = hex_elements(coords, D, beta, c, f)
+def elem_autotune(kind: str, coords, D, beta, c, f, p: int, form: str, A, b, reps: int = 2) -> float:
+    el = _elem_inputs(kind, coords, D, beta, c, f)
     best = ctypes.c_double(0)
-    check("feint_hex_autotune", lib().feint_hex_autotune(ctypes.byref(el), int(p), FORMS[form], _ptr(A), _ptr(b),
-                                                         int(reps), ctypes.byref(best), _stream()))
+    check(f"feint_{kind}_autotune", _fn(kind, "feint_{}_autotune")(ctypes.byref(el), int(p), FORMS[form], _ptr(A),
+                                                                    _ptr(b), int(reps), ctypes.byref(best), _stream()))
     return best.value
+
+
+def integrate_hex_raw(coords, D, beta, c, f, p: int, form: str = "fp64", **kw):
+    return integrate_elem_raw("hex", coords, D, beta, c, f, p, form, **kw)
+
+
+def integrate_tet_raw(coords, D, beta, c, f, p: int, form: str = "fp64", **kw):
+    return integrate_elem_raw("tet", coords, D, beta, c, f, p, form, **kw)
+
+
+def hex_tile_count(p, form): return elem_tile_count("hex", p, form)
+def hex_tile_get(p, form): return elem_tile_get("hex", p, form)
+def hex_tile_set(p, form, tile): return elem_tile_set("hex", p, form, tile)
+def hex_tile_describe(p, form, tile): return elem_tile_describe("hex", p, form, tile)
+def hex_autotune(*a, **kw): return elem_autotune("hex", *a, **kw)
 
 
 def adjoint_raw(coords, D, beta, c, f, G, g, p: int, form: str = "fp64"):

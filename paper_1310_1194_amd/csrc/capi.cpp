@@ -22,7 +22,7 @@ namespace {
 std::mutex g_mu;
 std::map<int, DevTables *> g_tables;        // key: device * 64 + type * 16 + rule * 8 + p
 int g_tile[2][8][4];                        // chosen variant per (rule, p, form), prisms
-int g_tile_hex[8][4];                       // chosen variant per (p, form), hexahedra
+int g_tile_elem[3][8][4];                   // chosen variant per (type, p, form): 1 hexahedra, 2 tetrahedra
 thread_local std::string g_err;
 
 bool valid_form(int form) { return form >= FEINT_FP64 && form <= FEINT_FP16X3; }
@@ -42,17 +42,17 @@ const DevTables *find_tables(int p, int rule, int type) {
 }
 
 // Upload the tables of degree p on rule `rule` of element type `type`
-// (0 prism, 1 hexahedron) to the current device (once).
+// (0 prism, 1 hexahedron, 2 tetrahedron) to the current device (once).
 feint_status prepare_tables(int p, int rule, int type) {
     if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
-    if (!valid_rule(rule) || (type != 0 && type != 1) || (type == 1 && rule != 0)) return FEINT_ERR_INVALID_ARG;
+    if (!valid_rule(rule) || type < 0 || type > 2 || (type != 0 && rule != 0)) return FEINT_ERR_INVALID_ARG;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) { set_error("hipGetDevice", e); return FEINT_ERR_HIP; }
     std::lock_guard<std::mutex> lk(g_mu);
     const int key = dev * 64 + type * 16 + rule * 8 + p;
     if (g_tables.count(key)) return FEINT_OK;
-    HostTables H = type ? build_hex_tables(p) : build_tables(p, rule);
+    HostTables H = type == 2 ? build_tet_tables(p) : type == 1 ? build_hex_tables(p) : build_tables(p, rule);
     auto align = [](size_t x) { return (x + 255) / 256 * 256; };
     const size_t s_qw = align(H.qw.size() * 8), s_gll = align(H.gll.size() * 8), s_b64 = align(H.B64.size() * 8), s_b32 = align(H.B32.size() * 4);
     const size_t s_sp = align(H.bf_hi.size() * 2);
@@ -351,66 +351,69 @@ feint_status feint_autotune(const feint_elements *el, int p, feint_form form, vo
     return feint_autotune_rule(el, nullptr, p, form, FEINT_RULE_COLLAPSED, A, b, reps, best_ms, stream);
 }
 
-int feint_hex_nshp(int p) { return (p < 1 || p > kMaxP) ? -1 : (p + 1) * (p + 1) * (p + 1); }
-int feint_hex_nq(int p) { return feint_hex_nshp(p); }
+// ---- Hexahedra (type 1) and tetrahedra (type 2): generic helpers -------------
+static const FwdVariant *elem_variants(int type, int form, int p, int *cnt) {
+    *cnt = 0;
+    if (p < 1 || p > kMaxP || !valid_form(form)) return nullptr;
+    return type == 1 ? fwd_variants_hex(form, p, cnt) : fwd_variants_tet(form, p, cnt);
+}
 
-feint_status feint_prepare_hex(int p) { return prepare_tables(p, FEINT_RULE_COLLAPSED, 1); }
-
-int feint_hex_tile_count(int p, feint_form form) {
+static int elem_tile_count(int type, int p, int form) {
     int cnt = 0;
-    if (p < 1 || p > kMaxP || !valid_form(form)) return 0;
-    fwd_variants_hex(form, p, &cnt);
+    elem_variants(type, form, p, &cnt);
     return cnt;
 }
 
-int feint_hex_tile_get(int p, feint_form form) {
-    if (feint_hex_tile_count(p, form) == 0) return -1;
+static int elem_tile_get(int type, int p, int form) {
+    if (elem_tile_count(type, p, form) == 0) return -1;
     std::lock_guard<std::mutex> lk(g_mu);
-    return g_tile_hex[p][form];
+    return g_tile_elem[type][p][form];
 }
 
-feint_status feint_hex_tile_set(int p, feint_form form, int tile) {
+static feint_status elem_tile_set(int type, int p, int form, int tile) {
     if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
-    if (!valid_form(form) || feint_hex_tile_count(p, form) == 0) return FEINT_ERR_UNSUPPORTED_FORM;
-    if (tile < 0 || tile >= feint_hex_tile_count(p, form)) return FEINT_ERR_INVALID_ARG;
+    const int cnt = elem_tile_count(type, p, form);
+    if (cnt == 0) return FEINT_ERR_UNSUPPORTED_FORM;
+    if (tile < 0 || tile >= cnt) return FEINT_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(g_mu);
-    g_tile_hex[p][form] = tile;
+    g_tile_elem[type][p][form] = tile;
     return FEINT_OK;
 }
 
-feint_status feint_hex_tile_describe(int p, feint_form form, int tile, char *buf, size_t len) {
-    int cnt = 0;
+static feint_status elem_tile_describe(int type, int p, int form, int tile, char *buf, size_t len) {
     if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
     if (!valid_form(form)) return FEINT_ERR_UNSUPPORTED_FORM;
-    const FwdVariant *v = fwd_variants_hex(form, p, &cnt);
+    int cnt = 0;
+    const FwdVariant *v = elem_variants(type, form, p, &cnt);
     if (!buf || tile < 0 || tile >= cnt) return FEINT_ERR_INVALID_ARG;
     std::snprintf(buf, len, "%dx%d%s", v[tile].tm, v[tile].tn, v[tile].minw > 1 ? "o2" : "");
     return FEINT_OK;
 }
 
-// Forward parameters of a hexahedral launch (host checks done by the caller).
-static feint_status hex_params(const feint_elements *el, int p, feint_form form, void *A, void *b, hipStream_t st,
-                               FwdParams &prm, const FwdVariant **vsel, int tile) {
+// Forward parameters of a launch (host checks done by the caller); tile < 0
+// takes the chosen variant.
+static feint_status elem_params(int type, const feint_elements *el, int p, int form, void *A, void *b,
+                                hipStream_t st, FwdParams &prm, const FwdVariant **vsel, int tile) {
     const DevTables *T = nullptr;
-    feint_status s = tables_for_launch(p, st, &T, FEINT_RULE_COLLAPSED, 1);
+    feint_status s = tables_for_launch(p, st, &T, FEINT_RULE_COLLAPSED, type);
     if (s != FEINT_OK) return s;
     fill_fwd_params(prm, el, form, T);
     prm.A = A; prm.b = b;
     int cnt = 0;
-    const FwdVariant *v = fwd_variants_hex(form, p, &cnt);
+    const FwdVariant *v = elem_variants(type, form, p, &cnt);
     if (!v || cnt == 0) return FEINT_ERR_UNSUPPORTED_FORM;
     if (tile < 0) {
         std::lock_guard<std::mutex> lk(g_mu);
-        tile = g_tile_hex[p][form];
+        tile = g_tile_elem[type][p][form];
     }
     *vsel = &v[(tile >= 0 && tile < cnt) ? tile : 0];
     return FEINT_OK;
 }
 
-feint_status feint_integrate_hex(const feint_elements *el, int p, feint_form form, void *A, void *b,
-                                 double *xq, uint32_t *dev_status, void *stream) {
+static feint_status elem_integrate(int type, const feint_elements *el, int p, int form, void *A, void *b,
+                                   double *xq, uint32_t *dev_status, void *stream) {
     if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
-    if (!valid_form(form) || feint_hex_tile_count(p, form) == 0) return FEINT_ERR_UNSUPPORTED_FORM;
+    if (elem_tile_count(type, p, form) == 0) return FEINT_ERR_UNSUPPORTED_FORM;
     feint_status s = check_elements(el);
     if (s != FEINT_OK) return s;
     if (el->ne == 0) return FEINT_OK;
@@ -418,22 +421,22 @@ feint_status feint_integrate_hex(const feint_elements *el, int p, feint_form for
     hipStream_t st = (hipStream_t)stream;
     FwdParams prm;
     const FwdVariant *v = nullptr;
-    s = hex_params(el, p, form, A, b, st, prm, &v, -1);
+    s = elem_params(type, el, p, form, A, b, st, prm, &v, -1);
     if (s != FEINT_OK) return s;
     prm.xq = xq;
     prm.status = dev_status;
     return launch_forward(prm, v, st);
 }
 
-feint_status feint_hex_autotune(const feint_elements *el, int p, feint_form form, void *A, void *b, int reps,
-                                double *best_ms, void *stream) {
+static feint_status elem_autotune(int type, const feint_elements *el, int p, int form, void *A, void *b, int reps,
+                                  double *best_ms, void *stream) {
     if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
-    if (!valid_form(form) || feint_hex_tile_count(p, form) == 0) return FEINT_ERR_UNSUPPORTED_FORM;
+    const int cnt = elem_tile_count(type, p, form);
+    if (cnt == 0) return FEINT_ERR_UNSUPPORTED_FORM;
     feint_status s = check_elements(el);
     if (s != FEINT_OK) return s;
     if (!A || !b || el->ne == 0 || reps < 1) return FEINT_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
-    const int cnt = feint_hex_tile_count(p, form);
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return FEINT_ERR_HIP;
     int best = 0;
@@ -441,7 +444,7 @@ feint_status feint_hex_autotune(const feint_elements *el, int p, feint_form form
     for (int t = 0; t < cnt && s == FEINT_OK; ++t) {
         FwdParams prm;
         const FwdVariant *v = nullptr;
-        s = hex_params(el, p, form, A, b, st, prm, &v, t);
+        s = elem_params(type, el, p, form, A, b, st, prm, &v, t);
         if (s != FEINT_OK) break;
         s = launch_forward(prm, v, st);                       // warm-up
         if (s != FEINT_OK) break;
@@ -459,10 +462,46 @@ feint_status feint_hex_autotune(const feint_elements *el, int p, feint_form form
     if (s != FEINT_OK) return s;
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        g_tile_hex[p][form] = best;
+        g_tile_elem[type][p][form] = best;
     }
     if (best_ms) *best_ms = best_t;
     return FEINT_OK;
+}
+
+int feint_hex_nshp(int p) { return (p < 1 || p > kMaxP) ? -1 : (p + 1) * (p + 1) * (p + 1); }
+int feint_hex_nq(int p) { return feint_hex_nshp(p); }
+feint_status feint_prepare_hex(int p) { return prepare_tables(p, FEINT_RULE_COLLAPSED, 1); }
+int feint_hex_tile_count(int p, feint_form form) { return elem_tile_count(1, p, form); }
+int feint_hex_tile_get(int p, feint_form form) { return elem_tile_get(1, p, form); }
+feint_status feint_hex_tile_set(int p, feint_form form, int tile) { return elem_tile_set(1, p, form, tile); }
+feint_status feint_hex_tile_describe(int p, feint_form form, int tile, char *buf, size_t len) {
+    return elem_tile_describe(1, p, form, tile, buf, len);
+}
+feint_status feint_integrate_hex(const feint_elements *el, int p, feint_form form, void *A, void *b,
+                                 double *xq, uint32_t *dev_status, void *stream) {
+    return elem_integrate(1, el, p, form, A, b, xq, dev_status, stream);
+}
+feint_status feint_hex_autotune(const feint_elements *el, int p, feint_form form, void *A, void *b, int reps,
+                                double *best_ms, void *stream) {
+    return elem_autotune(1, el, p, form, A, b, reps, best_ms, stream);
+}
+
+int feint_tet_nshp(int p) { return (p < 1 || p > kMaxP) ? -1 : (p + 1) * (p + 2) * (p + 3) / 6; }
+int feint_tet_nq(int p) { return (p < 1 || p > kMaxP) ? -1 : (p + 2) * (p + 2) * (p + 2); }
+feint_status feint_prepare_tet(int p) { return prepare_tables(p, FEINT_RULE_COLLAPSED, 2); }
+int feint_tet_tile_count(int p, feint_form form) { return elem_tile_count(2, p, form); }
+int feint_tet_tile_get(int p, feint_form form) { return elem_tile_get(2, p, form); }
+feint_status feint_tet_tile_set(int p, feint_form form, int tile) { return elem_tile_set(2, p, form, tile); }
+feint_status feint_tet_tile_describe(int p, feint_form form, int tile, char *buf, size_t len) {
+    return elem_tile_describe(2, p, form, tile, buf, len);
+}
+feint_status feint_integrate_tet(const feint_elements *el, int p, feint_form form, void *A, void *b,
+                                 double *xq, uint32_t *dev_status, void *stream) {
+    return elem_integrate(2, el, p, form, A, b, xq, dev_status, stream);
+}
+feint_status feint_tet_autotune(const feint_elements *el, int p, feint_form form, void *A, void *b, int reps,
+                                double *best_ms, void *stream) {
+    return elem_autotune(2, el, p, form, A, b, reps, best_ms, stream);
 }
 
 const char *feint_status_string(feint_status s) {

@@ -184,6 +184,53 @@ __device__ inline double point_block_hex(const ElemHex &E, double xi, double eta
     return det;
 }
 
+// ---------------------------------------------------------------------------
+// Tetrahedra (affine map of the reference tetrahedron {xi >= 0, sum xi <= 1}:
+// x = v0 + J xi with the edge vectors v_i - v0 as the columns of J).
+struct ElemTet {
+    double X[12];   // vertices v0..v3
+    double D[9];
+    double be[3];
+    double c, f;
+};
+
+// det J and K = J^{-1} (rows = cross products of pairs of edge vectors / det);
+// the same at every point of the element.
+__device__ inline double tet_jacobian(const double *X, double K[9]) {
+    double c0[3], c1[3], c2[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        c0[d] = X[3 + d] - X[d];
+        c1[d] = X[6 + d] - X[d];
+        c2[d] = X[9 + d] - X[d];
+    }
+    const double r0[3] = {c1[1] * c2[2] - c1[2] * c2[1], c1[2] * c2[0] - c1[0] * c2[2], c1[0] * c2[1] - c1[1] * c2[0]};
+    const double r1[3] = {c2[1] * c0[2] - c2[2] * c0[1], c2[2] * c0[0] - c2[0] * c0[2], c2[0] * c0[1] - c2[1] * c0[0]};
+    const double r2[3] = {c0[1] * c1[2] - c0[2] * c1[1], c0[2] * c1[0] - c0[0] * c1[2], c0[0] * c1[1] - c0[1] * c1[0]};
+    const double det = c0[0] * r0[0] + c0[1] * r0[1] + c0[2] * r0[2];
+    const double inv = 1.0 / det;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        K[d] = r0[d] * inv;
+        K[3 + d] = r1[d] * inv;
+        K[6 + d] = r2[d] * inv;
+    }
+    return det;
+}
+
+__device__ inline void tet_map(const double *X, double a, double b, double c, double x[3]) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        x[d] = X[d] + a * (X[3 + d] - X[d]) + b * (X[6 + d] - X[d]) + c * (X[9 + d] - X[d]);
+}
+
+__device__ inline double point_block_tet(const ElemTet &E, double w, double W[16], double &sf) {
+    double K[9];
+    const double det = tet_jacobian(E.X, K);
+    fused_block(E, K, w * det, W, sf);
+    return det;
+}
+
 // Compiler-level fence for data exchanged through LDS between lanes of one
 // wave (a wave's LDS operations complete in issue order).
 __device__ inline void wave_sync() {

@@ -143,6 +143,29 @@ struct HexGeo {
     __device__ static void map(const Elem &E, const double *qp, double x[3]) { hex_map(E.X, qp[0], qp[1], qp[2], x); }
 };
 
+// Tetrahedra (Table 1's complete-basis 3D element): (p+1)(p+2)(p+3)/6 shape
+// functions, (p+2)^3 collapsed Gauss points; coordinates [ne][4][3].
+struct TetGeo {
+    typedef ElemTet Elem;
+    __host__ __device__ static constexpr int nshp(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+    __host__ __device__ static constexpr int nq(int p, int) { return (p + 2) * (p + 2) * (p + 2); }
+    __device__ static void load(const FwdParams &prm, int64_t e, Elem &E) {
+#pragma unroll
+        for (int i = 0; i < 12; ++i) E.X[i] = prm.coords[12 * e + i];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) E.D[i] = prm.D[9 * e + i];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) E.be[i] = prm.beta[3 * e + i];
+        E.c = prm.c[e];
+        E.f = prm.f[e];
+    }
+    __device__ static void coeffs(const FwdParams &, int64_t, const double *, Elem &) {}
+    __device__ static double block(const Elem &E, const double *qp, double W[16], double &sf) {
+        return point_block_tet(E, qp[3], W, sf);
+    }
+    __device__ static void map(const Elem &E, const double *qp, double x[3]) { tet_map(E.X, qp[0], qp[1], qp[2], x); }
+};
+
 // ---------------------------------------------------------------------------
 // 16x16x4 forms (FP64, FP32): one point (4 K-rows) per MFMA.
 // ---------------------------------------------------------------------------

@@ -54,6 +54,10 @@ int64_t items_of(int64_t ne) { return items_for<KER>(ne); }
 #define FEINT_K4U_HEX(P, T, TM, TN, W) \
     FwdVariant{TM, TN, 0, W, &launch_direct<K4<P, T, TM, TN, 0, HexGeo>, W>, &items_of<K4<P, T, TM, TN, 0, HexGeo>>}
 
+// Tetrahedra: the 16x16x4 kernel with the affine tetrahedral geometry.
+#define FEINT_K4U_TET(P, T, TM, TN, W) \
+    FwdVariant{TM, TN, 0, W, &launch_direct<K4<P, T, TM, TN, 0, TetGeo>, W>, &items_of<K4<P, T, TM, TN, 0, TetGeo>>}
+
 #define FEINT_K4U(P, T, TM, TN, W) FEINT_K4U_R(P, T, TM, TN, W, 0)
 #define FEINT_KSC(P, T, TM, TN, W) FEINT_KSC_R(P, T, TM, TN, W, 0)
 #define FEINT_K4S(P, T, TM, TN, SP, W) FEINT_K4S_R(P, T, TM, TN, SP, W, 0)

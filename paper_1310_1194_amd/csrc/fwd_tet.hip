@@ -1,0 +1,44 @@
+// Forward kernels for tetrahedral elements (Table 1's complete-basis 3D
+// element): the 16x16x4 MFMA kernel with the affine geometry, FP64 and FP32
+// forms; tile shapes per degree (n = 4, 10, 20, 35, 56, 84, 120 shape
+// functions: 1, 1, 2, 3, 4, 6, 8 tiles of 16), the first the default.
+#include "fwd_registry.h"
+
+namespace feint {
+namespace {
+const FwdVariant d1[] = {FEINT_K4U_TET(1, double, 1, 1, 2)};
+const FwdVariant d2[] = {FEINT_K4U_TET(2, double, 1, 1, 2)};
+const FwdVariant d3[] = {FEINT_K4U_TET(3, double, 2, 2, 2), FEINT_K4U_TET(3, double, 2, 1, 2)};
+const FwdVariant d4[] = {FEINT_K4U_TET(4, double, 3, 3, 2), FEINT_K4U_TET(4, double, 3, 1, 2)};
+const FwdVariant d5[] = {FEINT_K4U_TET(5, double, 4, 2, 2), FEINT_K4U_TET(5, double, 4, 1, 2)};
+const FwdVariant d6[] = {FEINT_K4U_TET(6, double, 6, 2, 1), FEINT_K4U_TET(6, double, 6, 1, 2)};
+const FwdVariant d7[] = {FEINT_K4U_TET(7, double, 8, 2, 1), FEINT_K4U_TET(7, double, 8, 1, 2)};
+const FwdVariant f1[] = {FEINT_K4U_TET(1, float, 1, 1, 2)};
+const FwdVariant f2[] = {FEINT_K4U_TET(2, float, 1, 1, 2)};
+const FwdVariant f3[] = {FEINT_K4U_TET(3, float, 2, 2, 2)};
+const FwdVariant f4[] = {FEINT_K4U_TET(4, float, 3, 3, 2), FEINT_K4U_TET(4, float, 3, 3, 1)};
+const FwdVariant f5[] = {FEINT_K4U_TET(5, float, 4, 4, 1), FEINT_K4U_TET(5, float, 4, 2, 2)};
+const FwdVariant f6[] = {FEINT_K4U_TET(6, float, 6, 3, 1), FEINT_K4U_TET(6, float, 6, 2, 1)};
+const FwdVariant f7[] = {FEINT_K4U_TET(7, float, 8, 4, 1), FEINT_K4U_TET(7, float, 8, 2, 1)};
+
+#define FEINT_PICK(a1, a2, a3, a4, a5, a6, a7)                    \
+    switch (p) {                                                   \
+    case 1: *count = (int)(sizeof(a1) / sizeof(a1[0])); return a1; \
+    case 2: *count = (int)(sizeof(a2) / sizeof(a2[0])); return a2; \
+    case 3: *count = (int)(sizeof(a3) / sizeof(a3[0])); return a3; \
+    case 4: *count = (int)(sizeof(a4) / sizeof(a4[0])); return a4; \
+    case 5: *count = (int)(sizeof(a5) / sizeof(a5[0])); return a5; \
+    case 6: *count = (int)(sizeof(a6) / sizeof(a6[0])); return a6; \
+    case 7: *count = (int)(sizeof(a7) / sizeof(a7[0])); return a7; \
+    }
+}  // namespace
+
+const FwdVariant *fwd_variants_tet(int form, int p, int *count) {
+    switch (form) {
+    case F64: FEINT_PICK(d1, d2, d3, d4, d5, d6, d7); break;
+    case F32: FEINT_PICK(f1, f2, f3, f4, f5, f6, f7); break;
+    }
+    *count = 0;
+    return nullptr;
+}
+}  // namespace feint

@@ -48,6 +48,8 @@ const FwdVariant *fwd_variants(int form, int p, int *count, int rule = 0);
 const FwdVariant *fwd_variants_sym(int form, int p, int *count);
 // Hexahedral elements (FP64 and FP32 forms; count 0 for the split forms).
 const FwdVariant *fwd_variants_hex(int form, int p, int *count);
+// Tetrahedral elements (FP64 and FP32 forms).
+const FwdVariant *fwd_variants_tet(int form, int p, int *count);
 const FwdVariant *fwd_variants_f64(int p, int *count);
 const FwdVariant *fwd_variants_f32(int p, int *count);
 const FwdVariant *fwd_variants_bf16(int p, int *count);

@@ -554,4 +554,88 @@ HostTables build_hex_tables(int p) {
     return T;
 }
 
+HostTables build_tet_tables(int p) {
+    if (p < 1 || p > kMaxP) throw std::runtime_error("degree out of range");
+    HostTables T;
+    T.p = p;
+    T.rule = 0;
+    const int n1 = p + 2;
+    T.n = (p + 1) * (p + 2) * (p + 3) / 6;
+    T.npad = pad16(T.n);
+    T.nq = n1 * n1 * n1;
+    T.nqp = pad8(T.nq);
+    T.nkb = T.nqp / 8;
+    double g[kMaxP + 2], gw[kMaxP + 2];
+    gauss_legendre_gw(n1, g, gw);
+    T.qw.assign((size_t)T.nqp * 4, 0.0);
+    for (int q = T.nq; q < T.nqp; ++q)        // padding points: inside, zero weight
+        T.qw[4 * q + 0] = T.qw[4 * q + 1] = T.qw[4 * q + 2] = 0.25;
+    // Duffy collapse of the cube onto the tetrahedron: zeta = (1+c)/2,
+    // eta = (1+b)(1-zeta)/2, xi = (1+a)(1-eta-zeta)/2; |dx/d(a,b,c)| =
+    // (1-b)(1-c)^2/64
+    for (int k = 0; k < n1; ++k)
+        for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n1; ++i) {
+                const int q = (k * n1 + j) * n1 + i;
+                const double ze = 0.5 * (1.0 + g[k]);
+                const double et = 0.5 * (1.0 + g[j]) * (1.0 - ze);
+                const double xi = 0.5 * (1.0 + g[i]) * (1.0 - et - ze);
+                T.qw[4 * q + 0] = xi;
+                T.qw[4 * q + 1] = et;
+                T.qw[4 * q + 2] = ze;
+                T.qw[4 * q + 3] = gw[i] * gw[j] * gw[k] * (1.0 - g[j]) * (1.0 - g[k]) * (1.0 - g[k]) / 64.0;
+            }
+    T.gll.assign(2 * (p + 1), 0.0);
+    // Lagrange basis on the lattice (i/p, j/p, k/p), k outer, j, i inner, as
+    // combinations of the modes P_a(2 xi - 1) P_b(2 eta - 1) P_c(2 zeta - 1),
+    // a + b + c <= p: C = V^{-1}, V[node][mode]
+    const int n = T.n;
+    std::vector<int> ma, mb, mc;
+    for (int c = 0; c <= p; ++c)
+        for (int b = 0; b + c <= p; ++b)
+            for (int a = 0; a + b + c <= p; ++a) { ma.push_back(a); mb.push_back(b); mc.push_back(c); }
+    long double P0[kMaxP + 1], dP0[kMaxP + 1], P1[kMaxP + 1], dP1[kMaxP + 1], P2[kMaxP + 1], dP2[kMaxP + 1];
+    std::vector<long double> V((size_t)n * n);
+    int node = 0;
+    for (int k = 0; k <= p; ++k)
+        for (int j = 0; j + k <= p; ++j)
+            for (int i = 0; i + j + k <= p; ++i, ++node) {
+                legendre_all(p, 2.0L * i / p - 1, P0, dP0);
+                legendre_all(p, 2.0L * j / p - 1, P1, dP1);
+                legendre_all(p, 2.0L * k / p - 1, P2, dP2);
+                for (int m = 0; m < n; ++m) V[(size_t)node * n + m] = P0[ma[m]] * P1[mb[m]] * P2[mc[m]];
+            }
+    const std::vector<long double> C = invert(n, V);
+    const int np = T.npad;
+    T.B64.assign((size_t)T.nqp * 4 * np, 0.0);
+    std::vector<long double> md(n), m0(n), m1(n), m2(n);
+    for (int q = 0; q < T.nq; ++q) {
+        legendre_all(p, 2.0L * T.qw[4 * q + 0] - 1, P0, dP0);
+        legendre_all(p, 2.0L * T.qw[4 * q + 1] - 1, P1, dP1);
+        legendre_all(p, 2.0L * T.qw[4 * q + 2] - 1, P2, dP2);
+        for (int m = 0; m < n; ++m) {
+            md[m] = P0[ma[m]] * P1[mb[m]] * P2[mc[m]];
+            m0[m] = 2 * dP0[ma[m]] * P1[mb[m]] * P2[mc[m]];
+            m1[m] = 2 * P0[ma[m]] * dP1[mb[m]] * P2[mc[m]];
+            m2[m] = 2 * P0[ma[m]] * P1[mb[m]] * dP2[mc[m]];
+        }
+        for (int a = 0; a < n; ++a) {
+            long double v = 0, d0 = 0, d1 = 0, d2 = 0;
+            for (int m = 0; m < n; ++m) {
+                const long double cm = C[(size_t)m * n + a];
+                v += cm * md[m];
+                d0 += cm * m0[m];
+                d1 += cm * m1[m];
+                d2 += cm * m2[m];
+            }
+            T.B64[((size_t)q * 4 + 0) * np + a] = (double)v;
+            T.B64[((size_t)q * 4 + 1) * np + a] = (double)d0;
+            T.B64[((size_t)q * 4 + 2) * np + a] = (double)d1;
+            T.B64[((size_t)q * 4 + 3) * np + a] = (double)d2;
+        }
+    }
+    derive_layouts(T);
+    return T;
+}
+
 }  // namespace feint

@@ -57,6 +57,10 @@ HostTables build_tables(int p, int rule = 0);
 // j) n1 + i, points on [-1,1]^3) and the tensor-product Gauss-Lobatto
 // Lagrange basis (a = (k (p+1) + j) (p+1) + i).
 HostTables build_hex_tables(int p);
+// Tables of the tetrahedral element of degree p: (p+2)^3 collapsed Gauss
+// points (q = (k n1 + j) n1 + i) and the Lagrange basis on the tetrahedral
+// lattice (k outer, j, i inner).
+HostTables build_tet_tables(int p);
 
 // Pieces exposed for the CPU tests of the library's host logic.
 void gauss_legendre_gw(int n, double *x, double *w);     // Golub-Welsch

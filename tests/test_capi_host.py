@@ -219,3 +219,27 @@ def test_hex_host_api():
     assert L.feint_integrate_hex(ctypes.byref(_el(0, null=True)), 3, 0, None, None, None, None, s) == 0
     assert L.feint_hex_tile_set(3, 0, 99) == -1 and L.feint_hex_tile_set(3, 2, 0) == -3
     assert L.feint_hex_autotune(ctypes.byref(_el(0, null=True)), 3, 0, A, A, 1, None, s) == -1
+
+
+def test_tet_host_api():
+    L = native.lib()
+    assert [L.feint_tet_nshp(p) for p in range(0, 9)] == [-1, 4, 10, 20, 35, 56, 84, 120, -1]
+    assert [L.feint_tet_nq(p) for p in range(1, 8)] == [(p + 2) ** 3 for p in range(1, 8)]
+    buf = ctypes.create_string_buffer(32)
+    for p in range(1, 8):
+        for form in (0, 1):
+            n = L.feint_tet_tile_count(p, form)
+            assert n >= 1
+            for t in range(n):
+                assert L.feint_tet_tile_describe(p, form, t, buf, 32) == 0
+                assert re.fullmatch(rb"\d+x\d+(o2)?", buf.value), buf.value
+        for form in (2, 3):
+            assert L.feint_tet_tile_count(p, form) == 0 and L.feint_tet_tile_get(p, form) == -1
+    el = _el(4)
+    A = ctypes.c_void_p(0x2000)
+    s = ctypes.c_void_p(0)
+    assert L.feint_integrate_tet(ctypes.byref(el), 3, 3, A, A, None, None, s) == -3
+    assert L.feint_integrate_tet(ctypes.byref(el), 0, 0, A, A, None, None, s) == -2
+    assert L.feint_integrate_tet(None, 3, 0, A, A, None, None, s) == -1
+    assert L.feint_integrate_tet(ctypes.byref(_el(0, null=True)), 3, 0, None, None, None, None, s) == 0
+    assert L.feint_tet_tile_set(3, 1, 99) == -1
