@@ -65,7 +65,7 @@ def traffic_record(key: str, tile: str):
     return rec.get("tiles", {}).get(tile)
 
 
-def cpu_baseline(batch, p, budget_s: float, chunk: int = 4096, fields=None, rule=None, hexa=False):
+def cpu_baseline(batch, p, budget_s: float, chunk: int = 4096, fields=None, rule=None, kind=None):
     """The oracle on the host's cores over the first elements of the workload,
     chunk by chunk until about `budget_s` seconds have been spent (with vertex
     coefficient fields when `fields` = (Dv, betav, cv, fv) is given)."""
@@ -75,8 +75,9 @@ def cpu_baseline(batch, p, budget_s: float, chunk: int = 4096, fields=None, rule
         sl = np.arange(done, min(batch.ne, done + chunk))
         sub = batch.subset(sl)
         t0 = time.perf_counter()
-        if hexa:
-            A, b, _ = oracle.integrate_hex(p, sub.coords, sub.D, sub.beta, sub.c, sub.f)
+        if kind:
+            fn = oracle.integrate_hex if kind == "hex" else oracle.integrate_tet
+            A, b, _ = fn(p, sub.coords, sub.D, sub.beta, sub.c, sub.f)
         elif fields is None:
             A, b, _ = oracle.integrate(p, sub.coords, sub.D, sub.beta, sub.c, sub.f, rule=rule)
         else:
@@ -127,7 +128,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--mode", default="forward", choices=["forward", "fields", "hex", "adjoint", "mixed", "assemble"])
+    ap.add_argument("--mode", default="forward", choices=["forward", "fields", "hex", "tet", "adjoint", "mixed", "assemble"])
     ap.add_argument("--workload", default=None)
     ap.add_argument("--rule", default="collapsed", choices=["collapsed", "symmetric"],
                     help="quadrature rule of the forward and fields modes")
@@ -154,15 +155,16 @@ def main():
         return bench_mixed(args)
     if args.mode == "assemble":
         return bench_assemble(args)
-    return bench_forward(args, fields=args.mode == "fields", hexa=args.mode == "hex")
+    return bench_forward(args, fields=args.mode == "fields", kind=args.mode if args.mode in ("hex", "tet") else None)
 
 
-def bench_forward(args, fields=False, hexa=False):
+def bench_forward(args, fields=False, kind=None):
     """Forward integration; with `fields` the coefficients are vertex fields
-    evaluated at every point (feint_integrate_fields); with `hexa` the
-    elements are hexahedra (feint_integrate_hex)."""
-    args.workload = args.workload or ("hex_p4_65536" if hexa else "p4_131072")
-    args.forms = args.forms or ("fp64,fp32" if args.sc or hexa else ",".join(FORMS))
+    evaluated at every point (feint_integrate_fields); with `kind` "hex" or
+    "tet" the elements are hexahedra or tetrahedra (feint_integrate_hex/_tet)."""
+    other_elem = kind is not None
+    args.workload = args.workload or {"hex": "hex_p4_65536", "tet": "tet_p4_393216"}.get(kind, "p4_131072")
+    args.forms = args.forms or ("fp64,fp32" if args.sc or other_elem else ",".join(FORMS))
     import torch
     import paper_1310_1194_amd as F
 
@@ -172,19 +174,19 @@ def bench_forward(args, fields=False, hexa=False):
     p = w["p"]
     rule = args.rule
     n, q = costmodel.nshp(p), costmodel.nq(p, rule)
-    if hexa:
+    if other_elem:
         if rule != "collapsed" or args.sc or fields:
-            raise SystemExit("hexahedra: tensor Gauss rule, table-reading kernels, element constants")
-        n = q = (p + 1) ** 3
+            raise SystemExit(f"{kind}: its own Gauss rule, table-reading kernels, element constants")
+        n, q = F.ELEMENTS[kind][1](p), F.ELEMENTS[kind][2](p)
     batch = meshgen.workload(args.workload)
     ne = batch.ne
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     vf = meshgen.vertex_fields(ne, 1000 + w["seed"]) if fields else None
-    if hexa:
+    if other_elem:
         X = (t(batch.coords), t(batch.D), t(batch.beta), t(batch.c), t(batch.f))
 
         def integrate(*a, A=None, b=None, rule=None):
-            return F.integrate_hex_raw(*a, A=A, b=b)
+            return F.integrate_elem_raw(kind, *a, A=A, b=b)
     elif fields:
         X = (t(batch.coords),) + tuple(t(a) for a in vf)
         integrate = F.integrate_fields_raw
@@ -219,14 +221,14 @@ def bench_forward(args, fields=False, hexa=False):
                 raise SystemExit(f"no SC variant compiled for p={p} form={form}")
             F.tile_set(p, form, sc[0], rule=rule)
         elif not args.no_tune:
-            if hexa:
-                tile_ms = F.hex_autotune(*X, p, form, A, b, reps=2)
+            if other_elem:
+                tile_ms = F.elem_autotune(kind, *X, p, form, A, b, reps=2)
             elif fields:
                 tile_ms = F.autotune_fields(*X, p, form, A, b, reps=2, rule=rule)
             else:
                 tile_ms = F.autotune(*X, p, form, A, b, reps=2, rule=rule)
-        if hexa:
-            tile = F.hex_tile_describe(p, form, F.hex_tile_get(p, form))
+        if other_elem:
+            tile = F.elem_tile_describe(kind, p, form, F.elem_tile_get(kind, p, form))
         else:
             tile = F.tile_describe(p, form, F.tile_get(p, form, rule=rule), rule=rule)
         for _ in range(args.warmup):
@@ -250,8 +252,8 @@ def bench_forward(args, fields=False, hexa=False):
                              A_sample=A[sample_idx].cpu().numpy(), b_sample=b[sample_idx].cpu().numpy())
         print(f"[bench] {form}: {ms:.3f} ms/launch (min {np.min(per):.3f}), tile {tile}", file=sys.stderr, flush=True)
 
-    fdom = 8 * n * n * q if hexa else costmodel.f_dom(p, rule)
-    in_bytes = (8 * (24 + 9 + 3 + 1 + 1) if hexa else
+    fdom = 8 * n * n * q if other_elem else costmodel.f_dom(p, rule)
+    in_bytes = (8 * (3 * F.ELEMENTS[kind][0] + 9 + 3 + 1 + 1) if other_elem else
                 costmodel.FIELD_INPUT_BYTES if fields else costmodel.INPUT_BYTES)
     for form, r in results.items():
         es = (n * n + n) * (8 if form == "fp64" else 4)
@@ -263,7 +265,7 @@ def bench_forward(args, fields=False, hexa=False):
     cpu = None
     if not args.no_cpu:
         rate, done, spent, cores, (Ar, br) = cpu_baseline(batch, p, args.cpu_budget, fields=vf,
-                                                          rule=None if rule == "collapsed" else rule, hexa=hexa)
+                                                          rule=None if rule == "collapsed" else rule, kind=kind)
         cpu = {"value": rate, "unit": "elements/s", "cores": cores, "kind": "oracle",
                "sample": f"first {done} of the {ne} elements of {args.workload} "
                          f"({spent:.1f} s, FP64, OpenMP over elements)",
@@ -279,7 +281,7 @@ def bench_forward(args, fields=False, hexa=False):
 
     h = results[headline]
     rkey = "" if rule == "collapsed" else ":" + rule
-    traffic = traffic_record(f"{'hex' if hexa else 'fields' if fields else 'fwd'}:{headline}:{args.workload}{rkey}",
+    traffic = traffic_record(f"{kind or ('fields' if fields else 'fwd')}:{headline}:{args.workload}{rkey}",
                              results[headline]["tile"])
     es = 8 if headline == "fp64" else 4
     alg_bytes = ne * (in_bytes + (n * n + n) * es)
@@ -308,7 +310,7 @@ def bench_forward(args, fields=False, hexa=False):
     line = {
         "metric": "elements/s + GFLOP/s (roofline %) at p=4, plain FP64 vs MFMA form at stated error"
                   + (" (coefficients varying in space, given at the vertices)" if fields else "")
-                  + (" (hexahedral elements)" if hexa else ""),
+                  + ({"hex": " (hexahedral elements)", "tet": " (tetrahedral elements)"}.get(kind, "")),
         "value": h["elements_per_s"],
         "unit": "elements/s",
         "n_gpus": 1,
@@ -323,7 +325,7 @@ def bench_forward(args, fields=False, hexa=False):
         "config": {"workload": args.workload + ("+vertex_fields" if fields else "")
                    + ("+symmetric_rule" if rule != "collapsed" else "") + ("+sc" if args.sc else ""),
                    "p": p, "ne": ne, "rule": rule, "shape_functions": "computed per point" if args.sc else "tables",
-                   "element": "hexahedron" if hexa else "prism",
+                   "element": {"hex": "hexahedron", "tet": "tetrahedron"}.get(kind, "prism"),
                    "nshp": n, "nq": q, "coefficients": "vertex fields" if fields else "element constants",
                    "mesh": f"{w['nx']}x{w['ny']}x{w['nz']}", "perturbation": w["amp"], "seed": w["seed"],
                    "form": headline, "parallelism": "single GPU"},
