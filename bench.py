@@ -164,7 +164,7 @@ def bench_forward(args, fields=False, kind=None):
     "tet" the elements are hexahedra or tetrahedra (feint_integrate_hex/_tet)."""
     other_elem = kind is not None
     args.workload = args.workload or {"hex": "hex_p4_65536", "tet": "tet_p4_393216"}.get(kind, "p4_131072")
-    args.forms = args.forms or ("fp64,fp32" if args.sc or other_elem else ",".join(FORMS))
+    args.forms = args.forms or ("fp64,fp32" if args.sc else ",".join(FORMS))
     import torch
     import paper_1310_1194_amd as F
 

@@ -189,8 +189,8 @@ def integrate_elem_raw(kind: str, coords, D, beta, c, f, p: int, form: str = "fp
                        status=None):
     """Hexahedra ("hex", coords [ne,8,3]) or tetrahedra ("tet", coords [ne,4,3]):
     forward integration; returns (A, b)."""
-    if form not in ("fp64", "fp32"):
-        raise ValueError(f"{kind}: forms fp64 and fp32")
+    if form not in FORMS:
+        raise ValueError(f"unknown form {form!r}")
     el = _elem_inputs(kind, coords, D, beta, c, f)
     ne, n, nqe = coords.shape[0], ELEMENTS[kind][1](p), ELEMENTS[kind][2](p)
     dt = out_dtype(form)

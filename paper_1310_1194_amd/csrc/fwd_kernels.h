@@ -328,16 +328,16 @@ struct K4 {
 // 2^f16_shift and Y by a per-element power of two so that both use the
 // normal range, and unscales exactly at the store.
 // ---------------------------------------------------------------------------
-template <int P, int FORM, int TM, int TN, int R = 0>
+template <int P, int FORM, int TM, int TN, int R = 0, class G = PrismGeo>
 struct K32 {
-    static constexpr int N = c_nshp(P), NP = c_pad16(N), NT = NP / 16, NQ = c_nq_rule(P, R);
+    static constexpr int N = G::nshp(P), NP = c_pad16(N), NT = NP / 16, NQ = G::nq(P, R);
     static constexpr int NQP = c_pad8(NQ);
     static constexpr int BM = c_cdiv(NT, TM), BN = c_cdiv(NT, TN), NBLK = BM * BN;
     static constexpr int EPI = 1;
     static constexpr int NBR = c_cdiv(TM * 16, 64);
     typedef typename SplitT<FORM>::vec HV;
     typedef typename SplitT<FORM>::scal HS;
-    typedef LoadCol<P> LC;
+    typedef LoadColN<N> LC;
 
     struct Slice {                            // one wave's LDS
         float W[64][WROW<float>::value];      // padded rows: conflict-free per-lane writes
@@ -345,8 +345,8 @@ struct K32 {
     };
     struct Smem { Slice w[4]; };
 
-    __device__ static float elem_scale(const FwdParams &prm, const ElemIn &E0, int64_t e) {
-        ElemIn E = E0;
+    __device__ static float elem_scale(const FwdParams &prm, const typename G::Elem &E0, int64_t e) {
+        typename G::Elem E = E0;
         // largest row sum of |W_q| over the element's points, times max |B|,
         // and the largest |w det J f| (the load-vector column): a bound on
         // |Y|; scale so that the bound lies in [2^13, 2^14)
@@ -357,8 +357,8 @@ struct K32 {
             if (q < NQ) {
                 const double *qp = prm.qw + 4 * q;
                 double W[16], sf;
-                field_at(prm, e, qp[0], qp[1], qp[2], E);
-                point_block(E, qp[0], qp[1], qp[2], qp[3], W, sf);
+                G::coeffs(prm, e, qp, E);
+                G::block(E, qp, W, sf);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const double s = fabs(W[4 * r]) + fabs(W[4 * r + 1]) + fabs(W[4 * r + 2]) + fabs(W[4 * r + 3]);
@@ -416,8 +416,8 @@ struct K32 {
         const int i16 = lane & 15, kg = lane >> 4;
         const int a0 = bi * TM * 16, b0 = bj * TN * 16;
         const int64_t e = elem_of(prm, slot);
-        ElemIn E;
-        load_elem_fwd(prm, e, E);
+        typename G::Elem E;
+        G::load(prm, e, E);
         const float ys = FORM == FP16X3 ? elem_scale(prm, E, e) : 1.0f;
         f32x4 acc[TMV][TNV];
 #pragma unroll
@@ -435,12 +435,12 @@ struct K32 {
                 double W[16], sf = 0.0;
                 if (q < NQ) {
                     const double *qp = prm.qw + 4 * q;
-                    field_at(prm, e, qp[0], qp[1], qp[2], E);
-                    const double det = point_block(E, qp[0], qp[1], qp[2], qp[3], W, sf);
+                    G::coeffs(prm, e, qp, E);
+                    const double det = G::block(E, qp, W, sf);
                     if (!(det > 0.0) && prm.status) atomicOr(prm.status, 1u);
                     if (prm.xq && blk == 0) {
                         double x[3];
-                        prism_map(E.X, qp[0], qp[1], qp[2], x);
+                        G::map(E, qp, x);
 #pragma unroll
                         for (int d = 0; d < 3; ++d) prm.xq[(e * NQ + q) * 3 + d] = x[d];
                     }

@@ -58,6 +58,10 @@ int64_t items_of(int64_t ne) { return items_for<KER>(ne); }
 #define FEINT_K4U_TET(P, T, TM, TN, W) \
     FwdVariant{TM, TN, 0, W, &launch_direct<K4<P, T, TM, TN, 0, TetGeo>, W>, &items_of<K4<P, T, TM, TN, 0, TetGeo>>}
 
+// Split forms on hexahedra and tetrahedra: the 16x16x32 kernel with their geometry.
+#define FEINT_K32U_G(P, F, TM, TN, W, GEO) \
+    FwdVariant{TM, TN, 0, W, &launch_direct<K32<P, F, TM, TN, 0, GEO>, W>, &items_of<K32<P, F, TM, TN, 0, GEO>>}
+
 #define FEINT_K4U(P, T, TM, TN, W) FEINT_K4U_R(P, T, TM, TN, W, 0)
 #define FEINT_KSC(P, T, TM, TN, W) FEINT_KSC_R(P, T, TM, TN, W, 0)
 #define FEINT_K4S(P, T, TM, TN, SP, W) FEINT_K4S_R(P, T, TM, TN, SP, W, 0)

@@ -1,7 +1,8 @@
 // Forward kernels for tetrahedral elements (Table 1's complete-basis 3D
-// element): the 16x16x4 MFMA kernel with the affine geometry, FP64 and FP32
-// forms; tile shapes per degree (n = 4, 10, 20, 35, 56, 84, 120 shape
-// functions: 1, 1, 2, 3, 4, 6, 8 tiles of 16), the first the default.
+// element): the 16x16x4 MFMA kernel (FP64, FP32) and the 16x16x32 split
+// kernel (bf16x3, fp16x3) with the affine geometry; tile shapes per degree
+// (n = 4, 10, 20, 35, 56, 84, 120 shape functions: 1, 1, 2, 3, 4, 6, 8 tiles
+// of 16), the first the default.
 #include "fwd_registry.h"
 
 namespace feint {
@@ -20,6 +21,20 @@ const FwdVariant f4[] = {FEINT_K4U_TET(4, float, 3, 3, 2), FEINT_K4U_TET(4, floa
 const FwdVariant f5[] = {FEINT_K4U_TET(5, float, 4, 4, 1), FEINT_K4U_TET(5, float, 4, 2, 2)};
 const FwdVariant f6[] = {FEINT_K4U_TET(6, float, 6, 3, 1), FEINT_K4U_TET(6, float, 6, 2, 1)};
 const FwdVariant f7[] = {FEINT_K4U_TET(7, float, 8, 4, 1), FEINT_K4U_TET(7, float, 8, 2, 1)};
+const FwdVariant b1[] = {FEINT_K32U_G(1, BF16X3, 1, 1, 1, TetGeo)};
+const FwdVariant b2[] = {FEINT_K32U_G(2, BF16X3, 1, 1, 1, TetGeo)};
+const FwdVariant b3[] = {FEINT_K32U_G(3, BF16X3, 2, 2, 1, TetGeo)};
+const FwdVariant b4[] = {FEINT_K32U_G(4, BF16X3, 3, 3, 1, TetGeo)};
+const FwdVariant b5[] = {FEINT_K32U_G(5, BF16X3, 4, 4, 1, TetGeo), FEINT_K32U_G(5, BF16X3, 4, 2, 1, TetGeo)};
+const FwdVariant b6[] = {FEINT_K32U_G(6, BF16X3, 6, 3, 1, TetGeo), FEINT_K32U_G(6, BF16X3, 6, 2, 1, TetGeo)};
+const FwdVariant b7[] = {FEINT_K32U_G(7, BF16X3, 8, 4, 1, TetGeo), FEINT_K32U_G(7, BF16X3, 8, 2, 1, TetGeo)};
+const FwdVariant h1[] = {FEINT_K32U_G(1, FP16X3, 1, 1, 1, TetGeo)};
+const FwdVariant h2[] = {FEINT_K32U_G(2, FP16X3, 1, 1, 1, TetGeo)};
+const FwdVariant h3[] = {FEINT_K32U_G(3, FP16X3, 2, 2, 1, TetGeo)};
+const FwdVariant h4[] = {FEINT_K32U_G(4, FP16X3, 3, 3, 1, TetGeo)};
+const FwdVariant h5[] = {FEINT_K32U_G(5, FP16X3, 4, 4, 1, TetGeo), FEINT_K32U_G(5, FP16X3, 4, 2, 1, TetGeo)};
+const FwdVariant h6[] = {FEINT_K32U_G(6, FP16X3, 6, 3, 1, TetGeo), FEINT_K32U_G(6, FP16X3, 6, 2, 1, TetGeo)};
+const FwdVariant h7[] = {FEINT_K32U_G(7, FP16X3, 8, 4, 1, TetGeo), FEINT_K32U_G(7, FP16X3, 8, 2, 1, TetGeo)};
 
 #define FEINT_PICK(a1, a2, a3, a4, a5, a6, a7)                    \
     switch (p) {                                                   \
@@ -37,6 +52,8 @@ const FwdVariant *fwd_variants_tet(int form, int p, int *count) {
     switch (form) {
     case F64: FEINT_PICK(d1, d2, d3, d4, d5, d6, d7); break;
     case F32: FEINT_PICK(f1, f2, f3, f4, f5, f6, f7); break;
+    case BF16X3: FEINT_PICK(b1, b2, b3, b4, b5, b6, b7); break;
+    case FP16X3: FEINT_PICK(h1, h2, h3, h4, h5, h6, h7); break;
     }
     *count = 0;
     return nullptr;

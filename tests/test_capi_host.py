@@ -206,18 +206,18 @@ def test_hex_host_api():
             for t in range(n):
                 assert L.feint_hex_tile_describe(p, form, t, buf, 32) == 0
                 assert re.fullmatch(rb"\d+x\d+(o2)?", buf.value), buf.value
-        for form in (2, 3):                          # split forms: not compiled for hexahedra
-            assert L.feint_hex_tile_count(p, form) == 0 and L.feint_hex_tile_get(p, form) == -1
+        for form in (2, 3):                          # split forms
+            assert L.feint_hex_tile_count(p, form) >= 1
     el = _el(4)
     A = ctypes.c_void_p(0x2000)
     s = ctypes.c_void_p(0)
-    assert L.feint_integrate_hex(ctypes.byref(el), 3, 2, A, A, None, None, s) == -3
+    assert L.feint_integrate_hex(ctypes.byref(el), 3, 7, A, A, None, None, s) == -3
     assert L.feint_integrate_hex(ctypes.byref(el), 8, 0, A, A, None, None, s) == -2
     assert L.feint_integrate_hex(None, 3, 0, A, A, None, None, s) == -1
     assert L.feint_integrate_hex(ctypes.byref(_el(4, null=True)), 3, 0, A, A, None, None, s) == -1
     assert L.feint_integrate_hex(ctypes.byref(el), 3, 0, None, A, None, None, s) == -1
     assert L.feint_integrate_hex(ctypes.byref(_el(0, null=True)), 3, 0, None, None, None, None, s) == 0
-    assert L.feint_hex_tile_set(3, 0, 99) == -1 and L.feint_hex_tile_set(3, 2, 0) == -3
+    assert L.feint_hex_tile_set(3, 0, 99) == -1 and L.feint_hex_tile_set(3, 5, 0) == -3
     assert L.feint_hex_autotune(ctypes.byref(_el(0, null=True)), 3, 0, A, A, 1, None, s) == -1
 
 
@@ -234,11 +234,11 @@ def test_tet_host_api():
                 assert L.feint_tet_tile_describe(p, form, t, buf, 32) == 0
                 assert re.fullmatch(rb"\d+x\d+(o2)?", buf.value), buf.value
         for form in (2, 3):
-            assert L.feint_tet_tile_count(p, form) == 0 and L.feint_tet_tile_get(p, form) == -1
+            assert L.feint_tet_tile_count(p, form) >= 1
     el = _el(4)
     A = ctypes.c_void_p(0x2000)
     s = ctypes.c_void_p(0)
-    assert L.feint_integrate_tet(ctypes.byref(el), 3, 3, A, A, None, None, s) == -3
+    assert L.feint_integrate_tet(ctypes.byref(el), 3, 4, A, A, None, None, s) == -3
     assert L.feint_integrate_tet(ctypes.byref(el), 0, 0, A, A, None, None, s) == -2
     assert L.feint_integrate_tet(None, 3, 0, A, A, None, None, s) == -1
     assert L.feint_integrate_tet(ctypes.byref(_el(0, null=True)), 3, 0, None, None, None, None, s) == 0

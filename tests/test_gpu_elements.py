@@ -1,6 +1,7 @@
 """GPU parity of the other element types of Table 1 -- hexahedra (tensor
 product basis) and tetrahedra (complete basis) -- against the oracle, through
-the C-ABI: every degree, form and compiled variant, mapped points in the
+the C-ABI: every degree, form (FP64, FP32 and the split forms) and compiled
+variant, mapped points in the
 rule's point order, the det J flag, an empty batch, and the full p = 4
 meshes on a sample of elements.  Tolerances are those of the prism forward
 tests."""
@@ -11,7 +12,7 @@ from gpu_util import flush, rel_errors
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": (1e-12, 1e-12), "fp32": (1e-5, 1e-4)}
+TOL = {"fp64": (1e-12, 1e-12), "fp32": (1e-5, 1e-4), "bf16x3": (1e-5, 2e-4), "fp16x3": (1e-5, 1e-4)}
 NV = {"hex": 8, "tet": 4}
 INVERT = {"hex": [4, 5, 6, 7, 0, 1, 2, 3], "tet": [0, 2, 1, 3]}
 
@@ -47,7 +48,7 @@ def dev(torch, b):
     return t(b.coords), t(b.D), t(b.beta), t(b.c), t(b.f)
 
 
-@pytest.mark.parametrize("form", ["fp64", "fp32"])
+@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16x3", "fp16x3"])
 @pytest.mark.parametrize("p", range(1, 8))
 @pytest.mark.parametrize("kind", ["hex", "tet"])
 def test_elem_parity_every_tile(torch_cuda, kind, p, form):
@@ -103,7 +104,7 @@ def test_elem_empty_batch(torch_cuda, kind):
     assert A.shape == (0, n, n) and b.shape == (0, n)
 
 
-@pytest.mark.parametrize("form", ["fp64", "fp32"])
+@pytest.mark.parametrize("form", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("name,kind", [("hex_p4_65536", "hex"), ("tet_p4_393216", "tet")])
 def test_elem_full_size_sampled(torch_cuda, name, kind, form):
     """The p = 4 meshes of the other element types on the 64x64x16 vertex grid,
