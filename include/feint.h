@@ -285,9 +285,9 @@ feint_status feint_autotune_rule(const feint_elements *el, const feint_fields *f
    the p+1 Gauss-Lobatto nodes; (p+1)^3 Gauss-Legendre points, q = (k n1 +
    j) n1 + i.  Inputs as feint_elements with coords [ne][8][3]; outputs
    A [ne][n][n] (row = test function), b [ne][n], n = (p+1)^3; xq (nullable)
-   [ne][(p+1)^3][3]; dev_status as feint_integrate.  Forms FEINT_FP64 and
-   FEINT_FP32 (16x16x4 MFMA); the split forms give UNSUPPORTED_FORM.
-   Variants, tile selection and autotuning as for prisms. */
+   [ne][(p+1)^3][3]; dev_status as feint_integrate.  All four forms (FP64
+   and FP32 on the 16x16x4 MFMA kernel, bf16x3 and fp16x3 on the 16x16x32
+   split kernel).  Variants, tile selection and autotuning as for prisms. */
 int feint_hex_nshp(int p);
 int feint_hex_nq(int p);
 feint_status feint_prepare_hex(int p);
