@@ -242,11 +242,24 @@ def integrate_tet_raw(coords, D, beta, c, f, p: int, form: str = "fp64", **kw):
     return integrate_elem_raw("tet", coords, D, beta, c, f, p, form, **kw)
 
 
-def hex_tile_count(p, form): return elem_tile_count("hex", p, form)
-def hex_tile_get(p, form): return elem_tile_get("hex", p, form)
-def hex_tile_set(p, form, tile): return elem_tile_set("hex", p, form, tile)
-def hex_tile_describe(p, form, tile): return elem_tile_describe("hex", p, form, tile)
-def hex_autotune(*a, **kw): return elem_autotune("hex", *a, **kw)
+def hex_tile_count(p, form):
+    return elem_tile_count("hex", p, form)
+
+
+def hex_tile_get(p, form):
+    return elem_tile_get("hex", p, form)
+
+
+def hex_tile_set(p, form, tile):
+    return elem_tile_set("hex", p, form, tile)
+
+
+def hex_tile_describe(p, form, tile):
+    return elem_tile_describe("hex", p, form, tile)
+
+
+def hex_autotune(*a, **kw):
+    return elem_autotune("hex", *a, **kw)
 
 
 def adjoint_raw(coords, D, beta, c, f, G, g, p: int, form: str = "fp64"):
