@@ -386,7 +386,10 @@ static feint_status elem_tile_describe(int type, int p, int form, int tile, char
     int cnt = 0;
     const FwdVariant *v = elem_variants(type, form, p, &cnt);
     if (!buf || tile < 0 || tile >= cnt) return FEINT_ERR_INVALID_ARG;
-    std::snprintf(buf, len, "%dx%d%s", v[tile].tm, v[tile].tn, v[tile].minw > 1 ? "o2" : "");
+    if (v[tile].staged == 3)
+        std::snprintf(buf, len, "v%d%s", v[tile].tn, v[tile].minw > 1 ? "o2" : "");
+    else
+        std::snprintf(buf, len, "%dx%d%s", v[tile].tm, v[tile].tn, v[tile].minw > 1 ? "o2" : "");
     return FEINT_OK;
 }
 

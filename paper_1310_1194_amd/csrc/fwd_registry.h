@@ -62,6 +62,10 @@ int64_t items_of(int64_t ne) { return items_for<KER>(ne); }
 #define FEINT_K32U_G(P, F, TM, TN, W, GEO) \
     FwdVariant{TM, TN, 0, W, &launch_direct<K32<P, F, TM, TN, 0, GEO>, W>, &items_of<K32<P, F, TM, TN, 0, GEO>>}
 
+// Vector-ALU kernel on hexahedra and tetrahedra (low degree).
+#define FEINT_KV_G(P, T, LPE, W, GEO) \
+    FwdVariant{0, LPE, 3, W, &launch_direct<KV<P, T, LPE, 0, GEO>, W>, &items_of<KV<P, T, LPE, 0, GEO>>}
+
 #define FEINT_K4U(P, T, TM, TN, W) FEINT_K4U_R(P, T, TM, TN, W, 0)
 #define FEINT_KSC(P, T, TM, TN, W) FEINT_KSC_R(P, T, TM, TN, W, 0)
 #define FEINT_K4S(P, T, TM, TN, SP, W) FEINT_K4S_R(P, T, TM, TN, SP, W, 0)

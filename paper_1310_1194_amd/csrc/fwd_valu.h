@@ -35,9 +35,9 @@ __device__ inline const T *uniform_ptr(const T *p) {
     return (const T *)(uintptr_t)(((uint64_t)hi << 32) | lo);
 }
 
-template <int P, typename T, int LPE, int R = 0>
+template <int P, typename T, int LPE, int R = 0, class G = PrismGeo>
 struct KV {
-    static constexpr int N = c_nshp(P), NP = c_pad16(N), NQ = c_nq_rule(P, R);
+    static constexpr int N = G::nshp(P), NP = c_pad16(N), NQ = G::nq(P, R);
     static constexpr int EPW = 64 / LPE;        // element slots per work item
     static constexpr int EPI = EPW, NBLK = 1;
     static constexpr int NPT = EPW * NQ;        // (element, point) pairs per item
@@ -72,12 +72,12 @@ struct KV {
             const int64_t slot = s0 + el;
             if (slot < nslot) {
                 const int64_t e = elem_of(prm, slot);
-                ElemIn E;
-                load_elem_fwd(prm, e, E);
+                typename G::Elem E;
+                G::load(prm, e, E);
                 const double *qp = qw + 4 * q;
                 double W[16], sf;
-                field_at(prm, e, qp[0], qp[1], qp[2], E);
-                const double det = point_block(E, qp[0], qp[1], qp[2], qp[3], W, sf);
+                G::coeffs(prm, e, qp, E);
+                const double det = G::block(E, qp, W, sf);
                 if (!(det > 0.0) && prm.status) atomicOr(prm.status, 1u);
                 T *w = sl.W[t];
                 w[0] = (T)W[0]; w[1] = (T)W[1]; w[2] = (T)W[2]; w[3] = (T)W[3];
@@ -88,7 +88,7 @@ struct KV {
                 sl.sf[t] = sf;
                 if (prm.xq) {
                     double x[3];
-                    prism_map(E.X, qp[0], qp[1], qp[2], x);
+                    G::map(E, qp, x);
 #pragma unroll
                     for (int d = 0; d < 3; ++d) prm.xq[(e * NQ + q) * 3 + d] = x[d];
                 }

@@ -286,6 +286,8 @@ WORKLOADS = {
     "hex_p4_65536": dict(nx=64, ny=64, nz=16, amp=0.2, seed=1, p=4, element="hexahedron"),
     # tetrahedra (six per cell) on the vertex grid of the p = 4 prism workload
     "tet_p4_393216": dict(nx=64, ny=64, nz=16, amp=0.2, seed=1, p=4, element="tetrahedron"),
+    "tet_p1_393216": dict(nx=64, ny=64, nz=16, amp=0.2, seed=1, p=1, element="tetrahedron"),
+    "tet_p2_393216": dict(nx=64, ny=64, nz=16, amp=0.2, seed=1, p=2, element="tetrahedron"),
 }
 
 
