@@ -276,6 +276,13 @@ feint_status feint_rule_tile_describe(int p, feint_form form, feint_rule rule, i
                                       size_t len);
 feint_status feint_autotune_rule(const feint_elements *el, const feint_fields *fl, int p, feint_form form,
                                  feint_rule rule, void *A, void *b, int reps, double *best_ms, void *stream);
+/* The adjoint on quadrature rule `rule` (the gradients of the forward pass
+   feint_integrate_rule computes with element-constant coefficients);
+   arguments, outputs and errors otherwise as feint_integrate_adjoint.  The
+   adjoint block-shape choice (feint_adjoint_tile_*) serves both rules. */
+feint_status feint_integrate_adjoint_rule(const feint_elements *el, int p, feint_form form, feint_rule rule,
+                                          const void *G, const void *g, double *dcoords, double *dD,
+                                          double *dbeta, double *dc, double *df, void *stream);
 
 /* ---- Hexahedral elements (Table 1, tensor-product basis) --------------------
    The same integration (CDR element matrix and load vector, W_q in FP64) on

@@ -61,6 +61,7 @@ def lib():
         L.oracle_hex_geometry.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp]
         L.oracle_integrate_hex.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [_dp] * 8 + [_ip]
         L.oracle_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64] + [_dp] * 13
+        L.oracle_adjoint_rule.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int64] + [_dp] * 13
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_max_threads.restype = ctypes.c_int
         _lib = L
@@ -200,12 +201,20 @@ def integrate_fields(p, coords, Dv, betav, cv, fv, n1=0, want_xq=False, rule=Non
     return A, b, flags
 
 
-def adjoint(p, coords, D, beta, c, f, G, g, n1=0):
-    """Gradients of sum_e <G_e,A_e> + <g_e,b_e>: dcoords, dD, dbeta, dc, df, per-element loss."""
+def adjoint(p, coords, D, beta, c, f, G, g, n1=0, rule=None):
+    """Gradients of sum_e <G_e,A_e> + <g_e,b_e>: dcoords, dD, dbeta, dc, df, per-element loss.
+    rule=None: collapsed Gauss with n1 points per direction; rule="symmetric": the symmetric rule."""
     coords = _c(coords); D = _c(D); beta = _c(beta); c = _c(c); f = _c(f); G = _c(G); g = _c(g)
     ne = coords.shape[0]
     dX = np.zeros_like(coords); dD = np.zeros_like(D); db = np.zeros_like(beta)
     dc = np.zeros(ne); df = np.zeros(ne); Le = np.zeros(ne)
+    if rule is not None:
+        pts, w = prism_rule(p, rule)
+        pts = _c(pts); w = _c(w)
+        rc = lib().oracle_adjoint_rule(p, w.shape[0], _p(pts), _p(w), ne, _p(coords), _p(D), _p(beta), _p(c), _p(f),
+                                       _p(G), _p(g), _p(dX), _p(dD), _p(db), _p(dc), _p(df), _p(Le))
+        assert rc == 0, rc
+        return dX, dD, db, dc, df, Le
     rc = lib().oracle_adjoint(p, n1, ne, _p(coords), _p(D), _p(beta), _p(c), _p(f), _p(G), _p(g),
                               _p(dX), _p(dD), _p(db), _p(dc), _p(df), _p(Le))
     assert rc == 0, rc

@@ -703,15 +703,38 @@ int oracle_integrate_rule(int p, int nq, const double *qpts, const double *qw, i
        =>  dL/dJ = L_q K^T - K^T (dL/dK) K^T;
      J_dl = sum_a x_ad dN_a/dxi_l  =>  dL/dx_ad = sum_l dL/dJ_dl dN_a/dxi_l.
    Also returns the per-element loss in Le (nullable). */
+static int adjoint_core(int p, int n1, int nq, const double *qpts, const double *qw, int64_t ne,
+                        const double *coords, const double *D, const double *beta, const double *c,
+                        const double *f, const double *G, const double *g, double *dcoords, double *dD,
+                        double *dbeta, double *dc, double *df, double *Le);
+
 int oracle_adjoint(int p, int n1, int64_t ne, const double *coords, const double *D,
                    const double *beta, const double *c, const double *f,
                    const double *G, const double *g,
                    double *dcoords, double *dD, double *dbeta, double *dc, double *df,
                    double *Le)
 {
+    return adjoint_core(p, n1, 0, NULL, NULL, ne, coords, D, beta, c, f, G, g, dcoords, dD, dbeta, dc, df, Le);
+}
+
+/* The adjoint on a rule given by the caller (qpts [nq][3], qw [nq]). */
+int oracle_adjoint_rule(int p, int nq, const double *qpts, const double *qw, int64_t ne, const double *coords,
+                        const double *D, const double *beta, const double *c, const double *f,
+                        const double *G, const double *g, double *dcoords, double *dD, double *dbeta,
+                        double *dc, double *df, double *Le)
+{
+    if (!qpts) return -1;
+    return adjoint_core(p, 0, nq, qpts, qw, ne, coords, D, beta, c, f, G, g, dcoords, dD, dbeta, dc, df, Le);
+}
+
+static int adjoint_core(int p, int n1, int nq, const double *qpts, const double *qw, int64_t ne,
+                        const double *coords, const double *D, const double *beta, const double *c,
+                        const double *f, const double *G, const double *g, double *dcoords, double *dD,
+                        double *dbeta, double *dc, double *df, double *Le)
+{
     rule_tables T;
     if (ne < 0) return -1;
-    if (make_tables(0, p, n1, 0, NULL, NULL, &T)) return -1;
+    if (make_tables(0, p, n1, nq, qpts, qw, &T)) return -1;
     const int n = T.n, nqp = T.nq;
     int64_t e;
 #pragma omp parallel for schedule(static)

@@ -262,7 +262,7 @@ def hex_autotune(*a, **kw):
     return elem_autotune("hex", *a, **kw)
 
 
-def adjoint_raw(coords, D, beta, c, f, G, g, p: int, form: str = "fp64"):
+def adjoint_raw(coords, D, beta, c, f, G, g, p: int, form: str = "fp64", rule: str = "collapsed"):
     """Gradients of sum_e <G_e,A_e> + <g_e,b_e>: (dcoords, dD, dbeta, dc, df), FP64."""
     el = elements(coords, D, beta, c, f)
     ne, n = coords.shape[0], nshp(p)
@@ -272,9 +272,14 @@ def adjoint_raw(coords, D, beta, c, f, G, g, p: int, form: str = "fp64"):
     if G.numel() != ne * n * n or g.numel() != ne * n:
         raise ValueError("G, g have the wrong size")
     outs = [torch.empty_like(t) for t in (coords, D, beta, c, f)]
-    check("feint_integrate_adjoint",
-          lib().feint_integrate_adjoint(ctypes.byref(el), int(p), FORMS[form], _ptr(G), _ptr(g),
-                                        *[_ptr(o) for o in outs], _stream()))
+    if rule == "collapsed":
+        check("feint_integrate_adjoint",
+              lib().feint_integrate_adjoint(ctypes.byref(el), int(p), FORMS[form], _ptr(G), _ptr(g),
+                                            *[_ptr(o) for o in outs], _stream()))
+    else:
+        check("feint_integrate_adjoint_rule",
+              lib().feint_integrate_adjoint_rule(ctypes.byref(el), int(p), FORMS[form], _rule(rule), _ptr(G),
+                                                 _ptr(g), *[_ptr(o) for o in outs], _stream()))
     return tuple(outs)
 
 

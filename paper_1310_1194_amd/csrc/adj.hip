@@ -40,9 +40,9 @@ struct AdjParams {
     const void *BT;     // [npad][nqp*4]  in the form's precision
 };
 
-template <int P, typename T, int TA, int TB>
+template <int P, typename T, int TA, int TB, int R = 0>
 struct Adj {
-    static constexpr int N = c_nshp(P), NP = c_pad16(N), NT = NP / 16, NQ = c_nq(P);
+    static constexpr int N = c_nshp(P), NP = c_pad16(N), NT = NP / 16, NQ = c_nq_rule(P, R);
     static constexpr int NQP = c_pad8(NQ);            // table rows
     static constexpr int NQ4 = (NQ + 3) / 4 * 4;       // points covered by 16-row tiles
     static constexpr int BA = c_cdiv(NT, TA), BB = c_cdiv(NT, TB), NBLK = BA * BB;
@@ -323,15 +323,17 @@ feint_status launch_adj(const AdjParams &prm, hipStream_t s) {
     return FEINT_OK;
 }
 
-// Compiled block shapes (TA x TB 16x16 tiles of G per wave) per degree; the
-// first is the default until feint_adjoint_autotune picks another.
+// Compiled block shapes (TA x TB 16x16 tiles of G per wave) per degree and
+// quadrature rule (the same shapes for both rules, so one choice per (degree,
+// form) serves both); the first is the default until feint_adjoint_autotune
+// picks another.
 struct AdjVariant {
     int ta, tb;
     feint_status (*launch)(const AdjParams &, hipStream_t);
 };
-#define FEINT_ADJ(P, T, TA, TB) AdjVariant{TA, TB, &launch_adj<Adj<P, T, TA, TB>>}
+#define FEINT_ADJ(P, T, TA, TB) AdjVariant{TA, TB, &launch_adj<Adj<P, T, TA, TB, R>>}
 
-template <typename T>
+template <typename T, int R>
 const AdjVariant *adj_variants_of(int p, int *count) {
     static const AdjVariant v1[] = {FEINT_ADJ(1, T, 1, 1)};
     static const AdjVariant v2[] = {FEINT_ADJ(2, T, 2, 2), FEINT_ADJ(2, T, 2, 1)};
@@ -360,9 +362,9 @@ const AdjVariant *adj_variants_of(int p, int *count) {
     return nullptr;
 }
 
-const AdjVariant *adj_variants(int form, int p, int *count) {
-    if (form == FEINT_FP64) return adj_variants_of<double>(p, count);
-    if (form == FEINT_FP32) return adj_variants_of<float>(p, count);
+const AdjVariant *adj_variants(int form, int p, int *count, int rule = 0) {
+    if (form == FEINT_FP64) return rule ? adj_variants_of<double, 1>(p, count) : adj_variants_of<double, 0>(p, count);
+    if (form == FEINT_FP32) return rule ? adj_variants_of<float, 1>(p, count) : adj_variants_of<float, 0>(p, count);
     *count = 0;
     return nullptr;
 }
@@ -370,9 +372,9 @@ const AdjVariant *adj_variants(int form, int p, int *count) {
 std::mutex g_adj_mu;
 int g_adj_tile[8][2];                       // chosen variant per (p, form)
 
-const AdjVariant *adj_chosen(int p, int form) {
+const AdjVariant *adj_chosen(int p, int form, int rule) {
     int cnt = 0;
-    const AdjVariant *v = adj_variants(form, p, &cnt);
+    const AdjVariant *v = adj_variants(form, p, &cnt, rule);
     if (!v || cnt == 0) return nullptr;
     std::lock_guard<std::mutex> lk(g_adj_mu);
     const int t = g_adj_tile[p][form];
@@ -381,7 +383,7 @@ const AdjVariant *adj_chosen(int p, int form) {
 
 feint_status adj_setup(const feint_elements *el, int p, feint_form form, const void *G, const void *g,
                        double *dcoords, double *dD, double *dbeta, double *dc, double *df, hipStream_t st,
-                       AdjParams &prm) {
+                       AdjParams &prm, int rule = 0) {
     if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
     if (form != FEINT_FP64 && form != FEINT_FP32) return FEINT_ERR_UNSUPPORTED_FORM;
     feint_status s = check_elements(el);
@@ -389,7 +391,7 @@ feint_status adj_setup(const feint_elements *el, int p, feint_form form, const v
     if (el->ne == 0) return FEINT_OK;
     if (!G || !g || !dcoords || !dD || !dbeta || !dc || !df) return FEINT_ERR_INVALID_ARG;
     const DevTables *T = nullptr;
-    s = tables_for_launch(p, st, &T);
+    s = tables_for_launch(p, st, &T, rule);
     if (s != FEINT_OK) return s;
     std::memset(&prm, 0, sizeof prm);
     prm.coords = el->coords; prm.D = el->D; prm.beta = el->beta; prm.c = el->c; prm.f = el->f;
@@ -424,7 +426,18 @@ feint_status feint_integrate_adjoint(const feint_elements *el, int p, feint_form
     AdjParams prm;
     feint_status s = adj_setup(el, p, form, G, g, dcoords, dD, dbeta, dc, df, st, prm);
     if (s != FEINT_OK || el->ne == 0) return s;
-    return adj_launch(adj_chosen(p, form), prm, st);
+    return adj_launch(adj_chosen(p, form, 0), prm, st);
+}
+
+feint_status feint_integrate_adjoint_rule(const feint_elements *el, int p, feint_form form, feint_rule rule,
+                                          const void *G, const void *g, double *dcoords, double *dD,
+                                          double *dbeta, double *dc, double *df, void *stream) {
+    if (rule != FEINT_RULE_COLLAPSED && rule != FEINT_RULE_SYMMETRIC) return FEINT_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    AdjParams prm;
+    feint_status s = adj_setup(el, p, form, G, g, dcoords, dD, dbeta, dc, df, st, prm, rule);
+    if (s != FEINT_OK || el->ne == 0) return s;
+    return adj_launch(adj_chosen(p, form, rule), prm, st);
 }
 
 int feint_adjoint_tile_count(int p, feint_form form) {

@@ -33,7 +33,7 @@ EXPORTS = (
     "feint_prepare_hex", "feint_integrate_hex", "feint_hex_tile_count", "feint_hex_tile_get", "feint_hex_tile_set",
     "feint_hex_tile_describe", "feint_hex_autotune", "feint_tet_nshp", "feint_tet_nq", "feint_prepare_tet",
     "feint_integrate_tet", "feint_tet_tile_count", "feint_tet_tile_get", "feint_tet_tile_set",
-    "feint_tet_tile_describe", "feint_tet_autotune",
+    "feint_tet_tile_describe", "feint_tet_autotune", "feint_integrate_adjoint_rule",
 )
 
 
@@ -130,6 +130,7 @@ def lib() -> ctypes.CDLL:
             "feint_hex_tile_set": (_i, [_i, _i, _i]),
             "feint_hex_tile_describe": (_i, [_i, _i, _i, ctypes.c_char_p, ctypes.c_size_t]),
             "feint_hex_autotune": (_i, [P, _i, _i, _vp, _vp, _i, ctypes.POINTER(ctypes.c_double), _vp]),
+            "feint_integrate_adjoint_rule": (_i, [P, _i, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
             "feint_tet_nshp": (_i, [_i]),
             "feint_tet_nq": (_i, [_i]),
             "feint_prepare_tet": (_i, [_i]),

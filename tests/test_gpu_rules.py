@@ -2,9 +2,9 @@
 degree 2p x (p+1) Gauss points in zeta, the point counts of the paper's
 Table 3) against the oracle on its own, independently solved rule: every
 degree, form and compiled variant, element constants and vertex fields,
-mapped points in the specified point order, the det J flag, and the full p = 4
-workload on a sample of elements.  Tolerances are those of the collapsed-rule
-forward tests."""
+mapped points in the specified point order, the det J flag, the full p = 4
+workload on a sample of elements, and the adjoint.  Tolerances are those of
+the collapsed-rule forward and adjoint tests."""
 import numpy as np
 import pytest
 
@@ -124,3 +124,37 @@ def test_rule_full_size_sampled(torch_cuda, form):
     flush(f"    A: {gA:.3e} / {mA:.3e}   b: {gb:.3e}")
     assert gA <= TOL[form][0] and mA <= TOL[form][1] and gb <= TOL[form][0]
     assert bool(torch.isfinite(A).all())
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+@pytest.mark.parametrize("p", range(1, 8))
+def test_rule_adjoint_parity(torch_cuda, p, form):
+    """The adjoint on the symmetric rule, every compiled block shape, against
+    the oracle's reverse-mode gradient on its own rule (tolerances of the
+    collapsed-rule adjoint tests: FP64 1e-11, FP32 2e-5)."""
+    import oracle
+    import paper_1310_1194_amd as F
+    torch = torch_cuda
+    tol = {"fp64": 1e-11, "fp32": 2e-5}[form]
+    batch = rule_batch(p, 140 + p)
+    n = F.nshp(p)
+    rng = np.random.default_rng(150 + p)
+    G = rng.normal(size=(batch.ne, n, n))
+    g = rng.normal(size=(batch.ne, n))
+    if form == "fp32":      # the fp32 form sees the seeds rounded to FP32
+        G = G.astype(np.float32).astype(np.float64)
+        g = g.astype(np.float32).astype(np.float64)
+    ref = oracle.adjoint(p, batch.coords, batch.D, batch.beta, batch.c, batch.f, G, g, rule=SYM)
+    dt = torch.float64 if form == "fp64" else torch.float32
+    X = to_dev(batch)
+    Gd, gd = torch.from_numpy(G).cuda().to(dt), torch.from_numpy(g).cuda().to(dt)
+    for tile in range(F.adjoint_tile_count(p, form)):
+        F.adjoint_tile_set(p, form, tile)
+        flush(f"[rule adjoint] p={p} form={form} block {F.adjoint_tile_describe(p, form, tile)} ne={batch.ne}")
+        got = F.adjoint_raw(*X, Gd, gd, p, form, rule=SYM)
+        torch.cuda.synchronize()
+        for name, a, r in zip(("dcoords", "dD", "dbeta", "dc", "df"), got, ref[:5]):
+            e = float(np.linalg.norm(a.cpu().numpy() - r) / np.linalg.norm(r))
+            flush(f"    {name}: {e:.3e}")
+            assert e <= tol, name
+    F.adjoint_tile_set(p, form, 0)

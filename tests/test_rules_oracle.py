@@ -161,3 +161,37 @@ def test_fields_on_rule_reduce_to_element_constants(p):
     A1, b1, _ = oracle.integrate_fields(p, X[None], rep(D), rep(be), rep(c), rep(f), rule="symmetric")
     assert np.abs(A1[0] - A0).max() < 1e-14 * np.abs(A0).max()
     assert np.abs(b1[0] - b0).max() < 1e-14 * np.abs(b0).max()
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_adjoint_on_symmetric_rule_central_differences(p):
+    """The oracle's adjoint on the symmetric rule against central differences
+    of its forward integration on the same rule (h = 1e-6)."""
+    rng = np.random.default_rng(300 + p)
+    X = distorted_prism(300 + p, amp=0.3)
+    D, be, c, f = coeffs(300 + p)
+    n = oracle.nshp(p)
+    G = rng.normal(0, 1, (n, n)); g = rng.normal(0, 1, n)
+
+    def loss(Xv, Dv, bv, cv, fv):
+        A, b, _ = integrate_sym(p, Xv, Dv, bv, cv, fv)
+        return float(np.sum(G * A) + g @ b)
+
+    dX, dD, db, dc, df, Le = oracle.adjoint(p, X[None], D[None], be[None], np.array([c]), np.array([f]),
+                                            G[None], g[None], rule="symmetric")
+    assert abs(Le[0] - loss(X, D, be, c, f)) < 1e-12 * abs(Le[0])
+    h = 1e-6
+    fdX = np.zeros(18)
+    for k in range(18):
+        e = np.zeros(18); e[k] = h
+        fdX[k] = (loss(X + e.reshape(6, 3), D, be, c, f) - loss(X - e.reshape(6, 3), D, be, c, f)) / (2 * h)
+    assert np.abs(fdX.reshape(6, 3) - dX[0]).max() < 1e-6 * np.abs(dX).max()
+    fdD = np.array([[(loss(X, D + h * np.outer(np.eye(3)[i], np.eye(3)[j]), be, c, f)
+                      - loss(X, D - h * np.outer(np.eye(3)[i], np.eye(3)[j]), be, c, f)) / (2 * h)
+                     for j in range(3)] for i in range(3)])
+    assert np.abs(fdD - dD[0]).max() < 1e-6 * np.abs(dD).max()
+    fdb = np.array([(loss(X, D, be + h * np.eye(3)[k], c, f) - loss(X, D, be - h * np.eye(3)[k], c, f)) / (2 * h)
+                    for k in range(3)])
+    assert np.abs(fdb - db[0]).max() < 1e-6 * np.abs(db).max()
+    assert abs((loss(X, D, be, c + h, f) - loss(X, D, be, c - h, f)) / (2 * h) - dc[0]) < 1e-6 * abs(dc[0])
+    assert abs((loss(X, D, be, c, f + h) - loss(X, D, be, c, f - h)) / (2 * h) - df[0]) < 1e-6 * abs(df[0])
