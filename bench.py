@@ -131,7 +131,7 @@ def main():
     ap.add_argument("--mode", default="forward", choices=["forward", "fields", "hex", "tet", "adjoint", "mixed", "assemble"])
     ap.add_argument("--workload", default=None)
     ap.add_argument("--rule", default="collapsed", choices=["collapsed", "symmetric"],
-                    help="quadrature rule of the forward and fields modes")
+                    help="quadrature rule of the forward, fields and adjoint modes")
     ap.add_argument("--sc", action="store_true",
                     help="forward/fields: time the variant that computes shape functions at each point "
                          "(the paper's SC strategy) instead of autotuning over the table-reading ones; "
@@ -348,6 +348,8 @@ def bench_adjoint(args):
     forms = (args.forms or "fp64,fp32").split(",")
     w = meshgen.WORKLOADS[args.workload]
     p = w["p"]
+    rule = args.rule
+    orule = None if rule == "collapsed" else rule
     batch = meshgen.workload(args.workload)
     dev = torch.device("cuda:0")
     if costmodel.nshp(p) ** 2 * batch.ne > 2 ** 28:       # large G: drawn on the device
@@ -364,17 +366,29 @@ def bench_adjoint(args):
         dt = torch.float64 if form == "fp64" else torch.float32
         Gd, gd = (t(G).to(dt), t(g).to(dt)) if G is not None else (Gdev.to(dt), gdev.to(dt))
         out = None
-        tune_ms = None if args.no_tune else F.adjoint_autotune(*X, Gd, gd, p, form, reps=2)
+        tune_ms = None
+        if args.no_tune:
+            pass
+        elif rule == "collapsed":
+            tune_ms = F.adjoint_autotune(*X, Gd, gd, p, form, reps=2)
+        else:                       # time every block shape on this rule's kernels
+            best = None
+            for tt in range(F.adjoint_tile_count(p, form)):
+                F.adjoint_tile_set(p, form, tt)
+                ms_t, _, _ = timed(lambda: F.adjoint_raw(*X, Gd, gd, p, form, rule=rule), 2, 1)
+                best = min(best, (ms_t, tt)) if best else (ms_t, tt)
+            F.adjoint_tile_set(p, form, best[1])
+            tune_ms = best[0]
         block = F.adjoint_tile_describe(p, form, F.adjoint_tile_get(p, form))
 
         def step():
             nonlocal out
-            out = F.adjoint_raw(*X, Gd, gd, p, form)
+            out = F.adjoint_raw(*X, Gd, gd, p, form, rule=rule)
         ms, mn, wall = timed(step, args.steps, args.warmup)
         es = 8 if form == "fp64" else 4
         res[form] = dict(kernel_ms_mean=ms, kernel_ms_min=mn, ms_per_step=wall, elements_per_s=ne / (wall * 1e-3),
                          block=block, tune_ms=tune_ms,
-                         gflops=costmodel.f_dom(p) * ne / (ms * 1e-3) / 1e9,
+                         gflops=costmodel.f_dom(p, rule) * ne / (ms * 1e-3) / 1e9,
                          hbm_gbs_algorithmic=ne * costmodel.adjoint_bytes_per_element(p, es) / (ms * 1e-3) / 1e9,
                          grads=[o[torch.from_numpy(sample).to(dev)].cpu().numpy() for o in out])
         del Gd, gd
@@ -386,7 +400,7 @@ def bench_adjoint(args):
         si = torch.from_numpy(sample).to(dev)
         Gs = G[sample] if G is not None else Gdev[si].cpu().numpy()
         gs = g[sample] if g is not None else gdev[si].cpu().numpy()
-        ref = oracle.adjoint(p, sub.coords, sub.D, sub.beta, sub.c, sub.f, Gs, gs)
+        ref = oracle.adjoint(p, sub.coords, sub.D, sub.beta, sub.c, sub.f, Gs, gs, rule=orule)
         for form, r in res.items():
             r["rel_err"] = max(float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(r["grads"], ref[:5]))
         chunk = min(ne, max(16, 2048 >> (2 * max(0, p - 3))))
@@ -397,7 +411,7 @@ def bench_adjoint(args):
             Gm = G[lo:hi] if G is not None else Gdev[lo:hi].cpu().numpy()
             gm = g[lo:hi] if g is not None else gdev[lo:hi].cpu().numpy()
             t0 = time.perf_counter()
-            oracle.adjoint(p, part.coords, part.D, part.beta, part.c, part.f, Gm, gm)
+            oracle.adjoint(p, part.coords, part.D, part.beta, part.c, part.f, Gm, gm, rule=orule)
             spent += time.perf_counter() - t0
             m = hi
         cpu = {"value": m / spent, "unit": "elements/s", "cores": oracle.max_threads(), "kind": "oracle",
@@ -410,7 +424,8 @@ def bench_adjoint(args):
             "unit": "elements/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": h["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": forms[0], "data": "synthetic (seeded mesh, coefficients, G, g ~ N(0,1))",
-            "config": {"workload": args.workload, "p": p, "ne": ne, "form": forms[0]},
+            "config": {"workload": args.workload + ("+symmetric_rule" if orule else ""), "p": p, "ne": ne,
+                       "form": forms[0], "rule": rule},
             "roofline": {"bound": "mfma", "achieved": h["gflops"] / 1e3, "peak": peak, "unit": "TFLOP/s",
                          "frac": h["gflops"] / 1e3 / peak, "traffic": None},
             "cpu_baseline": cpu, "forms": fmt(res)}
