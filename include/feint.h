@@ -230,7 +230,9 @@ feint_status feint_tile_set(int p, feint_form form, int tile);
    "s" (table staged in LDS), "sa" (A operands staged), "p" (K loop
    software-pipelined) or "c" (shape functions computed at each point from
    their tensor-product factors, no table read: the paper's SC strategy,
-   Sec. 4), or "vL" (vector-ALU kernel, L lanes per element); "o2" marks a
+   Sec. 4), or "KxTNf" (contraction per triangle point: K zeta rows of
+   shape functions by TN column tiles per wave, FP64 and FP32 on prisms),
+   or "vL" (vector-ALU kernel, L lanes per element); "o2" marks a
    two-waves-per-SIMD register budget. */
 feint_status feint_tile_describe(int p, feint_form form, int tile, char *buf, size_t len);
 feint_status feint_autotune(const feint_elements *el, int p, feint_form form,

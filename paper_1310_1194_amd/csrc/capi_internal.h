@@ -12,7 +12,8 @@ namespace feint {
 struct DevTables {
     int p, rule, n, npad, nq, nqp, nkb, f16_shift;
     float bmax;
-    const double *qw, *gll, *B64, *BT64;
+    const double *qw, *gll, *B64, *BT64, *tau64, *lam;
+    const float *tau32;
     const float *B32, *BT32, *Bc32;
     const uint16_t *bf_hi, *bf_lo, *hf_hi, *hf_lo;
     const float *Ycf;

@@ -1,0 +1,190 @@
+// Forward kernel that contracts per triangle point (FP64, FP32 on 16x16x4
+// MFMA).  Both prism rules are products of nij triangle points and p+1 points
+// in zeta (q = m nij + ij), and the basis is a product phi_(k,t) =
+// T_t(xi1, xi2) L_k(zeta), so B_q[r][(k,t)] = tau_r(t, ij) lam_r(k, m) with
+// tau = (T, dT/dxi1, dT/dxi2, T) and lam = (L, L, L, dL/dzeta).  Then
+//   A[(k,t)][(k',t')] = sum_ij sum_r tau_r(t, ij) Z_k[(ij, r)][(k',t')],
+//   Z_k[(ij, r)][b]   = sum_m lam_r(k, m) Y_(ij,m)[r][b],
+//   Y_q[r][b]         = sum_s W_q[r][s] B_q[s][b]          (as in K4),
+// i.e. for each row block k the element matrix is a GEMM over K = (ij, r)
+// whose left operand is the triangle factor table and whose right operand Z_k
+// combines the p+1 zeta points of one triangle point.  Per triangle point and
+// column tile this issues (p+1) * ceil(ntri/16) MFMAs instead of the (p+1)^2 *
+// ceil(ntri/16) ... of the point-by-point kernel, for (p+1)^2 extra FMAs per
+// lane (forming Z), which the FP64 and FP32 matrix rates leave room for.
+//
+// Rows of A come in blocks (k, t-tile), columns in tiles (k', t'-tile) of 16
+// (ntri padded to a multiple of 16, padding multiplied by zero).  A wave owns
+// TMK row blocks k (all their t-tiles) and TN column tiles of one element.
+// The load vector rides in the spare padded column of the last t'-tile of
+// k' = 0: its Z_k carries sum_m lam_0(k,m) w det J f in row r = 0.
+#pragma once
+#include "fwd_kernels.h"
+
+namespace feint {
+
+template <int P, typename T, int TMK, int TN, int R = 0>
+struct KF {
+    static constexpr int N = c_nshp(P), NP = c_pad16(N);
+    static constexpr int NK = P + 1, NTRI = (P + 1) * (P + 2) / 2, TT = c_cdiv(NTRI, 16), TP = TT * 16;
+    static constexpr int NQ = c_nq_rule(P, R), NIJ = NQ / NK;
+    static constexpr int NCT = NK * TT;                       // column tiles (k', t'-tile)
+    static constexpr int BM = c_cdiv(NK, TMK), BN = c_cdiv(NCT, TN), NBLK = BM * BN;
+    static constexpr int EPI = 1;
+    static constexpr int CIJ = 64 / NK;                       // triangle points per chunk
+    static constexpr int LCT = TT - 1, LCL = NTRI - LCT * 16;  // load-vector column: tile (0, LCT), lane LCL
+    static_assert(NTRI % 16 != 0, "the load vector needs a spare padded column");
+    static_assert(NIJ * NK == NQ, "the rule must be a product in zeta");
+    typedef typename AccT<T>::type V4;
+
+    struct Slice {
+        T W[64][WROW<T>::value];      // chunk point (ij - ij0) * NK + m
+        double sf[64];
+    };
+    struct Smem { Slice w[4]; };
+
+    template <int TMV, int TNV>
+    __device__ static void body(const FwdParams &prm, int64_t slot, int blk, int bi, int bj, Slice &sl) {
+        const int lane = threadIdx.x & 63;
+        const int i16 = lane & 15, kg = lane >> 4;
+        const int k0 = bi * TMK, c0 = bj * TN;
+        const int64_t e = elem_of(prm, slot);
+        ElemIn E;
+        load_elem_fwd(prm, e, E);
+        const T *tau = sizeof(T) == 8 ? (const T *)(const void *)prm.tau64 : (const T *)(const void *)prm.tau32;
+        // row factors of the lane (r = kg) for its row blocks, in registers
+        T lr[TMV][NK];
+#pragma unroll
+        for (int k = 0; k < TMV; ++k)
+#pragma unroll
+            for (int m = 0; m < NK; ++m) lr[k][m] = (T)prm.lam[(kg * NK + k0 + k) * NK + m];
+        // the lane's columns (k', t'): B_(ij,m)[s][col] = tau_s(t', ij) lam_s(k', m); tau is zero
+        // beyond ntri, so padding columns contribute nothing without a mask
+        int kpc[TNV], tcol[TNV];
+        bool lcol[TNV];
+#pragma unroll
+        for (int tj = 0; tj < TNV; ++tj) {
+            const int ct = c0 + tj, kp = ct / TT, tt = ct % TT;
+            kpc[tj] = kp;
+            tcol[tj] = tt * 16 + i16;
+            lcol[tj] = kp == 0 && tt == LCT && i16 == LCL;
+        }
+        V4 acc[TMV][TT][TNV];
+#pragma unroll
+        for (int k = 0; k < TMV; ++k)
+#pragma unroll
+            for (int ti = 0; ti < TT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < TNV; ++tj) acc[k][ti][tj] = V4{0, 0, 0, 0};
+        // triangle factors of point ij: A fragments (rows t) and the columns' four factors
+        auto fetch = [&](int ij, T (&ta)[TT], T (&tb)[TNV][4]) {
+#pragma unroll
+            for (int ti = 0; ti < TT; ++ti) ta[ti] = tau[((size_t)ij * 4 + kg) * TP + ti * 16 + i16];
+#pragma unroll
+            for (int tj = 0; tj < TNV; ++tj)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) tb[tj][s] = tau[((size_t)ij * 4 + s) * TP + tcol[tj]];
+        };
+
+        for (int ij0 = 0; ij0 < NIJ; ij0 += CIJ) {
+            const int cij = NIJ - ij0 < CIJ ? NIJ - ij0 : CIJ;
+            if (lane < cij * NK) {
+                const int il = lane / NK, m = lane - il * NK;
+                const int q = m * NIJ + ij0 + il;
+                const double *qp = prm.qw + 4 * q;
+                double W[16], sf;
+                field_at(prm, e, qp[0], qp[1], qp[2], E);
+                const double det = point_block(E, qp[0], qp[1], qp[2], qp[3], W, sf);
+                if (!(det > 0.0) && prm.status) atomicOr(prm.status, 1u);
+#pragma unroll
+                for (int k = 0; k < 16; ++k) sl.W[lane][k] = (T)W[k];
+                sl.sf[lane] = sf;
+                if (prm.xq && blk == 0) {
+                    double x[3];
+                    prism_map(E.X, qp[0], qp[1], qp[2], x);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) prm.xq[(e * NQ + q) * 3 + d] = x[d];
+                }
+            }
+            wave_sync();
+            T ta[TT], tb[TNV][4];
+            fetch(ij0, ta, tb);
+            for (int il = 0; il < cij; ++il) {
+                T tan[TT], tbn[TNV][4];
+                fetch(ij0 + (il + 1 < cij ? il + 1 : il), tan, tbn);
+                // the lane's row r = kg of W at the p+1 points of this triangle point
+                T w[NK][4], sfm[NK];
+#pragma unroll
+                for (int m = 0; m < NK; ++m) {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) w[m][s] = sl.W[il * NK + m][4 * kg + s];
+                    sfm[m] = kg == 0 ? (T)sl.sf[il * NK + m] : (T)0;
+                }
+#pragma unroll
+                for (int tj = 0; tj < TNV; ++tj) {
+                    const double *lc = prm.lam + (size_t)kpc[tj] * NK;     // lam_s(k', m) at [(s NK + k') NK + m]
+                    T y[NK];
+#pragma unroll
+                    for (int m = 0; m < NK; ++m) {
+                        T v = (T)0;
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) v += w[m][s] * ((T)lc[(size_t)s * NK * NK + m] * tb[tj][s]);
+                        y[m] = lcol[tj] ? sfm[m] : v;     // the load-vector column carries w det J f (r = 0)
+                    }
+#pragma unroll
+                    for (int k = 0; k < TMV; ++k) {
+                        T z = (T)0;
+#pragma unroll
+                        for (int m = 0; m < NK; ++m) z += lr[k][m] * y[m];
+#pragma unroll
+                        for (int ti = 0; ti < TT; ++ti) acc[k][ti][tj] = mfma4(ta[ti], z, acc[k][ti][tj]);
+                    }
+                }
+#pragma unroll
+                for (int ti = 0; ti < TT; ++ti) ta[ti] = tan[ti];
+#pragma unroll
+                for (int tj = 0; tj < TNV; ++tj)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) tb[tj][s] = tbn[tj][s];
+            }
+            wave_sync();
+        }
+        T *Aout = (T *)prm.A + offA_of(prm, e, N);
+        T *bout = (T *)prm.b + offb_of(prm, e, N);
+#pragma unroll
+        for (int k = 0; k < TMV; ++k)
+#pragma unroll
+            for (int ti = 0; ti < TT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < TNV; ++tj)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int tr = ti * 16 + acc_row<T>(lane, r);
+                        if (tr >= NTRI) continue;
+                        const int row = (k0 + k) * NTRI + tr;
+                        if (lcol[tj])
+                            bout[row] = acc[k][ti][tj][r];
+                        else if (tcol[tj] < NTRI)
+                            Aout[(size_t)row * N + kpc[tj] * NTRI + tcol[tj]] = acc[k][ti][tj][r];
+                    }
+    }
+
+    // Row blocks (TMK values of k) and column tiles (TN) of the last block
+    // are compile-time counts, so the loops carry no bounds tests.
+    __device__ static void run_slice(const FwdParams &prm, int64_t slot, int blk, Slice &sl) {
+        const int bi = blk / BN, bj = blk % BN;
+        constexpr int TML = NK - (BM - 1) * TMK, TNL = NCT - (BN - 1) * TN;
+        if (bi == BM - 1) {
+            if (bj == BN - 1) body<TML, TNL>(prm, slot, blk, bi, bj, sl);
+            else body<TML, TN>(prm, slot, blk, bi, bj, sl);
+        } else {
+            if (bj == BN - 1) body<TMK, TNL>(prm, slot, blk, bi, bj, sl);
+            else body<TMK, TN>(prm, slot, blk, bi, bj, sl);
+        }
+    }
+    __device__ static void run(const FwdParams &prm, int64_t slot, int blk, int wave, Smem &sm) {
+        run_slice(prm, slot, blk, sm.w[wave]);
+    }
+};
+
+}  // namespace feint

@@ -6,6 +6,7 @@
 #include "fwd_valu.h"
 #include "fwd_pipe.h"
 #include "fwd_sc.h"
+#include "fwd_fact.h"
 
 namespace feint {
 
@@ -65,6 +66,11 @@ int64_t items_of(int64_t ne) { return items_for<KER>(ne); }
 // Vector-ALU kernel on hexahedra and tetrahedra (low degree).
 #define FEINT_KV_G(P, T, LPE, W, GEO) \
     FwdVariant{0, LPE, 3, W, &launch_direct<KV<P, T, LPE, 0, GEO>, W>, &items_of<KV<P, T, LPE, 0, GEO>>}
+
+// F: contraction per triangle point (tensor factors of B, staged = 6):
+// TMK row blocks k and TN column tiles per wave.
+#define FEINT_KF_R(P, T, TMK, TN, W, R) \
+    FwdVariant{TMK, TN, 6, W, &launch_direct<KF<P, T, TMK, TN, R>, W>, &items_of<KF<P, T, TMK, TN, R>>}
 
 #define FEINT_K4U(P, T, TM, TN, W) FEINT_K4U_R(P, T, TM, TN, W, 0)
 #define FEINT_KSC(P, T, TM, TN, W) FEINT_KSC_R(P, T, TM, TN, W, 0)

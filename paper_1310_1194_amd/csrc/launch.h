@@ -13,6 +13,9 @@ struct FwdParams {
     uint32_t *status;
     const double *qw;        // [nqp][4]
     const double *gll;       // [2][p+1] Gauss-Lobatto nodes and Lagrange denominators
+    const double *tau64;     // prisms: [nij][4][tpad] triangle factors of B (T, dT/dxi1, dT/dxi2, T)
+    const float *tau32;
+    const double *lam;       // prisms: [4][p+1][p+1] line factors (L, L, L, dL/dzeta) at the zeta points
     const double *B64;       // [nqp][4][npad]
     const float *B32;        // [nqp][4][npad]
     const float *Bc32;       // [nqp][npad][4]
@@ -36,7 +39,8 @@ struct FwdVariant {
     int tm, tn;
     int staged;          // 1: the table is staged through LDS per workgroup (2: A operands only),
                          // 3: vector-ALU kernel, 4: software-pipelined split kernel,
-                         // 5: shape functions computed at each point (no B table)
+                         // 5: shape functions computed at each point (no B table),
+                         // 6: contraction per triangle point (tensor factors of B)
     int minw;            // waves per SIMD the register allocation allows
     void (*launch)(const FwdParams &, hipStream_t);
     int64_t (*items)(int64_t ne);   // work items (waves) of a launch over ne elements

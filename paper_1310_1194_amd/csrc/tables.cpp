@@ -166,13 +166,15 @@ ModalBasis make_modal(int p) {
     return mb;
 }
 
-void eval_modal(const ModalBasis &mb, const double *xi, double *phi, double *dphi) {
+// The tensor factors of the prism basis phi_(k,t) = T_t(xi1, xi2) L_k(zeta):
+// T, dT/dxi1, dT/dxi2 (ntri each) and L, dL/dzeta (p+1 each).
+void eval_factors(const ModalBasis &mb, double x1, double x2, double ze, long double *psi, long double *d1,
+                  long double *d2, long double *l, long double *dl) {
     const int p = mb.p, nt = mb.ntri;
     long double Pa[kMaxP + 1], dPa[kMaxP + 1], Pb[kMaxP + 1], dPb[kMaxP + 1], Pz[kMaxP + 1], dPz[kMaxP + 1];
-    legendre_all(p, 2.0L * xi[0] - 1, Pa, dPa);
-    legendre_all(p, 2.0L * xi[1] - 1, Pb, dPb);
-    legendre_all(p, (long double)xi[2], Pz, dPz);
-    long double psi[64], d1[64], d2[64], l[kMaxP + 1], dl[kMaxP + 1];
+    legendre_all(p, 2.0L * x1 - 1, Pa, dPa);
+    legendre_all(p, 2.0L * x2 - 1, Pb, dPb);
+    legendre_all(p, (long double)ze, Pz, dPz);
     for (int t = 0; t < nt; ++t) {
         long double v = 0, g1 = 0, g2 = 0;
         for (int m = 0; m < nt; ++m) {
@@ -191,6 +193,12 @@ void eval_modal(const ModalBasis &mb, const double *xi, double *phi, double *dph
         }
         l[k] = v; dl[k] = g;
     }
+}
+
+void eval_modal(const ModalBasis &mb, const double *xi, double *phi, double *dphi) {
+    const int p = mb.p, nt = mb.ntri;
+    long double psi[64], d1[64], d2[64], l[kMaxP + 1], dl[kMaxP + 1];
+    eval_factors(mb, xi[0], xi[1], xi[2], psi, d1, d2, l, dl);
     for (int k = 0; k <= p; ++k)
         for (int t = 0; t < nt; ++t) {
             int a = k * nt + t;
@@ -483,6 +491,36 @@ HostTables build_tables(int p, int rule) {
         }
     }
     derive_layouts(T);
+    // tensor factors for the kernels that contract per triangle point: both
+    // prism rules are products of nij triangle points and p+1 points in zeta
+    // with q = m nij + ij, so B_q[r][(k,t)] = tau_r(t, ij) lam_r(k, m) with
+    // tau = (T, dT/dxi1, dT/dxi2, T) and lam = (L, L, L, dL/dzeta)
+    const int nk = p + 1, nt = ntri_of(p);
+    T.nk = nk;
+    T.nij = T.nq / nk;
+    T.tpad = pad16(nt);
+    T.tau64.assign((size_t)T.nij * 4 * T.tpad, 0.0);
+    T.lam.assign((size_t)4 * nk * nk, 0.0);
+    {
+        long double psi[64], d1[64], d2[64], l[kMaxP + 1], dl[kMaxP + 1];
+        for (int ij = 0; ij < T.nij; ++ij) {
+            eval_factors(mb, T.qw[4 * ij + 0], T.qw[4 * ij + 1], 0.0, psi, d1, d2, l, dl);
+            for (int t = 0; t < nt; ++t) {
+                T.tau64[((size_t)ij * 4 + 0) * T.tpad + t] = (double)psi[t];
+                T.tau64[((size_t)ij * 4 + 1) * T.tpad + t] = (double)d1[t];
+                T.tau64[((size_t)ij * 4 + 2) * T.tpad + t] = (double)d2[t];
+                T.tau64[((size_t)ij * 4 + 3) * T.tpad + t] = (double)psi[t];
+            }
+        }
+        for (int m = 0; m < nk; ++m) {
+            eval_factors(mb, 1.0 / 3.0, 1.0 / 3.0, T.qw[4 * ((size_t)m * T.nij) + 2], psi, d1, d2, l, dl);
+            for (int k = 0; k < nk; ++k) {
+                for (int r = 0; r < 3; ++r) T.lam[((size_t)r * nk + k) * nk + m] = (double)l[k];
+                T.lam[((size_t)3 * nk + k) * nk + m] = (double)dl[k];
+            }
+        }
+    }
+    T.tau32.assign(T.tau64.begin(), T.tau64.end());
     return T;
 }
 

@@ -30,6 +30,11 @@ struct HostTables {
     int f16_shift = 0;               // fp16 tables hold B * 2^f16_shift
     std::vector<double> qw;          // [nqp][4]  xi1, xi2, zeta, w  (padded points: w = 0)
     std::vector<double> gll;         // [2][p+1]  Gauss-Lobatto nodes z_k and 1 / prod_{m != k} (z_k - z_m)
+    // prisms: tensor factors of B (q = m nij + ij, a = k ntri + t):
+    int nk = 0, nij = 0, tpad = 0;
+    std::vector<double> tau64;       // [nij][4][tpad]  T, dT/dxi1, dT/dxi2, T at triangle point ij
+    std::vector<float> tau32;
+    std::vector<double> lam;         // [4][nk][nk]     L_k, L_k, L_k, dL_k/dzeta at zeta point m
     std::vector<double> B64;         // [nqp][4][npad]  rows: phi, d/dxi1, d/dxi2, d/dzeta
     std::vector<float> B32;          // same, rounded to FP32
     std::vector<double> BT64;        // [npad][nqp*4]  transpose of B64 (shape-function major)
