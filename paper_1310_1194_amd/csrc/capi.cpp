@@ -54,11 +54,11 @@ feint_status prepare_tables(int p, int rule, int type) {
     if (g_tables.count(key)) return FEINT_OK;
     HostTables H = type == 2 ? build_tet_tables(p) : type == 1 ? build_hex_tables(p) : build_tables(p, rule);
     auto align = [](size_t x) { return (x + 255) / 256 * 256; };
-    const size_t s_tau = align(H.tau64.size() * 8), s_tau32 = align(H.tau32.size() * 4), s_lam = align(H.lam.size() * 8);
+    const size_t s_tau = align(H.tau64.size() * 8), s_tau32 = align(H.tau32.size() * 4), s_lam = align(H.lam.size() * 8), s_lam32 = align(H.lam32.size() * 4);
     const size_t s_qw = align(H.qw.size() * 8), s_gll = align(H.gll.size() * 8), s_b64 = align(H.B64.size() * 8), s_b32 = align(H.B32.size() * 4);
     const size_t s_sp = align(H.bf_hi.size() * 2);
     const size_t s_ycf = align(H.Ycf.size() * 4);
-    const size_t total = s_tau + s_tau32 + s_lam + s_qw + s_gll + 2 * s_b64 + 3 * s_b32 + 4 * s_sp + s_ycf;
+    const size_t total = s_tau + s_tau32 + s_lam + s_lam32 + s_qw + s_gll + 2 * s_b64 + 3 * s_b32 + 4 * s_sp + s_ycf;
     char *base = nullptr;
     e = hipMalloc((void **)&base, total);
     if (e != hipSuccess) { set_error("hipMalloc(tables)", e); return FEINT_ERR_HIP; }
@@ -80,6 +80,7 @@ feint_status prepare_tables(int p, int rule, int type) {
     T->gll = (const double *)put(H.gll.data(), H.gll.size() * 8, s_gll);
     T->tau64 = (const double *)put(H.tau64.data(), H.tau64.size() * 8, s_tau);
     T->tau32 = (const float *)put(H.tau32.data(), H.tau32.size() * 4, s_tau32);
+    T->lam32 = (const float *)put(H.lam32.data(), H.lam32.size() * 4, s_lam32);
     T->lam = (const double *)put(H.lam.data(), H.lam.size() * 8, s_lam);
     T->B64 = (const double *)put(H.B64.data(), H.B64.size() * 8, s_b64);
     T->B32 = (const float *)put(H.B32.data(), H.B32.size() * 4, s_b32);
@@ -133,7 +134,7 @@ void fill_fwd_params(FwdParams &prm, const feint_elements *el, int form, const D
     std::memset(&prm, 0, sizeof prm);
     prm.coords = el->coords; prm.D = el->D; prm.beta = el->beta; prm.c = el->c; prm.f = el->f;
     prm.ne = el->ne;
-    prm.qw = T->qw; prm.gll = T->gll; prm.tau64 = T->tau64; prm.tau32 = T->tau32; prm.lam = T->lam;
+    prm.qw = T->qw; prm.gll = T->gll; prm.tau64 = T->tau64; prm.tau32 = T->tau32; prm.lam = T->lam; prm.lam32 = T->lam32;
     prm.B64 = T->B64; prm.B32 = T->B32; prm.Bc32 = T->Bc32; prm.Ycf = T->Ycf;
     prm.Bhi = form == FEINT_FP16X3 ? T->hf_hi : T->bf_hi;
     prm.Blo = form == FEINT_FP16X3 ? T->hf_lo : T->bf_lo;

@@ -14,6 +14,7 @@ struct DevTables {
     float bmax;
     const double *qw, *gll, *B64, *BT64, *tau64, *lam;
     const float *tau32;
+    const float *lam32;
     const float *B32, *BT32, *Bc32;
     const uint16_t *bf_hi, *bf_lo, *hf_hi, *hf_lo;
     const float *Ycf;

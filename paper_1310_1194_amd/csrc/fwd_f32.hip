@@ -1,6 +1,6 @@
 // Forward kernels, FP32 form: compiled variants per degree (the first is the default until the
-// autotuner picks another): vector-ALU kernels at low degree, v_mfma_f32_16x16x4_f32 tiles point by point
-// at p = 3, and from p = 4 the contraction per triangle point (KF), which is the fastest there.
+// autotuner picks another): vector-ALU kernels at low degree, v_mfma_f32_16x16x4_f32 tiles point by point,
+// and from p = 3 the contraction per triangle point (KF), which is the fastest there.
 #include "fwd_registry.h"
 
 namespace feint {
@@ -16,31 +16,32 @@ const FwdVariant v2[] = {
     FEINT_K4S(2, float, 2, 2, 8, 1),
     FEINT_KSC(2, float, 2, 2, 1), FEINT_KF_R(2, float, 3, 3, 2, 0)};
 const FwdVariant v3[] = {
+    FEINT_KF_R(3, float, 4, 4, 2, 0),
     FEINT_K4S(3, float, 3, 3, 8, 1),
     FEINT_K4S(3, float, 3, 1, 8, 2),
     FEINT_KV(3, float, 40, 2),
-    FEINT_KSC(3, float, 3, 3, 1), FEINT_KF_R(3, float, 4, 4, 1, 0)};
+    FEINT_KSC(3, float, 3, 3, 1)};
 const FwdVariant v4[] = {
-    FEINT_KF_R(4, float, 5, 2, 1, 0),
+    FEINT_KF_R(4, float, 5, 3, 1, 0),
     FEINT_KF_R(4, float, 5, 5, 1, 0),
     FEINT_K4S(4, float, 5, 5, 8, 1),
     FEINT_K4S(4, float, 5, 3, 8, 2),
     FEINT_K4U(4, float, 5, 5, 1),
     FEINT_KSC(4, float, 5, 5, 1)};
 const FwdVariant v5[] = {
-    FEINT_KF_R(5, float, 6, 2, 1, 0),
+    FEINT_KF_R(5, float, 6, 3, 1, 0),
     FEINT_K4U(5, float, 8, 8, 1),
     FEINT_K4S(5, float, 8, 2, 8, 2),
     FEINT_K4U(5, float, 8, 4, 1),
     FEINT_KSC(5, float, 8, 4, 1)};
 const FwdVariant v6[] = {
-    FEINT_KF_R(6, float, 7, 2, 1, 0),
+    FEINT_KF_R(6, float, 7, 4, 1, 0),
+    FEINT_KF_R(6, float, 7, 3, 1, 0),
     FEINT_K4S(6, float, 13, 2, 8, 1),
     FEINT_K4U(6, float, 13, 4, 1),
-    FEINT_K4U(6, float, 13, 3, 2),
     FEINT_KSC(6, float, 13, 2, 1)};
 const FwdVariant v7[] = {
-    FEINT_KF_R(7, float, 8, 1, 1, 0),
+    FEINT_KF_R(7, float, 8, 2, 1, 0),
     FEINT_K4U(7, float, 9, 6, 1),
     FEINT_K4U(7, float, 6, 3, 1),
     FEINT_KSC(7, float, 9, 3, 1)};

@@ -1,6 +1,6 @@
 // Forward kernels, FP64 form: compiled variants per degree (the first is the default until the
-// autotuner picks another): vector-ALU kernels at low degree, v_mfma_f64_16x16x4_f64 tiles point by point
-// at p = 3, and from p = 4 the contraction per triangle point (KF), which is the fastest there.
+// autotuner picks another): vector-ALU kernels at low degree, v_mfma_f64_16x16x4_f64 tiles point by point,
+// and from p = 3 the contraction per triangle point (KF), which is the fastest there.
 #include "fwd_registry.h"
 
 namespace feint {
@@ -17,32 +17,34 @@ const FwdVariant v2[] = {
     FEINT_K4S(2, double, 2, 1, 8, 2),
     FEINT_KSC(2, double, 2, 2, 1), FEINT_KF_R(2, double, 3, 3, 2, 0)};
 const FwdVariant v3[] = {
+    FEINT_KF_R(3, double, 4, 2, 1, 0),
     FEINT_K4S(3, double, 3, 3, 8, 1),
     FEINT_K4S(3, double, 3, 1, 8, 2),
     FEINT_KV(3, double, 40, 2),
-    FEINT_KSC(3, double, 3, 3, 1), FEINT_KF_R(3, double, 4, 4, 1, 0)};
+    FEINT_KF_R(3, double, 4, 4, 1, 0),
+    FEINT_KSC(3, double, 3, 3, 1)};
 const FwdVariant v4[] = {
-    FEINT_KF_R(4, double, 5, 2, 1, 0),
+    FEINT_KF_R(4, double, 5, 5, 1, 0),
+    FEINT_KF_R(4, double, 5, 3, 1, 0),
     FEINT_KF_R(4, double, 5, 1, 1, 0),
     FEINT_K4S(4, double, 5, 3, 8, 2),
     FEINT_K4U(4, double, 5, 1, 2),
-    FEINT_K4S(4, double, 5, 2, 8, 2),
     FEINT_KSC(4, double, 5, 3, 1)};
 const FwdVariant v5[] = {
-    FEINT_KF_R(5, double, 6, 1, 1, 0),
     FEINT_KF_R(5, double, 3, 2, 1, 0),
+    FEINT_KF_R(5, double, 6, 1, 1, 0),
     FEINT_K4U(5, double, 8, 1, 2),
     FEINT_K4S(5, double, 8, 1, 4, 2),
     FEINT_KSC(5, double, 8, 2, 1)};
 const FwdVariant v6[] = {
-    FEINT_KF_R(6, double, 4, 1, 1, 0),
-    FEINT_KF_R(6, double, 3, 2, 1, 0),
+    FEINT_KF_R(6, double, 7, 1, 1, 0),
+    FEINT_KF_R(6, double, 4, 2, 1, 0),
     FEINT_K4U(6, double, 13, 1, 2),
     FEINT_K4S(6, double, 13, 1, 4, 1),
     FEINT_KSC(6, double, 13, 1, 1)};
 const FwdVariant v7[] = {
+    FEINT_KF_R(7, double, 4, 1, 1, 0),
     FEINT_KF_R(7, double, 3, 1, 1, 0),
-    FEINT_KF_R(7, double, 2, 1, 1, 0),
     FEINT_K4U(7, double, 9, 2, 1),
     FEINT_K4U(7, double, 6, 2, 1),
     FEINT_KSC(7, double, 6, 2, 1)};

@@ -9,13 +9,16 @@
 // i.e. for each row block k the element matrix is a GEMM over K = (ij, r)
 // whose left operand is the triangle factor table and whose right operand Z_k
 // combines the p+1 zeta points of one triangle point.  Per triangle point and
-// column tile this issues (p+1) * ceil(ntri/16) MFMAs instead of the (p+1)^2 *
-// ceil(ntri/16) ... of the point-by-point kernel, for (p+1)^2 extra FMAs per
-// lane (forming Z), which the FP64 and FP32 matrix rates leave room for.
+// column tile this issues (p+1) * ceil(ntri/16) MFMAs where the point-by-point
+// kernel issues (p+1)^2 * ceil(ntri/16), for O((p+1)^2) extra FMAs per lane
+// (forming Z), which the FP64 and FP32 matrix rates leave room for.
 //
 // Rows of A come in blocks (k, t-tile), columns in tiles (k', t'-tile) of 16
 // (ntri padded to a multiple of 16, padding multiplied by zero).  A wave owns
-// TMK row blocks k (all their t-tiles) and TN column tiles of one element.
+// TMK row blocks k (all their t-tiles) and TN column tiles k' of one t'-tile
+// of one element.  Since lam_0 = lam_1 = lam_2 = L, the lane's column needs
+// only u = sum_{s<3} W[r][s] tau_s(t') and v = W[r][3] tau_3(t') per point,
+// shared by its TN column tiles: Y[r][(k',t')] = L_k'(zeta_m) u + L'_k'(zeta_m) v.
 // The load vector rides in the spare padded column of the last t'-tile of
 // k' = 0: its Z_k carries sum_m lam_0(k,m) w det J f in row r = 0.
 #pragma once
@@ -28,13 +31,13 @@ struct KF {
     static constexpr int N = c_nshp(P), NP = c_pad16(N);
     static constexpr int NK = P + 1, NTRI = (P + 1) * (P + 2) / 2, TT = c_cdiv(NTRI, 16), TP = TT * 16;
     static constexpr int NQ = c_nq_rule(P, R), NIJ = NQ / NK;
-    static constexpr int NCT = NK * TT;                       // column tiles (k', t'-tile)
-    static constexpr int BM = c_cdiv(NK, TMK), BN = c_cdiv(NCT, TN), NBLK = BM * BN;
+    static constexpr int BM = c_cdiv(NK, TMK), BK = c_cdiv(NK, TN), BN = TT * BK, NBLK = BM * BN;
     static constexpr int EPI = 1;
     static constexpr int CIJ = 64 / NK;                       // triangle points per chunk
     static constexpr int LCT = TT - 1, LCL = NTRI - LCT * 16;  // load-vector column: tile (0, LCT), lane LCL
     static_assert(NTRI % 16 != 0, "the load vector needs a spare padded column");
     static_assert(NIJ * NK == NQ, "the rule must be a product in zeta");
+    static_assert(TN <= NK && TMK <= NK, "tile counts beyond the zeta factor");
     typedef typename AccT<T>::type V4;
 
     struct Slice {
@@ -47,28 +50,27 @@ struct KF {
     __device__ static void body(const FwdParams &prm, int64_t slot, int blk, int bi, int bj, Slice &sl) {
         const int lane = threadIdx.x & 63;
         const int i16 = lane & 15, kg = lane >> 4;
-        const int k0 = bi * TMK, c0 = bj * TN;
+        const int k0 = bi * TMK, tt = bj / BK, kp0 = (bj - tt * BK) * TN;
         const int64_t e = elem_of(prm, slot);
         ElemIn E;
         load_elem_fwd(prm, e, E);
         const T *tau = sizeof(T) == 8 ? (const T *)(const void *)prm.tau64 : (const T *)(const void *)prm.tau32;
+        const T *lam = sizeof(T) == 8 ? (const T *)(const void *)prm.lam : (const T *)(const void *)prm.lam32;
         // row factors of the lane (r = kg) for its row blocks, in registers
         T lr[TMV][NK];
 #pragma unroll
         for (int k = 0; k < TMV; ++k)
 #pragma unroll
-            for (int m = 0; m < NK; ++m) lr[k][m] = (T)prm.lam[(kg * NK + k0 + k) * NK + m];
-        // the lane's columns (k', t'): B_(ij,m)[s][col] = tau_s(t', ij) lam_s(k', m); tau is zero
-        // beyond ntri, so padding columns contribute nothing without a mask
-        int kpc[TNV], tcol[TNV];
-        bool lcol[TNV];
-#pragma unroll
-        for (int tj = 0; tj < TNV; ++tj) {
-            const int ct = c0 + tj, kp = ct / TT, tt = ct % TT;
-            kpc[tj] = kp;
-            tcol[tj] = tt * 16 + i16;
-            lcol[tj] = kp == 0 && tt == LCT && i16 == LCL;
-        }
+            for (int m = 0; m < NK; ++m) lr[k][m] = lam[(kg * NK + k0 + k) * NK + m];
+        // the lane's column t' (tau is zero beyond ntri, so padding columns contribute
+        // nothing without a mask) and the column factors L_k', L'_k' of its tiles
+        const int tcol = tt * 16 + i16;
+        const bool lcol = kp0 == 0 && tt == LCT && i16 == LCL;
+        // The column factors are the same for the whole wave and the table is never written
+        // while kernels run: reading them through the constant address space lets them be
+        // scalar loads into SGPRs instead of per-lane loads in the inner loop.
+        typedef const __attribute__((address_space(4))) T CT;
+        const CT *lv = (const CT *)(lam + (size_t)kp0 * NK), *ld = (const CT *)(lam + (size_t)(3 * NK + kp0) * NK);
         V4 acc[TMV][TT][TNV];
 #pragma unroll
         for (int k = 0; k < TMV; ++k)
@@ -76,14 +78,12 @@ struct KF {
             for (int ti = 0; ti < TT; ++ti)
 #pragma unroll
                 for (int tj = 0; tj < TNV; ++tj) acc[k][ti][tj] = V4{0, 0, 0, 0};
-        // triangle factors of point ij: A fragments (rows t) and the columns' four factors
-        auto fetch = [&](int ij, T (&ta)[TT], T (&tb)[TNV][4]) {
+        // triangle factors of point ij: A fragments (rows t) and the column's four factors
+        auto fetch = [&](int ij, T (&ta)[TT], T (&tb)[4]) {
 #pragma unroll
             for (int ti = 0; ti < TT; ++ti) ta[ti] = tau[((size_t)ij * 4 + kg) * TP + ti * 16 + i16];
 #pragma unroll
-            for (int tj = 0; tj < TNV; ++tj)
-#pragma unroll
-                for (int s = 0; s < 4; ++s) tb[tj][s] = tau[((size_t)ij * 4 + s) * TP + tcol[tj]];
+            for (int s = 0; s < 4; ++s) tb[s] = tau[((size_t)ij * 4 + s) * TP + tcol];
         };
 
         for (int ij0 = 0; ij0 < NIJ; ij0 += CIJ) {
@@ -107,29 +107,31 @@ struct KF {
                 }
             }
             wave_sync();
-            T ta[TT], tb[TNV][4];
+            T ta[TT], tb[4];
             fetch(ij0, ta, tb);
             for (int il = 0; il < cij; ++il) {
-                T tan[TT], tbn[TNV][4];
+                T tan[TT], tbn[4];
                 fetch(ij0 + (il + 1 < cij ? il + 1 : il), tan, tbn);
-                // the lane's row r = kg of W at the p+1 points of this triangle point
-                T w[NK][4], sfm[NK];
+                // keep the next point's loads at the top of the iteration, in flight under
+                // its arithmetic (the scheduler would otherwise sink them to the end)
+                __builtin_amdgcn_sched_barrier(0);
+                // the lane's row r = kg of W at the p+1 points of this triangle point, folded with
+                // the column's factors
+                T u[NK], v[NK], sfm[NK];
 #pragma unroll
                 for (int m = 0; m < NK; ++m) {
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) w[m][s] = sl.W[il * NK + m][4 * kg + s];
+                    const T *wr = &sl.W[il * NK + m][4 * kg];
+                    u[m] = wr[0] * tb[0] + wr[1] * tb[1] + wr[2] * tb[2];
+                    v[m] = wr[3] * tb[3];
                     sfm[m] = kg == 0 ? (T)sl.sf[il * NK + m] : (T)0;
                 }
 #pragma unroll
                 for (int tj = 0; tj < TNV; ++tj) {
-                    const double *lc = prm.lam + (size_t)kpc[tj] * NK;     // lam_s(k', m) at [(s NK + k') NK + m]
                     T y[NK];
 #pragma unroll
                     for (int m = 0; m < NK; ++m) {
-                        T v = (T)0;
-#pragma unroll
-                        for (int s = 0; s < 4; ++s) v += w[m][s] * ((T)lc[(size_t)s * NK * NK + m] * tb[tj][s]);
-                        y[m] = lcol[tj] ? sfm[m] : v;     // the load-vector column carries w det J f (r = 0)
+                        const T yv = lv[tj * NK + m] * u[m] + ld[tj * NK + m] * v[m];
+                        y[m] = (tj == 0 && lcol) ? sfm[m] : yv;   // the load-vector column carries w det J f
                     }
 #pragma unroll
                     for (int k = 0; k < TMV; ++k) {
@@ -143,9 +145,7 @@ struct KF {
 #pragma unroll
                 for (int ti = 0; ti < TT; ++ti) ta[ti] = tan[ti];
 #pragma unroll
-                for (int tj = 0; tj < TNV; ++tj)
-#pragma unroll
-                    for (int s = 0; s < 4; ++s) tb[tj][s] = tbn[tj][s];
+                for (int s = 0; s < 4; ++s) tb[s] = tbn[s];
             }
             wave_sync();
         }
@@ -162,23 +162,24 @@ struct KF {
                         const int tr = ti * 16 + acc_row<T>(lane, r);
                         if (tr >= NTRI) continue;
                         const int row = (k0 + k) * NTRI + tr;
-                        if (lcol[tj])
+                        if (tj == 0 && lcol)
                             bout[row] = acc[k][ti][tj][r];
-                        else if (tcol[tj] < NTRI)
-                            Aout[(size_t)row * N + kpc[tj] * NTRI + tcol[tj]] = acc[k][ti][tj][r];
+                        else if (tcol < NTRI)
+                            Aout[(size_t)row * N + (kp0 + tj) * NTRI + tcol] = acc[k][ti][tj][r];
                     }
     }
 
-    // Row blocks (TMK values of k) and column tiles (TN) of the last block
-    // are compile-time counts, so the loops carry no bounds tests.
+    // Row blocks (TMK values of k) and column tiles (TN values of k') of the
+    // last blocks are compile-time counts, so the loops carry no bounds tests.
     __device__ static void run_slice(const FwdParams &prm, int64_t slot, int blk, Slice &sl) {
         const int bi = blk / BN, bj = blk % BN;
-        constexpr int TML = NK - (BM - 1) * TMK, TNL = NCT - (BN - 1) * TN;
+        constexpr int TML = NK - (BM - 1) * TMK, TNL = NK - (BK - 1) * TN;
+        const bool lastn = bj % BK == BK - 1;
         if (bi == BM - 1) {
-            if (bj == BN - 1) body<TML, TNL>(prm, slot, blk, bi, bj, sl);
+            if (lastn) body<TML, TNL>(prm, slot, blk, bi, bj, sl);
             else body<TML, TN>(prm, slot, blk, bi, bj, sl);
         } else {
-            if (bj == BN - 1) body<TMK, TNL>(prm, slot, blk, bi, bj, sl);
+            if (lastn) body<TMK, TNL>(prm, slot, blk, bi, bj, sl);
             else body<TMK, TN>(prm, slot, blk, bi, bj, sl);
         }
     }

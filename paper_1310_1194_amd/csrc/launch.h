@@ -15,6 +15,7 @@ struct FwdParams {
     const double *gll;       // [2][p+1] Gauss-Lobatto nodes and Lagrange denominators
     const double *tau64;     // prisms: [nij][4][tpad] triangle factors of B (T, dT/dxi1, dT/dxi2, T)
     const float *tau32;
+    const float *lam32;
     const double *lam;       // prisms: [4][p+1][p+1] line factors (L, L, L, dL/dzeta) at the zeta points
     const double *B64;       // [nqp][4][npad]
     const float *B32;        // [nqp][4][npad]

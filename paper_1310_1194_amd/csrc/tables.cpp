@@ -521,6 +521,7 @@ HostTables build_tables(int p, int rule) {
         }
     }
     T.tau32.assign(T.tau64.begin(), T.tau64.end());
+    T.lam32.assign(T.lam.begin(), T.lam.end());
     return T;
 }
 

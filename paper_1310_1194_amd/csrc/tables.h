@@ -35,6 +35,7 @@ struct HostTables {
     std::vector<double> tau64;       // [nij][4][tpad]  T, dT/dxi1, dT/dxi2, T at triangle point ij
     std::vector<float> tau32;
     std::vector<double> lam;         // [4][nk][nk]     L_k, L_k, L_k, dL_k/dzeta at zeta point m
+    std::vector<float> lam32;        // lam rounded to FP32
     std::vector<double> B64;         // [nqp][4][npad]  rows: phi, d/dxi1, d/dxi2, d/dzeta
     std::vector<float> B32;          // same, rounded to FP32
     std::vector<double> BT64;        // [npad][nqp*4]  transpose of B64 (shape-function major)
