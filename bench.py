@@ -258,8 +258,13 @@ def bench_forward(args, fields=False, kind=None):
     for form, r in results.items():
         es = (n * n + n) * (8 if form == "fp64" else 4)
         alg_bytes = ne * (in_bytes + es)
+        # gflops: the B^T W B formulation's work (F_dom) per second, comparable across
+        # kernels and with the paper; gflops_alg: the work of the algorithm the chosen
+        # tile runs (fewer flops for the triangle-point contraction), the roofline numerator
+        r["alg_flops_per_element"] = fdom if other_elem else costmodel.f_kernel(p, rule, r["tile"])
         r["gflops"] = fdom * ne / (r["kernel_ms_mean"] * 1e-3) / 1e9
-        r["tflops_frac_of_peak"] = r["gflops"] / 1e3 / PEAK_TFLOPS[form]
+        r["gflops_alg"] = r["alg_flops_per_element"] * ne / (r["kernel_ms_mean"] * 1e-3) / 1e9
+        r["tflops_frac_of_peak"] = r["gflops_alg"] / 1e3 / PEAK_TFLOPS[form]
         r["hbm_gbs_algorithmic"] = alg_bytes / (r["kernel_ms_mean"] * 1e-3) / 1e9
 
     cpu = None
@@ -288,21 +293,27 @@ def bench_forward(args, fields=False, kind=None):
     # bound = the larger ideal time: MFMA work (three products for a split
     # form) at the dtype's dense peak, or the algorithmic bytes at HBM peak
     products = 3 if headline in ("bf16x3", "fp16x3") else 1
-    t_mfma = products * fdom * ne / (PEAK_TFLOPS[headline] * 1e12)
+    falg = h["alg_flops_per_element"]
+    t_mfma = products * falg * ne / (PEAK_TFLOPS[headline] * 1e12)
     t_hbm = alg_bytes / (HBM_PEAK_GBS * 1e9)
     if t_hbm > t_mfma:
         roofline = {"bound": "hbm", "achieved": h["hbm_gbs_algorithmic"], "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": h["hbm_gbs_algorithmic"] / HBM_PEAK_GBS}
     else:
-        roofline = {"bound": "mfma", "achieved": h["gflops"] / 1e3, "peak": PEAK_TFLOPS[headline],
-                    "unit": "TFLOP/s", "frac": h["gflops"] / 1e3 / PEAK_TFLOPS[headline]}
+        roofline = {"bound": "mfma", "achieved": h["gflops_alg"] / 1e3, "peak": PEAK_TFLOPS[headline],
+                    "unit": "TFLOP/s", "frac": h["gflops_alg"] / 1e3 / PEAK_TFLOPS[headline]}
     npad, nqp = (n + 15) // 16 * 16, (q + 7) // 8 * 8
-    hw_flops = products * 8.0 * npad * npad * (nqp if products == 3 else q) * ne
-    roofline.update({"traffic": traffic, "kernel_ms": h["kernel_ms_mean"], "flops_per_launch": fdom * ne,
+    kf = not other_elem and costmodel.is_kf_tile(h["tile"])
+    hw_flops = (costmodel.kf_mfma_flops(p, rule) * ne if kf else
+                products * 8.0 * npad * npad * (nqp if products == 3 else q) * ne)
+    roofline.update({"traffic": traffic, "kernel_ms": h["kernel_ms_mean"], "flops_per_launch": falg * ne,
+                     "fdom_per_launch": fdom * ne,
                      "hw_mfma_frac": hw_flops / (h["kernel_ms_mean"] * 1e-3) / (PEAK_TFLOPS[headline] * 1e12),
                      "alg_bytes_per_launch": alg_bytes,
-                     "note": "algorithmic flops 8 n^2 nq per element (one product per entry; "
-                             "a split form issues three products); bytes %d in + (n^2+n) outputs" % in_bytes})
+                     "note": ("algorithmic flops of the triangle-point contraction per element "
+                              "(8 n^2 nij + 8 (p+1)^2 nij n + 24 nq ntri + 12 nq n)" if kf else
+                              "algorithmic flops 8 n^2 nq per element (one product per entry; "
+                              "a split form issues three products)") + "; bytes %d in + (n^2+n) outputs" % in_bytes})
     forms_out = {}
     for form, r in results.items():
         forms_out[form] = {k: (float(f"{v:.5g}") if isinstance(v, float) else v) for k, v in r.items()
@@ -464,7 +475,9 @@ def bench_mixed(args):
     plan.capture(*X, pd, gA, gb, goA, gob)
     ms_g, mn_g, wall_g = timed(plan.replay, args.steps, args.warmup)
     counts = np.bincount(batch.p, minlength=7)
-    flops = sum(int(counts[d]) * costmodel.f_dom(d) for d in range(1, 7))
+    fdom = sum(int(counts[d]) * costmodel.f_dom(d) for d in range(1, 7))
+    shapes = plan.tile_describe(plan.tile).split(",")     # one entry per degree 1..6
+    flops = sum(int(counts[d]) * costmodel.f_kernel(d, "collapsed", shapes[d - 1]) for d in range(1, 7))
     es = 8 if form == "fp64" else 4
     bytes_ = sum(int(counts[d]) * costmodel.bytes_per_element(d, es) for d in range(1, 7))
     peak = PEAK_TFLOPS[form]
@@ -491,10 +504,12 @@ def bench_mixed(args):
                        "tile_set": plan.tile, "tile_set_shapes": plan.tile_describe(plan.tile)},
             "tile_sets_ms": sets_ms,
             "bucket_ms": ms_b, "persistent_ms": ms_p, "persistent_ms_min": mn_p, "graph_ms": ms_g,
-            "graph_ms_min": mn_g, "tune_ms": tune_ms, "gflops": flops / (ms_p * 1e-3) / 1e9,
+            "graph_ms_min": mn_g, "tune_ms": tune_ms, "gflops": fdom / (ms_p * 1e-3) / 1e9,
             "roofline": {"bound": "mfma", "achieved": flops / (ms_p * 1e-3) / 1e12, "peak": peak,
                          "unit": "TFLOP/s", "frac": flops / (ms_p * 1e-3) / 1e12 / peak, "traffic": None,
-                         "flops_per_launch": flops, "alg_bytes_per_launch": bytes_},
+                         "flops_per_launch": flops, "fdom_per_launch": fdom, "alg_bytes_per_launch": bytes_,
+                         "note": "flops of the algorithm each degree's kernel runs: 8 n^2 nq per element "
+                                 "point by point, the triangle-point contraction's count for KxTNf shapes"},
             "cpu_baseline": cpu}
     plan.close()
     print(json.dumps(fmt(line)))

@@ -57,6 +57,36 @@ def f_dom(p: int, rule: str = "collapsed") -> int:
     return 8 * nshp(p) ** 2 * nq(p, rule)
 
 
+def f_kf(p: int, rule: str = "collapsed") -> int:
+    """Flops per element of the contraction per triangle point (the rule is nij
+    triangle points times p+1 points in zeta, the basis triangle factor times
+    line factor): the GEMM over (triangle point, derivative row), 8 n^2 nij;
+    forming Z_k from the p+1 zeta points, 8 (p+1)^2 nij n; forming Y from the
+    point blocks and the factors, 24 nq ntri + 12 nq n."""
+    n, nk, nt, q = nshp(p), p + 1, ntri(p), nq(p, rule)
+    nij = q // nk
+    return 8 * n * n * nij + 8 * nk * nk * nij * n + 24 * q * nt + 12 * q * n
+
+
+def kf_mfma_flops(p: int, rule: str = "collapsed") -> int:
+    """Hardware MFMA flops per element of the triangle-point contraction:
+    one 16x16x4 product per (row block, column block) pair of 16-padded
+    triangle tiles and zeta indices, per triangle point."""
+    nk, tt = p + 1, -(-ntri(p) // 16)
+    return 2 * 16 * 16 * 4 * (nq(p, rule) // nk) * (nk * tt) ** 2
+
+
+def is_kf_tile(desc: str) -> bool:
+    """Tile descriptions "KxTNf" (optionally "o2") name the triangle-point contraction."""
+    import re
+    return re.fullmatch(r"\d+x\d+f(o2)?", desc) is not None
+
+
+def f_kernel(p: int, rule: str, desc: str) -> int:
+    """Algorithmic flops per element of the algorithm the tile runs."""
+    return f_kf(p, rule) if is_kf_tile(desc) else f_dom(p, rule)
+
+
 def f_full(p: int) -> int:
     """F_dom + load vector and gradient transform (28 n nq) + geometry (220 nq)."""
     n, q = nshp(p), nq(p)

@@ -24,6 +24,7 @@
 #include "capi_internal.h"
 #include "fwd_kernels.h"
 #include "fwd_valu.h"
+#include "fwd_fact.h"
 #include "tables.h"
 
 namespace feint {
@@ -53,6 +54,10 @@ struct MixedParams {
     const double *qw[8];
     const double *B64[8];
     const float *B32[8];
+    const double *tau64[8];   // per-degree factor tables of the triangle-point contraction
+    const float *tau32[8];
+    const double *lam[8];
+    const float *lam32[8];
     const int32_t *perm;
     MixedHdr *hdr;
     MixSizes sz;
@@ -208,6 +213,10 @@ __device__ __attribute__((noinline)) void run_item(const MixedParams &mp, int d,
     prm.qw = mp.qw[d];
     prm.B64 = mp.B64[d];
     prm.B32 = mp.B32[d];
+    prm.tau64 = mp.tau64[d];
+    prm.tau32 = mp.tau32[d];
+    prm.lam = mp.lam[d];
+    prm.lam32 = mp.lam32[d];
     prm.perm = mp.perm + mp.hdr->bstart[d];
     prm.ne = mp.hdr->count[d];          // slots of this bucket
     KER::run_slice(prm, item / KER::NBLK, (int)(item % KER::NBLK), *(typename KER::Slice *)slice);
@@ -279,9 +288,14 @@ MixVariant make_variant(const char *desc) {
 }
 
 const MixVariant *mix_variants(int form, int *count) {
-    // p = 1, 2 on the vector ALUs (v8: 8 lanes per element, v18: 18), MFMA tiles above;
-    // the last set of each form keeps MFMA tiles at every degree for comparison
+    // p = 1, 2 on the vector ALUs (v8: 8 lanes per element, v18: 18), MFMA tiles above:
+    // the contraction per triangle point (KxTNf) or point by point (TMxTN); the last set
+    // of each form keeps point-by-point MFMA tiles at every degree for comparison
     static const MixVariant f32[] = {
+        make_variant<KV<1, float, 8>, KV<2, float, 18>, KF<3, float, 4, 4>, KF<4, float, 5, 3>,
+                     KF<5, float, 6, 3>, KF<6, float, 7, 4>>("v8,v18,4x4f,5x3f,6x3f,7x4f"),
+        make_variant<KV<1, float, 8>, KV<2, float, 18>, KF<3, float, 4, 4>, KF<4, float, 5, 5>,
+                     KF<5, float, 6, 3>, KF<6, float, 7, 3>>("v8,v18,4x4f,5x5f,6x3f,7x3f"),
         make_variant<KV<1, float, 8>, KV<2, float, 18>, K4<3, float, 3, 3>, K4<4, float, 5, 5>,
                      K4<5, float, 8, 8>, K4<6, float, 13, 5>>("v8,v18,3x3,5x5,8x8,13x5"),
         make_variant<KV<1, float, 8>, KV<2, float, 18>, K4<3, float, 3, 3>, K4<4, float, 5, 5>,
@@ -296,6 +310,10 @@ const MixVariant *mix_variants(int form, int *count) {
                      K4<5, float, 8, 2>, K4<6, float, 13, 1>>("1x1,2x2,3x3,5x3,8x2,13x1"),
     };
     static const MixVariant f64[] = {
+        make_variant<KV<1, double, 8>, KV<2, double, 18>, KF<3, double, 4, 2>, KF<4, double, 5, 5>,
+                     KF<5, double, 3, 2>, KF<6, double, 7, 1>>("v8,v18,4x2f,5x5f,3x2f,7x1f"),
+        make_variant<KV<1, double, 8>, KV<2, double, 18>, KF<3, double, 4, 2>, KF<4, double, 5, 3>,
+                     KF<5, double, 6, 1>, KF<6, double, 4, 2>>("v8,v18,4x2f,5x3f,6x1f,4x2f"),
         make_variant<KV<1, double, 8>, KV<2, double, 18>, K4<3, double, 3, 3>, K4<4, double, 5, 3>,
                      K4<5, double, 8, 4>, K4<6, double, 13, 2>>("v8,v18,3x3,5x3,8x4,13x2"),
         make_variant<KV<1, double, 8>, KV<2, double, 18>, K4<3, double, 3, 3>, K4<4, double, 5, 1>,
@@ -374,6 +392,10 @@ feint_status enqueue_persist(feint_mixed_plan *pl, const feint_elements *el, voi
         mp.qw[d] = pl->tab[d]->qw;
         mp.B64[d] = pl->tab[d]->B64;
         mp.B32[d] = pl->tab[d]->B32;
+        mp.tau64[d] = pl->tab[d]->tau64;
+        mp.tau32[d] = pl->tab[d]->tau32;
+        mp.lam[d] = pl->tab[d]->lam;
+        mp.lam32[d] = pl->tab[d]->lam32;
     }
     mp.perm = pl->perm;
     mp.hdr = pl->hdr;

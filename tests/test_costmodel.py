@@ -62,3 +62,33 @@ def test_this_library_counts():
     assert cm.f_dom(4) == 8 * 75 * 75 * 125
     assert cm.INPUT_BYTES == 256
     assert cm.bytes_per_element(4, 8) == 256 + 8 * (75 * 75 + 75)
+
+
+@pytest.mark.parametrize("rule", ["collapsed", "symmetric"])
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_triangle_point_contraction_count(p, rule):
+    """The factorized contraction's flop count against a walk over its loop
+    nest: Y per (point, row r, triangle column) and per column (k', t'), Z_k
+    per (k, triangle point, r, column) over the p+1 zeta points, then the GEMM
+    over (triangle point, r) for every entry."""
+    n, nk, nt, q = cm.nshp(p), p + 1, cm.ntri(p), cm.nq(p, rule)
+    nij = q // nk
+    assert nij * nk == q and nij == (cm.PAPER_TRIANGLE_POINTS[p] if rule == "symmetric" else nk * nk)
+    flops = 0
+    for _pt in range(q):
+        for _r in range(4):
+            flops += sum(6 for _t in range(nt))            # u = sum_{s<3} W tau_s, v = W tau_3
+            flops += sum(3 for _c in range(n))             # L u + L' v
+    for _k in range(nk):
+        for _ij in range(nij):
+            for _r in range(4):
+                flops += sum(2 * nk for _c in range(n))    # sum over zeta points
+    flops += sum(2 * 4 * nij for _e in range(n * n))       # GEMM over (ij, r)
+    assert cm.f_kf(p, rule) == flops
+    assert cm.f_kernel(p, rule, "5x3f") == flops and cm.f_kernel(p, rule, "4x4fo2") == flops
+    assert cm.f_kernel(p, rule, "5x5p") == cm.f_dom(p, rule) and cm.f_kernel(p, rule, "v8o2") == cm.f_dom(p, rule)
+
+
+def test_triangle_point_contraction_saves_work_from_p2():
+    ratio = [cm.f_dom(p) / cm.f_kf(p) for p in P]
+    assert ratio[0] < 1 < ratio[1] and all(a < b for a, b in zip(ratio, ratio[1:]))
