@@ -261,7 +261,10 @@ def bench_forward(args, fields=False, kind=None):
         # gflops: the B^T W B formulation's work (F_dom) per second, comparable across
         # kernels and with the paper; gflops_alg: the work of the algorithm the chosen
         # tile runs (fewer flops for the triangle-point contraction), the roofline numerator
-        r["alg_flops_per_element"] = fdom if other_elem else costmodel.f_kernel(p, rule, r["tile"])
+        if costmodel.is_kf_tile(r["tile"]):       # prisms and hexahedra: factorised along the third coordinate
+            r["alg_flops_per_element"] = costmodel.f_factored(n, p + 1, q)
+        else:
+            r["alg_flops_per_element"] = fdom
         r["gflops"] = fdom * ne / (r["kernel_ms_mean"] * 1e-3) / 1e9
         r["gflops_alg"] = r["alg_flops_per_element"] * ne / (r["kernel_ms_mean"] * 1e-3) / 1e9
         r["tflops_frac_of_peak"] = r["gflops_alg"] / 1e3 / PEAK_TFLOPS[form]
@@ -303,8 +306,8 @@ def bench_forward(args, fields=False, kind=None):
         roofline = {"bound": "mfma", "achieved": h["gflops_alg"] / 1e3, "peak": PEAK_TFLOPS[headline],
                     "unit": "TFLOP/s", "frac": h["gflops_alg"] / 1e3 / PEAK_TFLOPS[headline]}
     npad, nqp = (n + 15) // 16 * 16, (q + 7) // 8 * 8
-    kf = not other_elem and costmodel.is_kf_tile(h["tile"])
-    hw_flops = (costmodel.kf_mfma_flops(p, rule) * ne if kf else
+    kf = costmodel.is_kf_tile(h["tile"])
+    hw_flops = (costmodel.kf_mfma_flops(p, rule, n, q) * ne if kf else
                 products * 8.0 * npad * npad * (nqp if products == 3 else q) * ne)
     roofline.update({"traffic": traffic, "kernel_ms": h["kernel_ms_mean"], "flops_per_launch": falg * ne,
                      "fdom_per_launch": fdom * ne,

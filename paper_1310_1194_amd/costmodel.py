@@ -57,23 +57,31 @@ def f_dom(p: int, rule: str = "collapsed") -> int:
     return 8 * nshp(p) ** 2 * nq(p, rule)
 
 
+def f_factored(n: int, nk: int, nq_: int) -> int:
+    """Flops per element of the contraction factorised along the third
+    coordinate (the rule is nij plane points times nk line points, the basis
+    n = nk * nt plane factors times line factors): the GEMM over (plane point,
+    derivative row), 8 n^2 nij; forming Z_k from the nk line points,
+    8 nk^2 nij n; forming Y from the point blocks and the factors,
+    24 nq nt + 12 nq n."""
+    nij, nt = nq_ // nk, n // nk
+    return 8 * n * n * nij + 8 * nk * nk * nij * n + 24 * nq_ * nt + 12 * nq_ * n
+
+
 def f_kf(p: int, rule: str = "collapsed") -> int:
-    """Flops per element of the contraction per triangle point (the rule is nij
-    triangle points times p+1 points in zeta, the basis triangle factor times
-    line factor): the GEMM over (triangle point, derivative row), 8 n^2 nij;
-    forming Z_k from the p+1 zeta points, 8 (p+1)^2 nij n; forming Y from the
-    point blocks and the factors, 24 nq ntri + 12 nq n."""
-    n, nk, nt, q = nshp(p), p + 1, ntri(p), nq(p, rule)
-    nij = q // nk
-    return 8 * n * n * nij + 8 * nk * nk * nij * n + 24 * q * nt + 12 * q * n
+    """f_factored for prisms: ntri triangle functions times p+1 line functions."""
+    return f_factored(nshp(p), p + 1, nq(p, rule))
 
 
-def kf_mfma_flops(p: int, rule: str = "collapsed") -> int:
-    """Hardware MFMA flops per element of the triangle-point contraction:
-    one 16x16x4 product per (row block, column block) pair of 16-padded
-    triangle tiles and zeta indices, per triangle point."""
-    nk, tt = p + 1, -(-ntri(p) // 16)
-    return 2 * 16 * 16 * 4 * (nq(p, rule) // nk) * (nk * tt) ** 2
+def kf_mfma_flops(p: int, rule: str = "collapsed", n: int = 0, nq_: int = 0) -> int:
+    """Hardware MFMA flops per element of the factorised contraction: one
+    16x16x4 product per (row block, column block) pair of 16-padded plane
+    tiles and line indices, per plane point (prisms by default; n and nq_
+    give another element's shape-function and point counts)."""
+    nk = p + 1
+    n, nq_ = n or nshp(p), nq_ or nq(p, rule)
+    tt = -(-(n // nk) // 16)
+    return 2 * 16 * 16 * 4 * (nq_ // nk) * (nk * tt) ** 2
 
 
 def is_kf_tile(desc: str) -> bool:

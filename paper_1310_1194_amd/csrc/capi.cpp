@@ -272,6 +272,20 @@ feint_status feint_rule_tile_set(int p, feint_form form, feint_rule rule, int ti
     return FEINT_OK;
 }
 
+// "TMxTN" plus the kernel kind (s staged, sa A operands staged, p pipelined,
+// c shape functions computed per point, f contraction per triangle or plane
+// point; "vL" vector-ALU kernel with L lanes per element) and "o2" for a
+// two-waves-per-SIMD register budget.
+static void describe_variant(const FwdVariant &v, char *buf, size_t len) {
+    if (v.staged == 3)
+        std::snprintf(buf, len, "v%d%s", v.tn, v.minw > 1 ? "o2" : "");
+    else
+        std::snprintf(buf, len, "%dx%d%s%s", v.tm, v.tn,
+                      v.staged == 1 ? "s" : v.staged == 2 ? "sa" : v.staged == 4 ? "p"
+                      : v.staged == 5 ? "c" : v.staged == 6 ? "f" : "",
+                      v.minw > 1 ? "o2" : "");
+}
+
 feint_status feint_rule_tile_describe(int p, feint_form form, feint_rule rule, int tile, char *buf, size_t len) {
     int cnt = 0;
     if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
@@ -279,13 +293,7 @@ feint_status feint_rule_tile_describe(int p, feint_form form, feint_rule rule, i
     if (!valid_rule(rule)) return FEINT_ERR_INVALID_ARG;
     const FwdVariant *v = fwd_variants(form, p, &cnt, rule);
     if (!buf || tile < 0 || tile >= cnt) return FEINT_ERR_INVALID_ARG;
-    if (v[tile].staged == 3)
-        std::snprintf(buf, len, "v%d%s", v[tile].tn, v[tile].minw > 1 ? "o2" : "");
-    else
-        std::snprintf(buf, len, "%dx%d%s%s", v[tile].tm, v[tile].tn,
-                      v[tile].staged == 1 ? "s" : v[tile].staged == 2 ? "sa" : v[tile].staged == 4 ? "p"
-                      : v[tile].staged == 5 ? "c" : v[tile].staged == 6 ? "f" : "",
-                      v[tile].minw > 1 ? "o2" : "");
+    describe_variant(v[tile], buf, len);
     return FEINT_OK;
 }
 
@@ -392,10 +400,7 @@ static feint_status elem_tile_describe(int type, int p, int form, int tile, char
     int cnt = 0;
     const FwdVariant *v = elem_variants(type, form, p, &cnt);
     if (!buf || tile < 0 || tile >= cnt) return FEINT_ERR_INVALID_ARG;
-    if (v[tile].staged == 3)
-        std::snprintf(buf, len, "v%d%s", v[tile].tn, v[tile].minw > 1 ? "o2" : "");
-    else
-        std::snprintf(buf, len, "%dx%d%s", v[tile].tm, v[tile].tn, v[tile].minw > 1 ? "o2" : "");
+    describe_variant(v[tile], buf, len);
     return FEINT_OK;
 }
 

@@ -13,6 +13,11 @@
 // kernel issues (p+1)^2 * ceil(ntri/16), for O((p+1)^2) extra FMAs per lane
 // (forming Z), which the FP64 and FP32 matrix rates leave room for.
 //
+// Hexahedra (geometry policy HexGeo) have the same structure: tensor Gauss
+// points with q = m (p+1)^2 + ij and the tensor basis phi_(k,t) = T_t L_k with
+// the plane factor T_(i',j') = l_i'(xi1) l_j'(xi2), (p+1)^2 of them in place
+// of the triangle's.
+//
 // Rows of A come in blocks (k, t-tile), columns in tiles (k', t'-tile) of 16
 // (ntri padded to a multiple of 16, padding multiplied by zero).  A wave owns
 // TMK row blocks k (all their t-tiles) and TN column tiles k' of one t'-tile
@@ -26,17 +31,17 @@
 
 namespace feint {
 
-template <int P, typename T, int TMK, int TN, int R = 0>
+template <int P, typename T, int TMK, int TN, int R = 0, class G = PrismGeo>
 struct KF {
-    static constexpr int N = c_nshp(P), NP = c_pad16(N);
-    static constexpr int NK = P + 1, NTRI = (P + 1) * (P + 2) / 2, TT = c_cdiv(NTRI, 16), TP = TT * 16;
-    static constexpr int NQ = c_nq_rule(P, R), NIJ = NQ / NK;
+    static constexpr int N = G::nshp(P), NP = c_pad16(N);
+    static constexpr int NK = P + 1, NTRI = N / NK, TT = c_cdiv(NTRI, 16), TP = TT * 16;
+    static constexpr int NQ = G::nq(P, R), NIJ = NQ / NK;
     static constexpr int BM = c_cdiv(NK, TMK), BK = c_cdiv(NK, TN), BN = TT * BK, NBLK = BM * BN;
     static constexpr int EPI = 1;
     static constexpr int CIJ = 64 / NK;                       // triangle points per chunk
     static constexpr int LCT = TT - 1, LCL = NTRI - LCT * 16;  // load-vector column: tile (0, LCT), lane LCL
     static_assert(NTRI % 16 != 0, "the load vector needs a spare padded column");
-    static_assert(NIJ * NK == NQ, "the rule must be a product in zeta");
+    static_assert(NIJ * NK == NQ && NTRI * NK == N, "the rule and the basis must be products in zeta");
     static_assert(TN <= NK && TMK <= NK, "tile counts beyond the zeta factor");
     typedef typename AccT<T>::type V4;
 
@@ -52,8 +57,8 @@ struct KF {
         const int i16 = lane & 15, kg = lane >> 4;
         const int k0 = bi * TMK, tt = bj / BK, kp0 = (bj - tt * BK) * TN;
         const int64_t e = elem_of(prm, slot);
-        ElemIn E;
-        load_elem_fwd(prm, e, E);
+        typename G::Elem E;
+        G::load(prm, e, E);
         const T *tau = sizeof(T) == 8 ? (const T *)(const void *)prm.tau64 : (const T *)(const void *)prm.tau32;
         const T *lam = sizeof(T) == 8 ? (const T *)(const void *)prm.lam : (const T *)(const void *)prm.lam32;
         // row factors of the lane (r = kg) for its row blocks, in registers
@@ -93,15 +98,15 @@ struct KF {
                 const int q = m * NIJ + ij0 + il;
                 const double *qp = prm.qw + 4 * q;
                 double W[16], sf;
-                field_at(prm, e, qp[0], qp[1], qp[2], E);
-                const double det = point_block(E, qp[0], qp[1], qp[2], qp[3], W, sf);
+                G::coeffs(prm, e, qp, E);
+                const double det = G::block(E, qp, W, sf);
                 if (!(det > 0.0) && prm.status) atomicOr(prm.status, 1u);
 #pragma unroll
                 for (int k = 0; k < 16; ++k) sl.W[lane][k] = (T)W[k];
                 sl.sf[lane] = sf;
                 if (prm.xq && blk == 0) {
                     double x[3];
-                    prism_map(E.X, qp[0], qp[1], qp[2], x);
+                    G::map(E, qp, x);
 #pragma unroll
                     for (int d = 0; d < 3; ++d) prm.xq[(e * NQ + q) * 3 + d] = x[d];
                 }

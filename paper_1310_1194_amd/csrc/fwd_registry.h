@@ -71,6 +71,9 @@ int64_t items_of(int64_t ne) { return items_for<KER>(ne); }
 // TMK row blocks k and TN column tiles per wave.
 #define FEINT_KF_R(P, T, TMK, TN, W, R) \
     FwdVariant{TMK, TN, 6, W, &launch_direct<KF<P, T, TMK, TN, R>, W>, &items_of<KF<P, T, TMK, TN, R>>}
+#define FEINT_KF_HEX(P, T, TMK, TN, W)                                        \
+    FwdVariant{TMK, TN, 6, W, &launch_direct<KF<P, T, TMK, TN, 0, HexGeo>, W>, \
+               &items_of<KF<P, T, TMK, TN, 0, HexGeo>>}
 
 #define FEINT_K4U(P, T, TM, TN, W) FEINT_K4U_R(P, T, TM, TN, W, 0)
 #define FEINT_KSC(P, T, TM, TN, W) FEINT_KSC_R(P, T, TM, TN, W, 0)

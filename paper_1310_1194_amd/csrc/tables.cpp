@@ -590,6 +590,39 @@ HostTables build_hex_tables(int p) {
                 }
     }
     derive_layouts(T);
+    // tensor factors for the kernels that contract per plane point: q = m nij + ij with
+    // ij = j n1 + i, a = k nt + t with t = j' n1 + i', so B_q[r][(k,t)] = tau_r(t, ij)
+    // lam_r(k, m) with tau = (l_i' l_j', l_i'' l_j', l_i' l_j'', l_i' l_j') at (x_i, y_j) and
+    // lam = (l_k, l_k, l_k, l_k') at z_m
+    const int nt = n1 * n1;
+    T.nk = n1;
+    T.nij = nt;
+    T.tpad = pad16(nt);
+    T.tau64.assign((size_t)T.nij * 4 * T.tpad, 0.0);
+    T.lam.assign((size_t)4 * n1 * n1, 0.0);
+    for (int j = 0; j < n1; ++j)
+        for (int i = 0; i < n1; ++i) {
+            line(g[i], lx, dlx);
+            line(g[j], ly, dly);
+            const size_t ij = (size_t)j * n1 + i;
+            for (int jj = 0; jj < n1; ++jj)
+                for (int ii = 0; ii < n1; ++ii) {
+                    const int t = jj * n1 + ii;
+                    T.tau64[(ij * 4 + 0) * T.tpad + t] = lx[ii] * ly[jj];
+                    T.tau64[(ij * 4 + 1) * T.tpad + t] = dlx[ii] * ly[jj];
+                    T.tau64[(ij * 4 + 2) * T.tpad + t] = lx[ii] * dly[jj];
+                    T.tau64[(ij * 4 + 3) * T.tpad + t] = lx[ii] * ly[jj];
+                }
+        }
+    for (int m = 0; m < n1; ++m) {
+        line(g[m], lz, dlz);
+        for (int k = 0; k < n1; ++k) {
+            for (int r = 0; r < 3; ++r) T.lam[((size_t)r * n1 + k) * n1 + m] = lz[k];
+            T.lam[((size_t)3 * n1 + k) * n1 + m] = dlz[k];
+        }
+    }
+    T.tau32.assign(T.tau64.begin(), T.tau64.end());
+    T.lam32.assign(T.lam.begin(), T.lam.end());
     return T;
 }
 

@@ -30,7 +30,8 @@ struct HostTables {
     int f16_shift = 0;               // fp16 tables hold B * 2^f16_shift
     std::vector<double> qw;          // [nqp][4]  xi1, xi2, zeta, w  (padded points: w = 0)
     std::vector<double> gll;         // [2][p+1]  Gauss-Lobatto nodes z_k and 1 / prod_{m != k} (z_k - z_m)
-    // prisms: tensor factors of B (q = m nij + ij, a = k ntri + t):
+    // prisms and hexahedra: tensor factors of B (q = m nij + ij, a = k ntri + t; for
+    // hexahedra ntri = nij = (p+1)^2 plane functions and points):
     int nk = 0, nij = 0, tpad = 0;
     std::vector<double> tau64;       // [nij][4][tpad]  T, dT/dxi1, dT/dxi2, T at triangle point ij
     std::vector<float> tau32;

@@ -92,3 +92,15 @@ def test_triangle_point_contraction_count(p, rule):
 def test_triangle_point_contraction_saves_work_from_p2():
     ratio = [cm.f_dom(p) / cm.f_kf(p) for p in P]
     assert ratio[0] < 1 < ratio[1] and all(a < b for a, b in zip(ratio, ratio[1:]))
+
+
+@pytest.mark.parametrize("p", [1, 2, 4])
+def test_factored_count_hexahedra(p):
+    """Hexahedra: (p+1)^2 plane functions and points times p+1 line functions
+    and points; the same loop walk as for prisms."""
+    n1 = p + 1
+    n, nk, nt, q = n1 ** 3, n1, n1 ** 2, n1 ** 3
+    nij = q // nk
+    flops = q * 4 * (6 * nt + 3 * n) + nk * nij * 4 * n * 2 * nk + n * n * 2 * 4 * nij
+    assert cm.f_factored(n, nk, q) == flops
+    assert cm.kf_mfma_flops(p, n=n, nq_=q) == 2048 * nij * (nk * -(-nt // 16)) ** 2
