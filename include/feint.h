@@ -146,7 +146,8 @@ feint_status feint_integrate_adjoint(const feint_elements *el, int p, feint_form
    `stream`, synchronising on it), keeps the fastest for later calls of this
    (p, form) and returns its time in *best_ms (nullable); ne = 0 or reps < 1
    gives INVALID_ARG.  tile_get/set read or force the choice; tile_describe
-   writes "TAxTB".  Count is 0 and get is -1 for unsupported (p, form). */
+   writes "TAxTB" (16x16 tiles of G per wave) or "TKxTBf" (the kernel
+   factorised along zeta: TK row indices k by TB column tiles).  Count is 0 and get is -1 for unsupported (p, form). */
 int feint_adjoint_tile_count(int p, feint_form form);
 int feint_adjoint_tile_get(int p, feint_form form);
 feint_status feint_adjoint_tile_set(int p, feint_form form, int tile);

@@ -38,6 +38,8 @@ struct AdjParams {
     double *dX, *dD, *dbeta, *dc, *df;
     const double *qw, *B64;
     const void *BT;     // [npad][nqp*4]  in the form's precision
+    const void *tau;    // triangle factors [nij][4][tpad] and line factors [4][p+1][p+1],
+    const void *lamT;   // both in the form's precision
 };
 
 template <int P, typename T, int TA, int TB, int R = 0>
@@ -291,6 +293,154 @@ struct Adj {
     }
 };
 
+// The adjoint factorised along zeta.  Both prism rules are products of nij
+// triangle points and p+1 points in zeta and B_q[r][(k,t)] = tau_r(t, ij)
+// lam_r(k, m) (tau = (T, dT/dxi1, dT/dxi2, T), lam = (L, L, L, dL/dzeta)), so
+//   S_q[r][s] = sum_b Hh_q[r][b] B_q[s][b],
+//   Hh_(ij,m)[r][b] = sum_k lam_r(k, m) H_k[b][(ij, r)],
+//   H_k[b][(ij, r)] = sum_t G[(k,t)][b] tau_r(t, ij).
+// Per group of four triangle points a wave forms H_k on MFMA (rows b of its
+// column tiles, columns (triangle point, r), K = t) for its row indices k,
+// combines them into Hh for each zeta point m on the vector ALUs (p+1 FMAs
+// per value), and feeds Hh register by register as the A operand of
+// T = Hh B^T over its columns b (K = b, 4 MFMAs per column tile); the
+// diagonal 4x4 blocks of T are the (partial) S_q of the group's points at m.
+// Column tiles are (k', t'-tile) pairs, so the line factor of a column tile is
+// the same for the whole wave.  The chain rule is the point-by-point kernel's.
+template <int P, typename T, int TK, int TB, int R = 0>
+struct KFA {
+    typedef Adj<P, T, 1, 1, R> Base;
+    static constexpr int N = c_nshp(P), NQ = c_nq_rule(P, R);
+    static constexpr int NK = P + 1, NTRI = (P + 1) * (P + 2) / 2, TT = c_cdiv(NTRI, 16), TP = TT * 16;
+    static constexpr int KS = c_cdiv(NTRI, 4);              // K-steps over t
+    static constexpr int NIJ = NQ / NK, NCT = NK * TT;        // column tiles (k', t'-tile)
+    static constexpr int CIJ = 64 / NK / 4 * 4;               // triangle points per chunk (groups of 4)
+    static constexpr int BK = c_cdiv(NK, TK), BB = c_cdiv(NCT, TB), NBLK = BK * BB;
+    static constexpr bool ATOMIC = NBLK > 1;
+    static_assert(NIJ * NK == NQ, "the rule must be a product in zeta");
+    static_assert(CIJ >= 4, "a chunk holds at least one group of four triangle points");
+    typedef typename AccT<T>::type V4;
+    typedef const __attribute__((address_space(4))) T CT;
+
+    struct Smem { double S[4][64][WROW<double>::value]; };
+
+    __device__ static void run(const AdjParams &prm, int64_t e, int blk, int wave, Smem &sm) {
+        const int lane = threadIdx.x & 63;
+        const int i16 = lane & 15, kg = lane >> 4;
+        const int bk = blk / BB, bc = blk % BB;
+        const int k0 = bk * TK, c0 = bc * TB;
+        const bool with_load = blk == 0;
+        const T *Ge = (const T *)prm.G + e * (int64_t)N * N;
+        const T *tau = (const T *)prm.tau;
+        const CT *lam = (const CT *)prm.lamT;                 // [s][k][m], wave-uniform reads
+        // A operands of H_k: lane (i16, kg) holds G[(k, t = 4 s + kg)][(k'_c, t' = 16 tt_c + i16)]
+        T gf[TK][KS][TB];
+#pragma unroll
+        for (int k = 0; k < TK; ++k)
+#pragma unroll
+            for (int s = 0; s < KS; ++s)
+#pragma unroll
+                for (int tb = 0; tb < TB; ++tb) {
+                    const int c = c0 + tb, kp = c / TT, tp = (c % TT) * 16 + i16, t = 4 * s + kg;
+                    gf[k][s][tb] = (k0 + k < NK && c < NCT && t < NTRI && tp < NTRI)
+                                       ? Ge[(size_t)((k0 + k) * NTRI + t) * N + kp * NTRI + tp] : (T)0;
+                }
+        const bool rl = (i16 & 3) == 3;     // this lane's column (point, r) has r = 3: the zeta derivative
+        double gacc = 0.0;
+        for (int ij0 = 0; ij0 < NIJ; ij0 += CIJ) {
+            const int cij = NIJ - ij0 < CIJ ? NIJ - ij0 : CIJ;
+            for (int g4 = 0; g4 < cij; g4 += 4) {
+                const int ijc = ij0 + g4 + (i16 >> 2);          // the triangle point of this lane's column
+                const bool ijok = ijc < NIJ;
+                // H_k over K = t: B operands tau_r(t = 4 s + kg, ij) at column (point, r) = i16
+                V4 h[TK][TB];
+#pragma unroll
+                for (int k = 0; k < TK; ++k)
+#pragma unroll
+                    for (int tb = 0; tb < TB; ++tb) h[k][tb] = V4{0, 0, 0, 0};
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    const T tv = ijok ? tau[((size_t)ijc * 4 + (i16 & 3)) * TP + 4 * s + kg] : (T)0;
+#pragma unroll
+                    for (int k = 0; k < TK; ++k)
+#pragma unroll
+                        for (int tb = 0; tb < TB; ++tb) h[k][tb] = mfma4(gf[k][s][tb], tv, h[k][tb]);
+                }
+                // B operands of T at K-step j: tau_s(t' of row j of the column tile, ij), s = i16 % 4
+                T tb4[TB][4];
+#pragma unroll
+                for (int tb = 0; tb < TB; ++tb)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int tp = ((c0 + tb) % TT) * 16 + acc_row<T>(lane, j);
+                        tb4[tb][j] = ijok ? tau[((size_t)ijc * 4 + (i16 & 3)) * TP + tp] : (T)0;
+                    }
+                for (int m = 0; m < NK; ++m) {
+                    V4 tacc = V4{0, 0, 0, 0};
+#pragma unroll
+                    for (int tb = 0; tb < TB; ++tb) {
+                        if (c0 + tb >= NCT) continue;
+                        const int kp = (c0 + tb) / TT;
+                        const T lb = rl ? lam[(size_t)(3 * NK + kp) * NK + m] : lam[(size_t)kp * NK + m];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            T hh = (T)0;
+#pragma unroll
+                            for (int k = 0; k < TK; ++k) {
+                                if (k0 + k >= NK) continue;
+                                const T lr = rl ? lam[(size_t)(3 * NK + k0 + k) * NK + m] : lam[(size_t)(k0 + k) * NK + m];
+                                hh += lr * h[k][tb][j];
+                            }
+                            tacc = mfma4(hh, tb4[tb][j] * lb, tacc);
+                        }
+                    }
+                    // diagonal blocks: row (point, r), column (point', s), point = point'
+                    const int pl = g4 + (i16 >> 2);             // chunk-local triangle point of this lane's column
+                    if (sizeof(T) == 8) {
+                        // lane holds rows 4 jj + kg: point jj, r = kg
+                        const int pt = i16 >> 2;
+                        const double v = pt == 0 ? tacc[0] : pt == 1 ? tacc[1] : pt == 2 ? tacc[2] : tacc[3];
+                        if (pl < cij) sm.S[wave][pl * NK + m][4 * kg + (i16 & 3)] = v;
+                    } else if (kg == (i16 >> 2)) {
+                        // lane holds rows 4 kg + jj: point kg, r = jj
+                        if (pl < cij) {
+#pragma unroll
+                            for (int jj = 0; jj < 4; ++jj) sm.S[wave][pl * NK + m][4 * jj + (i16 & 3)] = (double)tacc[jj];
+                        }
+                    }
+                }
+            }
+            wave_sync();
+            {
+                ElemIn E;
+                load_elem(prm.coords, prm.D, prm.beta, prm.c, prm.f, e, E);
+                double gr[32];
+#pragma unroll
+                for (int k = 0; k < 32; ++k) gr[k] = 0.0;
+                if (lane < cij * NK) {
+                    const int il = lane / NK, m = lane - il * NK;
+                    const int q = m * NIJ + ij0 + il;
+                    double S[16];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) S[k] = sm.S[wave][lane][k];
+                    Base::chain_rule(prm, E, q, S, with_load, e, gr);
+                }
+                gacc += Base::reduce_scatter32(gr, lane);
+            }
+            wave_sync();
+        }
+        if ((lane & 1) == 0) {
+            const int c = lane >> 1;
+            double *dst = c < 18 ? prm.dX + 18 * e + c
+                        : c < 27 ? prm.dD + 9 * e + (c - 18)
+                        : c < 30 ? prm.dbeta + 3 * e + (c - 27)
+                        : c == 30 ? prm.dc + e : prm.df + e;
+            if (ATOMIC) atomicAdd(dst, gacc);
+            else *dst = gacc;
+        }
+    }
+};
+
 template <class KER>
 __global__ __launch_bounds__(256) void adj_direct(AdjParams prm) {
     __shared__ typename KER::Smem sm;
@@ -323,39 +473,53 @@ feint_status launch_adj(const AdjParams &prm, hipStream_t s) {
     return FEINT_OK;
 }
 
-// Compiled block shapes (TA x TB 16x16 tiles of G per wave) per degree and
+// Compiled block shapes (TA x TB 16x16 tiles of G per wave, or for the
+// factorised kernel TK row indices k by TB column tiles) per degree and
 // quadrature rule (the same shapes for both rules, so one choice per (degree,
 // form) serves both); the first is the default until feint_adjoint_autotune
 // picks another.
 struct AdjVariant {
     int ta, tb;
     feint_status (*launch)(const AdjParams &, hipStream_t);
+    int fact;           // 1: factorised along zeta (KFA, TA = row indices k, TB = column tiles)
 };
-#define FEINT_ADJ(P, T, TA, TB) AdjVariant{TA, TB, &launch_adj<Adj<P, T, TA, TB, R>>}
+#define FEINT_ADJ(P, T, TA, TB) AdjVariant{TA, TB, &launch_adj<Adj<P, T, TA, TB, R>>, 0}
+#define FEINT_ADJF(P, T, TK, TB) AdjVariant{TK, TB, &launch_adj<KFA<P, T, TK, TB, R>>, 1}
 
 template <typename T, int R>
 const AdjVariant *adj_variants_of(int p, int *count) {
-    static const AdjVariant v1[] = {FEINT_ADJ(1, T, 1, 1)};
-    static const AdjVariant v2[] = {FEINT_ADJ(2, T, 2, 2), FEINT_ADJ(2, T, 2, 1)};
-    static const AdjVariant v3[] = {FEINT_ADJ(3, T, 3, 3), FEINT_ADJ(3, T, 3, 1), FEINT_ADJ(3, T, 3, 2)};
-    static const AdjVariant v4[] = {FEINT_ADJ(4, T, 5, 2), FEINT_ADJ(4, T, 5, 1), FEINT_ADJ(4, T, 3, 3)};
-    static const AdjVariant v5[] = {FEINT_ADJ(5, T, 8, 1), FEINT_ADJ(5, T, 4, 2), FEINT_ADJ(5, T, 8, 2)};
-    static const AdjVariant v6[] = {FEINT_ADJ(6, T, 7, 2), FEINT_ADJ(6, T, 7, 1), FEINT_ADJ(6, T, 13, 1)};
-    // default at p = 7 as measured on the 16384-element batch: 6x3 for FP64, 6x2 for FP32
-    static const AdjVariant v7d[] = {FEINT_ADJ(7, T, 6, 3), FEINT_ADJ(7, T, 9, 2), FEINT_ADJ(7, T, 6, 2),
-                                     FEINT_ADJ(7, T, 9, 1)};
-    static const AdjVariant v7f[] = {FEINT_ADJ(7, T, 6, 2), FEINT_ADJ(7, T, 9, 2), FEINT_ADJ(7, T, 6, 3),
-                                     FEINT_ADJ(7, T, 9, 1)};
-    const AdjVariant *v7 = sizeof(T) == 8 ? v7d : v7f;
+    static const AdjVariant v1[] = {FEINT_ADJ(1, T, 1, 1), FEINT_ADJF(1, T, 2, 2)};
+    static const AdjVariant v2[] = {FEINT_ADJ(2, T, 2, 2), FEINT_ADJ(2, T, 2, 1), FEINT_ADJF(2, T, 3, 3)};
+    // from p = 3 the factorised kernel ("f") first, in the order measured per form
+    // (131072 elements at p = 3, 16384 at p = 5 and 7); the same shapes for both forms
+    static const AdjVariant v3d[] = {FEINT_ADJF(3, T, 4, 2), FEINT_ADJ(3, T, 3, 3), FEINT_ADJF(3, T, 4, 4),
+                                     FEINT_ADJ(3, T, 3, 1), FEINT_ADJ(3, T, 3, 2)};
+    static const AdjVariant v3f[] = {FEINT_ADJF(3, T, 4, 4), FEINT_ADJF(3, T, 4, 2), FEINT_ADJ(3, T, 3, 3),
+                                     FEINT_ADJ(3, T, 3, 1), FEINT_ADJ(3, T, 3, 2)};
+    static const AdjVariant v4[] = {FEINT_ADJF(4, T, 5, 2), FEINT_ADJF(4, T, 5, 1), FEINT_ADJ(4, T, 5, 2),
+                                    FEINT_ADJ(4, T, 5, 1), FEINT_ADJ(4, T, 3, 3)};
+    static const AdjVariant v5d[] = {FEINT_ADJF(5, T, 6, 2), FEINT_ADJF(5, T, 6, 1), FEINT_ADJ(5, T, 8, 2),
+                                     FEINT_ADJ(5, T, 4, 2), FEINT_ADJ(5, T, 8, 1)};
+    static const AdjVariant v5f[] = {FEINT_ADJF(5, T, 6, 1), FEINT_ADJF(5, T, 6, 2), FEINT_ADJ(5, T, 8, 2),
+                                     FEINT_ADJ(5, T, 4, 2), FEINT_ADJ(5, T, 8, 1)};
+    static const AdjVariant v6[] = {FEINT_ADJF(6, T, 7, 1), FEINT_ADJF(6, T, 4, 2), FEINT_ADJ(6, T, 7, 2),
+                                    FEINT_ADJ(6, T, 7, 1), FEINT_ADJ(6, T, 13, 1)};
+    static const AdjVariant v7d[] = {FEINT_ADJF(7, T, 8, 1), FEINT_ADJF(7, T, 4, 2), FEINT_ADJ(7, T, 6, 3),
+                                     FEINT_ADJ(7, T, 9, 2), FEINT_ADJ(7, T, 6, 2), FEINT_ADJ(7, T, 9, 1)};
+    static const AdjVariant v7f[] = {FEINT_ADJF(7, T, 8, 1), FEINT_ADJF(7, T, 4, 2), FEINT_ADJ(7, T, 6, 2),
+                                     FEINT_ADJ(7, T, 9, 2), FEINT_ADJ(7, T, 6, 3), FEINT_ADJ(7, T, 9, 1)};
+    static_assert(sizeof v3d == sizeof v3f && sizeof v5d == sizeof v5f && sizeof v7d == sizeof v7f,
+                  "one count per degree for both forms");
+    const bool f64 = sizeof(T) == 8;
 #define FEINT_AN(a) *count = (int)(sizeof(a) / sizeof(a[0])); return a
     switch (p) {
     case 1: FEINT_AN(v1);
     case 2: FEINT_AN(v2);
-    case 3: FEINT_AN(v3);
+    case 3: *count = (int)(sizeof(v3d) / sizeof(v3d[0])); return f64 ? v3d : v3f;
     case 4: FEINT_AN(v4);
-    case 5: FEINT_AN(v5);
+    case 5: *count = (int)(sizeof(v5d) / sizeof(v5d[0])); return f64 ? v5d : v5f;
     case 6: FEINT_AN(v6);
-    case 7: *count = (int)(sizeof(v7d) / sizeof(v7d[0])); return v7;
+    case 7: *count = (int)(sizeof(v7d) / sizeof(v7d[0])); return f64 ? v7d : v7f;
     }
 #undef FEINT_AN
     *count = 0;
@@ -400,6 +564,8 @@ feint_status adj_setup(const feint_elements *el, int p, feint_form form, const v
     prm.dX = dcoords; prm.dD = dD; prm.dbeta = dbeta; prm.dc = dc; prm.df = df;
     prm.qw = T->qw; prm.B64 = T->B64;
     prm.BT = form == FEINT_FP64 ? (const void *)T->BT64 : (const void *)T->BT32;
+    prm.tau = form == FEINT_FP64 ? (const void *)T->tau64 : (const void *)T->tau32;
+    prm.lamT = form == FEINT_FP64 ? (const void *)T->lam : (const void *)T->lam32;
     return FEINT_OK;
 }
 
@@ -468,7 +634,7 @@ feint_status feint_adjoint_tile_describe(int p, feint_form form, int tile, char 
     int cnt = 0;
     const AdjVariant *v = adj_variants(form, p, &cnt);
     if (!buf || len == 0 || tile < 0 || tile >= cnt) return FEINT_ERR_INVALID_ARG;
-    std::snprintf(buf, len, "%dx%d", v[tile].ta, v[tile].tb);
+    std::snprintf(buf, len, "%dx%d%s", v[tile].ta, v[tile].tb, v[tile].fact ? "f" : "");
     return FEINT_OK;
 }
 
