@@ -84,6 +84,15 @@ def kf_mfma_flops(p: int, rule: str = "collapsed", n: int = 0, nq_: int = 0) -> 
     return 2 * 16 * 16 * 4 * (nq_ // nk) * (nk * tt) ** 2
 
 
+def f_adjoint_factored(p: int, rule: str = "collapsed") -> int:
+    """Flops per element of the adjoint factorised along zeta: H_k = G^T tau
+    (8 n^2 nij), Hh = sum_k lam H_k (8 (p+1)^2 nij n), and per point the 16
+    sums over b of Hh B (32 nq n) with B's factor products (4 nq n)."""
+    n, nk, q = nshp(p), p + 1, nq(p, rule)
+    nij = q // nk
+    return 8 * n * n * nij + 8 * nk * nk * nij * n + 36 * q * n
+
+
 def is_kf_tile(desc: str) -> bool:
     """Tile descriptions "KxTNf" (optionally "o2") name the triangle-point contraction."""
     import re

@@ -104,3 +104,18 @@ def test_factored_count_hexahedra(p):
     flops = q * 4 * (6 * nt + 3 * n) + nk * nij * 4 * n * 2 * nk + n * n * 2 * 4 * nij
     assert cm.f_factored(n, nk, q) == flops
     assert cm.kf_mfma_flops(p, n=n, nq_=q) == 2048 * nij * (nk * -(-nt // 16)) ** 2
+
+
+@pytest.mark.parametrize("rule", ["collapsed", "symmetric"])
+@pytest.mark.parametrize("p", [1, 3])
+def test_adjoint_factored_count(p, rule):
+    """Loop walk of the factorised adjoint: H_k over the triangle index, Hh over
+    the zeta rows, and per point the 4x4 sums over b with B's factor products."""
+    n, nk, nt, q = cm.nshp(p), p + 1, cm.ntri(p), cm.nq(p, rule)
+    nij = q // nk
+    flops = 0
+    for _k in range(nk):
+        flops += sum(2 * nt for _b in range(n) for _col in range(4 * nij))     # H_k[b][(ij, r)]
+    flops += sum(2 * nk for _pt in range(q) for _r in range(4) for _b in range(n))   # Hh
+    flops += sum(4 + 16 * 2 for _pt in range(q) for _b in range(n))             # B products, S_q sums
+    assert cm.f_adjoint_factored(p, rule) == flops
