@@ -25,7 +25,8 @@
 // only u = sum_{s<3} W[r][s] tau_s(t') and v = W[r][3] tau_3(t') per point,
 // shared by its TN column tiles: Y[r][(k',t')] = L_k'(zeta_m) u + L'_k'(zeta_m) v.
 // The load vector rides in the spare padded column of the last t'-tile of
-// k' = 0: its Z_k carries sum_m lam_0(k,m) w det J f in row r = 0.
+// k' = 0: its Z_k carries sum_m lam_0(k,m) w det J f in row r = 0 (where ntri
+// is a multiple of 16 it is summed separately in FP64).
 #pragma once
 #include "fwd_kernels.h"
 
@@ -39,8 +40,11 @@ struct KF {
     static constexpr int BM = c_cdiv(NK, TMK), BK = c_cdiv(NK, TN), BN = TT * BK, NBLK = BM * BN;
     static constexpr int EPI = 1;
     static constexpr int CIJ = 64 / NK;                       // triangle points per chunk
-    static constexpr int LCT = TT - 1, LCL = NTRI - LCT * 16;  // load-vector column: tile (0, LCT), lane LCL
-    static_assert(NTRI % 16 != 0, "the load vector needs a spare padded column");
+    // The load vector rides in a spare padded column (tile (0, LCT), lane LCL) when ntri
+    // leaves one; otherwise (hexahedra at p = 3 and 7) the blocks of the first column tile
+    // accumulate it in FP64 beside the contraction.
+    static constexpr bool SPARE = NTRI % 16 != 0;
+    static constexpr int LCT = TT - 1, LCL = NTRI - LCT * 16;
     static_assert(NIJ * NK == NQ && NTRI * NK == N, "the rule and the basis must be products in zeta");
     static_assert(TN <= NK && TMK <= NK, "tile counts beyond the zeta factor");
     typedef typename AccT<T>::type V4;
@@ -70,7 +74,17 @@ struct KF {
         // the lane's column t' (tau is zero beyond ntri, so padding columns contribute
         // nothing without a mask) and the column factors L_k', L'_k' of its tiles
         const int tcol = tt * 16 + i16;
-        const bool lcol = kp0 == 0 && tt == LCT && i16 == LCL;
+        const bool lcol = SPARE && kp0 == 0 && tt == LCT && i16 == LCL;
+        // without a spare column: b[(k,t)] = sum_ij tau_0(t, ij) sum_m L_k(zeta_m) (w det J f)_(ij,m),
+        // in FP64 from the FP64 tables, by the blocks of the first column tile
+        const bool bblk = !SPARE && kp0 == 0 && tt == 0;
+        typedef const __attribute__((address_space(4))) double CD;
+        const CD *l64 = (const CD *)prm.lam;
+        double bacc[SPARE ? 1 : TMV][TT];
+#pragma unroll
+        for (int k = 0; k < (SPARE ? 1 : TMV); ++k)
+#pragma unroll
+            for (int ti = 0; ti < TT; ++ti) bacc[k][ti] = 0.0;
         // The column factors are the same for the whole wave and the table is never written
         // while kernels run: reading them through the constant address space lets them be
         // scalar loads into SGPRs instead of per-lane loads in the inner loop.
@@ -120,6 +134,19 @@ struct KF {
                 // keep the next point's loads at the top of the iteration, in flight under
                 // its arithmetic (the scheduler would otherwise sink them to the end)
                 __builtin_amdgcn_sched_barrier(0);
+                if constexpr (!SPARE) {
+                    if (bblk) {
+#pragma unroll
+                        for (int k = 0; k < TMV; ++k) {
+                            double sk = 0.0;
+#pragma unroll
+                            for (int m = 0; m < NK; ++m) sk += l64[(k0 + k) * NK + m] * sl.sf[il * NK + m];
+#pragma unroll
+                            for (int ti = 0; ti < TT; ++ti)
+                                bacc[k][ti] += prm.tau64[((size_t)(ij0 + il) * 4) * TP + ti * 16 + i16] * sk;
+                        }
+                    }
+                }
                 // the lane's row r = kg of W at the p+1 points of this triangle point, folded with
                 // the column's factors
                 T u[NK], v[NK], sfm[NK];
@@ -172,6 +199,15 @@ struct KF {
                         else if (tcol < NTRI)
                             Aout[(size_t)row * N + (kp0 + tj) * NTRI + tcol] = acc[k][ti][tj][r];
                     }
+        if constexpr (!SPARE) {
+            if (bblk && kg == 0) {
+#pragma unroll
+                for (int k = 0; k < TMV; ++k)
+#pragma unroll
+                    for (int ti = 0; ti < TT; ++ti)
+                        if (ti * 16 + i16 < NTRI) bout[(k0 + k) * NTRI + ti * 16 + i16] = (T)bacc[k][ti];
+            }
+        }
     }
 
     // Row blocks (TMK values of k) and column tiles (TN values of k') of the
