@@ -17,6 +17,8 @@ const FwdVariant v2[] = {
     FEINT_K4S(2, double, 2, 1, 8, 2),
     FEINT_KSC(2, double, 2, 2, 1), FEINT_KF_R(2, double, 3, 3, 2, 0)};
 const FwdVariant v3[] = {
+    FEINT_KF_R(3, double, 4, 2, 2, 0),
+    FEINT_KF_R(3, double, 4, 1, 2, 0),
     FEINT_KF_R(3, double, 4, 2, 1, 0),
     FEINT_K4S(3, double, 3, 3, 8, 1),
     FEINT_K4S(3, double, 3, 1, 8, 2),
