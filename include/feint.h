@@ -216,11 +216,14 @@ void feint_mixed_plan_destroy(feint_mixed_plan *plan);
 
 /* ---- Tile autotuning -------------------------------------------------------
    Each (degree, form) has several compiled variants: tile shapes of the MFMA
-   kernels (16x16 output tiles per wave) and, for FP64 and FP32 at p <= 3,
-   vector-ALU kernels that give each element a group of lanes (Sec. 2.2's
-   operation counts make the contraction too small at low degree to fill
-   MFMA tiles; which side of the crossover a degree falls on is what the
-   autotuner measures).  feint_autotune times each candidate with HIP
+   kernels (16x16 output tiles per wave), for FP64 and FP32 the kernels that
+   contract per triangle point (the rule and the basis factorised along
+   zeta: fewer flops, the default from p = 3), and for FP64 and FP32 at
+   p <= 3 vector-ALU kernels that give each element a group of lanes (Sec.
+   2.2's operation counts make the contraction too small at low degree to
+   fill MFMA tiles; which side of the crossover a degree falls on is what
+   the autotuner measures).  All variants compute the same A and b to the
+   form's rounding.  feint_autotune times each candidate with HIP
    events on the caller's inputs and outputs (ne elements, `reps`
    repetitions) and keeps the fastest for later calls; feint_tile_get/set
    read or force the choice (index into the candidate list). */
