@@ -441,8 +441,8 @@ struct KFA {
     }
 };
 
-template <class KER>
-__global__ __launch_bounds__(256) void adj_direct(AdjParams prm) {
+template <class KER, int MINW = 1>
+__global__ __launch_bounds__(256, MINW) void adj_direct(AdjParams prm) {
     __shared__ typename KER::Smem sm;
     const int wave = wave_uniform(threadIdx.x >> 6);
     const int64_t item = (int64_t)blockIdx.x * 4 + wave;
@@ -457,7 +457,7 @@ __global__ void zero_f64(double *p, int64_t n) {
 
 namespace {
 
-template <class KER>
+template <class KER, int MINW = 1>
 feint_status launch_adj(const AdjParams &prm, hipStream_t s) {
     if (KER::ATOMIC) {
         double *outs[5] = {prm.dX, prm.dD, prm.dbeta, prm.dc, prm.df};
@@ -469,7 +469,7 @@ feint_status launch_adj(const AdjParams &prm, hipStream_t s) {
     }
     const int64_t blocks = (prm.ne * KER::NBLK + 3) / 4;
     if (blocks > 0x7fffffffLL) return FEINT_ERR_TOO_LARGE;
-    hipLaunchKernelGGL(adj_direct<KER>, dim3((unsigned)blocks), dim3(256), 0, s, prm);
+    hipLaunchKernelGGL((adj_direct<KER, MINW>), dim3((unsigned)blocks), dim3(256), 0, s, prm);
     return FEINT_OK;
 }
 
@@ -481,23 +481,28 @@ feint_status launch_adj(const AdjParams &prm, hipStream_t s) {
 struct AdjVariant {
     int ta, tb;
     feint_status (*launch)(const AdjParams &, hipStream_t);
-    int fact;           // 1: factorised along zeta (KFA, TA = row indices k, TB = column tiles)
+    int fact;           // 1: factorised along zeta (KFA, TA = row indices k, TB = column tiles),
+                        // 2: the same with a two-waves-per-SIMD register budget
 };
 #define FEINT_ADJ(P, T, TA, TB) AdjVariant{TA, TB, &launch_adj<Adj<P, T, TA, TB, R>>, 0}
 #define FEINT_ADJF(P, T, TK, TB) AdjVariant{TK, TB, &launch_adj<KFA<P, T, TK, TB, R>>, 1}
+#define FEINT_ADJF2(P, T, TK, TB) AdjVariant{TK, TB, &launch_adj<KFA<P, T, TK, TB, R>, 2>, 2}
 
 template <typename T, int R>
 const AdjVariant *adj_variants_of(int p, int *count) {
     static const AdjVariant v1[] = {FEINT_ADJ(1, T, 1, 1), FEINT_ADJF(1, T, 2, 2)};
     static const AdjVariant v2[] = {FEINT_ADJ(2, T, 2, 2), FEINT_ADJ(2, T, 2, 1), FEINT_ADJF(2, T, 3, 3)};
-    // from p = 3 the factorised kernel ("f") first, in the order measured per form
-    // (131072 elements at p = 3, 16384 at p = 5 and 7); the same shapes for both forms
-    static const AdjVariant v3d[] = {FEINT_ADJF(3, T, 4, 2), FEINT_ADJ(3, T, 3, 3), FEINT_ADJF(3, T, 4, 4),
-                                     FEINT_ADJ(3, T, 3, 1), FEINT_ADJ(3, T, 3, 2)};
-    static const AdjVariant v3f[] = {FEINT_ADJF(3, T, 4, 4), FEINT_ADJF(3, T, 4, 2), FEINT_ADJ(3, T, 3, 3),
-                                     FEINT_ADJ(3, T, 3, 1), FEINT_ADJ(3, T, 3, 2)};
-    static const AdjVariant v4[] = {FEINT_ADJF(4, T, 5, 2), FEINT_ADJF(4, T, 5, 1), FEINT_ADJ(4, T, 5, 2),
-                                    FEINT_ADJ(4, T, 5, 1), FEINT_ADJ(4, T, 3, 3)};
+    // from p = 3 the factorised kernel ("f", "fo2" with two waves per SIMD) first, in the
+    // order measured per form (131072 elements at p = 3 and 4, 16384 at p = 5 and 7); the
+    // same shapes for both forms
+    static const AdjVariant v3d[] = {FEINT_ADJF2(3, T, 4, 2), FEINT_ADJ(3, T, 3, 3), FEINT_ADJF(3, T, 4, 2),
+                                     FEINT_ADJF(3, T, 4, 4), FEINT_ADJ(3, T, 3, 1), FEINT_ADJ(3, T, 3, 2),
+                                     FEINT_ADJF2(3, T, 4, 1)};
+    static const AdjVariant v3f[] = {FEINT_ADJF2(3, T, 4, 2), FEINT_ADJF(3, T, 4, 4), FEINT_ADJF(3, T, 4, 2),
+                                     FEINT_ADJ(3, T, 3, 3), FEINT_ADJ(3, T, 3, 1), FEINT_ADJ(3, T, 3, 2),
+                                     FEINT_ADJF2(3, T, 4, 1)};
+    static const AdjVariant v4[] = {FEINT_ADJF2(4, T, 5, 1), FEINT_ADJF(4, T, 5, 1), FEINT_ADJF(4, T, 5, 2),
+                                    FEINT_ADJ(4, T, 5, 2), FEINT_ADJ(4, T, 5, 1), FEINT_ADJ(4, T, 3, 3)};
     static const AdjVariant v5d[] = {FEINT_ADJF(5, T, 6, 2), FEINT_ADJF(5, T, 6, 1), FEINT_ADJ(5, T, 8, 2),
                                      FEINT_ADJ(5, T, 4, 2), FEINT_ADJ(5, T, 8, 1)};
     static const AdjVariant v5f[] = {FEINT_ADJF(5, T, 6, 1), FEINT_ADJF(5, T, 6, 2), FEINT_ADJ(5, T, 8, 2),
@@ -634,7 +639,7 @@ feint_status feint_adjoint_tile_describe(int p, feint_form form, int tile, char 
     int cnt = 0;
     const AdjVariant *v = adj_variants(form, p, &cnt);
     if (!buf || len == 0 || tile < 0 || tile >= cnt) return FEINT_ERR_INVALID_ARG;
-    std::snprintf(buf, len, "%dx%d%s", v[tile].ta, v[tile].tb, v[tile].fact ? "f" : "");
+    std::snprintf(buf, len, "%dx%d%s%s", v[tile].ta, v[tile].tb, v[tile].fact ? "f" : "", v[tile].fact == 2 ? "o2" : "");
     return FEINT_OK;
 }
 
