@@ -16,8 +16,10 @@ const FwdVariant d2[] = {FEINT_KF_HEX(2, double, 3, 3, 2),
     FEINT_KV_G(2, double, 32, 2, HexGeo),
     FEINT_K4U_HEX(2, double, 2, 2, 2),
     FEINT_K4U_HEX(2, double, 2, 1, 2)};
-const FwdVariant d3[] = {FEINT_KF_HEX(3, double, 4, 4, 1),
+const FwdVariant d3[] = {FEINT_KF_HEX(3, double, 4, 2, 2),
+    FEINT_KF_HEX(3, double, 4, 1, 2),
     FEINT_KF_HEX(3, double, 4, 2, 1),
+    FEINT_KF_HEX(3, double, 4, 4, 1),
     FEINT_K4U_HEX(3, double, 4, 1, 2),
     FEINT_K4U_HEX(3, double, 4, 2, 1),
     FEINT_K4U_HEX(3, double, 2, 2, 2)};
