@@ -522,8 +522,8 @@ static int make_tables(int type, int p, int n1, int nq, const double *qpts, cons
     } else {
         oracle_rule(n1, T->pts, T->w);
     }
-    /* step 6 of Algorithm 1: shape functions at every point (the same for
-       every element of degree p, so they are evaluated once) */
+    /* Algorithm 1's shape functions at every point (the same for every
+       element of degree p, so they are evaluated once) */
     for (int q = 0; q < T->nq; ++q)
         (type == 2 ? oracle_tet_basis : type ? oracle_hex_basis : oracle_basis)(
             p, T->pts + 3 * q, T->phi + (size_t)q * T->n, T->dphi + (size_t)3 * q * T->n);
@@ -574,19 +574,19 @@ static int integrate_core(int type, int p, int n1, int nq, const double *qpts, c
     int64_t e;
 #pragma omp parallel for schedule(static)
     for (e = 0; e < ne; ++e) {
-        const double *X = coords + (size_t)nx * e;  /* step 2: geometry data */
+        const double *X = coords + (size_t)nx * e;  /* geometry data of the element */
         double *Ae = A + (size_t)e * n * n, *bv = b + (size_t)e * n;
         double *gphys = (double *)malloc(sizeof(double) * 3 * n);
         double *Dg = (double *)malloc(sizeof(double) * 3 * n);
         double *bg = (double *)malloc(sizeof(double) * n);
         int bad = 0;
-        memset(Ae, 0, sizeof(double) * n * n);    /* step 4 */
+        memset(Ae, 0, sizeof(double) * n * n);    /* clear the element matrix */
         memset(bv, 0, sizeof(double) * n);
-        for (int q = 0; q < nqp; ++q) {           /* step 5 */
+        for (int q = 0; q < nqp; ++q) {           /* loop over quadrature points */
             const double *phi = T.phi + (size_t)q * n, *dphi = T.dphi + (size_t)3 * q * n;
             double J[9], K[9], det, x[3];
             bad |= (type == 2 ? oracle_tet_geometry : type ? oracle_hex_geometry : oracle_geometry)(
-                X, T.pts + 3 * q, J, &det, K, x);                                      /* step 7 */
+                X, T.pts + 3 * q, J, &det, K, x);                                      /* Jacobian, det, inverse */
             if (xq) for (int d = 0; d < 3; ++d) xq[((size_t)e * nqp + q) * 3 + d] = x[d];
             /* coefficients at the point */
             double De[9], be[3], ce, fe;
@@ -609,7 +609,7 @@ static int integrate_core(int type, int p, int n1, int nq, const double *qpts, c
                 }
             }
             double wd = T.w[q] * det;
-            for (int a = 0; a < n; ++a) {         /* step 8: grad phi = J^{-T} ref grad */
+            for (int a = 0; a < n; ++a) {         /* physical derivatives: grad phi = J^{-T} ref grad */
                 for (int d = 0; d < 3; ++d) {
                     double s = 0.0;
                     for (int l = 0; l < 3; ++l) s += K[3 * l + d] * dphi[3 * a + l];
@@ -622,7 +622,7 @@ static int integrate_core(int type, int p, int n1, int nq, const double *qpts, c
                 }
                 bg[a] = be[0] * gphys[3 * a] + be[1] * gphys[3 * a + 1] + be[2] * gphys[3 * a + 2];
             }
-            for (int a = 0; a < n; ++a) {         /* steps 9-12, CDR integrand */
+            for (int a = 0; a < n; ++a) {         /* double loop over shape functions, CDR integrand */
                 const double *ga = gphys + 3 * a;
                 for (int bb = 0; bb < n; ++bb) {
                     const double *Dgb = Dg + 3 * bb;

@@ -51,7 +51,7 @@ __device__ inline void load_elem(const double *__restrict__ coords, const double
 }
 
 // Geometry at one reference point (xi1, xi2, zeta) of the bilinear prism
-// (Algorithm 1, step 7).  With t = (1+zeta)/2 the map is
+// (the Jacobian of Algorithm 1).  With t = (1+zeta)/2 the map is
 // x = (1-t) T_bot(xi) + t T_top(xi), so the Jacobian columns are
 //   dx/dxi1 = (1-t)(v1-v0) + t(v4-v3),  dx/dxi2 = (1-t)(v2-v0) + t(v5-v3),
 //   dx/dzeta = ((v3-v0) l0 + (v4-v1) l1 + (v5-v2) l2) / 2,

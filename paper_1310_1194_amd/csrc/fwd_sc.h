@@ -1,7 +1,7 @@
 // Forward kernel that computes the shape functions at each point instead of
 // reading them from precomputed tables: the paper's SC strategy (Sec. 4: the
 // DD_SC and WF_SC variants compute shape functions and their derivatives in
-// step 8 of the point loop; the SR variants read them).  The paper builds
+// the point loop; the SR variants read them).  The paper builds
 // them from monomials in the vertical and, separately, the horizontal
 // direction combined by tensor-product rules; here the same tensor structure
 // of the prism basis phi_a = T_t(xi1, xi2) L_k(zeta), a = k ntri + t, gives

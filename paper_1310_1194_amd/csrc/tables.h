@@ -1,7 +1,7 @@
 // Reference tables of one polynomial degree: quadrature points and weights
 // and the shape-function values and reference gradients at every point,
-// laid out for the kernels.  These are the data the paper's Algorithm 1
-// reads in steps 3 and 6 (and, in Sec. 2.2, recommends keeping in fast memory
+// laid out for the kernels.  These are the quadrature data and shape
+// functions the paper's Algorithm 1 reads (and, in Sec. 2.2, recommends keeping in fast memory
 // because they are identical for every element of a degree).
 #pragma once
 #include <cstdint>
