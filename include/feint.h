@@ -60,7 +60,9 @@ typedef enum {
    its determinant and inverse and the per-point coefficient block W_q are
    always computed in FP64.  The load vector is formed by the same
    contraction (a spare padded column carries w det J f), so it carries the
-   form's precision; at p = 7 (no spare column) it is accumulated in FP64. */
+   form's precision; where a kernel has no spare column (the point-by-point
+   kernels at p = 7, the factorised hexahedral kernel at p = 3 and 7) it is
+   accumulated in FP64. */
 typedef enum {
     FEINT_FP64 = 0,    /* FP64 MFMA, FP64 outputs */
     FEINT_FP32 = 1,    /* FP32 MFMA, FP32 outputs */
@@ -234,8 +236,9 @@ feint_status feint_tile_set(int p, feint_form form, int tile);
    "s" (table staged in LDS), "sa" (A operands staged), "p" (K loop
    software-pipelined) or "c" (shape functions computed at each point from
    their tensor-product factors, no table read: the paper's SC strategy,
-   Sec. 4), or "KxTNf" (contraction per triangle point: K zeta rows of
-   shape functions by TN column tiles per wave, FP64 and FP32 on prisms),
+   Sec. 4), or "KxTNf" (contraction per triangle point, or per plane point
+   for hexahedra: K zeta rows of shape functions by TN column tiles per
+   wave, FP64 and FP32),
    or "vL" (vector-ALU kernel, L lanes per element); "o2" marks a
    two-waves-per-SIMD register budget. */
 feint_status feint_tile_describe(int p, feint_form form, int tile, char *buf, size_t len);
@@ -299,8 +302,9 @@ feint_status feint_integrate_adjoint_rule(const feint_elements *el, int p, feint
    j) n1 + i.  Inputs as feint_elements with coords [ne][8][3]; outputs
    A [ne][n][n] (row = test function), b [ne][n], n = (p+1)^3; xq (nullable)
    [ne][(p+1)^3][3]; dev_status as feint_integrate.  All four forms (FP64
-   and FP32 on the 16x16x4 MFMA kernel, bf16x3 and fp16x3 on the 16x16x32
-   split kernel).  Variants, tile selection and autotuning as for prisms. */
+   and FP32 on the 16x16x4 MFMA kernels, point by point or factorised along
+   zeta per plane point; bf16x3 and fp16x3 on the 16x16x32 split kernel).
+   Variants, tile selection and autotuning as for prisms. */
 int feint_hex_nshp(int p);
 int feint_hex_nq(int p);
 feint_status feint_prepare_hex(int p);
