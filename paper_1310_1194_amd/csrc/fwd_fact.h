@@ -55,7 +55,9 @@ struct KF {
     };
     struct Smem { Slice w[4]; };
 
-    template <int TMV, int TNV>
+    // LB: this block holds the load-vector column (a compile-time flag, so the blocks
+    // without it run a loop with no load-vector work at all)
+    template <int TMV, int TNV, bool LB>
     __device__ static void body(const FwdParams &prm, int64_t slot, int blk, int bi, int bj, Slice &sl) {
         const int lane = threadIdx.x & 63;
         const int i16 = lane & 15, kg = lane >> 4;
@@ -74,7 +76,12 @@ struct KF {
         // the lane's column t' (tau is zero beyond ntri, so padding columns contribute
         // nothing without a mask) and the column factors L_k', L'_k' of its tiles
         const int tcol = tt * 16 + i16;
-        const bool lcol = SPARE && kp0 == 0 && tt == LCT && i16 == LCL;
+        // lsel is 1 on the load-vector lane of row r = 0, else 0: that lane's column is
+        // padding, where tau is zero and so is its Y, so Y + lsel w det J f places w det J f
+        // there exactly and leaves every other lane unchanged, without a lane-dependent
+        // branch around the Y arithmetic.
+        const bool lcol = LB && i16 == LCL;
+        const T lsel = (lcol && kg == 0) ? (T)1 : (T)0;
         // without a spare column: b[(k,t)] = sum_ij tau_0(t, ij) sum_m L_k(zeta_m) (w det J f)_(ij,m),
         // in FP64 from the FP64 tables, by the blocks of the first column tile
         const bool bblk = !SPARE && kp0 == 0 && tt == 0;
@@ -155,7 +162,7 @@ struct KF {
                     const T *wr = &sl.W[il * NK + m][4 * kg];
                     u[m] = wr[0] * tb[0] + wr[1] * tb[1] + wr[2] * tb[2];
                     v[m] = wr[3] * tb[3];
-                    sfm[m] = kg == 0 ? (T)sl.sf[il * NK + m] : (T)0;
+                    sfm[m] = LB ? lsel * (T)sl.sf[il * NK + m] : (T)0;
                 }
 #pragma unroll
                 for (int tj = 0; tj < TNV; ++tj) {
@@ -163,7 +170,7 @@ struct KF {
 #pragma unroll
                     for (int m = 0; m < NK; ++m) {
                         const T yv = lv[tj * NK + m] * u[m] + ld[tj * NK + m] * v[m];
-                        y[m] = (tj == 0 && lcol) ? sfm[m] : yv;   // the load-vector column carries w det J f
+                        y[m] = (LB && tj == 0) ? yv + sfm[m] : yv;     // the load-vector column carries w det J f
                     }
 #pragma unroll
                     for (int k = 0; k < TMV; ++k) {
@@ -210,18 +217,28 @@ struct KF {
         }
     }
 
+    template <int TMV, int TNV>
+    __device__ static void with_lb(bool lb, const FwdParams &prm, int64_t slot, int blk, int bi, int bj, Slice &sl) {
+        if (lb) body<TMV, TNV, true>(prm, slot, blk, bi, bj, sl);
+        else body<TMV, TNV, false>(prm, slot, blk, bi, bj, sl);
+    }
+
     // Row blocks (TMK values of k) and column tiles (TN values of k') of the
     // last blocks are compile-time counts, so the loops carry no bounds tests.
     __device__ static void run_slice(const FwdParams &prm, int64_t slot, int blk, Slice &sl) {
         const int bi = blk / BN, bj = blk % BN;
         constexpr int TML = NK - (BM - 1) * TMK, TNL = NK - (BK - 1) * TN;
-        const bool lastn = bj % BK == BK - 1;
-        if (bi == BM - 1) {
-            if (lastn) body<TML, TNL>(prm, slot, blk, bi, bj, sl);
-            else body<TML, TN>(prm, slot, blk, bi, bj, sl);
+        // one call site per distinct (row count, column count): where the last blocks have
+        // the regular counts the body is inlined once, not twice
+        const bool lastm = TML != TMK && bi == BM - 1, lastn = TNL != TN && bj % BK == BK - 1;
+        // the load-vector column: first column tile (k' = 0) of the last triangle tile
+        const bool lb = SPARE && bj % BK == 0 && bj / BK == LCT;
+        if (lastm) {
+            if (lastn) with_lb<TML, TNL>(lb, prm, slot, blk, bi, bj, sl);
+            else with_lb<TML, TN>(lb, prm, slot, blk, bi, bj, sl);
         } else {
-            if (lastn) body<TMK, TNL>(prm, slot, blk, bi, bj, sl);
-            else body<TMK, TN>(prm, slot, blk, bi, bj, sl);
+            if (lastn) with_lb<TMK, TNL>(lb, prm, slot, blk, bi, bj, sl);
+            else with_lb<TMK, TN>(lb, prm, slot, blk, bi, bj, sl);
         }
     }
     __device__ static void run(const FwdParams &prm, int64_t slot, int blk, int wave, Smem &sm) {
