@@ -310,10 +310,10 @@ const MixVariant *mix_variants(int form, int *count) {
                      K4<5, float, 8, 2>, K4<6, float, 13, 1>>("1x1,2x2,3x3,5x3,8x2,13x1"),
     };
     static const MixVariant f64[] = {
-        make_variant<KV<1, double, 8>, KV<2, double, 18>, KF<3, double, 4, 2>, KF<4, double, 5, 3>,
-                     KF<5, double, 6, 1>, KF<6, double, 4, 2>>("v8,v18,4x2f,5x3f,6x1f,4x2f"),
         make_variant<KV<1, double, 8>, KV<2, double, 18>, KF<3, double, 4, 2>, KF<4, double, 5, 5>,
                      KF<5, double, 3, 2>, KF<6, double, 7, 1>>("v8,v18,4x2f,5x5f,3x2f,7x1f"),
+        make_variant<KV<1, double, 8>, KV<2, double, 18>, KF<3, double, 4, 2>, KF<4, double, 5, 3>,
+                     KF<5, double, 6, 1>, KF<6, double, 4, 2>>("v8,v18,4x2f,5x3f,6x1f,4x2f"),
         make_variant<KV<1, double, 8>, KV<2, double, 18>, K4<3, double, 3, 3>, K4<4, double, 5, 3>,
                      K4<5, double, 8, 4>, K4<6, double, 13, 2>>("v8,v18,3x3,5x3,8x4,13x2"),
         make_variant<KV<1, double, 8>, KV<2, double, 18>, K4<3, double, 3, 3>, K4<4, double, 5, 1>,
