@@ -33,6 +33,7 @@ const FwdVariant v4[] = {
     FEINT_K4U(4, double, 5, 1, 2),
     FEINT_KSC(4, double, 5, 3, 1)};
 const FwdVariant v5[] = {
+    FEINT_KF_R(5, double, 6, 2, 1, 0),
     FEINT_KF_R(5, double, 3, 2, 1, 0),
     FEINT_KF_R(5, double, 6, 1, 1, 0),
     FEINT_K4U(5, double, 8, 1, 2),
@@ -45,8 +46,9 @@ const FwdVariant v6[] = {
     FEINT_K4S(6, double, 13, 1, 4, 1),
     FEINT_KSC(6, double, 13, 1, 1)};
 const FwdVariant v7[] = {
+    FEINT_KF_R(7, double, 4, 2, 1, 0),
+    FEINT_KF_R(7, double, 2, 2, 1, 0),
     FEINT_KF_R(7, double, 4, 1, 1, 0),
-    FEINT_KF_R(7, double, 3, 1, 1, 0),
     FEINT_K4U(7, double, 9, 2, 1),
     FEINT_K4U(7, double, 6, 2, 1),
     FEINT_KSC(7, double, 6, 2, 1)};

@@ -311,6 +311,8 @@ const MixVariant *mix_variants(int form, int *count) {
     };
     static const MixVariant f64[] = {
         make_variant<KV<1, double, 8>, KV<2, double, 18>, KF<3, double, 4, 2>, KF<4, double, 5, 5>,
+                     KF<5, double, 6, 2>, KF<6, double, 7, 1>>("v8,v18,4x2f,5x5f,6x2f,7x1f"),
+        make_variant<KV<1, double, 8>, KV<2, double, 18>, KF<3, double, 4, 2>, KF<4, double, 5, 5>,
                      KF<5, double, 3, 2>, KF<6, double, 7, 1>>("v8,v18,4x2f,5x5f,3x2f,7x1f"),
         make_variant<KV<1, double, 8>, KV<2, double, 18>, KF<3, double, 4, 2>, KF<4, double, 5, 3>,
                      KF<5, double, 6, 1>, KF<6, double, 4, 2>>("v8,v18,4x2f,5x3f,6x1f,4x2f"),
