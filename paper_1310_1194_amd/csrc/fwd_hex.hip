@@ -32,8 +32,9 @@ const FwdVariant d5[] = {FEINT_KF_HEX(5, double, 3, 2, 1),
     FEINT_KF_HEX(5, double, 2, 2, 1),
     FEINT_K4U_HEX(5, double, 7, 2, 1),
     FEINT_K4U_HEX(5, double, 14, 1, 1)};
-const FwdVariant d6[] = {FEINT_KF_HEX(6, double, 2, 2, 1),
-    FEINT_KF_HEX(6, double, 3, 1, 1),
+const FwdVariant d6[] = {FEINT_KF_HEX(6, double, 4, 1, 1),
+    FEINT_KF_HEX(6, double, 3, 2, 1),
+    FEINT_KF_HEX(6, double, 2, 2, 1),
     FEINT_K4U_HEX(6, double, 8, 2, 1),
     FEINT_K4U_HEX(6, double, 11, 1, 1),
     FEINT_K4U_HEX(6, double, 6, 2, 1)};
