@@ -29,6 +29,7 @@ const FwdVariant v4[] = {
     FEINT_K4U(4, float, 5, 5, 1),
     FEINT_KSC(4, float, 5, 5, 1)};
 const FwdVariant v5[] = {
+    FEINT_KF_R(5, float, 6, 6, 1, 0),
     FEINT_KF_R(5, float, 6, 3, 1, 0),
     FEINT_K4U(5, float, 8, 8, 1),
     FEINT_K4S(5, float, 8, 2, 8, 2),

@@ -21,7 +21,7 @@ const FwdVariant f1[] = {FEINT_KV_R(1, float, 8, 2, S), FEINT_K4S_R(1, float, 1,
 const FwdVariant f2[] = {FEINT_KV_R(2, float, 18, 2, S), FEINT_K4S_R(2, float, 2, 2, 8, 1, S), FEINT_KSC_R(2, float, 2, 2, 1, S), FEINT_KF_R(2, float, 3, 3, 2, S)};
 const FwdVariant f3[] = {FEINT_KF_R(3, float, 4, 4, 2, S), FEINT_K4S_R(3, float, 3, 3, 8, 1, S), FEINT_KV_R(3, float, 40, 2, S), FEINT_KSC_R(3, float, 3, 3, 1, S)};
 const FwdVariant f4[] = {FEINT_KF_R(4, float, 5, 3, 1, S), FEINT_KF_R(4, float, 5, 5, 1, S), FEINT_K4U_R(4, float, 5, 5, 1, S), FEINT_K4S_R(4, float, 5, 5, 8, 1, S), FEINT_KSC_R(4, float, 5, 5, 1, S)};
-const FwdVariant f5[] = {FEINT_KF_R(5, float, 6, 3, 1, S), FEINT_K4S_R(5, float, 8, 4, 8, 1, S), FEINT_K4U_R(5, float, 8, 8, 1, S), FEINT_KSC_R(5, float, 8, 4, 1, S)};
+const FwdVariant f5[] = {FEINT_KF_R(5, float, 6, 6, 1, S), FEINT_KF_R(5, float, 6, 3, 1, S), FEINT_K4S_R(5, float, 8, 4, 8, 1, S), FEINT_K4U_R(5, float, 8, 8, 1, S), FEINT_KSC_R(5, float, 8, 4, 1, S)};
 const FwdVariant f6[] = {FEINT_KF_R(6, float, 7, 4, 1, S), FEINT_KF_R(6, float, 7, 3, 1, S), FEINT_K4S_R(6, float, 13, 2, 8, 1, S), FEINT_K4U_R(6, float, 13, 4, 1, S), FEINT_KSC_R(6, float, 13, 2, 1, S)};
 const FwdVariant f7[] = {FEINT_KF_R(7, float, 8, 2, 1, S), FEINT_K4U_R(7, float, 9, 6, 1, S), FEINT_K4U_R(7, float, 9, 3, 1, S), FEINT_KSC_R(7, float, 9, 3, 1, S)};
 // bf16x3
