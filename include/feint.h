@@ -191,7 +191,13 @@ feint_status feint_integrate_mixed(feint_mixed_plan *plan, const feint_elements 
                                    uint32_t *dev_status, void *stream);
 
 /* Capture bucketing + persistent launch for fixed pointers into a HIP graph
-   held by the plan (replaces any previous one), then instantiate it. */
+   held by the plan (replaces any previous one), then instantiate it.
+   Capturing runs nothing: the captured bucketing first happens when the
+   graph is launched, so until then feint_integrate_mixed and
+   feint_mixed_autotune still see only the last eager feint_mixed_bucket
+   (INVALID_ARG, with no launch, if there was none for this ne).  The
+   pointers are baked into the graph: the caller keeps every captured
+   buffer alive until the plan is destroyed or captures again. */
 feint_status feint_mixed_graph_capture(feint_mixed_plan *plan, const feint_elements *el,
                                        const int8_t *p, void *A_packed, void *b_packed,
                                        int64_t *offA, int64_t *offb, uint32_t *dev_status,

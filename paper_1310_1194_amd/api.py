@@ -419,6 +419,7 @@ class MixedPlan:
         if getattr(self, "_h", None) and self._h.value:
             lib().feint_mixed_plan_destroy(self._h)
             self._h = ctypes.c_void_p()
+        self._captured = None
 
     def __del__(self):
         try:
@@ -450,11 +451,18 @@ class MixedPlan:
                                                                    _ptr(offA), _ptr(offb), _ptr(status), _stream()))
 
     def capture(self, coords, D, beta, c, f, p, A, b, offA, offb, status=None):
-        """Capture bucketing + persistent launch for these buffers into a HIP graph."""
+        """Capture bucketing + persistent launch for these buffers into a HIP graph.
+
+        The graph holds raw device pointers, so the plan keeps references to
+        every captured tensor until the next capture or close(): a replay
+        never writes into memory the caching allocator has handed out again.
+        """
         el = elements(coords, D, beta, c, f)
+        self._captured = None
         check("feint_mixed_graph_capture",
               lib().feint_mixed_graph_capture(self._h, ctypes.byref(el), _ptr(p), _ptr(A), _ptr(b), _ptr(offA),
                                               _ptr(offb), _ptr(status), _stream()))
+        self._captured = (coords, D, beta, c, f, p, A, b, offA, offb, status)
 
     def replay(self):
         check("feint_mixed_graph_launch", lib().feint_mixed_graph_launch(self._h, _stream()))

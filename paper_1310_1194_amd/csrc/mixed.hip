@@ -339,7 +339,8 @@ struct feint_mixed_plan {
     int dev = 0;
     int form = 0;
     int64_t ne_max = 0, nblk_max = 0;
-    int64_t ne_bucketed = -1;
+    int64_t ne_bucketed = -1;    // batch size the plan's bucketing scratch holds (-1: none yet)
+    int64_t ne_captured = -1;    // batch size the captured graph buckets when it is launched
     char *scratch = nullptr;
     MixedHdr *hdr = nullptr;
     int64_t *blk_sums = nullptr;
@@ -487,6 +488,7 @@ feint_status feint_mixed_graph_capture(feint_mixed_plan *pl, const feint_element
     if (el->ne > 0 && (!p || !A || !b)) return FEINT_ERR_INVALID_ARG;
     if (!offA || !offb) return FEINT_ERR_INVALID_ARG;
     drop_graph(pl);
+    pl->ne_captured = -1;
     hipError_t e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail("hipStreamBeginCapture", e);
     s = enqueue_bucket(pl, p, el->ne, offA, offb, dev_status, pl->cap_stream);
@@ -504,7 +506,9 @@ feint_status feint_mixed_graph_capture(feint_mixed_plan *pl, const feint_element
         drop_graph(pl);
         return hip_fail("hipGraphInstantiate", e);
     }
-    pl->ne_bucketed = el->ne;
+    // Capturing runs nothing: the bucketing scratch still holds whatever the last eager
+    // bucketing (if any) left there, so ne_bucketed is unchanged until the graph runs.
+    pl->ne_captured = el->ne;
     return FEINT_OK;
 }
 
@@ -512,7 +516,9 @@ feint_status feint_mixed_graph_launch(feint_mixed_plan *pl, void *stream) {
     if (!pl) return FEINT_ERR_INVALID_ARG;
     if (!pl->exec) return FEINT_ERR_NOT_PREPARED;
     hipError_t e = hipGraphLaunch(pl->exec, (hipStream_t)stream);
-    return e == hipSuccess ? FEINT_OK : hip_fail("hipGraphLaunch", e);
+    if (e != hipSuccess) return hip_fail("hipGraphLaunch", e);
+    pl->ne_bucketed = pl->ne_captured;      // the graph's bucketing rewrites the scratch
+    return FEINT_OK;
 }
 
 feint_status feint_mixed_autotune(feint_mixed_plan *pl, const feint_elements *el, void *A, void *b,

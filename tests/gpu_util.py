@@ -28,6 +28,23 @@ def rel_errors(got, ref):
     return float(glob), float(per.max())
 
 
+def grad_errors(got, ref, floor=1e-3):
+    """Errors of one gradient array, [ne, ...]: (global relative Frobenius
+    error, max over elements of ||got_e - ref_e|| / d_e).  d_e is the element's
+    own reference norm, floored at `floor` times the root-mean-square of those
+    norms over the batch, so that an element whose gradient happens to be
+    nearly zero (dc, df are single sums of random terms) is judged on the
+    batch's scale rather than on its own."""
+    ne = ref.shape[0]
+    got = np.asarray(got, dtype=np.float64).reshape(ne, -1)
+    ref = np.asarray(ref, dtype=np.float64).reshape(ne, -1)
+    glob = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    nrm = np.linalg.norm(ref, axis=1)
+    d = np.maximum(nrm, floor * np.sqrt(np.mean(nrm ** 2)))
+    per = np.linalg.norm(got - ref, axis=1) / d
+    return float(glob), float(per.max())
+
+
 def oracle_of(batch, p):
     return oracle.integrate(p, batch.coords, batch.D, batch.beta, batch.c, batch.f)
 

@@ -1,19 +1,41 @@
 """GPU parity of the adjoint (gradients of sum_e <G_e,A_e> + <g_e,b_e>) against
 the oracle's reverse-mode gradient and against central differences.
 
-Tolerances (relative Frobenius error per gradient array):
-  fp64  1e-11 (blocks of G summed with FP64 atomics for p >= 4 reorder sums);
-  fp32  2e-5 (G, B and U = B G in FP32; S_q and the chain rule in FP64).
+Tolerances, per gradient array (dcoords, dD, dbeta, dc, df): the global
+relative Frobenius error over the batch, and the maximum over elements of
+the element's error relative to its own reference norm (floored at 1e-2 of
+the batch's root-mean-square element norm, because dc and df are single sums
+of terms of random sign that can cancel to near zero; `gpu_util.grad_errors`):
+  fp64  1e-11 global, 1e-10 per element (partial gradients of the waves that
+        share an element are summed with FP64 atomics, in varying order;
+        measured <= 6e-15 global, 6e-13 per element);
+  fp32  4e-6 global, 5e-5 per element (G, the tables and the products U, T
+        accumulated in FP32 over K = n or 4 nij terms, u = 2^-24 times
+        sqrt(K) times the cancellation ratio; S_q and the chain rule in FP64;
+        measured <= 3.4e-7 global, 8e-6 per element).
+The FP32 adjoint is also held against central differences (h = 1e-6) of the
+FP64 forward on the sampled elements of the p = 3 workload: 1e-5 per element
+(FP32 rounding of the contraction, ~1e-7, plus the differences' own
+truncation and cancellation error, ~1e-8).
 """
 import numpy as np
 import pytest
 
-from gpu_util import flush, small_batch, to_dev
+from gpu_util import flush, grad_errors, small_batch, to_dev
 
 pytestmark = pytest.mark.gpu
 
 NAMES = ("dcoords", "dD", "dbeta", "dc", "df")
-TOL = {"fp64": 1e-11, "fp32": 2e-5}
+TOL = {"fp64": (1e-11, 1e-10), "fp32": (4e-6, 5e-5)}
+
+
+def check_grads(got, ref, form, sel=None, tag=""):
+    """Every gradient array against the oracle, globally and per element."""
+    for name, a, r in zip(NAMES, got, ref[:5]):
+        a = a[sel] if sel is not None else a
+        g, m = grad_errors(a.cpu().numpy(), r, floor=1e-2)
+        flush(f"    {name}{tag}: global {g:.3e} max-elem {m:.3e}")
+        assert g <= TOL[form][0] and m <= TOL[form][1], name
 
 
 @pytest.fixture(scope="module")
@@ -50,10 +72,7 @@ def test_adjoint_parity(torch_cuda, p, form):
         flush(f"[adjoint] p={p} form={form} block {F.adjoint_tile_describe(p, form, tile)} ne={batch.ne}")
         got = F.adjoint_raw(*X, Gd, gd, p, form)
         torch.cuda.synchronize()
-        for name, a, r in zip(NAMES, got, ref[:5]):
-            e = rel(a.cpu().numpy(), r)
-            flush(f"    {name}: {e:.3e}")
-            assert e <= TOL[form], name
+        check_grads(got, ref, form)
     F.adjoint_tile_set(p, form, 0)
 
 
@@ -78,8 +97,7 @@ def test_adjoint_autotune(torch_cuda):
     got = F.adjoint_raw(*X, Gd, gd, p, "fp64")
     torch.cuda.synchronize()
     ref = oracle.adjoint(p, batch.coords, batch.D, batch.beta, batch.c, batch.f, G, g)
-    for a, r in zip(got, ref[:5]):
-        assert rel(a.cpu().numpy(), r) <= TOL["fp64"]
+    check_grads(got, ref, "fp64")
     F.adjoint_tile_set(p, "fp64", 0)
 
 
@@ -101,9 +119,10 @@ def test_autograd_function(torch_cuda):
 
 @pytest.mark.parametrize("form", ["fp64", "fp32"])
 def test_adjoint_full_size_sampled(torch_cuda, form):
-    """The p=3 adjoint workload (64x64x16 mesh, 131072 elements, G, g ~ N(0,1)):
-    the 64 sampled elements against the oracle gradient and against central
-    differences (h = 1e-6) of the GPU FP64 forward."""
+    """The p=3 adjoint workload (64x64x16 mesh, 131072 elements, G, g ~ N(0,1)),
+    in the benchmark's launch configuration (block shape autotuned first): the
+    64 sampled elements against the oracle gradient and, in both forms, against
+    central differences (h = 1e-6) of the GPU FP64 forward."""
     import oracle
     import paper_1310_1194_amd as F
     from paper_1310_1194_amd import meshgen
@@ -115,6 +134,8 @@ def test_adjoint_full_size_sampled(torch_cuda, form):
     flush(f"[adjoint-full] form={form} ne={batch.ne}")
     X = to_dev(batch)
     Gd, gd = torch.from_numpy(G).cuda().to(dt), torch.from_numpy(g).cuda().to(dt)
+    ms = F.adjoint_autotune(*X, Gd, gd, p, form, reps=1)
+    flush(f"    autotuned block {F.adjoint_tile_describe(p, form, F.adjoint_tile_get(p, form))}: {ms:.3f} ms")
     grads = F.adjoint_raw(*X, Gd, gd, p, form)
     torch.cuda.synchronize()
     sub = batch.subset(sample)
@@ -124,13 +145,8 @@ def test_adjoint_full_size_sampled(torch_cuda, form):
         gs = gs.astype(np.float32).astype(np.float64)
     ref = oracle.adjoint(p, sub.coords, sub.D, sub.beta, sub.c, sub.f, Gs, gs)
     si = torch.from_numpy(sample).cuda()
-    for name, a, r in zip(NAMES, grads, ref[:5]):
-        e = rel(a[si].cpu().numpy(), r)
-        flush(f"    {name} vs oracle: {e:.3e}")
-        assert e <= TOL[form]
-    if form != "fp64":
-        return
-    # central differences of the GPU forward, all 32 inputs of the 64 elements
+    check_grads(grads, ref, form, si, " vs oracle")
+    # central differences of the GPU FP64 forward, all 32 inputs of the 64 elements
     h = 1e-6
     m = len(sample)
     flat = np.concatenate([sub.coords.reshape(m, 18), sub.D.reshape(m, 9), sub.beta, sub.c[:, None], sub.f[:, None]], 1)
@@ -142,6 +158,7 @@ def test_adjoint_full_size_sampled(torch_cuda, form):
     A, b = F.integrate_raw(*Xp, p, "fp64")
     Ae = A.cpu().numpy().reshape(m, 64, -1)
     be = b.cpu().numpy().reshape(m, 64, -1)
+    # the FP32 adjoint saw G, g rounded to FP32: differentiate the same loss
     Le = np.einsum("mkij,mij->mk", Ae.reshape(m, 64, F.nshp(p), F.nshp(p)), Gs) + np.einsum("mki,mi->mk", be, gs)
     fd = (Le[:, :32] - Le[:, 32:]) / (2 * h)
     got = np.concatenate([grads[0][si].cpu().numpy().reshape(m, 18), grads[1][si].cpu().numpy().reshape(m, 9),
@@ -149,7 +166,7 @@ def test_adjoint_full_size_sampled(torch_cuda, form):
                           grads[4][si].cpu().numpy()[:, None]], 1)
     err = np.linalg.norm(fd - got, axis=1) / np.linalg.norm(got, axis=1)
     flush(f"    central differences: max per-element rel err {err.max():.3e}")
-    assert err.max() < 1e-6
+    assert err.max() < (1e-6 if form == "fp64" else 1e-5)
 
 
 @pytest.mark.parametrize("form", ["fp64", "fp32"])
@@ -165,7 +182,10 @@ def test_adjoint_p7_full_size_sampled(torch_cuda, form):
     dt = torch.float64 if form == "fp64" else torch.float32
     G, g, sample = meshgen.adjoint_seeds_device(batch, p, seed=4, dtype=dt)
     flush(f"[adjoint-p7] form={form} ne={batch.ne}")
-    grads = F.adjoint_raw(*to_dev(batch), G, g, p, form)
+    X = to_dev(batch)
+    ms = F.adjoint_autotune(*X, G, g, p, form, reps=1)
+    flush(f"    autotuned block {F.adjoint_tile_describe(p, form, F.adjoint_tile_get(p, form))}: {ms:.3f} ms")
+    grads = F.adjoint_raw(*X, G, g, p, form)
     torch.cuda.synchronize()
     si = torch.from_numpy(sample).cuda()
     Gs = G[si].double().cpu().numpy()
@@ -173,7 +193,4 @@ def test_adjoint_p7_full_size_sampled(torch_cuda, form):
     del G, g
     sub = batch.subset(sample)
     ref = oracle.adjoint(p, sub.coords, sub.D, sub.beta, sub.c, sub.f, Gs, gs)
-    for name, a, r in zip(NAMES, grads, ref[:5]):
-        e = rel(a[si].cpu().numpy(), r)
-        flush(f"    {name} vs oracle: {e:.3e}")
-        assert e <= TOL[form]
+    check_grads(grads, ref, form, si, " vs oracle")

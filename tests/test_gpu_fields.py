@@ -10,7 +10,7 @@ from gpu_util import flush, rel_errors, small_batch
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": (1e-12, 1e-12), "fp32": (1e-5, 1e-4), "bf16x3": (1e-5, 2e-4), "fp16x3": (1e-5, 1e-4)}
+TOL = {"fp64": (1e-12, 1e-12), "fp32": (2e-6, 2e-5), "bf16x3": (1e-5, 5e-5), "fp16x3": (2e-6, 2e-5)}   # derivation: test_gpu_forward.py
 
 
 @pytest.fixture(scope="module")

@@ -3,11 +3,18 @@
 Tolerances (relative Frobenius error against the oracle, per result A and b,
 global over the batch and maximum over single elements):
   fp64    1e-12 global and per element (the target of the method's FP64 form);
-  bf16x3  1e-5 global; per element 2e-4 (nearly degenerate elements);
-  fp32    1e-5 global; per element 1e-4 (W_q and B rounded to FP32, FP32 sums
-          of K = 4 nq terms: sqrt(K) * 2^-24 * (sum |terms| / |entry|));
-  fp16x3  1e-5 global; per element 1e-4 (hi+lo fp16 keeps 22 bits, the FP32
-          accumulation dominates as for fp32).
+  bf16x3  1e-5 global (the target of the split form); per element 5e-5: the
+          split keeps 16 bits of each operand, so the neglected lo*lo product
+          and the FP32 accumulation leave ~2^-17 relative per term, summed
+          over K = 4 nq terms with cancellation (measured <= 4e-6 on A,
+          6e-6 on b, at every degree and tile);
+  fp32    2e-6 global, 2e-5 per element: W_q and the tables rounded to FP32
+          (u = 2^-24) and FP32 sums of K terms give sqrt(K) u (sum |terms| /
+          |entry|) per entry, i.e. 1e-6 to 1e-5 for the largest cancellation
+          ratios of these meshes and a few 1e-7 in the Frobenius norm
+          (measured <= 9e-7 global and per element);
+  fp16x3  as fp32 (hi+lo fp16 keeps 22 bits of each operand, so the FP32
+          accumulation dominates; measured <= 6e-7).
 The load vector is formed by the same contraction as A (a spare padded
 column of Y carries w det J f), so it carries the form's precision and is held
 to the same tolerances as A; at p = 7 (no spare column) it is accumulated in
@@ -20,7 +27,7 @@ from gpu_util import flush, oracle_of, rel_errors, small_batch, to_dev
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": (1e-12, 1e-12), "fp32": (1e-5, 1e-4), "bf16x3": (1e-5, 2e-4), "fp16x3": (1e-5, 1e-4)}
+TOL = {"fp64": (1e-12, 1e-12), "fp32": (2e-6, 2e-5), "bf16x3": (1e-5, 5e-5), "fp16x3": (2e-6, 2e-5)}
 BTOL = TOL
 
 
@@ -107,11 +114,16 @@ def test_empty_batch(torch_cuda):
     assert A.shape == (0, 18, 18) and b.shape == (0, 18)
 
 
-@pytest.mark.parametrize("name,form", [("p1_4096", "fp64"), ("p4_131072", "fp64"), ("p4_131072", "bf16x3"),
-                                       ("p4_131072", "fp32"), ("p7_16384", "bf16x3")])
+FULL = [("p1_4096", "fp64"), ("p1_524288", "fp64"), ("p1_524288", "fp32")] + \
+    [(w, f) for w in ("p4_131072", "p7_16384") for f in ("fp64", "fp32", "bf16x3", "fp16x3")]
+
+
+@pytest.mark.parametrize("name,form", FULL)
 def test_full_size_sampled(torch_cuda, name, form):
-    """Full-size workloads in the benchmark's launch configuration; the oracle
-    checks a seeded sample of elements one by one."""
+    """Full-size workloads in the benchmark's launch configuration (the tile
+    shape autotuned on the whole batch first, as the benchmark does); the
+    oracle checks a seeded sample of elements, the first and the last one by
+    one, and every output must be finite."""
     import oracle
     import paper_1310_1194_amd as F
     from paper_1310_1194_amd import meshgen
@@ -120,7 +132,16 @@ def test_full_size_sampled(torch_cuda, name, form):
     batch = meshgen.workload(name)
     flush(f"[full] {name} form={form} ne={batch.ne}")
     args = to_dev(batch)
-    A, b = F.integrate_raw(*args, p, form)
+    dt = torch.float64 if form == "fp64" else torch.float32
+    n = F.nshp(p)
+    A = torch.empty((batch.ne, n, n), dtype=dt, device="cuda")
+    b = torch.empty((batch.ne, n), dtype=dt, device="cuda")
+    ms = F.autotune(*args, p, form, A, b, reps=1)
+    tile = F.tile_get(p, form)
+    flush(f"    autotuned tile {F.tile_describe(p, form, tile)}: {ms:.3f} ms")
+    A.fill_(float("nan"))
+    b.fill_(float("nan"))
+    F.integrate_raw(*args, p, form, A=A, b=b)
     torch.cuda.synchronize()
     rng = np.random.default_rng(123)
     idx = np.sort(rng.choice(batch.ne, min(batch.ne, 96 if p < 7 else 24), replace=False))
@@ -130,6 +151,8 @@ def test_full_size_sampled(torch_cuda, name, form):
     ti = torch.from_numpy(idx).cuda()
     gA, mA = rel_errors(A[ti].cpu().numpy(), Ar)
     gb, mb = rel_errors(b[ti].cpu().numpy(), br)
-    flush(f"    A: global {gA:.3e} max-elem {mA:.3e}   b: {gb:.3e}")
-    assert gA <= TOL[form][0] and mA <= TOL[form][1] and gb <= BTOL[form][0]
-    assert bool(torch.isfinite(A).all())
+    flush(f"    A: global {gA:.3e} max-elem {mA:.3e}   b: global {gb:.3e} max-elem {mb:.3e}")
+    assert gA <= TOL[form][0] and mA <= TOL[form][1]
+    assert gb <= BTOL[form][0] and mb <= BTOL[form][1]
+    assert bool(torch.isfinite(A).all()) and bool(torch.isfinite(b).all())
+    F.tile_set(p, form, 0)

@@ -8,11 +8,11 @@ the collapsed-rule forward and adjoint tests."""
 import numpy as np
 import pytest
 
-from gpu_util import flush, rel_errors, to_dev
+from gpu_util import flush, grad_errors, rel_errors, to_dev
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": (1e-12, 1e-12), "fp32": (1e-5, 1e-4), "bf16x3": (1e-5, 2e-4), "fp16x3": (1e-5, 1e-4)}
+TOL = {"fp64": (1e-12, 1e-12), "fp32": (2e-6, 2e-5), "bf16x3": (1e-5, 5e-5), "fp16x3": (2e-6, 2e-5)}   # derivation: test_gpu_forward.py
 SYM = "symmetric"
 
 
@@ -130,12 +130,12 @@ def test_rule_full_size_sampled(torch_cuda, form):
 @pytest.mark.parametrize("p", range(1, 8))
 def test_rule_adjoint_parity(torch_cuda, p, form):
     """The adjoint on the symmetric rule, every compiled block shape, against
-    the oracle's reverse-mode gradient on its own rule (tolerances of the
-    collapsed-rule adjoint tests: FP64 1e-11, FP32 2e-5)."""
+    the oracle's reverse-mode gradient on its own rule, globally and per
+    element (the tolerances of the collapsed-rule adjoint tests)."""
     import oracle
     import paper_1310_1194_amd as F
     torch = torch_cuda
-    tol = {"fp64": 1e-11, "fp32": 2e-5}[form]
+    tol = {"fp64": (1e-11, 1e-10), "fp32": (4e-6, 5e-5)}[form]
     batch = rule_batch(p, 140 + p)
     n = F.nshp(p)
     rng = np.random.default_rng(150 + p)
@@ -154,7 +154,7 @@ def test_rule_adjoint_parity(torch_cuda, p, form):
         got = F.adjoint_raw(*X, Gd, gd, p, form, rule=SYM)
         torch.cuda.synchronize()
         for name, a, r in zip(("dcoords", "dD", "dbeta", "dc", "df"), got, ref[:5]):
-            e = float(np.linalg.norm(a.cpu().numpy() - r) / np.linalg.norm(r))
-            flush(f"    {name}: {e:.3e}")
-            assert e <= tol, name
+            e, m = grad_errors(a.cpu().numpy(), r, floor=1e-2)
+            flush(f"    {name}: global {e:.3e} max-elem {m:.3e}")
+            assert e <= tol[0] and m <= tol[1], name
     F.adjoint_tile_set(p, form, 0)
