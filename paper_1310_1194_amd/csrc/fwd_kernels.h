@@ -320,6 +320,20 @@ struct K4 {
     }
 };
 
+// Scales of the fp16 split form (1 for bf16): ys multiplies the columns of A,
+// yb the load-vector column.
+struct SplitScale {
+    float ys, yb;
+};
+
+// The power of two that places a positive bound m in [2^13, 2^14) (1 for a
+// zero or non-finite bound), clamped to 2^+-60.
+__device__ inline float pow2_scale(double m) {
+    if (!(m > 0.0) || !(m < 1e300)) return 1.0f;
+    const int ex = 13 - (int)floor(log2(m));
+    return ldexpf(1.0f, ex < -60 ? -60 : (ex > 60 ? 60 : ex));
+}
+
 // ---------------------------------------------------------------------------
 // 16x16x32 split forms (bf16x3, fp16x3): eight points (32 K-rows) per MFMA.
 // x = hi + lo with hi = rn(x), lo = rn(x - hi); products hi*hi + hi*lo + lo*hi
@@ -345,13 +359,17 @@ struct K32 {
     };
     struct Smem { Slice w[4]; };
 
-    __device__ static float elem_scale(const FwdParams &prm, const typename G::Elem &E0, int64_t e) {
+    // Per-element power-of-two scales of the fp16 form: ys for the columns of
+    // A (a bound on |Y| = |W_q B_q|, the largest row sum of |W_q| over the
+    // element's points times max |B|) and yb for the load-vector column (the
+    // largest |w det J f|), each placing its bound in [2^13, 2^14).  The two
+    // are separate because f can be orders of magnitude below the other
+    // coefficients: under the scale of A the load-vector column would sink
+    // into the subnormal range of fp16 and lose its relative precision.
+    __device__ static SplitScale elem_scale(const FwdParams &prm, const typename G::Elem &E0, int64_t e) {
         typename G::Elem E = E0;
-        // largest row sum of |W_q| over the element's points, times max |B|,
-        // and the largest |w det J f| (the load-vector column): a bound on
-        // |Y|; scale so that the bound lies in [2^13, 2^14)
         const int lane = threadIdx.x & 63;
-        double m = 0.0;
+        double m = 0.0, mb = 0.0;
         for (int qc = 0; qc < NQ; qc += 64) {
             const int q = qc + lane;
             if (q < NQ) {
@@ -364,21 +382,16 @@ struct K32 {
                     const double s = fabs(W[4 * r]) + fabs(W[4 * r + 1]) + fabs(W[4 * r + 2]) + fabs(W[4 * r + 3]);
                     m = s > m ? s : m;
                 }
-                if (LC::on) {
-                    const double s = fabs(sf) / (double)prm.bmax;
-                    m = s > m ? s : m;
-                }
+                mb = fabs(sf) > mb ? fabs(sf) : mb;
             }
         }
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
-            const double o = __shfl_xor(m, off, 64);
+            const double o = __shfl_xor(m, off, 64), ob = __shfl_xor(mb, off, 64);
             m = o > m ? o : m;
+            mb = ob > mb ? ob : mb;
         }
-        m *= (double)prm.bmax;
-        if (!(m > 0.0) || !(m < 1e300)) return 1.0f;
-        const int ex = 13 - (int)floor(log2(m));
-        return ldexpf(1.0f, ex < -60 ? -60 : (ex > 60 ? 60 : ex));
+        return SplitScale{pow2_scale(m * (double)prm.bmax), pow2_scale(mb)};
     }
 
     // hi = rn(y), lo = rn(y - hi), two values per conversion instruction.
@@ -418,7 +431,8 @@ struct K32 {
         const int64_t e = elem_of(prm, slot);
         typename G::Elem E;
         G::load(prm, e, E);
-        const float ys = FORM == FP16X3 ? elem_scale(prm, E, e) : 1.0f;
+        const SplitScale sc = FORM == FP16X3 ? elem_scale(prm, E, e) : SplitScale{1.0f, 1.0f};
+        const float ys = sc.ys, yb = sc.yb;
         f32x4 acc[TMV][TNV];
 #pragma unroll
         for (int ti = 0; ti < TMV; ++ti)
@@ -517,8 +531,8 @@ struct K32 {
                     if (LC::on && b0 + tj * 16 == LC::tile0 && i16 == LC::lane) {   // load-vector column
 #pragma unroll
                         for (int r = 0; r < 8; ++r) y[r] = 0.0f;
-                        y[0] = (float)sl.sf[qa] * ys;
-                        y[4] = (float)sl.sf[qa + 1] * ys;
+                        y[0] = (float)sl.sf[qa] * yb;
+                        y[4] = (float)sl.sf[qa + 1] * yb;
                     }
                     split8(y, yh[tj], yl[tj]);
                 }
@@ -539,6 +553,7 @@ struct K32 {
             wave_sync();
         }
         const float unscale = FORM == FP16X3 ? ldexpf(1.0f, -prm.f16_shift) / ys : 1.0f;
+        const float unscale_b = FORM == FP16X3 ? ldexpf(1.0f, -prm.f16_shift) / yb : 1.0f;
         float *Aout = (float *)prm.A + offA_of(prm, e, N);
         float *bout = (float *)prm.b + offb_of(prm, e, N);
 #pragma unroll
@@ -552,7 +567,7 @@ struct K32 {
                     if (row < N && col < N)
                         Aout[(size_t)row * N + col] = acc[ti][tj][r] * unscale;
                     else if (LC::on && row < N && col == N)
-                        bout[row] = acc[ti][tj][r] * unscale;
+                        bout[row] = acc[ti][tj][r] * unscale_b;
                 }
             }
         if (!LC::on && bj == 0) {

@@ -37,11 +37,13 @@ struct K32P {
     };
     struct Smem { Slice w[4]; };
 
-    // W_q (FP32, times the fp16 scale) and w det J f of every point into the
-    // slice; returns the element's fp16 scale (1 for bf16).
-    __device__ static float geometry(const FwdParams &prm, ElemIn &E, int64_t e, int blk, Slice &sl) {
+    // W_q (FP32, times the fp16 scale of A's columns) and w det J f of every
+    // point into the slice; returns the element's fp16 scales (ys for A's
+    // columns, yb for the load-vector column; both 1 for bf16), as
+    // K32::elem_scale derives them.
+    __device__ static SplitScale geometry(const FwdParams &prm, ElemIn &E, int64_t e, int blk, Slice &sl) {
         const int lane = threadIdx.x & 63;
-        double m = 0.0;
+        double m = 0.0, mb = 0.0;
         for (int qc = 0; qc < NQP; qc += 64) {
             const int q = qc + lane;
             if (q < NQP) {
@@ -64,7 +66,7 @@ struct K32P {
                                               fabs(W[4 * r + 3])) * (double)prm.bmax;
                             m = s > m ? s : m;
                         }
-                        m = fabs(sf) > m ? fabs(sf) : m;
+                        mb = fabs(sf) > mb ? fabs(sf) : mb;
                     }
                 } else {
 #pragma unroll
@@ -75,24 +77,24 @@ struct K32P {
                 sl.sf[q] = sf;
             }
         }
-        float ys = 1.0f;
+        float ys = 1.0f, yb = 1.0f;
         if (FORM == FP16X3) {
-            // bound on |Y| over the element; scale it into [2^13, 2^14)
+            // bounds on |Y| over the element (A's columns, load-vector column);
+            // each scaled into [2^13, 2^14)
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) {
-                const double o = __shfl_xor(m, off, 64);
+                const double o = __shfl_xor(m, off, 64), ob = __shfl_xor(mb, off, 64);
                 m = o > m ? o : m;
+                mb = ob > mb ? ob : mb;
             }
-            if (m > 0.0 && m < 1e300) {
-                const int ex = 13 - (int)floor(log2(m));
-                ys = ldexpf(1.0f, ex < -60 ? -60 : (ex > 60 ? 60 : ex));
-            }
+            ys = pow2_scale(m);
+            yb = pow2_scale(mb);
             for (int q = lane; q < NQP; q += 64)     // each lane rescales the rows it wrote
 #pragma unroll
                 for (int k = 0; k < 16; ++k) sl.W[q][k] *= ys;
         }
         wave_sync();
-        return ys;
+        return SplitScale{ys, yb};
     }
 
     template <int TMV, int TNV>
@@ -125,12 +127,12 @@ struct K32P {
     struct PointW {
         float wa[16], wb[16], za, zb;
     };
-    __device__ static void read_w(const Slice &sl, int kb, int lane, float ys, PointW &pw) {
+    __device__ static void read_w(const Slice &sl, int kb, int lane, float yb, PointW &pw) {
         const int qa = kb * 8 + 2 * (lane >> 4);
 #pragma unroll
         for (int k = 0; k < 16; ++k) { pw.wa[k] = sl.W[qa][k]; pw.wb[k] = sl.W[qa + 1][k]; }
-        pw.za = (float)sl.sf[qa] * ys;
-        pw.zb = (float)sl.sf[qa + 1] * ys;
+        pw.za = (float)sl.sf[qa] * yb;
+        pw.zb = (float)sl.sf[qa + 1] * yb;
     }
 
     // Y = W_q B_q for the lane's column of tile tj and its two points,
@@ -181,12 +183,13 @@ struct K32P {
         const int i16 = lane & 15, kg = lane >> 4;
         const int a0 = bi * TM * 16, b0 = bj * TN * 16;
         const int64_t e = elem_of(prm, slot);
-        float ys;
+        SplitScale sc;
         {
             ElemIn E;
             load_elem_fwd(prm, e, E);
-            ys = geometry(prm, E, e, blk, sl);
+            sc = geometry(prm, E, e, blk, sl);
         }
+        const float ys = sc.ys, yb = sc.yb;
         f32x4 acc[TMV][TNV];
 #pragma unroll
         for (int ti = 0; ti < TMV; ++ti)
@@ -201,7 +204,7 @@ struct K32P {
             load_yc<TNV>(prm, 0, b0, lane, y0);
             load_yc<TNV>(prm, NKB > 1 ? 1 : 0, b0, lane, ycA);
             PointW pw;
-            read_w(sl, 0, lane, ys, pw);
+            read_w(sl, 0, lane, yb, pw);
 #pragma unroll
             for (int tj = 0; tj < TNV; ++tj) form_y_tile(pw, tj, b0, lane, y0[tj], s0.yh[tj], s0.yl[tj]);
         }
@@ -220,7 +223,7 @@ struct K32P {
             load_a<TMV>(prm, k1, a0, lane, nxt.ah, nxt.al);
             load_yc<TNV>(prm, k2, b0, lane, ycl);
             PointW pw;
-            read_w(sl, k1, lane, ys, pw);
+            read_w(sl, k1, lane, yb, pw);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int tj = 0; tj < TNV; ++tj) {
@@ -242,6 +245,7 @@ struct K32P {
         if (kb < NKB) mfma_block<TMV, TNV>(acc, s0);
 
         const float unscale = FORM == FP16X3 ? ldexpf(1.0f, -prm.f16_shift) / ys : 1.0f;
+        const float unscale_b = FORM == FP16X3 ? ldexpf(1.0f, -prm.f16_shift) / yb : 1.0f;
         float *Aout = (float *)prm.A + offA_of(prm, e, N);
         float *bout = (float *)prm.b + offb_of(prm, e, N);
         if (!LC::on && bj == 0) {
@@ -277,7 +281,7 @@ struct K32P {
                     if (row < N && col < N)
                         Aout[(size_t)row * N + col] = acc[ti][tj][r] * unscale;
                     else if (LC::on && row < N && col == N)
-                        bout[row] = acc[ti][tj][r] * unscale;
+                        bout[row] = acc[ti][tj][r] * unscale_b;
                 }
             }
     }

@@ -251,10 +251,14 @@ struct K32S {
         const int a0 = bi * TM * 16, b0 = bj * TN * 16;
         const int64_t e = active ? elem_of(prm, slot) : 0;
         ElemIn E;
-        float ys = 1.0f;
+        float ys = 1.0f, yb = 1.0f;
         if (active) {
             load_elem_fwd(prm, e, E);
-            if (FORM == FP16X3) ys = Plain::elem_scale(prm, E, e);
+            if (FORM == FP16X3) {
+                const SplitScale sc = Plain::elem_scale(prm, E, e);
+                ys = sc.ys;
+                yb = sc.yb;
+            }
         }
         f32x4 acc[TMV][TNV];
 #pragma unroll
@@ -341,8 +345,8 @@ struct K32S {
                         if (LC::on && b0 + tj * 16 == LC::tile0 && i16 == LC::lane) {   // load-vector column
 #pragma unroll
                             for (int r = 0; r < 8; ++r) y[r] = 0.0f;
-                            y[0] = (float)sm.sf[wave][q0 + qa - qc] * ys;
-                            y[4] = (float)sm.sf[wave][q0 + qa + 1 - qc] * ys;
+                            y[0] = (float)sm.sf[wave][q0 + qa - qc] * yb;
+                            y[4] = (float)sm.sf[wave][q0 + qa + 1 - qc] * yb;
                         }
                         Plain::split8(y, yh[tj], yl[tj]);
                     }
@@ -374,6 +378,7 @@ struct K32S {
         }
         if (!active) return;
         const float unscale = FORM == FP16X3 ? ldexpf(1.0f, -prm.f16_shift) / ys : 1.0f;
+        const float unscale_b = FORM == FP16X3 ? ldexpf(1.0f, -prm.f16_shift) / yb : 1.0f;
         float *Aout = (float *)prm.A + offA_of(prm, e, N);
         float *bout = (float *)prm.b + offb_of(prm, e, N);
 #pragma unroll
@@ -387,7 +392,7 @@ struct K32S {
                     if (row < N && col < N)
                         Aout[(size_t)row * N + col] = acc[ti][tj][r] * unscale;
                     else if (LC::on && row < N && col == N)
-                        bout[row] = acc[ti][tj][r] * unscale;
+                        bout[row] = acc[ti][tj][r] * unscale_b;
                 }
             }
         if (!LC::on && bj == 0) {

@@ -4,7 +4,10 @@ the C-ABI: every degree, form (FP64, FP32 and the split forms) and compiled
 variant, mapped points in the
 rule's point order, the det J flag, an empty batch, and the full p = 4
 meshes on a sample of elements.  Tolerances are those of the prism forward
-tests."""
+tests, except that the FP32 global tolerance grows with the length K = 4 nq
+of the contraction's FP32 sums as 2 sqrt(K) 2^-24 once that exceeds 2e-6
+(hexahedra at p = 7 contract K = 2048 terms point by point: measured 2.1e-6;
+5.4e-6 allowed)."""
 import numpy as np
 import pytest
 
@@ -14,6 +17,10 @@ pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": (1e-12, 1e-12), "fp32": (2e-6, 2e-5), "bf16x3": (1e-5, 5e-5), "fp16x3": (2e-6, 2e-5)}   # derivation: test_gpu_forward.py
 NV = {"hex": 8, "tet": 4}
+
+
+def fp32_global_tol(K):
+    return max(TOL["fp32"][0], 2.0 * np.sqrt(K) * 2.0 ** -24)
 INVERT = {"hex": [4, 5, 6, 7, 0, 1, 2, 3], "tet": [0, 2, 1, 3]}
 
 
@@ -64,8 +71,9 @@ def test_elem_parity_every_tile(torch_cuda, kind, p, form):
         gA, mA = rel_errors(A.cpu().numpy(), Ar)
         gb, mb = rel_errors(b.cpu().numpy(), br)
         flush(f"    A: {gA:.3e} / {mA:.3e}   b: {gb:.3e} / {mb:.3e}")
-        assert gA <= TOL[form][0] and mA <= TOL[form][1]
-        assert gb <= TOL[form][0] and mb <= TOL[form][1]
+        tg = fp32_global_tol(4 * F.ELEMENTS[kind][2](p)) if form == "fp32" else TOL[form][0]
+        assert gA <= tg and mA <= TOL[form][1]
+        assert gb <= tg and mb <= TOL[form][1]
     F.elem_tile_set(kind, p, form, 0)
 
 
