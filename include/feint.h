@@ -210,6 +210,28 @@ feint_status feint_mixed_graph_launch(feint_mixed_plan *plan, void *stream);
 feint_status feint_mixed_autotune(feint_mixed_plan *plan, const feint_elements *el,
                                   void *A_packed, void *b_packed, const int64_t *offA,
                                   const int64_t *offb, int reps, double *best_ms, void *stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the
+   mixed-degree integration of a batch -- bucketing of p[ne] (int8, device)
+   into offA[ne+1], offb[ne+1] and the persistent launch into the packed
+   A_packed, b_packed, as feint_mixed_bucket followed by
+   feint_integrate_mixed with the first compiled tile set -- without a plan
+   and without allocating.  Its bucketing scratch is a fixed device array of
+   the library (about 4.3 MB per GPU, held until the process ends) that
+   every call on a GPU shares and that keeps the last call's contents;
+   calls that overlap on one GPU (two streams, two threads) race on it and
+   must be serialised by the caller.  At most FEINT_NOALLOC_MAX_NE elements
+   (FEINT_ERR_TOO_LARGE beyond, before any launch, with the reason in
+   feint_last_error).  The tables of degrees 1..6 must have been prepared
+   (feint_prepare) on the current device: otherwise FEINT_ERR_NOT_PREPARED,
+   since preparing them would allocate.  The caller sizes A_packed and
+   b_packed (sum of n(p_e)^2 and n(p_e) values of the form's dtype).  form
+   is FEINT_FP32 or FEINT_FP64; errors otherwise as for feint_integrate_mixed
+   (elements with p outside [1,6] set bit 1 of *dev_status). */
+#define FEINT_NOALLOC_MAX_NE 1048576
+feint_status feint_integrate_mixed_noalloc(const feint_elements *el, const int8_t *p, feint_form form,
+                                           void *A_packed, void *b_packed, int64_t *offA, int64_t *offb,
+                                           uint32_t *dev_status, void *stream);
 /* Number of compiled tile sets of the plan's form, the one in use, and a
    forced choice. */
 int feint_mixed_tile_count(const feint_mixed_plan *plan);

@@ -12,7 +12,7 @@ import torch
 from . import native
 import numpy as np
 
-from .native import FORMS, RULES, Elements, Fields, check, lib
+from .native import FORMS, RULES, Elements, FeintError, Fields, check, lib
 
 
 def nshp(p: int) -> int:
@@ -400,6 +400,32 @@ def adjoint_autotune(coords, D, beta, c, f, G, g, p: int, form: str = "fp64", re
           lib().feint_adjoint_autotune(ctypes.byref(el), int(p), FORMS[form], _ptr(G), _ptr(g),
                                        *[_ptr(o) for o in outs], int(reps), ctypes.byref(best), _stream()))
     return best.value
+
+
+NOALLOC_MAX_NE = 1048576     # FEINT_NOALLOC_MAX_NE
+
+
+def integrate_mixed_noalloc(coords, D, beta, c, f, p, A, b, offA, offb, form: str = "fp32", status=None):
+    """Mixed-degree integration through the library's allocation-free entry
+    point (bucketing + persistent launch on the library's fixed scratch):
+    every buffer is the caller's; the tables of degrees 1..6 must have been
+    prepared (`prepare(d)`); at most NOALLOC_MAX_NE elements."""
+    if form not in ("fp32", "fp64"):
+        raise ValueError("mixed batches support the fp32 and fp64 forms")
+    if p.dtype != torch.int8 or not p.is_contiguous() or p.numel() != coords.shape[0]:
+        raise TypeError("p must be a contiguous int8 tensor with one entry per element")
+    ne = coords.shape[0]
+    if offA.dtype != torch.int64 or offb.dtype != torch.int64 or offA.numel() < ne + 1 or offb.numel() < ne + 1:
+        raise ValueError("offA, offb must be int64 with ne + 1 entries")
+    dt = out_dtype(form)
+    if A.dtype != dt or b.dtype != dt:
+        raise ValueError("A, b must have the form's dtype")
+    el = elements(coords, D, beta, c, f)
+    code = lib().feint_integrate_mixed_noalloc(ctypes.byref(el), _ptr(p), FORMS[form], _ptr(A), _ptr(b),
+                                               _ptr(offA), _ptr(offb), _ptr(status), _stream())
+    if code == -6:
+        raise FeintError("feint_integrate_mixed_noalloc", code, lib().feint_last_error().decode())
+    check("feint_integrate_mixed_noalloc", code)
 
 
 class MixedPlan:

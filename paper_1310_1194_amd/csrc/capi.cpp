@@ -33,6 +33,8 @@ void set_error(const char *what, hipError_t e) {
     g_err = std::string(what) + ": " + hipGetErrorString(e);
 }
 
+void set_error_msg(const std::string &msg) { g_err = msg; }
+
 const DevTables *find_tables(int p, int rule, int type) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return nullptr;

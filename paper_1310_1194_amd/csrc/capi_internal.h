@@ -1,5 +1,6 @@
 // Internal helpers shared by the C-ABI translation units.
 #pragma once
+#include <string>
 #include <hip/hip_runtime.h>
 
 #include "feint.h"
@@ -22,6 +23,8 @@ struct DevTables {
 };
 
 void set_error(const char *what, hipError_t e);
+// Set the thread's last-error text to a message of the library's own.
+void set_error_msg(const std::string &msg);
 feint_status prepare_tables(int p, int rule = 0, int type = 0);
 const DevTables *find_tables(int p, int rule = 0, int type = 0);
 feint_status tables_for_launch(int p, hipStream_t stream, const DevTables **out, int rule = 0, int type = 0);

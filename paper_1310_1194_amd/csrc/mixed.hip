@@ -19,6 +19,7 @@
 
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 
 #include "capi_internal.h"
@@ -346,7 +347,7 @@ struct feint_mixed_plan {
     int64_t *blk_sums = nullptr;
     int32_t *perm = nullptr;
     int tile = 0;
-    int grid[8] = {0};
+    int grid[16] = {0};
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -367,23 +368,55 @@ void drop_graph(feint_mixed_plan *pl) {
     pl->graph = nullptr;
 }
 
-feint_status enqueue_bucket(feint_mixed_plan *pl, const int8_t *p, int64_t ne, int64_t *offA, int64_t *offb,
+// Device memory one bucketing + persistent launch works in: the queue header,
+// the per-block degree sums and the permutation into bucket order, plus the
+// degree tables and the launch grid of each compiled tile set.
+struct MixedWork {
+    MixedHdr *hdr;
+    int64_t *blk_sums;
+    int32_t *perm;
+    const DevTables *const *tab;   // [8], degrees 1..6
+    int form;
+    const int *grid;               // per compiled tile set
+};
+
+// Bytes of scratch a batch of ne elements needs: header, block sums, permutation.
+constexpr size_t SCR_HDR = 256;
+constexpr size_t scratch_blk_bytes(int64_t ne) {
+    return ((size_t)((ne + BUCKET_ELEMS - 1) / BUCKET_ELEMS) * 8 * 8 + 255) / 256 * 256;
+}
+constexpr size_t scratch_bytes(int64_t ne) {
+    return SCR_HDR + scratch_blk_bytes(ne) + ((size_t)ne * 4 + 255) / 256 * 256;
+}
+
+MixedWork work_in(char *base, int64_t ne_max, const DevTables *const *tab, int form, const int *grid) {
+    MixedWork w;
+    w.hdr = (MixedHdr *)base;
+    w.blk_sums = (int64_t *)(base + SCR_HDR);
+    w.perm = (int32_t *)(base + SCR_HDR + scratch_blk_bytes(ne_max));
+    w.tab = tab;
+    w.form = form;
+    w.grid = grid;
+    return w;
+}
+
+feint_status enqueue_bucket(const MixedWork &w, const int8_t *p, int64_t ne, int64_t *offA, int64_t *offb,
                             uint32_t *status, hipStream_t s) {
     const int64_t nblk = (ne + BUCKET_ELEMS - 1) / BUCKET_ELEMS;
     (void)hipGetLastError();
-    if (nblk > 0) hipLaunchKernelGGL(k_count, dim3((unsigned)nblk), dim3(256), 0, s, p, ne, pl->blk_sums, status);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_THREADS), 0, s, nblk, pl->blk_sums, pl->hdr, offA, offb, ne);
+    if (nblk > 0) hipLaunchKernelGGL(k_count, dim3((unsigned)nblk), dim3(256), 0, s, p, ne, w.blk_sums, status);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_THREADS), 0, s, nblk, w.blk_sums, w.hdr, offA, offb, ne);
     if (nblk > 0)
-        hipLaunchKernelGGL(k_scatter, dim3((unsigned)nblk), dim3(256), 0, s, p, ne, (const int64_t *)pl->blk_sums,
-                           (const MixedHdr *)pl->hdr, pl->perm, offA, offb);
+        hipLaunchKernelGGL(k_scatter, dim3((unsigned)nblk), dim3(256), 0, s, p, ne, (const int64_t *)w.blk_sums,
+                           (const MixedHdr *)w.hdr, w.perm, offA, offb);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? FEINT_OK : hip_fail("bucketing launch", e);
 }
 
-feint_status enqueue_persist(feint_mixed_plan *pl, const feint_elements *el, void *A, void *b, const int64_t *offA,
+feint_status enqueue_persist(const MixedWork &w, const feint_elements *el, void *A, void *b, const int64_t *offA,
                              const int64_t *offb, uint32_t *status, hipStream_t s, int tile) {
     int cnt = 0;
-    const MixVariant *vars = mix_variants(pl->form, &cnt);
+    const MixVariant *vars = mix_variants(w.form, &cnt);
     const MixVariant &v = vars[tile];
     MixedParams mp;
     std::memset(&mp, 0, sizeof mp);
@@ -392,23 +425,76 @@ feint_status enqueue_persist(feint_mixed_plan *pl, const feint_elements *el, voi
     mp.base.A = A; mp.base.b = b; mp.base.status = status;
     mp.base.offA = offA; mp.base.offb = offb;
     for (int d = 1; d <= MIX_MAXP; ++d) {
-        mp.qw[d] = pl->tab[d]->qw;
-        mp.B64[d] = pl->tab[d]->B64;
-        mp.B32[d] = pl->tab[d]->B32;
-        mp.tau64[d] = pl->tab[d]->tau64;
-        mp.tau32[d] = pl->tab[d]->tau32;
-        mp.lam[d] = pl->tab[d]->lam;
-        mp.lam32[d] = pl->tab[d]->lam32;
+        mp.qw[d] = w.tab[d]->qw;
+        mp.B64[d] = w.tab[d]->B64;
+        mp.B32[d] = w.tab[d]->B32;
+        mp.tau64[d] = w.tab[d]->tau64;
+        mp.tau32[d] = w.tab[d]->tau32;
+        mp.lam[d] = w.tab[d]->lam;
+        mp.lam32[d] = w.tab[d]->lam32;
     }
-    mp.perm = pl->perm;
-    mp.hdr = pl->hdr;
+    mp.perm = w.perm;
+    mp.hdr = w.hdr;
     mp.sz = v.sz;
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_prep, dim3(1), dim3(64), 0, s, pl->hdr, v.sz);
+    hipLaunchKernelGGL(k_prep, dim3(1), dim3(64), 0, s, w.hdr, v.sz);
     void *args[] = {&mp};
-    hipError_t e = hipLaunchKernel(v.kernel, dim3(pl->grid[tile]), dim3(256), args, 0, s);
+    hipError_t e = hipLaunchKernel(v.kernel, dim3(w.grid[tile]), dim3(256), args, 0, s);
     if (e == hipSuccess) e = hipGetLastError();
     return e == hipSuccess ? FEINT_OK : hip_fail("persistent launch", e);
+}
+
+// Launch grid of every compiled tile set of `form` on device `dev`: as many
+// workgroups as fit the device at once (persistent waves).
+hipError_t persistent_grids(int form, int dev, int *grid) {
+    int cnt = 0, cus = 0;
+    const MixVariant *vars = mix_variants(form, &cnt);
+    if (cnt > 16) return hipErrorInvalidValue;          // grid arrays hold 16 tile sets
+    hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    for (int t = 0; t < cnt && e == hipSuccess; ++t) {
+        int nb = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, vars[t].kernel, 256, 0);
+        grid[t] = (nb > 0 ? nb : 1) * cus;
+    }
+    return e;
+}
+
+MixedWork plan_work(const feint_mixed_plan *pl) {
+    return work_in(pl->scratch, pl->ne_max, pl->tab, pl->form, pl->grid);
+}
+
+// ---- The allocation-free entry point --------------------------------------
+// Its bucketing scratch (queue header, block sums, permutation) is this
+// file-scope device array, one copy per GPU, held until the process ends.
+// Host code never passes the array's name to a kernel (on the host it is a
+// stand-in, not a device address): the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+constexpr int64_t NOALLOC_MAX_NE = FEINT_NOALLOC_MAX_NE;
+static __device__ __align__(256) unsigned char scratch[scratch_bytes(NOALLOC_MAX_NE)];
+
+struct NoAllocDev {
+    char *ptr = nullptr;          // device address of `scratch` on this device
+    int grid[2][16] = {{0}};      // persistent grid per form (FP64, FP32) and tile set
+};
+std::mutex g_na_mu;
+std::map<int, NoAllocDev> g_na;   // key: device
+
+// Set-up of the current device on its first call: the scratch's device
+// address and the persistent grids.  Neither allocates device memory.
+feint_status noalloc_device(int dev, const NoAllocDev **out) {
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    auto it = g_na.find(dev);
+    if (it == g_na.end()) {
+        NoAllocDev nd;
+        hipError_t e = hipGetSymbolAddress((void **)&nd.ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !nd.ptr) return hip_fail("hipGetSymbolAddress(scratch)", e);
+        e = persistent_grids(FEINT_FP64, dev, nd.grid[0]);
+        if (e == hipSuccess) e = persistent_grids(FEINT_FP32, dev, nd.grid[1]);
+        if (e != hipSuccess) return hip_fail("persistent grid", e);
+        it = g_na.emplace(dev, nd).first;
+    }
+    *out = &it->second;
+    return FEINT_OK;
 }
 
 }  // namespace
@@ -432,21 +518,9 @@ feint_status feint_mixed_plan_create(int64_t ne_max, feint_form form, feint_mixe
         if (s != FEINT_OK) { delete pl; return s; }
         pl->tab[d] = find_tables(d);
     }
-    const size_t s_hdr = 256, s_blk = ((size_t)pl->nblk_max * 8 * 8 + 255) / 256 * 256;
-    const size_t s_perm = ((size_t)ne_max * 4 + 255) / 256 * 256;
-    e = hipMalloc((void **)&pl->scratch, s_hdr + s_blk + s_perm);
+    e = hipMalloc((void **)&pl->scratch, scratch_bytes(ne_max));
     if (e != hipSuccess) { delete pl; return hip_fail("hipMalloc(plan)", e); }
-    pl->hdr = (MixedHdr *)pl->scratch;
-    pl->blk_sums = (int64_t *)(pl->scratch + s_hdr);
-    pl->perm = (int32_t *)(pl->scratch + s_hdr + s_blk);
-    int cnt = 0, cus = 0;
-    const MixVariant *vars = mix_variants(form, &cnt);
-    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->dev);
-    for (int t = 0; t < cnt && e == hipSuccess; ++t) {
-        int nb = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, vars[t].kernel, 256, 0);
-        pl->grid[t] = (nb > 0 ? nb : 1) * cus;
-    }
+    e = persistent_grids(form, pl->dev, pl->grid);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         (void)hipFree(pl->scratch);
@@ -462,7 +536,7 @@ feint_status feint_mixed_bucket(feint_mixed_plan *pl, const int8_t *p, int64_t n
     if (!pl || !offA || !offb || ne < 0) return FEINT_ERR_INVALID_ARG;
     if (ne > pl->ne_max) return FEINT_ERR_TOO_LARGE;
     if (ne > 0 && !p) return FEINT_ERR_INVALID_ARG;
-    feint_status s = enqueue_bucket(pl, p, ne, offA, offb, dev_status, (hipStream_t)stream);
+    feint_status s = enqueue_bucket(plan_work(pl), p, ne, offA, offb, dev_status, (hipStream_t)stream);
     if (s == FEINT_OK) pl->ne_bucketed = ne;
     return s;
 }
@@ -475,7 +549,7 @@ feint_status feint_integrate_mixed(feint_mixed_plan *pl, const feint_elements *e
     if (el->ne != pl->ne_bucketed) return FEINT_ERR_INVALID_ARG;   // bucket this batch first
     if (el->ne == 0) return FEINT_OK;
     if (!A || !b || !offA || !offb) return FEINT_ERR_INVALID_ARG;
-    return enqueue_persist(pl, el, A, b, offA, offb, dev_status, (hipStream_t)stream, pl->tile);
+    return enqueue_persist(plan_work(pl), el, A, b, offA, offb, dev_status, (hipStream_t)stream, pl->tile);
 }
 
 feint_status feint_mixed_graph_capture(feint_mixed_plan *pl, const feint_elements *el, const int8_t *p, void *A,
@@ -491,8 +565,9 @@ feint_status feint_mixed_graph_capture(feint_mixed_plan *pl, const feint_element
     pl->ne_captured = -1;
     hipError_t e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail("hipStreamBeginCapture", e);
-    s = enqueue_bucket(pl, p, el->ne, offA, offb, dev_status, pl->cap_stream);
-    if (s == FEINT_OK && el->ne > 0) s = enqueue_persist(pl, el, A, b, offA, offb, dev_status, pl->cap_stream, pl->tile);
+    const MixedWork w = plan_work(pl);
+    s = enqueue_bucket(w, p, el->ne, offA, offb, dev_status, pl->cap_stream);
+    if (s == FEINT_OK && el->ne > 0) s = enqueue_persist(w, el, A, b, offA, offb, dev_status, pl->cap_stream, pl->tile);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(pl->cap_stream, &g);
     if (s != FEINT_OK) {
@@ -537,9 +612,10 @@ feint_status feint_mixed_autotune(feint_mixed_plan *pl, const feint_elements *el
     int best = pl->tile;
     float best_t = 1e30f;
     for (int t = 0; t < cnt && s == FEINT_OK; ++t) {
-        s = enqueue_persist(pl, el, A, b, offA, offb, nullptr, st, t);
+        const MixedWork w = plan_work(pl);
+        s = enqueue_persist(w, el, A, b, offA, offb, nullptr, st, t);
         (void)hipEventRecord(e0, st);
-        for (int r = 0; r < reps && s == FEINT_OK; ++r) s = enqueue_persist(pl, el, A, b, offA, offb, nullptr, st, t);
+        for (int r = 0; r < reps && s == FEINT_OK; ++r) s = enqueue_persist(w, el, A, b, offA, offb, nullptr, st, t);
         (void)hipEventRecord(e1, st);
         if (s != FEINT_OK) break;
         if (hipEventSynchronize(e1) != hipSuccess) { s = FEINT_ERR_HIP; break; }
@@ -591,6 +667,36 @@ void feint_mixed_plan_destroy(feint_mixed_plan *pl) {
     (void)hipFree(pl->scratch);
     (void)hipSetDevice(cur);
     delete pl;
+}
+
+feint_status feint_integrate_mixed_noalloc(const feint_elements *el, const int8_t *p, feint_form form, void *A,
+                                           void *b, int64_t *offA, int64_t *offb, uint32_t *dev_status,
+                                           void *stream) {
+    if (form != FEINT_FP32 && form != FEINT_FP64) return FEINT_ERR_UNSUPPORTED_FORM;
+    feint_status s = check_elements(el);
+    if (s != FEINT_OK) return s;
+    if (el->ne > NOALLOC_MAX_NE) {
+        set_error_msg("feint_integrate_mixed_noalloc: " + std::to_string(el->ne) + " elements exceed the " +
+                      std::to_string(NOALLOC_MAX_NE) + " its fixed scratch holds");
+        return FEINT_ERR_TOO_LARGE;
+    }
+    if (!offA || !offb) return FEINT_ERR_INVALID_ARG;
+    if (el->ne > 0 && (!p || !A || !b)) return FEINT_ERR_INVALID_ARG;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail("hipGetDevice", e);
+    // the degree tables must exist already: preparing them would allocate
+    const DevTables *tab[8] = {nullptr};
+    for (int d = 1; d <= MIX_MAXP; ++d)
+        if (!(tab[d] = find_tables(d))) return FEINT_ERR_NOT_PREPARED;
+    const NoAllocDev *nd = nullptr;
+    s = noalloc_device(dev, &nd);
+    if (s != FEINT_OK) return s;
+    const MixedWork w = work_in(nd->ptr, NOALLOC_MAX_NE, tab, form, nd->grid[form == FEINT_FP64 ? 0 : 1]);
+    const hipStream_t st = (hipStream_t)stream;
+    s = enqueue_bucket(w, p, el->ne, offA, offb, dev_status, st);
+    if (s != FEINT_OK || el->ne == 0) return s;
+    return enqueue_persist(w, el, A, b, offA, offb, dev_status, st, 0);
 }
 
 }  // extern "C"

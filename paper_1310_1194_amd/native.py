@@ -34,6 +34,7 @@ EXPORTS = (
     "feint_hex_tile_describe", "feint_hex_autotune", "feint_tet_nshp", "feint_tet_nq", "feint_prepare_tet",
     "feint_integrate_tet", "feint_tet_tile_count", "feint_tet_tile_get", "feint_tet_tile_set",
     "feint_tet_tile_describe", "feint_tet_autotune", "feint_integrate_adjoint_rule",
+    "feint_integrate_mixed_noalloc",
 )
 
 
@@ -91,6 +92,7 @@ def lib() -> ctypes.CDLL:
             "feint_integrate_mixed": (_i, [_vp, P, _vp, _vp, _vp, _vp, _vp, _vp]),
             "feint_mixed_graph_capture": (_i, [_vp, P, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
             "feint_mixed_graph_launch": (_i, [_vp, _vp]),
+            "feint_integrate_mixed_noalloc": (_i, [P, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
             "feint_mixed_plan_destroy": (None, [_vp]),
             "feint_mixed_autotune": (_i, [_vp, P, _vp, _vp, _vp, _vp, _i, ctypes.POINTER(ctypes.c_double), _vp]),
             "feint_mixed_tile_count": (_i, [_vp]),
