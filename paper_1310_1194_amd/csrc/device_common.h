@@ -12,6 +12,8 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef short i16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 
 constexpr int WAVE = 64;
 
@@ -267,6 +269,21 @@ __device__ inline f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
 }
 __device__ inline f32x4 mfma32(f16x8 a, f16x8 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+// 16x16x16 (bf16, fp16): lane l supplies A[l%16][4(l/16)+v], B[4(l/16)+v][l%16], v = 0..3.
+__device__ inline f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ inline f32x4 mfma16(f16x4 a, f16x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+}
+// 4x4x4, 16 independent blocks (bf16, fp16): block b = l/4; lane l supplies
+// A_b[l%4][v] and B_b[v][l%4], v = 0..3, and holds D_b[r][l%4], r = 0..3.
+__device__ inline f32x4 mfma4b(bf16x4 a, bf16x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ inline f32x4 mfma4b(f16x4 a, f16x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_4x4x4f16(a, b, c, 0, 0, 0);
 }
 
 }  // namespace feint

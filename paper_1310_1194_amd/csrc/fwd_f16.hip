@@ -12,6 +12,8 @@ const FwdVariant v3[] = {
     FEINT_K32S(3, FP16X3, 3, 3, true, 1),
     FEINT_K32S(3, FP16X3, 3, 1, true, 2)};
 const FwdVariant v4[] = {
+    FEINT_K32Y(4, FP16X3, 5, 5, 2, 0),
+    FEINT_K32Y(4, FP16X3, 5, 3, 3, 0),
     FEINT_K32U(4, FP16X3, 5, 3, 2),
     FEINT_K32U(4, FP16X3, 5, 5, 1),
     FEINT_K32S(4, FP16X3, 5, 5, true, 1),
@@ -28,6 +30,10 @@ const FwdVariant v6[] = {
     FEINT_K32S(6, FP16X3, 7, 4, false, 1),
     FEINT_K32U(6, FP16X3, 13, 2, 1)};
 const FwdVariant v7[] = {
+    FEINT_K32Y(7, FP16X3, 3, 3, 2, 1),
+    FEINT_K32Y(7, FP16X3, 6, 3, 1, 1),
+    FEINT_K32Y(7, FP16X3, 6, 6, 1, 1),
+    FEINT_K32Y(7, FP16X3, 9, 3, 1, 1),
     FEINT_K32P(7, FP16X3, 6, 6, 1),
     FEINT_K32S(7, FP16X3, 6, 6, false, 1),
     FEINT_K32U(7, FP16X3, 6, 6, 1),

@@ -7,6 +7,7 @@
 #include "fwd_pipe.h"
 #include "fwd_sc.h"
 #include "fwd_fact.h"
+#include "fwd_ymfma.h"
 
 namespace feint {
 
@@ -46,6 +47,13 @@ int64_t items_of(int64_t ne) { return items_for<KER>(ne); }
 #define FEINT_K32S_R(P, F, TM, TN, SY, W, R) \
     FwdVariant{TM, TN, 1 + !(SY), W, &launch_staged<K32S<P, F, TM, TN, SY, R>, W>, \
                &items_of<K32S<P, F, TM, TN, SY, R>>}
+
+// Y: split kernel whose Y = W_q B_q is formed on the matrix cores (staged = 7).
+// CH: 1 points in chunks of 64, 0 the element's points at once.
+#define FEINT_K32Y_R(P, F, TM, TN, W, R, CH)                                                  \
+    FwdVariant{TM, TN, 7, W, &launch_direct<K32Y<P, F, TM, TN, R, CH>, W>, \
+               &items_of<K32Y<P, F, TM, TN, R, CH>>}
+#define FEINT_K32Y(P, F, TM, TN, W, CH) FEINT_K32Y_R(P, F, TM, TN, W, 0, CH)
 
 // C: shape functions computed at each point, no B table (staged = 5).
 #define FEINT_KSC_R(P, T, TM, TN, W, R) \
