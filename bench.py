@@ -8,10 +8,16 @@ in FP64, fused coefficient blocks, the B^T W B contraction, load vector,
 stores), inputs resident in HBM.  The headline form is the split-bf16 MFMA
 form (bf16x3); the plain FP64, FP32 and fp16x3 forms are timed beside it, and
 every form's relative error against the FP64 oracle on a sample of elements is
-stated in the same line.
+stated in the same line.  The default run (mode "suite") adds, as keys of
+`configs` in the same line, every other configured workload in its own launch
+configuration: p = 1 at 4096 and 524288 elements, the mixed-degree batch
+replayed from a HIP graph, the p = 3 adjoint and the p = 7 forward and
+adjoint, each with its roofline, its error against the oracle and its CPU
+baseline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--copy-cal]
-                    [--mode forward|fields|adjoint|mixed|assemble] [--workload NAME] [--forms LIST]
+                    [--mode suite|forward|fields|hex|tet|adjoint|mixed|assemble]
+                    [--workload NAME] [--forms LIST]
 """
 from __future__ import annotations
 
@@ -63,6 +69,32 @@ def traffic_record(key: str, tile: str):
     if not rec or rec.get("source_sha") != kernel_source_sha():
         return None
     return rec.get("tiles", {}).get(tile)
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        for line in Path("/proc/cpuinfo").read_text().splitlines():
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def single_thread_rate(fn, m: int):
+    """Elements/s of fn(m) with the oracle on one thread (its OpenMP pool
+    restored afterwards)."""
+    import oracle
+    nt = oracle.max_threads()
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        fn(m)
+        dt = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(nt)
+    return {"value": m / dt, "unit": "elements/s", "cores": 1, "sample": f"first {m} elements ({dt:.2f} s)"}
 
 
 def cpu_baseline(batch, p, budget_s: float, chunk: int = 4096, fields=None, rule=None, kind=None):
@@ -128,7 +160,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--mode", default="forward", choices=["forward", "fields", "hex", "tet", "adjoint", "mixed", "assemble"])
+    ap.add_argument("--mode", default="suite",
+                    choices=["suite", "forward", "fields", "hex", "tet", "adjoint", "mixed", "assemble"])
     ap.add_argument("--workload", default=None)
     ap.add_argument("--rule", default="collapsed", choices=["collapsed", "symmetric"],
                     help="quadrature rule of the forward, fields and adjoint modes")
@@ -149,16 +182,21 @@ def main():
                                    "is independent per element and is not sharded here",
                           "n_gpus": args.gpus}))
         sys.exit(2)
-    if args.mode == "adjoint":
-        return bench_adjoint(args)
-    if args.mode == "mixed":
-        return bench_mixed(args)
-    if args.mode == "assemble":
-        return bench_assemble(args)
-    return bench_forward(args, fields=args.mode == "fields", kind=args.mode if args.mode in ("hex", "tet") else None)
+    if args.mode == "suite":
+        line = bench_suite(args)
+    elif args.mode == "adjoint":
+        line = bench_adjoint(args)
+    elif args.mode == "mixed":
+        line = bench_mixed(args)
+    elif args.mode == "assemble":
+        line = bench_assemble(args)
+    else:
+        line = bench_forward(args, fields=args.mode == "fields",
+                             kind=args.mode if args.mode in ("hex", "tet") else None)
+    print(json.dumps(line))
 
 
-def bench_forward(args, fields=False, kind=None):
+def bench_forward(args, fields=False, kind=None, err_idx=None, cpu_budget=None):
     """Forward integration; with `fields` the coefficients are vertex fields
     evaluated at every point (feint_integrate_fields); with `kind` "hex" or
     "tet" the elements are hexahedra or tetrahedra (feint_integrate_hex/_tet)."""
@@ -245,7 +283,7 @@ def bench_forward(args, fields=False, kind=None):
         wall = time.perf_counter() - t0
         per = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
         ms = float(np.mean(per))
-        sample_idx = torch.arange(min(ne, 4096), device=dev)
+        sample_idx = torch.from_numpy(err_idx).to(dev) if err_idx is not None else torch.arange(min(ne, 4096), device=dev)
         results[form] = dict(ms_per_step=wall * 1e3 / args.steps, kernel_ms_mean=ms,
                              kernel_ms_min=float(np.min(per)), tile=tile, tune_ms=tile_ms,
                              elements_per_s=ne * args.steps / wall,
@@ -265,19 +303,41 @@ def bench_forward(args, fields=False, kind=None):
             r["alg_flops_per_element"] = costmodel.f_factored(n, p + 1, q)
         else:
             r["alg_flops_per_element"] = fdom
-        r["gflops"] = fdom * ne / (r["kernel_ms_mean"] * 1e-3) / 1e9
+        r["fdom_equiv_gflops"] = fdom * ne / (r["kernel_ms_mean"] * 1e-3) / 1e9
         r["gflops_alg"] = r["alg_flops_per_element"] * ne / (r["kernel_ms_mean"] * 1e-3) / 1e9
         r["tflops_frac_of_peak"] = r["gflops_alg"] / 1e3 / PEAK_TFLOPS[form]
         r["hbm_gbs_algorithmic"] = alg_bytes / (r["kernel_ms_mean"] * 1e-3) / 1e9
 
     cpu = None
     if not args.no_cpu:
-        rate, done, spent, cores, (Ar, br) = cpu_baseline(batch, p, args.cpu_budget, fields=vf,
-                                                          rule=None if rule == "collapsed" else rule, kind=kind)
+        import oracle
+        orule = None if rule == "collapsed" else rule
+        budget = args.cpu_budget if cpu_budget is None else cpu_budget
+        chunk = 4096 if p < 6 else 256
+        rate, done, spent, cores, (Ar, br) = cpu_baseline(batch, p, budget, chunk=chunk, fields=vf, rule=orule,
+                                                          kind=kind)
+
+        def one(m):
+            sub = batch.subset(np.arange(min(m, ne)))
+            if kind:
+                fn = oracle.integrate_hex if kind == "hex" else oracle.integrate_tet
+                fn(p, sub.coords, sub.D, sub.beta, sub.c, sub.f)
+            elif vf is not None:
+                oracle.integrate_fields(p, sub.coords, *[np.ascontiguousarray(a[:sub.ne]) for a in vf], rule=orule)
+            else:
+                oracle.integrate(p, sub.coords, sub.D, sub.beta, sub.c, sub.f, rule=orule)
         cpu = {"value": rate, "unit": "elements/s", "cores": cores, "kind": "oracle",
                "sample": f"first {done} of the {ne} elements of {args.workload} "
                          f"({spent:.1f} s, FP64, OpenMP over elements)",
-               "cpu": platform.processor() or platform.machine()}
+               "cpu": cpu_model(),
+               "single_thread": single_thread_rate(one, min(ne, 1024 if p <= 4 else 64 >> max(0, p - 5)))}
+        if err_idx is not None:       # the sampled elements, one by one
+            sub = batch.subset(err_idx)
+            if kind:
+                fn = oracle.integrate_hex if kind == "hex" else oracle.integrate_tet
+                Ar, br, _ = fn(p, sub.coords, sub.D, sub.beta, sub.c, sub.f)
+            else:
+                Ar, br, _ = oracle.integrate(p, sub.coords, sub.D, sub.beta, sub.c, sub.f, rule=orule)
         m = Ar.shape[0]
         for form, r in results.items():
             gA, mA = rel_err(r["A_sample"][:m], Ar)
@@ -285,7 +345,8 @@ def bench_forward(args, fields=False, kind=None):
             r["rel_err_A"] = gA
             r["rel_err_A_max_elem"] = mA
             r["rel_err_b"] = gb
-            r["err_sample"] = m
+            r["rel_err_b_max_elem"] = mb
+            r["err_sample"] = m if err_idx is None else f"{m} elements (every {ne // m}th)"
 
     h = results[headline]
     rkey = "" if rule == "collapsed" else ":" + rule
@@ -343,14 +404,68 @@ def bench_forward(args, fields=False, kind=None):
                    "nshp": n, "nq": q, "coefficients": "vertex fields" if fields else "element constants",
                    "mesh": f"{w['nx']}x{w['ny']}x{w['nz']}", "perturbation": w["amp"], "seed": w["seed"],
                    "form": headline, "parallelism": "single GPU"},
-        "gflops": h["gflops"],
+        "fdom_equiv_gflops": h["fdom_equiv_gflops"],
         "speedup_vs_fp64_gpu": results["fp64"]["kernel_ms_mean"] / h["kernel_ms_mean"] if "fp64" in results else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": forms_out,
         "device": torch.cuda.get_device_name(0),
     }
-    print(json.dumps(line))
+    return line
+
+
+SUMMARY_DROP = ("n_gpus", "steps", "warmup", "higher_is_better", "scaling", "vs_baseline", "data", "metric")
+
+
+def summarise(line):
+    """A workload's line without the keys the enclosing line already states."""
+    return {k: v for k, v in line.items() if k not in SUMMARY_DROP}
+
+
+def bench_suite(args):
+    """The default run: the p = 4 headline (all four forms) and, as keys of the
+    same line, every other configured workload in its own launch
+    configuration: p = 1 at 4096 elements (latency-bound) and at 524288 (HBM),
+    the mixed-degree batch replayed from a HIP graph, the p = 3 adjoint and
+    the p = 7 forward (split forms beside FP32 and FP64) and adjoint."""
+    import copy
+    import torch
+
+    def sub(**kw):
+        a = copy.copy(args)
+        for k, v in kw.items():
+            setattr(a, k, v)
+        return a
+    steps, warm = min(args.steps, 10), min(args.warmup, 3)
+    budget = min(args.cpu_budget, 4.0)
+    line = bench_forward(sub(workload="p4_131072", forms=None))
+    cfg = {}
+    stage = lambda name: print(f"[bench] suite: {name}", file=sys.stderr, flush=True)
+    stage("p1_4096")
+    cfg["p1_4096"] = summarise(bench_forward(sub(workload="p1_4096", forms="fp64,fp32"),
+                                             err_idx=np.arange(4096), cpu_budget=budget))
+    torch.cuda.empty_cache()
+    stage("p1_524288")
+    cfg["p1_524288"] = summarise(bench_forward(sub(workload="p1_524288", forms="fp64,fp32"), cpu_budget=budget))
+    torch.cuda.empty_cache()
+    stage("mixed_262144")
+    cfg["mixed_262144"] = summarise(bench_mixed(sub(workload="mixed_262144", forms="fp32", steps=steps,
+                                                    warmup=warm)))
+    torch.cuda.empty_cache()
+    stage("adj_p3_131072")
+    cfg["adj_p3_131072"] = summarise(bench_adjoint(sub(workload="adj_p3_131072", forms="fp32,fp64", steps=steps,
+                                                       warmup=warm, cpu_budget=budget)))
+    torch.cuda.empty_cache()
+    stage("p7_16384")
+    cfg["p7_16384"] = summarise(bench_forward(sub(workload="p7_16384", forms="bf16x3,fp16x3,fp32,fp64",
+                                                  steps=steps, warmup=warm),
+                                              err_idx=np.arange(0, 16384, 16), cpu_budget=budget))
+    torch.cuda.empty_cache()
+    stage("adj_p7_16384")
+    cfg["adj_p7_16384"] = summarise(bench_adjoint(sub(workload="p7_16384", forms="fp32,fp64", steps=steps,
+                                                      warmup=warm, cpu_budget=budget)))
+    line["configs"] = cfg
+    return line
 
 
 def bench_adjoint(args):
@@ -402,7 +517,7 @@ def bench_adjoint(args):
         es = 8 if form == "fp64" else 4
         res[form] = dict(kernel_ms_mean=ms, kernel_ms_min=mn, ms_per_step=wall, elements_per_s=ne / (wall * 1e-3),
                          block=block, tune_ms=tune_ms,
-                         gflops=costmodel.f_dom(p, rule) * ne / (ms * 1e-3) / 1e9,
+                         fdom_equiv_gflops=costmodel.f_dom(p, rule) * ne / (ms * 1e-3) / 1e9,
                          gflops_alg=(costmodel.f_adjoint_factored(p, rule) if costmodel.is_kf_tile(block)
                                      else costmodel.f_dom(p, rule)) * ne / (ms * 1e-3) / 1e9,
                          hbm_gbs_algorithmic=ne * costmodel.adjoint_bytes_per_element(p, es) / (ms * 1e-3) / 1e9,
@@ -417,8 +532,12 @@ def bench_adjoint(args):
         Gs = G[sample] if G is not None else Gdev[si].cpu().numpy()
         gs = g[sample] if g is not None else gdev[si].cpu().numpy()
         ref = oracle.adjoint(p, sub.coords, sub.D, sub.beta, sub.c, sub.f, Gs, gs, rule=orule)
+        names = ("dcoords", "dD", "dbeta", "dc", "df")
         for form, r in res.items():
             r["rel_err"] = max(float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(r["grads"], ref[:5]))
+            r["rel_err_per_array"] = {nm: dict(zip(("global", "max_elem"), rel_err(a, b)))
+                                      for nm, a, b in zip(names, r["grads"], ref[:5])}
+            r["err_sample"] = len(sample)
         chunk = min(ne, max(16, 2048 >> (2 * max(0, p - 3))))
         m, spent = 0, 0.0
         while spent < args.cpu_budget and m < ne:     # whole chunks until the time budget is spent
@@ -430,8 +549,16 @@ def bench_adjoint(args):
             oracle.adjoint(p, part.coords, part.D, part.beta, part.c, part.f, Gm, gm, rule=orule)
             spent += time.perf_counter() - t0
             m = hi
+        m1 = min(ne, 256 if p <= 3 else 4)
+
+        def one(k):
+            part = batch.subset(np.arange(k))
+            Gk = G[:k] if G is not None else Gdev[:k].cpu().numpy()
+            gk = g[:k] if g is not None else gdev[:k].cpu().numpy()
+            oracle.adjoint(p, part.coords, part.D, part.beta, part.c, part.f, Gk, gk, rule=orule)
         cpu = {"value": m / spent, "unit": "elements/s", "cores": oracle.max_threads(), "kind": "oracle",
-               "sample": f"first {m} of {ne} elements ({spent:.1f} s, FP64 reverse mode)"}
+               "sample": f"first {m} of {ne} elements ({spent:.1f} s, FP64 reverse mode)", "cpu": cpu_model(),
+               "single_thread": single_thread_rate(one, m1)}
     for r in res.values():
         r.pop("grads", None)
     h = res[forms[0]]
@@ -448,7 +575,7 @@ def bench_adjoint(args):
                                  "point by point; the factorised kernel's count for TKxTBf shapes "
                                  "(8 n^2 nij + 8 (p+1)^2 nij n + 36 nq n)"},
             "cpu_baseline": cpu, "forms": fmt(res)}
-    print(json.dumps(line))
+    return line
 
 
 def bench_mixed(args):
@@ -482,6 +609,23 @@ def bench_mixed(args):
     goA, gob = torch.empty_like(offA), torch.empty_like(offb)
     plan.capture(*X, pd, gA, gb, goA, gob)
     ms_g, mn_g, wall_g = timed(plan.replay, args.steps, args.warmup)
+    errs = None
+    if not args.no_cpu:
+        # the first 1024 elements of each degree, from the graph replay's outputs, against the oracle
+        import oracle
+        torch.cuda.synchronize()
+        oA, ob = goA.cpu().numpy(), gob.cpu().numpy()
+        errs = {}
+        for d in range(1, 7):
+            idx = np.nonzero(batch.p == d)[0][:1024]
+            n = costmodel.nshp(d)
+            ia = torch.from_numpy(np.concatenate([np.arange(oA[e], oA[e] + n * n) for e in idx])).to(dev)
+            ib = torch.from_numpy(np.concatenate([np.arange(ob[e], ob[e] + n) for e in idx])).to(dev)
+            sub = batch.subset(idx)
+            Ar, br, _ = oracle.integrate(d, sub.coords, sub.D, sub.beta, sub.c, sub.f)
+            gA_, mA_ = rel_err(gA[ia].cpu().numpy().reshape(len(idx), n, n), Ar)
+            gb_, _ = rel_err(gb[ib].cpu().numpy().reshape(len(idx), n), br)
+            errs[f"p{d}"] = {"rel_err_A": gA_, "rel_err_A_max_elem": mA_, "rel_err_b": gb_, "elements": len(idx)}
     counts = np.bincount(batch.p, minlength=7)
     fdom = sum(int(counts[d]) * costmodel.f_dom(d) for d in range(1, 7))
     shapes = plan.tile_describe(plan.tile).split(",")     # one entry per degree 1..6
@@ -503,7 +647,7 @@ def bench_mixed(args):
         rate = 1.0 / sum(frac[d - 1] / rates[d] for d in range(1, 7))
         cpu = {"value": rate, "unit": "elements/s", "cores": oracle.max_threads(), "kind": "oracle",
                "sample": "per degree the first elements of that degree (4096 >> 2(p-1), at least 16); "
-                         "rate combined with the batch's degree mix"}
+                         "rate combined with the batch's degree mix", "cpu": cpu_model()}
     line = {"metric": "mixed-degree elements/s (one persistent degree-bucketed launch, HIP graph)",
             "value": ne / (ms_g * 1e-3), "unit": "elements/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": wall_g, "higher_is_better": True, "scaling": "weak",
@@ -512,15 +656,15 @@ def bench_mixed(args):
                        "tile_set": plan.tile, "tile_set_shapes": plan.tile_describe(plan.tile)},
             "tile_sets_ms": sets_ms,
             "bucket_ms": ms_b, "persistent_ms": ms_p, "persistent_ms_min": mn_p, "graph_ms": ms_g,
-            "graph_ms_min": mn_g, "tune_ms": tune_ms, "gflops": fdom / (ms_p * 1e-3) / 1e9,
+            "graph_ms_min": mn_g, "tune_ms": tune_ms, "fdom_equiv_gflops": fdom / (ms_p * 1e-3) / 1e9,
             "roofline": {"bound": "mfma", "achieved": flops / (ms_p * 1e-3) / 1e12, "peak": peak,
                          "unit": "TFLOP/s", "frac": flops / (ms_p * 1e-3) / 1e12 / peak, "traffic": None,
                          "flops_per_launch": flops, "fdom_per_launch": fdom, "alg_bytes_per_launch": bytes_,
                          "note": "flops of the algorithm each degree's kernel runs: 8 n^2 nq per element "
                                  "point by point, the triangle-point contraction's count for KxTNf shapes"},
-            "cpu_baseline": cpu}
+            "cpu_baseline": cpu, "errors_vs_oracle": errs}
     plan.close()
-    print(json.dumps(fmt(line)))
+    return fmt(line)
 
 
 def bench_assemble(args):
@@ -581,7 +725,7 @@ def bench_assemble(args):
                          "frac": h["gbs"] / HBM_PEAK_GBS, "traffic": None},
             "cpu_baseline": cpu, "forms": fmt(res)}
     plan.close()
-    print(json.dumps(fmt(line)))
+    return fmt(line)
 
 
 if __name__ == "__main__":
