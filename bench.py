@@ -47,7 +47,10 @@ DTYPE_DESC = {"bf16x3": "bf16x3 (split bf16 MFMA, fp32 accumulate, fp64 geometry
               "fp32": "fp32 (fp32 MFMA, fp64 geometry)", "fp64": "fp64"}
 KERNEL_SOURCES = ["paper_1310_1194_amd/csrc/fwd_kernels.h", "paper_1310_1194_amd/csrc/fwd_staged.h",
                   "paper_1310_1194_amd/csrc/fwd_pipe.h", "paper_1310_1194_amd/csrc/fwd_valu.h",
+                  "paper_1310_1194_amd/csrc/fwd_fact.h", "paper_1310_1194_amd/csrc/fwd_ymfma.h",
                   "paper_1310_1194_amd/csrc/fwd_registry.h", "paper_1310_1194_amd/csrc/fwd_bf16.hip",
+                  "paper_1310_1194_amd/csrc/fwd_f16.hip", "paper_1310_1194_amd/csrc/fwd_f32.hip",
+                  "paper_1310_1194_amd/csrc/fwd_f64.hip",
                   "paper_1310_1194_amd/csrc/device_common.h", "paper_1310_1194_amd/csrc/tables.cpp"]
 
 
