@@ -11,12 +11,13 @@ every form's relative error against the FP64 oracle on a sample of elements is
 stated in the same line.  The default run (mode "suite") adds, as keys of
 `configs` in the same line, every other configured workload in its own launch
 configuration: p = 1 at 4096 and 524288 elements, the mixed-degree batch
-replayed from a HIP graph, the p = 3 adjoint and the p = 7 forward and
-adjoint, each with its roofline, its error against the oracle and its CPU
-baseline.
+replayed from a HIP graph, the p = 3 adjoint, the p = 7 forward and
+adjoint, and the paper's own term (Laplace) on its quadrature at its batch
+sizes for p = 1..7, each with its roofline, its error against the oracle and
+its CPU baseline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--copy-cal]
-                    [--mode suite|forward|fields|hex|tet|adjoint|mixed|assemble]
+                    [--mode suite|forward|fields|hex|tet|adjoint|mixed|assemble|laplace]
                     [--workload NAME] [--forms LIST]
 """
 from __future__ import annotations
@@ -164,7 +165,7 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", default="suite",
-                    choices=["suite", "forward", "fields", "hex", "tet", "adjoint", "mixed", "assemble"])
+                    choices=["suite", "forward", "fields", "hex", "tet", "adjoint", "mixed", "assemble", "laplace"])
     ap.add_argument("--workload", default=None)
     ap.add_argument("--rule", default="collapsed", choices=["collapsed", "symmetric"],
                     help="quadrature rule of the forward, fields and adjoint modes")
@@ -193,6 +194,8 @@ def main():
         line = bench_mixed(args)
     elif args.mode == "assemble":
         line = bench_assemble(args)
+    elif args.mode == "laplace":
+        line = bench_laplace(args)
     else:
         line = bench_forward(args, fields=args.mode == "fields",
                              kind=args.mode if args.mode in ("hex", "tet") else None)
@@ -467,7 +470,85 @@ def bench_suite(args):
     stage("adj_p7_16384")
     cfg["adj_p7_16384"] = summarise(bench_adjoint(sub(workload="p7_16384", forms="fp32,fp64", steps=steps,
                                                       warmup=warm, cpu_budget=budget)))
+    torch.cuda.empty_cache()
+    stage("laplace_paper_sweep")
+    cfg["laplace_paper_sweep"] = summarise(bench_laplace(sub(workload=None, forms="fp32", steps=steps,
+                                                             warmup=warm)))
     line["configs"] = cfg
+    return line
+
+
+def bench_laplace(args):
+    """The paper's own term (Laplace, eq. (1)) on its quadrature (the symmetric
+    rule, N_I points), FP32 (its precision), at the paper's batch sizes: element
+    matrices of about 500 MB, N_e = 500e6 / (4 n^2), for p = 1..7, on the
+    perturbed prism mesh (first N_e elements).  GFLOP/s in the paper's
+    convention = Table 2's operation count per element (shape functions,
+    Jacobian, 7 per matrix entry, all per point) times N_e / kernel time."""
+    import torch
+    import paper_1310_1194_amd as F
+    dev = torch.device("cuda:0")
+    form = (args.forms or "fp32").split(",")[0]
+    degrees = [int(x) for x in (args.workload or "1,2,3,4,5,6,7").split(",")] if args.workload and \
+        args.workload[0].isdigit() else list(range(1, 8))
+    steps, warm = max(3, min(args.steps, 10)), max(1, min(args.warmup, 3))
+    rows = {}
+    cpu = None
+    for p in degrees:
+        n = costmodel.nshp(p)
+        ne = 500_000_000 // (4 * n * n)
+        cells = -(-ne // 2)
+        nx = ny = min(128, max(4, int(round(cells ** (1 / 3)))))
+        nz = -(-cells // (nx * ny))
+        batch = meshgen.make_batch(nx, ny, nz, amp=0.2, seed=10 + p).subset(np.arange(ne))
+        X = torch.from_numpy(np.ascontiguousarray(batch.coords)).to(dev)
+        dt = torch.float64 if form == "fp64" else torch.float32
+        A = torch.empty((ne, n, n), dtype=dt, device=dev)
+        tune = None if args.no_tune else F.laplace_autotune(X, p, form, A, reps=2)
+        tile = F.laplace_tile_describe(p, form, F.laplace_tile_get(p, form))
+        ms, mn, wall = timed(lambda: F.integrate_laplace_raw(X, p, form, A=A), steps, warm)
+        points = F.nq(p, "symmetric")
+        paper_ops = costmodel.laplace_paper_ops(p, points)
+        own = costmodel.f_kf(p, "symmetric") if costmodel.is_kf_tile(tile) else costmodel.f_dom(p, "symmetric")
+        peak = PEAK_TFLOPS[form]
+        r = dict(ne=ne, mesh=f"{nx}x{ny}x{nz}", points=points, tile=tile, tune_ms=tune, kernel_ms_mean=ms,
+                 kernel_ms_min=mn, us_per_element=ms * 1e3 / ne, elements_per_s=ne / (ms * 1e-3),
+                 paper_convention_gflops=paper_ops * ne / (ms * 1e-3) / 1e9,
+                 own_count_tflops=own * ne / (ms * 1e-3) / 1e12, own_count_frac_of_peak=own * ne / (ms * 1e-3) / 1e12 / peak,
+                 hbm_gbs_algorithmic=ne * (8 * 18 + n * n * (8 if form == "fp64" else 4)) / (ms * 1e-3) / 1e9)
+        if not args.no_cpu:
+            import oracle
+            idx = np.unique(np.linspace(0, ne - 1, min(ne, 64)).astype(np.int64))
+            Ar, _ = oracle.integrate_laplace(p, batch.coords[idx])
+            r["rel_err_A"], r["rel_err_A_max_elem"] = rel_err(A[torch.from_numpy(idx).to(dev)].cpu().numpy(), Ar)
+            r["err_sample"] = len(idx)
+            if p == 4:
+                m = min(ne, 4096)
+                t0 = time.perf_counter()
+                oracle.integrate_laplace(p, batch.coords[:m])
+                spent = time.perf_counter() - t0
+                cpu = {"value": m / spent, "unit": "elements/s", "cores": oracle.max_threads(), "kind": "oracle",
+                       "sample": f"p = 4: the first {m} of the {ne} elements ({spent:.2f} s, FP64)", "cpu": cpu_model(),
+                       "single_thread": single_thread_rate(lambda k: oracle.integrate_laplace(p, batch.coords[:k]),
+                                                           min(ne, 1024))}
+        rows[f"p{p}"] = r
+        print(f"[bench] laplace p={p} ne={ne}: {ms:.3f} ms, {r['paper_convention_gflops']:.0f} GFLOP/s (paper "
+              f"convention), tile {tile}", file=sys.stderr, flush=True)
+        del A, X
+        torch.cuda.empty_cache()
+    h = rows.get("p4") or next(iter(rows.values()))
+    line = {"metric": "Laplace-term integration (the paper's eq. (1) on its N_I points) at its 500 MB batch sizes: "
+                      "elements/s and GFLOP/s in the paper's convention",
+            "value": h["elements_per_s"], "unit": "elements/s", "n_gpus": 1, "steps": steps, "warmup": warm,
+            "ms_per_step": h["kernel_ms_mean"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": form, "data": "synthetic (seeded perturbed prism meshes)",
+            "config": {"workload": "laplace_paper_sweep", "rule": "symmetric", "degrees": degrees,
+                       "batch": "N_e = 500e6 / (4 n^2) per degree (element matrices of about 500 MB)"},
+            "roofline": {"bound": "mfma", "achieved": h["own_count_tflops"], "peak": PEAK_TFLOPS[form],
+                         "unit": "TFLOP/s", "frac": h["own_count_frac_of_peak"], "traffic": None,
+                         "note": "p = 4 row; flops of the algorithm the variant runs (the factorised count for "
+                                 "KxTNf shapes, 8 n^2 N_I point by point)"},
+            "cpu_baseline": cpu, "degrees": fmt(rows)}
     return line
 
 

@@ -366,6 +366,27 @@ feint_status feint_tet_tile_describe(int p, feint_form form, int tile, char *buf
 feint_status feint_tet_autotune(const feint_elements *el, int p, feint_form form, void *A, void *b, int reps,
                                 double *best_ms, void *stream);
 
+/* ---- The paper's own term (eq. (1), Sec. 2) on its quadrature ---------------
+   The stiffness matrix of the Laplace operator alone,
+     A_ab = sum_q w_q det J_q grad phi_a . grad phi_b,
+   with no coefficients and no load vector (the paper integrates exactly this
+   term, Sec. 2, and counts its work in Table 2), on the symmetric prism rule
+   of feint_integrate_rule (the N_I points of Table 3).  coords [ne][6][3]
+   FP64 (device); A [ne][n][n], row-major, double for FEINT_FP64 and float
+   for FEINT_FP32 (the paper's precision); the split forms give
+   UNSUPPORTED_FORM.  xq (nullable) [ne][N_I][3] mapped points; dev_status
+   bit 0 as for feint_integrate.  ne == 0 is a no-op; null coords or A with
+   ne > 0 give INVALID_ARG.  Tile calls and the autotuner as for the other
+   element types ("vL", "KxTNf"). */
+feint_status feint_integrate_laplace(const double *coords, int64_t ne, int p, feint_form form, void *A,
+                                     double *xq, uint32_t *dev_status, void *stream);
+int feint_laplace_tile_count(int p, feint_form form);
+int feint_laplace_tile_get(int p, feint_form form);
+feint_status feint_laplace_tile_set(int p, feint_form form, int tile);
+feint_status feint_laplace_tile_describe(int p, feint_form form, int tile, char *buf, size_t len);
+feint_status feint_laplace_autotune(const double *coords, int64_t ne, int p, feint_form form, void *A, int reps,
+                                    double *best_ms, void *stream);
+
 /* ---- Global assembly (Sec. 2) ----------------------------------------------
    The element matrices and load vectors of one degree are summed into a CSR
    matrix and a right-hand side through the element-to-global dof map.

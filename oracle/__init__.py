@@ -180,6 +180,19 @@ def integrate(p, coords, D, beta, c, f, n1=0, want_xq=False, rule=None):
     return A, b, flags
 
 
+def integrate_laplace(p, coords, rule="symmetric"):
+    """The paper's own term (its eq. (1)): A_ab = sum_q w_q det J_q grad phi_a .
+    grad phi_b on the given rule (default: the symmetric rule, the paper's
+    N_I points), i.e. the element loop above with D = I and no convection,
+    reaction or source.  Returns A [ne,n,n] and the det J <= 0 flags."""
+    coords = _c(coords)
+    ne = coords.shape[0]
+    D = np.repeat(np.eye(3)[None], ne, axis=0)
+    z3, z1 = np.zeros((ne, 3)), np.zeros(ne)
+    A, _, flags = integrate(p, coords, D, z3, z1, z1, rule=rule)
+    return A, flags
+
+
 def integrate_fields(p, coords, Dv, betav, cv, fv, n1=0, want_xq=False, rule=None):
     """Coefficients given at the six vertices (Dv [ne,6,3,3], betav [ne,6,3],
     cv [ne,6], fv [ne,6]) and evaluated at each point with the geometry shape

@@ -262,6 +262,59 @@ def hex_autotune(*a, **kw):
     return elem_autotune("hex", *a, **kw)
 
 
+def _laplace_inputs(coords, p, form):
+    if form not in ("fp64", "fp32"):
+        raise ValueError("the Laplace kernels run in the fp64 and fp32 forms")
+    ne = coords.shape[0]
+    _check_input("coords", coords, (6, 3), ne)
+    return ne, nshp(p)
+
+
+def integrate_laplace_raw(coords, p: int, form: str = "fp32", *, A=None, xq=None, status=None):
+    """The paper's own term: the Laplace stiffness matrix of prisms on its
+    quadrature (the symmetric rule, N_I points), no coefficients, no load
+    vector; returns A [ne, n, n]."""
+    ne, n = _laplace_inputs(coords, p, form)
+    dt = out_dtype(form)
+    if A is None:
+        A = torch.empty((ne, n, n), dtype=dt, device=coords.device)
+    if A.dtype != dt or A.numel() != ne * n * n:
+        raise ValueError("A has the wrong dtype or size")
+    if xq is not None and (xq.dtype != torch.float64 or xq.numel() != ne * nq(p, "symmetric") * 3):
+        raise ValueError("xq must be float64 with ne*nq*3 entries")
+    if status is not None and (status.dtype != torch.int32 or status.numel() < 1):
+        raise ValueError("status must be an int32 tensor")
+    check("feint_integrate_laplace", lib().feint_integrate_laplace(_ptr(coords), ne, int(p), FORMS[form], _ptr(A),
+                                                                   _ptr(xq), _ptr(status), _stream()))
+    return A
+
+
+def laplace_tile_count(p: int, form: str) -> int:
+    return lib().feint_laplace_tile_count(int(p), FORMS[form])
+
+
+def laplace_tile_get(p: int, form: str) -> int:
+    return lib().feint_laplace_tile_get(int(p), FORMS[form])
+
+
+def laplace_tile_set(p: int, form: str, tile: int) -> None:
+    check("feint_laplace_tile_set", lib().feint_laplace_tile_set(int(p), FORMS[form], int(tile)))
+
+
+def laplace_tile_describe(p: int, form: str, tile: int) -> str:
+    buf = ctypes.create_string_buffer(32)
+    check("feint_laplace_tile_describe", lib().feint_laplace_tile_describe(int(p), FORMS[form], int(tile), buf, 32))
+    return buf.value.decode()
+
+
+def laplace_autotune(coords, p: int, form: str, A, reps: int = 2) -> float:
+    ne, _ = _laplace_inputs(coords, p, form)
+    best = ctypes.c_double(0)
+    check("feint_laplace_autotune", lib().feint_laplace_autotune(_ptr(coords), ne, int(p), FORMS[form], _ptr(A),
+                                                                 int(reps), ctypes.byref(best), _stream()))
+    return best.value
+
+
 def adjoint_raw(coords, D, beta, c, f, G, g, p: int, form: str = "fp64", rule: str = "collapsed"):
     """Gradients of sum_e <G_e,A_e> + <g_e,b_e>: (dcoords, dD, dbeta, dc, df), FP64."""
     el = elements(coords, D, beta, c, f)

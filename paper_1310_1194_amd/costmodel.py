@@ -52,6 +52,18 @@ def paper_total_ops(p: int) -> int:
                           + paper_matrix_ops_per_point(p))
 
 
+def laplace_paper_ops_per_point(p: int) -> int:
+    """Work of the Laplace kernel (the paper's term on its rule) at one point,
+    counted the paper's way: shape functions, Jacobian, 7 per matrix entry."""
+    return paper_shape_ops_per_point(p) + PAPER_JACOBIAN_OPS + paper_matrix_ops_per_point(p)
+
+
+def laplace_paper_ops(p: int, points: int) -> int:
+    """The Laplace kernel's work per element in the paper's convention, for a
+    rule of `points` points (the kernel's rule has the paper's N_I)."""
+    return points * laplace_paper_ops_per_point(p)
+
+
 def f_dom(p: int, rule: str = "collapsed") -> int:
     """Algorithmic flops of the contraction per element: 8 n^2 nq."""
     return 8 * nshp(p) ** 2 * nq(p, rule)

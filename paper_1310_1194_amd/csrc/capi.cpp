@@ -23,6 +23,7 @@ std::mutex g_mu;
 std::map<int, DevTables *> g_tables;        // key: device * 64 + type * 16 + rule * 8 + p
 int g_tile[2][8][4];                        // chosen variant per (rule, p, form), prisms
 int g_tile_elem[3][8][4];                   // chosen variant per (type, p, form): 1 hexahedra, 2 tetrahedra
+int g_tile_lap[8][2];                       // chosen variant per (p, form) of the Laplace kernels
 thread_local std::string g_err;
 
 bool valid_form(int form) { return form >= FEINT_FP64 && form <= FEINT_FP16X3; }
@@ -518,6 +519,125 @@ feint_status feint_integrate_tet(const feint_elements *el, int p, feint_form for
 feint_status feint_tet_autotune(const feint_elements *el, int p, feint_form form, void *A, void *b, int reps,
                                 double *best_ms, void *stream) {
     return elem_autotune(2, el, p, form, A, b, reps, best_ms, stream);
+}
+
+// ---- The Laplace term alone on the symmetric rule --------------------------
+static int lap_tile_count(int p, int form) {
+    int cnt = 0;
+    if (p < 1 || p > kMaxP || (form != FEINT_FP64 && form != FEINT_FP32)) return 0;
+    fwd_variants_lap(form, p, &cnt);
+    return cnt;
+}
+
+// Forward parameters of a Laplace launch (host checks done by the caller); tile < 0
+// takes the chosen variant.
+static feint_status lap_params(const double *coords, int64_t ne, int p, int form, void *A, hipStream_t st,
+                               FwdParams &prm, const FwdVariant **vsel, int tile) {
+    const DevTables *T = nullptr;
+    feint_status s = tables_for_launch(p, st, &T, FEINT_RULE_SYMMETRIC, 0);
+    if (s != FEINT_OK) return s;
+    const feint_elements el = {coords, nullptr, nullptr, nullptr, nullptr, ne};
+    fill_fwd_params(prm, &el, form, T);
+    prm.A = A;
+    prm.b = nullptr;
+    int cnt = 0;
+    const FwdVariant *v = fwd_variants_lap(form, p, &cnt);
+    if (!v || cnt == 0) return FEINT_ERR_UNSUPPORTED_FORM;
+    if (tile < 0) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        tile = g_tile_lap[p][form];
+    }
+    *vsel = &v[(tile >= 0 && tile < cnt) ? tile : 0];
+    return FEINT_OK;
+}
+
+static feint_status lap_check(const double *coords, int64_t ne, int p, int form, const void *A) {
+    if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
+    if (lap_tile_count(p, form) == 0) return FEINT_ERR_UNSUPPORTED_FORM;
+    if (ne < 0) return FEINT_ERR_INVALID_ARG;
+    if (ne > 0 && (!coords || !A)) return FEINT_ERR_INVALID_ARG;
+    return FEINT_OK;
+}
+
+feint_status feint_integrate_laplace(const double *coords, int64_t ne, int p, feint_form form, void *A, double *xq,
+                                     uint32_t *dev_status, void *stream) {
+    feint_status s = lap_check(coords, ne, p, form, A);
+    if (s != FEINT_OK || ne == 0) return s;
+    hipStream_t st = (hipStream_t)stream;
+    FwdParams prm;
+    const FwdVariant *v = nullptr;
+    s = lap_params(coords, ne, p, form, A, st, prm, &v, -1);
+    if (s != FEINT_OK) return s;
+    prm.xq = xq;
+    prm.status = dev_status;
+    return launch_forward(prm, v, st);
+}
+
+int feint_laplace_tile_count(int p, feint_form form) { return lap_tile_count(p, form); }
+
+int feint_laplace_tile_get(int p, feint_form form) {
+    if (lap_tile_count(p, form) == 0) return -1;
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_tile_lap[p][form];
+}
+
+feint_status feint_laplace_tile_set(int p, feint_form form, int tile) {
+    if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
+    const int cnt = lap_tile_count(p, form);
+    if (cnt == 0) return FEINT_ERR_UNSUPPORTED_FORM;
+    if (tile < 0 || tile >= cnt) return FEINT_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tile_lap[p][form] = tile;
+    return FEINT_OK;
+}
+
+feint_status feint_laplace_tile_describe(int p, feint_form form, int tile, char *buf, size_t len) {
+    if (p < 1 || p > kMaxP) return FEINT_ERR_UNSUPPORTED_DEGREE;
+    const int cnt = lap_tile_count(p, form);
+    if (cnt == 0) return FEINT_ERR_UNSUPPORTED_FORM;
+    if (!buf || tile < 0 || tile >= cnt) return FEINT_ERR_INVALID_ARG;
+    int c = 0;
+    describe_variant(fwd_variants_lap(form, p, &c)[tile], buf, len);
+    return FEINT_OK;
+}
+
+feint_status feint_laplace_autotune(const double *coords, int64_t ne, int p, feint_form form, void *A, int reps,
+                                    double *best_ms, void *stream) {
+    feint_status s = lap_check(coords, ne, p, form, A);
+    if (s != FEINT_OK) return s;
+    if (ne == 0 || reps < 1) return FEINT_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const int cnt = lap_tile_count(p, form);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return FEINT_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return FEINT_ERR_HIP; }
+    int best = 0;
+    float best_t = 1e30f;
+    for (int t = 0; t < cnt && s == FEINT_OK; ++t) {
+        FwdParams prm;
+        const FwdVariant *v = nullptr;
+        s = lap_params(coords, ne, p, form, A, st, prm, &v, t);
+        if (s != FEINT_OK) break;
+        s = launch_forward(prm, v, st);                       // warm-up
+        if (s != FEINT_OK) break;
+        (void)hipEventRecord(e0, st);
+        for (int r = 0; r < reps && s == FEINT_OK; ++r) s = launch_forward(prm, v, st);
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) { s = FEINT_ERR_HIP; break; }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (ms < best_t) { best_t = ms; best = t; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != FEINT_OK) return s;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_tile_lap[p][form] = best;
+    }
+    if (best_ms) *best_ms = best_t;
+    return FEINT_OK;
 }
 
 const char *feint_status_string(feint_status s) {

@@ -116,6 +116,20 @@ __device__ inline void fused_block(const El &E, const double K[9], double wd, do
     sf = wd * E.f;
 }
 
+// The Laplace term alone (the paper's eq. (1)): grad phi_a . grad phi_b =
+// ref_a . (K K^T) ref_b, so W = wd [[0, 0], [0, K K^T]] (row-major into W[16]).
+__device__ inline void laplace_block(const double K[9], double wd, double W[16]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) W[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        W[4 * (i + 1)] = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            W[4 * (i + 1) + 1 + j] = wd * (K[3 * i] * K[3 * j] + K[3 * i + 1] * K[3 * j + 1] + K[3 * i + 2] * K[3 * j + 2]);
+    }
+}
+
 // Prism: W_q and sf at reference point (xi1, xi2, zeta) with weight w; returns det J.
 __device__ inline double point_block(const ElemIn &E, double xi1, double xi2, double ze, double w,
                                      double W[16], double &sf) {

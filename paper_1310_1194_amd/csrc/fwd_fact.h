@@ -84,7 +84,7 @@ struct KF {
         const T lsel = (lcol && kg == 0) ? (T)1 : (T)0;
         // without a spare column: b[(k,t)] = sum_ij tau_0(t, ij) sum_m L_k(zeta_m) (w det J f)_(ij,m),
         // in FP64 from the FP64 tables, by the blocks of the first column tile
-        const bool bblk = !SPARE && kp0 == 0 && tt == 0;
+        const bool bblk = G::LOAD && !SPARE && kp0 == 0 && tt == 0;
         typedef const __attribute__((address_space(4))) double CD;
         const CD *l64 = (const CD *)prm.lam;
         double bacc[SPARE ? 1 : TMV][TT];
@@ -232,7 +232,7 @@ struct KF {
         // the regular counts the body is inlined once, not twice
         const bool lastm = TML != TMK && bi == BM - 1, lastn = TNL != TN && bj % BK == BK - 1;
         // the load-vector column: first column tile (k' = 0) of the last triangle tile
-        const bool lb = SPARE && bj % BK == 0 && bj / BK == LCT;
+        const bool lb = G::LOAD && SPARE && bj % BK == 0 && bj / BK == LCT;
         if (lastm) {
             if (lastn) with_lb<TML, TNL>(lb, prm, slot, blk, bi, bj, sl);
             else with_lb<TML, TN>(lb, prm, slot, blk, bi, bj, sl);

@@ -108,6 +108,7 @@ template <int P> using LoadCol = LoadColN<c_nshp(P)>;
 // mapped point.  qp = (reference coordinates, weight) of the point.
 struct PrismGeo {
     typedef ElemIn Elem;
+    static constexpr bool LOAD = true;          // the element has a load vector
     __host__ __device__ static constexpr int nshp(int p) { return c_nshp(p); }
     __host__ __device__ static constexpr int nq(int p, int r) { return c_nq_rule(p, r); }
     __device__ static void load(const FwdParams &prm, int64_t e, Elem &E) { load_elem_fwd(prm, e, E); }
@@ -120,10 +121,37 @@ struct PrismGeo {
     __device__ static void map(const Elem &E, const double *qp, double x[3]) { prism_map(E.X, qp[0], qp[1], qp[2], x); }
 };
 
+// The paper's own term on prisms (its eq. (1), Laplace): A_ab = sum_q w_q det J_q
+// grad phi_a . grad phi_b with no load vector, so W_q = w det J [[0, 0], [0, K K^T]];
+// only the vertex coordinates are read.
+struct ElemX {
+    double X[18];   // vertices v0..v5
+};
+struct PrismLaplaceGeo {
+    typedef ElemX Elem;
+    static constexpr bool LOAD = false;
+    __host__ __device__ static constexpr int nshp(int p) { return c_nshp(p); }
+    __host__ __device__ static constexpr int nq(int p, int r) { return c_nq_rule(p, r); }
+    __device__ static void load(const FwdParams &prm, int64_t e, Elem &E) {
+#pragma unroll
+        for (int i = 0; i < 18; ++i) E.X[i] = prm.coords[18 * e + i];
+    }
+    __device__ static void coeffs(const FwdParams &, int64_t, const double *, Elem &) {}
+    __device__ static double block(const Elem &E, const double *qp, double W[16], double &sf) {
+        double K[9];
+        const double det = prism_jacobian(E.X, qp[0], qp[1], qp[2], K);
+        laplace_block(K, qp[3] * det, W);
+        sf = 0.0;
+        return det;
+    }
+    __device__ static void map(const Elem &E, const double *qp, double x[3]) { prism_map(E.X, qp[0], qp[1], qp[2], x); }
+};
+
 // Hexahedra (Table 1's tensor-product element): (p+1)^3 shape functions and
 // (p+1)^3 Gauss points; coordinates [ne][8][3], coefficients per element.
 struct HexGeo {
     typedef ElemHex Elem;
+    static constexpr bool LOAD = true;
     __host__ __device__ static constexpr int nshp(int p) { return (p + 1) * (p + 1) * (p + 1); }
     __host__ __device__ static constexpr int nq(int p, int) { return (p + 1) * (p + 1) * (p + 1); }
     __device__ static void load(const FwdParams &prm, int64_t e, Elem &E) {
@@ -147,6 +175,7 @@ struct HexGeo {
 // functions, (p+2)^3 collapsed Gauss points; coordinates [ne][4][3].
 struct TetGeo {
     typedef ElemTet Elem;
+    static constexpr bool LOAD = true;
     __host__ __device__ static constexpr int nshp(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
     __host__ __device__ static constexpr int nq(int p, int) { return (p + 2) * (p + 2) * (p + 2); }
     __device__ static void load(const FwdParams &prm, int64_t e, Elem &E) {

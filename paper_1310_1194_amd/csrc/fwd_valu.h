@@ -150,7 +150,7 @@ struct KV {
             T *Aout = (T *)prm.A + offA_of(prm, e, N);
 #pragma unroll
             for (int i = 0; i < N; ++i) Aout[(size_t)i * N + j] = acc[i];
-            ((T *)prm.b)[offb_of(prm, e, N) + j] = (T)bj;
+            if constexpr (G::LOAD) ((T *)prm.b)[offb_of(prm, e, N) + j] = (T)bj;
         }
     }
 };

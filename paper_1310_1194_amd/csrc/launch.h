@@ -55,6 +55,8 @@ const FwdVariant *fwd_variants_sym(int form, int p, int *count);
 const FwdVariant *fwd_variants_hex(int form, int p, int *count);
 // Tetrahedral elements (FP64 and FP32 forms).
 const FwdVariant *fwd_variants_tet(int form, int p, int *count);
+// The Laplace term alone on the symmetric rule (FP64 and FP32 forms).
+const FwdVariant *fwd_variants_lap(int form, int p, int *count);
 const FwdVariant *fwd_variants_f64(int p, int *count);
 const FwdVariant *fwd_variants_f32(int p, int *count);
 const FwdVariant *fwd_variants_bf16(int p, int *count);

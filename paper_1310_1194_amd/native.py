@@ -34,7 +34,8 @@ EXPORTS = (
     "feint_hex_tile_describe", "feint_hex_autotune", "feint_tet_nshp", "feint_tet_nq", "feint_prepare_tet",
     "feint_integrate_tet", "feint_tet_tile_count", "feint_tet_tile_get", "feint_tet_tile_set",
     "feint_tet_tile_describe", "feint_tet_autotune", "feint_integrate_adjoint_rule",
-    "feint_integrate_mixed_noalloc",
+    "feint_integrate_mixed_noalloc", "feint_integrate_laplace", "feint_laplace_tile_count",
+    "feint_laplace_tile_get", "feint_laplace_tile_set", "feint_laplace_tile_describe", "feint_laplace_autotune",
 )
 
 
@@ -142,6 +143,12 @@ def lib() -> ctypes.CDLL:
             "feint_tet_tile_set": (_i, [_i, _i, _i]),
             "feint_tet_tile_describe": (_i, [_i, _i, _i, ctypes.c_char_p, ctypes.c_size_t]),
             "feint_tet_autotune": (_i, [P, _i, _i, _vp, _vp, _i, ctypes.POINTER(ctypes.c_double), _vp]),
+            "feint_integrate_laplace": (_i, [_vp, _i64, _i, _i, _vp, _vp, _vp, _vp]),
+            "feint_laplace_tile_count": (_i, [_i, _i]),
+            "feint_laplace_tile_get": (_i, [_i, _i]),
+            "feint_laplace_tile_set": (_i, [_i, _i, _i]),
+            "feint_laplace_tile_describe": (_i, [_i, _i, _i, ctypes.c_char_p, ctypes.c_size_t]),
+            "feint_laplace_autotune": (_i, [_vp, _i64, _i, _i, _vp, _i, ctypes.POINTER(ctypes.c_double), _vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)

@@ -243,3 +243,32 @@ def test_tet_host_api():
     assert L.feint_integrate_tet(None, 3, 0, A, A, None, None, s) == -1
     assert L.feint_integrate_tet(ctypes.byref(_el(0, null=True)), 3, 0, None, None, None, None, s) == 0
     assert L.feint_tet_tile_set(3, 1, 99) == -1
+
+
+def test_laplace_host_api():
+    """The Laplace-only entry points: FP64 and FP32 variants at every degree, the
+    split forms refused, and every host-side error before any launch."""
+    L = native.lib()
+    buf = ctypes.create_string_buffer(32)
+    for p in range(1, 8):
+        for form in (0, 1):
+            n = L.feint_laplace_tile_count(p, form)
+            assert n >= 1 and L.feint_laplace_tile_get(p, form) == 0
+            for t in range(n):
+                assert L.feint_laplace_tile_describe(p, form, t, buf, 32) == 0
+                assert re.fullmatch(rb"(\d+x\d+f|v\d+)(o2)?", buf.value), buf.value
+        for form in (2, 3):
+            assert L.feint_laplace_tile_count(p, form) == 0 and L.feint_laplace_tile_get(p, form) == -1
+    X = ctypes.c_void_p(0x1000)
+    A = ctypes.c_void_p(0x2000)
+    s = ctypes.c_void_p(0)
+    assert L.feint_integrate_laplace(X, 4, 3, 2, A, None, None, s) == -3
+    assert L.feint_integrate_laplace(X, 4, 8, 0, A, None, None, s) == -2
+    assert L.feint_integrate_laplace(X, -1, 3, 0, A, None, None, s) == -1
+    assert L.feint_integrate_laplace(None, 4, 3, 0, A, None, None, s) == -1
+    assert L.feint_integrate_laplace(X, 4, 3, 1, None, None, None, s) == -1
+    assert L.feint_integrate_laplace(None, 0, 3, 0, None, None, None, s) == 0
+    assert L.feint_laplace_tile_set(3, 0, 99) == -1 and L.feint_laplace_tile_set(3, 2, 0) == -3
+    assert L.feint_laplace_tile_set(0, 0, 0) == -2
+    assert L.feint_laplace_autotune(X, 0, 3, 0, A, 1, None, s) == -1
+    assert L.feint_laplace_autotune(X, 4, 3, 0, A, 0, None, s) == -1

@@ -119,3 +119,23 @@ def test_adjoint_factored_count(p, rule):
     flops += sum(2 * nk for _pt in range(q) for _r in range(4) for _b in range(n))   # Hh
     flops += sum(4 + 16 * 2 for _pt in range(q) for _b in range(n))             # B products, S_q sums
     assert cm.f_adjoint_factored(p, rule) == flops
+
+
+@pytest.mark.parametrize("p", P)
+def test_laplace_kernel_work_is_table2(p):
+    """The Laplace kernel integrates the paper's term on the library's symmetric
+    rule: its point count (from the C-ABI) is the paper's N_I (Table 3 / 4), its
+    matrix has Table 3's entries, and its work counted the paper's way equals
+    Table 2 per point and in total."""
+    from paper_1310_1194_amd.native import lib
+    g = golden()
+    points = lib().feint_nq_rule(p, 1)
+    assert 4 * points == g["table3_quadrature"][p - 1]
+    assert cm.nshp(p) ** 2 == g["table3_element_matrix"][p - 1]
+    per_point = cm.laplace_paper_ops_per_point(p)
+    printed = (g["table2_shape_per_point"][p - 1] if p < 7 else 5628) + g["table2_jacobian_per_point"][p - 1] \
+        + g["table2_matrix_per_point"][p - 1]
+    assert per_point == printed
+    total = cm.laplace_paper_ops(p, points) / 1e3
+    printed_total = g["table2_shape_total"][p - 1] + g["table2_jacobian_total"][p - 1] + g["table2_matrix_total"][p - 1]
+    assert abs(total - printed_total) <= 1.0 + 0.001 * printed_total

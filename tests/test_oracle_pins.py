@@ -580,3 +580,24 @@ def test_fields_are_linear():
     A3, b3, _ = oracle.integrate_fields(p, batch.coords, *[2.0 * x - 3.0 * y for x, y in zip(F1, F2)])
     assert np.abs(A3 - (2 * A1 - 3 * A2)).max() <= 1e-13 * np.abs(A3).max()
     assert np.abs(b3 - (2 * b1 - 3 * b2)).max() <= 1e-13 * np.abs(b3).max()
+
+
+def test_laplace_right_prism_p1_textbook():
+    """The Laplace-only oracle (the paper's eq. (1)) on its symmetric rule, p=1,
+    right prism: M_z (x) K_T + K_z (x) M_T with the textbook P1 triangle and
+    linear 1D matrices (the rule is exact on affine prisms)."""
+    import oracle
+    P = np.array([[0.1, 0.2], [0.9, 0.3], [0.4, 1.1]])
+    z0, H = 0.25, 0.6
+    X = np.array([[*P[i], z0] for i in range(3)] + [[*P[i], z0 + H] for i in range(3)])
+    area = 0.5 * ((P[1, 0] - P[0, 0]) * (P[2, 1] - P[0, 1]) - (P[2, 0] - P[0, 0]) * (P[1, 1] - P[0, 1]))
+    bb = np.array([P[(i + 1) % 3, 1] - P[(i + 2) % 3, 1] for i in range(3)])
+    cc = np.array([P[(i + 2) % 3, 0] - P[(i + 1) % 3, 0] for i in range(3)])
+    KT = (np.outer(bb, bb) + np.outer(cc, cc)) / (4 * area)
+    MT = area / 12 * (np.ones((3, 3)) + np.eye(3))
+    Mz = H / 6 * np.array([[2, 1], [1, 2]])
+    Kz = np.array([[1, -1], [-1, 1]]) / H
+    expect = np.kron(Mz, KT) + np.kron(Kz, MT)
+    A, flags = oracle.integrate_laplace(1, X[None])
+    assert flags[0] == 0
+    assert np.abs(A[0] - expect).max() < 1e-14 * np.abs(expect).max() * 10
