@@ -8,6 +8,7 @@
 #include "fwd_sc.h"
 #include "fwd_fact.h"
 #include "fwd_ymfma.h"
+#include "fwd_hsf.h"
 
 namespace feint {
 
@@ -82,6 +83,11 @@ int64_t items_of(int64_t ne) { return items_for<KER>(ne); }
 #define FEINT_KF_HEX(P, T, TMK, TN, W)                                        \
     FwdVariant{TMK, TN, 6, W, &launch_direct<KF<P, T, TMK, TN, 0, HexGeo>, W>, \
                &items_of<KF<P, T, TMK, TN, 0, HexGeo>>}
+
+// H: hexahedra by sum factorisation in all three directions (staged = 8): EPW
+// elements per workgroup of NTH threads (tm = EPW, tn = NTH / 64 waves).
+#define FEINT_KH(P, T, NTH, EPW) \
+    FwdVariant{EPW, (NTH) / 64, 8, 1, &launch_hsf<P, T, NTH, EPW>, &items_hsf<EPW>}
 
 #define FEINT_K4U(P, T, TM, TN, W) FEINT_K4U_R(P, T, TM, TN, W, 0)
 #define FEINT_KSC(P, T, TM, TN, W) FEINT_KSC_R(P, T, TM, TN, W, 0)
