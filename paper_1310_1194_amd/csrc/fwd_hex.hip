@@ -5,20 +5,21 @@
 // summed in FP64); the 16x16x32 split kernel (bf16x3, fp16x3); all with the trilinear
 // geometry (at p = 1 first the vector-ALU kernel, "vL" = L lanes per element);
 // in FP64 and FP32 first the sum factorisation in all three directions
-// ("sfWw" = W waves per workgroup, "xE" = E elements per workgroup).
+// ("sfWw" = W waves per workgroup, "xE" = E elements per workgroup, "r" = W_q formed
+// again in each pass of the slots, "o2" = two waves per SIMD asked of the register allocator).
 // Compiled tile shapes per degree (n = 8, 27, 64, 125, 216, 343, 512 shape
 // functions: 1, 2, 4, 8, 14, 22, 32 tiles of 16), the first the default.
 #include "fwd_registry.h"
 
 namespace feint {
 namespace {
-const FwdVariant d1[] = {FEINT_KH(1, double, 64, 8), FEINT_KV_G(1, double, 8, 2, HexGeo), FEINT_K4U_HEX(1, double, 1, 1, 2),
+const FwdVariant d1[] = {FEINT_KH(1, double, 64, 8, 1), FEINT_KV_G(1, double, 8, 2, HexGeo), FEINT_K4U_HEX(1, double, 1, 1, 2),
     FEINT_KF_HEX(1, double, 2, 2, 2)};
-const FwdVariant d2[] = {FEINT_KH(2, double, 64, 2), FEINT_KH(2, double, 128, 4), FEINT_KF_HEX(2, double, 3, 3, 2),
+const FwdVariant d2[] = {FEINT_KH(2, double, 64, 2, 1), FEINT_KH(2, double, 128, 4, 1), FEINT_KF_HEX(2, double, 3, 3, 2),
     FEINT_KV_G(2, double, 32, 2, HexGeo),
     FEINT_K4U_HEX(2, double, 2, 2, 2),
     FEINT_K4U_HEX(2, double, 2, 1, 2)};
-const FwdVariant d3[] = {FEINT_KH(3, double, 64, 1), FEINT_KH(3, double, 128, 2),
+const FwdVariant d3[] = {FEINT_KH(3, double, 64, 1, 1), FEINT_KH(3, double, 128, 2, 1),
     FEINT_KF_HEX(3, double, 4, 2, 2),
     FEINT_KF_HEX(3, double, 4, 1, 2),
     FEINT_KF_HEX(3, double, 4, 2, 1),
@@ -26,58 +27,58 @@ const FwdVariant d3[] = {FEINT_KH(3, double, 64, 1), FEINT_KH(3, double, 128, 2)
     FEINT_K4U_HEX(3, double, 4, 1, 2),
     FEINT_K4U_HEX(3, double, 4, 2, 1),
     FEINT_K4U_HEX(3, double, 2, 2, 2)};
-const FwdVariant d4[] = {FEINT_KH(4, double, 128, 1), FEINT_KH(4, double, 256, 2),
+const FwdVariant d4[] = {FEINT_KH(4, double, 256, 2, 1), FEINT_KH(4, double, 128, 1, 1),
     FEINT_KF_HEX(4, double, 5, 3, 1),
     FEINT_KF_HEX(4, double, 5, 2, 1),
     FEINT_KF_HEX(4, double, 5, 1, 1),
     FEINT_K4U_HEX(4, double, 8, 1, 2),
     FEINT_K4U_HEX(4, double, 8, 2, 1)};
-const FwdVariant d5[] = {FEINT_KH(5, double, 256, 1),
+const FwdVariant d5[] = {FEINT_KH(5, double, 256, 1, 1), FEINT_KH(5, double, 256, 1, 2),
     FEINT_KF_HEX(5, double, 3, 2, 1),
     FEINT_KF_HEX(5, double, 2, 2, 1),
     FEINT_K4U_HEX(5, double, 7, 2, 1),
     FEINT_K4U_HEX(5, double, 14, 1, 1)};
-const FwdVariant d6[] = {FEINT_KH(6, double, 256, 1),
+const FwdVariant d6[] = {FEINT_KH(6, double, 256, 2, 1), FEINT_KH(6, double, 256, 1, 1),
     FEINT_KF_HEX(6, double, 4, 1, 1),
     FEINT_KF_HEX(6, double, 3, 2, 1),
     FEINT_KF_HEX(6, double, 2, 2, 1),
     FEINT_K4U_HEX(6, double, 8, 2, 1),
     FEINT_K4U_HEX(6, double, 11, 1, 1),
     FEINT_K4U_HEX(6, double, 6, 2, 1)};
-const FwdVariant d7[] = {FEINT_KH(7, double, 256, 1),
+const FwdVariant d7[] = {FEINT_KH(7, double, 256, 1, 1),
     FEINT_KF_HEX(7, double, 4, 1, 1),
     FEINT_KF_HEX(7, double, 2, 1, 1),
     FEINT_KF_HEX(7, double, 1, 2, 1),
     FEINT_K4U_HEX(7, double, 8, 1, 1),
     FEINT_K4U_HEX(7, double, 4, 2, 1)};
-const FwdVariant f1[] = {FEINT_KH(1, float, 64, 8), FEINT_KV_G(1, float, 8, 2, HexGeo), FEINT_K4U_HEX(1, float, 1, 1, 2),
+const FwdVariant f1[] = {FEINT_KH(1, float, 64, 8, 1), FEINT_KV_G(1, float, 8, 2, HexGeo), FEINT_K4U_HEX(1, float, 1, 1, 2),
     FEINT_KF_HEX(1, float, 2, 2, 2)};
-const FwdVariant f2[] = {FEINT_KH(2, float, 64, 2), FEINT_KH(2, float, 128, 4), FEINT_K4U_HEX(2, float, 2, 2, 2),
+const FwdVariant f2[] = {FEINT_KH(2, float, 64, 2, 1), FEINT_KH(2, float, 128, 4, 1), FEINT_K4U_HEX(2, float, 2, 2, 2),
     FEINT_KF_HEX(2, float, 3, 3, 2),
     FEINT_KV_G(2, float, 32, 2, HexGeo)};
-const FwdVariant f3[] = {FEINT_KH(3, float, 64, 1), FEINT_KH(3, float, 128, 2),
+const FwdVariant f3[] = {FEINT_KH(3, float, 64, 1, 1), FEINT_KH(3, float, 128, 2, 1),
     FEINT_KF_HEX(3, float, 4, 4, 2),
     FEINT_KF_HEX(3, float, 4, 4, 1),
     FEINT_K4U_HEX(3, float, 2, 4, 1),
     FEINT_K4U_HEX(3, float, 4, 4, 1),
     FEINT_K4U_HEX(3, float, 4, 2, 1)};
-const FwdVariant f4[] = {FEINT_KH(4, float, 128, 1), FEINT_KH(4, float, 256, 2),
+const FwdVariant f4[] = {FEINT_KH(4, float, 128, 1, 1), FEINT_KH(4, float, 256, 2, 1),
     FEINT_KF_HEX(4, float, 5, 5, 1),
     FEINT_KF_HEX(4, float, 5, 3, 1),
     FEINT_KF_HEX(4, float, 5, 2, 1),
     FEINT_K4U_HEX(4, float, 8, 4, 1),
     FEINT_K4U_HEX(4, float, 8, 2, 1)};
-const FwdVariant f5[] = {FEINT_KH(5, float, 256, 1),
+const FwdVariant f5[] = {FEINT_KH(5, float, 256, 1, 1),
     FEINT_KF_HEX(5, float, 6, 3, 1),
     FEINT_KF_HEX(5, float, 6, 2, 1),
     FEINT_K4U_HEX(5, float, 14, 2, 1),
     FEINT_K4U_HEX(5, float, 7, 4, 1)};
-const FwdVariant f6[] = {FEINT_KH(6, float, 384, 1), FEINT_KH(6, float, 256, 1),
+const FwdVariant f6[] = {FEINT_KH(6, float, 256, 2, 1), FEINT_KH(6, float, 256, 1, 1), FEINT_KHR(6, float, 256, 1, 2),
     FEINT_KF_HEX(6, float, 7, 2, 1),
     FEINT_KF_HEX(6, float, 4, 2, 1),
     FEINT_K4U_HEX(6, float, 8, 4, 1),
     FEINT_K4U_HEX(6, float, 6, 4, 1)};
-const FwdVariant f7[] = {FEINT_KH(7, float, 256, 1),
+const FwdVariant f7[] = {FEINT_KHR(7, float, 256, 1, 2), FEINT_KH(7, float, 256, 1, 1),
     FEINT_KF_HEX(7, float, 8, 1, 1),
     FEINT_KF_HEX(7, float, 4, 1, 1),
     FEINT_KF_HEX(7, float, 2, 2, 1),

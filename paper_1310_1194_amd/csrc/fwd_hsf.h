@@ -31,24 +31,81 @@
 // workgroup's lanes at once run in further passes over the same W_q.
 #pragma once
 #include "fwd_kernels.h"
+#include "hex_factors.h"
+#include <type_traits>
 
 namespace feint {
 
-template <int P, typename T, int NTH, int EPW>
+template <int I>
+using ic = std::integral_constant<int, I>;
+
+// for (i = B; i < E; ++i) f(i) with i a compile-time constant
+template <int B, int E, class Fn>
+__device__ __forceinline__ void static_for(Fn &&f) {
+    if constexpr (B < E) {
+        f(ic<B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// A table value as an FP32 instruction literal.
+template <uint64_t BITS>
+__device__ __forceinline__ float kval() {
+    return (float)__builtin_bit_cast(double, BITS);
+}
+#define FEINT_HL(K, M) kval<__builtin_bit_cast(uint64_t, hexc::Fac<P>::v.L[K][M])>()
+#define FEINT_HD(K, M) kval<__builtin_bit_cast(uint64_t, hexc::Fac<P>::v.D[K][M])>()
+
+// The same uniform pointer, opaque to the optimiser: FP64 table values (which
+// cannot be literals) read through it are loaded where they are used instead of
+// being hoisted out of the loops, where at p >= 5 they would outnumber the
+// scalar registers.
+template <class PT>
+__device__ __forceinline__ PT fresh(PT p) {
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+template <int P, typename T, int NTH, int EPW, bool RECOMP = false>
 struct KH {
     static constexpr int n = P + 1, N2 = n * n, N3 = N2 * n;
-    static constexpr int BS = (N2 % 2) ? N2 : N2 + 1;        // exchange row stride: odd, distinct banks
+    // LDS strides of the exchange, in elements of T, against one row of the banks
+    // (M elements = 256 bytes).  A slot writes N2 consecutive elements (lane (q3, b1))
+    // and reads rows b2 = 0..n-1 at stride BS (lane (b2, b1)): BS >= N2 is the first
+    // stride whose n row segments of n elements share a bank least often, and a slot
+    // starts N2 banks after the previous one, so the writes of a wave fill consecutive
+    // banks.
+    static constexpr int M = 256 / (int)sizeof(T);
+    __host__ __device__ static constexpr int bank_mult(int bs) {
+        int cnt[256] = {}, mx = 0;
+        for (int rh = 0; rh < n; ++rh)
+            for (int rl = 0; rl < n; ++rl) {
+                const int c = ++cnt[(rh * bs + rl) % M];
+                mx = c > mx ? c : mx;
+            }
+        return mx;
+    }
+    __host__ __device__ static constexpr int row_stride() {
+        int best = N2, bm = bank_mult(N2);
+        for (int bs = N2 + 1; bs < N2 + M; ++bs)
+            if (bank_mult(bs) < bm) { bm = bank_mult(bs); best = bs; }
+        return best;
+    }
+    static constexpr int BS = row_stride();
+    static constexpr int SS = 4 * n * BS + (((N2 - 4 * n * BS) % M) + M) % M;
     static constexpr int SPP = NTH / N2;                       // (element, a1) slots per pass
     static constexpr int SLOTS = EPW * n;
     static constexpr int PASSES = (SLOTS + SPP - 1) / SPP;
     static constexpr int NWC = 13;                             // nonzero entries of W_q
     static_assert(SPP >= 1, "a slot needs (p+1)^2 lanes");
+    // RECOMP: with several passes, W_q is formed again at the start of each pass, so
+    // that the exchange can share its space (half the LDS: two workgroups per CU)
+    static constexpr bool ALIAS = PASSES == 1 || RECOMP;
     static constexpr size_t W_BYTES = (size_t)EPW * NWC * N3 * sizeof(T);
     static constexpr size_t S_BYTES = (size_t)EPW * 2 * N3 * sizeof(double);
-    static constexpr size_t X_BYTES = (size_t)SPP * 4 * n * BS * sizeof(T);
-    // one pass: the exchange reuses the W_q and load-vector space once those are read
+    static constexpr size_t X_BYTES = (size_t)SPP * SS * sizeof(T);
     static constexpr size_t LDS_BYTES =
-        PASSES == 1 ? (W_BYTES + S_BYTES > X_BYTES ? W_BYTES + S_BYTES : X_BYTES) : W_BYTES + S_BYTES + X_BYTES;
+        ALIAS ? (W_BYTES + S_BYTES > X_BYTES ? W_BYTES + S_BYTES : X_BYTES) : W_BYTES + S_BYTES + X_BYTES;
     static_assert(LDS_BYTES <= 160 * 1024, "LDS budget of one workgroup");
 
     // W_q entries kept (row-major index into W[16]): the first column below the
@@ -61,41 +118,48 @@ struct KH {
         T *Wl = (T *)smem;                                        // [EPW][13][q1][q2][q3]
         double *S0 = (double *)(smem + W_BYTES);                  // [EPW][N3]
         double *S1 = S0 + EPW * N3;
-        T *Xl = (T *)(PASSES == 1 ? smem : smem + W_BYTES + S_BYTES);   // [SPP][4][n][BS]
+        T *Xl = (T *)(ALIAS ? smem : smem + W_BYTES + S_BYTES);    // [SPP][SS]: [4][n][BS] per slot
         const int tid = threadIdx.x;
         const int64_t e0 = (int64_t)blockIdx.x * EPW;
         const T *lam = sizeof(T) == 8 ? (const T *)(const void *)prm.lam : (const T *)(const void *)prm.lam32;
         const T *Lt = lam, *Dt = lam + 3 * N2;                    // l_k(g_m), d_k(g_m) at [k][m]
-        typedef const __attribute__((address_space(4))) T CT;     // wave-uniform reads: scalar loads
+        // the factors the later passes index with wave-uniform values: FP32 literals,
+        // FP64 scalar loads
+        typedef const __attribute__((address_space(4))) T CT;
         const CT *Lu = (const CT *)Lt, *Du = (const CT *)Dt;
+        constexpr bool LIT = sizeof(T) == 4;
 
         // ---- W_q, w det J f, mapped points and the det J flag, one point per lane
-        for (int pi = tid; pi < EPW * N3; pi += NTH) {
-            const int el = pi / N3, q = pi - el * N3;
-            const int q1 = q % n, q2 = (q / n) % n, q3 = q / N2;
-            const int wq = (q1 * n + q2) * n + q3;
-            const int64_t e = e0 + el;
-            double W[16], sf = 0.0;
-            if (e < prm.ne) {
-                ElemHex E;
-                HexGeo::load(prm, e, E);
-                const double *qp = prm.qw + 4 * q;
-                const double det = HexGeo::block(E, qp, W, sf);
-                if (!(det > 0.0) && prm.status) atomicOr(prm.status, 1u);
-                if (prm.xq) {
-                    double x[3];
-                    HexGeo::map(E, qp, x);
+        // (`first`: the first time, which also writes the per-point outputs)
+        auto form_w = [&](bool first) {
+            for (int pi = tid; pi < EPW * N3; pi += NTH) {
+                const int el = pi / N3, q = pi - el * N3;
+                const int q1 = q % n, q2 = (q / n) % n, q3 = q / N2;
+                const int wq = (q1 * n + q2) * n + q3;
+                const int64_t e = e0 + el;
+                double W[16], sf = 0.0;
+                if (e < prm.ne) {
+                    ElemHex E;
+                    HexGeo::load(prm, e, E);
+                    const double *qp = prm.qw + 4 * q;
+                    const double det = HexGeo::block(E, qp, W, sf);
+                    if (first && !(det > 0.0) && prm.status) atomicOr(prm.status, 1u);
+                    if (first && prm.xq) {
+                        double x[3];
+                        HexGeo::map(E, qp, x);
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) prm.xq[(e * N3 + q) * 3 + d] = x[d];
+                        for (int d = 0; d < 3; ++d) prm.xq[(e * N3 + q) * 3 + d] = x[d];
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) W[k] = 0.0;
                 }
-            } else {
 #pragma unroll
-                for (int k = 0; k < 16; ++k) W[k] = 0.0;
+                for (int k = 0; k < NWC; ++k) Wl[(el * NWC + k) * N3 + wq] = (T)W[widx(k)];
+                if (first) S0[el * N3 + q] = sf;
             }
-#pragma unroll
-            for (int k = 0; k < NWC; ++k) Wl[(el * NWC + k) * N3 + wq] = (T)W[widx(k)];
-            S0[el * N3 + q] = sf;
-        }
+        };
+        form_w(true);
         __syncthreads();
 
         // ---- load vector b[(a3 a2 a1)] = sum_q l_a1 l_a2 l_a3 (w det J f)_q, in FP64
@@ -128,6 +192,10 @@ struct KH {
         const int g = tid / N2, r = tid - g * N2;
         const int rh = r / n, rl = r - rh * n;                    // (q3, b1), then (b2, b1)
         for (int ps = 0; ps < PASSES; ++ps) {
+            if (RECOMP && ps > 0) {                               // the exchange held W_q's space
+                form_w(false);
+                __syncthreads();
+            }
             const int slot = ps * SPP + g;
             const bool active = g < SPP && slot < SLOTS;
             const int el = active ? slot / n : 0, a1 = active ? slot - el * n : 0;
@@ -166,9 +234,9 @@ struct KH {
                     }
                 }
             }
-            if (PASSES == 1) __syncthreads();                     // W_q and b's space become the exchange
+            if (ALIAS) __syncthreads();                           // W_q and b's space become the exchange
 
-            T *xs = Xl + (active ? g : 0) * 4 * n * BS;
+            T *xs = Xl + (active ? g : 0) * SS;
             for (int a2 = 0; a2 < n; ++a2) {
                 // ---- pass 2 (xi2): T2[s3][t3][b2] for this lane's (a1, a2, q3, b1)
                 T t2[4][n];
@@ -176,25 +244,33 @@ struct KH {
                 for (int c = 0; c < 4; ++c)
 #pragma unroll
                     for (int m = 0; m < n; ++m) t2[c][m] = (T)0;
-#pragma unroll
-                for (int q2 = 0; q2 < n; ++q2) {
-                    const T ya = Lu[a2 * n + q2], dya = Du[a2 * n + q2];
+                static_for<0, n>([&](auto q2c) {
+                    constexpr int q2 = decltype(q2c)::value;
+                    const CT *Lq = fresh(Lu), *Dq = fresh(Du);
+                    const T ya = Lq[a2 * n + q2], dya = Dq[a2 * n + q2];
                     T v[2][3];
 #pragma unroll
                     for (int ct = 0; ct < 3; ++ct) {
                         v[0][ct] = fma_t(ya, t1[ct][q2], dya * t1[3 + ct][q2]);
                         v[1][ct] = ya * t1[6 + ct][q2];
                     }
-#pragma unroll
-                    for (int b2 = 0; b2 < n; ++b2) {
-                        const T yb = Lu[b2 * n + q2], dyb = Du[b2 * n + q2];
+                    static_for<0, n>([&](auto b2c) {
+                        constexpr int b2 = decltype(b2c)::value;
+                        T yb, dyb;
+                        if constexpr (LIT) {
+                            yb = FEINT_HL(b2, q2);
+                            dyb = FEINT_HD(b2, q2);
+                        } else {
+                            yb = Lq[b2 * n + q2];
+                            dyb = Dq[b2 * n + q2];
+                        }
 #pragma unroll
                         for (int s = 0; s < 2; ++s) {
                             t2[2 * s][b2] = fma_t(yb, v[s][0], fma_t(dyb, v[s][1], t2[2 * s][b2]));
                             t2[2 * s + 1][b2] = fma_t(yb, v[s][2], t2[2 * s + 1][b2]);
                         }
-                    }
-                }
+                    });
+                });
                 if (active) {
 #pragma unroll
                     for (int c = 0; c < 4; ++c)
@@ -213,41 +289,56 @@ struct KH {
                 __syncthreads();
                 if (store) {
                     T *row0 = (T *)prm.A + offA_of(prm, e, N3) + (size_t)(a2 * n + a1) * N3 + rh * n + rl;
-#pragma unroll
-                    for (int a3 = 0; a3 < n; ++a3) {
+                    static_for<0, n>([&](auto a3c) {
+                        constexpr int a3 = decltype(a3c)::value;
                         T u0[n], u1[n];
-#pragma unroll
-                        for (int m = 0; m < n; ++m) {
-                            const T za = Lu[a3 * n + m], dza = Du[a3 * n + m];
+                        const CT *La = fresh(Lu), *Da = fresh(Du);
+                        static_for<0, n>([&](auto mc) {
+                            constexpr int m = decltype(mc)::value;
+                            T za, dza;
+                            if constexpr (LIT) {
+                                za = FEINT_HL(a3, m);
+                                dza = FEINT_HD(a3, m);
+                            } else {
+                                za = La[a3 * n + m];
+                                dza = Da[a3 * n + m];
+                            }
                             u0[m] = fma_t(za, t3[0][m], dza * t3[2][m]);
                             u1[m] = fma_t(za, t3[1][m], dza * t3[3][m]);
-                        }
+                        });
                         T *row = row0 + (size_t)a3 * N2 * N3;
-#pragma unroll
-                        for (int b3 = 0; b3 < n; ++b3) {
+                        static_for<0, n>([&](auto b3c) {
+                            constexpr int b3 = decltype(b3c)::value;
+                            const CT *Lb = fresh(Lu), *Db = fresh(Du);
                             T s = (T)0;
-#pragma unroll
-                            for (int m = 0; m < n; ++m) s = fma_t(Lu[b3 * n + m], u0[m], fma_t(Du[b3 * n + m], u1[m], s));
+                            static_for<0, n>([&](auto mc) {
+                                constexpr int m = decltype(mc)::value;
+                                if constexpr (LIT)
+                                    s = fma_t(FEINT_HL(b3, m), u0[m], fma_t(FEINT_HD(b3, m), u1[m], s));
+                                else
+                                    s = fma_t(Lb[b3 * n + m], u0[m], fma_t(Db[b3 * n + m], u1[m], s));
+                            });
                             row[b3 * N2] = s;
-                        }
-                    }
+                        });
+                    });
                 }
             }
         }
     }
 };
 
-template <class KER, int NTH>
-__global__ void __launch_bounds__(NTH) fwd_hsf(FwdParams prm) {
+template <class KER, int NTH, int MINW>
+__global__ void __launch_bounds__(NTH, MINW) fwd_hsf(FwdParams prm) {
     __shared__ __attribute__((aligned(16))) unsigned char smem[KER::LDS_BYTES];
     KER::run(prm, smem);
 }
 
-template <int P, typename T, int NTH, int EPW>
+template <int P, typename T, int NTH, int EPW, bool RECOMP, int MINW>
 void launch_hsf(const FwdParams &prm, hipStream_t s) {
     const int64_t blocks = (prm.ne + EPW - 1) / EPW;
     if (blocks > 0)
-        hipLaunchKernelGGL((fwd_hsf<KH<P, T, NTH, EPW>, NTH>), dim3((unsigned)blocks), dim3(NTH), 0, s, prm);
+        hipLaunchKernelGGL((fwd_hsf<KH<P, T, NTH, EPW, RECOMP>, NTH, MINW>), dim3((unsigned)blocks), dim3(NTH), 0, s,
+                           prm);
 }
 
 // four work items per workgroup in the launcher's count (its grid-size check)

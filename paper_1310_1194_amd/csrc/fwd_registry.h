@@ -85,9 +85,13 @@ int64_t items_of(int64_t ne) { return items_for<KER>(ne); }
                &items_of<KF<P, T, TMK, TN, 0, HexGeo>>}
 
 // H: hexahedra by sum factorisation in all three directions (staged = 8): EPW
-// elements per workgroup of NTH threads (tm = EPW, tn = NTH / 64 waves).
-#define FEINT_KH(P, T, NTH, EPW) \
-    FwdVariant{EPW, (NTH) / 64, 8, 1, &launch_hsf<P, T, NTH, EPW>, &items_hsf<EPW>}
+// elements per workgroup of NTH threads (tm = EPW, tn = NTH / 64 waves), W waves
+// per SIMD asked of the register allocator; KHR forms W_q again in every pass of
+// the slots (staged = 9).
+#define FEINT_KH(P, T, NTH, EPW, W) \
+    FwdVariant{EPW, (NTH) / 64, 8, W, &launch_hsf<P, T, NTH, EPW, false, W>, &items_hsf<EPW>}
+#define FEINT_KHR(P, T, NTH, EPW, W) \
+    FwdVariant{EPW, (NTH) / 64, 9, W, &launch_hsf<P, T, NTH, EPW, true, W>, &items_hsf<EPW>}
 
 #define FEINT_K4U(P, T, TM, TN, W) FEINT_K4U_R(P, T, TM, TN, W, 0)
 #define FEINT_KSC(P, T, TM, TN, W) FEINT_KSC_R(P, T, TM, TN, W, 0)

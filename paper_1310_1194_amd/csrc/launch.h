@@ -41,7 +41,9 @@ struct FwdVariant {
     int staged;          // 1: the table is staged through LDS per workgroup (2: A operands only),
                          // 3: vector-ALU kernel, 4: software-pipelined split kernel,
                          // 5: shape functions computed at each point (no B table),
-                         // 6: contraction per triangle point (tensor factors of B)
+                         // 6: contraction per triangle point (tensor factors of B),
+                         // 7: split kernel with Y formed on the matrix cores,
+                         // 8: hexahedra by sum factorisation (9: W_q formed in each pass)
     int minw;            // waves per SIMD the register allocation allows
     void (*launch)(const FwdParams &, hipStream_t);
     int64_t (*items)(int64_t ne);   // work items (waves) of a launch over ne elements
