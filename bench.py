@@ -12,13 +12,14 @@ stated in the same line.  The default run (mode "suite") adds, as keys of
 `configs` in the same line, every other configured workload in its own launch
 configuration: p = 1 at 4096 and 524288 elements, the mixed-degree batch
 replayed from a HIP graph, the p = 3 adjoint, the p = 7 forward and
-adjoint, and the paper's own term (Laplace) on its quadrature at its batch
-sizes for p = 1..7, each with its roofline, its error against the oracle and
-its CPU baseline.
+adjoint, hexahedra at p = 4..7 (sum factorisation in three directions beside
+the contraction along xi3 only), and the paper's own term (Laplace) on its
+quadrature at its batch sizes for p = 1..7, each with its roofline, its error
+against the oracle and its CPU baseline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--copy-cal]
                     [--mode suite|forward|fields|hex|tet|adjoint|mixed|assemble|laplace]
-                    [--workload NAME] [--forms LIST]
+                    [--workload NAME] [--forms LIST] [--hex-ps LIST]
 """
 from __future__ import annotations
 
@@ -167,6 +168,7 @@ def main():
     ap.add_argument("--mode", default="suite",
                     choices=["suite", "forward", "fields", "hex", "tet", "adjoint", "mixed", "assemble", "laplace"])
     ap.add_argument("--workload", default=None)
+    ap.add_argument("--hex-ps", default=None, help="--mode hex: degrees (default 4,5,6,7)")
     ap.add_argument("--rule", default="collapsed", choices=["collapsed", "symmetric"],
                     help="quadrature rule of the forward, fields and adjoint modes")
     ap.add_argument("--sc", action="store_true",
@@ -196,6 +198,8 @@ def main():
         line = bench_assemble(args)
     elif args.mode == "laplace":
         line = bench_laplace(args)
+    elif args.mode == "hex":
+        line = bench_hex(args)
     else:
         line = bench_forward(args, fields=args.mode == "fields",
                              kind=args.mode if args.mode in ("hex", "tet") else None)
@@ -471,11 +475,129 @@ def bench_suite(args):
     cfg["adj_p7_16384"] = summarise(bench_adjoint(sub(workload="p7_16384", forms="fp32,fp64", steps=steps,
                                                       warmup=warm, cpu_budget=budget)))
     torch.cuda.empty_cache()
+    stage("hex_p4_p7")
+    cfg["hex_p4_p7"] = summarise(bench_hex(sub(workload=None, forms="fp64,fp32", steps=steps, warmup=warm)))
+    torch.cuda.empty_cache()
     stage("laplace_paper_sweep")
     cfg["laplace_paper_sweep"] = summarise(bench_laplace(sub(workload=None, forms="fp32", steps=steps,
                                                              warmup=warm)))
     line["configs"] = cfg
     return line
+
+
+HEX_WORKLOADS = {4: "hex_p4_65536", 5: "hex_p5_16384", 6: "hex_p6_8192", 7: "hex_p7_2048"}
+VEC_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+
+
+def bench_hex(args):
+    """Hexahedra at p = 4..7 (hex_p4_65536, hex_p5_16384, hex_p6_8192,
+    hex_p7_2048; element matrices of 4.3 to 8.2 GB in FP64), FP64 and FP32: the
+    sum factorisation in all three directions next to the contraction
+    factorised along xi3 only, each in its fastest compiled variant.  Per
+    kernel: mean launch time (HIP events on the launch stream), elements/s, the
+    flops of its own algorithm per second, and its roofline -- the larger of
+    (own flops at the peak of the unit it runs on: FP64/FP32 vector for the sum
+    factorisation, the matrix cores for the xi3 contraction) and (input bytes +
+    element matrix and load vector written, at the HBM peak), as a fraction of
+    the measured time; errors against the oracle on a spread sample."""
+    import torch
+    import paper_1310_1194_amd as F
+    from paper_1310_1194_amd import costmodel
+    dev = torch.device("cuda:0")
+    ps = [int(x) for x in (args.hex_ps or "4,5,6,7").split(",")]
+    forms = [f for f in (args.forms or "fp64,fp32").split(",") if f]
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    in_bytes = 8 * (24 + 9 + 3 + 1 + 1)
+    out, head = {}, None
+    for p in ps:
+        name = HEX_WORKLOADS[p]
+        batch = meshgen.workload(name)
+        ne, n = batch.ne, (p + 1) ** 3
+        X = tuple(t(a) for a in (batch.coords, batch.D, batch.beta, batch.c, batch.f))
+        nsamp = {4: 256, 5: 128, 6: 64, 7: 64}[p]
+        idx = np.unique(np.linspace(0, ne - 1, nsamp).astype(np.int64))
+        ref = None
+        if not args.no_cpu:
+            import oracle
+            sub = batch.subset(idx)
+            Ar, br, _ = oracle.integrate_hex(p, sub.coords, sub.D, sub.beta, sub.c, sub.f)
+            ref = (Ar, br)
+        per_p = {"workload": name, "ne": ne, "nshp": n, "nq": n}
+        for form in forms:
+            dt = torch.float64 if form == "fp64" else torch.float32
+            A = torch.empty((ne, n, n), dtype=dt, device=dev)
+            b = torch.empty((ne, n), dtype=dt, device=dev)
+            cnt = F.elem_tile_count("hex", p, form)
+            descs = [F.elem_tile_describe("hex", p, form, k) for k in range(cnt)]
+            kinds = {"sumfact": [k for k in range(cnt) if costmodel.is_sf_tile(descs[k])],
+                     "xi3": [k for k in range(cnt) if costmodel.is_kf_tile(descs[k])]}
+
+            def timed(tile, steps, warm):
+                F.elem_tile_set("hex", p, form, tile)
+                for _ in range(warm):
+                    F.integrate_elem_raw("hex", *X, p, form, A=A, b=b)
+                torch.cuda.synchronize()
+                stream = torch.cuda.current_stream()
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+                ev[0].record(stream)
+                for k in range(steps):
+                    F.integrate_elem_raw("hex", *X, p, form, A=A, b=b)
+                    ev[k + 1].record(stream)
+                torch.cuda.synchronize()
+                return [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+
+            res = {}
+            for kname, tiles in kinds.items():
+                if not tiles:
+                    continue
+                best = min(tiles, key=lambda k: float(np.min(timed(k, 2, 1))))
+                per = timed(best, args.steps, args.warmup)
+                ms = float(np.mean(per))
+                es = 8 if form == "fp64" else 4
+                nbytes = ne * (in_bytes + (n * n + n) * es)
+                if kname == "sumfact":
+                    flops, peak, unit = costmodel.f_hex_sumfact(p) * ne, VEC_PEAK_TFLOPS[form], "alu"
+                else:
+                    flops, peak, unit = costmodel.f_factored(n, p + 1, n) * ne, PEAK_TFLOPS[form], "mfma"
+                t_alu, t_hbm = flops / (peak * 1e12), nbytes / (HBM_PEAK_GBS * 1e9)
+                bound = "hbm" if t_hbm >= t_alu else unit
+                r = {"tile": descs[best], "kernel_ms_mean": ms, "kernel_ms_min": float(np.min(per)),
+                     "elements_per_s": ne / (ms * 1e-3), "alg_flops_per_element": flops / ne,
+                     "gflops_alg": flops / (ms * 1e-3) / 1e9,
+                     "fdom_equiv_gflops": 8.0 * n * n * n * ne / (ms * 1e-3) / 1e9,
+                     "hbm_gbs_algorithmic": nbytes / (ms * 1e-3) / 1e9,
+                     "roofline": {"bound": bound, "peak": HBM_PEAK_GBS if bound == "hbm" else peak,
+                                  "unit": "GB/s" if bound == "hbm" else "TFLOP/s",
+                                  "achieved": (nbytes / (ms * 1e-3) / 1e9 if bound == "hbm"
+                                               else flops / (ms * 1e-3) / 1e12),
+                                  "frac": max(t_alu, t_hbm) / (ms * 1e-3),
+                                  "alu_frac": t_alu / (ms * 1e-3), "hbm_frac": t_hbm / (ms * 1e-3)}}
+                if ref is not None:
+                    ti = torch.from_numpy(idx).to(dev)
+                    gA, mA = rel_err(A[ti].cpu().numpy(), ref[0])
+                    gb, _ = rel_err(b[ti].cpu().numpy(), ref[1])
+                    r.update(rel_err_A=gA, rel_err_A_max_elem=mA, rel_err_b=gb, err_sample=len(idx))
+                res[kname] = {k: (float(f"{v:.5g}") if isinstance(v, float) else v) for k, v in r.items()}
+                print(f"[bench] hex p={p} {form} {kname} {descs[best]}: {ms:.3f} ms", file=sys.stderr, flush=True)
+            F.elem_tile_set("hex", p, form, 0)
+            if "sumfact" in res and "xi3" in res:
+                res["speedup_vs_xi3"] = round(res["xi3"]["kernel_ms_mean"] / res["sumfact"]["kernel_ms_mean"], 3)
+            per_p[form] = res
+            del A, b
+            torch.cuda.empty_cache()
+        out[f"p{p}"] = per_p
+        if head is None and forms[0] in per_p and "sumfact" in per_p[forms[0]]:
+            head = (p, forms[0], per_p[forms[0]]["sumfact"], name)
+    hp, hform, h, hname = head
+    return {
+        "metric": "elements/s, hexahedra p = 4..7: sum factorisation in three directions vs along xi3 only",
+        "value": h["elements_per_s"], "unit": "elements/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": h["kernel_ms_mean"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": DTYPE_DESC[hform],
+        "data": "synthetic (seeded perturbed hexahedral meshes and coefficients)",
+        "config": {"workload": hname, "p": hp, "form": hform, "element": "hexahedron",
+                   "parallelism": "single GPU"},
+        "roofline": h["roofline"], "degrees": out, "device": torch.cuda.get_device_name(0)}
 
 
 def bench_laplace(args):

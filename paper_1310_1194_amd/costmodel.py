@@ -105,6 +105,26 @@ def f_adjoint_factored(p: int, rule: str = "collapsed") -> int:
     return 8 * n * n * nij + 8 * nk * nk * nij * n + 36 * q * n
 
 
+def f_hex_sumfact(p: int) -> int:
+    """Flops per element of the hexahedral contraction factorised in all three
+    directions (n = p+1 points and 1D factors per direction; an FMA counts 2):
+    the xi1 pass, per (a1, q3, b1) and q1, 4 products of the a1 and b1 factors
+    and 13 FMAs per q2 (the nonzero entries of W_q): n^4 (4 + 26 n); the xi2
+    pass, per (a1, q3, b1), a2 and q2, 6 products and 3 FMAs folding the a2
+    factors and 6 n FMAs with the b2 factors: n^5 (12 + 12 n); the xi3 pass, per
+    (a1, a2, b2, b1) and a3, 2 n products and 2 n FMAs folding the a3 factors and
+    2 n^2 FMAs with the b3 factors: n^6 (6 + 4 n); the load vector, three
+    passes of n FMAs per output: 6 n^4.  Total 10 n^4 + 38 n^5 + 18 n^6 + 4 n^7."""
+    n = p + 1
+    return 10 * n ** 4 + 38 * n ** 5 + 18 * n ** 6 + 4 * n ** 7
+
+
+def is_sf_tile(desc: str) -> bool:
+    """Tile descriptions "sfWw..." name the hexahedral sum factorisation."""
+    import re
+    return re.fullmatch(r"sf\d+w(x\d+)?r?(o2)?", desc) is not None
+
+
 def is_kf_tile(desc: str) -> bool:
     """Tile descriptions "KxTNf" (optionally "o2") name the triangle-point contraction."""
     import re

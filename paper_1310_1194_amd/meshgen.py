@@ -284,6 +284,10 @@ WORKLOADS = {
     "p1_524288":    dict(nx=64, ny=64, nz=64, amp=0.2, seed=0, p=1),
     # hexahedra (one per cell) on the vertex grid of the p = 4 prism workload
     "hex_p4_65536": dict(nx=64, ny=64, nz=16, amp=0.2, seed=1, p=4, element="hexahedron"),
+    # hexahedra at p = 5..7 (element matrices of 6.1, 7.7 and 4.3 GB in FP64)
+    "hex_p5_16384": dict(nx=32, ny=32, nz=16, amp=0.2, seed=1, p=5, element="hexahedron"),
+    "hex_p6_8192":  dict(nx=32, ny=16, nz=16, amp=0.2, seed=1, p=6, element="hexahedron"),
+    "hex_p7_2048":  dict(nx=16, ny=16, nz=8,  amp=0.2, seed=1, p=7, element="hexahedron"),
     # tetrahedra (six per cell) on the vertex grid of the p = 4 prism workload
     "tet_p4_393216": dict(nx=64, ny=64, nz=16, amp=0.2, seed=1, p=4, element="tetrahedron"),
     "tet_p1_393216": dict(nx=64, ny=64, nz=16, amp=0.2, seed=1, p=1, element="tetrahedron"),

@@ -139,3 +139,22 @@ def test_laplace_kernel_work_is_table2(p):
     total = cm.laplace_paper_ops(p, points) / 1e3
     printed_total = g["table2_shape_total"][p - 1] + g["table2_jacobian_total"][p - 1] + g["table2_matrix_total"][p - 1]
     assert abs(total - printed_total) <= 1.0 + 0.001 * printed_total
+
+
+def test_hex_sumfact_flops_by_pass():
+    """The sum factorisation's flop count, enumerated pass by pass as the
+    kernel runs them (per lane item and loop, an FMA as 2), equals the closed
+    form; and it is O(n^7) against the xi3-only contraction's O(n^8) and the
+    8 n^9 of the point-by-point product."""
+    from paper_1310_1194_amd import costmodel
+    for p in range(1, 8):
+        n = p + 1
+        items = n ** 3                                   # (a1, q3, b1), then (a1, b2, b1) per a2
+        pass1 = items * n * (4 + 2 * 13 * n)             # per q1: 4 products, 13 FMAs per q2
+        pass2 = items * n * n * (2 * 3 + 6 + 2 * 6 * n)  # per (a2, q2): 3 FMAs + 6 products, 6 FMAs per b2
+        pass3 = items * n * n * (2 * 2 * n + 2 * n + 2 * 2 * n * n)   # per (a2, a3): 2n FMAs + 2n products, 2n^2 FMAs
+        load = 3 * n ** 3 * n * 2                        # three passes of n FMAs per output
+        assert pass1 + pass2 + pass3 + load == costmodel.f_hex_sumfact(p), p
+        assert costmodel.f_hex_sumfact(p) < costmodel.f_factored(n ** 3, n, n ** 3) < 8 * n ** 9
+    # the leading term 4 n^7 is already more than half of the work at p = 7
+    assert 4 * 8 ** 7 / costmodel.f_hex_sumfact(7) > 0.5
