@@ -28,6 +28,13 @@ def rel_errors(got, ref):
     return float(glob), float(per.max())
 
 
+def elem_errors(got, ref):
+    """Per-element relative Frobenius errors."""
+    got = np.asarray(got, dtype=np.float64).reshape(ref.shape[0], -1)
+    ref = ref.reshape(ref.shape[0], -1)
+    return np.linalg.norm(got - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-300)
+
+
 def grad_errors(got, ref, floor=1e-3):
     """Errors of one gradient array, [ne, ...]: (global relative Frobenius
     error, max over elements of ||got_e - ref_e|| / d_e).  d_e is the element's
@@ -55,3 +62,34 @@ def small_batch(p, seed=0, amp=0.2):
     b = meshgen.make_batch(*dims, amp=amp, seed=seed)
     keep = b.ne - 1 if b.ne > 2 else b.ne   # ragged: drop the last element
     return b.subset(np.arange(keep))
+
+
+def det_condition(coords, pts):
+    """Per element, max over the rule's points of |J e1| |J e2| |J e3| / |det J|
+    (Hadamard's ratio, >= 1): how much the rounding of det J, and of
+    J^-1 = cofactors / det J, is amplified at the element's worst point.  Two
+    correct FP64 evaluations of the same element matrix by different
+    formulas for J differ by a few u times this (u = 2^-53).  J is taken from
+    the bilinear prism map x = sum N_a x_a (N_a = lambda_a (1 - zeta)/2,
+    N_(a+3) = lambda_a (1 + zeta)/2, lambda = (1 - xi1 - xi2, xi1, xi2));
+    a CPU test checks it against the oracle's Jacobian."""
+    X = np.asarray(coords, dtype=np.float64)                  # [ne, 6, 3]
+    xi1, xi2, ze = pts[:, 0], pts[:, 1], pts[:, 2]
+    lam = np.stack([1.0 - xi1 - xi2, xi1, xi2], axis=1)       # [nq, 3]
+    dl1 = np.array([-1.0, 1.0, 0.0])
+    dl2 = np.array([-1.0, 0.0, 1.0])
+    lo, hi = (1.0 - ze)[:, None] / 2, (1.0 + ze)[:, None] / 2
+    dN1 = np.concatenate([dl1[None, :] * lo, dl1[None, :] * hi], axis=1)   # [nq, 6]
+    dN2 = np.concatenate([dl2[None, :] * lo, dl2[None, :] * hi], axis=1)
+    dN3 = np.concatenate([-lam / 2, lam / 2], axis=1)
+    cols = [np.einsum("qa,ead->eqd", dN, X) for dN in (dN1, dN2, dN3)]   # [ne, nq, 3] each
+    det = np.einsum("eqd,eqd->eq", cols[0], np.cross(cols[1], cols[2]))
+    had = np.linalg.norm(cols[0], axis=2) * np.linalg.norm(cols[1], axis=2) * np.linalg.norm(cols[2], axis=2)
+    return (had / np.abs(det)).max(axis=1)
+
+
+def fp64_elem_tol(coords, p, floor=1e-12):
+    """Per-element FP64 tolerance: floor, or 16 u times the element's det J
+    condition (measured: a few u times it)."""
+    pts, _ = oracle.prism_rule(p, "collapsed")
+    return np.maximum(floor, 16 * 2.0 ** -53 * det_condition(coords, pts))

@@ -601,3 +601,24 @@ def test_laplace_right_prism_p1_textbook():
     A, flags = oracle.integrate_laplace(1, X[None])
     assert flags[0] == 0
     assert np.abs(A[0] - expect).max() < 1e-14 * np.abs(expect).max() * 10
+
+
+def test_det_condition_helper_matches_oracle_jacobian():
+    """The conditioning estimate the FP64 GPU tolerances use takes J from the
+    prism map; it must agree with the oracle's Jacobian (det and columns) on a
+    distorted mesh, including an element with an inverted corner."""
+    import sys
+    from pathlib import Path
+    sys.path.insert(0, str(Path(__file__).parent))
+    from gpu_util import det_condition
+    from paper_1310_1194_amd import meshgen
+    b = meshgen.make_batch(3, 2, 2, amp=0.3, seed=4)
+    pts, _ = oracle.prism_rule(3, "collapsed")
+    kap = det_condition(b.coords, pts)
+    for e in (0, 5, b.ne - 1):
+        ref = 0.0
+        for q in range(pts.shape[0]):
+            J, det, K, x = oracle.geometry(b.coords[e], pts[q])
+            ref = max(ref, np.prod(np.linalg.norm(J, axis=0)) / abs(det))
+        assert abs(kap[e] - ref) <= 1e-9 * ref
+    assert (kap >= 1.0 - 1e-12).all()
