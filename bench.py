@@ -134,6 +134,32 @@ def rel_err(got, ref):
     return float(np.linalg.norm(got - ref) / np.linalg.norm(ref)), float(per.max())
 
 
+def graph_replay_ms(fn, n):
+    """Mean time per launch of n launches of fn captured in one HIP graph
+    (torch.cuda.CUDAGraph) and replayed, events around each replay."""
+    import torch
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(n):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    reps = 10
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / (reps * n)
+
+
 def timed(fn, steps, warmup, stream=None):
     """Warm up, then time `steps` calls with HIP events on the launch stream
     (bracketed by device synchronisation); returns (mean, min) ms per call and
@@ -298,6 +324,11 @@ def bench_forward(args, fields=False, kind=None, err_idx=None, cpu_budget=None):
                              kernel_ms_min=float(np.min(per)), tile=tile, tune_ms=tile_ms,
                              elements_per_s=ne * args.steps / wall,
                              A_sample=A[sample_idx].cpu().numpy(), b_sample=b[sample_idx].cpu().numpy())
+        if ne <= 8192 and not other_elem and not fields:
+            # a launch this small is bound by its submission: the same launches
+            # replayed from a HIP graph show what the kernel itself takes
+            results[form]["graph_replay_ms_per_launch"] = graph_replay_ms(
+                lambda: integrate(*X, p, form, A=A, b=b, rule=rule), 32)
         print(f"[bench] {form}: {ms:.3f} ms/launch (min {np.min(per):.3f}), tile {tile}", file=sys.stderr, flush=True)
 
     fdom = 8 * n * n * q if other_elem else costmodel.f_dom(p, rule)
