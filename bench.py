@@ -524,7 +524,8 @@ def bench_hex(args):
     """Hexahedra at p = 4..7 (hex_p4_65536, hex_p5_16384, hex_p6_8192,
     hex_p7_2048; element matrices of 4.3 to 8.2 GB in FP64), FP64 and FP32: the
     sum factorisation in all three directions next to the contraction
-    factorised along xi3 only, each in its fastest compiled variant.  Per
+    factorised along xi3 only, each in its fastest compiled variant, and a
+    device fill of the same output buffer (the practical write ceiling).  Per
     kernel: mean launch time (HIP events on the launch stream), elements/s, the
     flops of its own algorithm per second, and its roofline -- the larger of
     (own flops at the peak of the unit it runs on: FP64/FP32 vector for the sum
@@ -577,11 +578,21 @@ def bench_hex(args):
                 torch.cuda.synchronize()
                 return [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
 
-            res = {}
+            # the practical write ceiling: a device fill of the same output buffer
+            A.zero_()
+            torch.cuda.synchronize()
+            f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            f0.record()
+            for _ in range(3):
+                A.zero_()
+            f1.record()
+            torch.cuda.synchronize()
+            fill_gbs = A.numel() * A.element_size() / (f0.elapsed_time(f1) / 3 * 1e-3) / 1e9
+            res = {"fill_gbs": round(fill_gbs, 1)}
             for kname, tiles in kinds.items():
                 if not tiles:
                     continue
-                best = min(tiles, key=lambda k: float(np.min(timed(k, 2, 1))))
+                best = min(tiles, key=lambda k: float(np.min(timed(k, 4, 1))))
                 per = timed(best, args.steps, args.warmup)
                 ms = float(np.mean(per))
                 es = 8 if form == "fp64" else 4
@@ -602,7 +613,8 @@ def bench_hex(args):
                                   "achieved": (nbytes / (ms * 1e-3) / 1e9 if bound == "hbm"
                                                else flops / (ms * 1e-3) / 1e12),
                                   "frac": max(t_alu, t_hbm) / (ms * 1e-3),
-                                  "alu_frac": t_alu / (ms * 1e-3), "hbm_frac": t_hbm / (ms * 1e-3)}}
+                                  "alu_frac": t_alu / (ms * 1e-3), "hbm_frac": t_hbm / (ms * 1e-3),
+                                  "write_frac_of_fill": n * n * es * ne / (ms * 1e-3) / 1e9 / fill_gbs}}
                 if ref is not None:
                     ti = torch.from_numpy(idx).to(dev)
                     gA, mA = rel_err(A[ti].cpu().numpy(), ref[0])

@@ -122,7 +122,7 @@ def f_hex_sumfact(p: int) -> int:
 def is_sf_tile(desc: str) -> bool:
     """Tile descriptions "sfWw..." name the hexahedral sum factorisation."""
     import re
-    return re.fullmatch(r"sf\d+w(x\d+)?r?(o2)?", desc) is not None
+    return re.fullmatch(r"sf\d+w(x\d+)?[rl]?(o\d)?", desc) is not None
 
 
 def is_kf_tile(desc: str) -> bool:

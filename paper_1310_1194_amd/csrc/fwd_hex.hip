@@ -6,7 +6,8 @@
 // geometry (at p = 1 first the vector-ALU kernel, "vL" = L lanes per element);
 // in FP64 and FP32 first the sum factorisation in all three directions
 // ("sfWw" = W waves per workgroup, "xE" = E elements per workgroup, "r" = W_q formed
-// again in each pass of the slots, "o2" = two waves per SIMD asked of the register allocator).
+// again in each pass of the slots, "l" = that and the last pass reading T2 from LDS where
+// it is used, "oK" = K waves per SIMD asked of the register allocator).
 // Compiled tile shapes per degree (n = 8, 27, 64, 125, 216, 343, 512 shape
 // functions: 1, 2, 4, 8, 14, 22, 32 tiles of 16), the first the default.
 #include "fwd_registry.h"
@@ -27,25 +28,25 @@ const FwdVariant d3[] = {FEINT_KH(3, double, 64, 1, 1), FEINT_KH(3, double, 128,
     FEINT_K4U_HEX(3, double, 4, 1, 2),
     FEINT_K4U_HEX(3, double, 4, 2, 1),
     FEINT_K4U_HEX(3, double, 2, 2, 2)};
-const FwdVariant d4[] = {FEINT_KH(4, double, 256, 2, 1), FEINT_KH(4, double, 128, 1, 1),
+const FwdVariant d4[] = {FEINT_KH(4, double, 128, 1, 1), FEINT_KH(4, double, 256, 2, 1), FEINT_KHL(4, double, 128, 1, 3),
     FEINT_KF_HEX(4, double, 5, 3, 1),
     FEINT_KF_HEX(4, double, 5, 2, 1),
     FEINT_KF_HEX(4, double, 5, 1, 1),
     FEINT_K4U_HEX(4, double, 8, 1, 2),
     FEINT_K4U_HEX(4, double, 8, 2, 1)};
-const FwdVariant d5[] = {FEINT_KH(5, double, 256, 1, 1), FEINT_KH(5, double, 256, 1, 2),
+const FwdVariant d5[] = {FEINT_KH(5, double, 256, 1, 1), FEINT_KH(5, double, 256, 1, 2), FEINT_KHL(5, double, 128, 1, 2),
     FEINT_KF_HEX(5, double, 3, 2, 1),
     FEINT_KF_HEX(5, double, 2, 2, 1),
     FEINT_K4U_HEX(5, double, 7, 2, 1),
     FEINT_K4U_HEX(5, double, 14, 1, 1)};
-const FwdVariant d6[] = {FEINT_KH(6, double, 256, 2, 1), FEINT_KH(6, double, 256, 1, 1),
+const FwdVariant d6[] = {FEINT_KHL(6, double, 256, 1, 2), FEINT_KH(6, double, 256, 2, 1), FEINT_KH(6, double, 256, 1, 1),
     FEINT_KF_HEX(6, double, 4, 1, 1),
     FEINT_KF_HEX(6, double, 3, 2, 1),
     FEINT_KF_HEX(6, double, 2, 2, 1),
     FEINT_K4U_HEX(6, double, 8, 2, 1),
     FEINT_K4U_HEX(6, double, 11, 1, 1),
     FEINT_K4U_HEX(6, double, 6, 2, 1)};
-const FwdVariant d7[] = {FEINT_KH(7, double, 256, 1, 1),
+const FwdVariant d7[] = {FEINT_KHL(7, double, 256, 1, 2), FEINT_KH(7, double, 256, 1, 1),
     FEINT_KF_HEX(7, double, 4, 1, 1),
     FEINT_KF_HEX(7, double, 2, 1, 1),
     FEINT_KF_HEX(7, double, 1, 2, 1),
@@ -73,12 +74,12 @@ const FwdVariant f5[] = {FEINT_KH(5, float, 256, 1, 1),
     FEINT_KF_HEX(5, float, 6, 2, 1),
     FEINT_K4U_HEX(5, float, 14, 2, 1),
     FEINT_K4U_HEX(5, float, 7, 4, 1)};
-const FwdVariant f6[] = {FEINT_KH(6, float, 256, 2, 1), FEINT_KH(6, float, 256, 1, 1), FEINT_KHR(6, float, 256, 1, 2),
+const FwdVariant f6[] = {FEINT_KH(6, float, 256, 2, 1), FEINT_KHL(6, float, 256, 1, 3), FEINT_KH(6, float, 256, 1, 1), FEINT_KHR(6, float, 256, 1, 2),
     FEINT_KF_HEX(6, float, 7, 2, 1),
     FEINT_KF_HEX(6, float, 4, 2, 1),
     FEINT_K4U_HEX(6, float, 8, 4, 1),
     FEINT_K4U_HEX(6, float, 6, 4, 1)};
-const FwdVariant f7[] = {FEINT_KHR(7, float, 256, 1, 2), FEINT_KH(7, float, 256, 1, 1),
+const FwdVariant f7[] = {FEINT_KHR(7, float, 256, 1, 2), FEINT_KHL(7, float, 256, 1, 3), FEINT_KH(7, float, 256, 1, 1),
     FEINT_KF_HEX(7, float, 8, 1, 1),
     FEINT_KF_HEX(7, float, 4, 1, 1),
     FEINT_KF_HEX(7, float, 2, 2, 1),

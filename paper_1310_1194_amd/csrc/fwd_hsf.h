@@ -66,7 +66,7 @@ __device__ __forceinline__ PT fresh(PT p) {
     return p;
 }
 
-template <int P, typename T, int NTH, int EPW, bool RECOMP = false>
+template <int P, typename T, int NTH, int EPW, bool RECOMP = false, bool LEAN = false>
 struct KH {
     static constexpr int n = P + 1, N2 = n * n, N3 = N2 * n;
     // LDS strides of the exchange, in elements of T, against one row of the banks
@@ -238,56 +238,107 @@ struct KH {
 
             T *xs = Xl + (active ? g : 0) * SS;
             for (int a2 = 0; a2 < n; ++a2) {
-                // ---- pass 2 (xi2): T2[s3][t3][b2] for this lane's (a1, a2, q3, b1)
-                T t2[4][n];
+                // ---- pass 2 (xi2): T2[s3][t3][b2] for this lane's (a1, a2, q3, b1); LEAN: one s3
+                // half at a time (2n accumulators live instead of 4n)
+                auto pass2 = [&](auto s0c, auto s1c) {
+                    constexpr int S0 = decltype(s0c)::value, S1 = decltype(s1c)::value;
+                    T t2[4][n];
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
+                    for (int c = 2 * S0; c < 2 * S1; ++c)
 #pragma unroll
-                    for (int m = 0; m < n; ++m) t2[c][m] = (T)0;
-                static_for<0, n>([&](auto q2c) {
-                    constexpr int q2 = decltype(q2c)::value;
-                    const CT *Lq = fresh(Lu), *Dq = fresh(Du);
-                    const T ya = Lq[a2 * n + q2], dya = Dq[a2 * n + q2];
-                    T v[2][3];
+                        for (int m = 0; m < n; ++m) t2[c][m] = (T)0;
+                    static_for<0, n>([&](auto q2c) {
+                        constexpr int q2 = decltype(q2c)::value;
+                        const CT *Lq = fresh(Lu), *Dq = fresh(Du);
+                        const T ya = Lq[a2 * n + q2], dya = Dq[a2 * n + q2];
+                        T v[2][3];
 #pragma unroll
-                    for (int ct = 0; ct < 3; ++ct) {
-                        v[0][ct] = fma_t(ya, t1[ct][q2], dya * t1[3 + ct][q2]);
-                        v[1][ct] = ya * t1[6 + ct][q2];
-                    }
-                    static_for<0, n>([&](auto b2c) {
-                        constexpr int b2 = decltype(b2c)::value;
-                        T yb, dyb;
-                        if constexpr (LIT) {
-                            yb = FEINT_HL(b2, q2);
-                            dyb = FEINT_HD(b2, q2);
-                        } else {
-                            yb = Lq[b2 * n + q2];
-                            dyb = Dq[b2 * n + q2];
+                        for (int ct = 0; ct < 3; ++ct) {
+                            if (S0 == 0) v[0][ct] = fma_t(ya, t1[ct][q2], dya * t1[3 + ct][q2]);
+                            if (S1 == 2) v[1][ct] = ya * t1[6 + ct][q2];
                         }
+                        static_for<0, n>([&](auto b2c) {
+                            constexpr int b2 = decltype(b2c)::value;
+                            T yb, dyb;
+                            if constexpr (LIT) {
+                                yb = FEINT_HL(b2, q2);
+                                dyb = FEINT_HD(b2, q2);
+                            } else {
+                                yb = Lq[b2 * n + q2];
+                                dyb = Dq[b2 * n + q2];
+                            }
 #pragma unroll
-                        for (int s = 0; s < 2; ++s) {
-                            t2[2 * s][b2] = fma_t(yb, v[s][0], fma_t(dyb, v[s][1], t2[2 * s][b2]));
-                            t2[2 * s + 1][b2] = fma_t(yb, v[s][2], t2[2 * s + 1][b2]);
-                        }
+                            for (int s = S0; s < S1; ++s) {
+                                t2[2 * s][b2] = fma_t(yb, v[s][0], fma_t(dyb, v[s][1], t2[2 * s][b2]));
+                                t2[2 * s + 1][b2] = fma_t(yb, v[s][2], t2[2 * s + 1][b2]);
+                            }
+                        });
                     });
-                });
-                if (active) {
+                    if (active) {
 #pragma unroll
-                    for (int c = 0; c < 4; ++c)
+                        for (int c = 2 * S0; c < 2 * S1; ++c)
 #pragma unroll
-                        for (int b2 = 0; b2 < n; ++b2) xs[(c * n + b2) * BS + q3 * n + b1] = t2[c][b2];
+                            for (int b2 = 0; b2 < n; ++b2) xs[(c * n + b2) * BS + q3 * n + b1] = t2[c][b2];
+                    }
+                };
+                if constexpr (LEAN) {
+                    pass2(ic<0>{}, ic<1>{});
+                    pass2(ic<1>{}, ic<2>{});
+                } else {
+                    pass2(ic<0>{}, ic<2>{});
                 }
                 __syncthreads();
                 // ---- pass 3 (xi3): this lane now owns (b2, b1) = (rh, rl)
                 T t3[4][n];
-                if (active) {
+                if (!LEAN && active) {
 #pragma unroll
                     for (int c = 0; c < 4; ++c)
 #pragma unroll
                         for (int m = 0; m < n; ++m) t3[c][m] = xs[(c * n + rh) * BS + m * n + rl];
                 }
-                __syncthreads();
-                if (store) {
+                if (!LEAN) __syncthreads();
+                if (LEAN) {
+                    // T2 read from the exchange where it is used, the q3 sum taken point by point
+                    // into n accumulators (instead of 4n T2 values and 2n folded ones in registers)
+                    if (store) {
+                        T *row0 = (T *)prm.A + offA_of(prm, e, N3) + (size_t)(a2 * n + a1) * N3 + rh * n + rl;
+                        const T *xr = xs + rh * BS + rl;
+                        static_for<0, n>([&](auto a3c) {
+                            constexpr int a3 = decltype(a3c)::value;
+                            T acc[n];
+#pragma unroll
+                            for (int k = 0; k < n; ++k) acc[k] = (T)0;
+                            const CT *La = fresh(Lu), *Da = fresh(Du);
+                            static_for<0, n>([&](auto mc) {
+                                constexpr int m = decltype(mc)::value;
+                                T za, dza;
+                                if constexpr (LIT) {
+                                    za = FEINT_HL(a3, m);
+                                    dza = FEINT_HD(a3, m);
+                                } else {
+                                    za = La[a3 * n + m];
+                                    dza = Da[a3 * n + m];
+                                }
+                                const T x0 = xr[(0 * n) * BS + m * n], x1 = xr[(1 * n) * BS + m * n];
+                                const T x2 = xr[(2 * n) * BS + m * n], x3 = xr[(3 * n) * BS + m * n];
+                                const T u0 = fma_t(za, x0, dza * x2), u1 = fma_t(za, x1, dza * x3);
+                                const CT *Lm = fresh((const CT *)&hexc::FacT<P>::v.L[m][0]);
+                                const CT *Dm = fresh((const CT *)&hexc::FacT<P>::v.D[m][0]);
+                                static_for<0, n>([&](auto bc) {
+                                    constexpr int b3 = decltype(bc)::value;
+                                    if constexpr (LIT)
+                                        acc[b3] = fma_t(FEINT_HL(b3, m), u0, fma_t(FEINT_HD(b3, m), u1, acc[b3]));
+                                    else
+                                        acc[b3] = fma_t((T)Lm[b3], u0, fma_t((T)Dm[b3], u1, acc[b3]));
+                                });
+                            });
+                            T *row = row0 + (size_t)a3 * N2 * N3;
+#pragma unroll
+                            for (int b3 = 0; b3 < n; ++b3) row[b3 * N2] = acc[b3];
+                        });
+                    }
+                    __syncthreads();                              // the exchange is written again next
+                } else if (store) {
                     T *row0 = (T *)prm.A + offA_of(prm, e, N3) + (size_t)(a2 * n + a1) * N3 + rh * n + rl;
                     static_for<0, n>([&](auto a3c) {
                         constexpr int a3 = decltype(a3c)::value;
@@ -333,12 +384,12 @@ __global__ void __launch_bounds__(NTH, MINW) fwd_hsf(FwdParams prm) {
     KER::run(prm, smem);
 }
 
-template <int P, typename T, int NTH, int EPW, bool RECOMP, int MINW>
+template <int P, typename T, int NTH, int EPW, bool RECOMP, int MINW, bool LEAN = false>
 void launch_hsf(const FwdParams &prm, hipStream_t s) {
     const int64_t blocks = (prm.ne + EPW - 1) / EPW;
     if (blocks > 0)
-        hipLaunchKernelGGL((fwd_hsf<KH<P, T, NTH, EPW, RECOMP>, NTH, MINW>), dim3((unsigned)blocks), dim3(NTH), 0, s,
-                           prm);
+        hipLaunchKernelGGL((fwd_hsf<KH<P, T, NTH, EPW, RECOMP, LEAN>, NTH, MINW>), dim3((unsigned)blocks), dim3(NTH),
+                           0, s, prm);
 }
 
 // four work items per workgroup in the launcher's count (its grid-size check)

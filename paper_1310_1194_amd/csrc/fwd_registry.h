@@ -92,6 +92,10 @@ int64_t items_of(int64_t ne) { return items_for<KER>(ne); }
     FwdVariant{EPW, (NTH) / 64, 8, W, &launch_hsf<P, T, NTH, EPW, false, W>, &items_hsf<EPW>}
 #define FEINT_KHR(P, T, NTH, EPW, W) \
     FwdVariant{EPW, (NTH) / 64, 9, W, &launch_hsf<P, T, NTH, EPW, true, W>, &items_hsf<EPW>}
+// KHL: W_q formed again per pass, and the last pass reading T2 from LDS where it
+// is used (fewer registers: two waves per SIMD in FP64 at p >= 5; staged = 10)
+#define FEINT_KHL(P, T, NTH, EPW, W) \
+    FwdVariant{EPW, (NTH) / 64, 10, W, &launch_hsf<P, T, NTH, EPW, true, W, true>, &items_hsf<EPW>}
 
 #define FEINT_K4U(P, T, TM, TN, W) FEINT_K4U_R(P, T, TM, TN, W, 0)
 #define FEINT_KSC(P, T, TM, TN, W) FEINT_KSC_R(P, T, TM, TN, W, 0)

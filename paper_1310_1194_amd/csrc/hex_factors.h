@@ -105,5 +105,25 @@ struct Fac {
     static constexpr Factors<P> v = make_factors<P>();
 };
 
+// The same values point-major ([m][k]), so that the factors of every k at one
+// point are contiguous.
+template <int P>
+constexpr Factors<P> make_factors_t() {
+    constexpr int n = P + 1;
+    const Factors<P> F = make_factors<P>();
+    Factors<P> T{};
+    for (int k = 0; k < n; ++k)
+        for (int m = 0; m < n; ++m) {
+            T.L[m][k] = F.L[k][m];
+            T.D[m][k] = F.D[k][m];
+        }
+    return T;
+}
+
+template <int P>
+struct FacT {
+    static constexpr Factors<P> v = make_factors_t<P>();
+};
+
 }  // namespace hexc
 }  // namespace feint

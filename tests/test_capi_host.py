@@ -205,7 +205,7 @@ def test_hex_host_api():
             assert n >= 1
             for t in range(n):
                 assert L.feint_hex_tile_describe(p, form, t, buf, 32) == 0
-                assert re.fullmatch(rb"(\d+x\d+f?|v\d+)(o2)?|sf\d+w(x\d+)?r?(o2)?", buf.value), buf.value
+                assert re.fullmatch(rb"(\d+x\d+f?|v\d+)(o2)?|sf\d+w(x\d+)?[rl]?(o\d)?", buf.value), buf.value
             # FP64 and FP32 start with the sum factorisation in all three directions
             assert L.feint_hex_tile_describe(p, form, 0, buf, 32) == 0 and buf.value.startswith(b"sf")
         for form in (2, 3):                          # split forms
