@@ -281,7 +281,7 @@ feint_status feint_rule_tile_set(int p, feint_form form, feint_rule rule, int ti
 // and "o2" for a two-waves-per-SIMD register budget.
 static void describe_variant(const FwdVariant &v, char *buf, size_t len) {
     if (v.staged == 3)
-        std::snprintf(buf, len, "v%d%s", v.tn, v.minw > 1 ? "o2" : "");
+        std::snprintf(buf, len, "v%d%s", v.tn, v.minw > 1 ? ("o" + std::to_string(v.minw)).c_str() : "");
     else if (v.staged >= 8 && v.staged <= 10)
         std::snprintf(buf, len, "sf%dw%s%s%s", v.tn, v.tm > 1 ? ("x" + std::to_string(v.tm)).c_str() : "",
                       v.staged == 9 ? "r" : v.staged == 10 ? "l" : "",

@@ -6,6 +6,8 @@
 namespace feint {
 namespace {
 const FwdVariant v1[] = {
+    FEINT_KE(1, float, 3),
+    FEINT_KE(1, float, 2),
     FEINT_KV(1, float, 8, 2),
     FEINT_KV(1, float, 6, 2),
     FEINT_K4S(1, float, 1, 1, 8, 1),

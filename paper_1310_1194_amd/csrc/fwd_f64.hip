@@ -6,6 +6,7 @@
 namespace feint {
 namespace {
 const FwdVariant v1[] = {
+    FEINT_KE(1, double, 2),
     FEINT_KV(1, double, 8, 2),
     FEINT_KV(1, double, 6, 2),
     FEINT_K4S(1, double, 1, 1, 8, 1),

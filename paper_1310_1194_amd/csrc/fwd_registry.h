@@ -42,6 +42,10 @@ int64_t items_of(int64_t ne) { return items_for<KER>(ne); }
 // V: vector-ALU kernel, LPE lanes per element (tm = 0, tn = LPE, staged = 3).
 #define FEINT_KV_R(P, T, LPE, W, R) \
     FwdVariant{0, LPE, 3, W, &launch_direct<KV<P, T, LPE, R>, W>, &items_of<KV<P, T, LPE, R>>}
+// E: one element per lane, vector ALU (p = 1; tm = 0, tn = 1 lane per element, staged = 3).
+#define FEINT_KE_R(P, T, W, R) \
+    FwdVariant{0, 1, 3, W, &launch_direct<KE<P, T, R>, W>, &items_of<KE<P, T, R>>}
+#define FEINT_KE(P, T, W) FEINT_KE_R(P, T, W, 0)
 // P: software-pipelined split kernel (staged = 4).
 #define FEINT_K32P_R(P, F, TM, TN, W, R) \
     FwdVariant{TM, TN, 4, W, &launch_direct<K32P<P, F, TM, TN, R>, W>, &items_of<K32P<P, F, TM, TN, R>>}

@@ -155,4 +155,98 @@ struct KV {
     }
 };
 
+// One element per lane (p = 1, n = 6): each lane runs its own element's point
+// loop -- W_q in FP64, then y_r = (W_q B_q)[r][j] (13 FMAs per column) and
+// A_ij += sum_r B_q[r][i] y_r (4 per entry) -- while the whole wave is at the
+// same point, so every table entry is wave-uniform and enters the FMAs as a
+// scalar operand.  Against the kernel above (LPE lanes per element), no lane
+// sits on a padding column and W_q needs no LDS: about half the vector
+// instructions per element.  64 elements per wave; each lane loads and stores
+// its own element (staging those through LDS for wave-contiguous accesses
+// measured slower: the index arithmetic and the waits cost more than the
+// scattered lines).  Lanes past the batch compute on element 0 and store
+// nothing.
+template <int P, typename T, int R = 0, class G = PrismGeo>
+struct KE {
+    static constexpr int N = G::nshp(P), NP = c_pad16(N), NQ = G::nq(P, R);
+    static constexpr int EPI = 64, NBLK = 1;
+    static_assert(N <= 8, "one element per lane holds its n^2 accumulators");
+    typedef const __attribute__((address_space(4))) T CT;
+    typedef const __attribute__((address_space(4))) double CD;
+    struct Smem { int unused; };
+
+    __device__ static void run(const FwdParams &prm, int64_t group, int blk, int wave, Smem &) {
+        (void)blk;
+        (void)wave;
+        const int lane = threadIdx.x & 63;
+        const int64_t slot = group * 64 + lane;
+        const bool act = slot < prm.ne;
+        const int64_t e = act ? elem_of(prm, slot) : 0;
+        typename G::Elem E;
+        G::load(prm, e, E);
+        const T *Bt = uniform_ptr(sizeof(T) == 8 ? (const T *)(const void *)prm.B64
+                                                 : (const T *)(const void *)prm.B32);
+        const double *B64 = uniform_ptr(prm.B64);
+        const double *qw = uniform_ptr(prm.qw);
+        T acc[N][N];
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int j = 0; j < N; ++j) acc[i][j] = (T)0;
+        double bj[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) bj[j] = 0.0;
+#pragma unroll 1
+        for (int q = 0; q < NQ; ++q) {
+            const double *qp = qw + 4 * q;
+            double W[16], sf;
+            G::coeffs(prm, e, qp, E);
+            const double det = G::block(E, qp, W, sf);
+            if (act && !(det > 0.0) && prm.status) atomicOr(prm.status, 1u);
+            if (act && prm.xq) {
+                double x[3];
+                G::map(E, qp, x);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) prm.xq[(e * NQ + q) * 3 + d] = x[d];
+            }
+            const CT *Bq = (const CT *)(Bt + (size_t)q * 4 * NP);
+            T w[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) w[k] = (T)W[k];
+            T y[4][N];
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                const T c0 = Bq[j], c1 = Bq[NP + j], c2 = Bq[2 * NP + j], c3 = Bq[3 * NP + j];
+                y[0][j] = fma_t(w[3], c3, fma_t(w[2], c2, fma_t(w[1], c1, w[0] * c0)));
+#pragma unroll
+                for (int r = 1; r < 4; ++r) y[r][j] = fma_t(w[4 * r + 3], c3, fma_t(w[4 * r + 2], c2, w[4 * r + 1] * c1));
+            }
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const T b0 = Bq[i], b1 = Bq[NP + i], b2 = Bq[2 * NP + i], b3 = Bq[3 * NP + i];
+#pragma unroll
+                for (int j = 0; j < N; ++j)
+                    acc[i][j] = fma_t(b3, y[3][j], fma_t(b2, y[2][j], fma_t(b1, y[1][j], fma_t(b0, y[0][j], acc[i][j]))));
+            }
+            if constexpr (G::LOAD) {
+                const CD *B0 = (const CD *)(B64 + (size_t)q * 4 * NP);
+#pragma unroll
+                for (int j = 0; j < N; ++j) bj[j] = __builtin_fma(sf, B0[j], bj[j]);
+            }
+        }
+        if (act) {
+            T *Aout = (T *)prm.A + offA_of(prm, e, N);
+#pragma unroll
+            for (int i = 0; i < N; ++i)
+#pragma unroll
+                for (int j = 0; j < N; ++j) Aout[i * N + j] = acc[i][j];
+            if constexpr (G::LOAD) {
+                T *bout = (T *)prm.b + offb_of(prm, e, N);
+#pragma unroll
+                for (int j = 0; j < N; ++j) bout[j] = (T)bj[j];
+            }
+        }
+    }
+};
+
 }  // namespace feint

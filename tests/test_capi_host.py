@@ -65,7 +65,7 @@ def test_tiles():
             assert n >= 1
             buf = ctypes.create_string_buffer(16)
             assert L.feint_tile_describe(p, form, n - 1, buf, 16) == 0
-            assert re.fullmatch(rb"(\d+x\d+(s|sa|p|c|f)?|v\d+)(o2)?", buf.value)
+            assert re.fullmatch(rb"(\d+x\d+(s|sa|p|c|f)?|v\d+)(o\d)?", buf.value)
             assert L.feint_tile_set(p, form, n) == -1
     assert L.feint_tile_count(0, 0) == 0
 
@@ -166,7 +166,7 @@ def test_rule_counts_and_points():
 def test_rule_tiles_and_validation():
     L = native.lib()
     buf = ctypes.create_string_buffer(32)
-    pat = re.compile(r"(\d+x\d+(s|sa|p|c|f)?|v\d+)(o2)?")
+    pat = re.compile(r"(\d+x\d+(s|sa|p|c|f)?|v\d+)(o\d)?")
     for form in range(4):
         for p in range(1, 8):
             n = L.feint_rule_tile_count(p, form, 1)
@@ -205,7 +205,7 @@ def test_hex_host_api():
             assert n >= 1
             for t in range(n):
                 assert L.feint_hex_tile_describe(p, form, t, buf, 32) == 0
-                assert re.fullmatch(rb"(\d+x\d+f?|v\d+)(o2)?|sf\d+w(x\d+)?[rl]?(o\d)?", buf.value), buf.value
+                assert re.fullmatch(rb"(\d+x\d+f?|v\d+)(o\d)?|sf\d+w(x\d+)?[rl]?(o\d)?", buf.value), buf.value
             # FP64 and FP32 start with the sum factorisation in all three directions
             assert L.feint_hex_tile_describe(p, form, 0, buf, 32) == 0 and buf.value.startswith(b"sf")
         for form in (2, 3):                          # split forms
@@ -234,7 +234,7 @@ def test_tet_host_api():
             assert n >= 1
             for t in range(n):
                 assert L.feint_tet_tile_describe(p, form, t, buf, 32) == 0
-                assert re.fullmatch(rb"(\d+x\d+f?|v\d+)(o2)?", buf.value), buf.value
+                assert re.fullmatch(rb"(\d+x\d+f?|v\d+)(o\d)?", buf.value), buf.value
         for form in (2, 3):
             assert L.feint_tet_tile_count(p, form) >= 1
     el = _el(4)
