@@ -1,8 +1,9 @@
 // Forward kernels of the paper's own term (Laplace, eq. (1)) on its quadrature
 // (the symmetric triangle rule of degree 2p x (p+1) Gauss points in zeta, the
-// N_I of Table 3), FP64 and FP32: the vector-ALU kernel at p <= 2 and the
-// contraction per triangle point above, with the Laplace geometry policy
-// (coordinates only, W_q = w det J [[0, 0], [0, K K^T]], no load vector).
+// N_I of Table 3), FP64 and FP32: the vector-ALU kernels at p <= 2 (at p = 1
+// also one element per lane) and the contraction per triangle point above,
+// with the Laplace geometry policy (coordinates only,
+// W_q = w det J [[0, 0], [0, K K^T]], no load vector).
 // The first shape per degree is the default until the autotuner picks another.
 #include "fwd_registry.h"
 
@@ -12,10 +13,12 @@ constexpr int S = 1;
 typedef PrismLaplaceGeo L;
 #define LKV(P, T, LPE, W) \
     FwdVariant{0, LPE, 3, W, &launch_direct<KV<P, T, LPE, S, L>, W>, &items_of<KV<P, T, LPE, S, L>>}
+#define LKE(P, T, W) \
+    FwdVariant{0, 1, 3, W, &launch_direct<KE<P, T, S, L>, W>, &items_of<KE<P, T, S, L>>}
 #define LKF(P, T, TMK, TN, W) \
     FwdVariant{TMK, TN, 6, W, &launch_direct<KF<P, T, TMK, TN, S, L>, W>, &items_of<KF<P, T, TMK, TN, S, L>>}
 // FP64
-const FwdVariant d1[] = {LKV(1, double, 8, 2), LKF(1, double, 2, 2, 2)};
+const FwdVariant d1[] = {LKE(1, double, 2), LKV(1, double, 8, 2), LKF(1, double, 2, 2, 2)};
 const FwdVariant d2[] = {LKV(2, double, 18, 2), LKF(2, double, 3, 3, 2)};
 const FwdVariant d3[] = {LKF(3, double, 4, 2, 2), LKF(3, double, 4, 2, 1), LKV(3, double, 40, 2)};
 const FwdVariant d4[] = {LKF(4, double, 5, 5, 1), LKF(4, double, 5, 3, 1)};
@@ -23,7 +26,7 @@ const FwdVariant d5[] = {LKF(5, double, 6, 2, 1), LKF(5, double, 3, 2, 1)};
 const FwdVariant d6[] = {LKF(6, double, 7, 1, 1), LKF(6, double, 4, 2, 1)};
 const FwdVariant d7[] = {LKF(7, double, 4, 2, 1), LKF(7, double, 4, 1, 1)};
 // FP32
-const FwdVariant f1[] = {LKV(1, float, 8, 2), LKF(1, float, 2, 2, 2)};
+const FwdVariant f1[] = {LKE(1, float, 3), LKE(1, float, 2), LKV(1, float, 8, 2), LKF(1, float, 2, 2, 2)};
 const FwdVariant f2[] = {LKV(2, float, 18, 2), LKF(2, float, 3, 3, 2)};
 const FwdVariant f3[] = {LKF(3, float, 4, 4, 2), LKV(3, float, 40, 2)};
 const FwdVariant f4[] = {LKF(4, float, 5, 3, 1), LKF(4, float, 5, 5, 1)};

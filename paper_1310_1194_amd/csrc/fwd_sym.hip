@@ -9,7 +9,7 @@ namespace feint {
 namespace {
 constexpr int S = 1;
 // FP64
-const FwdVariant d1[] = {FEINT_KV_R(1, double, 8, 2, S), FEINT_K4S_R(1, double, 1, 1, 8, 1, S), FEINT_KSC_R(1, double, 1, 1, 1, S), FEINT_KF_R(1, double, 2, 2, 2, S)};
+const FwdVariant d1[] = {FEINT_KE_R(1, double, 2, S), FEINT_KV_R(1, double, 8, 2, S), FEINT_K4S_R(1, double, 1, 1, 8, 1, S), FEINT_KSC_R(1, double, 1, 1, 1, S), FEINT_KF_R(1, double, 2, 2, 2, S)};
 const FwdVariant d2[] = {FEINT_KV_R(2, double, 18, 2, S), FEINT_K4S_R(2, double, 2, 2, 8, 1, S), FEINT_KSC_R(2, double, 2, 2, 1, S), FEINT_KF_R(2, double, 3, 3, 2, S)};
 const FwdVariant d3[] = {FEINT_KF_R(3, double, 4, 2, 2, S), FEINT_KF_R(3, double, 4, 2, 1, S), FEINT_K4S_R(3, double, 3, 3, 8, 1, S), FEINT_KV_R(3, double, 40, 2, S), FEINT_KSC_R(3, double, 3, 3, 1, S)};
 const FwdVariant d4[] = {FEINT_KF_R(4, double, 5, 5, 1, S), FEINT_KF_R(4, double, 5, 3, 1, S), FEINT_K4S_R(4, double, 5, 3, 8, 2, S), FEINT_K4U_R(4, double, 5, 1, 2, S), FEINT_KSC_R(4, double, 5, 3, 1, S)};
@@ -17,7 +17,7 @@ const FwdVariant d5[] = {FEINT_KF_R(5, double, 6, 2, 1, S), FEINT_KF_R(5, double
 const FwdVariant d6[] = {FEINT_KF_R(6, double, 7, 1, 1, S), FEINT_KF_R(6, double, 4, 2, 1, S), FEINT_K4U_R(6, double, 13, 1, 2, S), FEINT_K4S_R(6, double, 13, 1, 4, 1, S), FEINT_KSC_R(6, double, 13, 1, 1, S)};
 const FwdVariant d7[] = {FEINT_KF_R(7, double, 4, 2, 1, S), FEINT_KF_R(7, double, 2, 2, 1, S), FEINT_KF_R(7, double, 4, 1, 1, S), FEINT_K4U_R(7, double, 9, 2, 1, S), FEINT_K4U_R(7, double, 6, 2, 1, S), FEINT_KSC_R(7, double, 6, 2, 1, S)};
 // FP32
-const FwdVariant f1[] = {FEINT_KV_R(1, float, 8, 2, S), FEINT_K4S_R(1, float, 1, 1, 8, 1, S), FEINT_KSC_R(1, float, 1, 1, 1, S), FEINT_KF_R(1, float, 2, 2, 2, S)};
+const FwdVariant f1[] = {FEINT_KE_R(1, float, 3, S), FEINT_KV_R(1, float, 8, 2, S), FEINT_K4S_R(1, float, 1, 1, 8, 1, S), FEINT_KSC_R(1, float, 1, 1, 1, S), FEINT_KF_R(1, float, 2, 2, 2, S)};
 const FwdVariant f2[] = {FEINT_KV_R(2, float, 18, 2, S), FEINT_K4S_R(2, float, 2, 2, 8, 1, S), FEINT_KSC_R(2, float, 2, 2, 1, S), FEINT_KF_R(2, float, 3, 3, 2, S)};
 const FwdVariant f3[] = {FEINT_KF_R(3, float, 4, 4, 2, S), FEINT_K4S_R(3, float, 3, 3, 8, 1, S), FEINT_KV_R(3, float, 40, 2, S), FEINT_KSC_R(3, float, 3, 3, 1, S)};
 const FwdVariant f4[] = {FEINT_KF_R(4, float, 5, 3, 1, S), FEINT_KF_R(4, float, 5, 5, 1, S), FEINT_K4U_R(4, float, 5, 5, 1, S), FEINT_K4S_R(4, float, 5, 5, 8, 1, S), FEINT_KSC_R(4, float, 5, 5, 1, S)};
