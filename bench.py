@@ -53,7 +53,9 @@ KERNEL_SOURCES = ["paper_1310_1194_amd/csrc/fwd_kernels.h", "paper_1310_1194_amd
                   "paper_1310_1194_amd/csrc/fwd_registry.h", "paper_1310_1194_amd/csrc/fwd_bf16.hip",
                   "paper_1310_1194_amd/csrc/fwd_f16.hip", "paper_1310_1194_amd/csrc/fwd_f32.hip",
                   "paper_1310_1194_amd/csrc/fwd_f64.hip",
-                  "paper_1310_1194_amd/csrc/device_common.h", "paper_1310_1194_amd/csrc/tables.cpp"]
+                  "paper_1310_1194_amd/csrc/device_common.h", "paper_1310_1194_amd/csrc/tables.cpp",
+                  "paper_1310_1194_amd/csrc/fwd_hsf.h", "paper_1310_1194_amd/csrc/hex_factors.h",
+                  "paper_1310_1194_amd/csrc/fwd_hex.hip"]
 
 
 def kernel_source_sha() -> str:
@@ -541,6 +543,12 @@ def bench_hex(args):
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     in_bytes = 8 * (24 + 9 + 3 + 1 + 1)
     out, head = {}, None
+    if args.copy_cal:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for p in ps:
         name = HEX_WORKLOADS[p]
         batch = meshgen.workload(name)
@@ -615,6 +623,8 @@ def bench_hex(args):
                                   "frac": max(t_alu, t_hbm) / (ms * 1e-3),
                                   "alu_frac": t_alu / (ms * 1e-3), "hbm_frac": t_hbm / (ms * 1e-3),
                                   "write_frac_of_fill": n * n * es * ne / (ms * 1e-3) / 1e9 / fill_gbs}}
+                if kname == "sumfact":
+                    r["roofline"]["traffic"] = traffic_record(f"hexsf:{form}:{name}", descs[best])
                 if ref is not None:
                     ti = torch.from_numpy(idx).to(dev)
                     gA, mA = rel_err(A[ti].cpu().numpy(), ref[0])
