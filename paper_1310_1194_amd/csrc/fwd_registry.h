@@ -46,6 +46,8 @@ int64_t items_of(int64_t ne) { return items_for<KER>(ne); }
 #define FEINT_KE_R(P, T, W, R) \
     FwdVariant{0, 1, 3, W, &launch_direct<KE<P, T, R>, W>, &items_of<KE<P, T, R>>}
 #define FEINT_KE(P, T, W) FEINT_KE_R(P, T, W, 0)
+#define FEINT_KE_G(P, T, W, GEO) \
+    FwdVariant{0, 1, 3, W, &launch_direct<KE<P, T, 0, GEO>, W>, &items_of<KE<P, T, 0, GEO>>}
 // P: software-pipelined split kernel (staged = 4).
 #define FEINT_K32P_R(P, F, TM, TN, W, R) \
     FwdVariant{TM, TN, 4, W, &launch_direct<K32P<P, F, TM, TN, R>, W>, &items_of<K32P<P, F, TM, TN, R>>}

@@ -1,6 +1,7 @@
 // Forward kernels for tetrahedral elements (Table 1's complete-basis 3D
 // element): the 16x16x4 MFMA kernel (FP64, FP32; below p = 3 first the
-// vector-ALU kernel, "vL" = L lanes per element) and the 16x16x32 split
+// vector-ALU kernel, "vL" = L lanes per element, at p = 1 "v1" = one element
+// per lane) and the 16x16x32 split
 // kernel (bf16x3, fp16x3) with the affine geometry; tile shapes per degree
 // (n = 4, 10, 20, 35, 56, 84, 120 shape functions: 1, 1, 2, 3, 4, 6, 8 tiles
 // of 16), the first the default.
@@ -8,7 +9,7 @@
 
 namespace feint {
 namespace {
-const FwdVariant d1[] = {FEINT_KV_G(1, double, 8, 2, TetGeo), FEINT_K4U_TET(1, double, 1, 1, 2)};
+const FwdVariant d1[] = {FEINT_KE_G(1, double, 2, TetGeo), FEINT_KV_G(1, double, 8, 2, TetGeo), FEINT_K4U_TET(1, double, 1, 1, 2)};
 const FwdVariant d2[] = {FEINT_KV_G(2, double, 16, 2, TetGeo), FEINT_K4U_TET(2, double, 1, 1, 2)};
 const FwdVariant d3[] = {FEINT_K4U_TET(3, double, 2, 2, 2), FEINT_K4U_TET(3, double, 2, 1, 2),
                          FEINT_KV_G(3, double, 32, 2, TetGeo)};
@@ -16,7 +17,7 @@ const FwdVariant d4[] = {FEINT_K4U_TET(4, double, 3, 3, 2), FEINT_K4U_TET(4, dou
 const FwdVariant d5[] = {FEINT_K4U_TET(5, double, 4, 2, 2), FEINT_K4U_TET(5, double, 4, 1, 2)};
 const FwdVariant d6[] = {FEINT_K4U_TET(6, double, 6, 2, 1), FEINT_K4U_TET(6, double, 6, 1, 2)};
 const FwdVariant d7[] = {FEINT_K4U_TET(7, double, 8, 2, 1), FEINT_K4U_TET(7, double, 8, 1, 2)};
-const FwdVariant f1[] = {FEINT_KV_G(1, float, 8, 2, TetGeo), FEINT_K4U_TET(1, float, 1, 1, 2)};
+const FwdVariant f1[] = {FEINT_KE_G(1, float, 3, TetGeo), FEINT_KE_G(1, float, 2, TetGeo), FEINT_KV_G(1, float, 8, 2, TetGeo), FEINT_K4U_TET(1, float, 1, 1, 2)};
 const FwdVariant f2[] = {FEINT_KV_G(2, float, 16, 2, TetGeo), FEINT_K4U_TET(2, float, 1, 1, 2)};
 const FwdVariant f3[] = {FEINT_K4U_TET(3, float, 2, 2, 2), FEINT_KV_G(3, float, 32, 2, TetGeo)};
 const FwdVariant f4[] = {FEINT_K4U_TET(4, float, 3, 3, 2), FEINT_K4U_TET(4, float, 3, 3, 1)};
