@@ -61,7 +61,9 @@ feint_status prepare_tables(int p, int rule, int type) {
     const size_t s_qw = align(H.qw.size() * 8), s_gll = align(H.gll.size() * 8), s_b64 = align(H.B64.size() * 8), s_b32 = align(H.B32.size() * 4);
     const size_t s_sp = align(H.bf_hi.size() * 2);
     const size_t s_ycf = align(H.Ycf.size() * 4);
-    const size_t total = s_tau + s_tau32 + s_lam + s_lam32 + s_qw + s_gll + 2 * s_b64 + 3 * s_b32 + 4 * s_sp + s_ycf;
+    const size_t s_m64 = align(H.Mref.size() * 8), s_m32 = align(H.Mref32.size() * 4);
+    const size_t total = s_tau + s_tau32 + s_lam + s_lam32 + s_qw + s_gll + 2 * s_b64 + 3 * s_b32 + 4 * s_sp + s_ycf +
+                         s_m64 + s_m32;
     char *base = nullptr;
     e = hipMalloc((void **)&base, total);
     if (e != hipSuccess) { set_error("hipMalloc(tables)", e); return FEINT_ERR_HIP; }
@@ -95,6 +97,8 @@ feint_status prepare_tables(int p, int rule, int type) {
     T->hf_hi = (const uint16_t *)put(H.hf_hi.data(), H.hf_hi.size() * 2, s_sp);
     T->hf_lo = (const uint16_t *)put(H.hf_lo.data(), H.hf_lo.size() * 2, s_sp);
     T->Ycf = (const float *)put(H.Ycf.data(), H.Ycf.size() * 4, s_ycf);
+    T->Mref64 = (const double *)put(H.Mref.data(), H.Mref.size() * 8, s_m64);
+    T->Mref32 = (const float *)put(H.Mref32.data(), H.Mref32.size() * 4, s_m32);
     T->base = base;
     e = hipMemcpy(base, host.data(), total, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -139,6 +143,7 @@ void fill_fwd_params(FwdParams &prm, const feint_elements *el, int form, const D
     prm.ne = el->ne;
     prm.qw = T->qw; prm.gll = T->gll; prm.tau64 = T->tau64; prm.tau32 = T->tau32; prm.lam = T->lam; prm.lam32 = T->lam32;
     prm.B64 = T->B64; prm.B32 = T->B32; prm.Bc32 = T->Bc32; prm.Ycf = T->Ycf;
+    prm.Mref64 = T->Mref64; prm.Mref32 = T->Mref32;
     prm.Bhi = form == FEINT_FP16X3 ? T->hf_hi : T->bf_hi;
     prm.Blo = form == FEINT_FP16X3 ? T->hf_lo : T->bf_lo;
     prm.bmax = T->bmax;
@@ -282,6 +287,9 @@ feint_status feint_rule_tile_set(int p, feint_form form, feint_rule rule, int ti
 static void describe_variant(const FwdVariant &v, char *buf, size_t len) {
     if (v.staged == 3)
         std::snprintf(buf, len, "v%d%s", v.tn, v.minw > 1 ? ("o" + std::to_string(v.minw)).c_str() : "");
+    else if (v.staged == 11)
+        std::snprintf(buf, len, "ref%d%s%s%s", v.tm, v.tn % 4 == 2 ? "s" : "", v.tn >= 4 ? ("e" + std::to_string(v.tn / 4)).c_str() : "",
+                      v.minw > 1 ? ("o" + std::to_string(v.minw)).c_str() : "");
     else if (v.staged >= 8 && v.staged <= 10)
         std::snprintf(buf, len, "sf%dw%s%s%s", v.tn, v.tm > 1 ? ("x" + std::to_string(v.tm)).c_str() : "",
                       v.staged == 9 ? "r" : v.staged == 10 ? "l" : "",

@@ -19,6 +19,8 @@ struct DevTables {
     const float *B32, *BT32, *Bc32;
     const uint16_t *bf_hi, *bf_lo, *hf_hi, *hf_lo;
     const float *Ycf;
+    const double *Mref64;
+    const float *Mref32;
     void *base;
 };
 

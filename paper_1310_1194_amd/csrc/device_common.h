@@ -4,6 +4,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 namespace feint {
 
@@ -255,7 +256,66 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+template <int I>
+using ic = std::integral_constant<int, I>;
+
+// for (i = B; i < E; ++i) f(i) with i a compile-time constant
+template <int B, int E, class Fn>
+__device__ __forceinline__ void static_for(Fn &&f) {
+    if constexpr (B < E) {
+        f(ic<B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
 __device__ inline int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline int64_t wave_uniform64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// A copy of a wave-uniform pointer that the compiler can see is uniform
+// (values passed to non-inlined functions are otherwise taken as divergent).
+template <typename T>
+__device__ inline const T *uniform_ptr(const T *p) {
+    const uint64_t v = (uint64_t)(uintptr_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return (const T *)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Raw buffer access: a resource over BYTES bytes from a wave-uniform base (stride
+// 0, the CDNA data-format word), addressed by a per-lane 32-bit byte offset plus
+// a wave-uniform byte offset.  Accesses past BYTES are dropped (stores) or read
+// zero (loads) by the hardware's range check.
+__device__ inline __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+__device__ inline void buffer_store(double v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff, 0);
+}
+__device__ inline void buffer_store(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+}
+template <typename T> __device__ inline T buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <> __device__ inline double buffer_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+template <> __device__ inline float buffer_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+
+// The same wave-uniform pointer, opaque to the optimiser: table values read
+// through it are loaded where they are used instead of being hoisted out of
+// the loops (where, held in scalar registers across them, they can outnumber
+// the scalar register file and spill).
+template <class PT>
+__device__ __forceinline__ PT fresh(PT p) {
+    asm volatile("" : "+s"(p));
+    return p;
+}
 
 // Fused multiply-add in the operands' own precision.
 __device__ inline float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }

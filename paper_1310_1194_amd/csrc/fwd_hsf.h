@@ -36,18 +36,6 @@
 
 namespace feint {
 
-template <int I>
-using ic = std::integral_constant<int, I>;
-
-// for (i = B; i < E; ++i) f(i) with i a compile-time constant
-template <int B, int E, class Fn>
-__device__ __forceinline__ void static_for(Fn &&f) {
-    if constexpr (B < E) {
-        f(ic<B>{});
-        static_for<B + 1, E>(f);
-    }
-}
-
 // A table value as an FP32 instruction literal.
 template <uint64_t BITS>
 __device__ __forceinline__ float kval() {
@@ -55,16 +43,6 @@ __device__ __forceinline__ float kval() {
 }
 #define FEINT_HL(K, M) kval<__builtin_bit_cast(uint64_t, hexc::Fac<P>::v.L[K][M])>()
 #define FEINT_HD(K, M) kval<__builtin_bit_cast(uint64_t, hexc::Fac<P>::v.D[K][M])>()
-
-// The same uniform pointer, opaque to the optimiser: FP64 table values (which
-// cannot be literals) read through it are loaded where they are used instead of
-// being hoisted out of the loops, where at p >= 5 they would outnumber the
-// scalar registers.
-template <class PT>
-__device__ __forceinline__ PT fresh(PT p) {
-    asm volatile("" : "+s"(p));
-    return p;
-}
 
 template <int P, typename T, int NTH, int EPW, bool RECOMP = false, bool LEAN = false>
 struct KH {

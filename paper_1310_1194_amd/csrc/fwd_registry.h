@@ -9,6 +9,7 @@
 #include "fwd_fact.h"
 #include "fwd_ymfma.h"
 #include "fwd_hsf.h"
+#include "fwd_tref.h"
 
 namespace feint {
 
@@ -46,6 +47,11 @@ int64_t items_of(int64_t ne) { return items_for<KER>(ne); }
 #define FEINT_KE_R(P, T, W, R) \
     FwdVariant{0, 1, 3, W, &launch_direct<KE<P, T, R>, W>, &items_of<KE<P, T, R>>}
 #define FEINT_KE(P, T, W) FEINT_KE_R(P, T, W, 0)
+// R: tetrahedra from reference matrices (staged = 11): one element per lane.
+#define FEINT_KT(P, T, R, W) FwdVariant{R, 1, 11, W, &launch_direct<KT<P, T, R>, W>, &items_of<KT<P, T, R>>}
+#define FEINT_KTS(P, T, W) FwdVariant{1, 2, 11, W, &launch_direct<KT<P, T, 1, true>, W>, &items_of<KT<P, T, 1, true>>}
+#define FEINT_KTE(P, T, E, S, W) \
+    FwdVariant{1, (S ? 2 : 1) + 4 * E, 11, W, &launch_direct<KT<P, T, 1, S, E>, W>, &items_of<KT<P, T, 1, S, E>>}
 #define FEINT_KE_G(P, T, W, GEO) \
     FwdVariant{0, 1, 3, W, &launch_direct<KE<P, T, 0, GEO>, W>, &items_of<KE<P, T, 0, GEO>>}
 // P: software-pipelined split kernel (staged = 4).

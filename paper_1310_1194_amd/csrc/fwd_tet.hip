@@ -1,29 +1,33 @@
 // Forward kernels for tetrahedral elements (Table 1's complete-basis 3D
-// element): the 16x16x4 MFMA kernel (FP64, FP32; below p = 3 first the
-// vector-ALU kernel, "vL" = L lanes per element, at p = 1 "v1" = one element
-// per lane) and the 16x16x32 split
-// kernel (bf16x3, fp16x3) with the affine geometry; tile shapes per degree
-// (n = 4, 10, 20, 35, 56, 84, 120 shape functions: 1, 1, 2, 3, 4, 6, 8 tiles
-// of 16), the first the default.
+// element).  FP64 and FP32 start with the reference-matrix GEMM: "refR" = R
+// row tiles of 16 elements per pass over the column tiles, "s" = results
+// staged through LDS so that a store writes 64 consecutive entries of one
+// element, "eE" = E elements per wave (64 without it).  The point-by-point
+// kernels follow: the 16x16x4 MFMA kernel, below p = 3 the vector-ALU kernel
+// ("vL" = L lanes per element, at p = 1 "v1" = one element per lane), and the
+// 16x16x32 split kernel (bf16x3, fp16x3), all with the affine geometry; tile
+// shapes per degree (n = 4, 10, 20, 35, 56, 84, 120 shape functions: 1, 1, 2,
+// 3, 4, 6, 8 tiles of 16).  The first of each list is the default (the
+// fastest measured at 393216 elements where measured).
 #include "fwd_registry.h"
 
 namespace feint {
 namespace {
-const FwdVariant d1[] = {FEINT_KE_G(1, double, 2, TetGeo), FEINT_KV_G(1, double, 8, 2, TetGeo), FEINT_K4U_TET(1, double, 1, 1, 2)};
-const FwdVariant d2[] = {FEINT_KV_G(2, double, 16, 2, TetGeo), FEINT_K4U_TET(2, double, 1, 1, 2)};
-const FwdVariant d3[] = {FEINT_K4U_TET(3, double, 2, 2, 2), FEINT_K4U_TET(3, double, 2, 1, 2),
+const FwdVariant d1[] = {FEINT_KT(1, double, 4, 2), FEINT_KE_G(1, double, 2, TetGeo), FEINT_KV_G(1, double, 8, 2, TetGeo), FEINT_K4U_TET(1, double, 1, 1, 2)};
+const FwdVariant d2[] = {FEINT_KTS(2, double, 2), FEINT_KTE(2, double, 16, true, 2), FEINT_KT(2, double, 1, 2), FEINT_KTE(2, double, 16, false, 2), FEINT_KT(2, double, 4, 2), FEINT_KV_G(2, double, 16, 2, TetGeo), FEINT_K4U_TET(2, double, 1, 1, 2)};
+const FwdVariant d3[] = {FEINT_KTE(3, double, 16, true, 2), FEINT_KTS(3, double, 2), FEINT_KT(3, double, 1, 2), FEINT_KTE(3, double, 16, false, 2), FEINT_KT(3, double, 4, 2), FEINT_K4U_TET(3, double, 2, 2, 2), FEINT_K4U_TET(3, double, 2, 1, 2),
                          FEINT_KV_G(3, double, 32, 2, TetGeo)};
-const FwdVariant d4[] = {FEINT_K4U_TET(4, double, 3, 3, 2), FEINT_K4U_TET(4, double, 3, 1, 2)};
-const FwdVariant d5[] = {FEINT_K4U_TET(5, double, 4, 2, 2), FEINT_K4U_TET(5, double, 4, 1, 2)};
-const FwdVariant d6[] = {FEINT_K4U_TET(6, double, 6, 2, 1), FEINT_K4U_TET(6, double, 6, 1, 2)};
-const FwdVariant d7[] = {FEINT_K4U_TET(7, double, 8, 2, 1), FEINT_K4U_TET(7, double, 8, 1, 2)};
-const FwdVariant f1[] = {FEINT_KE_G(1, float, 3, TetGeo), FEINT_KE_G(1, float, 2, TetGeo), FEINT_KV_G(1, float, 8, 2, TetGeo), FEINT_K4U_TET(1, float, 1, 1, 2)};
-const FwdVariant f2[] = {FEINT_KV_G(2, float, 16, 2, TetGeo), FEINT_K4U_TET(2, float, 1, 1, 2)};
-const FwdVariant f3[] = {FEINT_K4U_TET(3, float, 2, 2, 2), FEINT_KV_G(3, float, 32, 2, TetGeo)};
-const FwdVariant f4[] = {FEINT_K4U_TET(4, float, 3, 3, 2), FEINT_K4U_TET(4, float, 3, 3, 1)};
-const FwdVariant f5[] = {FEINT_K4U_TET(5, float, 4, 4, 1), FEINT_K4U_TET(5, float, 4, 2, 2)};
-const FwdVariant f6[] = {FEINT_K4U_TET(6, float, 6, 3, 1), FEINT_K4U_TET(6, float, 6, 2, 1)};
-const FwdVariant f7[] = {FEINT_K4U_TET(7, float, 8, 4, 1), FEINT_K4U_TET(7, float, 8, 2, 1)};
+const FwdVariant d4[] = {FEINT_KTE(4, double, 16, true, 2), FEINT_KTS(4, double, 2), FEINT_KT(4, double, 1, 2), FEINT_KTE(4, double, 16, false, 2), FEINT_KT(4, double, 4, 2), FEINT_K4U_TET(4, double, 3, 3, 2), FEINT_K4U_TET(4, double, 3, 1, 2)};
+const FwdVariant d5[] = {FEINT_KTE(5, double, 16, true, 2), FEINT_KTS(5, double, 2), FEINT_KT(5, double, 1, 2), FEINT_KTE(5, double, 16, false, 2), FEINT_KT(5, double, 4, 2), FEINT_K4U_TET(5, double, 4, 2, 2), FEINT_K4U_TET(5, double, 4, 1, 2)};
+const FwdVariant d6[] = {FEINT_KTE(6, double, 16, true, 2), FEINT_KTS(6, double, 2), FEINT_KT(6, double, 1, 2), FEINT_KTE(6, double, 16, false, 2), FEINT_KT(6, double, 4, 2), FEINT_K4U_TET(6, double, 6, 2, 1), FEINT_K4U_TET(6, double, 6, 1, 2)};
+const FwdVariant d7[] = {FEINT_KTE(7, double, 16, true, 2), FEINT_KTS(7, double, 2), FEINT_KT(7, double, 1, 2), FEINT_KTE(7, double, 16, false, 2), FEINT_KT(7, double, 4, 2), FEINT_K4U_TET(7, double, 8, 2, 1), FEINT_K4U_TET(7, double, 8, 1, 2)};
+const FwdVariant f1[] = {FEINT_KT(1, float, 4, 2), FEINT_KE_G(1, float, 3, TetGeo), FEINT_KE_G(1, float, 2, TetGeo), FEINT_KV_G(1, float, 8, 2, TetGeo), FEINT_K4U_TET(1, float, 1, 1, 2)};
+const FwdVariant f2[] = {FEINT_KTE(2, float, 16, false, 2), FEINT_KTE(2, float, 16, true, 2), FEINT_KTS(2, float, 2), FEINT_KT(2, float, 1, 2), FEINT_KT(2, float, 4, 2), FEINT_KV_G(2, float, 16, 2, TetGeo), FEINT_K4U_TET(2, float, 1, 1, 2)};
+const FwdVariant f3[] = {FEINT_KT(3, float, 1, 2), FEINT_KTE(3, float, 16, true, 2), FEINT_KTS(3, float, 2), FEINT_KTE(3, float, 16, false, 2), FEINT_KT(3, float, 4, 2), FEINT_K4U_TET(3, float, 2, 2, 2), FEINT_KV_G(3, float, 32, 2, TetGeo)};
+const FwdVariant f4[] = {FEINT_KT(4, float, 1, 2), FEINT_KTE(4, float, 16, true, 2), FEINT_KTS(4, float, 2), FEINT_KTE(4, float, 16, false, 2), FEINT_KT(4, float, 4, 2), FEINT_K4U_TET(4, float, 3, 3, 2), FEINT_K4U_TET(4, float, 3, 3, 1)};
+const FwdVariant f5[] = {FEINT_KT(5, float, 1, 2), FEINT_KTE(5, float, 16, true, 2), FEINT_KTS(5, float, 2), FEINT_KTE(5, float, 16, false, 2), FEINT_KT(5, float, 4, 2), FEINT_K4U_TET(5, float, 4, 4, 1), FEINT_K4U_TET(5, float, 4, 2, 2)};
+const FwdVariant f6[] = {FEINT_KT(6, float, 1, 2), FEINT_KTE(6, float, 16, true, 2), FEINT_KTS(6, float, 2), FEINT_KTE(6, float, 16, false, 2), FEINT_KT(6, float, 4, 2), FEINT_K4U_TET(6, float, 6, 3, 1), FEINT_K4U_TET(6, float, 6, 2, 1)};
+const FwdVariant f7[] = {FEINT_KT(7, float, 1, 2), FEINT_KTE(7, float, 16, true, 2), FEINT_KTS(7, float, 2), FEINT_KTE(7, float, 16, false, 2), FEINT_KT(7, float, 4, 2), FEINT_K4U_TET(7, float, 8, 4, 1), FEINT_K4U_TET(7, float, 8, 2, 1)};
 const FwdVariant b1[] = {FEINT_K32U_G(1, BF16X3, 1, 1, 1, TetGeo)};
 const FwdVariant b2[] = {FEINT_K32U_G(2, BF16X3, 1, 1, 1, TetGeo)};
 const FwdVariant b3[] = {FEINT_K32U_G(3, BF16X3, 2, 2, 1, TetGeo)};

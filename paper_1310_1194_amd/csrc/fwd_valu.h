@@ -25,16 +25,6 @@
 
 namespace feint {
 
-// A copy of a wave-uniform pointer that the compiler can see is uniform
-// (values passed to non-inlined functions are otherwise taken as divergent).
-template <typename T>
-__device__ inline const T *uniform_ptr(const T *p) {
-    const uint64_t v = (uint64_t)(uintptr_t)p;
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
-    return (const T *)(uintptr_t)(((uint64_t)hi << 32) | lo);
-}
-
 template <int P, typename T, int LPE, int R = 0, class G = PrismGeo>
 struct KV {
     static constexpr int N = G::nshp(P), NP = c_pad16(N), NQ = G::nq(P, R);

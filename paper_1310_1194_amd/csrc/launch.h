@@ -23,6 +23,8 @@ struct FwdParams {
     const uint16_t *Bhi;     // [nkb][npad/16][64][8] split table of the form (bf16 or fp16),
     const uint16_t *Blo;     //   in A-fragment order
     const float *Ycf;        // [nkb][npad/16][64][8] FP32 columns in B-fragment order
+    const double *Mref64;    // tetrahedra: reference matrices [16][n*n padded to 16] and load vector [n]
+    const float *Mref32;
     float bmax;              // max |B| (fp16 form: used for the per-element scale)
     int f16_shift;           // fp16 tables hold B * 2^f16_shift
     // mixed-degree launches: element ids in bucket order and packed offsets
@@ -43,7 +45,9 @@ struct FwdVariant {
                          // 5: shape functions computed at each point (no B table),
                          // 6: contraction per triangle point (tensor factors of B),
                          // 7: split kernel with Y formed on the matrix cores,
-                         // 8: hexahedra by sum factorisation (9: W_q formed in each pass)
+                         // 8: hexahedra by sum factorisation (9: W_q formed in each pass,
+                         // 10: and the last pass reading from LDS), 11: tetrahedra from
+                         // reference matrices
     int minw;            // waves per SIMD the register allocation allows
     void (*launch)(const FwdParams &, hipStream_t);
     int64_t (*items)(int64_t ne);   // work items (waves) of a launch over ne elements

@@ -680,6 +680,7 @@ HostTables build_tet_tables(int p) {
     const std::vector<long double> C = invert(n, V);
     const int np = T.npad;
     T.B64.assign((size_t)T.nqp * 4 * np, 0.0);
+    std::vector<long double> Bx((size_t)T.nq * 4 * n);    // the basis rows in extended precision
     std::vector<long double> md(n), m0(n), m1(n), m2(n);
     for (int q = 0; q < T.nq; ++q) {
         legendre_all(p, 2.0L * T.qw[4 * q + 0] - 1, P0, dP0);
@@ -704,9 +705,39 @@ HostTables build_tet_tables(int p) {
             T.B64[((size_t)q * 4 + 1) * np + a] = (double)d0;
             T.B64[((size_t)q * 4 + 2) * np + a] = (double)d1;
             T.B64[((size_t)q * 4 + 3) * np + a] = (double)d2;
+            Bx[((size_t)q * 4 + 0) * n + a] = v;
+            Bx[((size_t)q * 4 + 1) * n + a] = d0;
+            Bx[((size_t)q * 4 + 2) * n + a] = d1;
+            Bx[((size_t)q * 4 + 3) * n + a] = d2;
         }
     }
     derive_layouts(T);
+    // reference matrices of the 13 nonzero entries of W (row r of B for the test
+    // function a, row s for b), and the reference load vector
+    static const int rs[13][2] = {{0, 0}, {0, 1}, {0, 2}, {0, 3}, {1, 1}, {1, 2}, {1, 3},
+                                  {2, 1}, {2, 2}, {2, 3}, {3, 1}, {3, 2}, {3, 3}};
+    const size_t n2p = ((size_t)n * n + 15) / 16 * 16;    // entries padded to whole blocks of 16 (zero)
+    T.Mref.assign(n2p * 16 + n, 0.0);
+    std::vector<long double> acc((size_t)13 * n * n, 0.0L), b0(n, 0.0L);
+    for (int q = 0; q < T.nq; ++q) {
+        const long double w = T.qw[4 * q + 3];
+        const long double *Bq = &Bx[(size_t)q * 4 * n];
+        for (int a = 0; a < n; ++a) {
+            b0[a] += w * Bq[a];
+            for (int k = 0; k < 13; ++k) {
+                const long double wa = w * Bq[rs[k][0] * n + a];
+                long double *row = &acc[((size_t)k * n + a) * n];
+                const long double *bs = Bq + rs[k][1] * n;
+                for (int b = 0; b < n; ++b) row[b] += wa * bs[b];
+            }
+        }
+    }
+    for (int a = 0; a < n; ++a) {
+        for (int b = 0; b < n; ++b)
+            for (int k = 0; k < 13; ++k) T.Mref[(size_t)k * n2p + (size_t)a * n + b] = (double)acc[((size_t)k * n + a) * n + b];
+        T.Mref[n2p * 16 + a] = (double)b0[a];
+    }
+    T.Mref32.assign(T.Mref.begin(), T.Mref.end());
     return T;
 }
 

@@ -51,6 +51,14 @@ struct HostTables {
     // l holds column 16 t + l%16 at points 2 (l/16) and 2 (l/16) + 1 of the
     // K-block, four rows each.
     std::vector<float> Ycf;
+    // Tetrahedra (affine, so W_q = w_q W with one W per element): the reference
+    // matrices M_rs = sum_q w_q B_q[r]^T B_q[s] of the 13 nonzero entries (r, s) of
+    // W, slot-major [16][n*n padded to a multiple of 16] (slots 0..12 in the order
+    // 00 01 02 03 11 12 13 21 22 23 31 32 33, entry a*n + b; slots 13..15 and the
+    // padding zero), then the reference load vector
+    // m0[a] = sum_q w_q phi_a(q); summed in extended precision.
+    std::vector<double> Mref;
+    std::vector<float> Mref32;
 };
 
 // Points of the prism rule `rule` for degree p: qw [nq][4] = (xi1, xi2, zeta,

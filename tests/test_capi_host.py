@@ -234,7 +234,9 @@ def test_tet_host_api():
             assert n >= 1
             for t in range(n):
                 assert L.feint_tet_tile_describe(p, form, t, buf, 32) == 0
-                assert re.fullmatch(rb"(\d+x\d+f?|v\d+)(o\d)?", buf.value), buf.value
+                assert re.fullmatch(rb"(\d+x\d+f?|v\d+|ref[124]s?(e\d+)?)(o\d)?", buf.value), buf.value
+            # FP64 and FP32 start with the reference-matrix kernel (affine elements)
+            assert L.feint_tet_tile_describe(p, form, 0, buf, 32) == 0 and buf.value.startswith(b"ref")
         for form in (2, 3):
             assert L.feint_tet_tile_count(p, form) >= 1
     el = _el(4)
