@@ -13,7 +13,9 @@ stated in the same line.  The default run (mode "suite") adds, as keys of
 configuration: p = 1 at 4096 and 524288 elements, the mixed-degree batch
 replayed from a HIP graph, the p = 3 adjoint, the p = 7 forward and
 adjoint, hexahedra at p = 4..7 (sum factorisation in three directions beside
-the contraction along xi3 only), and the paper's own term (Laplace) on its
+the contraction along xi3 only), tetrahedra at p = 4 (FP64 and FP32 from
+reference matrices; FP32 heads the tetrahedral lines, where the split forms
+integrate point by point and are slower), and the paper's own term (Laplace) on its
 quadrature at its batch sizes for p = 1..7, each with its roofline, its error
 against the oracle and its CPU baseline.
 
@@ -55,7 +57,8 @@ KERNEL_SOURCES = ["paper_1310_1194_amd/csrc/fwd_kernels.h", "paper_1310_1194_amd
                   "paper_1310_1194_amd/csrc/fwd_f64.hip",
                   "paper_1310_1194_amd/csrc/device_common.h", "paper_1310_1194_amd/csrc/tables.cpp",
                   "paper_1310_1194_amd/csrc/fwd_hsf.h", "paper_1310_1194_amd/csrc/hex_factors.h",
-                  "paper_1310_1194_amd/csrc/fwd_hex.hip"]
+                  "paper_1310_1194_amd/csrc/fwd_hex.hip", "paper_1310_1194_amd/csrc/fwd_tref.h",
+                  "paper_1310_1194_amd/csrc/fwd_tet.hip"]
 
 
 def kernel_source_sha() -> str:
@@ -270,7 +273,10 @@ def bench_forward(args, fields=False, kind=None, err_idx=None, cpu_budget=None):
         X = (t(batch.coords), t(batch.D), t(batch.beta), t(batch.c), t(batch.f))
         integrate = F.integrate_raw
     forms = [f for f in args.forms.split(",") if f]
-    headline = HEADLINE if HEADLINE in forms else forms[0]
+    # tetrahedra: the FP32 reference-matrix GEMM is faster than the split forms
+    # (which integrate point by point) at a smaller error, so it heads their line
+    hform = "fp32" if kind == "tet" else HEADLINE
+    headline = hform if hform in forms else forms[0]
     if args.sc and not set(forms) <= {"fp64", "fp32"}:
         raise SystemExit("--sc: the SC variants are compiled for the fp64 and fp32 forms")
 
@@ -344,6 +350,8 @@ def bench_forward(args, fields=False, kind=None, err_idx=None, cpu_budget=None):
         # tile runs (fewer flops for the triangle-point contraction), the roofline numerator
         if costmodel.is_kf_tile(r["tile"]):       # prisms and hexahedra: factorised along the third coordinate
             r["alg_flops_per_element"] = costmodel.f_factored(n, p + 1, q)
+        elif kind == "tet" and costmodel.is_tet_ref_tile(r["tile"]):   # the reference-matrix GEMM
+            r["alg_flops_per_element"] = costmodel.f_tet_reference(n)
         else:
             r["alg_flops_per_element"] = fdom
         r["fdom_equiv_gflops"] = fdom * ne / (r["kernel_ms_mean"] * 1e-3) / 1e9
@@ -411,7 +419,9 @@ def bench_forward(args, fields=False, kind=None, err_idx=None, cpu_budget=None):
                     "unit": "TFLOP/s", "frac": h["gflops_alg"] / 1e3 / PEAK_TFLOPS[headline]}
     npad, nqp = (n + 15) // 16 * 16, (q + 7) // 8 * 8
     kf = costmodel.is_kf_tile(h["tile"])
+    tref = kind == "tet" and costmodel.is_tet_ref_tile(h["tile"])
     hw_flops = (costmodel.kf_mfma_flops(p, rule, n, q) * ne if kf else
+                costmodel.tet_reference_mfma_flops(n) * ne if tref else
                 products * 8.0 * npad * npad * (nqp if products == 3 else q) * ne)
     roofline.update({"traffic": traffic, "kernel_ms": h["kernel_ms_mean"], "flops_per_launch": falg * ne,
                      "fdom_per_launch": fdom * ne,
@@ -419,6 +429,7 @@ def bench_forward(args, fields=False, kind=None, err_idx=None, cpu_budget=None):
                      "alg_bytes_per_launch": alg_bytes,
                      "note": ("algorithmic flops of the triangle-point contraction per element "
                               "(8 n^2 nij + 8 (p+1)^2 nij n + 24 nq ntri + 12 nq n)" if kf else
+                              "algorithmic flops of the reference-matrix GEMM per element (26 n^2 + n)" if tref else
                               "algorithmic flops 8 n^2 nq per element (one product per entry; "
                               "a split form issues three products)") + "; bytes %d in + (n^2+n) outputs" % in_bytes})
     forms_out = {}
@@ -469,8 +480,9 @@ def bench_suite(args):
     """The default run: the p = 4 headline (all four forms) and, as keys of the
     same line, every other configured workload in its own launch
     configuration: p = 1 at 4096 elements (latency-bound) and at 524288 (HBM),
-    the mixed-degree batch replayed from a HIP graph, the p = 3 adjoint and
-    the p = 7 forward (split forms beside FP32 and FP64) and adjoint."""
+    the mixed-degree batch replayed from a HIP graph, the p = 3 adjoint,
+    the p = 7 forward (split forms beside FP32 and FP64) and adjoint,
+    hexahedra at p = 4..7, tetrahedra at p = 4 and the paper's Laplace sweep."""
     import copy
     import torch
 
@@ -510,6 +522,12 @@ def bench_suite(args):
     torch.cuda.empty_cache()
     stage("hex_p4_p7")
     cfg["hex_p4_p7"] = summarise(bench_hex(sub(workload=None, forms="fp64,fp32", steps=steps, warmup=warm)))
+    torch.cuda.empty_cache()
+    stage("tet_p4_393216")
+    cfg["tet_p4_393216"] = summarise(bench_forward(sub(workload="tet_p4_393216", forms="fp64,fp32", steps=steps,
+                                                       warmup=warm),
+                                                   kind="tet", err_idx=np.arange(0, 393216, 96),
+                                                   cpu_budget=min(budget, 2.0)))
     torch.cuda.empty_cache()
     stage("laplace_paper_sweep")
     cfg["laplace_paper_sweep"] = summarise(bench_laplace(sub(workload=None, forms="fp32", steps=steps,

@@ -119,6 +119,26 @@ def f_hex_sumfact(p: int) -> int:
     return 10 * n ** 4 + 38 * n ** 5 + 18 * n ** 6 + 4 * n ** 7
 
 
+def f_tet_reference(n: int) -> int:
+    """Flops per element of the tetrahedral reference-matrix GEMM: the element
+    matrix as a combination of 13 reference matrices (13 multiply-adds per
+    entry) and the load vector as a multiple of one reference vector."""
+    return 26 * n * n + n
+
+
+def tet_reference_mfma_flops(n: int) -> int:
+    """Issued 16x16x4 MFMA flops per element of that GEMM: K = 13 slots padded
+    to 16, n^2 entries padded to a multiple of 16 (full waves of elements)."""
+    return 2 * 16 * ((n * n + 15) // 16 * 16)
+
+
+def is_tet_ref_tile(desc: str) -> bool:
+    """Tile descriptions "refR" (optionally "s", "eE", "oK") name the tetrahedral
+    reference-matrix GEMM."""
+    import re
+    return re.fullmatch(r"ref\d+s?(e\d+)?(o\d)?", desc) is not None
+
+
 def is_sf_tile(desc: str) -> bool:
     """Tile descriptions "sfWw..." name the hexahedral sum factorisation."""
     import re

@@ -159,3 +159,25 @@ def test_hex_sumfact_flops_by_pass():
         assert p == 1 or costmodel.f_factored(n ** 3, n, n ** 3) < 8 * n ** 9
     # the leading term 4 n^7 is already more than half of the work at p = 7
     assert 4 * 8 ** 7 / costmodel.f_hex_sumfact(7) > 0.5
+
+
+def test_tet_reference_gemm_count():
+    """The tetrahedral reference-matrix GEMM: the element block W has 13
+    entries that are not identically zero (column 0 below the diagonal is),
+    so an entry of A takes 13 multiply-adds, and an entry of b one multiply;
+    the count is far below the point-by-point 8 n^2 nq at every degree, and
+    the tile names that select it are recognised."""
+    import numpy as np
+    from paper_1310_1194_amd import costmodel
+    pattern = np.ones((4, 4), dtype=bool)
+    pattern[1:, 0] = False            # W = det J [[c, (K beta)^T], [0, K D K^T]]
+    assert pattern.sum() == 13
+    for p in range(1, 8):
+        n = (p + 1) * (p + 2) * (p + 3) // 6
+        assert costmodel.f_tet_reference(n) == 2 * int(pattern.sum()) * n * n + n
+        assert costmodel.f_tet_reference(n) < 8 * n * n * (p + 2) ** 3 / 8
+        assert costmodel.tet_reference_mfma_flops(n) >= 2 * 13 * n * n
+    for d in ("ref4o2", "ref1o2", "ref1so2", "ref1e16o2", "ref1se16o2", "ref4"):
+        assert costmodel.is_tet_ref_tile(d)
+    for d in ("5x5f", "3x3", "v1o3", "sf4w"):
+        assert not costmodel.is_tet_ref_tile(d)

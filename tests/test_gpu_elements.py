@@ -77,6 +77,39 @@ def test_elem_parity_every_tile(torch_cuda, kind, p, form):
     F.elem_tile_set(kind, p, form, 0)
 
 
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+@pytest.mark.parametrize("p", [3, 4, 7])
+def test_tet_reference_gemm_full_waves(torch_cuda, p, form):
+    """The reference-matrix kernels ("ref...") on 150 tetrahedra: two full
+    waves of 64 elements (nine of 16) and a ragged tail, so that both the
+    full-wave store path and the masked one run at every degree where the
+    every-tile test has fewer elements than a wave."""
+    import paper_1310_1194_amd as F
+    from paper_1310_1194_amd import meshgen
+    batch = meshgen.make_tet_batch(4, 4, 2, amp=0.2, seed=230 + p)
+    batch = batch.subset(np.arange(150))
+    Ar, br, _ = oracle_of("tet", p, batch)
+    X = dev(torch_cuda, batch)
+    ran = 0
+    for tile in range(F.elem_tile_count("tet", p, form)):
+        name = F.elem_tile_describe("tet", p, form, tile)
+        if not name.startswith("ref"):
+            continue
+        F.elem_tile_set("tet", p, form, tile)
+        flush(f"[tet ref] p={p} form={form} tile={name} ne={batch.ne}")
+        A, b = F.integrate_elem_raw("tet", *X, p, form)
+        torch_cuda.cuda.synchronize()
+        gA, mA = rel_errors(A.cpu().numpy(), Ar)
+        gb, mb = rel_errors(b.cpu().numpy(), br)
+        flush(f"    A: {gA:.3e} / {mA:.3e}   b: {gb:.3e} / {mb:.3e}")
+        tg = fp32_global_tol(4 * F.ELEMENTS["tet"][2](p)) if form == "fp32" else TOL[form][0]
+        assert gA <= tg and mA <= TOL[form][1]
+        assert gb <= tg and mb <= TOL[form][1]
+        ran += 1
+    F.elem_tile_set("tet", p, form, 0)
+    assert ran >= 1
+
+
 @pytest.mark.parametrize("p", [1, 2, 3])
 @pytest.mark.parametrize("kind", ["hex", "tet"])
 def test_elem_mapped_points_and_status(torch_cuda, kind, p):
