@@ -435,7 +435,7 @@ def bench_forward(args, fields=False, kind=None, err_idx=None, cpu_budget=None):
     forms_out = {}
     for form, r in results.items():
         forms_out[form] = {k: (float(f"{v:.5g}") if isinstance(v, float) else v) for k, v in r.items()
-                           if not k.endswith("_sample")}
+                           if k not in ("A_sample", "b_sample")}
     line = {
         "metric": "elements/s + GFLOP/s (roofline %) at p=4, plain FP64 vs MFMA form at stated error"
                   + (" (coefficients varying in space, given at the vertices)" if fields else "")
