@@ -282,7 +282,8 @@ feint_status feint_rule_tile_set(int p, feint_form form, feint_rule rule, int ti
 
 // "TMxTN" plus the kernel kind (s staged, sa A operands staged, p pipelined,
 // c shape functions computed per point, f contraction per triangle or plane
-// point, y split form with Y formed on the matrix cores; "vL" vector-ALU kernel with L lanes per element)
+// point, fw the same with two waves per element sharing its point blocks, y split form with Y formed on
+// the matrix cores; "vL" vector-ALU kernel with L lanes per element)
 // and "o2" for a two-waves-per-SIMD register budget.
 static void describe_variant(const FwdVariant &v, char *buf, size_t len) {
     if (v.staged == 3)
@@ -297,7 +298,7 @@ static void describe_variant(const FwdVariant &v, char *buf, size_t len) {
     else
         std::snprintf(buf, len, "%dx%d%s%s", v.tm, v.tn,
                       v.staged == 1 ? "s" : v.staged == 2 ? "sa" : v.staged == 4 ? "p"
-                      : v.staged == 5 ? "c" : v.staged == 6 ? "f" : v.staged == 7 ? "y" : "",
+                      : v.staged == 5 ? "c" : v.staged == 6 ? "f" : v.staged == 7 ? "y" : v.staged == 13 ? "fw" : "",
                       v.minw > 1 ? "o2" : "");
 }
 

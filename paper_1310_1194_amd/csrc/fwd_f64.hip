@@ -1,6 +1,8 @@
 // Forward kernels, FP64 form: compiled variants per degree (the first is the default until the
 // autotuner picks another): vector-ALU kernels at low degree, v_mfma_f64_16x16x4_f64 tiles point by point,
-// and from p = 3 the contraction per triangle point (KF), which is the fastest there.
+// and from p = 3 the contraction per triangle point (KF); "KxTNfw" is that contraction with the waves
+// of an element sharing its point blocks through LDS (KF2), the default from p = 3 where it was
+// measured faster (all but p = 3 in FP32).
 #include "fwd_registry.h"
 
 namespace feint {
@@ -18,6 +20,7 @@ const FwdVariant v2[] = {
     FEINT_K4S(2, double, 2, 1, 8, 2),
     FEINT_KSC(2, double, 2, 2, 1), FEINT_KF_R(2, double, 3, 3, 2, 0)};
 const FwdVariant v3[] = {
+    FEINT_KF2(3, double, 4, 2, 2),
     FEINT_KF_R(3, double, 4, 2, 2, 0),
     FEINT_KF_R(3, double, 4, 1, 2, 0),
     FEINT_KF_R(3, double, 4, 2, 1, 0),
@@ -27,6 +30,7 @@ const FwdVariant v3[] = {
     FEINT_KF_R(3, double, 4, 4, 1, 0),
     FEINT_KSC(3, double, 3, 3, 1)};
 const FwdVariant v4[] = {
+    FEINT_KF2(4, double, 5, 3, 2),
     FEINT_KF_R(4, double, 5, 5, 1, 0),
     FEINT_KF_R(4, double, 5, 3, 1, 0),
     FEINT_KF_R(4, double, 5, 1, 1, 0),
@@ -34,6 +38,7 @@ const FwdVariant v4[] = {
     FEINT_K4U(4, double, 5, 1, 2),
     FEINT_KSC(4, double, 5, 3, 1)};
 const FwdVariant v5[] = {
+    FEINT_KF2(5, double, 3, 2, 2),
     FEINT_KF_R(5, double, 6, 2, 1, 0),
     FEINT_KF_R(5, double, 3, 2, 1, 0),
     FEINT_KF_R(5, double, 6, 1, 1, 0),
@@ -41,12 +46,14 @@ const FwdVariant v5[] = {
     FEINT_K4S(5, double, 8, 1, 4, 2),
     FEINT_KSC(5, double, 8, 2, 1)};
 const FwdVariant v6[] = {
+    FEINT_KF2(6, double, 2, 2, 2),
     FEINT_KF_R(6, double, 7, 1, 1, 0),
     FEINT_KF_R(6, double, 4, 2, 1, 0),
     FEINT_K4U(6, double, 13, 1, 2),
     FEINT_K4S(6, double, 13, 1, 4, 1),
     FEINT_KSC(6, double, 13, 1, 1)};
 const FwdVariant v7[] = {
+    FEINT_KF2(7, double, 2, 2, 2),
     FEINT_KF_R(7, double, 4, 2, 1, 0),
     FEINT_KF_R(7, double, 2, 2, 1, 0),
     FEINT_KF_R(7, double, 4, 1, 1, 0),

@@ -246,4 +246,208 @@ struct KF {
     }
 };
 
+// The same contraction with the element's point blocks shared by the waves
+// that work on it (FP64, FP32).  Where the element has two blocks, a
+// workgroup of four waves takes two elements, two waves each; otherwise it
+// takes one element and its four waves take the blocks in turn.  The waves of
+// an element form W_q and w det J f of its points (one point per lane, the
+// points split between them) into the element's LDS area, the workgroup
+// synchronises once, and each wave then contracts its blocks over all
+// triangle points, reading W from that area.  The point blocks are formed
+// once per element, however many blocks it has, and before any accumulator
+// is live, so a block shape can be chosen for two waves per SIMD without
+// repeating the FP64 geometry.
+template <int P, typename T, int TMK, int TN, int R = 0, class G = PrismGeo>
+struct KF2 {
+    typedef KF<P, T, TMK, TN, R, G> F;
+    static constexpr int N = F::N, NK = F::NK, NTRI = F::NTRI, TT = F::TT, TP = F::TP, NQ = F::NQ, NIJ = F::NIJ;
+    static constexpr int BM = F::BM, BK = F::BK, BN = F::BN, NB = F::NBLK;   // blocks of an element
+    static constexpr int WPE = NB == 2 ? 2 : 4;        // waves per element
+    static constexpr int EPW = 4 / WPE;                // elements per workgroup
+    static constexpr int EPI = 1, NBLK = WPE;          // work items: one per wave
+    static constexpr bool SPARE = F::SPARE;
+    static constexpr int LCT = F::LCT, LCL = F::LCL;
+    typedef typename AccT<T>::type V4;
+
+    struct ElemArea {
+        T W[NQ][WROW<T>::value];      // point q in the rule's order (q = m nij + ij)
+        double sf[NQ];
+    };
+    struct Smem { ElemArea el[EPW]; };
+
+    template <int TMV, int TNV, bool LB>
+    __device__ static void body(const FwdParams &prm, int64_t slot, int bi, int bj, const ElemArea &ea) {
+        const int lane = threadIdx.x & 63;
+        const int i16 = lane & 15, kg = lane >> 4;
+        const int k0 = bi * TMK, tt = bj / BK, kp0 = (bj - tt * BK) * TN;
+        const int64_t e = elem_of(prm, slot);
+        const T *tau = sizeof(T) == 8 ? (const T *)(const void *)prm.tau64 : (const T *)(const void *)prm.tau32;
+        const T *lam = sizeof(T) == 8 ? (const T *)(const void *)prm.lam : (const T *)(const void *)prm.lam32;
+        T lr[TMV][NK];
+#pragma unroll
+        for (int k = 0; k < TMV; ++k)
+#pragma unroll
+            for (int m = 0; m < NK; ++m) lr[k][m] = lam[(kg * NK + k0 + k) * NK + m];
+        const int tcol = tt * 16 + i16;
+        const bool lcol = LB && i16 == LCL;
+        const T lsel = (lcol && kg == 0) ? (T)1 : (T)0;
+        const bool bblk = G::LOAD && !SPARE && kp0 == 0 && tt == 0;
+        const double *l64 = prm.lam;
+        double bacc[SPARE ? 1 : TMV][TT];
+#pragma unroll
+        for (int k = 0; k < (SPARE ? 1 : TMV); ++k)
+#pragma unroll
+            for (int ti = 0; ti < TT; ++ti) bacc[k][ti] = 0.0;
+        typedef const __attribute__((address_space(4))) T CT;
+        const CT *lv = (const CT *)(lam + (size_t)kp0 * NK), *ld = (const CT *)(lam + (size_t)(3 * NK + kp0) * NK);
+        V4 acc[TMV][TT][TNV];
+#pragma unroll
+        for (int k = 0; k < TMV; ++k)
+#pragma unroll
+            for (int ti = 0; ti < TT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < TNV; ++tj) acc[k][ti][tj] = V4{0, 0, 0, 0};
+        auto fetch = [&](int ij, T (&ta)[TT], T (&tb)[4]) {
+#pragma unroll
+            for (int ti = 0; ti < TT; ++ti) ta[ti] = tau[((size_t)ij * 4 + kg) * TP + ti * 16 + i16];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) tb[s] = tau[((size_t)ij * 4 + s) * TP + tcol];
+        };
+        T ta[TT], tb[4];
+        fetch(0, ta, tb);
+        for (int ij = 0; ij < NIJ; ++ij) {
+            T tan[TT], tbn[4];
+            fetch(ij + 1 < NIJ ? ij + 1 : ij, tan, tbn);
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (!SPARE) {
+                if (bblk) {
+#pragma unroll
+                    for (int k = 0; k < TMV; ++k) {
+                        double sk = 0.0;
+#pragma unroll
+                        for (int m = 0; m < NK; ++m) sk += l64[(k0 + k) * NK + m] * ea.sf[m * NIJ + ij];
+#pragma unroll
+                        for (int ti = 0; ti < TT; ++ti)
+                            bacc[k][ti] += prm.tau64[((size_t)ij * 4) * TP + ti * 16 + i16] * sk;
+                    }
+                }
+            }
+            T u[NK], v[NK], sfm[NK];
+#pragma unroll
+            for (int m = 0; m < NK; ++m) {
+                const T *wr = &ea.W[m * NIJ + ij][4 * kg];
+                u[m] = wr[0] * tb[0] + wr[1] * tb[1] + wr[2] * tb[2];
+                v[m] = wr[3] * tb[3];
+                sfm[m] = LB ? lsel * (T)ea.sf[m * NIJ + ij] : (T)0;
+            }
+#pragma unroll
+            for (int tj = 0; tj < TNV; ++tj) {
+                T y[NK];
+#pragma unroll
+                for (int m = 0; m < NK; ++m) {
+                    const T yv = lv[tj * NK + m] * u[m] + ld[tj * NK + m] * v[m];
+                    y[m] = (LB && tj == 0) ? yv + sfm[m] : yv;
+                }
+#pragma unroll
+                for (int k = 0; k < TMV; ++k) {
+                    T z = (T)0;
+#pragma unroll
+                    for (int m = 0; m < NK; ++m) z += lr[k][m] * y[m];
+#pragma unroll
+                    for (int ti = 0; ti < TT; ++ti) acc[k][ti][tj] = mfma4(ta[ti], z, acc[k][ti][tj]);
+                }
+            }
+#pragma unroll
+            for (int ti = 0; ti < TT; ++ti) ta[ti] = tan[ti];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) tb[s] = tbn[s];
+        }
+        T *Aout = (T *)prm.A + offA_of(prm, e, N);
+        T *bout = (T *)prm.b + offb_of(prm, e, N);
+#pragma unroll
+        for (int k = 0; k < TMV; ++k)
+#pragma unroll
+            for (int ti = 0; ti < TT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < TNV; ++tj)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int tr = ti * 16 + acc_row<T>(lane, r);
+                        if (tr >= NTRI) continue;
+                        const int row = (k0 + k) * NTRI + tr;
+                        if (tj == 0 && lcol)
+                            bout[row] = acc[k][ti][tj][r];
+                        else if (tcol < NTRI)
+                            Aout[(size_t)row * N + (kp0 + tj) * NTRI + tcol] = acc[k][ti][tj][r];
+                    }
+        if constexpr (!SPARE) {
+            if (bblk && kg == 0) {
+#pragma unroll
+                for (int k = 0; k < TMV; ++k)
+#pragma unroll
+                    for (int ti = 0; ti < TT; ++ti)
+                        if (ti * 16 + i16 < NTRI) bout[(k0 + k) * NTRI + ti * 16 + i16] = (T)bacc[k][ti];
+            }
+        }
+    }
+
+    template <int TMV, int TNV>
+    __device__ static void with_lb(bool lb, const FwdParams &prm, int64_t slot, int bi, int bj, const ElemArea &ea) {
+        if (lb) body<TMV, TNV, true>(prm, slot, bi, bj, ea);
+        else body<TMV, TNV, false>(prm, slot, bi, bj, ea);
+    }
+
+    // Every wave of the workgroup reaches the barrier; LIVE is false for the
+    // waves past the batch (the second element of the last workgroup).  WV is
+    // the wave's index among its element's waves.
+    __device__ static void run_coop(const FwdParams &prm, int64_t slot, int wv, int wave, bool live, Smem &sm) {
+        const int lane = threadIdx.x & 63;
+        ElemArea &ea = sm.el[wave / WPE];
+        if (live) {
+            const int64_t e = elem_of(prm, slot);
+            typename G::Elem E;
+            G::load(prm, e, E);
+            for (int qc = wv * 64; qc < NQ; qc += WPE * 64) {
+                const int q = qc + lane;
+                if (q < NQ) {
+                    const double *qp = prm.qw + 4 * q;
+                    double W[16], sf;
+                    G::coeffs(prm, e, qp, E);
+                    const double det = G::block(E, qp, W, sf);
+                    if (!(det > 0.0) && prm.status) atomicOr(prm.status, 1u);
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) ea.W[q][k] = (T)W[k];
+                    ea.sf[q] = sf;
+                    if (prm.xq) {
+                        double x[3];
+                        G::map(E, qp, x);
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) prm.xq[(e * NQ + q) * 3 + d] = x[d];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (!live) return;
+        if constexpr (NB == WPE) {
+            one_block(prm, slot, wv, ea);              // one block per wave: no loop
+        } else {
+            for (int blk = wv; blk < NB; blk += WPE) one_block(prm, slot, blk, ea);
+        }
+    }
+    __device__ static void one_block(const FwdParams &prm, int64_t slot, int blk, const ElemArea &ea) {
+        constexpr int TML = NK - (BM - 1) * TMK, TNL = NK - (BK - 1) * TN;
+        const int bi = blk / BN, bj = blk % BN;
+        const bool lastm = TML != TMK && bi == BM - 1, lastn = TNL != TN && bj % BK == BK - 1;
+        const bool lb = G::LOAD && SPARE && bj % BK == 0 && bj / BK == LCT;
+        if (lastm) {
+            if (lastn) with_lb<TML, TNL>(lb, prm, slot, bi, bj, ea);
+            else with_lb<TML, TN>(lb, prm, slot, bi, bj, ea);
+        } else {
+            if (lastn) with_lb<TMK, TNL>(lb, prm, slot, bi, bj, ea);
+            else with_lb<TMK, TN>(lb, prm, slot, bi, bj, ea);
+        }
+    }
+};
+
 }  // namespace feint

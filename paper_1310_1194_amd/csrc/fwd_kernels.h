@@ -633,6 +633,18 @@ __host__ __device__ inline int64_t items_for(int64_t ne) {
     return (ne + KER::EPI - 1) / KER::EPI * KER::NBLK;
 }
 
+// Cooperative launch: workgroup of 4 waves, one work item each, where the
+// waves of a workgroup share LDS across a barrier; every wave runs the kernel
+// (those past the batch with live = false) so that every wave reaches it.
+template <class KER, int MINW>
+__global__ __launch_bounds__(256, MINW) void fwd_coop(FwdParams prm) {
+    __shared__ typename KER::Smem sm;
+    const int wave = wave_uniform(threadIdx.x >> 6);
+    const int64_t item = (int64_t)blockIdx.x * 4 + wave;
+    const bool live = item < items_for<KER>(prm.ne);
+    KER::run_coop(prm, item / KER::NBLK, (int)(item % KER::NBLK), wave, live, sm);
+}
+
 // Grid-stride-free direct launch: workgroup of 4 waves, one work item each.
 template <class KER, int MINW>
 __global__ __launch_bounds__(256, MINW) void fwd_direct(FwdParams prm) {

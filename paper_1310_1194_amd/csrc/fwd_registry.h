@@ -21,6 +21,13 @@ void launch_direct(const FwdParams &prm, hipStream_t s) {
 }
 
 template <class KER, int MINW>
+void launch_coop(const FwdParams &prm, hipStream_t s) {
+    const int64_t items = items_for<KER>(prm.ne);
+    const int64_t blocks = (items + 3) / 4;
+    hipLaunchKernelGGL((fwd_coop<KER, MINW>), dim3((unsigned)blocks), dim3(256), 0, s, prm);
+}
+
+template <class KER, int MINW>
 void launch_staged(const FwdParams &prm, hipStream_t s) {
     const int64_t items = items_for<KER>(prm.ne);
     const int64_t blocks = (items + 3) / 4;
@@ -92,6 +99,9 @@ int64_t items_of(int64_t ne) { return items_for<KER>(ne); }
 // TMK row blocks k and TN column tiles per wave.
 #define FEINT_KF_R(P, T, TMK, TN, W, R) \
     FwdVariant{TMK, TN, 6, W, &launch_direct<KF<P, T, TMK, TN, R>, W>, &items_of<KF<P, T, TMK, TN, R>>}
+// the same, two waves per element sharing its point blocks through LDS (staged = 13)
+#define FEINT_KF2(P, T, TMK, TN, W) \
+    FwdVariant{TMK, TN, 13, W, &launch_coop<KF2<P, T, TMK, TN>, W>, &items_of<KF2<P, T, TMK, TN>>}
 #define FEINT_KF_HEX(P, T, TMK, TN, W)                                        \
     FwdVariant{TMK, TN, 6, W, &launch_direct<KF<P, T, TMK, TN, 0, HexGeo>, W>, \
                &items_of<KF<P, T, TMK, TN, 0, HexGeo>>}
