@@ -525,7 +525,7 @@ def bench_suite(args):
     torch.cuda.empty_cache()
     stage("tet_p4_393216")
     cfg["tet_p4_393216"] = summarise(bench_forward(sub(workload="tet_p4_393216", forms="fp64,fp32", steps=steps,
-                                                       warmup=warm),
+                                                       warmup=warm, rule="collapsed", sc=False),
                                                    kind="tet", err_idx=np.arange(0, 393216, 96),
                                                    cpu_budget=min(budget, 2.0)))
     torch.cuda.empty_cache()

@@ -100,8 +100,9 @@ int64_t items_of(int64_t ne) { return items_for<KER>(ne); }
 #define FEINT_KF_R(P, T, TMK, TN, W, R) \
     FwdVariant{TMK, TN, 6, W, &launch_direct<KF<P, T, TMK, TN, R>, W>, &items_of<KF<P, T, TMK, TN, R>>}
 // the same, two waves per element sharing its point blocks through LDS (staged = 13)
-#define FEINT_KF2(P, T, TMK, TN, W) \
-    FwdVariant{TMK, TN, 13, W, &launch_coop<KF2<P, T, TMK, TN>, W>, &items_of<KF2<P, T, TMK, TN>>}
+#define FEINT_KF2_R(P, T, TMK, TN, W, R) \
+    FwdVariant{TMK, TN, 13, W, &launch_coop<KF2<P, T, TMK, TN, R>, W>, &items_of<KF2<P, T, TMK, TN, R>>}
+#define FEINT_KF2(P, T, TMK, TN, W) FEINT_KF2_R(P, T, TMK, TN, W, 0)
 #define FEINT_KF_HEX(P, T, TMK, TN, W)                                        \
     FwdVariant{TMK, TN, 6, W, &launch_direct<KF<P, T, TMK, TN, 0, HexGeo>, W>, \
                &items_of<KF<P, T, TMK, TN, 0, HexGeo>>}
