@@ -27,6 +27,7 @@ const FwdVariant v3[] = {
     FEINT_KV(3, float, 40, 2),
     FEINT_KSC(3, float, 3, 3, 1)};
 const FwdVariant v4[] = {
+    FEINT_KF2(4, float, 3, 5, 2),
     FEINT_KF2(4, float, 5, 3, 2),
     FEINT_KF_R(4, float, 5, 3, 1, 0),
     FEINT_KF_R(4, float, 5, 5, 1, 0),
