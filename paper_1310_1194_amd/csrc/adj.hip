@@ -441,6 +441,148 @@ struct KFA {
     }
 };
 
+// The same adjoint with the chain rule taken once per point: a workgroup
+// of four waves takes one element, its waves take the element's blocks in
+// turn and add each block's share of S_q into one LDS array of the element's
+// points (LDS atomics: the blocks' shares of a point come from different
+// waves), the workgroup synchronises, and the chain rule then runs once per
+// point over all 256 lanes, where the blocks of the one-wave kernel each run
+// it on their share.  The 32 gradient components are summed across the waves
+// through LDS and written by one wave: no atomics in global memory.
+template <int P, typename T, int TK, int TB, int R = 0>
+struct KFA2 {
+    typedef KFA<P, T, TK, TB, R> F;
+    typedef typename F::Base Base;
+    static constexpr int N = F::N, NQ = F::NQ, NK = F::NK, NTRI = F::NTRI, TT = F::TT, TP = F::TP, KS = F::KS;
+    static constexpr int NIJ = F::NIJ, NCT = F::NCT, BB = F::BB, NB = F::NBLK;
+    static constexpr int NBLK = 4;                 // work items per element: the workgroup's waves
+    static constexpr int SR = 17;                  // row stride of S (doubles)
+    typedef typename AccT<T>::type V4;
+    typedef const __attribute__((address_space(4))) T CT;
+
+    struct Smem {
+        double S[NQ][SR];                          // S_q[r][s] at 4 r + s
+        double red[4][32];
+    };
+
+    __device__ static void run_coop(const AdjParams &prm, int64_t e, int wv, int wave, bool live, Smem &sm) {
+        (void)wave;
+        const int lane = threadIdx.x & 63;
+        const int i16 = lane & 15, kg = lane >> 4;
+        for (int i = threadIdx.x; i < NQ * SR; i += 256) (&sm.S[0][0])[i] = 0.0;
+        __syncthreads();
+        if (live) {
+            const T *Ge = (const T *)prm.G + e * (int64_t)N * N;
+            const T *tau = (const T *)prm.tau;
+            const CT *lam = (const CT *)prm.lamT;
+            const bool rl = (i16 & 3) == 3;
+            for (int blk = wv; blk < NB; blk += 4) {
+                const int bk = blk / BB, bc = blk % BB;
+                const int k0 = bk * TK, c0 = bc * TB;
+                T gf[TK][KS][TB];
+#pragma unroll
+                for (int k = 0; k < TK; ++k)
+#pragma unroll
+                    for (int st = 0; st < KS; ++st)
+#pragma unroll
+                        for (int tb = 0; tb < TB; ++tb) {
+                            const int c = c0 + tb, kp = c / TT, tp = (c % TT) * 16 + i16, t = 4 * st + kg;
+                            gf[k][st][tb] = (k0 + k < NK && c < NCT && t < NTRI && tp < NTRI)
+                                                ? Ge[(size_t)((k0 + k) * NTRI + t) * N + kp * NTRI + tp] : (T)0;
+                        }
+                for (int g4 = 0; g4 < NIJ; g4 += 4) {
+                    const int ijc = g4 + (i16 >> 2);
+                    const bool ijok = ijc < NIJ;
+                    V4 h[TK][TB];
+#pragma unroll
+                    for (int k = 0; k < TK; ++k)
+#pragma unroll
+                        for (int tb = 0; tb < TB; ++tb) h[k][tb] = V4{0, 0, 0, 0};
+#pragma unroll
+                    for (int st = 0; st < KS; ++st) {
+                        const T tv = ijok ? tau[((size_t)ijc * 4 + (i16 & 3)) * TP + 4 * st + kg] : (T)0;
+#pragma unroll
+                        for (int k = 0; k < TK; ++k)
+#pragma unroll
+                            for (int tb = 0; tb < TB; ++tb) h[k][tb] = mfma4(gf[k][st][tb], tv, h[k][tb]);
+                    }
+                    T tb4[TB][4];
+#pragma unroll
+                    for (int tb = 0; tb < TB; ++tb)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int tp = ((c0 + tb) % TT) * 16 + acc_row<T>(lane, j);
+                            tb4[tb][j] = ijok ? tau[((size_t)ijc * 4 + (i16 & 3)) * TP + tp] : (T)0;
+                        }
+                    for (int m = 0; m < NK; ++m) {
+                        V4 tacc = V4{0, 0, 0, 0};
+#pragma unroll
+                        for (int tb = 0; tb < TB; ++tb) {
+                            if (c0 + tb >= NCT) continue;
+                            const int kp = (c0 + tb) / TT;
+                            const T lb = rl ? lam[(size_t)(3 * NK + kp) * NK + m] : lam[(size_t)kp * NK + m];
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) {
+                                T hh = (T)0;
+#pragma unroll
+                                for (int k = 0; k < TK; ++k) {
+                                    if (k0 + k >= NK) continue;
+                                    const T lr = rl ? lam[(size_t)(3 * NK + k0 + k) * NK + m] : lam[(size_t)(k0 + k) * NK + m];
+                                    hh += lr * h[k][tb][j];
+                                }
+                                tacc = mfma4(hh, tb4[tb][j] * lb, tacc);
+                            }
+                        }
+                        // the diagonal 4x4 blocks (point = point') are this block's share of S_q
+                        if (ijok) {
+                            const int q = m * NIJ + ijc;
+                            if (sizeof(T) == 8) {
+                                const int pt = i16 >> 2;        // lane holds rows 4 jj + kg: point jj, r = kg
+                                const double v = pt == 0 ? tacc[0] : pt == 1 ? tacc[1] : pt == 2 ? tacc[2] : tacc[3];
+                                atomicAdd(&sm.S[q][4 * kg + (i16 & 3)], v);
+                            } else if (kg == (i16 >> 2)) {     // lane holds rows 4 kg + jj: point kg, r = jj
+#pragma unroll
+                                for (int jj = 0; jj < 4; ++jj) atomicAdd(&sm.S[q][4 * jj + (i16 & 3)], (double)tacc[jj]);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (live) {
+            ElemIn E;
+            load_elem(prm.coords, prm.D, prm.beta, prm.c, prm.f, e, E);
+            double gacc = 0.0;
+            for (int q0 = wv * 64; q0 < NQ; q0 += 256) {
+                double gr[32];
+#pragma unroll
+                for (int k = 0; k < 32; ++k) gr[k] = 0.0;
+                const int q = q0 + lane;
+                if (q < NQ) {
+                    double S[16];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) S[k] = sm.S[q][k];
+                    Base::chain_rule(prm, E, q, S, true, e, gr);
+                }
+                gacc += Base::reduce_scatter32(gr, lane);
+            }
+            if ((lane & 1) == 0) sm.red[wv][lane >> 1] = gacc;
+        }
+        __syncthreads();
+        if (live && wv == 0 && lane < 32) {
+            // component c: vertices 0..17, D 18..26, beta 27..29, c 30, f 31
+            const int c = lane;
+            const double g = sm.red[0][c] + sm.red[1][c] + sm.red[2][c] + sm.red[3][c];
+            double *dst = c < 18 ? prm.dX + 18 * e + c
+                        : c < 27 ? prm.dD + 9 * e + (c - 18)
+                        : c < 30 ? prm.dbeta + 3 * e + (c - 27)
+                        : c == 30 ? prm.dc + e : prm.df + e;
+            *dst = g;
+        }
+    }
+};
+
 template <class KER, int MINW = 1>
 __global__ __launch_bounds__(256, MINW) void adj_direct(AdjParams prm) {
     __shared__ typename KER::Smem sm;
@@ -458,6 +600,15 @@ __global__ void zero_f64(double *p, int64_t n) {
 namespace {
 
 template <class KER, int MINW = 1>
+__global__ __launch_bounds__(256, MINW) void adj_coop(AdjParams prm) {
+    __shared__ typename KER::Smem sm;
+    const int wave = wave_uniform(threadIdx.x >> 6);
+    const int64_t item = (int64_t)blockIdx.x * 4 + wave;
+    const bool live = item < prm.ne * KER::NBLK;     // the same for the four waves of an element
+    KER::run_coop(prm, item / KER::NBLK, (int)(item % KER::NBLK), wave, live, sm);
+}
+
+template <class KER, int MINW = 1>
 feint_status launch_adj(const AdjParams &prm, hipStream_t s) {
     if (KER::ATOMIC) {
         double *outs[5] = {prm.dX, prm.dD, prm.dbeta, prm.dc, prm.df};
@@ -473,6 +624,15 @@ feint_status launch_adj(const AdjParams &prm, hipStream_t s) {
     return FEINT_OK;
 }
 
+// one workgroup per element, every wave of it reaching the barriers
+template <class KER, int MINW = 1>
+feint_status launch_adj_coop(const AdjParams &prm, hipStream_t s) {
+    const int64_t blocks = (prm.ne * KER::NBLK + 3) / 4;
+    if (blocks > 0x7fffffffLL) return FEINT_ERR_TOO_LARGE;
+    hipLaunchKernelGGL((adj_coop<KER, MINW>), dim3((unsigned)blocks), dim3(256), 0, s, prm);
+    return FEINT_OK;
+}
+
 // Compiled block shapes (TA x TB 16x16 tiles of G per wave, or for the
 // factorised kernel TK row indices k by TB column tiles) per degree and
 // quadrature rule (the same shapes for both rules, so one choice per (degree,
@@ -482,11 +642,14 @@ struct AdjVariant {
     int ta, tb;
     feint_status (*launch)(const AdjParams &, hipStream_t);
     int fact;           // 1: factorised along zeta (KFA, TA = row indices k, TB = column tiles),
-                        // 2: the same with a two-waves-per-SIMD register budget
+                        // 2: the same with a two-waves-per-SIMD register budget, 3 (4): the same with
+                        // the chain rule shared by the waves of an element (KFA2; 4 at two waves per SIMD)
 };
 #define FEINT_ADJ(P, T, TA, TB) AdjVariant{TA, TB, &launch_adj<Adj<P, T, TA, TB, R>>, 0}
 #define FEINT_ADJF(P, T, TK, TB) AdjVariant{TK, TB, &launch_adj<KFA<P, T, TK, TB, R>>, 1}
 #define FEINT_ADJF2(P, T, TK, TB) AdjVariant{TK, TB, &launch_adj<KFA<P, T, TK, TB, R>, 2>, 2}
+#define FEINT_ADJW(P, T, TK, TB) AdjVariant{TK, TB, &launch_adj_coop<KFA2<P, T, TK, TB, R>>, 3}
+#define FEINT_ADJW2(P, T, TK, TB) AdjVariant{TK, TB, &launch_adj_coop<KFA2<P, T, TK, TB, R>, 2>, 4}
 
 template <typename T, int R>
 const AdjVariant *adj_variants_of(int p, int *count) {
@@ -494,24 +657,26 @@ const AdjVariant *adj_variants_of(int p, int *count) {
     static const AdjVariant v2[] = {FEINT_ADJ(2, T, 2, 2), FEINT_ADJ(2, T, 2, 1), FEINT_ADJF(2, T, 3, 3)};
     // from p = 3 the factorised kernel ("f", "fo2" with two waves per SIMD) first, in the
     // order measured per form (131072 elements at p = 3 and 4, 16384 at p = 5 and 7); the
-    // same shapes for both forms
+    // same shapes for both forms; from p = 5 the one with the chain rule shared by the waves
+    // of an element ("fw") first (p = 7: 1.4x FP64, 2.0x FP32), at p = 3 and 4 it is slower
     static const AdjVariant v3d[] = {FEINT_ADJF2(3, T, 4, 2), FEINT_ADJ(3, T, 3, 3), FEINT_ADJF(3, T, 4, 2),
                                      FEINT_ADJF(3, T, 4, 4), FEINT_ADJ(3, T, 3, 1), FEINT_ADJ(3, T, 3, 2),
-                                     FEINT_ADJF2(3, T, 4, 1)};
+                                     FEINT_ADJF2(3, T, 4, 1), FEINT_ADJW2(3, T, 4, 2)};
     static const AdjVariant v3f[] = {FEINT_ADJF2(3, T, 4, 2), FEINT_ADJF(3, T, 4, 4), FEINT_ADJF(3, T, 4, 2),
                                      FEINT_ADJ(3, T, 3, 3), FEINT_ADJ(3, T, 3, 1), FEINT_ADJ(3, T, 3, 2),
-                                     FEINT_ADJF2(3, T, 4, 1)};
+                                     FEINT_ADJF2(3, T, 4, 1), FEINT_ADJW2(3, T, 4, 2)};
     static const AdjVariant v4[] = {FEINT_ADJF2(4, T, 5, 1), FEINT_ADJF(4, T, 5, 1), FEINT_ADJF(4, T, 5, 2),
-                                    FEINT_ADJ(4, T, 5, 2), FEINT_ADJ(4, T, 5, 1), FEINT_ADJ(4, T, 3, 3)};
-    static const AdjVariant v5d[] = {FEINT_ADJF(5, T, 6, 2), FEINT_ADJF(5, T, 6, 1), FEINT_ADJ(5, T, 8, 2),
+                                    FEINT_ADJ(4, T, 5, 2), FEINT_ADJ(4, T, 5, 1), FEINT_ADJ(4, T, 3, 3),
+                                    FEINT_ADJW(4, T, 5, 1)};
+    static const AdjVariant v5d[] = {FEINT_ADJW(5, T, 6, 1), FEINT_ADJF(5, T, 6, 2), FEINT_ADJF(5, T, 6, 1), FEINT_ADJ(5, T, 8, 2),
                                      FEINT_ADJ(5, T, 4, 2), FEINT_ADJ(5, T, 8, 1)};
-    static const AdjVariant v5f[] = {FEINT_ADJF(5, T, 6, 1), FEINT_ADJF(5, T, 6, 2), FEINT_ADJ(5, T, 8, 2),
+    static const AdjVariant v5f[] = {FEINT_ADJW(5, T, 6, 1), FEINT_ADJF(5, T, 6, 1), FEINT_ADJF(5, T, 6, 2), FEINT_ADJ(5, T, 8, 2),
                                      FEINT_ADJ(5, T, 4, 2), FEINT_ADJ(5, T, 8, 1)};
-    static const AdjVariant v6[] = {FEINT_ADJF(6, T, 7, 1), FEINT_ADJF(6, T, 4, 2), FEINT_ADJ(6, T, 7, 2),
+    static const AdjVariant v6[] = {FEINT_ADJW(6, T, 7, 1), FEINT_ADJF(6, T, 7, 1), FEINT_ADJF(6, T, 4, 2), FEINT_ADJ(6, T, 7, 2),
                                     FEINT_ADJ(6, T, 7, 1), FEINT_ADJ(6, T, 13, 1)};
-    static const AdjVariant v7d[] = {FEINT_ADJF(7, T, 8, 1), FEINT_ADJF(7, T, 4, 2), FEINT_ADJ(7, T, 6, 3),
+    static const AdjVariant v7d[] = {FEINT_ADJW(7, T, 8, 1), FEINT_ADJF(7, T, 8, 1), FEINT_ADJF(7, T, 4, 2), FEINT_ADJ(7, T, 6, 3),
                                      FEINT_ADJ(7, T, 9, 2), FEINT_ADJ(7, T, 6, 2), FEINT_ADJ(7, T, 9, 1)};
-    static const AdjVariant v7f[] = {FEINT_ADJF(7, T, 8, 1), FEINT_ADJF(7, T, 4, 2), FEINT_ADJ(7, T, 6, 2),
+    static const AdjVariant v7f[] = {FEINT_ADJW(7, T, 8, 1), FEINT_ADJF(7, T, 8, 1), FEINT_ADJF(7, T, 4, 2), FEINT_ADJ(7, T, 6, 2),
                                      FEINT_ADJ(7, T, 9, 2), FEINT_ADJ(7, T, 6, 3), FEINT_ADJ(7, T, 9, 1)};
     static_assert(sizeof v3d == sizeof v3f && sizeof v5d == sizeof v5f && sizeof v7d == sizeof v7f,
                   "one count per degree for both forms");
@@ -639,7 +804,8 @@ feint_status feint_adjoint_tile_describe(int p, feint_form form, int tile, char 
     int cnt = 0;
     const AdjVariant *v = adj_variants(form, p, &cnt);
     if (!buf || len == 0 || tile < 0 || tile >= cnt) return FEINT_ERR_INVALID_ARG;
-    std::snprintf(buf, len, "%dx%d%s%s", v[tile].ta, v[tile].tb, v[tile].fact ? "f" : "", v[tile].fact == 2 ? "o2" : "");
+    std::snprintf(buf, len, "%dx%d%s%s", v[tile].ta, v[tile].tb,
+                  v[tile].fact >= 3 ? "fw" : v[tile].fact ? "f" : "", v[tile].fact == 2 || v[tile].fact == 4 ? "o2" : "");
     return FEINT_OK;
 }
 

@@ -80,7 +80,7 @@ def test_adjoint_tiles():
             assert L.feint_adjoint_tile_get(p, form) == 0
             for t in range(n):
                 assert L.feint_adjoint_tile_describe(p, form, t, buf, 16) == 0
-                assert re.fullmatch(rb"\d+x\d+(f|fo2)?", buf.value)
+                assert re.fullmatch(rb"\d+x\d+(f|fo2|fw|fwo2)?", buf.value)
             assert L.feint_adjoint_tile_set(p, form, n) == -1
             assert L.feint_adjoint_tile_describe(p, form, n, buf, 16) == -1
         for form in (2, 3):          # split forms have no adjoint
