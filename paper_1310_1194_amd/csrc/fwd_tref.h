@@ -11,18 +11,22 @@
 // point-by-point product -- the same sum in another order (the oracle still
 // integrates point by point).
 //
-// A wave owns 64 (or 16, 32) elements.  Over a batch of elements the separated sum is a
-// GEMM, A[(e)][(a,b)] = sum_k W_e[k] M_k[(a,b)] with K = 13 slots padded to 16:
-// each lane forms one element's W and stages it in the wave's LDS slice, the
-// lanes then pick up their 16x16x4 MFMA A fragments (a tile of 16 elements x
-// 4 K-steps per row tile) once, and for every 16-entry column tile the wave loads the B
-// fragments (M, slot-major, 16 consecutive entries per K row, the next tile's
-// in flight during the current MFMAs) and issues 16 MFMAs; accumulator rows are
-// elements, so 16 lanes store 16 consecutive entries of one element.  Stores
-// and fragment loads go through buffer resources: a wave-uniform base, one
-// fixed 32-bit offset per lane and row, the tile's offset in a scalar register,
-// so the loop carries no per-lane address arithmetic.  The load vector
-// b[e][a] = sf_e m0[a] follows.
+// A wave owns EPW (64, 32 or 16) elements.  Over a batch of elements the
+// separated sum is a GEMM, A[(e)][(a,b)] = sum_k W_e[k] M_k[(a,b)] with K = 13
+// slots padded to 16: each lane forms one element's W and stages it in the
+// wave's LDS slice, the lanes pick up their 16x16x4 MFMA A fragments (16
+// elements x 4 K-steps per row tile of 16 elements) once, and for every
+// 16-entry column tile the wave loads the B fragments (M, slot-major, 16
+// consecutive entries per K row, the next tile's in flight during the current
+// MFMAs) and issues 4 MFMAs per row tile.  RTP row tiles take one pass over the
+// column tiles before the next RTP (one: the wave's writes stay within 16
+// element rows at a time); accumulator rows are elements, so 16 lanes store 16
+// consecutive entries of one element, or with STG four column tiles go
+// through LDS first and each store writes 64 consecutive entries of one
+// element.  Stores and fragment loads go through buffer resources: a
+// wave-uniform base, one fixed 32-bit offset per lane and row, the tile's
+// offset in a scalar register, so the loop carries no per-lane address
+// arithmetic.  The load vector b[e][a] = sf_e m0[a] follows.
 #pragma once
 #include "fwd_kernels.h"
 
