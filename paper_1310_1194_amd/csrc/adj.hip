@@ -441,42 +441,46 @@ struct KFA {
     }
 };
 
-// The same adjoint with the chain rule taken once per point: a workgroup
-// of four waves takes one element, its waves take the element's blocks in
-// turn and add each block's share of S_q into one LDS array of the element's
-// points (LDS atomics: the blocks' shares of a point come from different
-// waves), the workgroup synchronises, and the chain rule then runs once per
-// point over all 256 lanes, where the blocks of the one-wave kernel each run
-// it on their share.  The 32 gradient components are summed across the waves
-// through LDS and written by one wave: no atomics in global memory.
+// The same adjoint with the chain rule taken once per point: where the
+// element has two blocks a workgroup of four waves takes two elements, two
+// waves each, otherwise one element and its four waves take the blocks in
+// turn.  Each block's share of S_q is added into one LDS array of the
+// element's points (LDS atomics: the blocks' shares of a point come from
+// different waves), the workgroup synchronises, and the chain rule then runs
+// once per point on the element's waves, where the blocks of the one-wave
+// kernel each run it on their share.  The 32 gradient components are summed
+// across the element's waves through LDS and written by one wave: no atomics
+// in global memory.
 template <int P, typename T, int TK, int TB, int R = 0>
 struct KFA2 {
     typedef KFA<P, T, TK, TB, R> F;
     typedef typename F::Base Base;
     static constexpr int N = F::N, NQ = F::NQ, NK = F::NK, NTRI = F::NTRI, TT = F::TT, TP = F::TP, KS = F::KS;
     static constexpr int NIJ = F::NIJ, NCT = F::NCT, BB = F::BB, NB = F::NBLK;
-    static constexpr int NBLK = 4;                 // work items per element: the workgroup's waves
+    static constexpr int WPE = NB == 2 ? 2 : 4;    // waves per element
+    static constexpr int EPW = 4 / WPE;            // elements per workgroup
+    static constexpr int NBLK = WPE;               // work items per element: its waves
     static constexpr int SR = 17;                  // row stride of S (doubles)
     typedef typename AccT<T>::type V4;
     typedef const __attribute__((address_space(4))) T CT;
 
     struct Smem {
-        double S[NQ][SR];                          // S_q[r][s] at 4 r + s
+        double S[EPW][NQ][SR];                     // per element: S_q[r][s] at 4 r + s
         double red[4][32];
     };
 
     __device__ static void run_coop(const AdjParams &prm, int64_t e, int wv, int wave, bool live, Smem &sm) {
-        (void)wave;
         const int lane = threadIdx.x & 63;
         const int i16 = lane & 15, kg = lane >> 4;
-        for (int i = threadIdx.x; i < NQ * SR; i += 256) (&sm.S[0][0])[i] = 0.0;
+        const int el = wave / WPE;                 // the element's area in this workgroup
+        for (int i = threadIdx.x; i < EPW * NQ * SR; i += 256) (&sm.S[0][0][0])[i] = 0.0;
         __syncthreads();
         if (live) {
             const T *Ge = (const T *)prm.G + e * (int64_t)N * N;
             const T *tau = (const T *)prm.tau;
             const CT *lam = (const CT *)prm.lamT;
             const bool rl = (i16 & 3) == 3;
-            for (int blk = wv; blk < NB; blk += 4) {
+            for (int blk = wv; blk < NB; blk += WPE) {
                 const int bk = blk / BB, bc = blk % BB;
                 const int k0 = bk * TK, c0 = bc * TB;
                 T gf[TK][KS][TB];
@@ -539,10 +543,10 @@ struct KFA2 {
                             if (sizeof(T) == 8) {
                                 const int pt = i16 >> 2;        // lane holds rows 4 jj + kg: point jj, r = kg
                                 const double v = pt == 0 ? tacc[0] : pt == 1 ? tacc[1] : pt == 2 ? tacc[2] : tacc[3];
-                                atomicAdd(&sm.S[q][4 * kg + (i16 & 3)], v);
+                                atomicAdd(&sm.S[el][q][4 * kg + (i16 & 3)], v);
                             } else if (kg == (i16 >> 2)) {     // lane holds rows 4 kg + jj: point kg, r = jj
 #pragma unroll
-                                for (int jj = 0; jj < 4; ++jj) atomicAdd(&sm.S[q][4 * jj + (i16 & 3)], (double)tacc[jj]);
+                                for (int jj = 0; jj < 4; ++jj) atomicAdd(&sm.S[el][q][4 * jj + (i16 & 3)], (double)tacc[jj]);
                             }
                         }
                     }
@@ -554,7 +558,7 @@ struct KFA2 {
             ElemIn E;
             load_elem(prm.coords, prm.D, prm.beta, prm.c, prm.f, e, E);
             double gacc = 0.0;
-            for (int q0 = wv * 64; q0 < NQ; q0 += 256) {
+            for (int q0 = wv * 64; q0 < NQ; q0 += WPE * 64) {
                 double gr[32];
 #pragma unroll
                 for (int k = 0; k < 32; ++k) gr[k] = 0.0;
@@ -562,18 +566,20 @@ struct KFA2 {
                 if (q < NQ) {
                     double S[16];
 #pragma unroll
-                    for (int k = 0; k < 16; ++k) S[k] = sm.S[q][k];
+                    for (int k = 0; k < 16; ++k) S[k] = sm.S[el][q][k];
                     Base::chain_rule(prm, E, q, S, true, e, gr);
                 }
                 gacc += Base::reduce_scatter32(gr, lane);
             }
-            if ((lane & 1) == 0) sm.red[wv][lane >> 1] = gacc;
+            if ((lane & 1) == 0) sm.red[wave][lane >> 1] = gacc;
         }
         __syncthreads();
         if (live && wv == 0 && lane < 32) {
             // component c: vertices 0..17, D 18..26, beta 27..29, c 30, f 31
             const int c = lane;
-            const double g = sm.red[0][c] + sm.red[1][c] + sm.red[2][c] + sm.red[3][c];
+            double g = 0.0;
+#pragma unroll
+            for (int w = 0; w < WPE; ++w) g += sm.red[el * WPE + w][c];
             double *dst = c < 18 ? prm.dX + 18 * e + c
                         : c < 27 ? prm.dD + 9 * e + (c - 18)
                         : c < 30 ? prm.dbeta + 3 * e + (c - 27)
@@ -658,13 +664,14 @@ const AdjVariant *adj_variants_of(int p, int *count) {
     // from p = 3 the factorised kernel ("f", "fo2" with two waves per SIMD) first, in the
     // order measured per form (131072 elements at p = 3 and 4, 16384 at p = 5 and 7); the
     // same shapes for both forms; from p = 5 the one with the chain rule shared by the waves
-    // of an element ("fw") first (p = 7: 1.4x FP64, 2.0x FP32), at p = 3 and 4 it is slower
+    // of an element ("fw") first (p = 7: 1.4x FP64, 2.0x FP32), and in FP32 at p = 3 (two
+    // waves per element, 1.1x); FP64 at p = 3 level, at p = 4 slower
     static const AdjVariant v3d[] = {FEINT_ADJF2(3, T, 4, 2), FEINT_ADJ(3, T, 3, 3), FEINT_ADJF(3, T, 4, 2),
                                      FEINT_ADJF(3, T, 4, 4), FEINT_ADJ(3, T, 3, 1), FEINT_ADJ(3, T, 3, 2),
                                      FEINT_ADJF2(3, T, 4, 1), FEINT_ADJW2(3, T, 4, 2)};
-    static const AdjVariant v3f[] = {FEINT_ADJF2(3, T, 4, 2), FEINT_ADJF(3, T, 4, 4), FEINT_ADJF(3, T, 4, 2),
-                                     FEINT_ADJ(3, T, 3, 3), FEINT_ADJ(3, T, 3, 1), FEINT_ADJ(3, T, 3, 2),
-                                     FEINT_ADJF2(3, T, 4, 1), FEINT_ADJW2(3, T, 4, 2)};
+    static const AdjVariant v3f[] = {FEINT_ADJW2(3, T, 4, 2), FEINT_ADJF2(3, T, 4, 2), FEINT_ADJF(3, T, 4, 4),
+                                     FEINT_ADJF(3, T, 4, 2), FEINT_ADJ(3, T, 3, 3), FEINT_ADJ(3, T, 3, 1),
+                                     FEINT_ADJ(3, T, 3, 2), FEINT_ADJF2(3, T, 4, 1)};
     static const AdjVariant v4[] = {FEINT_ADJF2(4, T, 5, 1), FEINT_ADJF(4, T, 5, 1), FEINT_ADJF(4, T, 5, 2),
                                     FEINT_ADJ(4, T, 5, 2), FEINT_ADJ(4, T, 5, 1), FEINT_ADJ(4, T, 3, 3),
                                     FEINT_ADJW(4, T, 5, 1)};
