@@ -831,6 +831,9 @@ feint_status feint_adjoint_autotune(const feint_elements *el, int p, feint_form 
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return FEINT_ERR_HIP; }
     int best = 0;
     float best_t = 1e30f;
+    // one launch of every variant first, so that the first ones timed do not
+    // pay for the device settling (clocks, first launches) after other work
+    for (int t = 0; t < cnt && s == FEINT_OK; ++t) s = adj_launch(&v[t], prm, st);
     for (int t = 0; t < cnt && s == FEINT_OK; ++t) {
         s = adj_launch(&v[t], prm, st);                     // warm-up
         if (s != FEINT_OK) break;

@@ -352,7 +352,10 @@ feint_status feint_autotune_rule(const feint_elements *el, const feint_fields *f
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return FEINT_ERR_HIP;
     int best = 0;
     float best_t = 1e30f;
-    for (int t = 0; t < cnt; ++t) {
+    // one launch of every variant first, so that the first ones timed do not
+    // pay for the device settling (clocks, first launches) after other work
+    for (int t = 0; t < cnt && s == FEINT_OK; ++t) s = launch_forward(prm, &v[t], st);
+    for (int t = 0; t < cnt && s == FEINT_OK; ++t) {
         s = launch_forward(prm, &v[t], st);                 // warm-up
         if (s != FEINT_OK) break;
         (void)hipEventRecord(e0, st);
@@ -471,6 +474,12 @@ static feint_status elem_autotune(int type, const feint_elements *el, int p, int
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return FEINT_ERR_HIP;
     int best = 0;
     float best_t = 1e30f;
+    for (int t = 0; t < cnt && s == FEINT_OK; ++t) {   // one launch of every variant first
+        FwdParams prm;
+        const FwdVariant *v = nullptr;
+        s = elem_params(type, el, p, form, A, b, st, prm, &v, t);
+        if (s == FEINT_OK) s = launch_forward(prm, v, st);
+    }
     for (int t = 0; t < cnt && s == FEINT_OK; ++t) {
         FwdParams prm;
         const FwdVariant *v = nullptr;
@@ -626,6 +635,12 @@ feint_status feint_laplace_autotune(const double *coords, int64_t ne, int p, fei
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return FEINT_ERR_HIP; }
     int best = 0;
     float best_t = 1e30f;
+    for (int t = 0; t < cnt && s == FEINT_OK; ++t) {   // one launch of every variant first
+        FwdParams prm;
+        const FwdVariant *v = nullptr;
+        s = lap_params(coords, ne, p, form, A, st, prm, &v, t);
+        if (s == FEINT_OK) s = launch_forward(prm, v, st);
+    }
     for (int t = 0; t < cnt && s == FEINT_OK; ++t) {
         FwdParams prm;
         const FwdVariant *v = nullptr;
