@@ -420,7 +420,7 @@ def bench_forward(args, fields=False, kind=None, err_idx=None, cpu_budget=None):
     npad, nqp = (n + 15) // 16 * 16, (q + 7) // 8 * 8
     kf = costmodel.is_kf_tile(h["tile"])
     tref = kind == "tet" and costmodel.is_tet_ref_tile(h["tile"])
-    hw_flops = (costmodel.kf_mfma_flops(p, rule, n, q) * ne if kf else
+    hw_flops = (products * costmodel.kf_mfma_flops(p, rule, n, q) * ne if kf else
                 costmodel.tet_reference_mfma_flops(n) * ne if tref else
                 products * 8.0 * npad * npad * (nqp if products == 3 else q) * ne)
     roofline.update({"traffic": traffic, "kernel_ms": h["kernel_ms_mean"], "flops_per_launch": falg * ne,

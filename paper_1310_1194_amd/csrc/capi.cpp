@@ -62,8 +62,9 @@ feint_status prepare_tables(int p, int rule, int type) {
     const size_t s_sp = align(H.bf_hi.size() * 2);
     const size_t s_ycf = align(H.Ycf.size() * 4);
     const size_t s_m64 = align(H.Mref.size() * 8), s_m32 = align(H.Mref32.size() * 4);
+    const size_t s_tb = align(H.taub_hi.size() * 2);
     const size_t total = s_tau + s_tau32 + s_lam + s_lam32 + s_qw + s_gll + 2 * s_b64 + 3 * s_b32 + 4 * s_sp + s_ycf +
-                         s_m64 + s_m32;
+                         s_m64 + s_m32 + 2 * s_tb;
     char *base = nullptr;
     e = hipMalloc((void **)&base, total);
     if (e != hipSuccess) { set_error("hipMalloc(tables)", e); return FEINT_ERR_HIP; }
@@ -99,6 +100,8 @@ feint_status prepare_tables(int p, int rule, int type) {
     T->Ycf = (const float *)put(H.Ycf.data(), H.Ycf.size() * 4, s_ycf);
     T->Mref64 = (const double *)put(H.Mref.data(), H.Mref.size() * 8, s_m64);
     T->Mref32 = (const float *)put(H.Mref32.data(), H.Mref32.size() * 4, s_m32);
+    T->taubh = (const uint16_t *)put(H.taub_hi.data(), H.taub_hi.size() * 2, s_tb);
+    T->taubl = (const uint16_t *)put(H.taub_lo.data(), H.taub_lo.size() * 2, s_tb);
     T->base = base;
     e = hipMemcpy(base, host.data(), total, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -144,6 +147,7 @@ void fill_fwd_params(FwdParams &prm, const feint_elements *el, int form, const D
     prm.qw = T->qw; prm.gll = T->gll; prm.tau64 = T->tau64; prm.tau32 = T->tau32; prm.lam = T->lam; prm.lam32 = T->lam32;
     prm.B64 = T->B64; prm.B32 = T->B32; prm.Bc32 = T->Bc32; prm.Ycf = T->Ycf;
     prm.Mref64 = T->Mref64; prm.Mref32 = T->Mref32;
+    prm.taubh = T->taubh; prm.taubl = T->taubl;
     prm.Bhi = form == FEINT_FP16X3 ? T->hf_hi : T->bf_hi;
     prm.Blo = form == FEINT_FP16X3 ? T->hf_lo : T->bf_lo;
     prm.bmax = T->bmax;
@@ -298,7 +302,7 @@ static void describe_variant(const FwdVariant &v, char *buf, size_t len) {
     else
         std::snprintf(buf, len, "%dx%d%s%s", v.tm, v.tn,
                       v.staged == 1 ? "s" : v.staged == 2 ? "sa" : v.staged == 4 ? "p"
-                      : v.staged == 5 ? "c" : v.staged == 6 ? "f" : v.staged == 7 ? "y" : v.staged == 13 ? "fw" : "",
+                      : v.staged == 5 ? "c" : v.staged == 6 ? "f" : v.staged == 7 ? "y" : v.staged == 13 ? "fw" : v.staged == 14 ? "fwb" : "",
                       v.minw > 1 ? "o2" : "");
 }
 

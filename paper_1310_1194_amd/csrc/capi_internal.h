@@ -21,6 +21,7 @@ struct DevTables {
     const float *Ycf;
     const double *Mref64;
     const float *Mref32;
+    const uint16_t *taubh, *taubl;
     void *base;
 };
 

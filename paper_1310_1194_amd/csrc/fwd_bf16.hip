@@ -31,6 +31,8 @@ const FwdVariant v6[] = {
     FEINT_K32S(6, BF16X3, 7, 4, false, 1),
     FEINT_K32U(6, BF16X3, 13, 2, 1)};
 const FwdVariant v7[] = {
+    FEINT_KF2S(7, 4, 2, 2),
+    FEINT_KF2S(7, 4, 1, 2),
     FEINT_K32Y(7, BF16X3, 3, 3, 2, 1),
     FEINT_K32Y(7, BF16X3, 6, 3, 1, 1),
     FEINT_K32Y(7, BF16X3, 6, 6, 1, 1),

@@ -522,6 +522,23 @@ HostTables build_tables(int p, int rule) {
     }
     T.tau32.assign(T.tau64.begin(), T.tau64.end());
     T.lam32.assign(T.lam.begin(), T.lam.end());
+    {
+        const int nch = (T.nij + 7) / 8, tt = T.tpad / 16;
+        T.taub_hi.assign((size_t)nch * tt * 64 * 8, 0);
+        T.taub_lo.assign((size_t)nch * tt * 64 * 8, 0);
+        for (int c = 0; c < nch; ++c)
+            for (int ti = 0; ti < tt; ++ti)
+                for (int l = 0; l < 64; ++l)
+                    for (int v = 0; v < 8; ++v) {
+                        const int ij = 8 * c + 2 * (l / 16) + v / 4, r = v % 4, t = 16 * ti + l % 16;
+                        if (ij >= T.nij) continue;
+                        const double x = T.tau64[((size_t)ij * 4 + r) * T.tpad + t];
+                        const size_t o = (((size_t)c * tt + ti) * 64 + l) * 8 + v;
+                        const uint16_t h = to_bf16((float)x);
+                        T.taub_hi[o] = h;
+                        T.taub_lo[o] = to_bf16((float)(x - (double)from_bf16(h)));
+                    }
+    }
     return T;
 }
 

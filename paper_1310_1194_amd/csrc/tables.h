@@ -37,6 +37,10 @@ struct HostTables {
     std::vector<float> tau32;
     std::vector<double> lam;         // [4][nk][nk]     L_k, L_k, L_k, dL_k/dzeta at zeta point m
     std::vector<float> lam32;        // lam rounded to FP32
+    // tau split into bf16 hi + lo in 16x16x32 A-fragment order, [nij/8 chunks][tpad/16]
+    // [64 lanes][8]: lane l, value v holds tau_r(t, ij) with t = 16 tile + l%16,
+    // ij = 8 chunk + 2 (l/16) + v/4, r = v%4 (zero past the last triangle point)
+    std::vector<uint16_t> taub_hi, taub_lo;
     std::vector<double> B64;         // [nqp][4][npad]  rows: phi, d/dxi1, d/dxi2, d/dzeta
     std::vector<float> B32;          // same, rounded to FP32
     std::vector<double> BT64;        // [npad][nqp*4]  transpose of B64 (shape-function major)
