@@ -104,8 +104,9 @@ int64_t items_of(int64_t ne) { return items_for<KER>(ne); }
     FwdVariant{TMK, TN, 13, W, &launch_coop<KF2<P, T, TMK, TN, R>, W>, &items_of<KF2<P, T, TMK, TN, R>>}
 #define FEINT_KF2(P, T, TMK, TN, W) FEINT_KF2_R(P, T, TMK, TN, W, 0)
 // the split form (bf16x3) of it (staged = 14)
-#define FEINT_KF2S(P, TMK, TN, W) \
-    FwdVariant{TMK, TN, 14, W, &launch_coop<KF2S<P, TMK, TN>, W>, &items_of<KF2S<P, TMK, TN>>}
+#define FEINT_KF2S_R(P, TMK, TN, W, R) \
+    FwdVariant{TMK, TN, 14, W, &launch_coop<KF2S<P, TMK, TN, R>, W>, &items_of<KF2S<P, TMK, TN, R>>}
+#define FEINT_KF2S(P, TMK, TN, W) FEINT_KF2S_R(P, TMK, TN, W, 0)
 #define FEINT_KF_HEX(P, T, TMK, TN, W)                                        \
     FwdVariant{TMK, TN, 6, W, &launch_direct<KF<P, T, TMK, TN, 0, HexGeo>, W>, \
                &items_of<KF<P, T, TMK, TN, 0, HexGeo>>}
