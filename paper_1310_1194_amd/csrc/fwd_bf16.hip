@@ -19,18 +19,27 @@ const FwdVariant v4[] = {
     FEINT_K32U(4, BF16X3, 5, 5, 1),
     FEINT_K32S(4, BF16X3, 5, 5, true, 1),
     FEINT_K32U(4, BF16X3, 5, 3, 1),
-    FEINT_K32P(4, BF16X3, 5, 3, 1)};
+    FEINT_K32P(4, BF16X3, 5, 3, 1),
+    FEINT_KF2G(4, 5, 3, 2),
+    FEINT_KF2G(4, 3, 3, 2),
+    FEINT_KF2G(4, 5, 1, 2)};
 const FwdVariant v5[] = {
+    FEINT_KF2G(5, 3, 2, 2),
     FEINT_K32S(5, BF16X3, 8, 4, false, 1),
     FEINT_K32S(5, BF16X3, 8, 4, true, 1),
     FEINT_K32S(5, BF16X3, 4, 4, false, 2),
-    FEINT_K32U(5, BF16X3, 8, 4, 1)};
+    FEINT_K32U(5, BF16X3, 8, 4, 1),
+    FEINT_KF2G(5, 3, 3, 2)};
 const FwdVariant v6[] = {
+    FEINT_KF2G(6, 7, 1, 2),
     FEINT_K32S(6, BF16X3, 13, 2, false, 2),
     FEINT_K32S(6, BF16X3, 13, 2, false, 1),
     FEINT_K32S(6, BF16X3, 7, 4, false, 1),
     FEINT_K32U(6, BF16X3, 13, 2, 1)};
+
 const FwdVariant v7[] = {
+    FEINT_KF2G(7, 4, 2, 2),
+    FEINT_KF2G(7, 4, 1, 2),
     FEINT_KF2S(7, 4, 2, 2),
     FEINT_KF2S(7, 4, 1, 2),
     FEINT_K32Y(7, BF16X3, 3, 3, 2, 1),

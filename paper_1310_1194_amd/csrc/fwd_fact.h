@@ -620,4 +620,189 @@ struct KF2S {
     }
 };
 
+// The split form with the zeta sum taken first.  Z_k[(ij, r)][(k', t')] =
+// sum_s tau_s(t', ij) G[r][s] with G[r][s] = sum_m lam_r(k, m) lam_s(k', m)
+// W_m(ij)[r][s]: G does not depend on the output column t', so each
+// (triangle point, k, k') combination of a lane group's pair of triangle
+// points is summed once, by one lane of the group, into the wave's LDS, and
+// every lane then forms its eight Z values from the 13 nonzero G entries
+// (W_m[r][0] = 0 for r >= 1) and its four tau values: 13 FMAs per eight Z
+// values in place of about 70.  The load vector's zeta sum
+// sum_m lam_0(k, m) w det J f rides in the G block of column k' = 0 and is
+// added on the spare column, whose tau values are zero.  Otherwise as KF2S.
+template <int P, int TMK, int TN, int R = 0, class G = PrismGeo>
+struct KF2G {
+    typedef KF<P, float, TMK, TN, R, G> F;
+    typedef KF2<P, float, TMK, TN, R, G> K2;
+    static constexpr int N = F::N, NK = F::NK, NTRI = F::NTRI, TT = F::TT, TP = F::TP, NQ = F::NQ, NIJ = F::NIJ;
+    static constexpr int BM = F::BM, BK = F::BK, BN = F::BN, NB = F::NBLK;
+    static constexpr int NCH = (NIJ + 7) / 8;          // chunks of eight triangle points
+    static constexpr int WPE = K2::WPE, EPW = K2::EPW;
+    static constexpr int EPI = 1, NBLK = WPE;
+    static constexpr int LCT = F::LCT, LCL = F::LCL;
+    static constexpr int NCB = 2 * TMK * TN;            // combinations of a full block
+    static constexpr int GST = NCB * 16 + 4;            // one lane group's G blocks (padded: the groups start on different banks)
+    static_assert(F::SPARE, "the load vector rides in a spare padded column");
+    static_assert(NCB <= 32, "at most two combinations per lane of a group");
+    typedef typename K2::ElemArea ElemArea;
+    struct alignas(16) Area { ElemArea a; };           // 16-byte reads of every element's point blocks
+    struct Smem {
+        Area el[EPW];
+        float gs[4][4 * GST];                          // per wave, per lane group
+    };
+    typedef bf16x8 HV;
+    typedef K32<P, BF16X3, 1, 1, R, G> Split;          // split8: hi = rn(y), lo = rn(y - hi)
+
+    template <int TMV, int TNV, bool LB>
+    __device__ static void body(const FwdParams &prm, int64_t slot, int bi, int bj, const ElemArea &ea, float *gs) {
+        constexpr int NC = 2 * TMV * TNV, NCL = (NC + 15) / 16;
+        const int lane = threadIdx.x & 63;
+        const int i16 = lane & 15, g = lane >> 4;
+        const int k0 = bi * TMK, tt = bj / BK, kp0 = (bj - tt * BK) * TN;
+        const int64_t e = elem_of(prm, slot);
+        const float *tau = prm.tau32;
+        const float *lam = prm.lam32;                  // [r][k][m]; rows 0..2 hold L, row 3 dL
+        const int tcol = tt * 16 + i16;
+        const bool lcol = LB && i16 == LCL;
+        // this lane's combinations for the zeta sums, c = i16 + 16 cl: triangle
+        // point ch of its group's pair, row k0 + ck, column kp0 + cj (lanes
+        // past NC repeat combination 0 and store nothing)
+        int cc[NCL], chh[NCL];
+        float vv[NCL][NK], vd[NCL][NK], dv[NCL][NK], dd[NCL][NK], lk[NCL][NK];
+#pragma unroll
+        for (int cl = 0; cl < NCL; ++cl) {
+            const int c = i16 + 16 * cl < NC ? i16 + 16 * cl : 0;
+            const int ck = (c / TNV) % TMV, cj = c % TNV;
+            cc[cl] = i16 + 16 * cl;
+            chh[cl] = c / (TMV * TNV);
+#pragma unroll
+            for (int m = 0; m < NK; ++m) {
+                const float a = lam[(size_t)(k0 + ck) * NK + m], da = lam[(size_t)(3 * NK + k0 + ck) * NK + m];
+                const float b = lam[(size_t)(kp0 + cj) * NK + m], db = lam[(size_t)(3 * NK + kp0 + cj) * NK + m];
+                vv[cl][m] = a * b; vd[cl][m] = a * db; dv[cl][m] = da * b; dd[cl][m] = da * db;
+                lk[cl][m] = a;
+            }
+        }
+        float *gw = gs + g * GST;                      // this lane group's blocks
+        f32x4 acc[TMV][TT][TNV];
+#pragma unroll
+        for (int k = 0; k < TMV; ++k)
+#pragma unroll
+            for (int ti = 0; ti < TT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < TNV; ++tj) acc[k][ti][tj] = f32x4{0, 0, 0, 0};
+        for (int c8 = 0; c8 < NCH; ++c8) {
+            HV ah[TT], al[TT];
+#pragma unroll
+            for (int ti = 0; ti < TT; ++ti) {
+                const size_t o = (((size_t)c8 * TT + ti) * 64 + lane) * 8;
+                ah[ti] = *(const HV *)(prm.taubh + o);
+                al[ti] = *(const HV *)(prm.taubl + o);
+            }
+            float tb[2][4];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int ij = c8 * 8 + 2 * g + h;
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) tb[h][s4] = ij < NIJ ? tau[((size_t)ij * 4 + s4) * TP + tcol] : 0.0f;
+            }
+            // G of this lane's combinations; the previous chunk's reads come first
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+#pragma unroll
+            for (int cl = 0; cl < NCL; ++cl) {
+                const int ij = c8 * 8 + 2 * g + chh[cl];
+                f32x4 g0 = {0, 0, 0, 0}, g1 = {0, 0, 0, 0}, g2 = {0, 0, 0, 0}, g3 = {0, 0, 0, 0};
+                if (ij < NIJ) {
+#pragma unroll
+                    for (int m = 0; m < NK; ++m) {
+                        const f32x4 *wr = (const f32x4 *)&ea.W[m * NIJ + ij][0];
+                        const f32x4 w0 = wr[0], w1 = wr[1], w2 = wr[2], w3 = wr[3];
+                        const float xvv = vv[cl][m], xvd = vd[cl][m], xdv = dv[cl][m], xdd = dd[cl][m];
+                        g0[0] += xvv * w0[0]; g0[1] += xvv * w0[1]; g0[2] += xvv * w0[2]; g0[3] += xvd * w0[3];
+                        g1[0] += xvv * w1[1]; g1[1] += xvv * w1[2]; g1[2] += xvd * w1[3];
+                        if (LB) g1[3] += lk[cl][m] * (float)ea.sf[m * NIJ + ij];
+                        g2[0] += xvv * w2[1]; g2[1] += xvv * w2[2]; g2[2] += xvd * w2[3];
+                        g2[3] += xdv * w3[1]; g3[0] += xdv * w3[2]; g3[1] += xdd * w3[3];
+                    }
+                }
+                if (cc[cl] < NC) {
+                    f32x4 *gp = (f32x4 *)(gw + cc[cl] * 16);
+                    gp[0] = g0; gp[1] = g1; gp[2] = g2; gp[3] = g3;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+#pragma unroll
+            for (int k = 0; k < TMV; ++k)
+#pragma unroll
+                for (int tj = 0; tj < TNV; ++tj) {
+                    float z[8];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const f32x4 *gp = (const f32x4 *)(gw + ((h * TMV + k) * TNV + tj) * 16);
+                        const f32x4 a = gp[0], b = gp[1], cc = gp[2], d = gp[3];
+                        const float *t = tb[h];
+                        float z0 = a[0] * t[0] + a[1] * t[1] + a[2] * t[2] + a[3] * t[3];
+                        if (LB && tj == 0) z0 += lcol ? b[3] : 0.0f;   // the load-vector column
+                        z[4 * h + 0] = z0;
+                        z[4 * h + 1] = b[0] * t[1] + b[1] * t[2] + b[2] * t[3];
+                        z[4 * h + 2] = cc[0] * t[1] + cc[1] * t[2] + cc[2] * t[3];
+                        z[4 * h + 3] = cc[3] * t[1] + d[0] * t[2] + d[1] * t[3];
+                    }
+                    HV zh, zl;
+                    Split::split8(z, zh, zl);
+#pragma unroll
+                    for (int ti = 0; ti < TT; ++ti) {
+                        acc[k][ti][tj] = mfma32(ah[ti], zl, acc[k][ti][tj]);
+                        acc[k][ti][tj] = mfma32(al[ti], zh, acc[k][ti][tj]);
+                        acc[k][ti][tj] = mfma32(ah[ti], zh, acc[k][ti][tj]);
+                    }
+                }
+        }
+        float *Aout = (float *)prm.A + offA_of(prm, e, N);
+        float *bout = (float *)prm.b + offb_of(prm, e, N);
+#pragma unroll
+        for (int k = 0; k < TMV; ++k)
+#pragma unroll
+            for (int ti = 0; ti < TT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < TNV; ++tj)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int tr = ti * 16 + acc_row<float>(lane, r);
+                        if (tr >= NTRI) continue;
+                        const int row = (k0 + k) * NTRI + tr;
+                        if (tj == 0 && lcol)
+                            bout[row] = acc[k][ti][tj][r];
+                        else if (tcol < NTRI)
+                            Aout[(size_t)row * N + (kp0 + tj) * NTRI + tcol] = acc[k][ti][tj][r];
+                    }
+    }
+
+    template <int TMV, int TNV>
+    __device__ static void with_lb(bool lb, const FwdParams &prm, int64_t slot, int bi, int bj, const ElemArea &ea, float *gs) {
+        if (lb) body<TMV, TNV, true>(prm, slot, bi, bj, ea, gs);
+        else body<TMV, TNV, false>(prm, slot, bi, bj, ea, gs);
+    }
+    __device__ static void one_block(const FwdParams &prm, int64_t slot, int blk, const ElemArea &ea, float *gs) {
+        constexpr int TML = NK - (BM - 1) * TMK, TNL = NK - (BK - 1) * TN;
+        const int bi = blk / BN, bj = blk % BN;
+        const bool lastm = TML != TMK && bi == BM - 1, lastn = TNL != TN && bj % BK == BK - 1;
+        const bool lb = G::LOAD && bj % BK == 0 && bj / BK == LCT;
+        if (lastm) {
+            if (lastn) with_lb<TML, TNL>(lb, prm, slot, bi, bj, ea, gs);
+            else with_lb<TML, TN>(lb, prm, slot, bi, bj, ea, gs);
+        } else {
+            if (lastn) with_lb<TMK, TNL>(lb, prm, slot, bi, bj, ea, gs);
+            else with_lb<TMK, TN>(lb, prm, slot, bi, bj, ea, gs);
+        }
+    }
+    __device__ static void run_coop(const FwdParams &prm, int64_t slot, int wv, int wave, bool live, Smem &sm) {
+        ElemArea &ea = sm.el[wave / WPE].a;
+        K2::geometry(prm, slot, wv, live, ea);
+        __syncthreads();
+        if (!live) return;
+        for (int blk = wv; blk < NB; blk += WPE) one_block(prm, slot, blk, ea, sm.gs[wave]);
+    }
+};
+
 }  // namespace feint
