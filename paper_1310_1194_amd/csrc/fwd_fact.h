@@ -706,8 +706,11 @@ struct KF2G {
 #pragma unroll
                 for (int s4 = 0; s4 < 4; ++s4) tb[h][s4] = ij < NIJ ? tau[((size_t)ij * 4 + s4) * TP + tcol] : 0.0f;
             }
-            // G of this lane's combinations; the previous chunk's reads come first
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            // G of this lane's combinations; the previous chunk's reads come
+            // first.  A wave's LDS operations execute in order, so the fences only
+            // keep the compiler from moving LDS accesses across them (wavefront
+            // scope: no wait for the table loads in flight)
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
             for (int cl = 0; cl < NCL; ++cl) {
                 const int ij = c8 * 8 + 2 * g + chh[cl];
@@ -730,7 +733,7 @@ struct KF2G {
                     gp[0] = g0; gp[1] = g1; gp[2] = g2; gp[3] = g3;
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
             for (int k = 0; k < TMV; ++k)
 #pragma unroll
