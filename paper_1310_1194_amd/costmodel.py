@@ -146,10 +146,11 @@ def is_sf_tile(desc: str) -> bool:
 
 
 def is_kf_tile(desc: str) -> bool:
-    """Tile descriptions "KxTNf", "KxTNfw" and (split forms) "KxTNfwb" and
-    "KxTNfwg", optionally "o2", name the triangle-point contraction."""
+    """Tile descriptions "KxTNf", "KxTNfw", "KxTNfz" and (split forms)
+    "KxTNfwb" and "KxTNfwg", optionally "o2", name the triangle-point
+    contraction."""
     import re
-    return re.fullmatch(r"\d+x\d+f(w[bg]?)?(o2)?", desc) is not None
+    return re.fullmatch(r"\d+x\d+f(w[bg]?|z)?(o2)?", desc) is not None
 
 
 def f_kernel(p: int, rule: str, desc: str) -> int:

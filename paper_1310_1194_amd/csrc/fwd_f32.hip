@@ -44,6 +44,7 @@ const FwdVariant v5[] = {
     FEINT_K4U(5, float, 8, 4, 1),
     FEINT_KSC(5, float, 8, 4, 1)};
 const FwdVariant v6[] = {
+    FEINT_KF2Z(6, float, 4, 2, 2, 2),
     FEINT_KF2(6, float, 4, 2, 2),
     FEINT_KF_R(6, float, 7, 4, 1, 0),
     FEINT_KF_R(6, float, 7, 3, 1, 0),
@@ -51,6 +52,7 @@ const FwdVariant v6[] = {
     FEINT_K4U(6, float, 13, 4, 1),
     FEINT_KSC(6, float, 13, 2, 1)};
 const FwdVariant v7[] = {
+    FEINT_KF2Z(7, float, 4, 2, 4, 2),
     FEINT_KF2(7, float, 4, 2, 2),
     FEINT_KF_R(7, float, 8, 2, 1, 0),
     FEINT_K4U(7, float, 9, 6, 1),

@@ -38,6 +38,7 @@ const FwdVariant v4[] = {
     FEINT_K4U(4, double, 5, 1, 2),
     FEINT_KSC(4, double, 5, 3, 1)};
 const FwdVariant v5[] = {
+    FEINT_KF2Z(5, double, 3, 2, 4, 2),
     FEINT_KF2(5, double, 3, 2, 2),
     FEINT_KF_R(5, double, 6, 2, 1, 0),
     FEINT_KF_R(5, double, 3, 2, 1, 0),
@@ -46,6 +47,7 @@ const FwdVariant v5[] = {
     FEINT_K4S(5, double, 8, 1, 4, 2),
     FEINT_KSC(5, double, 8, 2, 1)};
 const FwdVariant v6[] = {
+    FEINT_KF2Z(6, double, 2, 2, 2, 2),
     FEINT_KF2(6, double, 2, 2, 2),
     FEINT_KF_R(6, double, 7, 1, 1, 0),
     FEINT_KF_R(6, double, 4, 2, 1, 0),
@@ -53,6 +55,7 @@ const FwdVariant v6[] = {
     FEINT_K4S(6, double, 13, 1, 4, 1),
     FEINT_KSC(6, double, 13, 1, 1)};
 const FwdVariant v7[] = {
+    FEINT_KF2Z(7, double, 2, 2, 2, 2),
     FEINT_KF2(7, double, 2, 2, 2),
     FEINT_KF_R(7, double, 4, 2, 1, 0),
     FEINT_KF_R(7, double, 2, 2, 1, 0),

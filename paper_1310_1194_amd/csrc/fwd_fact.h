@@ -808,4 +808,175 @@ struct KF2G {
     }
 };
 
+// The FP64 / FP32 contraction with the zeta sums taken first, as KF2G does
+// for the split form: Z_k[(ij, r)][(k', t')] = sum_s tau_s(t', ij) G[r][s]
+// with G[r][s] = sum_m lam_r(k, m) lam_s(k', m) W_m(ij)[r][s].  Per batch of
+// IJB triangle points, the wave's lanes form the 16 entries G[r][s] of every
+// (k, k') block of the wave's tile block, one or more entries per lane, into
+// the wave's LDS.  G[r][0] = 0 for r >= 1 (W_m[r][0] = 0); the slot of r = 1
+// carries the load vector's zeta sum sum_m lam_0(k, m) w det J f in the block
+// of column k' = 0, read from the same slot of the point blocks, where w det J
+// f is stored.  Lane (r, t') then reads row r of each block and forms its Z
+// value with four FMAs, against about nine vector instructions per Z value
+// in KF2.  On gfx950 FP64 vector work and FP64 MFMAs never overlap, so what
+// this removes comes off the FP64 time directly.
+template <int P, typename T, int TMK, int TN, int IJB = 4, int R = 0, class G = PrismGeo>
+struct KF2Z {
+    typedef KF<P, T, TMK, TN, R, G> F;
+    typedef KF2<P, T, TMK, TN, R, G> K2;
+    static constexpr int N = F::N, NK = F::NK, NTRI = F::NTRI, TT = F::TT, TP = F::TP, NQ = F::NQ, NIJ = F::NIJ;
+    static constexpr int BM = F::BM, BK = F::BK, BN = F::BN, NB = F::NBLK;
+    static constexpr int WPE = K2::WPE, EPW = K2::EPW;
+    static constexpr int EPI = 1, NBLK = WPE;
+    static constexpr int LCT = F::LCT, LCL = F::LCL;
+    static constexpr int NVB = 16 * TMK * TN;          // G entries of a full block per triangle point
+    static constexpr int NJ = (NVB + 63) / 64;         // entries per lane
+    static_assert(F::SPARE, "the load vector rides in a spare padded column");
+    typedef typename K2::ElemArea ElemArea;
+    typedef typename AccT<T>::type V4;
+    struct alignas(16) Area { ElemArea a; };
+    struct Smem {
+        Area el[EPW];
+        T gs[4][IJB][NJ * 64];                         // per wave
+    };
+
+    template <int TMV, int TNV, bool LB>
+    __device__ static void body(const FwdParams &prm, int64_t slot, int bi, int bj, const ElemArea &ea, T (*gs)[NJ * 64]) {
+        constexpr int NV = 16 * TMV * TNV;
+        const int lane = threadIdx.x & 63;
+        const int i16 = lane & 15, kg = lane >> 4;
+        const int k0 = bi * TMK, tt = bj / BK, kp0 = (bj - tt * BK) * TN;
+        const int64_t e = elem_of(prm, slot);
+        const T *tau = sizeof(T) == 8 ? (const T *)(const void *)prm.tau64 : (const T *)(const void *)prm.tau32;
+        const T *lam = sizeof(T) == 8 ? (const T *)(const void *)prm.lam : (const T *)(const void *)prm.lam32;
+        const int tcol = tt * 16 + i16;
+        const bool lcol = LB && i16 == LCL;
+        const T lsel = (lcol && kg == 0) ? (T)1 : (T)0;
+        // this lane's G entries v = lane + 64 j: block (k, tj) = v / 16, entry (r, s)
+        int col[NJ];
+        T pf[NJ][NK];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int v = lane + 64 * j;
+            const int vv = v < NV ? v : 0;
+            const int cb = vv / 16, rs = vv % 16, r = rs / 4, s = rs % 4;
+            const int k = k0 + cb / TNV, kp = kp0 + cb % TNV;
+            const bool ls = LB && r == 1 && s == 0 && cb % TNV == 0;   // the load-vector slot
+            const bool zero = v >= NV || (r >= 1 && s == 0 && !ls);
+            col[j] = rs;
+#pragma unroll
+            for (int m = 0; m < NK; ++m) {
+                const T a = lam[(size_t)(r * NK + k) * NK + m];
+                const T b = ls ? (T)1 : lam[(size_t)(s * NK + kp) * NK + m];
+                pf[j][m] = zero ? (T)0 : (ls ? lam[(size_t)k * NK + m] : a * b);
+            }
+        }
+        V4 acc[TMV][TT][TNV];
+#pragma unroll
+        for (int k = 0; k < TMV; ++k)
+#pragma unroll
+            for (int ti = 0; ti < TT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < TNV; ++tj) acc[k][ti][tj] = V4{0, 0, 0, 0};
+        for (int ij0 = 0; ij0 < NIJ; ij0 += IJB) {
+            T ta[IJB][TT], tb[IJB][4];
+#pragma unroll
+            for (int b = 0; b < IJB; ++b) {
+                const int ij = ij0 + b < NIJ ? ij0 + b : NIJ - 1;
+#pragma unroll
+                for (int ti = 0; ti < TT; ++ti) ta[b][ti] = tau[((size_t)ij * 4 + kg) * TP + ti * 16 + i16];
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) tb[b][s4] = tau[((size_t)ij * 4 + s4) * TP + tcol];
+                if (kg != 0) tb[b][0] = (T)0;                 // G[r][0] of r >= 1 is not a Z term
+            }
+            // the batch's G entries; the previous batch's reads come first.  A
+            // wave's LDS operations execute in order: the fences only keep the
+            // compiler from moving LDS accesses across them
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+            for (int b = 0; b < IJB; ++b) {
+                const int ij = ij0 + b;
+                if (ij < NIJ) {
+#pragma unroll
+                    for (int j = 0; j < NJ; ++j) {
+                        T gv = (T)0;
+#pragma unroll
+                        for (int m = 0; m < NK; ++m) gv += pf[j][m] * ea.W[m * NIJ + ij][col[j]];
+                        if (lane + 64 * j < NV) gs[b][lane + 64 * j] = gv;
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+            for (int b = 0; b < IJB; ++b) {
+                if (ij0 + b < NIJ) {
+#pragma unroll
+                    for (int tj = 0; tj < TNV; ++tj)
+#pragma unroll
+                        for (int k = 0; k < TMV; ++k) {
+                            const T *gp = &gs[b][(k * TNV + tj) * 16];
+                            T z = gp[4 * kg] * tb[b][0] + gp[4 * kg + 1] * tb[b][1] + gp[4 * kg + 2] * tb[b][2] +
+                                  gp[4 * kg + 3] * tb[b][3];
+                            if (LB && tj == 0) z += lsel * gp[4];   // the load-vector column
+#pragma unroll
+                            for (int ti = 0; ti < TT; ++ti) acc[k][ti][tj] = mfma4(ta[b][ti], z, acc[k][ti][tj]);
+                        }
+                }
+            }
+        }
+        T *Aout = (T *)prm.A + offA_of(prm, e, N);
+        T *bout = (T *)prm.b + offb_of(prm, e, N);
+#pragma unroll
+        for (int k = 0; k < TMV; ++k)
+#pragma unroll
+            for (int ti = 0; ti < TT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < TNV; ++tj)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int tr = ti * 16 + acc_row<T>(lane, r);
+                        if (tr >= NTRI) continue;
+                        const int row = (k0 + k) * NTRI + tr;
+                        if (tj == 0 && lcol)
+                            bout[row] = acc[k][ti][tj][r];
+                        else if (tcol < NTRI)
+                            Aout[(size_t)row * N + (kp0 + tj) * NTRI + tcol] = acc[k][ti][tj][r];
+                    }
+    }
+
+    template <int TMV, int TNV>
+    __device__ static void with_lb(bool lb, const FwdParams &prm, int64_t slot, int bi, int bj, const ElemArea &ea,
+                                   T (*gs)[NJ * 64]) {
+        if (lb) body<TMV, TNV, true>(prm, slot, bi, bj, ea, gs);
+        else body<TMV, TNV, false>(prm, slot, bi, bj, ea, gs);
+    }
+    __device__ static void one_block(const FwdParams &prm, int64_t slot, int blk, const ElemArea &ea, T (*gs)[NJ * 64]) {
+        constexpr int TML = NK - (BM - 1) * TMK, TNL = NK - (BK - 1) * TN;
+        const int bi = blk / BN, bj = blk % BN;
+        const bool lastm = TML != TMK && bi == BM - 1, lastn = TNL != TN && bj % BK == BK - 1;
+        const bool lb = G::LOAD && bj % BK == 0 && bj / BK == LCT;
+        if (lastm) {
+            if (lastn) with_lb<TML, TNL>(lb, prm, slot, bi, bj, ea, gs);
+            else with_lb<TML, TN>(lb, prm, slot, bi, bj, ea, gs);
+        } else {
+            if (lastn) with_lb<TMK, TNL>(lb, prm, slot, bi, bj, ea, gs);
+            else with_lb<TMK, TN>(lb, prm, slot, bi, bj, ea, gs);
+        }
+    }
+    __device__ static void run_coop(const FwdParams &prm, int64_t slot, int wv, int wave, bool live, Smem &sm) {
+        ElemArea &ea = sm.el[wave / WPE].a;
+        K2::geometry(prm, slot, wv, live, ea);
+        if (live) {
+            // w det J f into the W[1][0] slot (zero in every point block), by the
+            // lane that formed the point
+            const int lane = threadIdx.x & 63;
+            for (int qc = wv * 64; qc < NQ; qc += WPE * 64)
+                if (qc + lane < NQ) ea.W[qc + lane][4] = (T)ea.sf[qc + lane];
+        }
+        __syncthreads();
+        if (!live) return;
+        for (int blk = wv; blk < NB; blk += WPE) one_block(prm, slot, blk, ea, sm.gs[wave]);
+    }
+};
+
 }  // namespace feint

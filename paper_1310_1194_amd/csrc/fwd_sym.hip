@@ -13,9 +13,9 @@ const FwdVariant d1[] = {FEINT_KE_R(1, double, 2, S), FEINT_KV_R(1, double, 8, 2
 const FwdVariant d2[] = {FEINT_KV_R(2, double, 18, 2, S), FEINT_K4S_R(2, double, 2, 2, 8, 1, S), FEINT_KSC_R(2, double, 2, 2, 1, S), FEINT_KF_R(2, double, 3, 3, 2, S)};
 const FwdVariant d3[] = {FEINT_KF2_R(3, double, 4, 2, 2, S), FEINT_KF_R(3, double, 4, 2, 2, S), FEINT_KF_R(3, double, 4, 2, 1, S), FEINT_K4S_R(3, double, 3, 3, 8, 1, S), FEINT_KV_R(3, double, 40, 2, S), FEINT_KSC_R(3, double, 3, 3, 1, S)};
 const FwdVariant d4[] = {FEINT_KF2_R(4, double, 5, 3, 2, S), FEINT_KF_R(4, double, 5, 5, 1, S), FEINT_KF_R(4, double, 5, 3, 1, S), FEINT_K4S_R(4, double, 5, 3, 8, 2, S), FEINT_K4U_R(4, double, 5, 1, 2, S), FEINT_KSC_R(4, double, 5, 3, 1, S)};
-const FwdVariant d5[] = {FEINT_KF2_R(5, double, 3, 2, 2, S), FEINT_KF_R(5, double, 6, 2, 1, S), FEINT_KF_R(5, double, 3, 2, 1, S), FEINT_KF_R(5, double, 6, 1, 1, S), FEINT_K4S_R(5, double, 8, 1, 4, 2, S), FEINT_K4U_R(5, double, 8, 1, 2, S), FEINT_KSC_R(5, double, 8, 2, 1, S)};
-const FwdVariant d6[] = {FEINT_KF2_R(6, double, 2, 2, 2, S), FEINT_KF_R(6, double, 7, 1, 1, S), FEINT_KF_R(6, double, 4, 2, 1, S), FEINT_K4U_R(6, double, 13, 1, 2, S), FEINT_K4S_R(6, double, 13, 1, 4, 1, S), FEINT_KSC_R(6, double, 13, 1, 1, S)};
-const FwdVariant d7[] = {FEINT_KF2_R(7, double, 2, 2, 2, S), FEINT_KF_R(7, double, 4, 2, 1, S), FEINT_KF_R(7, double, 2, 2, 1, S), FEINT_KF_R(7, double, 4, 1, 1, S), FEINT_K4U_R(7, double, 9, 2, 1, S), FEINT_K4U_R(7, double, 6, 2, 1, S), FEINT_KSC_R(7, double, 6, 2, 1, S)};
+const FwdVariant d5[] = {FEINT_KF2_R(5, double, 3, 2, 2, S), FEINT_KF2Z_R(5, double, 3, 2, 4, 2, S), FEINT_KF_R(5, double, 6, 2, 1, S), FEINT_KF_R(5, double, 3, 2, 1, S), FEINT_KF_R(5, double, 6, 1, 1, S), FEINT_K4S_R(5, double, 8, 1, 4, 2, S), FEINT_K4U_R(5, double, 8, 1, 2, S), FEINT_KSC_R(5, double, 8, 2, 1, S)};
+const FwdVariant d6[] = {FEINT_KF2Z_R(6, double, 2, 2, 2, 2, S), FEINT_KF2_R(6, double, 2, 2, 2, S), FEINT_KF_R(6, double, 7, 1, 1, S), FEINT_KF_R(6, double, 4, 2, 1, S), FEINT_K4U_R(6, double, 13, 1, 2, S), FEINT_K4S_R(6, double, 13, 1, 4, 1, S), FEINT_KSC_R(6, double, 13, 1, 1, S)};
+const FwdVariant d7[] = {FEINT_KF2Z_R(7, double, 2, 2, 2, 2, S), FEINT_KF2_R(7, double, 2, 2, 2, S), FEINT_KF_R(7, double, 4, 2, 1, S), FEINT_KF_R(7, double, 2, 2, 1, S), FEINT_KF_R(7, double, 4, 1, 1, S), FEINT_K4U_R(7, double, 9, 2, 1, S), FEINT_K4U_R(7, double, 6, 2, 1, S), FEINT_KSC_R(7, double, 6, 2, 1, S)};
 // FP32
 const FwdVariant f1[] = {FEINT_KE_R(1, float, 3, S), FEINT_KV_R(1, float, 8, 2, S), FEINT_K4S_R(1, float, 1, 1, 8, 1, S), FEINT_KSC_R(1, float, 1, 1, 1, S), FEINT_KF_R(1, float, 2, 2, 2, S)};
 const FwdVariant f2[] = {FEINT_KV_R(2, float, 18, 2, S), FEINT_K4S_R(2, float, 2, 2, 8, 1, S), FEINT_KSC_R(2, float, 2, 2, 1, S), FEINT_KF_R(2, float, 3, 3, 2, S)};
@@ -23,7 +23,7 @@ const FwdVariant f3[] = {FEINT_KF_R(3, float, 4, 4, 2, S), FEINT_KF2_R(3, float,
 const FwdVariant f4[] = {FEINT_KF2_R(4, float, 5, 3, 2, S), FEINT_KF_R(4, float, 5, 3, 1, S), FEINT_KF_R(4, float, 5, 5, 1, S), FEINT_K4U_R(4, float, 5, 5, 1, S), FEINT_K4S_R(4, float, 5, 5, 8, 1, S), FEINT_KSC_R(4, float, 5, 5, 1, S)};
 const FwdVariant f5[] = {FEINT_KF2_R(5, float, 6, 3, 2, S), FEINT_KF_R(5, float, 6, 6, 1, S), FEINT_KF_R(5, float, 6, 3, 1, S), FEINT_K4S_R(5, float, 8, 4, 8, 1, S), FEINT_K4U_R(5, float, 8, 8, 1, S), FEINT_KSC_R(5, float, 8, 4, 1, S)};
 const FwdVariant f6[] = {FEINT_KF2_R(6, float, 2, 2, 2, S), FEINT_KF_R(6, float, 7, 4, 1, S), FEINT_KF_R(6, float, 7, 3, 1, S), FEINT_K4S_R(6, float, 13, 2, 8, 1, S), FEINT_K4U_R(6, float, 13, 4, 1, S), FEINT_KSC_R(6, float, 13, 2, 1, S)};
-const FwdVariant f7[] = {FEINT_KF2_R(7, float, 4, 2, 2, S), FEINT_KF_R(7, float, 8, 2, 1, S), FEINT_K4U_R(7, float, 9, 6, 1, S), FEINT_K4U_R(7, float, 9, 3, 1, S), FEINT_KSC_R(7, float, 9, 3, 1, S)};
+const FwdVariant f7[] = {FEINT_KF2Z_R(7, float, 4, 2, 4, 2, S), FEINT_KF2_R(7, float, 4, 2, 2, S), FEINT_KF_R(7, float, 8, 2, 1, S), FEINT_K4U_R(7, float, 9, 6, 1, S), FEINT_K4U_R(7, float, 9, 3, 1, S), FEINT_KSC_R(7, float, 9, 3, 1, S)};
 // bf16x3
 const FwdVariant b1[] = {FEINT_K32S_R(1, BF16X3, 1, 1, true, 1, S)};
 const FwdVariant b2[] = {FEINT_K32S_R(2, BF16X3, 2, 2, true, 1, S)};
