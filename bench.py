@@ -349,7 +349,8 @@ def bench_forward(args, fields=False, kind=None, err_idx=None, cpu_budget=None):
         # kernels and with the paper; gflops_alg: the work of the algorithm the chosen
         # tile runs (fewer flops for the triangle-point contraction), the roofline numerator
         if costmodel.is_kf_tile(r["tile"]):       # prisms and hexahedra: factorised along the third coordinate
-            r["alg_flops_per_element"] = costmodel.f_factored(n, p + 1, q)
+            r["alg_flops_per_element"] = (costmodel.f_factored_zfirst(n, p + 1, q) if costmodel.is_zfirst_tile(r["tile"])
+                                          else costmodel.f_factored(n, p + 1, q))
         elif kind == "tet" and costmodel.is_tet_ref_tile(r["tile"]):   # the reference-matrix GEMM
             r["alg_flops_per_element"] = costmodel.f_tet_reference(n)
         else:
@@ -702,7 +703,9 @@ def bench_laplace(args):
         ms, mn, wall = timed(lambda: F.integrate_laplace_raw(X, p, form, A=A), steps, warm)
         points = F.nq(p, "symmetric")
         paper_ops = costmodel.laplace_paper_ops(p, points)
-        own = costmodel.f_kf(p, "symmetric") if costmodel.is_kf_tile(tile) else costmodel.f_dom(p, "symmetric")
+        own = ((costmodel.f_factored_zfirst(costmodel.nshp(p), p + 1, costmodel.nq(p, "symmetric"))
+                if costmodel.is_zfirst_tile(tile) else costmodel.f_kf(p, "symmetric"))
+               if costmodel.is_kf_tile(tile) else costmodel.f_dom(p, "symmetric"))
         peak = PEAK_TFLOPS[form]
         r = dict(ne=ne, mesh=f"{nx}x{ny}x{nz}", points=points, tile=tile, tune_ms=tune, kernel_ms_mean=ms,
                  kernel_ms_min=mn, us_per_element=ms * 1e3 / ne, elements_per_s=ne / (ms * 1e-3),

@@ -80,6 +80,24 @@ def f_factored(n: int, nk: int, nq_: int) -> int:
     return 8 * n * n * nij + 8 * nk * nk * nij * n + 24 * nq_ * nt + 12 * nq_ * n
 
 
+def f_factored_zfirst(n: int, nk: int, nq_: int) -> int:
+    """Flops per element of the factorised contraction with the line-point
+    sums taken first: the GEMM over (plane point, derivative row), 8 n^2 nij;
+    per (plane point, k, k') the 13 nonzero entries of
+    G[r][s] = sum_m lam_r(k, m) lam_s(k', m) W_m[r][s], 26 nk^3 nij; and each of
+    the 4 nk n nij Z values as four products with the plane factors,
+    32 nk n nij."""
+    nij = nq_ // nk
+    return 8 * n * n * nij + 26 * nk ** 3 * nij + 32 * nk * n * nij
+
+
+def is_zfirst_tile(desc: str) -> bool:
+    """Tiles "KxTNfz" (FP64, FP32) and "KxTNfwg" (split), optionally "o2",
+    take the line-point sums first."""
+    import re
+    return re.fullmatch(r"\d+x\d+f(z|wg)(o2)?", desc) is not None
+
+
 def f_kf(p: int, rule: str = "collapsed") -> int:
     """f_factored for prisms: ntri triangle functions times p+1 line functions."""
     return f_factored(nshp(p), p + 1, nq(p, rule))

@@ -20,22 +20,25 @@ typedef PrismLaplaceGeo L;
     FwdVariant{TMK, TN, 6, W, &launch_direct<KF<P, T, TMK, TN, S, L>, W>, &items_of<KF<P, T, TMK, TN, S, L>>}
 #define LKF2(P, T, TMK, TN, W) \
     FwdVariant{TMK, TN, 13, W, &launch_coop<KF2<P, T, TMK, TN, S, L>, W>, &items_of<KF2<P, T, TMK, TN, S, L>>}
+#define LKF2Z(P, T, TMK, TN, IJB, W)                                           \
+    FwdVariant{TMK, TN, 16, W, &launch_coop<KF2Z<P, T, TMK, TN, IJB, S, L>, W>, \
+               &items_of<KF2Z<P, T, TMK, TN, IJB, S, L>>}
 // FP64
 const FwdVariant d1[] = {LKE(1, double, 2), LKV(1, double, 8, 2), LKF(1, double, 2, 2, 2)};
 const FwdVariant d2[] = {LKV(2, double, 18, 2), LKF(2, double, 3, 3, 2)};
 const FwdVariant d3[] = {LKF2(3, double, 4, 2, 2), LKF(3, double, 4, 2, 2), LKF(3, double, 4, 2, 1), LKV(3, double, 40, 2)};
 const FwdVariant d4[] = {LKF2(4, double, 5, 3, 2), LKF(4, double, 5, 5, 1), LKF(4, double, 5, 3, 1)};
 const FwdVariant d5[] = {LKF2(5, double, 3, 2, 2), LKF(5, double, 6, 2, 1), LKF(5, double, 3, 2, 1)};
-const FwdVariant d6[] = {LKF2(6, double, 2, 2, 2), LKF(6, double, 7, 1, 1), LKF(6, double, 4, 2, 1)};
-const FwdVariant d7[] = {LKF2(7, double, 2, 2, 2), LKF(7, double, 4, 2, 1), LKF(7, double, 4, 1, 1)};
+const FwdVariant d6[] = {LKF2Z(6, double, 2, 2, 2, 2), LKF2(6, double, 2, 2, 2), LKF(6, double, 7, 1, 1), LKF(6, double, 4, 2, 1)};
+const FwdVariant d7[] = {LKF2Z(7, double, 2, 2, 2, 2), LKF2(7, double, 2, 2, 2), LKF(7, double, 4, 2, 1), LKF(7, double, 4, 1, 1)};
 // FP32
 const FwdVariant f1[] = {LKE(1, float, 3), LKE(1, float, 2), LKV(1, float, 8, 2), LKF(1, float, 2, 2, 2)};
 const FwdVariant f2[] = {LKV(2, float, 18, 2), LKF(2, float, 3, 3, 2)};
 const FwdVariant f3[] = {LKF(3, float, 4, 4, 2), LKF2(3, float, 4, 2, 2), LKV(3, float, 40, 2)};
 const FwdVariant f4[] = {LKF2(4, float, 5, 3, 2), LKF(4, float, 5, 3, 1), LKF(4, float, 5, 5, 1)};
 const FwdVariant f5[] = {LKF2(5, float, 6, 3, 2), LKF(5, float, 6, 6, 1), LKF(5, float, 6, 3, 1)};
-const FwdVariant f6[] = {LKF2(6, float, 4, 2, 2), LKF(6, float, 7, 4, 1), LKF(6, float, 7, 3, 1)};
-const FwdVariant f7[] = {LKF2(7, float, 4, 2, 2), LKF(7, float, 8, 2, 1), LKF(7, float, 4, 2, 1)};
+const FwdVariant f6[] = {LKF2Z(6, float, 4, 2, 2, 2), LKF2(6, float, 4, 2, 2), LKF(6, float, 7, 4, 1), LKF(6, float, 7, 3, 1)};
+const FwdVariant f7[] = {LKF2Z(7, float, 4, 2, 4, 2), LKF2(7, float, 4, 2, 2), LKF(7, float, 8, 2, 1), LKF(7, float, 4, 2, 1)};
 
 #define FEINT_PICK(a1, a2, a3, a4, a5, a6, a7)                  \
     switch (p) {                                                 \

@@ -260,7 +260,7 @@ def test_laplace_host_api():
             assert n >= 1 and L.feint_laplace_tile_get(p, form) == 0
             for t in range(n):
                 assert L.feint_laplace_tile_describe(p, form, t, buf, 32) == 0
-                assert re.fullmatch(rb"(\d+x\d+fw?|v\d+)(o\d)?", buf.value), buf.value
+                assert re.fullmatch(rb"(\d+x\d+f[wz]?|v\d+)(o\d)?", buf.value), buf.value
         for form in (2, 3):
             assert L.feint_laplace_tile_count(p, form) == 0 and L.feint_laplace_tile_get(p, form) == -1
     X = ctypes.c_void_p(0x1000)

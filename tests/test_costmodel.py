@@ -192,3 +192,27 @@ def test_kf_tile_names():
     for d in ("5x5", "5x5yo2", "v1o2", "ref1o2", "5x3fwx"):
         assert not costmodel.is_kf_tile(d)
     assert costmodel.f_kernel(4, "collapsed", "5x3fwo2") == costmodel.f_kf(4)
+
+
+def test_zfirst_count_by_loops():
+    """The line-point-sums-first count against the loops it describes, on a
+    small prism (p = 2, collapsed rule): G entries per (plane point, k, k'),
+    then four products per Z value, then the GEMM."""
+    from paper_1310_1194_amd import costmodel as C
+    p = 2
+    n, nk, q = C.nshp(p), p + 1, C.nq(p, "collapsed")
+    nij, nt = q // nk, n // nk
+    flops = 0
+    for _ij in range(nij):
+        for _k in range(nk):
+            for _kp in range(nk):
+                flops += 13 * nk * 2                      # 13 entries, nk FMAs each
+        for _r in range(4):
+            for _k in range(nk):
+                for _col in range(n):
+                    flops += 4 * 2                        # sum over s of G[r][s] tau_s
+    flops += 2 * n * n * 4 * nij                          # the GEMM, K = 4 nij
+    assert C.f_factored_zfirst(n, nk, q) == flops
+    assert C.f_factored_zfirst(C.nshp(7), 8, C.nq(7, "collapsed")) < C.f_kf(7)
+    assert C.is_zfirst_tile("2x2fzo2") and C.is_zfirst_tile("4x2fwgo2")
+    assert not C.is_zfirst_tile("2x2fwo2") and not C.is_zfirst_tile("4x2fwbo2")
