@@ -92,10 +92,10 @@ def f_factored_zfirst(n: int, nk: int, nq_: int) -> int:
 
 
 def is_zfirst_tile(desc: str) -> bool:
-    """Tiles "KxTNfz" (FP64, FP32) and "KxTNfwg" (split), optionally "o2",
-    take the line-point sums first."""
+    """Tiles "KxTNfz" (FP64, FP32) and "KxTNfwg" (split), optionally "o" and
+    the waves per SIMD, take the line-point sums first."""
     import re
-    return re.fullmatch(r"\d+x\d+f(z|wg)(o2)?", desc) is not None
+    return re.fullmatch(r"\d+x\d+f(z|wg)(o\d)?", desc) is not None
 
 
 def f_kf(p: int, rule: str = "collapsed") -> int:
@@ -165,10 +165,10 @@ def is_sf_tile(desc: str) -> bool:
 
 def is_kf_tile(desc: str) -> bool:
     """Tile descriptions "KxTNf", "KxTNfw", "KxTNfz" and (split forms)
-    "KxTNfwb" and "KxTNfwg", optionally "o2", name the triangle-point
-    contraction."""
+    "KxTNfwb" and "KxTNfwg", optionally "o" and the waves per SIMD, name the
+    triangle-point contraction."""
     import re
-    return re.fullmatch(r"\d+x\d+f(w[bg]?|z)?(o2)?", desc) is not None
+    return re.fullmatch(r"\d+x\d+f(w[bg]?|z)?(o\d)?", desc) is not None
 
 
 def f_kernel(p: int, rule: str, desc: str) -> int:

@@ -303,7 +303,7 @@ static void describe_variant(const FwdVariant &v, char *buf, size_t len) {
         std::snprintf(buf, len, "%dx%d%s%s", v.tm, v.tn,
                       v.staged == 1 ? "s" : v.staged == 2 ? "sa" : v.staged == 4 ? "p"
                       : v.staged == 5 ? "c" : v.staged == 6 ? "f" : v.staged == 7 ? "y" : v.staged == 13 ? "fw" : v.staged == 14 ? "fwb" : v.staged == 15 ? "fwg" : v.staged == 16 ? "fz" : "",
-                      v.minw > 1 ? "o2" : "");
+                      v.minw > 1 ? ("o" + std::to_string(v.minw)).c_str() : "");
 }
 
 feint_status feint_rule_tile_describe(int p, feint_form form, feint_rule rule, int tile, char *buf, size_t len) {

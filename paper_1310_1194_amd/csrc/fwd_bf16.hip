@@ -20,9 +20,9 @@ const FwdVariant v4[] = {
     FEINT_K32S(4, BF16X3, 5, 5, true, 1),
     FEINT_K32U(4, BF16X3, 5, 3, 1),
     FEINT_K32P(4, BF16X3, 5, 3, 1),
+    FEINT_KF2G(4, 3, 3, 3),
     FEINT_KF2G(4, 5, 3, 2),
-    FEINT_KF2G(4, 3, 3, 2),
-    FEINT_KF2G(4, 5, 1, 2)};
+    FEINT_KF2G(4, 5, 1, 3)};
 const FwdVariant v5[] = {
     FEINT_KF2G(5, 3, 2, 2),
     FEINT_K32S(5, BF16X3, 8, 4, false, 1),

@@ -187,7 +187,7 @@ def test_kf_tile_names():
     """Both triangle-point contractions (one wave per block "KxTNf", shared
     point blocks "KxTNfw") are priced with the factorised count."""
     from paper_1310_1194_amd import costmodel
-    for d in ("5x5f", "5x3fo2", "5x3fwo2", "3x5fw", "2x2fwo2", "4x2fwbo2", "4x2fwgo2", "2x2fzo2"):
+    for d in ("5x5f", "5x3fo2", "5x3fwo2", "3x5fw", "2x2fwo2", "4x2fwbo2", "4x2fwgo2", "2x2fzo2", "3x3fwgo3"):
         assert costmodel.is_kf_tile(d)
     for d in ("5x5", "5x5yo2", "v1o2", "ref1o2", "5x3fwx"):
         assert not costmodel.is_kf_tile(d)
