@@ -428,7 +428,10 @@ def bench_forward(args, fields=False, kind=None, err_idx=None, cpu_budget=None):
                      "fdom_per_launch": fdom * ne,
                      "hw_mfma_frac": hw_flops / (h["kernel_ms_mean"] * 1e-3) / (PEAK_TFLOPS[headline] * 1e12),
                      "alg_bytes_per_launch": alg_bytes,
-                     "note": ("algorithmic flops of the triangle-point contraction per element "
+                     "note": ("algorithmic flops of the triangle-point contraction with the line-point sums "
+                              "first per element (8 n^2 nij + 26 (p+1)^3 nij + 32 (p+1) n nij)"
+                              if kf and costmodel.is_zfirst_tile(h["tile"]) else
+                              "algorithmic flops of the triangle-point contraction per element "
                               "(8 n^2 nij + 8 (p+1)^2 nij n + 24 nq ntri + 12 nq n)" if kf else
                               "algorithmic flops of the reference-matrix GEMM per element (26 n^2 + n)" if tref else
                               "algorithmic flops 8 n^2 nq per element (one product per entry; "
