@@ -64,7 +64,7 @@ feint_status prepare_tables(int p, int rule, int type) {
     const size_t s_m64 = align(H.Mref.size() * 8), s_m32 = align(H.Mref32.size() * 4);
     const size_t s_tb = align(H.taub_hi.size() * 2);
     const size_t total = s_tau + s_tau32 + s_lam + s_lam32 + s_qw + s_gll + 2 * s_b64 + 3 * s_b32 + 4 * s_sp + s_ycf +
-                         s_m64 + s_m32 + 2 * s_tb;
+                         s_m64 + s_m32 + 4 * s_tb;
     char *base = nullptr;
     e = hipMalloc((void **)&base, total);
     if (e != hipSuccess) { set_error("hipMalloc(tables)", e); return FEINT_ERR_HIP; }
@@ -102,6 +102,11 @@ feint_status prepare_tables(int p, int rule, int type) {
     T->Mref32 = (const float *)put(H.Mref32.data(), H.Mref32.size() * 4, s_m32);
     T->taubh = (const uint16_t *)put(H.taub_hi.data(), H.taub_hi.size() * 2, s_tb);
     T->taubl = (const uint16_t *)put(H.taub_lo.data(), H.taub_lo.size() * 2, s_tb);
+    T->tauhh = (const uint16_t *)put(H.tauh_hi.data(), H.tauh_hi.size() * 2, s_tb);
+    T->tauhl = (const uint16_t *)put(H.tauh_lo.data(), H.tauh_lo.size() * 2, s_tb);
+    T->tau_f16_shift = H.tau_f16_shift;
+    T->f16_zc = (float)H.f16_zc;
+    T->f16_zb = (float)H.f16_zb;
     T->base = base;
     e = hipMemcpy(base, host.data(), total, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -147,7 +152,11 @@ void fill_fwd_params(FwdParams &prm, const feint_elements *el, int form, const D
     prm.qw = T->qw; prm.gll = T->gll; prm.tau64 = T->tau64; prm.tau32 = T->tau32; prm.lam = T->lam; prm.lam32 = T->lam32;
     prm.B64 = T->B64; prm.B32 = T->B32; prm.Bc32 = T->Bc32; prm.Ycf = T->Ycf;
     prm.Mref64 = T->Mref64; prm.Mref32 = T->Mref32;
-    prm.taubh = T->taubh; prm.taubl = T->taubl;
+    prm.taubh = form == FEINT_FP16X3 ? T->tauhh : T->taubh;
+    prm.taubl = form == FEINT_FP16X3 ? T->tauhl : T->taubl;
+    prm.tau_f16_shift = T->tau_f16_shift;
+    prm.f16_zc = T->f16_zc;
+    prm.f16_zb = T->f16_zb;
     prm.Bhi = form == FEINT_FP16X3 ? T->hf_hi : T->bf_hi;
     prm.Blo = form == FEINT_FP16X3 ? T->hf_lo : T->bf_lo;
     prm.bmax = T->bmax;

@@ -21,7 +21,9 @@ struct DevTables {
     const float *Ycf;
     const double *Mref64;
     const float *Mref32;
-    const uint16_t *taubh, *taubl;
+    const uint16_t *taubh, *taubl, *tauhh, *tauhl;
+    int tau_f16_shift;
+    float f16_zc, f16_zb;
     void *base;
 };
 

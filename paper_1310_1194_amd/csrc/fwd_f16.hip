@@ -18,18 +18,23 @@ const FwdVariant v4[] = {
     FEINT_K32U(4, FP16X3, 5, 5, 1),
     FEINT_K32S(4, FP16X3, 5, 5, true, 1),
     FEINT_K32U(4, FP16X3, 5, 3, 1),
-    FEINT_K32P(4, FP16X3, 5, 5, 1)};
+    FEINT_K32P(4, FP16X3, 5, 5, 1),
+    FEINT_KF2GH(4, 3, 3, 3)};
 const FwdVariant v5[] = {
+    FEINT_KF2GH(5, 3, 2, 2),
     FEINT_K32S(5, FP16X3, 8, 4, false, 1),
     FEINT_K32S(5, FP16X3, 8, 4, true, 1),
     FEINT_K32S(5, FP16X3, 4, 4, false, 2),
     FEINT_K32U(5, FP16X3, 8, 4, 1)};
 const FwdVariant v6[] = {
+    FEINT_KF2GH(6, 7, 1, 2),
     FEINT_K32S(6, FP16X3, 13, 2, false, 2),
     FEINT_K32S(6, FP16X3, 13, 2, false, 1),
     FEINT_K32S(6, FP16X3, 7, 4, false, 1),
     FEINT_K32U(6, FP16X3, 13, 2, 1)};
 const FwdVariant v7[] = {
+    FEINT_KF2GH(7, 4, 1, 2),
+    FEINT_KF2GH(7, 4, 2, 2),
     FEINT_K32Y(7, FP16X3, 3, 3, 2, 1),
     FEINT_K32Y(7, FP16X3, 6, 3, 1, 1),
     FEINT_K32Y(7, FP16X3, 6, 6, 1, 1),

@@ -630,7 +630,7 @@ struct KF2S {
 // values in place of about 70.  The load vector's zeta sum
 // sum_m lam_0(k, m) w det J f rides in the G block of column k' = 0 and is
 // added on the spare column, whose tau values are zero.  Otherwise as KF2S.
-template <int P, int TMK, int TN, int R = 0, class G = PrismGeo>
+template <int P, int TMK, int TN, int R = 0, class G = PrismGeo, int FORM = BF16X3>
 struct KF2G {
     typedef KF<P, float, TMK, TN, R, G> F;
     typedef KF2<P, float, TMK, TN, R, G> K2;
@@ -650,11 +650,37 @@ struct KF2G {
         Area el[EPW];
         float gs[4][4 * GST];                          // per wave, per lane group
     };
-    typedef bf16x8 HV;
-    typedef K32<P, BF16X3, 1, 1, R, G> Split;          // split8: hi = rn(y), lo = rn(y - hi)
+    typedef typename SplitT<FORM>::vec HV;
+    typedef K32<P, FORM, 1, 1, R, G> Split;            // split8: hi = rn(y), lo = rn(y - hi)
+    // fp16 form: the triangle table holds tau * 2^tau_f16_shift, and a block's
+    // Z values are scaled by powers of two that place bounds on them in
+    // [2^13, 2^14): ys from the element's largest |W| entry, yb (the
+    // load-vector column) from its largest |w det J f|; undone at the store
+    struct Scales { float ys, yb; };
+    __device__ static Scales scales(const FwdParams &prm, const ElemArea &ea) {
+        if constexpr (FORM != FP16X3) {
+            return Scales{1.0f, 1.0f};
+        } else {
+            const int lane = threadIdx.x & 63;
+            float wm = 0.0f;
+            double sm = 0.0;
+            for (int q = lane; q < NQ; q += 64) {
+#pragma unroll
+                for (int x = 0; x < 16; ++x) wm = fmaxf(wm, fabsf(ea.W[q][x]));
+                sm = fmax(sm, fabs(ea.sf[q]));
+            }
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                wm = fmaxf(wm, __shfl_xor(wm, off, 64));
+                sm = fmax(sm, __shfl_xor(sm, off, 64));
+            }
+            return Scales{pow2_scale((double)wm * prm.f16_zc), pow2_scale(sm * prm.f16_zb)};
+        }
+    }
 
     template <int TMV, int TNV, bool LB>
-    __device__ static void body(const FwdParams &prm, int64_t slot, int bi, int bj, const ElemArea &ea, float *gs) {
+    __device__ static void body(const FwdParams &prm, int64_t slot, int bi, int bj, const ElemArea &ea, float *gs,
+                                Scales sc) {
         constexpr int NC = 2 * TMV * TNV, NCL = (NC + 15) / 16;
         const int lane = threadIdx.x & 63;
         const int i16 = lane & 15, g = lane >> 4;
@@ -664,6 +690,7 @@ struct KF2G {
         const float *lam = prm.lam32;                  // [r][k][m]; rows 0..2 hold L, row 3 dL
         const int tcol = tt * 16 + i16;
         const bool lcol = LB && i16 == LCL;
+        const float zs = (LB && lcol) ? sc.yb : sc.ys;    // this lane's column: the load vector or A
         // this lane's combinations for the zeta sums, c = i16 + 16 cl: triangle
         // point ch of its group's pair, row k0 + ck, column kp0 + cj (lanes
         // past NC repeat combination 0 and store nothing)
@@ -704,7 +731,7 @@ struct KF2G {
             for (int h = 0; h < 2; ++h) {
                 const int ij = c8 * 8 + 2 * g + h;
 #pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4) tb[h][s4] = ij < NIJ ? tau[((size_t)ij * 4 + s4) * TP + tcol] : 0.0f;
+                for (int s4 = 0; s4 < 4; ++s4) tb[h][s4] = ij < NIJ ? tau[((size_t)ij * 4 + s4) * TP + tcol] * zs : 0.0f;
             }
             // G of this lane's combinations; the previous chunk's reads come
             // first.  A wave's LDS operations execute in order, so the fences only
@@ -745,7 +772,7 @@ struct KF2G {
                         const f32x4 a = gp[0], b = gp[1], cc = gp[2], d = gp[3];
                         const float *t = tb[h];
                         float z0 = a[0] * t[0] + a[1] * t[1] + a[2] * t[2] + a[3] * t[3];
-                        if (LB && tj == 0) z0 += lcol ? b[3] : 0.0f;   // the load-vector column
+                        if (LB && tj == 0) z0 += lcol ? b[3] * zs : 0.0f;   // the load-vector column
                         z[4 * h + 0] = z0;
                         z[4 * h + 1] = b[0] * t[1] + b[1] * t[2] + b[2] * t[3];
                         z[4 * h + 2] = cc[0] * t[1] + cc[1] * t[2] + cc[2] * t[3];
@@ -763,6 +790,8 @@ struct KF2G {
         }
         float *Aout = (float *)prm.A + offA_of(prm, e, N);
         float *bout = (float *)prm.b + offb_of(prm, e, N);
+        const float tu = FORM == FP16X3 ? ldexpf(1.0f, -prm.tau_f16_shift) : 1.0f;
+        const float ua = tu / sc.ys, ub = tu / sc.yb;
 #pragma unroll
         for (int k = 0; k < TMV; ++k)
 #pragma unroll
@@ -775,28 +804,29 @@ struct KF2G {
                         if (tr >= NTRI) continue;
                         const int row = (k0 + k) * NTRI + tr;
                         if (tj == 0 && lcol)
-                            bout[row] = acc[k][ti][tj][r];
+                            bout[row] = acc[k][ti][tj][r] * ub;
                         else if (tcol < NTRI)
-                            Aout[(size_t)row * N + (kp0 + tj) * NTRI + tcol] = acc[k][ti][tj][r];
+                            Aout[(size_t)row * N + (kp0 + tj) * NTRI + tcol] = acc[k][ti][tj][r] * ua;
                     }
     }
 
     template <int TMV, int TNV>
-    __device__ static void with_lb(bool lb, const FwdParams &prm, int64_t slot, int bi, int bj, const ElemArea &ea, float *gs) {
-        if (lb) body<TMV, TNV, true>(prm, slot, bi, bj, ea, gs);
-        else body<TMV, TNV, false>(prm, slot, bi, bj, ea, gs);
+    __device__ static void with_lb(bool lb, const FwdParams &prm, int64_t slot, int bi, int bj, const ElemArea &ea, float *gs,
+                                   Scales sc) {
+        if (lb) body<TMV, TNV, true>(prm, slot, bi, bj, ea, gs, sc);
+        else body<TMV, TNV, false>(prm, slot, bi, bj, ea, gs, sc);
     }
-    __device__ static void one_block(const FwdParams &prm, int64_t slot, int blk, const ElemArea &ea, float *gs) {
+    __device__ static void one_block(const FwdParams &prm, int64_t slot, int blk, const ElemArea &ea, float *gs, Scales sc) {
         constexpr int TML = NK - (BM - 1) * TMK, TNL = NK - (BK - 1) * TN;
         const int bi = blk / BN, bj = blk % BN;
         const bool lastm = TML != TMK && bi == BM - 1, lastn = TNL != TN && bj % BK == BK - 1;
         const bool lb = G::LOAD && bj % BK == 0 && bj / BK == LCT;
         if (lastm) {
-            if (lastn) with_lb<TML, TNL>(lb, prm, slot, bi, bj, ea, gs);
-            else with_lb<TML, TN>(lb, prm, slot, bi, bj, ea, gs);
+            if (lastn) with_lb<TML, TNL>(lb, prm, slot, bi, bj, ea, gs, sc);
+            else with_lb<TML, TN>(lb, prm, slot, bi, bj, ea, gs, sc);
         } else {
-            if (lastn) with_lb<TMK, TNL>(lb, prm, slot, bi, bj, ea, gs);
-            else with_lb<TMK, TN>(lb, prm, slot, bi, bj, ea, gs);
+            if (lastn) with_lb<TMK, TNL>(lb, prm, slot, bi, bj, ea, gs, sc);
+            else with_lb<TMK, TN>(lb, prm, slot, bi, bj, ea, gs, sc);
         }
     }
     __device__ static void run_coop(const FwdParams &prm, int64_t slot, int wv, int wave, bool live, Smem &sm) {
@@ -804,7 +834,8 @@ struct KF2G {
         K2::geometry(prm, slot, wv, live, ea);
         __syncthreads();
         if (!live) return;
-        for (int blk = wv; blk < NB; blk += WPE) one_block(prm, slot, blk, ea, sm.gs[wave]);
+        const Scales sc = scales(prm, ea);
+        for (int blk = wv; blk < NB; blk += WPE) one_block(prm, slot, blk, ea, sm.gs[wave], sc);
     }
 };
 

@@ -111,6 +111,10 @@ int64_t items_of(int64_t ne) { return items_for<KER>(ne); }
 #define FEINT_KF2G_R(P, TMK, TN, W, R) \
     FwdVariant{TMK, TN, 15, W, &launch_coop<KF2G<P, TMK, TN, R>, W>, &items_of<KF2G<P, TMK, TN, R>>}
 #define FEINT_KF2G(P, TMK, TN, W) FEINT_KF2G_R(P, TMK, TN, W, 0)
+#define FEINT_KF2GH_R(P, TMK, TN, W, R)                                                            \
+    FwdVariant{TMK, TN, 15, W, &launch_coop<KF2G<P, TMK, TN, R, PrismGeo, FP16X3>, W>,          \
+               &items_of<KF2G<P, TMK, TN, R, PrismGeo, FP16X3>>}
+#define FEINT_KF2GH(P, TMK, TN, W) FEINT_KF2GH_R(P, TMK, TN, W, 0)
 // FP64 / FP32 with the zeta sums taken first (staged = 16)
 #define FEINT_KF2Z_R(P, T, TMK, TN, IJB, W, R)                                                     \
     FwdVariant{TMK, TN, 16, W, &launch_coop<KF2Z<P, T, TMK, TN, IJB, R>, W>,                    \

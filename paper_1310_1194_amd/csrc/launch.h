@@ -25,8 +25,10 @@ struct FwdParams {
     const float *Ycf;        // [nkb][npad/16][64][8] FP32 columns in B-fragment order
     const double *Mref64;    // tetrahedra: reference matrices [16][n*n padded to 16] and load vector [n]
     const float *Mref32;
-    const uint16_t *taubh;   // prisms: triangle factors split into bf16 hi / lo, A-fragment order
-    const uint16_t *taubl;
+    const uint16_t *taubh;   // prisms: triangle factors split into hi / lo, A-fragment order (bf16;
+    const uint16_t *taubl;   //   fp16 of tau * 2^tau_f16_shift for the fp16 form)
+    int tau_f16_shift;
+    float f16_zc, f16_zb;    // fp16 form: |Z| <= f16_zc max|W|, load-vector zeta sums <= f16_zb max|w det J f|
     float bmax;              // max |B| (fp16 form: used for the per-element scale)
     int f16_shift;           // fp16 tables hold B * 2^f16_shift
     // mixed-degree launches: element ids in bucket order and packed offsets

@@ -526,6 +526,31 @@ HostTables build_tables(int p, int rule) {
         const int nch = (T.nij + 7) / 8, tt = T.tpad / 16;
         T.taub_hi.assign((size_t)nch * tt * 64 * 8, 0);
         T.taub_lo.assign((size_t)nch * tt * 64 * 8, 0);
+        T.tauh_hi.assign((size_t)nch * tt * 64 * 8, 0);
+        T.tauh_lo.assign((size_t)nch * tt * 64 * 8, 0);
+        double tmax = 0.0;
+        for (double v : T.tau64) tmax = std::fmax(tmax, std::fabs(v));
+        T.tau_f16_shift = tmax > 0.0 ? 13 - (int)std::floor(std::log2(tmax)) : 0;
+        const double ts = std::ldexp(1.0, T.tau_f16_shift);
+        // |Z| = |sum_s tau_s G[r][s]| <= max|tau| sum_s sum_m |lam_r(k,m) lam_s(k',m)| |W_m[r][s]|
+        //     <= 4 max|tau| max_{r,s,k,k'} sum_m |lam_r(k,m) lam_s(k',m)| max|W|
+        double lr = 0.0, l0 = 0.0;
+        for (int r = 0; r < 4; ++r)
+            for (int q = 0; q < 4; ++q)
+                for (int k = 0; k < nk; ++k)
+                    for (int kp = 0; kp < nk; ++kp) {
+                        double a = 0.0;
+                        for (int m = 0; m < nk; ++m)
+                            a += std::fabs(T.lam[((size_t)r * nk + k) * nk + m] * T.lam[((size_t)q * nk + kp) * nk + m]);
+                        lr = std::fmax(lr, a);
+                    }
+        for (int k = 0; k < nk; ++k) {
+            double a = 0.0;
+            for (int m = 0; m < nk; ++m) a += std::fabs(T.lam[(size_t)k * nk + m]);
+            l0 = std::fmax(l0, a);
+        }
+        T.f16_zc = 4.0 * tmax * lr;
+        T.f16_zb = l0;
         for (int c = 0; c < nch; ++c)
             for (int ti = 0; ti < tt; ++ti)
                 for (int l = 0; l < 64; ++l)
@@ -537,6 +562,10 @@ HostTables build_tables(int p, int rule) {
                         const uint16_t h = to_bf16((float)x);
                         T.taub_hi[o] = h;
                         T.taub_lo[o] = to_bf16((float)(x - (double)from_bf16(h)));
+                        const double xs = x * ts;
+                        const uint16_t hh = to_f16(xs);
+                        T.tauh_hi[o] = hh;
+                        T.tauh_lo[o] = to_f16(xs - from_f16(hh));
                     }
     }
     return T;

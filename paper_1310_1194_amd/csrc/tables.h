@@ -41,6 +41,12 @@ struct HostTables {
     // [64 lanes][8]: lane l, value v holds tau_r(t, ij) with t = 16 tile + l%16,
     // ij = 8 chunk + 2 (l/16) + v/4, r = v%4 (zero past the last triangle point)
     std::vector<uint16_t> taub_hi, taub_lo;
+    // the same in fp16, of tau * 2^tau_f16_shift (max |tau| * 2^shift in [2^13, 2^14))
+    std::vector<uint16_t> tauh_hi, tauh_lo;
+    int tau_f16_shift = 0;
+    // fp16 form's bounds: |Z| <= f16_zc * max |W entry| of the element, and the
+    // load vector's zeta sums <= f16_zb * max |w det J f|
+    double f16_zc = 0.0, f16_zb = 0.0;
     std::vector<double> B64;         // [nqp][4][npad]  rows: phi, d/dxi1, d/dxi2, d/dzeta
     std::vector<float> B32;          // same, rounded to FP32
     std::vector<double> BT64;        // [npad][nqp*4]  transpose of B64 (shape-function major)
