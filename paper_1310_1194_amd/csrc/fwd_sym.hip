@@ -37,9 +37,9 @@ const FwdVariant h1[] = {FEINT_K32S_R(1, FP16X3, 1, 1, true, 1, S)};
 const FwdVariant h2[] = {FEINT_K32S_R(2, FP16X3, 2, 2, true, 1, S)};
 const FwdVariant h3[] = {FEINT_K32S_R(3, FP16X3, 3, 3, true, 1, S)};
 const FwdVariant h4[] = {FEINT_K32P_R(4, FP16X3, 5, 5, 1, S), FEINT_K32U_R(4, FP16X3, 5, 3, 2, S)};
-const FwdVariant h5[] = {FEINT_K32S_R(5, FP16X3, 8, 4, false, 1, S), FEINT_K32U_R(5, FP16X3, 8, 4, 1, S)};
-const FwdVariant h6[] = {FEINT_K32S_R(6, FP16X3, 13, 2, false, 2, S), FEINT_K32U_R(6, FP16X3, 13, 2, 1, S)};
-const FwdVariant h7[] = {FEINT_K32P_R(7, FP16X3, 6, 6, 1, S), FEINT_K32P_R(7, FP16X3, 3, 6, 1, S)};
+const FwdVariant h5[] = {FEINT_K32S_R(5, FP16X3, 8, 4, false, 1, S), FEINT_KF2GH_R(5, 3, 2, 2, S), FEINT_K32U_R(5, FP16X3, 8, 4, 1, S)};
+const FwdVariant h6[] = {FEINT_KF2GH_R(6, 7, 1, 2, S), FEINT_K32S_R(6, FP16X3, 13, 2, false, 2, S), FEINT_K32U_R(6, FP16X3, 13, 2, 1, S)};
+const FwdVariant h7[] = {FEINT_KF2GH_R(7, 4, 2, 2, S), FEINT_KF2GH_R(7, 4, 1, 2, S), FEINT_K32P_R(7, FP16X3, 6, 6, 1, S), FEINT_K32P_R(7, FP16X3, 3, 6, 1, S)};
 
 #define FEINT_PICK(a1, a2, a3, a4, a5, a6, a7)                  \
     switch (p) {                                                 \
