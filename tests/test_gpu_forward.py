@@ -120,6 +120,40 @@ def test_empty_batch(torch_cuda):
     assert A.shape == (0, 18, 18) and b.shape == (0, 18)
 
 
+@pytest.mark.parametrize("form", ["bf16x3", "fp16x3"])
+@pytest.mark.parametrize("p", [4, 5, 7])
+def test_split_forms_per_element_scale(torch_cuda, p, form):
+    """The split forms on elements whose coefficients span eight orders of
+    magnitude (D, beta, c scaled together by 10^u, u ~ U(-4, 4) per element)
+    and whose source term spans another eight independently (f by 10^v,
+    v ~ U(-6, 2)): every compiled tile against the oracle, per element.  The
+    fp16 form's power-of-two scales are chosen per element (A and the load
+    vector separately), so the relative error per element must stay at the
+    unscaled batch's level."""
+    import oracle
+    import paper_1310_1194_amd as F
+    from paper_1310_1194_amd.meshgen import Batch
+    b0 = small_batch(p, seed=11)
+    rng = np.random.default_rng(1000 + p)
+    sa = 10.0 ** rng.uniform(-4.0, 4.0, b0.ne)
+    sf = 10.0 ** rng.uniform(-6.0, 2.0, b0.ne)
+    batch = Batch(b0.coords, np.ascontiguousarray(b0.D * sa[:, None, None]),
+                  np.ascontiguousarray(b0.beta * sa[:, None]), np.ascontiguousarray(b0.c * sa),
+                  np.ascontiguousarray(b0.f * sf))
+    Ar, br, _ = oracle_of(batch, p)
+    X = to_dev(batch)
+    for tile in range(F.tile_count(p, form)):
+        F.tile_set(p, form, tile)
+        flush(f"[scale] p={p} form={form} tile={F.tile_describe(p, form, tile)} ne={batch.ne}")
+        A, b = F.integrate_raw(*X, p, form)
+        torch_cuda.cuda.synchronize()
+        eA = elem_errors(A.cpu().numpy(), Ar)
+        eb = elem_errors(b.cpu().numpy(), br)
+        flush(f"    max-elem A {eA.max():.3e}  b {eb.max():.3e}")
+        assert eA.max() <= TOL[form][1] and eb.max() <= BTOL[form][1]
+    F.tile_set(p, form, 0)
+
+
 FULL = [("p1_4096", "fp64"), ("p1_524288", "fp64"), ("p1_524288", "fp32")] + \
     [(w, f) for w in ("p4_131072", "p7_16384") for f in ("fp64", "fp32", "bf16x3", "fp16x3")]
 
