@@ -36,6 +36,7 @@ const FwdVariant v4[] = {
     FEINT_K4U(4, float, 5, 5, 1),
     FEINT_KSC(4, float, 5, 5, 1)};
 const FwdVariant v5[] = {
+    FEINT_KF2Z(5, float, 3, 2, 4, 2),
     FEINT_KF2(5, float, 6, 3, 2),
     FEINT_KF_R(5, float, 6, 6, 1, 0),
     FEINT_KF_R(5, float, 6, 3, 1, 0),
