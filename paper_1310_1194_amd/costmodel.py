@@ -165,10 +165,10 @@ def is_sf_tile(desc: str) -> bool:
 
 def is_kf_tile(desc: str) -> bool:
     """Tile descriptions "KxTNf", "KxTNfw", "KxTNfz" and (split forms)
-    "KxTNfwb" and "KxTNfwg", optionally "o" and the waves per SIMD, name the
-    triangle-point contraction."""
+    "KxTNfwg", optionally "o" and the waves per SIMD, name the triangle-point
+    contraction."""
     import re
-    return re.fullmatch(r"\d+x\d+f(w[bg]?|z)?(o\d)?", desc) is not None
+    return re.fullmatch(r"\d+x\d+f(wg?|z)?(o\d)?", desc) is not None
 
 
 def f_kernel(p: int, rule: str, desc: str) -> int:

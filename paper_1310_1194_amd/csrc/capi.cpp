@@ -311,7 +311,7 @@ static void describe_variant(const FwdVariant &v, char *buf, size_t len) {
     else
         std::snprintf(buf, len, "%dx%d%s%s", v.tm, v.tn,
                       v.staged == 1 ? "s" : v.staged == 2 ? "sa" : v.staged == 4 ? "p"
-                      : v.staged == 5 ? "c" : v.staged == 6 ? "f" : v.staged == 7 ? "y" : v.staged == 13 ? "fw" : v.staged == 14 ? "fwb" : v.staged == 15 ? "fwg" : v.staged == 16 ? "fz" : "",
+                      : v.staged == 5 ? "c" : v.staged == 6 ? "f" : v.staged == 7 ? "y" : v.staged == 13 ? "fw" : v.staged == 15 ? "fwg" : v.staged == 16 ? "fz" : "",
                       v.minw > 1 ? ("o" + std::to_string(v.minw)).c_str() : "");
 }
 

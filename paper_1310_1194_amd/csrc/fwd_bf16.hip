@@ -40,8 +40,6 @@ const FwdVariant v6[] = {
 const FwdVariant v7[] = {
     FEINT_KF2G(7, 4, 2, 2),
     FEINT_KF2G(7, 4, 1, 2),
-    FEINT_KF2S(7, 4, 2, 2),
-    FEINT_KF2S(7, 4, 1, 2),
     FEINT_K32Y(7, BF16X3, 3, 3, 2, 1),
     FEINT_K32Y(7, BF16X3, 6, 3, 1, 1),
     FEINT_K32Y(7, BF16X3, 6, 6, 1, 1),

@@ -456,171 +456,13 @@ struct KF2 {
     }
 };
 
-// The split form (bf16x3) of the shared-point-block contraction.  The main
-// product takes eight triangle points per 16x16x32 MFMA: K = (triangle point
-// 2 g + v/4 of the chunk, row r = v%4) for lane group g and value v, so the A
-// operand is the triangle-factor table split on the host (hi + lo bf16, in
-// fragment order) and each lane forms Z_k[(ij, r)][col] for its eight K slots
-// (the same Y and Z arithmetic as the FP32 form, r now running inside the
-// lane, so the row factors lam_r(k, m) are wave-uniform scalar operands),
-// splits it and issues hi*hi + hi*lo + lo*hi per tile.  Per eight triangle
-// points and tile: 3 MFMAs of 16 cycles where the FP32 form issues 8 of 32.
-// The point blocks are formed once per element into LDS as in KF2.
-template <int P, int TMK, int TN, int R = 0, class G = PrismGeo>
-struct KF2S {
-    typedef KF<P, float, TMK, TN, R, G> F;
-    typedef KF2<P, float, TMK, TN, R, G> K2;
-    static constexpr int N = F::N, NK = F::NK, NTRI = F::NTRI, TT = F::TT, TP = F::TP, NQ = F::NQ, NIJ = F::NIJ;
-    static constexpr int BM = F::BM, BK = F::BK, BN = F::BN, NB = F::NBLK;
-    static constexpr int NCH = (NIJ + 7) / 8;          // chunks of eight triangle points
-    static constexpr int WPE = K2::WPE, EPW = K2::EPW;
-    static constexpr int EPI = 1, NBLK = WPE;
-    static constexpr int LCT = F::LCT, LCL = F::LCL;
-    static_assert(F::SPARE, "the load vector rides in a spare padded column");
-    typedef typename K2::ElemArea ElemArea;
-    typedef typename K2::Smem Smem;
-    typedef bf16x8 HV;
-    typedef K32<P, BF16X3, 1, 1, R, G> Split;          // split8: hi = rn(y), lo = rn(y - hi)
-
-    template <int TMV, int TNV, bool LB>
-    __device__ static void body(const FwdParams &prm, int64_t slot, int bi, int bj, const ElemArea &ea) {
-        const int lane = threadIdx.x & 63;
-        const int i16 = lane & 15, g = lane >> 4;
-        const int k0 = bi * TMK, tt = bj / BK, kp0 = (bj - tt * BK) * TN;
-        const int64_t e = elem_of(prm, slot);
-        const float *tau = prm.tau32;
-        typedef const __attribute__((address_space(4))) float CT;
-        const CT *lam = (const CT *)prm.lam32;              // [r][k][m], wave-uniform reads
-        const CT *lv = lam + (size_t)kp0 * NK, *ld = lam + (size_t)(3 * NK + kp0) * NK;
-        const int tcol = tt * 16 + i16;
-        const bool lcol = LB && i16 == LCL;
-        f32x4 acc[TMV][TT][TNV];
-#pragma unroll
-        for (int k = 0; k < TMV; ++k)
-#pragma unroll
-            for (int ti = 0; ti < TT; ++ti)
-#pragma unroll
-                for (int tj = 0; tj < TNV; ++tj) acc[k][ti][tj] = f32x4{0, 0, 0, 0};
-        for (int c = 0; c < NCH; ++c) {
-            HV ah[TT], al[TT];
-#pragma unroll
-            for (int ti = 0; ti < TT; ++ti) {
-                const size_t o = (((size_t)c * TT + ti) * 64 + lane) * 8;
-                ah[ti] = *(const HV *)(prm.taubh + o);
-                al[ti] = *(const HV *)(prm.taubl + o);
-            }
-            float zf[TMV][TNV][8];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int ij = c * 8 + 2 * g + h;
-                const bool ok = ij < NIJ;
-                float tb[4];
-#pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4) tb[s4] = ok ? tau[((size_t)ij * 4 + s4) * TP + tcol] : 0.0f;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int v = 4 * h + r;
-                    // keep each (point, row) slot's scalar loads inside it: hoisted above
-                    // the earlier slots they would be live together and spill
-                    __builtin_amdgcn_sched_barrier(0);
-                    float u[NK], w3[NK], sfm[NK];
-#pragma unroll
-                    for (int m = 0; m < NK; ++m) {
-                        if (ok) {
-                            const float *wr = &ea.W[m * NIJ + ij][4 * r];
-                            u[m] = wr[0] * tb[0] + wr[1] * tb[1] + wr[2] * tb[2];
-                            w3[m] = wr[3] * tb[3];
-                            sfm[m] = (LB && r == 0 && lcol) ? (float)ea.sf[m * NIJ + ij] : 0.0f;
-                        } else {
-                            u[m] = 0.0f;
-                            w3[m] = 0.0f;
-                            sfm[m] = 0.0f;
-                        }
-                    }
-#pragma unroll
-                    for (int tj = 0; tj < TNV; ++tj) {
-                        float y[NK];
-#pragma unroll
-                        for (int m = 0; m < NK; ++m) {
-                            const float yv = lv[tj * NK + m] * u[m] + ld[tj * NK + m] * w3[m];
-                            y[m] = (LB && tj == 0) ? yv + sfm[m] : yv;   // the load-vector column
-                        }
-                        // row factors through an opaque copy of the pointer, read where used
-                        // (hoisted, all 4 NK TMV of them would overflow the scalar registers)
-                        const CT *lr = fresh(lam) + (size_t)(r * NK + k0) * NK;
-#pragma unroll
-                        for (int k = 0; k < TMV; ++k) {
-                            float z = 0.0f;
-#pragma unroll
-                            for (int m = 0; m < NK; ++m) z += lr[k * NK + m] * y[m];
-                            zf[k][tj][v] = z;
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < TMV; ++k)
-#pragma unroll
-                for (int tj = 0; tj < TNV; ++tj) {
-                    HV zh, zl;
-                    Split::split8(zf[k][tj], zh, zl);
-#pragma unroll
-                    for (int ti = 0; ti < TT; ++ti) {
-                        acc[k][ti][tj] = mfma32(ah[ti], zl, acc[k][ti][tj]);
-                        acc[k][ti][tj] = mfma32(al[ti], zh, acc[k][ti][tj]);
-                        acc[k][ti][tj] = mfma32(ah[ti], zh, acc[k][ti][tj]);
-                    }
-                }
-        }
-        float *Aout = (float *)prm.A + offA_of(prm, e, N);
-        float *bout = (float *)prm.b + offb_of(prm, e, N);
-#pragma unroll
-        for (int k = 0; k < TMV; ++k)
-#pragma unroll
-            for (int ti = 0; ti < TT; ++ti)
-#pragma unroll
-                for (int tj = 0; tj < TNV; ++tj)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int tr = ti * 16 + acc_row<float>(lane, r);
-                        if (tr >= NTRI) continue;
-                        const int row = (k0 + k) * NTRI + tr;
-                        if (tj == 0 && lcol)
-                            bout[row] = acc[k][ti][tj][r];
-                        else if (tcol < NTRI)
-                            Aout[(size_t)row * N + (kp0 + tj) * NTRI + tcol] = acc[k][ti][tj][r];
-                    }
-    }
-
-    template <int TMV, int TNV>
-    __device__ static void with_lb(bool lb, const FwdParams &prm, int64_t slot, int bi, int bj, const ElemArea &ea) {
-        if (lb) body<TMV, TNV, true>(prm, slot, bi, bj, ea);
-        else body<TMV, TNV, false>(prm, slot, bi, bj, ea);
-    }
-    __device__ static void one_block(const FwdParams &prm, int64_t slot, int blk, const ElemArea &ea) {
-        constexpr int TML = NK - (BM - 1) * TMK, TNL = NK - (BK - 1) * TN;
-        const int bi = blk / BN, bj = blk % BN;
-        const bool lastm = TML != TMK && bi == BM - 1, lastn = TNL != TN && bj % BK == BK - 1;
-        const bool lb = G::LOAD && bj % BK == 0 && bj / BK == LCT;
-        if (lastm) {
-            if (lastn) with_lb<TML, TNL>(lb, prm, slot, bi, bj, ea);
-            else with_lb<TML, TN>(lb, prm, slot, bi, bj, ea);
-        } else {
-            if (lastn) with_lb<TMK, TNL>(lb, prm, slot, bi, bj, ea);
-            else with_lb<TMK, TN>(lb, prm, slot, bi, bj, ea);
-        }
-    }
-    // the point blocks as in KF2 (FP32 W), then this form's contraction
-    __device__ static void run_coop(const FwdParams &prm, int64_t slot, int wv, int wave, bool live, Smem &sm) {
-        ElemArea &ea = sm.el[wave / WPE];
-        K2::geometry(prm, slot, wv, live, ea);
-        __syncthreads();
-        if (!live) return;
-        for (int blk = wv; blk < NB; blk += WPE) one_block(prm, slot, blk, ea);
-    }
-};
-
-// The split form with the zeta sum taken first.  Z_k[(ij, r)][(k', t')] =
+// The split forms (bf16x3, fp16x3) of the shared-point-block contraction,
+// with the zeta sum taken first.  The main product takes eight triangle
+// points per 16x16x32 MFMA: K = (triangle point 2 g + v/4 of the chunk, row
+// r = v%4) for lane group g and value v, so the A operand is the
+// triangle-factor table split on the host (hi + lo, in fragment order) and
+// each lane forms Z_k[(ij, r)][col] for its eight K slots, splits it and
+// issues hi*hi + hi*lo + lo*hi per tile.  Z_k[(ij, r)][(k', t')] =
 // sum_s tau_s(t', ij) G[r][s] with G[r][s] = sum_m lam_r(k, m) lam_s(k', m)
 // W_m(ij)[r][s]: G does not depend on the output column t', so each
 // (triangle point, k, k') combination of a lane group's pair of triangle
@@ -629,7 +471,8 @@ struct KF2S {
 // (W_m[r][0] = 0 for r >= 1) and its four tau values: 13 FMAs per eight Z
 // values in place of about 70.  The load vector's zeta sum
 // sum_m lam_0(k, m) w det J f rides in the G block of column k' = 0 and is
-// added on the spare column, whose tau values are zero.  Otherwise as KF2S.
+// added on the spare column, whose tau values are zero.  The point blocks
+// are formed once per element into LDS as in KF2.
 template <int P, int TMK, int TN, int R = 0, class G = PrismGeo, int FORM = BF16X3>
 struct KF2G {
     typedef KF<P, float, TMK, TN, R, G> F;

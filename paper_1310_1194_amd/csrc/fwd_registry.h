@@ -103,11 +103,7 @@ int64_t items_of(int64_t ne) { return items_for<KER>(ne); }
 #define FEINT_KF2_R(P, T, TMK, TN, W, R) \
     FwdVariant{TMK, TN, 13, W, &launch_coop<KF2<P, T, TMK, TN, R>, W>, &items_of<KF2<P, T, TMK, TN, R>>}
 #define FEINT_KF2(P, T, TMK, TN, W) FEINT_KF2_R(P, T, TMK, TN, W, 0)
-// the split form (bf16x3) of it (staged = 14)
-#define FEINT_KF2S_R(P, TMK, TN, W, R) \
-    FwdVariant{TMK, TN, 14, W, &launch_coop<KF2S<P, TMK, TN, R>, W>, &items_of<KF2S<P, TMK, TN, R>>}
-#define FEINT_KF2S(P, TMK, TN, W) FEINT_KF2S_R(P, TMK, TN, W, 0)
-// the same with the zeta sums taken first and shared through LDS (staged = 15)
+// the split forms of it with the zeta sums taken first and shared through LDS (staged = 15)
 #define FEINT_KF2G_R(P, TMK, TN, W, R) \
     FwdVariant{TMK, TN, 15, W, &launch_coop<KF2G<P, TMK, TN, R>, W>, &items_of<KF2G<P, TMK, TN, R>>}
 #define FEINT_KF2G(P, TMK, TN, W) FEINT_KF2G_R(P, TMK, TN, W, 0)

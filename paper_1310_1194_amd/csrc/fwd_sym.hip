@@ -31,7 +31,7 @@ const FwdVariant b3[] = {FEINT_K32S_R(3, BF16X3, 3, 3, true, 1, S)};
 const FwdVariant b4[] = {FEINT_K32P_R(4, BF16X3, 5, 5, 1, S), FEINT_K32U_R(4, BF16X3, 5, 3, 2, S)};
 const FwdVariant b5[] = {FEINT_KF2G_R(5, 3, 2, 2, S), FEINT_K32S_R(5, BF16X3, 8, 4, false, 1, S), FEINT_K32U_R(5, BF16X3, 8, 4, 1, S)};
 const FwdVariant b6[] = {FEINT_KF2G_R(6, 7, 1, 2, S), FEINT_K32S_R(6, BF16X3, 13, 2, false, 2, S), FEINT_K32U_R(6, BF16X3, 13, 2, 1, S)};
-const FwdVariant b7[] = {FEINT_KF2G_R(7, 4, 2, 2, S), FEINT_KF2G_R(7, 4, 1, 2, S), FEINT_KF2S_R(7, 4, 2, 2, S), FEINT_KF2S_R(7, 4, 1, 2, S), FEINT_K32P_R(7, BF16X3, 6, 6, 1, S), FEINT_K32P_R(7, BF16X3, 6, 3, 1, S)};
+const FwdVariant b7[] = {FEINT_KF2G_R(7, 4, 2, 2, S), FEINT_KF2G_R(7, 4, 1, 2, S), FEINT_K32P_R(7, BF16X3, 6, 6, 1, S), FEINT_K32P_R(7, BF16X3, 6, 3, 1, S)};
 // fp16x3
 const FwdVariant h1[] = {FEINT_K32S_R(1, FP16X3, 1, 1, true, 1, S)};
 const FwdVariant h2[] = {FEINT_K32S_R(2, FP16X3, 2, 2, true, 1, S)};

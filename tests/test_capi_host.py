@@ -65,7 +65,7 @@ def test_tiles():
             assert n >= 1
             buf = ctypes.create_string_buffer(16)
             assert L.feint_tile_describe(p, form, n - 1, buf, 16) == 0
-            assert re.fullmatch(rb"(\d+x\d+(s|sa|p|c|f|fw|fwb|fwg|fz)?|v\d+)(o\d)?", buf.value)
+            assert re.fullmatch(rb"(\d+x\d+(s|sa|p|c|f|fw|fwg|fz)?|v\d+)(o\d)?", buf.value)
             assert L.feint_tile_set(p, form, n) == -1
     assert L.feint_tile_count(0, 0) == 0
 
@@ -166,7 +166,7 @@ def test_rule_counts_and_points():
 def test_rule_tiles_and_validation():
     L = native.lib()
     buf = ctypes.create_string_buffer(32)
-    pat = re.compile(r"(\d+x\d+(s|sa|p|c|f|fw|fwb|fwg|fz)?|v\d+)(o\d)?")
+    pat = re.compile(r"(\d+x\d+(s|sa|p|c|f|fw|fwg|fz)?|v\d+)(o\d)?")
     for form in range(4):
         for p in range(1, 8):
             n = L.feint_rule_tile_count(p, form, 1)

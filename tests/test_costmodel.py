@@ -187,7 +187,7 @@ def test_kf_tile_names():
     """Both triangle-point contractions (one wave per block "KxTNf", shared
     point blocks "KxTNfw") are priced with the factorised count."""
     from paper_1310_1194_amd import costmodel
-    for d in ("5x5f", "5x3fo2", "5x3fwo2", "3x5fw", "2x2fwo2", "4x2fwbo2", "4x2fwgo2", "2x2fzo2", "3x3fwgo3"):
+    for d in ("5x5f", "5x3fo2", "5x3fwo2", "3x5fw", "2x2fwo2", "4x2fwgo2", "2x2fzo2", "3x3fwgo3"):
         assert costmodel.is_kf_tile(d)
     for d in ("5x5", "5x5yo2", "v1o2", "ref1o2", "5x3fwx"):
         assert not costmodel.is_kf_tile(d)
@@ -215,4 +215,4 @@ def test_zfirst_count_by_loops():
     assert C.f_factored_zfirst(n, nk, q) == flops
     assert C.f_factored_zfirst(C.nshp(7), 8, C.nq(7, "collapsed")) < C.f_kf(7)
     assert C.is_zfirst_tile("2x2fzo2") and C.is_zfirst_tile("4x2fwgo2")
-    assert not C.is_zfirst_tile("2x2fwo2") and not C.is_zfirst_tile("4x2fwbo2")
+    assert not C.is_zfirst_tile("2x2fwo2") and not C.is_zfirst_tile("5x5yo2")
