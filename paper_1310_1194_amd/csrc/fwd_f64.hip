@@ -47,6 +47,7 @@ const FwdVariant v5[] = {
     FEINT_K4S(5, double, 8, 1, 4, 2),
     FEINT_KSC(5, double, 8, 2, 1)};
 const FwdVariant v6[] = {
+    FEINT_KF2Z(6, double, 4, 1, 2, 2),
     FEINT_KF2Z(6, double, 2, 2, 2, 2),
     FEINT_KF2(6, double, 2, 2, 2),
     FEINT_KF_R(6, double, 7, 1, 1, 0),
